@@ -28,6 +28,7 @@
 #include "fsic_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -643,9 +644,9 @@ static void fwd_free(fwd_t *f)
     free(f->X); free(f->iters); free(f->relres);
 }
 
-static int forward(const int *n, double h, const double *origin, int p, int lmax, double tol,
-                   int maxit, double rho_floor, int N, const double *psi, const double *fod,
-                   fwd_t *f)
+static int forward_impl(const int *n, double h, const double *origin, int p, int lmax,
+                        double tol, int maxit, double rho_floor, int N, const double *psi,
+                        const double *fod, fwd_t *f, int flo_only)
 {
     memset(f, 0, sizeof(*f));
     if (!n || !origin || !psi || !fod || N < 1 || h <= 0) return ORC_EBADARG;
@@ -714,6 +715,7 @@ static int forward(const int *n, double h, const double *origin, int p, int lmax
             for (int j = 0; j < N; ++j) s += f->Z[i * N + j] * f->F[(long)j * M + m];
             f->phi[(long)i * M + m] = s;
         }
+    if (flo_only) return 0;
     /* (c) Hartree potential of each FLO density, (d) its XC energy */
     int status = 0;
     double *rho = malloc((size_t)N * M * sizeof(double));
@@ -741,6 +743,32 @@ static int forward(const int *n, double h, const double *origin, int p, int lmax
     free(rho);
     return status;
 }
+
+static int forward(const int *n, double h, const double *origin, int p, int lmax, double tol,
+                   int maxit, double rho_floor, int N, const double *psi, const double *fod,
+                   fwd_t *f)
+{
+    return forward_impl(n, h, origin, p, lmax, tol, maxit, rho_floor, N, psi, fod, f, 0);
+}
+
+int orc_flo_spin(const int *n, double h, const double *origin, double rho_floor, int N,
+                 const double *psi, const double *fod, double *phi, double *T, double *S,
+                 double *Z)
+{
+    fwd_t f;
+    int st = forward_impl(n, h, origin, 1, 0, 1e-10, 1, rho_floor, N, psi, fod, &f, 1);
+    if (st == 0) {
+        const long M = grid_size(n);
+        if (phi) memcpy(phi, f.phi, (size_t)N * M * sizeof(double));
+        if (T) memcpy(T, f.T, (size_t)N * N * sizeof(double));
+        if (S) memcpy(S, f.S, (size_t)N * N * sizeof(double));
+        if (Z) memcpy(Z, f.Z, (size_t)N * N * sizeof(double));
+    }
+    fwd_free(&f);
+    return st;
+}
+
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 int orc_sic_spin(const int *n, double h, const double *origin, int p, int lmax,
                  double tol, int maxit, double vscale, double rho_floor,

@@ -91,6 +91,15 @@ int orc_sic_grad_spin(const int *n, double h, const double *origin, int p, int l
                       double tol, int maxit, double rho_floor,
                       int N, const double *psi, const double *fod, double *dEda);
 
+/* Fermi-Loewdin orbitals only (steps (a) and (b) of orc_sic_spin):
+ * phi[N*M]; T, S, Z may be NULL. */
+int orc_flo_spin(const int *n, double h, const double *origin, double rho_floor, int N,
+                 const double *psi, const double *fod, double *phi, double *T, double *S,
+                 double *Z);
+
+/* OpenMP threads the oracle uses. */
+int orc_num_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

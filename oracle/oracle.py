@@ -209,6 +209,23 @@ def sic_spin(psi, fod, n, h, origin, p=6, lmax=6, tol=1e-13, maxit=20000, vscale
     return r
 
 
+def flo_spin(psi, fod, n, h, origin, rho_floor=1e-30):
+    """Fermi-Loewdin orbitals of one spin channel: (phi, T, S, Z)."""
+    n, origin = _grid(n, origin)
+    psi = _f64(psi).reshape(psi.shape[0], -1)
+    fod = _f64(fod).reshape(-1, 3)
+    N, M = psi.shape
+    phi = np.zeros((N, M))
+    T = np.zeros((N, N)); S = np.zeros((N, N)); Z = np.zeros((N, N))
+    _check(lib().orc_flo_spin(_i(n), ctypes.c_double(h), _d(origin), ctypes.c_double(rho_floor),
+                              N, _d(psi), _d(fod), _d(phi), _d(T), _d(S), _d(Z)))
+    return phi, T, S, Z
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
+
+
 def sic_grad_spin(psi, fod, n, h, origin, p=6, lmax=6, tol=1e-13, maxit=20000, rho_floor=1e-30):
     """dE_SIC/da for one spin channel, shape (N, 3)."""
     n, origin = _grid(n, origin)

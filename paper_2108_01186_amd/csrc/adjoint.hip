@@ -1,0 +1,306 @@
+// Reverse-mode FOD gradient of the discrete SIC energy (the FOD forces of
+// Eq. 9-11, in exact form for this discretisation).
+//
+// With v_i = A rho_i, A = K^{-1} (4 pi I + C E_g P) (K = -L, C: ghost values
+// into the right-hand side, E_g: moments to ghost values, P: density to
+// moments), U_i = dV/2 rho_i^T A rho_i and dE_xc/drho = dV v_xc:
+//   dE/dphi_i = Gam_i = 2 dV phi_i omega_i,
+//   omega_i = -( (v_i + A^T rho_i) / 2 + v_xc(rho_i) ),
+//   A^T rho = w' + dV sum_lm zt_lm r^l Y_lm,  K w' = 4 pi rho,
+//   zt_lm = (1 / 4 pi) sum_ghost 4 pi/(2l+1) Y_lm / r^(l+1) (C^T w')_ghost.
+// phi = Q psi gives B = Gam psi^T (one grid-sized contraction on the FP64
+// matrix cores); the rest is N x N: Q = Z T, Z = S^{-1/2} (Daleckii-Krein
+// form of the derivative of the inverse square root), S = T G T^T,
+// T_i = u_i / |u_i|, u_i,a = psi_a(a_i) (cubic interpolant).
+#include "kernels.h"
+
+namespace fsic {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// regular solid harmonics (same construction as the multipole kernels)
+template <int L>
+__device__ __forceinline__ void solid_harmonics_adj(double x, double y, double z, const double *norm,
+                                                    double *R) {
+    const double r2 = x * x + y * y + z * z;
+    double cm = 1.0, sm = 0.0, dfact = 1.0;
+#pragma unroll
+    for (int m = 0; m <= L; ++m) {
+        if (m > 0) {
+            const double c2 = cm * x - sm * y;
+            sm = cm * y + sm * x;
+            cm = c2;
+            dfact *= (double)(2 * m - 1);
+        }
+        double pm2 = 0.0, pm1 = 0.0;
+#pragma unroll
+        for (int l = m; l <= L; ++l) {
+            double pl;
+            if (l == m)
+                pl = dfact;
+            else if (l == m + 1)
+                pl = (double)(2 * m + 1) * z * pm1;
+            else
+                pl = ((double)(2 * l - 1) * z * pm1 - (double)(l + m - 1) * r2 * pm2) / (double)(l - m);
+            pm2 = pm1;
+            pm1 = pl;
+            if (m == 0) {
+                R[l * l + l] = norm[l * l + l] * pl;
+            } else {
+                R[l * l + l + m] = norm[l * l + l + m] * cm * pl;
+                R[l * l + l - m] = norm[l * l + l - m] * sm * pl;
+            }
+        }
+    }
+}
+
+// W_o += dV sum_lm zt_o,lm r^l Y_lm (the P^T part of A^T rho)
+template <int L>
+__global__ __launch_bounds__(256) void k_adj_field(HarmTables ht, const OrbDesc *orb,
+                                                   const Item *items, const double *Zt, double *W) {
+    constexpr int NLM = (L + 1) * (L + 1);
+    const Item it = items[blockIdx.x];
+    if (it.orb < 0) return;
+    const OrbDesc od = orb[it.orb];
+    const long long M = (long long)od.nx * od.ny * od.nz;
+    const double dV = od.h * od.h * od.h;
+    double z[NLM];
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) z[q] = Zt[(size_t)it.orb * NLM + q];
+    const long long base = (long long)it.tile * kPW;
+    for (int e = 0; e < kPW / 256; ++e) {
+        const long long i = base + e * 256 + threadIdx.x;
+        if (i >= M) continue;
+        const int ix = (int)(i % od.nx);
+        const int iy = (int)((i / od.nx) % od.ny);
+        const int iz = (int)(i / ((long long)od.nx * od.ny));
+        double R[NLM];
+        solid_harmonics_adj<L>(od.origin[0] + od.h * ix - od.centre[0],
+                               od.origin[1] + od.h * iy - od.centre[1],
+                               od.origin[2] + od.h * iz - od.centre[2], ht.norm, R);
+        double f = 0.0;
+#pragma unroll
+        for (int q = 0; q < NLM; ++q) f += z[q] * R[q];
+        W[od.off + i] += dV * f;
+    }
+}
+
+// fully polarised LSDA potential (same parameterisation as the forward pass)
+__device__ __forceinline__ double vxc_pol(double rho, double floor) {
+    if (!(rho > floor)) return 0.0;
+    constexpr double kSixOverPiCbrt = 1.2407009817988000333;
+    constexpr double kRsCoef = 0.62035049089940001667;
+    const double r13 = cbrt(rho);
+    const double vx = -kSixOverPiCbrt * r13;
+    constexpr double A = 0.015545, a1 = 0.20548;
+    constexpr double b1 = 14.1189, b2 = 6.1977, b3 = 3.3662, b4 = 0.62517;
+    const double rs = kRsCoef / r13;
+    const double s = sqrt(rs);
+    const double q1 = 2.0 * A * (s * (b1 + s * (b2 + s * (b3 + s * b4))));
+    const double q1p = A * (b1 / s + 2.0 * b2 + 3.0 * b3 * s + 4.0 * b4 * rs);
+    const double lg = log1p(1.0 / q1);
+    const double q0 = -2.0 * A * (1.0 + a1 * rs);
+    const double ec = q0 * lg;
+    const double dec = -2.0 * A * a1 * lg - q0 * q1p / (q1 * (q1 + 1.0));
+    return vx + (ec - rs * dec * (1.0 / 3.0));
+}
+
+// B[i][a] = sum_m Gam_i(m) psi_a(m); wave w owns Gam tiles t1 = w, w + 4 and
+// every psi tile t2; block b sums the node range [b chunk, (b+1) chunk).
+__global__ __launch_bounds__(256) void k_adj_contract(int N, long long M, long long chunk,
+                                                      double dV, const double *PHI,
+                                                      const double *V, const double *W,
+                                                      const double *psi, double floor,
+                                                      double *partB) {
+    const int Nt = (N + 15) >> 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    dbl4 acc[2][8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[a][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const long long m0 = (long long)blockIdx.x * chunk;
+    const long long m1 = min(M, m0 + chunk);
+    for (long long m = m0; m < m1; m += 4) {
+        const long long mm = m + kk;
+        const bool ok = mm < m1;
+        double g[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int t1 = w + 4 * a;
+            const int i = 16 * t1 + row;
+            double gv = 0.0;
+            if (t1 < Nt && i < N && ok) {
+                const long long gi = (long long)i * M + mm;
+                const double ph = PHI[gi];
+                const double r = ph * ph;
+                const double om = -(0.5 * (V[gi] + W[gi]) + vxc_pol(r, floor));
+                gv = 2.0 * dV * ph * om;
+            }
+            g[a] = gv;
+        }
+        double f[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int r = 16 * t + row;
+            f[t] = (t < Nt && r < N && ok) ? psi[(long long)r * M + mm] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (w + 4 * a < Nt) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (t < Nt) acc[a][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[a], f[t], acc[a][t], 0, 0, 0);
+            }
+        }
+    }
+    const int NP = Nt * 16;
+    double *out = partB + (size_t)blockIdx.x * NP * NP;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int t1 = w + 4 * a;
+        if (t1 >= Nt) continue;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t >= Nt) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                // D layout of the f64 16x16x4 MFMA: lane l, item j -> row l/16 + 4 j, col l % 16
+                const int r = 16 * t1 + kk + 4 * j;
+                const int c = 16 * t + row;
+                out[(size_t)r * NP + c] = acc[a][t][j];
+            }
+        }
+    }
+}
+
+__global__ void k_adj_contract_final(int N, int nblk, const double *partB, double *Bm) {
+    const int NP = ((N + 15) >> 4) * 16;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+        const int i = e / N, j = e % N;
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += partB[(size_t)b * NP * NP + (size_t)i * NP + j];
+        Bm[e] = s;
+    }
+}
+
+// C = op(A) op(B) for N x N row-major matrices (flat pointers)
+__device__ void nn_gemm(int N, const double *A, int ta, const double *B, int tb, double *C) {
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        double s = 0.0;
+        for (int k = 0; k < N; ++k) {
+            const double a = ta ? A[k * N + i] : A[i * N + k];
+            const double b = tb ? B[j * N + k] : B[k * N + j];
+            s += a * b;
+        }
+        C[e] = s;
+    }
+}
+
+// Reverse mode through Q = Z T, Z = S^{-1/2}, S = T G T^T, T_i = u_i/|u_i|.
+//   Gam_T  = Z^T B + 2 Gam_S T G          (Gam_Q = B)
+//   Gam_Z  = B T^T
+//   Gam_S  = U [(U^T sym(Gam_Z) U) o K] U^T,
+//            K_jk = -1 / (sqrt(l_j) sqrt(l_k) (sqrt(l_j) + sqrt(l_k)))
+//   Gam_u_i = (Gam_T_i - (Gam_T_i . T_i) T_i) / |u_i|
+//   dE/da_i = sum_a Gam_u_i,a grad psi_a(a_i)
+__global__ __launch_bounds__(256) void k_lowdin_backward(int N, const double *Bm, const double *T,
+                                                         const double *G, const double *lam,
+                                                         const double *U, const double *Z,
+                                                         const double *rhoa, const double *du,
+                                                         double *work, double *dEda) {
+    const size_t NN = (size_t)N * N;
+    double *GT = work;            // Gam_T
+    double *T1 = work + NN;
+    double *T2 = work + 2 * NN;
+    double *T3 = work + 3 * NN;
+    // Gam_Z = B T^T, symmetrised
+    nn_gemm(N, Bm, 0, T, 1, T1);
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        T2[e] = 0.5 * (T1[i * N + j] + T1[j * N + i]);
+    }
+    __syncthreads();
+    // U^T sym U, times K
+    nn_gemm(N, U, 1, T2, 0, T1);
+    __syncthreads();
+    nn_gemm(N, T1, 0, U, 0, T3);
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int j = e / N, k = e % N;
+        const double sj = sqrt(lam[j]), sk = sqrt(lam[k]);
+        T3[e] *= -1.0 / (sj * sk * (sj + sk));
+    }
+    __syncthreads();
+    // Gam_S = U T3 U^T
+    nn_gemm(N, U, 0, T3, 0, T1);
+    __syncthreads();
+    nn_gemm(N, T1, 0, U, 1, T2);  // T2 = Gam_S
+    __syncthreads();
+    // Gam_T = Z^T B + 2 Gam_S T G
+    nn_gemm(N, Z, 1, Bm, 0, GT);
+    __syncthreads();
+    nn_gemm(N, T2, 0, T, 0, T1);
+    __syncthreads();
+    nn_gemm(N, T1, 0, G, 0, T3);
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) GT[e] += 2.0 * T3[e];
+    __syncthreads();
+    // Gam_u and dE/da
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        double dot = 0.0;
+        for (int a = 0; a < N; ++a) dot += GT[i * N + a] * T[i * N + a];
+        const double inv = 1.0 / sqrt(rhoa[i]);
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int a = 0; a < N; ++a) {
+            const double gu = (GT[i * N + a] - dot * T[i * N + a]) * inv;
+            gx += gu * du[((size_t)i * N + a) * 3 + 0];
+            gy += gu * du[((size_t)i * N + a) * 3 + 1];
+            gz += gu * du[((size_t)i * N + a) * 3 + 2];
+        }
+        dEda[3 * i + 0] = gx;
+        dEda[3 * i + 1] = gy;
+        dEda[3 * i + 2] = gz;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_adj_field(int lmax, const HarmTables &ht, const OrbDesc *orb, const Item *items8,
+                            int nitems8, const double *Zt, double *W, hipStream_t s) {
+    if (nitems8 <= 0) return hipSuccess;
+    switch (lmax) {
+#define CASE(L) case L: hipLaunchKernelGGL(k_adj_field<L>, dim3(nitems8), dim3(256), 0, s, ht, orb, items8, Zt, W); break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,
+                                    const double *W, const double *psi, double floor, double *partB,
+                                    int nblk, double *Bm, hipStream_t s) {
+    long long chunk = (M + nblk - 1) / nblk;
+    chunk = (chunk + 3) & ~3LL;
+    hipLaunchKernelGGL(k_adj_contract, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
+                       floor, partB);
+    hipLaunchKernelGGL(k_adj_contract_final, dim3(64), dim3(256), 0, s, N, nblk, partB, Bm);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowdin_backward(int N, const double *Bm, const double *T, const double *G,
+                                  const double *lam, const double *U, const double *Z,
+                                  const double *rhoa, const double *du, double *work,
+                                  double *dEda, hipStream_t s) {
+    hipLaunchKernelGGL(k_lowdin_backward, dim3(1), dim3(256), 0, s, N, Bm, T, G, lam, U, Z, rhoa, du,
+                       work, dEda);
+    return hipGetLastError();
+}
+
+}  // namespace fsic

@@ -1,0 +1,89 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// the FLOSIC SIC library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsic {
+
+constexpr int kMaxRadius = 6;    // fd_order <= 12
+constexpr int kMaxOrb = 128;     // orbitals per spin channel
+constexpr int kMaxL = 8;         // multipole order
+constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 1);
+
+// Stencil tile: 32 (x) by 16 (y) columns per 256-thread block, marching in z.
+constexpr int kTX = 32;
+constexpr int kTY = 16;
+// Pointwise tile: 256 threads x 4 nodes.
+constexpr int kPW = 1024;
+
+// Device status bits (first error wins in the host's reading order).
+enum : int {
+    kStVacuum = 1,
+    kStSingular = 2,
+    kStNonFinite = 4,
+};
+
+// One Poisson problem (one orbital density) in a batched solve.
+struct OrbDesc {
+    int nx, ny, nz;
+    int tiles_x, tiles_y, tiles_z, zc;  // stencil tiling (zc: planes per z-chunk)
+    int nt7, base7;                     // stencil partial-sum slots
+    int nt8, base8;                     // pointwise partial-sum slots
+    long long off;                      // element offset of this orbital's fields
+    long long goff;                     // element offset of its ghost values
+    double inv_h2;
+    double h;
+    double origin[3];
+    double centre[3];
+    int chan;                           // spin channel (for the moment tables)
+    int pad;
+};
+
+// Work item of a block: orbital and tile index; orb < 0 means idle block.
+struct Item {
+    int orb, tile;
+};
+
+struct Coeffs {
+    double c[kMaxRadius + 1];  // unit-spacing second-difference weights
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the 256 threads of a block; every thread gets the same value, in
+// a fixed order (bitwise reproducible).  sbuf: 4 doubles of shared memory.
+__device__ __forceinline__ double block_sum256(double v, double *sbuf) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sbuf[w] = v;
+    __syncthreads();
+    double s = (sbuf[0] + sbuf[1]) + (sbuf[2] + sbuf[3]);
+    return s;
+}
+
+// Fixed-order sum of n partial sums (n arbitrary) by a 256-thread block.
+__device__ __forceinline__ double sum_partials(const double *p, int n, double *sbuf) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) v += p[i];
+    return block_sum256(v, sbuf);
+}
+
+// Block-to-item table order: block b runs on XCD b % 8; items are split in 8
+// contiguous ranges so that neighbouring tiles share an XCD (and its L2).
+inline int xcd_item_of_block(int b, int nblocks) {
+    const int per = nblocks / 8;
+    return (b % 8) * per + b / 8;
+}
+
+}  // namespace fsic

@@ -1,0 +1,397 @@
+// Fermi orbitals and their Loewdin orthonormalisation (Eq. 6-8, Sec. II.A),
+// the cubic interpolation of the KS orbitals at the FODs (Sec. II.B), and the
+// reverse-mode derivative of that chain for the FOD gradient (Eq. 9-11).
+//
+// The two grid-sized contractions run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64):
+//   * the Gram matrix G = dV psi psi^T, from which the FO overlap follows
+//     exactly as S = dV F F^T = T G T^T (F = T psi), so F is never stored;
+//   * the Fermi-Loewdin orbitals phi = Q psi with Q = S^{-1/2} T.
+// Everything N x N (N <= 128) runs in one workgroup: S = T G T^T, a parallel
+// cyclic Jacobi eigen-decomposition (round-robin pairing), S^{-1/2}, Q.
+#include "kernels.h"
+
+namespace fsic {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// MFMA f64 16x16x4 fragment layout (64 lanes):
+//   A (16 x 4):  lane l holds A[l % 16][l / 16]
+//   B (4 x 16):  lane l holds B[l / 16][l % 16]
+//   D (16 x 16): lane l holds D[l / 16 + 4 j][l % 16], j = 0..3 (rows interleaved)
+__device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// cubic interpolation at the FODs, T = u / |u|
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void cubic_weights(double t, double *w, double *dw) {
+    // Lagrange basis on the nodes -1, 0, 1, 2 and its derivative in t
+    const double tm1 = t - 1.0, tm2 = t - 2.0, tp1 = t + 1.0;
+    w[0] = -t * tm1 * tm2 * (1.0 / 6.0);
+    w[1] = tp1 * tm1 * tm2 * 0.5;
+    w[2] = -tp1 * t * tm2 * 0.5;
+    w[3] = tp1 * t * tm1 * (1.0 / 6.0);
+    const double t2 = t * t;
+    dw[0] = -(3.0 * t2 - 6.0 * t + 2.0) * (1.0 / 6.0);
+    dw[1] = (3.0 * t2 - 4.0 * t - 1.0) * 0.5;
+    dw[2] = -(3.0 * t2 - 2.0 * t - 2.0) * 0.5;
+    dw[3] = (3.0 * t2 - 1.0) * (1.0 / 6.0);
+}
+
+__global__ __launch_bounds__(128) void k_interp(int N, int nx, int ny, int nz, double h,
+                                                const double *psi, const FodCell *cells,
+                                                double floor, double *u, double *du,
+                                                double *rhoa, double *T, int *status) {
+    __shared__ double sred[2];
+    const int i = blockIdx.x;  // FOD
+    const FodCell cl = cells[i];
+    double wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
+    cubic_weights(cl.t[0], wx, dx);
+    cubic_weights(cl.t[1], wy, dy);
+    cubic_weights(cl.t[2], wz, dz);
+    const long long M = (long long)nx * ny * nz;
+    const int a = threadIdx.x;
+    double val = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    if (a < N) {
+        const double *f = psi + (long long)a * M;
+        for (int c = 0; c < 4; ++c) {
+            for (int b = 0; b < 4; ++b) {
+                const double *row = f + ((long long)(cl.i0[2] - 1 + c) * ny + (cl.i0[1] - 1 + b)) * nx + (cl.i0[0] - 1);
+                double sx = 0.0, sdx = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sx += wx[q] * row[q];
+                    sdx += dx[q] * row[q];
+                }
+                val += wz[c] * wy[b] * sx;
+                gx += wz[c] * wy[b] * sdx;
+                gy += wz[c] * dy[b] * sx;
+                gz += dz[c] * wy[b] * sx;
+            }
+        }
+        const double ih = 1.0 / h;
+        u[(size_t)i * N + a] = val;
+        du[((size_t)i * N + a) * 3 + 0] = gx * ih;
+        du[((size_t)i * N + a) * 3 + 1] = gy * ih;
+        du[((size_t)i * N + a) * 3 + 2] = gz * ih;
+    }
+    // rho(a_i) = sum_a psi_a(a_i)^2 (occupations 1), fixed-order reduction
+    double sq = (a < N) ? val * val : 0.0;
+    sq = wave_sum(sq);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    const double rho = sred[0] + sred[1];
+    if (a == 0) {
+        rhoa[i] = rho;
+        if (!(rho > floor)) atomicOr(status, kStVacuum);
+        if (!isfinite(rho)) atomicOr(status, kStNonFinite);
+    }
+    if (a < N) T[(size_t)i * N + a] = (rho > floor) ? val / sqrt(rho) : 0.0;
+}
+
+hipError_t launch_interp(int N, int nx, int ny, int nz, double h, const double *psi,
+                         const FodCell *cells, double floor, double *u, double *du,
+                         double *rhoa, double *T, int *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_interp, dim3(N), dim3(128), 0, s, N, nx, ny, nz, h, psi, cells, floor, u,
+                       du, rhoa, T, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrix G = dV psi psi^T on the matrix cores
+// ---------------------------------------------------------------------------
+
+// Block b accumulates the node range [b*chunk, (b+1)*chunk); wave w owns the
+// upper-triangle tile pairs p = w, w+4, ...; partG[b] holds the block's sums.
+__global__ __launch_bounds__(256) void k_gram(int N, long long M, long long chunk,
+                                              const double *psi, double *partG) {
+    const int Nt = (N + 15) >> 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    constexpr int kMaxPairPerWave = 9;  // Nt <= 8: 36 pairs over 4 waves
+    dbl4 acc[kMaxPairPerWave];
+    int pt1[kMaxPairPerWave], pt2[kMaxPairPerWave];
+    int np = 0;
+    // pairs (t1 <= t2) enumerated row by row; wave w takes indices w, w+4, ...
+    for (int t1 = 0, idx = 0; t1 < Nt; ++t1)
+        for (int t2 = t1; t2 < Nt; ++t2, ++idx)
+            if (idx % 4 == w && np < kMaxPairPerWave) {
+                pt1[np] = t1;
+                pt2[np] = t2;
+                ++np;
+            }
+#pragma unroll
+    for (int q = 0; q < kMaxPairPerWave; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const long long m0 = (long long)blockIdx.x * chunk;
+    const long long m1 = min(M, m0 + chunk);
+    for (long long m = m0; m < m1; m += 4) {
+        double frag[8];
+        const long long mm = m + kk;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int r = 16 * t + row;
+            frag[t] = (t < Nt && r < N && mm < m1) ? psi[(long long)r * M + mm] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxPairPerWave; ++q) {
+            if (q < np) {
+                double fa = 0.0, fb = 0.0;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (t == pt1[q]) fa = frag[t];
+                    if (t == pt2[q]) fb = frag[t];
+                }
+                acc[q] = mfma16x16x4(fa, fb, acc[q]);
+            }
+        }
+    }
+    const int NP = Nt * 16;
+    double *out = partG + (size_t)blockIdx.x * NP * NP;
+#pragma unroll
+    for (int q = 0; q < kMaxPairPerWave; ++q) {
+        if (q < np) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 16 * pt1[q] + kk + 4 * j;
+                const int c = 16 * pt2[q] + row;
+                out[(size_t)r * NP + c] = acc[q][j];
+            }
+        }
+    }
+}
+
+__global__ void k_gram_final(int N, int nblk, double dV, const double *partG, double *G) {
+    const int NP = ((N + 15) >> 4) * 16;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+        int i = e / N, j = e % N;
+        if ((i >> 4) > (j >> 4)) { const int t = i; i = j; j = t; }
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += partG[(size_t)b * NP * NP + (size_t)i * NP + j];
+        G[e] = dV * s;
+    }
+}
+
+hipError_t launch_gram(int N, long long M, double dV, const double *psi, double *partG, int nblk,
+                       double *G, hipStream_t s) {
+    long long chunk = (M + nblk - 1) / nblk;
+    chunk = (chunk + 3) & ~3LL;
+    hipLaunchKernelGGL(k_gram, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, partG);
+    hipLaunchKernelGGL(k_gram_final, dim3(64), dim3(256), 0, s, N, nblk, dV, partG, G);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Loewdin: S = T G T^T, Jacobi, Z = S^{-1/2}, Q = Z T (one workgroup)
+// ---------------------------------------------------------------------------
+
+// C = A B (+ transposes) for N x N row-major matrices held anywhere (flat).
+__device__ void small_gemm(int N, const double *A, int ta, const double *B, int tb, double *C,
+                           double alpha) {
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        double s = 0.0;
+        for (int k = 0; k < N; ++k) {
+            const double a = ta ? A[k * N + i] : A[i * N + k];
+            const double b = tb ? B[j * N + k] : B[k * N + j];
+            s += a * b;
+        }
+        C[e] = alpha * s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lowdin(int N, int Ne, const double *T, const double *G,
+                                                double *S, double *lam, double *U, double *Z,
+                                                double *Qm, double *work, int lds_mode,
+                                                double eig_floor, int *status, double *info) {
+    extern __shared__ double dsm[];
+    __shared__ double rc[kMaxOrb / 2], rs_[kMaxOrb / 2];
+    __shared__ int rp[kMaxOrb / 2], rq[kMaxOrb / 2];
+    __shared__ double sred[4];
+    __shared__ int sflag;
+    // A (Ne x Ne) and V (Ne x Ne) in LDS or in work
+    double *A = (lds_mode >= 1) ? dsm : work;
+    double *V = (lds_mode >= 2) ? dsm + Ne * Ne : work + Ne * Ne;
+    double *TG = work + 2 * Ne * Ne;  // N x N scratch
+    // TG = T G
+    small_gemm(N, T, 0, G, 0, TG, 1.0);
+    __syncthreads();
+    // S = TG T^T, exactly symmetric, padded to Ne with the identity
+    for (int e = threadIdx.x; e < Ne * Ne; e += 256) {
+        const int i = e / Ne, j = e % Ne;
+        double v;
+        if (i < N && j < N) {
+            const int a = min(i, j), b = max(i, j);
+            double s = 0.0;
+            for (int k = 0; k < N; ++k) s += TG[a * N + k] * T[b * N + k];
+            v = s;
+            S[i * N + j] = v;
+        } else {
+            v = (i == j) ? 1.0 : 0.0;
+        }
+        A[e] = v;
+        V[e] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int half = Ne / 2;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        // convergence: off-diagonal vs diagonal mass
+        double off = 0.0, dg = 0.0;
+        for (int e = threadIdx.x; e < Ne * Ne; e += 256) {
+            const int i = e / Ne, j = e % Ne;
+            const double a = A[e];
+            if (i == j) dg += a * a; else off += a * a;
+        }
+        off = block_sum256(off, sred);
+        dg = block_sum256(dg, sred);
+        if (off <= 1e-30 * dg) break;
+        for (int r = 0; r < Ne - 1; ++r) {
+            // round-robin pairing: position 0 holds index 0, positions 1..Ne-1
+            // hold 1..Ne-1 rotated by r; pair position j with Ne-1-j
+            if (threadIdx.x < half) {
+                const int j = threadIdx.x;
+                auto at = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + r) % (Ne - 1)) + 1; };
+                int p = at(j), q = at(Ne - 1 - j);
+                if (p > q) { const int t = p; p = q; q = t; }
+                const double apq = A[p * Ne + q], app = A[p * Ne + p], aqq = A[q * Ne + q];
+                double c = 1.0, s = 0.0;
+                if (apq != 0.0 && fabs(apq) > 1e-300) {
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                }
+                rp[j] = p; rq[j] = q; rc[j] = c; rs_[j] = s;
+            }
+            __syncthreads();
+            // rows p, q of A <- J^T A
+            for (int e = threadIdx.x; e < half * Ne; e += 256) {
+                const int j = e / Ne, col = e % Ne;
+                const int p = rp[j], q = rq[j];
+                const double c = rc[j], s = rs_[j];
+                const double ap = A[p * Ne + col], aq = A[q * Ne + col];
+                A[p * Ne + col] = c * ap - s * aq;
+                A[q * Ne + col] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns p, q of A and V <- A J, V J
+            for (int e = threadIdx.x; e < half * Ne; e += 256) {
+                const int j = e / Ne, rw = e % Ne;
+                const int p = rp[j], q = rq[j];
+                const double c = rc[j], s = rs_[j];
+                const double ap = A[rw * Ne + p], aq = A[rw * Ne + q];
+                A[rw * Ne + p] = c * ap - s * aq;
+                A[rw * Ne + q] = s * ap + c * aq;
+                const double vp = V[rw * Ne + p], vq = V[rw * Ne + q];
+                V[rw * Ne + p] = c * vp - s * vq;
+                V[rw * Ne + q] = s * vp + c * vq;
+            }
+            __syncthreads();
+            if (threadIdx.x < half) {
+                const int p = rp[threadIdx.x], q = rq[threadIdx.x];
+                if (rs_[threadIdx.x] != 0.0) {
+                    A[p * Ne + q] = 0.0;
+                    A[q * Ne + p] = 0.0;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // eigenvalues, condition number, singularity test
+    if (threadIdx.x == 0) sflag = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += 256) lam[i] = A[i * Ne + i];
+    for (int e = threadIdx.x; e < N * N; e += 256) U[e] = V[(e / N) * Ne + (e % N)];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mn = lam[0], mx = lam[0];
+        for (int i = 1; i < N; ++i) { mn = fmin(mn, lam[i]); mx = fmax(mx, lam[i]); }
+        info[0] = mx / mn;
+        info[1] = mn;
+        if (!(mn > eig_floor)) { atomicOr(status, kStSingular); sflag = 1; }
+    }
+    __syncthreads();
+    if (sflag) return;
+    // Z = U diag(lam^{-1/2}) U^T ; Q = Z T
+    double *W = work + 2 * Ne * Ne;
+    for (int e = threadIdx.x; e < N * N; e += 256) W[e] = U[e] / sqrt(lam[e % N]);
+    __syncthreads();
+    small_gemm(N, W, 0, U, 1, Z, 1.0);
+    __syncthreads();
+    small_gemm(N, Z, 0, T, 0, Qm, 1.0);
+}
+
+hipError_t launch_lowdin(int N, const double *T, const double *G, double *S, double *lam,
+                         double *U, double *Z, double *Qm, double *work, double eig_floor,
+                         int *status, double *info, hipStream_t s) {
+    const int Ne = N + (N & 1);
+    int dev = 0;
+    hipGetDevice(&dev);
+    int maxsh = 0;
+    hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const size_t static_bytes = 4 * 64 * 8 + 64;  // rotation tables, reductions
+    const size_t need1 = (size_t)Ne * Ne * sizeof(double);
+    int mode = 0;
+    size_t dyn = 0;
+    if (2 * need1 + static_bytes <= (size_t)maxsh) { mode = 2; dyn = 2 * need1; }
+    else if (need1 + static_bytes <= (size_t)maxsh) { mode = 1; dyn = need1; }
+    if (dyn > 65536) hipFuncSetAttribute((const void *)k_lowdin, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    hipLaunchKernelGGL(k_lowdin, dim3(1), dim3(256), dyn, s, N, Ne, T, G, S, lam, U, Z, Qm, work,
+                       mode, eig_floor, status, info);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// out = A psi  (N x N times N x M) on the matrix cores
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_orb_gemm(int N, long long M, const double *A,
+                                                  const double *psi, double *out) {
+    const int Nt = (N + 15) >> 4;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kk = lane >> 4;
+    const long long nstrip = (M + 15) >> 4;
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwave = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long st = wave; st < nstrip; st += nwave) {
+        const long long m = st * 16 + row;
+        dbl4 acc[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int a0 = 0; a0 < N; a0 += 4) {
+            const int a = a0 + kk;
+            const double b = (a < N && m < M) ? psi[(long long)a * M + m] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t < Nt) {
+                    const int i = 16 * t + row;
+                    const double av = (i < N && a < N) ? A[i * N + a] : 0.0;
+                    acc[t] = mfma16x16x4(av, b, acc[t]);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t < Nt && m < M) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = 16 * t + kk + 4 * j;
+                    if (i < N) out[(long long)i * M + m] = acc[t][j];
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *psi, double *out,
+                           hipStream_t s) {
+    const long long nstrip = (M + 15) / 16;
+    long long nblk = (nstrip + 3) / 4;
+    if (nblk > 8192) nblk = 8192;
+    hipLaunchKernelGGL(k_orb_gemm, dim3((unsigned)nblk), dim3(256), 0, s, N, M, A, psi, out);
+    return hipGetLastError();
+}
+
+}  // namespace fsic

@@ -1,0 +1,182 @@
+// Host-side launchers of the HIP kernels (internal to the library).
+#pragma once
+
+#include "common.h"
+
+namespace fsic {
+
+// ----------------------------------------------------------------------------
+// stencil.hip: z-marching star stencil and conjugate-gradient sweeps
+// ----------------------------------------------------------------------------
+
+// Lu = L u (zero ghosts) for the orbitals of an item table.
+template <typename T>
+hipError_t launch_apply(int radius, const Coeffs &c, const Item *items, int nitems,
+                        const OrbDesc *orb, const T *u, T *Lu, hipStream_t s);
+
+// Arguments of one CG iteration over a batch of orbitals.
+template <typename T>
+struct CGIter {
+    const Item *items7;  // stencil items
+    int nitems7;
+    const Item *items8;  // pointwise items
+    int nitems8;
+    const OrbDesc *orb;
+    T *R;               // residual
+    T *Pold, *Pnew;     // search directions of iterations k-1 and k
+    T *Q;               // K p
+    T *X;               // solution (FP64 path) or FP32 correction (mixed path)
+    double *part7;      // [tot7]   p.q partial sums
+    double *part8;      // [2*tot8] r.r partial sums, by iteration parity
+    double *partRU;     // [tot7]   true-residual partial sums (mixed path)
+    int tot8;
+    int *done;          // per orbital: converged
+    int *iters;         // per orbital: iterations at convergence
+    double *rrfin;      // per orbital: residual norm^2 at convergence
+    const double *bb;   // per orbital: ||b||^2
+    double tol2;        // tol^2
+};
+
+// One stencil sweep (p_k = r_k + beta p_{k-1}; q = -L p_k; p.q partials).
+//   k: iteration; cur_from_ru / prev_from_ru: r_k.r_k (r_{k-1}.r_{k-1}) is in
+//   partRU rather than part8; check: test convergence on r_k.r_k first.
+template <typename T>
+hipError_t launch_cg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, int k,
+                             int cur_from_ru, int prev_from_ru, int check, hipStream_t s);
+
+// One pointwise update (x += alpha p; r -= alpha q; r.r partials).
+//   x_first: x is not read (x = alpha p).
+template <typename T>
+hipError_t launch_cg_update(const CGIter<T> &a, int k, int cur_from_ru, int x_first,
+                            hipStream_t s);
+
+// FP64 residual of x64 (+ x32): res = b + L (x64 + x32); writes x64new =
+// x64 + x32, r32 = (float) res (if r32 != null), res.res partials.
+hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7, int nitems7,
+                                const OrbDesc *orb, const int *done, const double *X64,
+                                const float *X32, const double *B, double *X64new, float *R32,
+                                double *partRU, hipStream_t s);
+
+// mixed precision: x64 += x32 (orbitals not yet converged)
+hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDesc *orb,
+                                   const int *done, double *X64, const float *X32, hipStream_t s);
+
+// mixed precision: mark orbitals whose FP64 residual (partRU) meets tol
+hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
+                           double tol2, int k, int *done, int *iters, double *rrfin, hipStream_t s);
+
+// per orbital: out[o] = sum of partials (stencil layout if stencil_layout,
+// else pointwise slot range starting at the parity-0 block)
+hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *part,
+                                  int stencil_layout, double *out, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// multipole.hip: Dirichlet values from a multipole expansion, right-hand side
+// ----------------------------------------------------------------------------
+
+struct HarmTables {
+    double norm[kMaxLM];   // real orthonormal Y_lm normalisation (incl. sqrt 2 for m != 0)
+    double gfac[kMaxLM];   // 4 pi / (2l + 1)
+};
+
+// Q[o][lm] = dV sum_r rho_o(r) |r-c|^l Y_lm; rho = src^2 if square else src.
+hipError_t launch_moments(int lmax, const HarmTables &ht, int norb, const OrbDesc *orb,
+                          const Item *items8, int nitems8, const double *src, int square,
+                          double *partQ, int tot8, double *Q, hipStream_t s);
+
+// ghost values on the face slabs: g[o] = sum_lm gfac Q_lm Y_lm / r^(l+1)
+hipError_t launch_ghosts(int radius, int lmax, const HarmTables &ht, int norb,
+                         const OrbDesc *orb, const long long *ghost_count, const double *Q,
+                         double *G, long long max_ghost, hipStream_t s);
+
+// b = scale * rho + (boundary term of the ghosts, if G != null); writes B,
+// R64 or R32 = b, optionally X64 = 0, and b.b partials into part8 slot 0.
+hipError_t launch_rhs(int radius, const Coeffs &c, const Item *items8, int nitems8,
+                      const OrbDesc *orb, const double *src, int square, double scale,
+                      const double *G, double *B, double *R64, float *R32, double *X64zero,
+                      double *part8, hipStream_t s);
+
+// Adjoint boundary term: zt[o][lm] = sum_ghost gfac Y_lm / r^(l+1) (C^T w)_ghost
+hipError_t launch_adjoint_boundary(int radius, int lmax, const HarmTables &ht, const Coeffs &c,
+                                   int norb, const OrbDesc *orb, const long long *ghost_count,
+                                   const double *W, double *partZ, int zchunks, double *Zt,
+                                   long long max_ghost, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// xc.hip: LSDA at full polarisation, Slater average, energies, adjoint source
+// ----------------------------------------------------------------------------
+
+hipError_t launch_xc_pointwise(long long count, const double *rho, double floor, double *ex,
+                               double *ec, double *vx, double *vc, hipStream_t s);
+
+struct ChanDesc {
+    int N;                 // orbitals
+    int first_orb;         // index of orbital 0 in the batch
+    long long M;
+    long long off;         // element offset of orbital 0's fields (phi, v)
+    int nx, ny, nz;
+    int nblk;              // blocks of the channel's pointwise passes
+    int blk_base;          // first partial slot (per orbital: [N][nblk])
+    int pad;
+    double h;
+    double vscale;
+    double *vsic;          // output V_SIC or null
+};
+
+// U and X partials per block and orbital, V_SIC
+hipError_t launch_sic_average(int nchan, const ChanDesc *chan, int nblk_total,
+                              const int *blk_chan, const double *PHI, const double *V,
+                              double floor, double *partU, double *partX, hipStream_t s);
+
+// per orbital U = dV/2 sum partU, X = dV sum partX; per channel E = -sum(U + X)
+hipError_t launch_sic_energy(int nchan, const ChanDesc *chan, const double *partU,
+                             const double *partX, double *U, double *X, double *Echan,
+                             hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// fo.hip: FOD interpolation, Gram matrix, Loewdin, Fermi-Loewdin GEMM
+// ----------------------------------------------------------------------------
+
+struct FodCell {
+    int i0[3];    // lower-left node of the 4-node stencil is i0 - 1
+    int pad;
+    double t[3];  // fractional position in [0, 1)
+};
+
+// u[i][a] = psi_a(a_i), du[i][a][3]; rhoa[i]; T[i][a]; sets status on vacuum
+hipError_t launch_interp(int N, int nx, int ny, int nz, double h, const double *psi,
+                         const FodCell *cells, double floor, double *u, double *du,
+                         double *rhoa, double *T, int *status, hipStream_t s);
+
+// G = dV psi psi^T (MFMA FP64), partial sums then reduction; nonortho = max|G - I|
+hipError_t launch_gram(int N, long long M, double dV, const double *psi, double *partG,
+                       int nblk, double *G, hipStream_t s);
+
+// Loewdin step on one block: S = T G T^T; S = U diag(lam) U^T (parallel
+// Jacobi); Z = S^{-1/2}; Q = Z T.  work: device scratch of >= 2 N^2 doubles.
+hipError_t launch_lowdin(int N, const double *T, const double *G, double *S, double *lam,
+                         double *U, double *Z, double *Qm, double *work, double eig_floor,
+                         int *status, double *info, hipStream_t s);
+
+// out[i][m] = sum_a A[i][a] psi[a][m]  (MFMA FP64), N <= 128
+hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *psi, double *out,
+                           hipStream_t s);
+
+// W_o += dV sum_lm zt_o,lm r^l Y_lm for every orbital of the batch
+hipError_t launch_adj_field(int lmax, const HarmTables &ht, const OrbDesc *orb, const Item *items8,
+                            int nitems8, const double *Zt, double *W, hipStream_t s);
+
+// B[i][a] = sum_m Gam_i(m) psi_a(m) with Gam_i = 2 dV phi_i omega_i built on
+// the fly, omega_i = -((v_i + w_i) / 2 + vxc(phi_i^2)) (MFMA FP64)
+hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,
+                                   const double *W, const double *psi, double floor, double *partB,
+                                   int nblk, double *Bm, hipStream_t s);
+
+// reverse mode through Q = S^{-1/2} T, S = T G T^T, T = u/|u|, u = psi(a):
+// dEda[i][d] = gscale * sum_a Gam_u[i][a] dpsi_a(a_i)/da_d
+hipError_t launch_lowdin_backward(int N, const double *Bm, const double *T, const double *G,
+                                  const double *lam, const double *U, const double *Z,
+                                  const double *rhoa, const double *du, double *work,
+                                  double *dEda, hipStream_t s);
+
+}  // namespace fsic

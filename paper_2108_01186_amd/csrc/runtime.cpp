@@ -1,0 +1,1150 @@
+// Host runtime of the FLOSIC SIC library: argument validation, batched work
+// plans (one Poisson problem per orbital, all orbitals of all spin channels
+// and systems in the same CG launches), workspace management, the forward
+// and backward passes and the operator-level entry points of fsic.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fsic.h"
+#include "kernels.h"
+
+using namespace fsic;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small device buffer that only grows
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n) {
+        if (n <= cap) return hipSuccess;
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc((void **)&p, std::max<size_t>(n, 1) * sizeof(T));
+        if (e == hipSuccess) cap = n;
+        return e;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// 2p-th order central second-difference weights on unit spacing, from the
+// moment conditions sum_k c_k k^(2j) = delta_{j1} (j = 1..p, c_-k = c_k)
+// solved by Gaussian elimination in extended precision.
+Coeffs fd_weights(int p) {
+    long double A[kMaxRadius][kMaxRadius + 1];
+    for (int j = 1; j <= p; ++j) {
+        for (int k = 1; k <= p; ++k) {
+            long double v = 1.0L;
+            for (int e = 0; e < 2 * j; ++e) v *= (long double)k;
+            A[j - 1][k - 1] = 2.0L * v;
+        }
+        A[j - 1][p] = (j == 1) ? 2.0L : 0.0L;  // second derivative of x^2 is 2
+    }
+    for (int col = 0; col < p; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < p; ++r)
+            if (fabsl(A[r][col]) > fabsl(A[piv][col])) piv = r;
+        if (piv != col)
+            for (int c = 0; c <= p; ++c) std::swap(A[col][c], A[piv][c]);
+        for (int r = 0; r < p; ++r) {
+            if (r == col) continue;
+            const long double f = A[r][col] / A[col][col];
+            for (int c = col; c <= p; ++c) A[r][c] -= f * A[col][c];
+        }
+    }
+    Coeffs cf{};
+    long double s = 0.0L;
+    for (int k = 1; k <= p; ++k) {
+        const long double ck = A[k - 1][p] / A[k - 1][k - 1];
+        cf.c[k] = (double)ck;
+        s += ck;
+    }
+    cf.c[0] = (double)(-2.0L * s);
+    return cf;
+}
+
+HarmTables harm_tables(int lmax) {
+    HarmTables t{};
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int l = 0; l <= lmax; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            const int am = m < 0 ? -m : m;
+            long double ratio = 1.0L;  // (l - |m|)! / (l + |m|)!
+            for (int k = l - am + 1; k <= l + am; ++k) ratio /= (long double)k;
+            long double nv = sqrtl((2.0L * l + 1.0L) / (4.0L * pi) * ratio);
+            if (m != 0) nv *= sqrtl(2.0L);
+            t.norm[l * l + l + m] = (double)nv;
+            t.gfac[l * l + l + m] = (double)(4.0L * pi / (2.0L * l + 1.0L));
+        }
+    }
+    return t;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Chan {
+    int sys, spin, N;
+    int n[3];
+    double h, origin[3];
+    long long M;
+    const double *psi;
+    std::vector<double> fod;   // host copy, N x 3
+    int first_orb;
+    long long off;             // field offset of orbital 0
+    std::vector<FodCell> cells;
+    int nblk;                  // pointwise blocks (sic average)
+    int blk_base;
+    // per-channel device small arrays (offsets into the small arena)
+    size_t so;                 // offset in doubles of this channel's small block
+};
+
+// small per-channel arrays, N <= kMaxOrb: u, du(3), rhoa, T, G, S, lam, U, Z, Qm, info(2), dEda(3)
+constexpr size_t kSmallPerChan = (size_t)kMaxOrb * kMaxOrb * 8 + (size_t)kMaxOrb * 8 + 64;
+enum SmallSlot { sU_ = 0, sDU, sRHOA, sT, sG, sS, sLAM, sEV, sZ, sQ, sINFO, sDEDA };
+size_t small_off(SmallSlot s) {
+    const size_t NN = (size_t)kMaxOrb * kMaxOrb;
+    switch (s) {
+        case sU_: return 0;
+        case sDU: return NN;                 // 3 NN
+        case sT: return 4 * NN;
+        case sG: return 5 * NN;
+        case sS: return 6 * NN;
+        case sEV: return 7 * NN;
+        case sZ: return 8 * NN;
+        case sQ: return 9 * NN;
+        case sRHOA: return 10 * NN;          // N
+        case sLAM: return 10 * NN + kMaxOrb;
+        case sINFO: return 10 * NN + 2 * kMaxOrb;
+        case sDEDA: return 10 * NN + 2 * kMaxOrb + 8;  // 3N
+    }
+    return 0;
+}
+constexpr size_t kSmallStride = (size_t)kMaxOrb * kMaxOrb * 10 + 2 * kMaxOrb + 8 + 3 * kMaxOrb + 8;
+
+// A batch of Poisson problems sharing one launch sequence.
+struct Batch {
+    std::vector<OrbDesc> orb;
+    std::vector<Item> items7, items8;
+    std::vector<long long> gcount;
+    long long fields = 0;  // total elements
+    long long ghosts = 0;
+    long long max_ghost = 0;
+    int tot7 = 0, tot8 = 0;
+};
+
+void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<Item> &out) {
+    const int n = (int)natural.size();
+    const int nb = ((n + 7) / 8) * 8;
+    out.assign(nb, Item{-1, 0});
+    const int per = nb / 8;
+    for (int b = 0; b < nb; ++b) {
+        const int idx = xcd_item_of_block(b, nb);
+        (void)per;
+        if (idx < n) out[b] = Item{natural[idx].first, natural[idx].second};
+    }
+}
+
+}  // namespace
+
+struct fsic_ctx {
+    fsic_opts opts{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+
+    // field buffers
+    DBuf<double> PHI, V, W, B, R, P0, P1, Q, X64b;
+    DBuf<float> R32, P32a, P32b, Q32, X32;
+    DBuf<double> Gh;  // ghost values
+    DBuf<double> part7, part8, partRU, partQ, partZ;
+    DBuf<double> bb, rrfin, relres, Qlm, Zt, ptrue;
+    DBuf<int> done, iters;
+    DBuf<OrbDesc> d_orb;
+    DBuf<Item> d_items7, d_items8;
+    DBuf<long long> d_gcount;
+    DBuf<double> small;   // per-channel small arrays
+    DBuf<double> work;    // Jacobi / N x N scratch
+    DBuf<double> partG;
+    DBuf<FodCell> d_cells;
+    DBuf<ChanDesc> d_chan;
+    DBuf<int> d_blkchan;
+    DBuf<double> partU, partX, Uo, Xo, Ech;
+    DBuf<int> status;
+    DBuf<double> bmat;
+    int *h_done = nullptr;  // pinned
+    // profiling (FSIC_PROFILE): events around every CG launch
+    std::vector<hipEvent_t> ev;
+    int32_t sweep_launches = 0, update_launches = 0;
+    double sweep_ms = 0, sweep_bytes = 0, update_ms = 0, update_bytes = 0;
+    size_t h_done_cap = 0;
+
+    // plan of the last forward pass (the tape)
+    std::vector<Chan> chans;
+    Batch batch;
+    int nsys = 0;
+    bool tape = false;
+    int radius = 6;
+    Coeffs cf{};
+    HarmTables ht{};
+
+    bool fail(fsic_status, const std::string &m) {
+        err = m;
+        return false;
+    }
+};
+
+namespace {
+
+fsic_status set_err(fsic_ctx *c, fsic_status s, const std::string &m) {
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                               \
+    do {                                                                                \
+        hipError_t _e = (call);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return set_err(ctx, _e == hipErrorOutOfMemory ? FSIC_ENOMEM : FSIC_EHIP,    \
+                           std::string(#call) + ": " + hipGetErrorString(_e));          \
+    } while (0)
+
+fsic_status validate_opts(const fsic_opts *o, std::string &why) {
+    if (!o) { why = "opts is NULL"; return FSIC_EINVAL; }
+    if (o->fd_order < 2 || o->fd_order > 12 || (o->fd_order & 1)) { why = "fd_order must be even in [2, 12]"; return FSIC_EINVAL; }
+    if (o->lmax < 0 || o->lmax > kMaxL) { why = "lmax must be in [0, 8]"; return FSIC_EINVAL; }
+    if (o->solver != FSIC_CG) { why = "solver must be FSIC_CG"; return FSIC_EINVAL; }
+    if (o->precision != FSIC_FP64 && o->precision != FSIC_MIXED) { why = "precision must be FSIC_FP64 or FSIC_MIXED"; return FSIC_EINVAL; }
+    if (!(o->tol > 0.0 && o->tol < 1.0)) { why = "tol must be in (0, 1)"; return FSIC_EINVAL; }
+    if (o->max_iter < 1) { why = "max_iter must be >= 1"; return FSIC_EINVAL; }
+    if (!std::isfinite(o->vsic_scale)) { why = "vsic_scale must be finite"; return FSIC_EINVAL; }
+    if (!(o->rho_floor >= 0.0) || !std::isfinite(o->rho_floor)) { why = "rho_floor must be finite and >= 0"; return FSIC_EINVAL; }
+    if (!(o->s_eig_floor > 0.0) || !std::isfinite(o->s_eig_floor)) { why = "s_eig_floor must be finite and > 0"; return FSIC_EINVAL; }
+    if (o->flags & ~(FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE)) { why = "unknown flag bits"; return FSIC_EINVAL; }
+    return FSIC_OK;
+}
+
+fsic_status validate_grid(const fsic_grid &g, std::string &why) {
+    for (int d = 0; d < 3; ++d) {
+        if (g.n[d] < 8 || g.n[d] > 4096) { why = "grid n must be in [8, 4096] on every axis"; return FSIC_EINVAL; }
+        if (!std::isfinite(g.origin[d])) { why = "grid origin must be finite"; return FSIC_EINVAL; }
+    }
+    if (!(g.h > 0.0) || !std::isfinite(g.h)) { why = "grid spacing h must be finite and > 0"; return FSIC_EINVAL; }
+    return FSIC_OK;
+}
+
+// Stencil tiling: columns of 32 x 16, z-chunks sized so the launch has
+// enough blocks to fill 256 compute units several times over.
+void tile_orbital(OrbDesc &od, int radius, long long total_cols_blocks) {
+    od.tiles_x = (od.nx + kTX - 1) / kTX;
+    od.tiles_y = (od.ny + kTY - 1) / kTY;
+    int zc = od.nz;
+    long long blocks = total_cols_blocks;
+    while (blocks < 2048 && zc >= 4 * radius && zc >= 32) {
+        zc = (zc + 1) / 2;
+        blocks *= 2;
+    }
+    od.zc = zc;
+    od.tiles_z = (od.nz + zc - 1) / zc;
+}
+
+// Build the batch of Poisson problems for a list of (grid, count) groups.
+struct Group {
+    int n[3];
+    double h, origin[3];
+    int count;
+    long long off;  // field offset of the first orbital
+    int chan;
+};
+
+void build_batch(const std::vector<Group> &groups, int radius, Batch &b) {
+    b = Batch{};
+    long long cols = 0;
+    for (const Group &g : groups)
+        cols += (long long)g.count * ((g.n[0] + kTX - 1) / kTX) * ((g.n[1] + kTY - 1) / kTY);
+    std::vector<std::pair<int, int>> nat7, nat8;
+    for (const Group &g : groups) {
+        const long long M = (long long)g.n[0] * g.n[1] * g.n[2];
+        for (int i = 0; i < g.count; ++i) {
+            OrbDesc od{};
+            od.nx = g.n[0]; od.ny = g.n[1]; od.nz = g.n[2];
+            tile_orbital(od, radius, cols);
+            od.nt7 = od.tiles_x * od.tiles_y * od.tiles_z;
+            od.base7 = b.tot7;
+            b.tot7 += od.nt7;
+            od.nt8 = (int)((M + kPW - 1) / kPW);
+            od.base8 = b.tot8;
+            b.tot8 += od.nt8;
+            od.off = g.off + (long long)i * M;
+            const long long G = 2LL * radius * ((long long)g.n[1] * g.n[2] + (long long)g.n[0] * g.n[2] + (long long)g.n[0] * g.n[1]);
+            od.goff = b.ghosts;
+            b.ghosts += G;
+            b.max_ghost = std::max(b.max_ghost, G);
+            b.gcount.push_back(G);
+            od.h = g.h;
+            od.inv_h2 = 1.0 / (g.h * g.h);
+            for (int d = 0; d < 3; ++d) {
+                od.origin[d] = g.origin[d];
+                od.centre[d] = g.origin[d] + 0.5 * g.h * (g.n[d] - 1);
+            }
+            od.chan = g.chan;
+            const int o = (int)b.orb.size();
+            b.orb.push_back(od);
+            for (int t = 0; t < od.nt7; ++t) nat7.push_back({o, t});
+            for (int t = 0; t < od.nt8; ++t) nat8.push_back({o, t});
+            b.fields = std::max(b.fields, od.off + M);
+        }
+    }
+    build_items(nat7, b.items7);
+    build_items(nat8, b.items8);
+}
+
+template <typename T>
+fsic_status upload(fsic_ctx *c, DBuf<T> &d, const std::vector<T> &h) {
+    HIPCHK(c, d.ensure(h.size()));
+    if (!h.empty())
+        HIPCHK(c, hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return FSIC_OK;
+}
+
+// Upload a batch's tables and size the solver buffers.
+fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
+    const size_t F = (size_t)b.fields;
+    fsic_status st;
+    if ((st = upload(c, c->d_orb, b.orb))) return st;
+    if ((st = upload(c, c->d_items7, b.items7))) return st;
+    if ((st = upload(c, c->d_items8, b.items8))) return st;
+    if ((st = upload(c, c->d_gcount, b.gcount))) return st;
+    HIPCHK(c, c->B.ensure(F));
+    if (precision == FSIC_FP64) {
+        HIPCHK(c, c->R.ensure(F));
+        HIPCHK(c, c->P0.ensure(F));
+        HIPCHK(c, c->P1.ensure(F));
+        HIPCHK(c, c->Q.ensure(F));
+    } else {
+        HIPCHK(c, c->R32.ensure(F));
+        HIPCHK(c, c->P32a.ensure(F));
+        HIPCHK(c, c->P32b.ensure(F));
+        HIPCHK(c, c->Q32.ensure(F));
+        HIPCHK(c, c->X32.ensure(F));
+    }
+    const int norb = (int)b.orb.size();
+    const int nlm = (c->opts.lmax + 1) * (c->opts.lmax + 1);
+    HIPCHK(c, c->Gh.ensure((size_t)b.ghosts));
+    HIPCHK(c, c->part7.ensure((size_t)b.tot7));
+    HIPCHK(c, c->partRU.ensure((size_t)b.tot7));
+    HIPCHK(c, c->part8.ensure(2 * (size_t)b.tot8));
+    HIPCHK(c, c->partQ.ensure((size_t)b.tot8 * kMaxLM));
+    HIPCHK(c, c->partZ.ensure((size_t)norb * 64 * kMaxLM));
+    HIPCHK(c, c->bb.ensure(norb));
+    HIPCHK(c, c->rrfin.ensure(norb));
+    HIPCHK(c, c->relres.ensure(norb));
+    HIPCHK(c, c->ptrue.ensure(norb));
+    HIPCHK(c, c->Qlm.ensure((size_t)norb * nlm));
+    HIPCHK(c, c->Zt.ensure((size_t)norb * nlm));
+    HIPCHK(c, c->done.ensure(norb));
+    HIPCHK(c, c->iters.ensure(norb));
+    if (c->h_done_cap < (size_t)norb) {
+        if (c->h_done) hipHostFree(c->h_done);
+        c->h_done = nullptr;
+        HIPCHK(c, hipHostMalloc((void **)&c->h_done, std::max(norb, 1) * sizeof(int)));
+        c->h_done_cap = norb;
+    }
+    return FSIC_OK;
+}
+
+struct SolveReport {
+    int max_iters = 0;
+    long long total_iters = 0;
+    int refinements = 0;
+    double max_relres = 0.0;
+    bool converged = true;
+};
+
+// Solve -L x = scale * rho (+ boundary term) for every orbital of batch b.
+//   src: densities (square = 0) or orbitals (square = 1), field layout of b;
+//   with_bc: Dirichlet values from the multipole expansion (else zero);
+//   X: solution (field layout of b).
+fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int square, double scale,
+                        bool with_bc, double *X, int precision, double tol, int max_iter,
+                        SolveReport &rep) {
+    hipStream_t s = c->stream;
+    const int norb = (int)b.orb.size();
+    const int nlm = (c->opts.lmax + 1) * (c->opts.lmax + 1);
+    const int nit7 = (int)b.items7.size(), nit8 = (int)b.items8.size();
+    const bool mixed = precision == FSIC_MIXED;
+    if (with_bc) {
+        HIPCHK(c, launch_moments(c->opts.lmax, c->ht, norb, c->d_orb.p, c->d_items8.p, nit8, src,
+                                 square, c->partQ.p, b.tot8, c->Qlm.p, s));
+        HIPCHK(c, launch_ghosts(c->radius, c->opts.lmax, c->ht, norb, c->d_orb.p, c->d_gcount.p,
+                                c->Qlm.p, c->Gh.p, b.max_ghost, s));
+    }
+    (void)nlm;
+    // b, r0 = b, x64 = 0 (mixed), ||b||^2 partials in part8 slot 0
+    HIPCHK(c, launch_rhs(c->radius, c->cf, c->d_items8.p, nit8, c->d_orb.p, src, square, scale,
+                         with_bc ? c->Gh.p : nullptr, c->B.p, mixed ? nullptr : c->R.p,
+                         mixed ? c->R32.p : nullptr, mixed ? X : nullptr, c->part8.p, s));
+    HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->part8.p, 0, c->bb.p, s));
+    HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
+    HIPCHK(c, hipMemsetAsync(c->iters.p, 0, norb * sizeof(int), s));
+    const double tol2 = tol * tol;
+    const int chunk = 32;
+    int k = 0;
+    bool all_done = false;
+    // profiling: one event pair per launch, recorded on the context's stream
+    const bool prof = (c->opts.flags & FSIC_PROFILE) != 0;
+    struct Rec { int kind, k, flag; hipEvent_t a, b; };  // kind 0 sweep, 1 update; flag: first access
+    std::vector<Rec> recs;
+    size_t evn = 0;
+    auto ev_pair = [&](hipEvent_t &a, hipEvent_t &b) -> hipError_t {
+        while (c->ev.size() < evn + 2) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            c->ev.push_back(e);
+        }
+        a = c->ev[evn];
+        b = c->ev[evn + 1];
+        evn += 2;
+        return hipSuccess;
+    };
+#define PROF_BEGIN(kind_, k_, flag_)                                   \
+    hipEvent_t _ea = nullptr, _eb = nullptr;                            \
+    if (prof) {                                                         \
+        HIPCHK(c, ev_pair(_ea, _eb));                                   \
+        HIPCHK(c, hipEventRecord(_ea, s));                              \
+        recs.push_back(Rec{kind_, k_, flag_, _ea, _eb});                \
+    }
+#define PROF_END() \
+    if (prof) HIPCHK(c, hipEventRecord(_eb, s));
+    if (!mixed) {
+        CGIter<double> a{};
+        a.items7 = c->d_items7.p; a.nitems7 = nit7;
+        a.items8 = c->d_items8.p; a.nitems8 = nit8;
+        a.orb = c->d_orb.p;
+        a.R = c->R.p; a.Q = c->Q.p; a.X = X;
+        a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.tot8 = b.tot8;
+        a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
+        a.tol2 = tol2;
+        while (k < max_iter + 1 && !all_done) {
+            const int kend = std::min(k + chunk, max_iter + 1);
+            for (; k < kend; ++k) {
+                a.Pold = (k & 1) ? c->P0.p : c->P1.p;
+                a.Pnew = (k & 1) ? c->P1.p : c->P0.p;
+                {
+                    PROF_BEGIN(0, k, k == 0)
+                    HIPCHK(c, launch_cg_stencil<double>(c->radius, c->cf, a, k, 0, 0, 1, s));
+                    PROF_END()
+                }
+                if (k < max_iter) {
+                    PROF_BEGIN(1, k, k == 0)
+                    HIPCHK(c, launch_cg_update<double>(a, k, 0, k == 0, s));
+                    PROF_END()
+                }
+            }
+            HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            all_done = true;
+            for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o];
+        }
+        // true FP64 residual of the final iterate
+        HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
+                                       X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
+        HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
+    } else {
+        CGIter<float> a{};
+        a.items7 = c->d_items7.p; a.nitems7 = nit7;
+        a.items8 = c->d_items8.p; a.nitems8 = nit8;
+        a.orb = c->d_orb.p;
+        a.R = c->R32.p; a.Q = c->Q32.p; a.X = c->X32.p;
+        a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.tot8 = b.tot8;
+        a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
+        a.tol2 = tol2;
+        int nref = 0;
+        while (k < max_iter && !all_done) {
+            const int kstart = k;
+            const int kend = std::min(k + chunk, max_iter);
+            for (; k < kend; ++k) {
+                const int j = k - kstart;
+                a.Pold = (k & 1) ? c->P32a.p : c->P32b.p;
+                a.Pnew = (k & 1) ? c->P32b.p : c->P32a.p;
+                const int cur_ru = (j == 0 && k > 0);
+                const int prev_ru = (j == 1 && k - 1 > 0);
+                {
+                    PROF_BEGIN(0, k, k == 0)
+                    HIPCHK(c, launch_cg_stencil<float>(c->radius, c->cf, a, k, cur_ru, prev_ru, cur_ru, s));
+                    PROF_END()
+                }
+                {
+                    PROF_BEGIN(1, k, j == 0)
+                    HIPCHK(c, launch_cg_update<float>(a, k, cur_ru, j == 0, s));
+                    PROF_END()
+                }
+            }
+            // reliable update: FP64 residual of x64 + x32, then x64 += x32
+            HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p,
+                                           c->done.p, X, c->X32.p, c->B.p, nullptr, c->R32.p,
+                                           c->partRU.p, s));
+            HIPCHK(c, launch_mixed_accumulate(nit8, c->d_items8.p, c->d_orb.p, c->done.p, X, c->X32.p, s));
+            HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, k, c->done.p,
+                                      c->iters.p, c->rrfin.p, s));
+            ++nref;
+            HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            all_done = true;
+            for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o];
+        }
+        rep.refinements += nref * norb;
+        // final report: FP64 residual of x64 (x32 already folded in)
+        HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
+                                       X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
+        HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
+    }
+    std::vector<int> it(norb);
+    std::vector<double> pt(norb), bbh(norb);
+    HIPCHK(c, hipMemcpyAsync(it.data(), c->iters.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(pt.data(), c->ptrue.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(bbh.data(), c->bb.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    std::vector<int> active_until(norb);
+    for (int o = 0; o < norb; ++o) {
+        const int itv = c->h_done[o] ? it[o] : max_iter;
+        active_until[o] = itv;
+        rep.max_iters = std::max(rep.max_iters, itv);
+        rep.total_iters += itv;
+        const double rr = bbh[o] > 0 ? std::sqrt(pt[o] / bbh[o]) : 0.0;
+        rep.max_relres = std::max(rep.max_relres, rr);
+        if (!c->h_done[o]) rep.converged = false;
+    }
+    if (prof) {
+        // algorithmic bytes: every array of every orbital still iterating,
+        // read or written once (sweep: r, p_old, p, q; update: x, p, r, q, x, r)
+        const double esz = mixed ? 4.0 : 8.0;
+        for (const Rec &r : recs) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+            double nodes = 0.0;
+            for (int o = 0; o < norb; ++o)
+                if (r.k < active_until[o])
+                    nodes += (double)b.orb[o].nx * b.orb[o].ny * b.orb[o].nz;
+            if (r.kind == 0) {
+                c->sweep_launches += 1;
+                c->sweep_ms += ms;
+                c->sweep_bytes += nodes * esz * (r.flag ? 3.0 : 4.0);
+            } else {
+                c->update_launches += 1;
+                c->update_ms += ms;
+                c->update_bytes += nodes * esz * (r.flag ? 5.0 : 6.0);
+            }
+        }
+    }
+#undef PROF_BEGIN
+#undef PROF_END
+    return FSIC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+fsic_status fsic_default_opts(fsic_opts *o) {
+    if (!o) return FSIC_EINVAL;
+    o->fd_order = 12;
+    o->lmax = 6;
+    o->solver = FSIC_CG;
+    o->precision = FSIC_FP64;
+    o->tol = 1e-10;
+    o->max_iter = 20000;
+    o->vsic_scale = 1.0;
+    o->rho_floor = 1e-30;
+    o->s_eig_floor = 1e-12;
+    o->flags = FSIC_WANT_VSIC;
+    return FSIC_OK;
+}
+
+const char *fsic_status_string(fsic_status s) {
+    switch (s) {
+        case FSIC_OK: return "ok";
+        case FSIC_EINVAL: return "invalid argument";
+        case FSIC_ENOMEM: return "out of memory";
+        case FSIC_EHIP: return "HIP runtime error";
+        case FSIC_ENONORTHO: return "input orbitals are not orthonormal on the grid";
+        case FSIC_EVACUUM: return "FOD in vacuum: rho(a_i) <= rho_floor";
+        case FSIC_EBOUNDARY: return "FOD interpolation stencil leaves the grid";
+        case FSIC_ESINGULAR: return "Fermi-orbital overlap is singular";
+        case FSIC_ENOCONV: return "Poisson solve did not converge";
+        case FSIC_ENOTAPE: return "no forward tape for backward";
+    }
+    return "unknown status";
+}
+
+const char *fsic_last_error(const fsic_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+fsic_status fsic_create(fsic_ctx **ctx, const fsic_opts *opts, void *hip_stream) {
+    if (!ctx) return FSIC_EINVAL;
+    *ctx = nullptr;
+    std::string why;
+    fsic_status st = validate_opts(opts, why);
+    if (st) return st;
+    fsic_ctx *c = new (std::nothrow) fsic_ctx();
+    if (!c) return FSIC_ENOMEM;
+    c->opts = *opts;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return FSIC_EHIP; }
+    c->radius = opts->fd_order / 2;
+    c->cf = fd_weights(c->radius);
+    c->ht = harm_tables(opts->lmax);
+    if (c->status.ensure(1) != hipSuccess) { delete c; return FSIC_ENOMEM; }
+    *ctx = c;
+    return FSIC_OK;
+}
+
+fsic_status fsic_set_opts(fsic_ctx *c, const fsic_opts *opts) {
+    if (!c) return FSIC_EINVAL;
+    std::string why;
+    fsic_status st = validate_opts(opts, why);
+    if (st) return set_err(c, st, why);
+    c->opts = *opts;
+    c->radius = opts->fd_order / 2;
+    c->cf = fd_weights(c->radius);
+    c->ht = harm_tables(opts->lmax);
+    c->tape = false;
+    return FSIC_OK;
+}
+
+void fsic_destroy(fsic_ctx *c) {
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    c->PHI.release(); c->V.release(); c->W.release(); c->B.release(); c->R.release();
+    c->P0.release(); c->P1.release(); c->Q.release(); c->X64b.release();
+    c->R32.release(); c->P32a.release(); c->P32b.release(); c->Q32.release(); c->X32.release();
+    c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
+    c->partQ.release(); c->partZ.release(); c->bb.release(); c->rrfin.release();
+    c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release();
+    c->done.release(); c->iters.release(); c->d_orb.release(); c->d_items7.release();
+    c->d_items8.release(); c->d_gcount.release(); c->small.release(); c->work.release();
+    c->partG.release(); c->d_cells.release(); c->d_chan.release(); c->d_blkchan.release();
+    c->partU.release(); c->partX.release(); c->Uo.release(); c->Xo.release(); c->Ech.release();
+    c->status.release(); c->bmat.release();
+    for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    if (c->h_done) hipHostFree(c->h_done);
+    delete c;
+}
+
+fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, double *e_sic,
+                         double *Uout, double *Xout, fsic_stats *st) {
+    if (!c) return FSIC_EINVAL;
+    const double t0 = now_ms();
+    if (nsys < 1 || !sys || !e_sic) return set_err(c, FSIC_EINVAL, "nsys >= 1, sys and e_sic are required");
+    c->tape = false;
+    const fsic_opts &o = c->opts;
+    const int P = c->radius;
+    std::string why;
+    // ---- validation and plan (host) ----
+    std::vector<Chan> chans;
+    long long off = 0;
+    int first = 0;
+    for (int k = 0; k < nsys; ++k) {
+        const fsic_system &sy = sys[k];
+        fsic_status vs = validate_grid(sy.grid, why);
+        if (vs) return set_err(c, vs, "system " + std::to_string(k) + ": " + why);
+        if (sy.nspin < 1 || sy.nspin > 2) return set_err(c, FSIC_EINVAL, "nspin must be 1 or 2");
+        const long long M = (long long)sy.grid.n[0] * sy.grid.n[1] * sy.grid.n[2];
+        for (int s = 0; s < sy.nspin; ++s) {
+            const int N = sy.nocc[s];
+            if (N < 1 || N > kMaxOrb) return set_err(c, FSIC_EINVAL, "nocc must be in [1, 128]");
+            if (!sy.psi[s] || !sy.fod[s]) return set_err(c, FSIC_EINVAL, "psi and fod are required");
+            Chan ch{};
+            ch.sys = k; ch.spin = s; ch.N = N;
+            for (int d = 0; d < 3; ++d) { ch.n[d] = sy.grid.n[d]; ch.origin[d] = sy.grid.origin[d]; }
+            ch.h = sy.grid.h;
+            ch.M = M;
+            ch.psi = sy.psi[s];
+            ch.fod.assign(sy.fod[s], sy.fod[s] + 3 * N);
+            ch.first_orb = first;
+            ch.off = off;
+            ch.cells.resize(N);
+            for (int i = 0; i < N; ++i) {
+                FodCell cl{};
+                for (int d = 0; d < 3; ++d) {
+                    const double a = ch.fod[3 * i + d];
+                    if (!std::isfinite(a)) return set_err(c, FSIC_EINVAL, "non-finite FOD coordinate");
+                    const double sc = (a - ch.origin[d]) / ch.h;
+                    const double fl = std::floor(sc);
+                    if (fl < 1.0 || fl > (double)(ch.n[d] - 3))
+                        return set_err(c, FSIC_EBOUNDARY, "system " + std::to_string(k) + " spin " + std::to_string(s) +
+                                                              " FOD " + std::to_string(i) + ": interpolation stencil leaves the grid");
+                    cl.i0[d] = (int)fl;
+                    cl.t[d] = sc - fl;
+                }
+                ch.cells[i] = cl;
+            }
+            off += (long long)N * M;
+            first += N;
+            chans.push_back(std::move(ch));
+        }
+    }
+    const size_t F = (size_t)off;
+    const int nchan = (int)chans.size();
+    const int norb = first;
+    std::vector<Group> groups;
+    for (int ci = 0; ci < nchan; ++ci) {
+        const Chan &ch = chans[ci];
+        Group g{};
+        for (int d = 0; d < 3; ++d) { g.n[d] = ch.n[d]; g.origin[d] = ch.origin[d]; }
+        g.h = ch.h; g.count = ch.N; g.off = ch.off; g.chan = ci;
+        groups.push_back(g);
+    }
+    Batch b;
+    build_batch(groups, P, b);
+    // channel descriptors for the average pass
+    std::vector<ChanDesc> cd(nchan);
+    std::vector<int> blkchan;
+    int nblk_total = 0;
+    for (int ci = 0; ci < nchan; ++ci) {
+        Chan &ch = chans[ci];
+        ch.nblk = (int)((ch.M + kPW - 1) / kPW);
+        ch.blk_base = nblk_total;
+        nblk_total += ch.nblk;
+        for (int t = 0; t < ch.nblk; ++t) blkchan.push_back(ci);
+        ChanDesc &d = cd[ci];
+        d.N = ch.N; d.first_orb = ch.first_orb; d.M = ch.M; d.off = ch.off;
+        d.nx = ch.n[0]; d.ny = ch.n[1]; d.nz = ch.n[2];
+        d.nblk = ch.nblk; d.blk_base = ch.blk_base; d.h = ch.h; d.vscale = o.vsic_scale;
+        d.vsic = (o.flags & FSIC_WANT_VSIC) ? sys[ch.sys].vsic[ch.spin] : nullptr;
+        ch.so = (size_t)ci * kSmallStride;
+    }
+    // ---- buffers ----
+    hipStream_t s = c->stream;
+    HIPCHK(c, c->PHI.ensure(F));
+    HIPCHK(c, c->V.ensure(F));
+    fsic_status pst = prepare_batch(c, b, o.precision);
+    if (pst) return pst;
+    HIPCHK(c, c->small.ensure((size_t)nchan * kSmallStride));
+    HIPCHK(c, c->work.ensure(4 * (size_t)kMaxOrb * kMaxOrb));
+    const int gram_blk = 256;
+    c->sweep_launches = c->update_launches = 0;
+    c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
+    HIPCHK(c, c->partG.ensure((size_t)gram_blk * kMaxOrb * kMaxOrb));
+    std::vector<FodCell> cells;
+    for (const Chan &ch : chans) cells.insert(cells.end(), ch.cells.begin(), ch.cells.end());
+    fsic_status ust;
+    if ((ust = upload(c, c->d_cells, cells))) return ust;
+    if ((ust = upload(c, c->d_chan, cd))) return ust;
+    if ((ust = upload(c, c->d_blkchan, blkchan))) return ust;
+    HIPCHK(c, c->partU.ensure((size_t)nblk_total * kMaxOrb));
+    HIPCHK(c, c->partX.ensure((size_t)nblk_total * kMaxOrb));
+    HIPCHK(c, c->Uo.ensure(norb));
+    HIPCHK(c, c->Xo.ensure(norb));
+    HIPCHK(c, c->Ech.ensure(nchan));
+    HIPCHK(c, hipMemsetAsync(c->status.p, 0, sizeof(int), s));
+    const double t1 = now_ms();
+
+    // ---- (a) Fermi orbitals, (b) Loewdin: per channel ----
+    int cell_base = 0;
+    for (int ci = 0; ci < nchan; ++ci) {
+        const Chan &ch = chans[ci];
+        double *sm = c->small.p + ch.so;
+        const double dV = ch.h * ch.h * ch.h;
+        HIPCHK(c, launch_interp(ch.N, ch.n[0], ch.n[1], ch.n[2], ch.h, ch.psi, c->d_cells.p + cell_base,
+                                o.rho_floor, sm + small_off(sU_), sm + small_off(sDU),
+                                sm + small_off(sRHOA), sm + small_off(sT), c->status.p, s));
+        HIPCHK(c, launch_gram(ch.N, ch.M, dV, ch.psi, c->partG.p, gram_blk, sm + small_off(sG), s));
+        HIPCHK(c, launch_lowdin(ch.N, sm + small_off(sT), sm + small_off(sG), sm + small_off(sS),
+                                sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
+                                sm + small_off(sQ), c->work.p, o.s_eig_floor, c->status.p,
+                                sm + small_off(sINFO), s));
+        cell_base += ch.N;
+    }
+    // device-detected problems stop the pass before the solves
+    int hstatus = 0;
+    HIPCHK(c, hipMemcpyAsync(&hstatus, c->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (hstatus & kStNonFinite) return set_err(c, FSIC_EINVAL, "non-finite orbital values at an FOD");
+    if (hstatus & kStVacuum) return set_err(c, FSIC_EVACUUM, "an FOD lies where rho(a_i) <= rho_floor");
+    if (hstatus & kStSingular) {
+        double info[2] = {0, 0};
+        for (const Chan &ch : chans) {
+            double h2[2];
+            if (hipMemcpy(h2, c->small.p + ch.so + small_off(sINFO), sizeof(h2), hipMemcpyDeviceToHost) == hipSuccess &&
+                (info[1] == 0 || h2[1] < info[1])) { info[0] = h2[0]; info[1] = h2[1]; }
+        }
+        return set_err(c, FSIC_ESINGULAR, "smallest eigenvalue of S = " + std::to_string(info[1]) +
+                                              " below s_eig_floor");
+    }
+    // orthonormality of the input and overlap statistics (N x N, host)
+    double nonortho = 0.0, condmax = 0.0, minrho = 1e300;
+    for (int ci = 0; ci < nchan; ++ci) {
+        const Chan &ch = chans[ci];
+        const double *sm = c->small.p + ch.so;
+        std::vector<double> G((size_t)ch.N * ch.N), info(2), rhoa(ch.N);
+        HIPCHK(c, hipMemcpy(G.data(), sm + small_off(sG), G.size() * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(info.data(), sm + small_off(sINFO), 2 * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(rhoa.data(), sm + small_off(sRHOA), ch.N * sizeof(double), hipMemcpyDeviceToHost));
+        for (int i = 0; i < ch.N; ++i) {
+            for (int j = 0; j < ch.N; ++j) {
+                const double g = G[(size_t)i * ch.N + j];
+                if (!std::isfinite(g)) return set_err(c, FSIC_EINVAL, "non-finite values in psi");
+                nonortho = std::max(nonortho, std::fabs(g - (i == j ? 1.0 : 0.0)));
+            }
+            minrho = std::min(minrho, rhoa[i]);
+        }
+        condmax = std::max(condmax, info[0]);
+    }
+    if (!(o.flags & FSIC_ALLOW_NONORTHO) && nonortho > 1e-8)
+        return set_err(c, FSIC_ENONORTHO, "max |dV psi psi^T - I| = " + std::to_string(nonortho));
+    // phi = Q psi on the matrix cores
+    for (int ci = 0; ci < nchan; ++ci) {
+        const Chan &ch = chans[ci];
+        HIPCHK(c, launch_orb_gemm(ch.N, ch.M, c->small.p + ch.so + small_off(sQ), ch.psi, c->PHI.p + ch.off, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    const double t2 = now_ms();
+
+    // ---- (c) Poisson solves for all orbitals at once ----
+    SolveReport rep;
+    fsic_status sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, true, c->V.p, o.precision, o.tol,
+                                  o.max_iter, rep);
+    if (sst) return sst;
+    const double t3 = now_ms();
+
+    // ---- (d) XC, (e) Slater average and energies ----
+    HIPCHK(c, launch_sic_average(nchan, c->d_chan.p, nblk_total, c->d_blkchan.p, c->PHI.p, c->V.p,
+                                 o.rho_floor, c->partU.p, c->partX.p, s));
+    HIPCHK(c, launch_sic_energy(nchan, c->d_chan.p, c->partU.p, c->partX.p, c->Uo.p, c->Xo.p, c->Ech.p, s));
+    std::vector<double> ech(nchan), uo(norb), xo(norb);
+    HIPCHK(c, hipMemcpyAsync(ech.data(), c->Ech.p, nchan * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(uo.data(), c->Uo.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(xo.data(), c->Xo.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int k = 0; k < nsys; ++k) e_sic[k] = 0.0;
+    for (int ci = 0; ci < nchan; ++ci) e_sic[chans[ci].sys] += ech[ci];
+    if (Uout) std::memcpy(Uout, uo.data(), norb * sizeof(double));
+    if (Xout) std::memcpy(Xout, xo.data(), norb * sizeof(double));
+    const double t4 = now_ms();
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->nsolves = norb;
+        st->max_iters = rep.max_iters;
+        st->total_iters = rep.total_iters;
+        st->outer_refinements = rep.refinements;
+        st->max_relres = rep.max_relres;
+        st->cond_S_max = condmax;
+        st->min_rho_fod = minrho;
+        st->max_nonortho = nonortho;
+        st->ms_phase[0] = t1 - t0;
+        st->ms_phase[1] = t2 - t1;
+        st->ms_phase[3] = t3 - t2;
+        st->ms_phase[4] = t4 - t3;
+        st->ms_phase[7] = t4 - t0;
+        st->sweep_launches = c->sweep_launches;
+        st->update_launches = c->update_launches;
+        st->sweep_ms = c->sweep_ms;
+        st->sweep_bytes = c->sweep_bytes;
+        st->update_ms = c->update_ms;
+        st->update_bytes = c->update_bytes;
+    }
+    c->chans = std::move(chans);
+    c->batch = std::move(b);
+    c->nsys = nsys;
+    c->tape = (o.flags & FSIC_KEEP_TAPE) != 0;
+    if (!rep.converged) return set_err(c, FSIC_ENOCONV, "a Poisson solve missed tol within max_iter");
+    return FSIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator-level entry points
+// ---------------------------------------------------------------------------
+
+namespace {
+struct OpCtx {
+    fsic_ctx *c = nullptr;
+    ~OpCtx() { fsic_destroy(c); }
+};
+}  // namespace
+
+fsic_status fsic_op_laplacian(const int32_t *n, double h, int32_t fd_order, int32_t count,
+                              const double *u, double *Lu, void *hip_stream) {
+    if (!n || !u || !Lu || count < 1 || fd_order < 2 || fd_order > 12 || (fd_order & 1))
+        return FSIC_EINVAL;
+    fsic_grid g{{n[0], n[1], n[2]}, h, {0, 0, 0}};
+    std::string why;
+    if (validate_grid(g, why)) return FSIC_EINVAL;
+    const int P = fd_order / 2;
+    std::vector<Group> groups(1);
+    for (int d = 0; d < 3; ++d) { groups[0].n[d] = n[d]; groups[0].origin[d] = 0.0; }
+    groups[0].h = h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
+    Batch b;
+    build_batch(groups, P, b);
+    hipStream_t s = (hipStream_t)hip_stream;
+    DBuf<OrbDesc> dorb;
+    DBuf<Item> dit;
+    if (dorb.ensure(b.orb.size()) || dit.ensure(b.items7.size())) return FSIC_ENOMEM;
+    hipMemcpyAsync(dorb.p, b.orb.data(), b.orb.size() * sizeof(OrbDesc), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dit.p, b.items7.data(), b.items7.size() * sizeof(Item), hipMemcpyHostToDevice, s);
+    hipError_t e = launch_apply<double>(P, fd_weights(P), dit.p, (int)b.items7.size(), dorb.p, u, Lu, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    dorb.release();
+    dit.release();
+    return (e || e2) ? FSIC_EHIP : FSIC_OK;
+}
+
+fsic_status fsic_op_laplacian_f32(const int32_t *n, double h, int32_t fd_order, int32_t count,
+                                  const float *u, float *Lu, void *hip_stream) {
+    if (!n || !u || !Lu || count < 1 || fd_order < 2 || fd_order > 12 || (fd_order & 1))
+        return FSIC_EINVAL;
+    fsic_grid g{{n[0], n[1], n[2]}, h, {0, 0, 0}};
+    std::string why;
+    if (validate_grid(g, why)) return FSIC_EINVAL;
+    const int P = fd_order / 2;
+    std::vector<Group> groups(1);
+    for (int d = 0; d < 3; ++d) { groups[0].n[d] = n[d]; groups[0].origin[d] = 0.0; }
+    groups[0].h = h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
+    Batch b;
+    build_batch(groups, P, b);
+    hipStream_t s = (hipStream_t)hip_stream;
+    DBuf<OrbDesc> dorb;
+    DBuf<Item> dit;
+    if (dorb.ensure(b.orb.size()) || dit.ensure(b.items7.size())) return FSIC_ENOMEM;
+    hipMemcpyAsync(dorb.p, b.orb.data(), b.orb.size() * sizeof(OrbDesc), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dit.p, b.items7.data(), b.items7.size() * sizeof(Item), hipMemcpyHostToDevice, s);
+    hipError_t e = launch_apply<float>(P, fd_weights(P), dit.p, (int)b.items7.size(), dorb.p, u, Lu, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    dorb.release();
+    dit.release();
+    return (e || e2) ? FSIC_EHIP : FSIC_OK;
+}
+
+fsic_status fsic_op_xc(int64_t count, const double *rho, double rho_floor, double *ex, double *ec,
+                       double *vx, double *vc, void *hip_stream) {
+    if (count < 0 || (count > 0 && !rho) || !(rho_floor >= 0.0)) return FSIC_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = launch_xc_pointwise(count, rho, rho_floor, ex, ec, vx, vc, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    return (e || e2) ? FSIC_EHIP : FSIC_OK;
+}
+
+fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lmax, int32_t count,
+                            const double *rho, double *v, double tol, int32_t max_iter,
+                            int32_t precision, int32_t *iters, double *relres, void *hip_stream) {
+    if (!grid || !rho || !v || count < 1) return FSIC_EINVAL;
+    fsic_opts o;
+    fsic_default_opts(&o);
+    o.fd_order = fd_order;
+    o.lmax = lmax;
+    o.tol = tol;
+    o.max_iter = max_iter;
+    o.precision = precision;
+    std::string why;
+    if (validate_opts(&o, why) || validate_grid(*grid, why)) return FSIC_EINVAL;
+    OpCtx oc;
+    fsic_status st = fsic_create(&oc.c, &o, hip_stream);
+    if (st) return st;
+    fsic_ctx *c = oc.c;
+    std::vector<Group> groups(1);
+    for (int d = 0; d < 3; ++d) { groups[0].n[d] = grid->n[d]; groups[0].origin[d] = grid->origin[d]; }
+    groups[0].h = grid->h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
+    Batch b;
+    build_batch(groups, c->radius, b);
+    st = prepare_batch(c, b, precision);
+    if (st) return st;
+    SolveReport rep;
+    st = solve_batch(c, b, rho, 0, 4.0 * M_PI, true, v, precision, tol, max_iter, rep);
+    if (st) return st;
+    std::vector<int> it(count);
+    std::vector<double> pt(count), bbh(count);
+    hipMemcpy(it.data(), c->iters.p, count * sizeof(int), hipMemcpyDeviceToHost);
+    hipMemcpy(pt.data(), c->ptrue.p, count * sizeof(double), hipMemcpyDeviceToHost);
+    hipMemcpy(bbh.data(), c->bb.p, count * sizeof(double), hipMemcpyDeviceToHost);
+    std::vector<int> dn(count);
+    hipMemcpy(dn.data(), c->done.p, count * sizeof(int), hipMemcpyDeviceToHost);
+    for (int f = 0; f < count; ++f) {
+        if (iters) iters[f] = dn[f] ? it[f] : max_iter;
+        if (relres) relres[f] = bbh[f] > 0 ? std::sqrt(pt[f] / bbh[f]) : 0.0;
+    }
+    return rep.converged ? FSIC_OK : FSIC_ENOCONV;
+}
+
+fsic_status fsic_op_invsqrt(int32_t N, int32_t count, const double *S, double *Z, double *lam,
+                            void *hip_stream) {
+    if (N < 1 || N > kMaxOrb || count < 1 || !S || !Z) return FSIC_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t NN = (size_t)N * N;
+    DBuf<double> T, tmp, work, info;
+    DBuf<int> status;
+    if (T.ensure(NN) || tmp.ensure(5 * NN) || work.ensure(3 * (size_t)kMaxOrb * kMaxOrb) ||
+        info.ensure(2) || status.ensure(1))
+        return FSIC_ENOMEM;
+    std::vector<double> eye(NN, 0.0);
+    for (int i = 0; i < N; ++i) eye[(size_t)i * N + i] = 1.0;
+    hipMemcpyAsync(T.p, eye.data(), NN * sizeof(double), hipMemcpyHostToDevice, s);
+    hipMemsetAsync(status.p, 0, sizeof(int), s);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < count && e == hipSuccess; ++k) {
+        double *lamk = lam ? lam + (size_t)k * N : tmp.p + 4 * NN;
+        e = launch_lowdin(N, T.p, S + k * NN, tmp.p, lamk, tmp.p + NN, Z + k * NN, tmp.p + 2 * NN,
+                          work.p, 0.0, status.p, info.p, s);
+    }
+    hipError_t e2 = hipStreamSynchronize(s);
+    int hs = 0;
+    hipMemcpy(&hs, status.p, sizeof(int), hipMemcpyDeviceToHost);
+    T.release(); tmp.release(); work.release(); info.release(); status.release();
+    if (e || e2) return FSIC_EHIP;
+    return (hs & kStSingular) ? FSIC_ESINGULAR : FSIC_OK;
+}
+
+fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, const double *fod,
+                        double rho_floor, double *T, double *G, double *S, double *Z, double *phi,
+                        void *hip_stream) {
+    if (!grid || !psi || !fod || N < 1 || N > kMaxOrb || !(rho_floor >= 0.0)) return FSIC_EINVAL;
+    std::string why;
+    if (validate_grid(*grid, why)) return FSIC_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<FodCell> cells(N);
+    for (int i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double a = fod[3 * i + d];
+            if (!std::isfinite(a)) return FSIC_EINVAL;
+            const double sc = (a - grid->origin[d]) / grid->h;
+            const double fl = std::floor(sc);
+            if (fl < 1.0 || fl > (double)(grid->n[d] - 3)) return FSIC_EBOUNDARY;
+            cells[i].i0[d] = (int)fl;
+            cells[i].t[d] = sc - fl;
+        }
+    const long long M = (long long)grid->n[0] * grid->n[1] * grid->n[2];
+    const double dV = grid->h * grid->h * grid->h;
+    DBuf<double> sm, work, partG;
+    DBuf<FodCell> dc;
+    DBuf<int> status;
+    if (sm.ensure(kSmallStride) || work.ensure(3 * (size_t)kMaxOrb * kMaxOrb) ||
+        partG.ensure(256 * (size_t)kMaxOrb * kMaxOrb) || dc.ensure(N) || status.ensure(1))
+        return FSIC_ENOMEM;
+    hipError_t e = hipMemcpyAsync(dc.p, cells.data(), N * sizeof(FodCell), hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemsetAsync(status.p, 0, sizeof(int), s);
+    double *b = sm.p;
+    if (!e) e = launch_interp(N, grid->n[0], grid->n[1], grid->n[2], grid->h, psi, dc.p, rho_floor,
+                              b + small_off(sU_), b + small_off(sDU), b + small_off(sRHOA),
+                              b + small_off(sT), status.p, s);
+    if (!e) e = launch_gram(N, M, dV, psi, partG.p, 256, b + small_off(sG), s);
+    if (!e) e = launch_lowdin(N, b + small_off(sT), b + small_off(sG), b + small_off(sS),
+                              b + small_off(sLAM), b + small_off(sEV), b + small_off(sZ),
+                              b + small_off(sQ), work.p, 0.0, status.p, b + small_off(sINFO), s);
+    if (!e && phi) e = launch_orb_gemm(N, M, b + small_off(sQ), psi, phi, s);
+    const size_t NN = (size_t)N * N * sizeof(double);
+    if (!e && T) e = hipMemcpyAsync(T, b + small_off(sT), NN, hipMemcpyDeviceToDevice, s);
+    if (!e && G) e = hipMemcpyAsync(G, b + small_off(sG), NN, hipMemcpyDeviceToDevice, s);
+    if (!e && S) e = hipMemcpyAsync(S, b + small_off(sS), NN, hipMemcpyDeviceToDevice, s);
+    if (!e && Z) e = hipMemcpyAsync(Z, b + small_off(sZ), NN, hipMemcpyDeviceToDevice, s);
+    int hs = 0;
+    if (!e) e = hipMemcpyAsync(&hs, status.p, sizeof(int), hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    sm.release(); work.release(); partG.release(); dc.release(); status.release();
+    if (e || e2) return FSIC_EHIP;
+    if (hs & kStVacuum) return FSIC_EVACUUM;
+    if (hs & kStSingular) return FSIC_ESINGULAR;
+    return FSIC_OK;
+}
+
+fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_da, fsic_stats *st) {
+    if (!c) return FSIC_EINVAL;
+    if (!c->tape) return set_err(c, FSIC_ENOTAPE, "backward needs a forward pass with FSIC_KEEP_TAPE");
+    if (!dE_da) return set_err(c, FSIC_EINVAL, "dE_da is required");
+    for (int k = 0; k < c->nsys; ++k)
+        if (!dE_da[k]) return set_err(c, FSIC_EINVAL, "dE_da[k] is required for every system");
+    const double t0 = now_ms();
+    const fsic_opts &o = c->opts;
+    const Batch &b = c->batch;
+    hipStream_t s = c->stream;
+    const int norb = (int)b.orb.size();
+    c->sweep_launches = c->update_launches = 0;
+    c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
+    fsic_status pst = prepare_batch(c, b, o.precision);
+    if (pst) return pst;
+    HIPCHK(c, c->W.ensure((size_t)b.fields));
+    HIPCHK(c, c->bmat.ensure((size_t)kMaxOrb * kMaxOrb));
+    // adjoint solves: K w' = 4 pi rho_i with zero Dirichlet values
+    SolveReport rep;
+    fsic_status sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, false, c->W.p, o.precision, o.tol,
+                                  o.max_iter, rep);
+    if (sst) return sst;
+    const double t1 = now_ms();
+    // boundary part of A^T rho: zt = E_g^T C^T w' / (4 pi), then W += P^T zt
+    HarmTables hta = c->ht;
+    for (int q = 0; q < kMaxLM; ++q) hta.gfac[q] /= 4.0 * M_PI;
+    const int zchunks = 64;
+    HIPCHK(c, launch_adjoint_boundary(c->radius, o.lmax, hta, c->cf, norb, c->d_orb.p, c->d_gcount.p,
+                                      c->W.p, c->partZ.p, zchunks, c->Zt.p, b.max_ghost, s));
+    HIPCHK(c, launch_adj_field(o.lmax, c->ht, c->d_orb.p, c->d_items8.p, (int)b.items8.size(),
+                               c->Zt.p, c->W.p, s));
+    // per channel: B = Gam psi^T, then the N x N reverse chain
+    std::vector<int> spin0(c->nsys, 0);
+    for (const Chan &ch : c->chans)
+        if (ch.spin == 0) spin0[ch.sys] = ch.N;
+    std::vector<std::vector<double>> host(c->chans.size());
+    for (size_t ci = 0; ci < c->chans.size(); ++ci) {
+        const Chan &ch = c->chans[ci];
+        double *sm = c->small.p + ch.so;
+        const double dV = ch.h * ch.h * ch.h;
+        HIPCHK(c, launch_adjoint_contract(ch.N, ch.M, dV, c->PHI.p + ch.off, c->V.p + ch.off,
+                                          c->W.p + ch.off, ch.psi, o.rho_floor, c->partG.p, 256,
+                                          c->bmat.p, s));
+        HIPCHK(c, launch_lowdin_backward(ch.N, c->bmat.p, sm + small_off(sT), sm + small_off(sG),
+                                         sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
+                                         sm + small_off(sRHOA), sm + small_off(sDU), c->work.p,
+                                         sm + small_off(sDEDA), s));
+        host[ci].resize(3 * (size_t)ch.N);
+        HIPCHK(c, hipMemcpyAsync(host[ci].data(), sm + small_off(sDEDA), 3 * ch.N * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (size_t ci = 0; ci < c->chans.size(); ++ci) {
+        const Chan &ch = c->chans[ci];
+        const double ge = grad_e ? grad_e[ch.sys] : 1.0;
+        double *dst = dE_da[ch.sys] + 3 * (ch.spin == 0 ? 0 : spin0[ch.sys]);
+        for (int q = 0; q < 3 * ch.N; ++q) dst[q] = ge * host[ci][q];
+    }
+    const double t2 = now_ms();
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->nsolves = norb;
+        st->max_iters = rep.max_iters;
+        st->total_iters = rep.total_iters;
+        st->outer_refinements = rep.refinements;
+        st->max_relres = rep.max_relres;
+        st->ms_phase[5] = t1 - t0;
+        st->ms_phase[6] = t2 - t1;
+        st->ms_phase[7] = t2 - t0;
+        st->sweep_launches = c->sweep_launches;
+        st->update_launches = c->update_launches;
+        st->sweep_ms = c->sweep_ms;
+        st->sweep_bytes = c->sweep_bytes;
+        st->update_ms = c->update_ms;
+        st->update_bytes = c->update_bytes;
+    }
+    if (!rep.converged) return set_err(c, FSIC_ENOCONV, "an adjoint Poisson solve missed tol within max_iter");
+    return FSIC_OK;
+}
+
+}  // extern "C"

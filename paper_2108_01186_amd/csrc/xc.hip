@@ -1,0 +1,166 @@
+// LSDA exchange-correlation of each FLO density at full spin polarisation
+// (E_xc[rho_i, 0] of Eq. 1; LSDA exchange and PW92 correlation, Sec. III),
+// the orbital SIC potentials V_i = -(v_H[rho_i] + v_xc[rho_i, 0]) (Eq. 5),
+// their generalised-Slater average weighted by the FLO densities (Eq. 13,
+// optionally scaled), and the per-orbital Hartree and XC energies.
+//
+// One fused pass per spin channel: each thread owns nodes and walks the
+// orbitals, so phi_i and v_i are read once and V_SIC is written once.
+#include "kernels.h"
+
+namespace fsic {
+
+// (6/pi)^(1/3) and (3/(4 pi))^(1/3)
+constexpr double kSixOverPiCbrt = 1.2407009817988000333;
+constexpr double kRsCoef = 0.62035049089940001667;
+
+// Fully polarised LSDA at one density.
+//   exchange: eps_x = -(3/4)(6/pi)^(1/3) rho^(1/3), v_x = (4/3) eps_x
+//   correlation: PW92 interpolation G(rs) with the zeta = 1 parameters
+//     A = 0.015545, alpha1 = 0.20548, beta1..4 = 14.1189, 6.1977, 3.3662, 0.62517;
+//     v_c = eps_c - (rs/3) d eps_c / d rs (no zeta term at zeta = 1).
+__device__ __forceinline__ void lsda_pol(double rho, double floor, double &ex, double &ec,
+                                         double &vx, double &vc) {
+    if (!(rho > floor)) {
+        ex = ec = vx = vc = 0.0;
+        return;
+    }
+    const double r13 = cbrt(rho);
+    ex = -0.75 * kSixOverPiCbrt * r13;
+    vx = -kSixOverPiCbrt * r13;
+    constexpr double A = 0.015545, a1 = 0.20548;
+    constexpr double b1 = 14.1189, b2 = 6.1977, b3 = 3.3662, b4 = 0.62517;
+    const double rs = kRsCoef / r13;
+    const double s = sqrt(rs);
+    const double q1 = 2.0 * A * (s * (b1 + s * (b2 + s * (b3 + s * b4)))) ;
+    const double q1p = A * (b1 / s + 2.0 * b2 + 3.0 * b3 * s + 4.0 * b4 * rs);
+    const double lg = log1p(1.0 / q1);
+    const double q0 = -2.0 * A * (1.0 + a1 * rs);
+    ec = q0 * lg;
+    const double dec = -2.0 * A * a1 * lg - q0 * q1p / (q1 * (q1 + 1.0));
+    vc = ec - rs * dec * (1.0 / 3.0);
+}
+
+__global__ __launch_bounds__(256) void k_xc_pointwise(long long count, const double *rho,
+                                                      double floor, double *ex, double *ec,
+                                                      double *vx, double *vc) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    double a, b, c, d;
+    lsda_pol(rho[i], floor, a, b, c, d);
+    if (ex) ex[i] = a;
+    if (ec) ec[i] = b;
+    if (vx) vx[i] = c;
+    if (vc) vc[i] = d;
+}
+
+hipError_t launch_xc_pointwise(long long count, const double *rho, double floor, double *ex,
+                               double *ec, double *vx, double *vc, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xc_pointwise, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       count, rho, floor, ex, ec, vx, vc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Slater average and energy partial sums
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_sic_average(const ChanDesc *chans, const int *blk_chan,
+                                                     const double *PHI, const double *V,
+                                                     double floor, double *partU, double *partX) {
+    __shared__ double su[4][kMaxOrb], sx[4][kMaxOrb];
+    const int c = blk_chan[blockIdx.x];
+    const ChanDesc ch = chans[c];
+    const int tile = blockIdx.x - ch.blk_base;
+    const long long base = (long long)tile * kPW;
+    double num[kPW / 256], den[kPW / 256];
+#pragma unroll
+    for (int e = 0; e < kPW / 256; ++e) num[e] = den[e] = 0.0;
+    const int w = threadIdx.x >> 6;
+    for (int i = 0; i < ch.N; ++i) {
+        const double *ph = PHI + ch.off + (long long)i * ch.M;
+        const double *vh = V + ch.off + (long long)i * ch.M;
+        double u = 0.0, x = 0.0;
+#pragma unroll
+        for (int e = 0; e < kPW / 256; ++e) {
+            const long long m = base + e * 256 + threadIdx.x;
+            if (m < ch.M) {
+                const double p = ph[m];
+                const double r = p * p;
+                const double v = vh[m];
+                double ex, ec, vx, vc;
+                lsda_pol(r, floor, ex, ec, vx, vc);
+                u += r * v;
+                x += r * (ex + ec);
+                const double Vi = -(v + vx + vc);
+                num[e] += r * Vi;
+                den[e] += r;
+            }
+        }
+        u = wave_sum(u);
+        x = wave_sum(x);
+        if ((threadIdx.x & 63) == 0) {
+            su[w][i] = u;
+            sx[w][i] = x;
+        }
+    }
+    if (ch.vsic) {
+#pragma unroll
+        for (int e = 0; e < kPW / 256; ++e) {
+            const long long m = base + e * 256 + threadIdx.x;
+            if (m < ch.M) ch.vsic[m] = (den[e] > floor) ? ch.vscale * num[e] / den[e] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ch.N; i += 256) {
+        partU[(size_t)blockIdx.x * kMaxOrb + i] = (su[0][i] + su[1][i]) + (su[2][i] + su[3][i]);
+        partX[(size_t)blockIdx.x * kMaxOrb + i] = (sx[0][i] + sx[1][i]) + (sx[2][i] + sx[3][i]);
+    }
+}
+
+__global__ __launch_bounds__(128) void k_sic_energy(const ChanDesc *chans, const double *partU,
+                                                    const double *partX, double *U, double *X,
+                                                    double *Echan) {
+    __shared__ double se[kMaxOrb];
+    const ChanDesc ch = chans[blockIdx.x];
+    const double dV = ch.h * ch.h * ch.h;
+    const int i = threadIdx.x;
+    if (i < ch.N) {
+        double su = 0.0, sx = 0.0;
+        for (int t = 0; t < ch.nblk; ++t) {
+            su += partU[(size_t)(ch.blk_base + t) * kMaxOrb + i];
+            sx += partX[(size_t)(ch.blk_base + t) * kMaxOrb + i];
+        }
+        const double ui = 0.5 * dV * su, xi = dV * sx;
+        U[ch.first_orb + i] = ui;
+        X[ch.first_orb + i] = xi;
+        se[i] = ui + xi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int k = 0; k < ch.N; ++k) e -= se[k];
+        Echan[blockIdx.x] = e;
+    }
+}
+
+hipError_t launch_sic_average(int nchan, const ChanDesc *chan, int nblk_total,
+                              const int *blk_chan, const double *PHI, const double *V,
+                              double floor, double *partU, double *partX, hipStream_t s) {
+    (void)nchan;
+    if (nblk_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sic_average, dim3(nblk_total), dim3(256), 0, s, chan, blk_chan, PHI, V,
+                       floor, partU, partX);
+    return hipGetLastError();
+}
+
+hipError_t launch_sic_energy(int nchan, const ChanDesc *chan, const double *partU,
+                             const double *partX, double *U, double *X, double *Echan,
+                             hipStream_t s) {
+    if (nchan <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sic_energy, dim3(nchan), dim3(128), 0, s, chan, partU, partX, U, X, Echan);
+    return hipGetLastError();
+}
+
+}  // namespace fsic

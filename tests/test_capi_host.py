@@ -1,0 +1,81 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/fsic.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsic.h")
+LIB = os.path.join(ROOT, "paper_2108_01186_amd", "libfsic.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsic_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libfsic.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("fsic_create", "fsic_forward", "fsic_backward", "fsic_destroy",
+                     "fsic_status_string", "fsic_default_opts"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_2108_01186_amd import fsic
+    assert sorted(fsic.EXPORTED) == declared_functions()
+
+
+def test_default_opts_and_status_strings():
+    from paper_2108_01186_amd import fsic
+    o = fsic.default_opts()
+    assert o.fd_order == 12 and o.lmax == 6 and o.tol == 1e-10 and o.max_iter == 20000
+    assert o.vsic_scale == 1.0 and o.rho_floor == 1e-30 and o.flags == fsic.FSIC_WANT_VSIC
+    for s in range(10):
+        assert fsic.fsic_status_string(s)
+    assert b"unknown" in fsic.fsic_status_string(99)
+
+
+def test_struct_layout_matches_header():
+    """Sizes of the ABI structs as a C compiler lays them out."""
+    from paper_2108_01186_amd import fsic
+    assert ctypes.sizeof(fsic.fsic_grid) == 4 * 3 + 4 + 8 + 24
+    assert ctypes.sizeof(fsic.fsic_opts) == 64
+    assert ctypes.sizeof(fsic.fsic_stats) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 8 * 8 + 4 + 4 + 8 * 4
+
+
+def test_invalid_arguments_rejected_on_host():
+    from paper_2108_01186_amd import fsic
+    n = (ctypes.c_int32 * 3)(16, 16, 16)
+    # odd stencil order, zero count, null pointers: rejected before any HIP call
+    assert fsic.fsic_op_laplacian(n, 0.3, 7, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == fsic.FSIC_EINVAL
+    assert fsic.fsic_op_laplacian(n, 0.3, 12, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == fsic.FSIC_EINVAL
+    assert fsic.fsic_op_laplacian(n, 0.3, 12, 1, None, ctypes.c_void_p(8), None) == fsic.FSIC_EINVAL
+    bad = (ctypes.c_int32 * 3)(4, 16, 16)
+    assert fsic.fsic_op_laplacian(bad, 0.3, 12, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == fsic.FSIC_EINVAL
+    assert fsic.fsic_op_laplacian(n, -0.3, 12, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == fsic.FSIC_EINVAL
+    assert fsic.fsic_op_invsqrt(0, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None, None) == fsic.FSIC_EINVAL
+    assert fsic.fsic_op_invsqrt(200, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None, None) == fsic.FSIC_EINVAL
+    o = fsic.default_opts(fd_order=13)
+    h = ctypes.c_void_p()
+    assert fsic.fsic_create(ctypes.byref(h), ctypes.byref(o), None) == fsic.FSIC_EINVAL
+    o = fsic.default_opts(tol=0.0)
+    assert fsic.fsic_create(ctypes.byref(h), ctypes.byref(o), None) == fsic.FSIC_EINVAL
+    o = fsic.default_opts(lmax=9)
+    assert fsic.fsic_create(ctypes.byref(h), ctypes.byref(o), None) == fsic.FSIC_EINVAL
+    assert fsic.fsic_create(None, ctypes.byref(fsic.default_opts()), None) == fsic.FSIC_EINVAL

@@ -1,0 +1,129 @@
+"""FOD gradient (forces) of the SIC energy: the library's adjoint (reverse
+mode, one adjoint Poisson solve per orbital) against the oracle's
+tangent-mode gradient and against central differences of the library's own
+energy (step 1e-4 Bohr, the check of Sec. II.B), through the C ABI and the
+torch.autograd.Function."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2108_01186_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2108_01186_amd import fsic
+    return fsic
+
+
+@pytest.fixture(scope="module")
+def mol40_grad_oracle(oracle, mol40):
+    s = mol40
+    return oracle.sic_grad_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mol40_gradient_vs_oracle(torch_cuda, F, mol40, mol40_grad_oracle, precision):
+    torch = torch_cuda
+    _say(f"gradient mol40 {precision}")
+    s = mol40
+    ctx = F.Context(precision=precision, tol=1e-11)
+    psi = torch.tensor(np.asarray(s.psi[0]), device="cuda")
+    fod = torch.tensor(s.fod[0], requires_grad=True)
+    E, vs = F.flosic_sic(ctx, s.n, s.h, s.origin, [psi], [fod])
+    E.backward()
+    g = fod.grad.numpy()
+    # forces to 1e-6 Ha/Bohr is the target; the arithmetic gives far better
+    assert np.abs(g - mol40_grad_oracle).max() < 1e-8, np.abs(g - mol40_grad_oracle).max()
+    ctx.close()
+
+
+def test_mol40_gradient_vs_central_differences(torch_cuda, F, mol40):
+    torch = torch_cuda
+    _say("gradient mol40 vs FD of the library energy")
+    s = mol40
+    ctx = F.Context(tol=1e-13, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE)
+    psi = torch.tensor(np.asarray(s.psi[0]), device="cuda")
+    d = {"n": s.n, "h": s.h, "origin": s.origin, "psi": [psi], "fod": [s.fod[0]]}
+    ctx.forward([d])
+    g = ctx.backward([[5]])[0][0]
+    eps = 1e-4
+    checked = 0
+    for (i, dd) in [(0, 2), (1, 0), (2, 1), (3, 0), (4, 2)]:
+        t = (s.fod[0][i, dd] - s.origin[dd]) / s.h
+        if math.floor(t + eps / s.h) != math.floor(t - eps / s.h):
+            continue
+        f = s.fod[0].copy()
+        f[i, dd] += eps
+        ep = ctx.forward([dict(d, fod=[f])])[0][0]
+        f[i, dd] -= 2 * eps
+        em = ctx.forward([dict(d, fod=[f])])[0][0]
+        assert abs((ep - em) / (2 * eps) - g[i, dd]) < 1e-7
+        checked += 1
+    assert checked >= 3
+    ctx.close()
+
+
+def test_two_spin_gradient_layout(torch_cuda, F, oracle):
+    """Spin-down gradients land after the spin-up ones; grad_e scales them."""
+    torch = torch_cuda
+    _say("gradient two spins")
+    s = synth.make_molecule("tiny2", 28, 0.33, 4, 9, (4, 3), seed=55)
+    ref = [oracle.sic_grad_spin(s.psi[k], s.fod[k], s.n, s.h, s.origin) for k in range(2)]
+    ctx = F.Context(tol=1e-11, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE)
+    d = {"n": s.n, "h": s.h, "origin": s.origin,
+         "psi": [torch.tensor(p, device="cuda") for p in s.psi], "fod": s.fod}
+    ctx.forward([d])
+    g = ctx.backward([[4, 3]], grad_e=[2.0])[0]
+    assert np.abs(g[0] - 2 * ref[0]).max() < 2e-8
+    assert np.abs(g[1] - 2 * ref[1]).max() < 2e-8
+    ctx.close()
+
+
+def test_one_electron_gradient_vanishes(torch_cuda, F):
+    """N = 1: E_SIC does not depend on the FOD (one-electron case)."""
+    torch = torch_cuda
+    _say("gradient one electron")
+    n, h, a = 40, 0.3, 0.7
+    x = -h * (n - 1) / 2 + h * np.arange(n)
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    psi = np.exp(-a * r2).reshape(1, -1)
+    psi /= math.sqrt(h ** 3 * float((psi @ psi.T).item()))
+    ctx = F.Context(tol=1e-12, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE)
+    d = {"n": (n, n, n), "h": h, "origin": np.full(3, -h * (n - 1) / 2),
+         "psi": [torch.tensor(psi, device="cuda")], "fod": [np.array([[0.2, -0.3, 0.5]])]}
+    e1 = ctx.forward([d])[0][0]
+    g = ctx.backward([[1]])[0][0]
+    e2 = ctx.forward([dict(d, fod=[np.array([[1.1, 0.4, -0.7]])])])[0][0]
+    assert abs(e1 - e2) < 1e-13
+    assert np.abs(g).max() < 1e-12
+    ctx.close()
+
+
+def test_backward_without_tape(torch_cuda, F, mol40):
+    torch = torch_cuda
+    _say("backward without tape")
+    s = mol40
+    ctx = F.Context()
+    d = {"n": s.n, "h": s.h, "origin": s.origin,
+         "psi": [torch.tensor(np.asarray(s.psi[0]), device="cuda")], "fod": [s.fod[0]]}
+    ctx.forward([d])
+    with pytest.raises(F.FsicError) as ei:
+        ctx.backward([[5]])
+    assert ei.value.status == F.FSIC_ENOTAPE
+    ctx.close()

@@ -1,0 +1,99 @@
+"""Forward parity of the whole SIC path (Fermi orbitals, Loewdin, Poisson,
+LSDA, Slater average, E_SIC) against the CPU oracle on the same seeded
+inputs, through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_2108_01186_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2108_01186_amd import fsic
+    return fsic
+
+
+def _to_dev(torch, sysobj):
+    sysobj.psi = [torch.as_tensor(np.asarray(p), device="cuda").contiguous() for p in sysobj.psi]
+    return sysobj
+
+
+@pytest.fixture(scope="module")
+def mol40_dev(torch_cuda, mol40):
+    import copy
+    s = copy.copy(mol40)
+    return _to_dev(torch_cuda, s)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp64", 1e-12), ("mixed", 1e-10)])
+def test_mol40_energy_and_potential(torch_cuda, F, oracle, mol40, mol40_dev, mol40_oracle,
+                                    precision, tol):
+    _say(f"forward mol40 {precision} tol={tol}")
+    r = mol40_oracle
+    out = F.sic_energy([mol40_dev], precision=precision, tol=tol)
+    e = out["e"][0]
+    # energy parity: 1e-8 Ha
+    assert abs(e - r.e) < 1e-8, (e, r.e)
+    assert np.abs(out["U"] - r.U).max() < 1e-9
+    assert np.abs(out["X"] - r.X).max() < 1e-11
+    vs = out["vsic"][0][0].cpu().numpy()
+    assert np.abs(vs - r.vsic).max() < 1e-7, np.abs(vs - r.vsic).max()
+    st = out["stats"]
+    assert st["max_relres"] <= tol
+    assert st["nsolves"] == 5
+
+
+def test_mol40_scale_factor(torch_cuda, F, mol40_dev, mol40_oracle):
+    _say("forward mol40 scale 0.5")
+    a = F.sic_energy([mol40_dev], vsic_scale=0.5)
+    b = F.sic_energy([mol40_dev], vsic_scale=1.0)
+    assert a["e"][0] == b["e"][0]
+    va, vb = a["vsic"][0][0].cpu().numpy(), b["vsic"][0][0].cpu().numpy()
+    assert np.abs(va - 0.5 * vb).max() <= 1e-15 * np.abs(vb).max()
+
+
+def test_mol40_bitwise_reproducible(torch_cuda, F, mol40_dev):
+    _say("forward mol40 twice")
+    a = F.sic_energy([mol40_dev])
+    b = F.sic_energy([mol40_dev])
+    assert a["e"][0] == b["e"][0]
+    assert np.array_equal(a["vsic"][0][0].cpu().numpy(), b["vsic"][0][0].cpu().numpy())
+
+
+def test_mol40_unitary_invariance(torch_cuda, F, mol40_dev, mol40_oracle):
+    torch = torch_cuda
+    _say("forward mol40 rotated orbitals")
+    rng = np.random.default_rng(3)
+    Qm, _ = np.linalg.qr(rng.normal(size=(5, 5)))
+    import copy
+    s2 = copy.copy(mol40_dev)
+    s2.psi = [(torch.tensor(Qm, device="cuda") @ mol40_dev.psi[0]).contiguous()]
+    out = F.sic_energy([s2])
+    assert abs(out["e"][0] - mol40_oracle.e) < 1e-8
+
+
+def test_two_systems_one_batch(torch_cuda, F, oracle, mol40_dev, mol40_oracle):
+    """Two uneven systems solved in the same launches give the same energies
+    as alone."""
+    _say("forward batch of two uneven systems")
+    small = synth.make_molecule("tiny", 24, 0.35, 3, 7, (3, 2), seed=77)
+    small = _to_dev(torch_cuda, small)
+    both = F.sic_energy([mol40_dev, small])
+    e_small_ref = sum(oracle.sic_spin(np.asarray(small.psi[s].cpu()), small.fod[s], small.n, small.h,
+                                      small.origin).e for s in range(2))
+    assert abs(both["e"][0] - mol40_oracle.e) < 1e-8
+    assert abs(both["e"][1] - e_small_ref) < 1e-8
