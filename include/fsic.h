@@ -116,9 +116,10 @@ typedef struct {
 
 typedef struct {
     int32_t nsolves;          /* Poisson solves in the call (forward: sum of nocc) */
-    int32_t max_iters;        /* largest CG iteration count of any solve */
-    int64_t total_iters;      /* sum of CG iterations over solves */
-    int32_t outer_refinements;/* FP64 corrections (mixed precision), summed over solves */
+    int32_t max_iters;        /* largest number of CG sweeps that did work for one solve */
+    int64_t total_iters;      /* CG sweeps that did work, summed over solves */
+    int32_t outer_refinements;/* mixed precision: rounds of FP64 residual checks (each
+                                 folds the FP32 correction into the FP64 solution) */
     double  max_relres;       /* largest final FP64 relative residual */
     double  cond_S_max;       /* largest condition number of any FO overlap S */
     double  min_rho_fod;      /* smallest rho(a_i) */

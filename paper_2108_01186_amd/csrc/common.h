@@ -12,11 +12,11 @@ constexpr int kMaxOrb = 128;     // orbitals per spin channel
 constexpr int kMaxL = 8;         // multipole order
 constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 1);
 
-// Stencil tile: 32 (x) by 16 (y) columns per 256-thread block, marching in z.
+// Stencil tile: 32 (x) by 8*cpt (y) columns per 256-thread block, marching in z.
 constexpr int kTX = 32;
-constexpr int kTY = 16;
-// Pointwise tile: 256 threads x 4 nodes.
-constexpr int kPW = 1024;
+// Pointwise tile: 256 threads x 16 nodes (few partial sums per orbital, so
+// the blocks that re-add them stay cheap).
+constexpr int kPW = 4096;
 
 // Device status bits (first error wins in the host's reading order).
 enum : int {
@@ -48,6 +48,8 @@ struct Item {
 
 struct Coeffs {
     double c[kMaxRadius + 1];  // unit-spacing second-difference weights
+    int cpt;                   // stencil tile: 32 x 8*cpt columns (1, 2 or 4; 1 and 4 only for p = 6)
+    int depth;                 // planes fetched ahead in the z march (2; 1, 3, 4 only for p = 6)
 };
 
 // ---------------------------------------------------------------------------

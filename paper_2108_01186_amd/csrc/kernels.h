@@ -28,10 +28,13 @@ struct CGIter {
     T *X;               // solution (FP64 path) or FP32 correction (mixed path)
     double *part7;      // [tot7]   p.q partial sums
     double *part8;      // [2*tot8] r.r partial sums, by iteration parity
-    double *partRU;     // [tot7]   true-residual partial sums (mixed path)
+    double *partRU;     // [tot7]   FP64-residual partial sums
     int tot8;
-    int *done;          // per orbital: converged
+    int *done;          // per orbital: 0 iterating, 1 converged, 2 paused until the next FP64 check
     int *iters;         // per orbital: iterations at convergence
+    int *rs_iter;       // per orbital: iteration that restarts CG from the FP64 residual (or null)
+    int *nact;          // per orbital: active sweeps [norb] then active updates [norb]
+    int norb;
     double *rrfin;      // per orbital: residual norm^2 at convergence
     const double *bb;   // per orbital: ||b||^2
     double tol2;        // tol^2
@@ -63,7 +66,8 @@ hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDes
 
 // mixed precision: mark orbitals whose FP64 residual (partRU) meets tol
 hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
-                           double tol2, int k, int *done, int *iters, double *rrfin, hipStream_t s);
+                           double tol2, int k, int *done, int *iters, double *rrfin, int *rs_iter,
+                           hipStream_t s);
 
 // per orbital: out[o] = sum of partials (stencil layout if stencil_layout,
 // else pointwise slot range starting at the parity-0 block)

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -75,6 +76,8 @@ Coeffs fd_weights(int p) {
         s += ck;
     }
     cf.c[0] = (double)(-2.0L * s);
+    cf.cpt = 2;
+    cf.depth = 2;
     return cf;
 }
 
@@ -176,7 +179,7 @@ struct fsic_ctx {
     DBuf<double> Gh;  // ghost values
     DBuf<double> part7, part8, partRU, partQ, partZ;
     DBuf<double> bb, rrfin, relres, Qlm, Zt, ptrue;
-    DBuf<int> done, iters;
+    DBuf<int> done, iters, rs_iter, nact;
     DBuf<OrbDesc> d_orb;
     DBuf<Item> d_items7, d_items8;
     DBuf<long long> d_gcount;
@@ -202,6 +205,7 @@ struct fsic_ctx {
     int nsys = 0;
     bool tape = false;
     int radius = 6;
+    int cpt_fp64 = 1, cpt_mixed = 2;  // stencil tile height per solve precision
     Coeffs cf{};
     HarmTables ht{};
 
@@ -252,9 +256,9 @@ fsic_status validate_grid(const fsic_grid &g, std::string &why) {
 
 // Stencil tiling: columns of 32 x 16, z-chunks sized so the launch has
 // enough blocks to fill 256 compute units several times over.
-void tile_orbital(OrbDesc &od, int radius, long long total_cols_blocks) {
+void tile_orbital(OrbDesc &od, int radius, int cpt, long long total_cols_blocks) {
     od.tiles_x = (od.nx + kTX - 1) / kTX;
-    od.tiles_y = (od.ny + kTY - 1) / kTY;
+    od.tiles_y = (od.ny + 8 * cpt - 1) / (8 * cpt);
     int zc = od.nz;
     long long blocks = total_cols_blocks;
     while (blocks < 2048 && zc >= 4 * radius && zc >= 32) {
@@ -274,18 +278,18 @@ struct Group {
     int chan;
 };
 
-void build_batch(const std::vector<Group> &groups, int radius, Batch &b) {
+void build_batch(const std::vector<Group> &groups, int radius, int cpt, Batch &b) {
     b = Batch{};
     long long cols = 0;
     for (const Group &g : groups)
-        cols += (long long)g.count * ((g.n[0] + kTX - 1) / kTX) * ((g.n[1] + kTY - 1) / kTY);
+        cols += (long long)g.count * ((g.n[0] + kTX - 1) / kTX) * ((g.n[1] + 8 * cpt - 1) / (8 * cpt));
     std::vector<std::pair<int, int>> nat7, nat8;
     for (const Group &g : groups) {
         const long long M = (long long)g.n[0] * g.n[1] * g.n[2];
         for (int i = 0; i < g.count; ++i) {
             OrbDesc od{};
             od.nx = g.n[0]; od.ny = g.n[1]; od.nz = g.n[2];
-            tile_orbital(od, radius, cols);
+            tile_orbital(od, radius, cpt, cols);
             od.nt7 = od.tiles_x * od.tiles_y * od.tiles_z;
             od.base7 = b.tot7;
             b.tot7 += od.nt7;
@@ -361,6 +365,8 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     HIPCHK(c, c->Zt.ensure((size_t)norb * nlm));
     HIPCHK(c, c->done.ensure(norb));
     HIPCHK(c, c->iters.ensure(norb));
+    HIPCHK(c, c->rs_iter.ensure(norb));
+    HIPCHK(c, c->nact.ensure(3 * (size_t)norb));
     if (c->h_done_cap < (size_t)norb) {
         if (c->h_done) hipHostFree(c->h_done);
         c->h_done = nullptr;
@@ -404,6 +410,8 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->part8.p, 0, c->bb.p, s));
     HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->iters.p, 0, norb * sizeof(int), s));
+    HIPCHK(c, hipMemsetAsync(c->rs_iter.p, 0xff, norb * sizeof(int), s));  // -1: no restart
+    HIPCHK(c, hipMemsetAsync(c->nact.p, 0, 3 * norb * sizeof(int), s));
     const double tol2 = tol * tol;
     const int chunk = 32;
     int k = 0;
@@ -442,6 +450,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         a.R = c->R.p; a.Q = c->Q.p; a.X = X;
         a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.tot8 = b.tot8;
         a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
+        a.rs_iter = nullptr; a.nact = c->nact.p; a.norb = norb;
         a.tol2 = tol2;
         while (k < max_iter + 1 && !all_done) {
             const int kend = std::min(k + chunk, max_iter + 1);
@@ -476,6 +485,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         a.R = c->R32.p; a.Q = c->Q32.p; a.X = c->X32.p;
         a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.tot8 = b.tot8;
         a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
+        a.rs_iter = c->rs_iter.p; a.nact = c->nact.p; a.norb = norb;
         a.tol2 = tol2;
         int nref = 0;
         while (k < max_iter && !all_done) {
@@ -489,7 +499,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                 const int prev_ru = (j == 1 && k - 1 > 0);
                 {
                     PROF_BEGIN(0, k, k == 0)
-                    HIPCHK(c, launch_cg_stencil<float>(c->radius, c->cf, a, k, cur_ru, prev_ru, cur_ru, s));
+                    HIPCHK(c, launch_cg_stencil<float>(c->radius, c->cf, a, k, cur_ru, prev_ru, 1, s));
                     PROF_END()
                 }
                 {
@@ -504,56 +514,53 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                            c->partRU.p, s));
             HIPCHK(c, launch_mixed_accumulate(nit8, c->d_items8.p, c->d_orb.p, c->done.p, X, c->X32.p, s));
             HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, k, c->done.p,
-                                      c->iters.p, c->rrfin.p, s));
+                                      c->iters.p, c->rrfin.p, c->rs_iter.p, s));
             ++nref;
             HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));
             all_done = true;
-            for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o];
+            for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o] == 1;
         }
-        rep.refinements += nref * norb;
+        rep.refinements += nref;
         // final report: FP64 residual of x64 (x32 already folded in)
         HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
                                        X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
         HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
     }
-    std::vector<int> it(norb);
+    std::vector<int> it(norb), na(3 * (size_t)norb);
     std::vector<double> pt(norb), bbh(norb);
     HIPCHK(c, hipMemcpyAsync(it.data(), c->iters.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(na.data(), c->nact.p, 3 * norb * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(pt.data(), c->ptrue.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(bbh.data(), c->bb.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    std::vector<int> active_until(norb);
     for (int o = 0; o < norb; ++o) {
-        const int itv = c->h_done[o] ? it[o] : max_iter;
-        active_until[o] = itv;
+        const int itv = na[o];  // stencil sweeps that did work for this orbital
         rep.max_iters = std::max(rep.max_iters, itv);
         rep.total_iters += itv;
         const double rr = bbh[o] > 0 ? std::sqrt(pt[o] / bbh[o]) : 0.0;
         rep.max_relres = std::max(rep.max_relres, rr);
-        if (!c->h_done[o]) rep.converged = false;
+        if (c->h_done[o] != 1) rep.converged = false;
     }
     if (prof) {
-        // algorithmic bytes: every array of every orbital still iterating,
-        // read or written once (sweep: r, p_old, p, q; update: x, p, r, q, x, r)
+        // algorithmic bytes: each array of each orbital that did work in a
+        // launch, read or written once (sweep: r, p_old, p, q -- the first
+        // sweep has no p_old; update: x, p, r, q, x, r -- x is not read when
+        // it restarts from zero)
         const double esz = mixed ? 4.0 : 8.0;
         for (const Rec &r : recs) {
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
-            double nodes = 0.0;
-            for (int o = 0; o < norb; ++o)
-                if (r.k < active_until[o])
-                    nodes += (double)b.orb[o].nx * b.orb[o].ny * b.orb[o].nz;
-            if (r.kind == 0) {
-                c->sweep_launches += 1;
-                c->sweep_ms += ms;
-                c->sweep_bytes += nodes * esz * (r.flag ? 3.0 : 4.0);
-            } else {
-                c->update_launches += 1;
-                c->update_ms += ms;
-                c->update_bytes += nodes * esz * (r.flag ? 5.0 : 6.0);
-            }
+            if (r.kind == 0) { c->sweep_launches += 1; c->sweep_ms += ms; }
+            else { c->update_launches += 1; c->update_ms += ms; }
+        }
+        for (int o = 0; o < norb; ++o) {
+            const double Mo = (double)b.orb[o].nx * b.orb[o].ny * b.orb[o].nz;
+            const int n7 = na[o], n8 = na[norb + o];
+            const int xfirst = mixed ? (n8 > 0 ? (n8 + chunk - 1) / chunk : 0) : (n8 > 0 ? 1 : 0);
+            c->sweep_bytes += Mo * esz * (4.0 * n7 - (n7 > 0 ? 1.0 : 0.0));
+            c->update_bytes += Mo * esz * (6.0 * n8 - xfirst);
         }
     }
 #undef PROF_BEGIN
@@ -615,6 +622,16 @@ fsic_status fsic_create(fsic_ctx **ctx, const fsic_opts *opts, void *hip_stream)
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return FSIC_EHIP; }
     c->radius = opts->fd_order / 2;
     c->cf = fd_weights(c->radius);
+    if (c->radius != 6) c->cpt_fp64 = c->cpt_mixed = 2;  // other orders: one tile shape
+    if (c->radius == 6) c->cf.depth = 1;
+    if (const char *e = getenv("FSIC_STENCIL_CPT")) {
+        const int v = atoi(e);
+        if (v == 2 || (c->radius == 6 && (v == 1 || v == 4))) c->cpt_fp64 = c->cpt_mixed = v;
+    }
+    if (const char *e = getenv("FSIC_STENCIL_DEPTH")) {
+        const int v = atoi(e);
+        if (c->radius == 6 && (v == 1 || (v == 2 && c->cpt_fp64 <= 2))) c->cf.depth = v;
+    }
     c->ht = harm_tables(opts->lmax);
     if (c->status.ensure(1) != hipSuccess) { delete c; return FSIC_ENOMEM; }
     *ctx = c;
@@ -627,8 +644,16 @@ fsic_status fsic_set_opts(fsic_ctx *c, const fsic_opts *opts) {
     fsic_status st = validate_opts(opts, why);
     if (st) return set_err(c, st, why);
     c->opts = *opts;
+    const int depth = c->cf.depth;
     c->radius = opts->fd_order / 2;
     c->cf = fd_weights(c->radius);
+    if (c->radius == 6) {
+        c->cf.depth = depth;
+        c->cpt_fp64 = 1;
+        c->cpt_mixed = 2;
+    } else {
+        c->cpt_fp64 = c->cpt_mixed = 2;
+    }
     c->ht = harm_tables(opts->lmax);
     c->tape = false;
     return FSIC_OK;
@@ -643,7 +668,7 @@ void fsic_destroy(fsic_ctx *c) {
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
     c->partQ.release(); c->partZ.release(); c->bb.release(); c->rrfin.release();
     c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release();
-    c->done.release(); c->iters.release(); c->d_orb.release(); c->d_items7.release();
+    c->done.release(); c->iters.release(); c->rs_iter.release(); c->nact.release(); c->d_orb.release(); c->d_items7.release();
     c->d_items8.release(); c->d_gcount.release(); c->small.release(); c->work.release();
     c->partG.release(); c->d_cells.release(); c->d_chan.release(); c->d_blkchan.release();
     c->partU.release(); c->partX.release(); c->Uo.release(); c->Xo.release(); c->Ech.release();
@@ -718,7 +743,8 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         groups.push_back(g);
     }
     Batch b;
-    build_batch(groups, P, b);
+    c->cf.cpt = (o.precision == FSIC_MIXED) ? c->cpt_mixed : c->cpt_fp64;
+    build_batch(groups, P, c->cf.cpt, b);
     // channel descriptors for the average pass
     std::vector<ChanDesc> cd(nchan);
     std::vector<int> blkchan;
@@ -897,7 +923,7 @@ fsic_status fsic_op_laplacian(const int32_t *n, double h, int32_t fd_order, int3
     for (int d = 0; d < 3; ++d) { groups[0].n[d] = n[d]; groups[0].origin[d] = 0.0; }
     groups[0].h = h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
     Batch b;
-    build_batch(groups, P, b);
+    build_batch(groups, P, 2, b);
     hipStream_t s = (hipStream_t)hip_stream;
     DBuf<OrbDesc> dorb;
     DBuf<Item> dit;
@@ -923,7 +949,7 @@ fsic_status fsic_op_laplacian_f32(const int32_t *n, double h, int32_t fd_order, 
     for (int d = 0; d < 3; ++d) { groups[0].n[d] = n[d]; groups[0].origin[d] = 0.0; }
     groups[0].h = h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
     Batch b;
-    build_batch(groups, P, b);
+    build_batch(groups, P, 2, b);
     hipStream_t s = (hipStream_t)hip_stream;
     DBuf<OrbDesc> dorb;
     DBuf<Item> dit;
@@ -967,7 +993,8 @@ fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lma
     for (int d = 0; d < 3; ++d) { groups[0].n[d] = grid->n[d]; groups[0].origin[d] = grid->origin[d]; }
     groups[0].h = grid->h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
     Batch b;
-    build_batch(groups, c->radius, b);
+    c->cf.cpt = (precision == FSIC_MIXED) ? c->cpt_mixed : c->cpt_fp64;
+    build_batch(groups, c->radius, c->cf.cpt, b);
     st = prepare_batch(c, b, precision);
     if (st) return st;
     SolveReport rep;

@@ -3,15 +3,19 @@
 // differences on a uniform grid; the Laplacian is the Kronecker sum of 1-D
 // second differences applied matrix-free).
 //
-// Design (gfx950): one 256-thread block owns a 32 x 16 column tile of an
+// Design (gfx950): one 256-thread block owns a 32 x 8*cpt column tile of an
 // orbital's grid and marches through a z-chunk.  Each thread keeps the
-// 2p + 1 z-neighbours of its two columns in registers; the current xy plane
-// with its p-deep cross-shaped halo is staged in LDS.  The operand of the
+// 2p + 1 z-neighbours of its cpt columns in registers; the current xy plane
+// with its p-deep cross-shaped halo is staged in double-buffered LDS, and the
+// next plane is fetched into registers while the current one is computed,
+// so one barrier per plane separates the stages.  The operand of the
 // stencil is produced on the fly by a policy (p = r + beta p_old for CG,
 // x64 + x32 for the FP64 residual), so every CG iteration is two HBM
 // passes: this sweep and one pointwise update.  Dot products accumulate in
 // FP64 into per-block partial sums that later blocks add up in a fixed
 // order, so results are bitwise reproducible.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace fsic {
@@ -20,25 +24,82 @@ namespace fsic {
 // z-marching stencil driver
 // ---------------------------------------------------------------------------
 
-template <typename T, int P, class Pol>
+// Raw buffer access: a uniform resource (base, size) plus a 32-bit vector
+// byte offset and a 32-bit scalar byte offset, so no per-lane 64-bit address
+// arithmetic is needed.  Every access here is in range by construction.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <class X> __device__ __forceinline__ X bld(Rsrc r, unsigned vidx, int sidx);
+template <> __device__ __forceinline__ float bld<float>(Rsrc r, unsigned vidx, int sidx) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vidx * 4u, sidx * 4, 0));
+}
+template <> __device__ __forceinline__ double bld<double>(Rsrc r, unsigned vidx, int sidx) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vidx * 8u, sidx * 8, 0));
+}
+__device__ __forceinline__ void bst(Rsrc r, unsigned vidx, int sidx, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vidx * 4u, sidx * 4, 0);
+}
+__device__ __forceinline__ void bst(Rsrc r, unsigned vidx, int sidx, double v) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, vidx * 8u, sidx * 8, 0);
+}
+
+// Workgroup barrier that orders LDS traffic only: this wave's LDS operations
+// complete (lgkmcnt(0)), then s_barrier.  Unlike __syncthreads() it does not
+// wait for outstanding global loads, so the next plane's prefetch stays in
+// flight across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt/expcnt: no wait; lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// calls f(integral_constant<int, U>, arg) for U = 0..N-1 (forced unrolling)
+template <int N, int U = 0>
+struct Unroller {
+    template <class F, class A>
+    __device__ __forceinline__ static void run(F &f, A arg) {
+        if constexpr (U < N) {
+            f(std::integral_constant<int, U>{}, arg);
+            Unroller<N, U + 1>::run(f, arg);
+        }
+    }
+};
+template <int N, class F, class A>
+__device__ __forceinline__ void unroll_steps(F &f, A arg) {
+    Unroller<N>::run(f, arg);
+}
+
+template <typename T, int P, int CPT, int D, class Pol>
 __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
-    __shared__ T sm[kTY + 2 * P][kTX + 2 * P];
+    using Raw = typename Pol::Raw;
+    constexpr int TY = 8 * CPT;              // tile rows (each thread owns CPT columns)
+    constexpr int W = kTX + 2 * P;           // LDS row length
+    constexpr int H = TY + 2 * P;            // LDS rows
+    constexpr int NH = 2 * P * (kTX + TY);   // cross-shaped halo values per plane
+    constexpr int HS = (NH + 255) / 256;     // halo slots per thread
+    constexpr int NW = 2 * P + 1;            // z window
+    __shared__ T sm[2][H * W + 1];           // double-buffered plane (+1 dump slot)
     __shared__ double sred[4];
     const Item it = pol.items[blockIdx.x];
     if (it.orb < 0) return;
     const OrbDesc od = pol.orb[it.orb];
     Pol p = pol;
+    p.tile0 = (it.tile == 0);
     if (!p.setup(it.orb, od, sred)) return;  // uniform across the block
+    p.init(od);
 
     const int nx = od.nx, ny = od.ny, nz = od.nz;
+    const int plane = nx * ny;
     const int bx = it.tile % od.tiles_x;
     const int by = (it.tile / od.tiles_x) % od.tiles_y;
     const int bz = it.tile / (od.tiles_x * od.tiles_y);
     const int tx = threadIdx.x & (kTX - 1);
     const int ty = threadIdx.x >> 5;  // 0..7
     const int x = bx * kTX + tx;
-    const int y0 = by * kTY + ty;
-    const int y1 = y0 + 8;
     const int z0 = bz * od.zc;
     const int z1 = min(nz, z0 + od.zc);
 
@@ -48,68 +109,114 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
     const T c0x3 = T(3) * c[0];
     const T ih2 = (T)od.inv_h2;
 
-    auto ld = [&](int xx, int yy, int zz) -> T {
-        if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) return T(0);
-        return p.load(od, ((long long)zz * ny + yy) * nx + xx);
+    // z-invariant 32-bit in-plane offsets; addresses are a uniform plane base
+    // plus these.  Invalid positions read a clamped in-grid node and are
+    // zeroed by select, so no load is predicated.
+    unsigned coff[CPT];
+    bool cval[CPT];
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) {
+        const int y = by * TY + ty + 8 * cc;
+        cval[cc] = (x < nx) && (y < ny);
+        coff[cc] = (unsigned)(min(y, ny - 1) * nx + min(x, nx - 1));
+    }
+    unsigned hoff[HS];
+    int hlds[HS];
+    bool hval[HS];
+#pragma unroll
+    for (int sl = 0; sl < HS; ++sl) {
+        const int hh = threadIdx.x + 256 * sl;
+        int hx = 0, hy = 0;
+        if (hh < 2 * P * TY) {
+            const int side = hh / (P * TY);
+            const int rem = hh - side * P * TY;
+            hy = rem / P;
+            hx = rem - hy * P;
+            hx = side ? kTX + hx : hx - P;
+        } else {
+            const int h2 = hh - 2 * P * TY;
+            const int side = h2 / (P * kTX);
+            const int rem = h2 - side * P * kTX;
+            const int yy = rem / kTX;
+            hx = rem - yy * kTX;
+            hy = side ? TY + yy : yy - P;
+        }
+        const int gx = bx * kTX + hx, gy = by * TY + hy;
+        hlds[sl] = (hh < NH) ? (hy + P) * W + (hx + P) : H * W;  // spare threads write the dump slot
+        hval[sl] = (hh < NH) && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        hoff[sl] = (unsigned)(min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1));
+    }
+    auto zoff = [&](int z) -> int {  // uniform element offset of plane z (clamped)
+        return min(max(z, 0), nz - 1) * plane;
     };
+    auto use = [&](const Raw &r, bool valid) -> T { return valid ? p.combine(r) : T(0); };
 
-    T qa[2 * P + 1], qb[2 * P + 1];
+    // z window of each column in registers, rotated by unrolling (no moves):
+    // plane z - P + j lives in slot (z - z0 + j) % NW
+    T q[CPT][NW];
 #pragma unroll
     for (int j = 0; j < 2 * P; ++j) {
-        qa[j] = ld(x, y0, z0 - P + j);
-        qb[j] = ld(x, y1, z0 - P + j);
+        const int z = z0 - P + j;
+        const int pz = zoff(z);
+        const bool zin = z >= 0 && z < nz;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) q[cc][j] = use(p.raw(coff[cc], pz), cval[cc] && zin);
     }
+    // prefetch ring: stage d holds the raw loads of plane z + d (+ P for the columns)
+    Raw sc[D][CPT], sh[D][HS];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int pc = zoff(z0 + d + P), ph = zoff(z0 + d);
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) sc[d][cc] = p.raw(coff[cc], pc);
+#pragma unroll
+        for (int sl = 0; sl < HS; ++sl) sh[d][sl] = p.raw(hoff[sl], ph);
+    }
+
     double dot = 0.0;
-    for (int z = z0; z < z1; ++z) {
-        qa[2 * P] = ld(x, y0, z + P);
-        qb[2 * P] = ld(x, y1, z + P);
-        sm[ty + P][tx + P] = qa[P];
-        sm[ty + 8 + P][tx + P] = qb[P];
-        for (int hh = threadIdx.x; hh < 2 * P * (kTX + kTY); hh += 256) {
-            int hx, hy;
-            if (hh < 2 * P * kTY) {
-                const int side = hh / (P * kTY);
-                const int rem = hh - side * P * kTY;
-                hy = rem / P;
-                hx = rem - hy * P;
-                hx = side ? kTX + hx : hx - P;
-            } else {
-                const int h2 = hh - 2 * P * kTY;
-                const int side = h2 / (P * kTX);
-                const int rem = h2 - side * P * kTX;
-                const int yy = rem / kTX;
-                hx = rem - yy * kTX;
-                hy = side ? kTY + yy : yy - P;
-            }
-            sm[hy + P][hx + P] = ld(bx * kTX + hx, by * kTY + hy, z);
-        }
-        __syncthreads();
-        T la = c0x3 * qa[P], lb = c0x3 * qb[P];
+    // one z step; U is the compile-time position in the unrolled block of NW*D
+    auto step = [&](auto uc, int zb) {
+        constexpr int u = decltype(uc)::value;
+        constexpr int d = u % D;
+        constexpr int sl0 = u % NW;  // slot of plane z - P
+        const int z = zb + u;
+        if (z >= z1) return;
+        // buffer parity follows the plane index (NW*D is odd, so u & 1 would
+        // reuse a buffer across the boundary of two unrolled blocks)
+        T *S = sm[(z - z0) & 1];
+        const bool ztop = (z + P) < nz;
 #pragma unroll
-        for (int k = 1; k <= P; ++k) {
-            la += c[k] * ((sm[ty + P][tx + P + k] + sm[ty + P][tx + P - k]) +
-                          (sm[ty + P + k][tx + P] + sm[ty + P - k][tx + P]) +
-                          (qa[P + k] + qa[P - k]));
-            lb += c[k] * ((sm[ty + 8 + P][tx + P + k] + sm[ty + 8 + P][tx + P - k]) +
-                          (sm[ty + 8 + P + k][tx + P] + sm[ty + 8 + P - k][tx + P]) +
-                          (qb[P + k] + qb[P - k]));
+        for (int cc = 0; cc < CPT; ++cc) {
+            q[cc][(sl0 + 2 * P) % NW] = use(sc[d][cc], cval[cc] && ztop);
+            S[(ty + 8 * cc + P) * W + tx + P] = q[cc][(sl0 + P) % NW];
         }
-        la *= ih2;
-        lb *= ih2;
-        if (x < nx) {
-            if (y0 < ny) dot += p.epilogue(od, ((long long)z * ny + y0) * nx + x, qa[P], la);
-            if (y1 < ny) dot += p.epilogue(od, ((long long)z * ny + y1) * nx + x, qb[P], lb);
-        }
-        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 2 * P; ++j) {
-            qa[j] = qa[j + 1];
-            qb[j] = qb[j + 1];
+        for (int sl = 0; sl < HS; ++sl) S[hlds[sl]] = use(sh[d][sl], hval[sl]);
+        lds_barrier();
+        if (z + D < z1) {  // refill this stage with plane z + D
+            const int pc = zoff(z + D + P), ph = zoff(z + D);
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) sc[d][cc] = p.raw(coff[cc], pc);
+#pragma unroll
+            for (int sl = 0; sl < HS; ++sl) sh[d][sl] = p.raw(hoff[sl], ph);
         }
-    }
+        const int pz = z * plane;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            const T *row = S + (ty + 8 * cc + P) * W + tx + P;
+            T lap = c0x3 * q[cc][(sl0 + P) % NW];
+#pragma unroll
+            for (int k = 1; k <= P; ++k)
+                lap += c[k] * ((row[k] + row[-k]) + (row[k * W] + row[-k * W]) +
+                               (q[cc][(sl0 + P + k) % NW] + q[cc][(sl0 + P - k) % NW]));
+            lap *= ih2;
+            if (cval[cc]) dot += p.epilogue(coff[cc], pz, q[cc][(sl0 + P) % NW], lap);
+        }
+    };
+    for (int zb = z0; zb < z1; zb += NW * D) unroll_steps<NW * D>(step, zb);
     if (p.wants_dot()) {
-        const double s = block_sum256(dot, sred);
-        if (threadIdx.x == 0) p.finish(it, od, s);
+        const double s2 = block_sum256(dot, sred);
+        p.finish(it, od, s2, sred);
     }
 }
 
@@ -123,19 +230,30 @@ struct PolApply {  // Lu = L u
     const OrbDesc *orb;
     const T *u;
     T *out;
+    struct Raw { T a; };
+    bool tile0;
+    Rsrc ru, ro;
     __device__ bool setup(int, const OrbDesc &, double *) { return true; }
-    __device__ T load(const OrbDesc &od, long long i) const { return u[od.off + i]; }
-    __device__ double epilogue(const OrbDesc &od, long long i, T, T lap) const {
-        out[od.off + i] = lap;
+    __device__ void init(const OrbDesc &od) {
+        const unsigned bytes = (unsigned)((long long)od.nx * od.ny * od.nz * sizeof(T));
+        ru = make_rsrc(u + od.off, bytes);
+        ro = make_rsrc(out + od.off, bytes);
+    }
+    __device__ Raw raw(unsigned i, int zo) const { return Raw{bld<T>(ru, i, zo)}; }
+    __device__ T combine(const Raw &r) const { return r.a; }
+    __device__ double epilogue(unsigned i, int zo, T, T lap) const {
+        bst(ro, i, zo, lap);
         return 0.0;
     }
     __device__ bool wants_dot() const { return false; }
-    __device__ void finish(const Item &, const OrbDesc &, double) const {}
+    __device__ void finish(const Item &, const OrbDesc &, double, double *) const {}
 };
 
+// r_j.r_j of an orbital: the CG recursion's partial sums (by iteration
+// parity) or those of the last FP64 residual, added in a fixed order
 template <typename T>
-__device__ __forceinline__ double rr_of(const CGIter<T> &a, const OrbDesc &od, int j,
-                                        int from_ru, double *sbuf) {
+__device__ __forceinline__ double rr_of(const CGIter<T> &a, const OrbDesc &od, int j, int from_ru,
+                                        double *sbuf) {
     if (from_ru) return sum_partials(a.partRU + od.base7, od.nt7, sbuf);
     return sum_partials(a.part8 + (size_t)(j & 1) * a.tot8 + od.base8, od.nt8, sbuf);
 }
@@ -147,46 +265,63 @@ struct PolCG {  // p_k = r_k + beta p_{k-1}; q = K p_k = -L p_k
     CGIter<T> a;
     int k, cur_ru, prev_ru, check;
     double beta;
+    bool tile0;
     __device__ bool setup(int o, const OrbDesc &od, double *sbuf) {
-        // other blocks of this orbital may set done[o] during this launch:
+        // other blocks of this orbital may change done[o] during this launch:
         // read it once and broadcast so the whole block takes one branch
         if (threadIdx.x == 0) sbuf[0] = (double)a.done[o];
         __syncthreads();
         const bool dn = sbuf[0] != 0.0;
         __syncthreads();
         if (dn) return false;
-        const double rr = rr_of(a, od, k, cur_ru, sbuf);
+        // restart (beta = 0) from the FP64 residual after an unconfirmed pause
+        const bool restart = a.rs_iter && a.rs_iter[o] == k;
+        const double rr = rr_of(a, od, k, cur_ru || restart, sbuf);
         if (check && rr <= a.tol2 * a.bb[o]) {
             if (threadIdx.x == 0) {
-                a.done[o] = 1;
-                a.iters[o] = k;
-                a.rrfin[o] = rr;
+                if (a.rs_iter) {
+                    a.done[o] = 2;  // mixed: confirm on the FP64 residual first
+                } else {
+                    a.done[o] = 1;
+                    a.iters[o] = k;
+                    a.rrfin[o] = rr;
+                }
             }
             return false;
         }
-        if (k == 0) {
+        if (k == 0 || restart) {
             beta = 0.0;
         } else {
-            const double rp = rr_of(a, od, k - 1, prev_ru, sbuf);
+            const bool pru = prev_ru || (a.rs_iter && a.rs_iter[o] == k - 1);
+            const double rp = rr_of(a, od, k - 1, pru, sbuf);
             beta = rr / rp;
         }
+        if (threadIdx.x == 0 && tile0) a.nact[o] += 1;  // one count per orbital and launch
         return true;
     }
-    __device__ T load(const OrbDesc &od, long long i) const {
-        const long long g = od.off + i;
-        if (k == 0) return a.R[g];
-        return a.R[g] + (T)beta * a.Pold[g];
+    struct Raw { T r, p; };
+    Rsrc rr_, rpo, rpn, rq;
+    __device__ void init(const OrbDesc &od) {
+        const unsigned bytes = (unsigned)((long long)od.nx * od.ny * od.nz * sizeof(T));
+        rr_ = make_rsrc(a.R + od.off, bytes);
+        rpo = make_rsrc(a.Pold + od.off, bytes);
+        rpn = make_rsrc(a.Pnew + od.off, bytes);
+        rq = make_rsrc(a.Q + od.off, bytes);
     }
-    __device__ double epilogue(const OrbDesc &od, long long i, T c, T lap) const {
-        const long long g = od.off + i;
-        const T q = -lap;
-        a.Pnew[g] = c;
-        a.Q[g] = q;
-        return (double)c * (double)q;
+    __device__ Raw raw(unsigned i, int zo) const {
+        if (k == 0) return Raw{bld<T>(rr_, i, zo), T(0)};
+        return Raw{bld<T>(rr_, i, zo), bld<T>(rpo, i, zo)};
+    }
+    __device__ T combine(const Raw &v) const { return v.r + (T)beta * v.p; }
+    __device__ double epilogue(unsigned i, int zo, T c, T lap) const {
+        const T qv = -lap;
+        bst(rpn, i, zo, c);
+        bst(rq, i, zo, qv);
+        return (double)c * (double)qv;
     }
     __device__ bool wants_dot() const { return true; }
-    __device__ void finish(const Item &it, const OrbDesc &od, double s) const {
-        a.part7[od.base7 + it.tile] = s;
+    __device__ void finish(const Item &it, const OrbDesc &od, double s, double *) const {
+        if (threadIdx.x == 0) a.part7[od.base7 + it.tile] = s;
     }
 };
 
@@ -200,21 +335,31 @@ struct PolRes {  // res = b + L x, x = x64 (+ x32)
     double *X64new;
     float *R32;
     double *partRU;
-    __device__ bool setup(int o, const OrbDesc &, double *) { return done == nullptr || !done[o]; }
-    __device__ double load(const OrbDesc &od, long long i) const {
-        const long long g = od.off + i;
-        return X32 ? X64[g] + (double)X32[g] : X64[g];
+    struct Raw { double a; float b; };
+    bool tile0;
+    Rsrc rx, rx32, rb, rxn, rr32;
+    __device__ bool setup(int o, const OrbDesc &, double *) { return done == nullptr || done[o] != 1; }
+    __device__ void init(const OrbDesc &od) {
+        const long long M = (long long)od.nx * od.ny * od.nz;
+        rx = make_rsrc(X64 + od.off, (unsigned)(M * 8));
+        rb = make_rsrc(B + od.off, (unsigned)(M * 8));
+        if (X32) rx32 = make_rsrc(X32 + od.off, (unsigned)(M * 4));
+        if (X64new) rxn = make_rsrc(X64new + od.off, (unsigned)(M * 8));
+        if (R32) rr32 = make_rsrc(R32 + od.off, (unsigned)(M * 4));
     }
-    __device__ double epilogue(const OrbDesc &od, long long i, double c, double lap) const {
-        const long long g = od.off + i;
-        const double res = B[g] + lap;
-        if (X64new) X64new[g] = c;
-        if (R32) R32[g] = (float)res;
+    __device__ Raw raw(unsigned i, int zo) const {
+        return Raw{bld<double>(rx, i, zo), X32 ? bld<float>(rx32, i, zo) : 0.0f};
+    }
+    __device__ double combine(const Raw &v) const { return v.a + (double)v.b; }
+    __device__ double epilogue(unsigned i, int zo, double c, double lap) const {
+        const double res = bld<double>(rb, i, zo) + lap;
+        if (X64new) bst(rxn, i, zo, c);
+        if (R32) bst(rr32, i, zo, (float)res);
         return res * res;
     }
     __device__ bool wants_dot() const { return true; }
-    __device__ void finish(const Item &it, const OrbDesc &od, double s) const {
-        partRU[od.base7 + it.tile] = s;
+    __device__ void finish(const Item &it, const OrbDesc &od, double s, double *) const {
+        if (threadIdx.x == 0) partRU[od.base7 + it.tile] = s;
     }
 };
 
@@ -222,35 +367,72 @@ struct PolRes {  // res = b + L x, x = x64 (+ x32)
 // pointwise CG update
 // ---------------------------------------------------------------------------
 
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 V; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 V; static constexpr int n = 2; };
+
+template <typename T>
+__device__ __forceinline__ double upd_elem(T &x, T &r, T pv, T qv, T al, int x_first) {
+    x = x_first ? al * pv : x + al * pv;
+    r = r - al * qv;
+    return (double)r * (double)r;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_update(CGIter<T> a, int k, int cur_ru, int x_first) {
+    using V = typename Vec16<T>::V;
+    constexpr int VN = Vec16<T>::n;
     __shared__ double sred[4];
     const Item it = a.items8[blockIdx.x];
     if (it.orb < 0) return;
     if (a.done[it.orb]) return;
     const OrbDesc od = a.orb[it.orb];
-    const double rr = rr_of(a, od, k, cur_ru, sred);
+    const bool restart = a.rs_iter && a.rs_iter[it.orb] == k;
+    const double rr = rr_of(a, od, k, cur_ru || restart, sred);
     const double pq = sum_partials(a.part7 + od.base7, od.nt7, sred);
     const double alpha = rr / pq;
     const T al = (T)alpha;
     const long long M = (long long)od.nx * od.ny * od.nz;
     const long long base = (long long)it.tile * kPW;
     double acc = 0.0;
+    if (((od.off | M) % VN) == 0) {
+        // 16-byte vector path: each thread owns VN consecutive nodes per pass
 #pragma unroll
-    for (int e = 0; e < kPW / 256; ++e) {
-        const long long i = base + e * 256 + threadIdx.x;
-        if (i < M) {
-            const long long g = od.off + i;
-            const T pv = a.Pnew[g];
-            const T xv = x_first ? al * pv : a.X[g] + al * pv;
-            const T rv = a.R[g] - al * a.Q[g];
-            a.X[g] = xv;
-            a.R[g] = rv;
-            acc += (double)rv * (double)rv;
+        for (int e = 0; e < kPW / (256 * VN); ++e) {
+            const long long i = base + (long long)(e * 256 + threadIdx.x) * VN;
+            if (i < M) {
+                const long long g = od.off + i;
+                V pv = *reinterpret_cast<const V *>(a.Pnew + g);
+                V qv = *reinterpret_cast<const V *>(a.Q + g);
+                V rv = *reinterpret_cast<const V *>(a.R + g);
+                V xv = x_first ? V{} : *reinterpret_cast<const V *>(a.X + g);
+                T *px = reinterpret_cast<T *>(&xv), *pr = reinterpret_cast<T *>(&rv);
+                const T *pp = reinterpret_cast<const T *>(&pv), *pqv = reinterpret_cast<const T *>(&qv);
+#pragma unroll
+                for (int j = 0; j < VN; ++j) acc += upd_elem(px[j], pr[j], pp[j], pqv[j], al, x_first);
+                *reinterpret_cast<V *>(a.X + g) = xv;
+                *reinterpret_cast<V *>(a.R + g) = rv;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPW / 256; ++e) {
+            const long long i = base + e * 256 + threadIdx.x;
+            if (i < M) {
+                const long long g = od.off + i;
+                T xv = x_first ? T(0) : a.X[g];
+                T rv = a.R[g];
+                acc += upd_elem(xv, rv, a.Pnew[g], a.Q[g], al, x_first);
+                a.X[g] = xv;
+                a.R[g] = rv;
+            }
         }
     }
     const double s = block_sum256(acc, sred);
-    if (threadIdx.x == 0) a.part8[(size_t)((k + 1) & 1) * a.tot8 + od.base8 + it.tile] = s;
+    if (threadIdx.x == 0) {
+        a.part8[(size_t)((k + 1) & 1) * a.tot8 + od.base8 + it.tile] = s;
+        if (it.tile == 0) a.nact[a.norb + it.orb] += 1;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_partials(int norb, const OrbDesc *orb,
@@ -271,7 +453,7 @@ __global__ __launch_bounds__(256) void k_mixed_accumulate(const Item *items8, co
                                                           const int *done, double *X64,
                                                           const float *X32) {
     const Item it = items8[blockIdx.x];
-    if (it.orb < 0 || done[it.orb]) return;
+    if (it.orb < 0 || done[it.orb] == 1) return;
     const OrbDesc od = orb[it.orb];
     const long long M = (long long)od.nx * od.ny * od.nz;
     const long long base = (long long)it.tile * kPW;
@@ -285,16 +467,23 @@ __global__ __launch_bounds__(256) void k_mixed_accumulate(const Item *items8, co
 // convergence on the FP64 residual of the last reliable update
 __global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const double *partRU,
                                                   const double *bb, double tol2, int k, int *done,
-                                                  int *iters, double *rrfin) {
+                                                  int *iters, double *rrfin, int *rs_iter) {
     __shared__ double sred[4];
     const int o = blockIdx.x;
-    if (done[o]) return;
+    if (done[o] == 1) return;
     const OrbDesc od = orb[o];
     const double rr = sum_partials(partRU + od.base7, od.nt7, sred);
-    if (threadIdx.x == 0 && rr <= tol2 * bb[o]) {
-        done[o] = 1;
-        iters[o] = k;
-        rrfin[o] = rr;
+    if (threadIdx.x == 0) {
+        if (rr <= tol2 * bb[o]) {
+            done[o] = 1;
+            iters[o] = k;
+            rrfin[o] = rr;
+        } else if (done[o] == 2) {
+            // the FP32 recursion met tol but the FP64 residual did not:
+            // resume with a restart from the FP64 residual
+            done[o] = 0;
+            rs_iter[o] = k;
+        }
     }
 }
 
@@ -302,23 +491,28 @@ __global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const doub
 // launchers
 // ---------------------------------------------------------------------------
 
-#define FSIC_RADIUS_SWITCH(radius, CALL) \
-    switch (radius) {                    \
-        case 1: CALL(1); break;          \
-        case 2: CALL(2); break;          \
-        case 3: CALL(3); break;          \
-        case 4: CALL(4); break;          \
-        case 5: CALL(5); break;          \
-        case 6: CALL(6); break;          \
-        default: return hipErrorInvalidValue; \
+#define FSIC_RADIUS_SWITCH(radius, CALL)                           \
+    switch (radius * 64 + c.cpt * 8 + c.depth) {                   \
+        case 1 * 64 + 2 * 8 + 2: CALL(1, 2, 2); break;             \
+        case 2 * 64 + 2 * 8 + 2: CALL(2, 2, 2); break;             \
+        case 3 * 64 + 2 * 8 + 2: CALL(3, 2, 2); break;             \
+        case 4 * 64 + 2 * 8 + 2: CALL(4, 2, 2); break;             \
+        case 5 * 64 + 2 * 8 + 2: CALL(5, 2, 2); break;             \
+        case 6 * 64 + 2 * 8 + 2: CALL(6, 2, 2); break;             \
+        case 6 * 64 + 1 * 8 + 2: CALL(6, 1, 2); break;             \
+        case 6 * 64 + 4 * 8 + 1: CALL(6, 4, 1); break;             \
+        case 6 * 64 + 1 * 8 + 1: CALL(6, 1, 1); break;             \
+        case 6 * 64 + 2 * 8 + 1: CALL(6, 2, 1); break;             \
+        default: return hipErrorInvalidValue;                      \
     }
+
 
 template <typename T>
 hipError_t launch_apply(int radius, const Coeffs &c, const Item *items, int nitems,
                         const OrbDesc *orb, const T *u, T *Lu, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    PolApply<T> pol{items, orb, u, Lu};
-#define CALL(P) hipLaunchKernelGGL((k_zmarch<T, P, PolApply<T>>), dim3(nitems), dim3(256), 0, s, pol, c)
+    PolApply<T> pol{items, orb, u, Lu, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolApply<T>>), dim3(nitems), dim3(256), 0, s, pol, c)
     FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
     return hipGetLastError();
@@ -328,8 +522,8 @@ template <typename T>
 hipError_t launch_cg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, int k,
                              int cur_from_ru, int prev_from_ru, int check, hipStream_t s) {
     if (a.nitems7 <= 0) return hipSuccess;
-    PolCG<T> pol{a.items7, a.orb, a, k, cur_from_ru, prev_from_ru, check, 0.0};
-#define CALL(P) hipLaunchKernelGGL((k_zmarch<T, P, PolCG<T>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
+    PolCG<T> pol{a.items7, a.orb, a, k, cur_from_ru, prev_from_ru, check, 0.0, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolCG<T>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
     FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
     return hipGetLastError();
@@ -349,8 +543,8 @@ hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7,
                                 const float *X32, const double *B, double *X64new, float *R32,
                                 double *partRU, hipStream_t s) {
     if (nitems7 <= 0) return hipSuccess;
-    PolRes pol{items7, orb, done, X64, X32, B, X64new, R32, partRU};
-#define CALL(P) hipLaunchKernelGGL((k_zmarch<double, P, PolRes>), dim3(nitems7), dim3(256), 0, s, pol, c)
+    PolRes pol{items7, orb, done, X64, X32, B, X64new, R32, partRU, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolRes>), dim3(nitems7), dim3(256), 0, s, pol, c)
     FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
     return hipGetLastError();
@@ -373,9 +567,11 @@ hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDes
 }
 
 hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
-                           double tol2, int k, int *done, int *iters, double *rrfin, hipStream_t s) {
+                           double tol2, int k, int *done, int *iters, double *rrfin, int *rs_iter,
+                           hipStream_t s) {
     if (norb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ru_check, dim3(norb), dim3(256), 0, s, orb, partRU, bb, tol2, k, done, iters, rrfin);
+    hipLaunchKernelGGL(k_ru_check, dim3(norb), dim3(256), 0, s, orb, partRU, bb, tol2, k, done,
+                       iters, rrfin, rs_iter);
     return hipGetLastError();
 }
 
