@@ -256,12 +256,23 @@ fsic_status validate_grid(const fsic_grid &g, std::string &why) {
 
 // Stencil tiling: columns of 32 x 16, z-chunks sized so the launch has
 // enough blocks to fill 256 compute units several times over.
+// target number of stencil blocks per launch (z-chunks are halved until it
+// is reached); FSIC_STENCIL_BLOCKS overrides it for tuning
+long long stencil_block_target() {
+    static long long v = [] {
+        const char *e = getenv("FSIC_STENCIL_BLOCKS");
+        return e ? std::max(1LL, atoll(e)) : 4096LL;
+    }();
+    return v;
+}
+
 void tile_orbital(OrbDesc &od, int radius, int cpt, long long total_cols_blocks) {
     od.tiles_x = (od.nx + kTX - 1) / kTX;
     od.tiles_y = (od.ny + 8 * cpt - 1) / (8 * cpt);
     int zc = od.nz;
     long long blocks = total_cols_blocks;
-    while (blocks < 2048 && zc >= 4 * radius && zc >= 32) {
+    const long long target = stencil_block_target();
+    while (blocks < target && zc >= 4 * radius && zc >= 16) {
         zc = (zc + 1) / 2;
         blocks *= 2;
     }

@@ -77,7 +77,9 @@ template <typename T, int P, int CPT, int D, class Pol>
 __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
     using Raw = typename Pol::Raw;
     constexpr int TY = 8 * CPT;              // tile rows (each thread owns CPT columns)
-    constexpr int W = kTX + 2 * P;           // LDS row length
+    // LDS row stride 64 elements (>= kTX + 2P): the +-k-row neighbours are
+    // then multiples of 64 elements apart and fit the ds_read2st64 offsets
+    constexpr int W = 64;
     constexpr int H = TY + 2 * P;            // LDS rows
     constexpr int NH = 2 * P * (kTX + TY);   // cross-shaped halo values per plane
     constexpr int HS = (NH + 255) / 256;     // halo slots per thread
@@ -203,11 +205,13 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
         const int pz = z * plane;
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
-            const T *row = S + (ty + 8 * cc + P) * W + tx + P;
+            // xb: this row from x - P; yb: this column from row - P (stride W)
+            const T *xb = S + (ty + 8 * cc + P) * W + tx;
+            const T *yb = S + (ty + 8 * cc) * W + tx + P;
             T lap = c0x3 * q[cc][(sl0 + P) % NW];
 #pragma unroll
             for (int k = 1; k <= P; ++k)
-                lap += c[k] * ((row[k] + row[-k]) + (row[k * W] + row[-k * W]) +
+                lap += c[k] * ((xb[P + k] + xb[P - k]) + (yb[(P + k) * W] + yb[(P - k) * W]) +
                                (q[cc][(sl0 + P + k) % NW] + q[cc][(sl0 + P - k) % NW]));
             lap *= ih2;
             if (cval[cc]) dot += p.epilogue(coff[cc], pz, q[cc][(sl0 + P) % NW], lap);
@@ -309,7 +313,7 @@ struct PolCG {  // p_k = r_k + beta p_{k-1}; q = K p_k = -L p_k
         rq = make_rsrc(a.Q + od.off, bytes);
     }
     __device__ Raw raw(unsigned i, int zo) const {
-        if (k == 0) return Raw{bld<T>(rr_, i, zo), T(0)};
+        // at k == 0 beta is 0 and p_old aliases r (finite), so no branch
         return Raw{bld<T>(rr_, i, zo), bld<T>(rpo, i, zo)};
     }
     __device__ T combine(const Raw &v) const { return v.r + (T)beta * v.p; }
@@ -325,6 +329,7 @@ struct PolCG {  // p_k = r_k + beta p_{k-1}; q = K p_k = -L p_k
     }
 };
 
+template <bool HAS32>
 struct PolRes {  // res = b + L x, x = x64 (+ x32)
     const Item *items;
     const OrbDesc *orb;
@@ -343,12 +348,13 @@ struct PolRes {  // res = b + L x, x = x64 (+ x32)
         const long long M = (long long)od.nx * od.ny * od.nz;
         rx = make_rsrc(X64 + od.off, (unsigned)(M * 8));
         rb = make_rsrc(B + od.off, (unsigned)(M * 8));
-        if (X32) rx32 = make_rsrc(X32 + od.off, (unsigned)(M * 4));
+        if constexpr (HAS32) rx32 = make_rsrc(X32 + od.off, (unsigned)(M * 4));
         if (X64new) rxn = make_rsrc(X64new + od.off, (unsigned)(M * 8));
         if (R32) rr32 = make_rsrc(R32 + od.off, (unsigned)(M * 4));
     }
     __device__ Raw raw(unsigned i, int zo) const {
-        return Raw{bld<double>(rx, i, zo), X32 ? bld<float>(rx32, i, zo) : 0.0f};
+        if constexpr (HAS32) return Raw{bld<double>(rx, i, zo), bld<float>(rx32, i, zo)};
+        return Raw{bld<double>(rx, i, zo), 0.0f};
     }
     __device__ double combine(const Raw &v) const { return v.a + (double)v.b; }
     __device__ double epilogue(unsigned i, int zo, double c, double lap) const {
@@ -523,6 +529,7 @@ hipError_t launch_cg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, in
                              int cur_from_ru, int prev_from_ru, int check, hipStream_t s) {
     if (a.nitems7 <= 0) return hipSuccess;
     PolCG<T> pol{a.items7, a.orb, a, k, cur_from_ru, prev_from_ru, check, 0.0, false};
+    if (k == 0) pol.a.Pold = a.R;  // beta = 0: any finite p_old will do
 #define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolCG<T>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
     FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
@@ -543,10 +550,17 @@ hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7,
                                 const float *X32, const double *B, double *X64new, float *R32,
                                 double *partRU, hipStream_t s) {
     if (nitems7 <= 0) return hipSuccess;
-    PolRes pol{items7, orb, done, X64, X32, B, X64new, R32, partRU, false};
-#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolRes>), dim3(nitems7), dim3(256), 0, s, pol, c)
-    FSIC_RADIUS_SWITCH(radius, CALL)
+    if (X32) {
+        PolRes<true> pol{items7, orb, done, X64, X32, B, X64new, R32, partRU, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolRes<true>>), dim3(nitems7), dim3(256), 0, s, pol, c)
+        FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
+    } else {
+        PolRes<false> pol{items7, orb, done, X64, X32, B, X64new, R32, partRU, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolRes<false>>), dim3(nitems7), dim3(256), 0, s, pol, c)
+        FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
+    }
     return hipGetLastError();
 }
 
