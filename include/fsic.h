@@ -9,7 +9,7 @@
  *   (a) the Fermi orbitals F_i = sum_a psi_a(a_i) psi_a / sqrt(rho(a_i))
  *       (Eq. 6-8; psi at the FODs by cubic interpolation, Sec. II.B),
  *   (b) their Loewdin orthonormalisation phi = S^{-1/2} F, S = dV F F^T
- *       (Sec. II.A),
+ *       (Sec. I.B),
  *   (c) one finite-difference Poisson solve per FLO density rho_i = phi_i^2
  *       (high-order centred Laplacian, Dirichlet values from a multipole
  *       expansion, Sec. II.A), solved by conjugate gradients,
@@ -148,7 +148,7 @@ fsic_status fsic_create(fsic_ctx **ctx, const fsic_opts *opts, void *hip_stream)
 /* Changes the options of an existing context (same validation as create). */
 fsic_status fsic_set_opts(fsic_ctx *ctx, const fsic_opts *opts);
 
-/* Forward pass over nsys systems (Eq. 1, 5-8, 13; Sec. II.A-C).
+/* Forward pass over nsys systems (Eq. 1, 5-8, 13; Sec. I.B, II.A-C).
  *   e_sic: HOST [nsys], E_SIC of each system summed over its spins (Hartree).
  *   U, X:  HOST or NULL, [sum over systems and spins of nocc]: the Hartree
  *          self-energy U[rho_i] and E_xc[rho_i, 0] of every FLO density, in
@@ -211,7 +211,7 @@ fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lma
 fsic_status fsic_op_invsqrt(int32_t N, int32_t count, const double *S, double *Z, double *lam,
                             void *hip_stream);
 
-/* Fermi-Loewdin orbitals of one spin channel (Eq. 6-8, Sec. II.A-B):
+/* Fermi-Loewdin orbitals of one spin channel (Eq. 6-8, Sec. I.B, II.B):
  * psi (DEVICE [N][M]) and FODs (HOST [N][3]) give, for every non-NULL
  * DEVICE output, T ([N][N], Eq. 8), G = dV psi psi^T ([N][N]), S = T G T^T
  * ([N][N], the FO overlap), Z = S^{-1/2} ([N][N]) and phi = Z T psi

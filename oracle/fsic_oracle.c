@@ -694,7 +694,7 @@ static int forward_impl(const int *n, double h, const double *origin, int p, int
             f->F[(long)i * M + m] = s;
         }
     /* (b) overlap S_ij = dV sum_r F_i F_j and Loewdin orthonormalisation
-     * phi = S^{-1/2} F (Sec. II.A: "FOs are normalized but not orthogonal") */
+     * phi = S^{-1/2} F (Sec. I.B: Fermi orbitals are normalised, not mutually orthogonal) */
     for (int i = 0; i < N; ++i)
         for (int j = 0; j <= i; ++j) {
             double s = dV * dot(M, f->F + (long)i * M, f->F + (long)j * M);

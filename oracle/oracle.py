@@ -6,7 +6,7 @@ imports this module and this module imports nothing from the GPU library.
 
 Every function follows the definitions of Diaz et al., arXiv 2108.01186:
 Eq. 1 (PZ-SIC energy), Eq. 5 (orbital SIC potential), Eq. 6-8 (Fermi orbitals
-and the transformation matrix), Sec. II.A (Loewdin orthonormalisation,
+and the transformation matrix), Sec. I.B (Loewdin orthonormalisation), Sec. II.A (the
 finite-difference Poisson problem with multipole Dirichlet values), Sec. II.B
 (cubic interpolation at the FODs), Sec. II.C / Eq. 13 (Slater-averaged SIC
 potential), Eq. 9-11 (FOD gradient).

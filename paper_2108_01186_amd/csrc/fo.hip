@@ -1,4 +1,4 @@
-// Fermi orbitals and their Loewdin orthonormalisation (Eq. 6-8, Sec. II.A),
+// Fermi orbitals and their Loewdin orthonormalisation (Eq. 6-8, Sec. I.B),
 // the cubic interpolation of the KS orbitals at the FODs (Sec. II.B), and the
 // reverse-mode derivative of that chain for the FOD gradient (Eq. 9-11).
 //

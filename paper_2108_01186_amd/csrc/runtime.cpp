@@ -620,6 +620,24 @@ const char *fsic_status_string(fsic_status s) {
 
 const char *fsic_last_error(const fsic_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+// Stencil weights and tile shape for a radius: 32 x 16 columns per block and
+// one plane of prefetch (the 12th-order default); FSIC_STENCIL_CPT and
+// FSIC_STENCIL_DEPTH override the shape for tuning.
+static void set_stencil_defaults(fsic_ctx *c, int radius) {
+    c->radius = radius;
+    c->cf = fd_weights(radius);
+    c->cpt_fp64 = c->cpt_mixed = 2;
+    if (radius == 6) c->cf.depth = 1;
+    if (const char *e = getenv("FSIC_STENCIL_CPT")) {
+        const int v = atoi(e);
+        if (v == 2 || (radius == 6 && (v == 1 || v == 4))) c->cpt_fp64 = c->cpt_mixed = v;
+    }
+    if (const char *e = getenv("FSIC_STENCIL_DEPTH")) {
+        const int v = atoi(e);
+        if (radius == 6 && (v == 1 || (v == 2 && c->cpt_fp64 <= 2))) c->cf.depth = v;
+    }
+}
+
 fsic_status fsic_create(fsic_ctx **ctx, const fsic_opts *opts, void *hip_stream) {
     if (!ctx) return FSIC_EINVAL;
     *ctx = nullptr;
@@ -631,18 +649,7 @@ fsic_status fsic_create(fsic_ctx **ctx, const fsic_opts *opts, void *hip_stream)
     c->opts = *opts;
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return FSIC_EHIP; }
-    c->radius = opts->fd_order / 2;
-    c->cf = fd_weights(c->radius);
-    if (c->radius != 6) c->cpt_fp64 = c->cpt_mixed = 2;  // other orders: one tile shape
-    if (c->radius == 6) c->cf.depth = 1;
-    if (const char *e = getenv("FSIC_STENCIL_CPT")) {
-        const int v = atoi(e);
-        if (v == 2 || (c->radius == 6 && (v == 1 || v == 4))) c->cpt_fp64 = c->cpt_mixed = v;
-    }
-    if (const char *e = getenv("FSIC_STENCIL_DEPTH")) {
-        const int v = atoi(e);
-        if (c->radius == 6 && (v == 1 || (v == 2 && c->cpt_fp64 <= 2))) c->cf.depth = v;
-    }
+    set_stencil_defaults(c, opts->fd_order / 2);
     c->ht = harm_tables(opts->lmax);
     if (c->status.ensure(1) != hipSuccess) { delete c; return FSIC_ENOMEM; }
     *ctx = c;
@@ -655,16 +662,7 @@ fsic_status fsic_set_opts(fsic_ctx *c, const fsic_opts *opts) {
     fsic_status st = validate_opts(opts, why);
     if (st) return set_err(c, st, why);
     c->opts = *opts;
-    const int depth = c->cf.depth;
-    c->radius = opts->fd_order / 2;
-    c->cf = fd_weights(c->radius);
-    if (c->radius == 6) {
-        c->cf.depth = depth;
-        c->cpt_fp64 = 1;
-        c->cpt_mixed = 2;
-    } else {
-        c->cpt_fp64 = c->cpt_mixed = 2;
-    }
+    set_stencil_defaults(c, opts->fd_order / 2);
     c->ht = harm_tables(opts->lmax);
     c->tape = false;
     return FSIC_OK;

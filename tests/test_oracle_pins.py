@@ -325,7 +325,7 @@ def test_jacobi_matches_lapack(oracle, N):
 
 
 # ---------------------------------------------------------------------------
-# Fermi and Fermi-Loewdin orbitals (Eq. 6-8, Sec. II.A)
+# Fermi and Fermi-Loewdin orbitals (Eq. 6-8, Sec. I.B)
 # ---------------------------------------------------------------------------
 
 def test_fo_normalised_flo_orthonormal(oracle, mol40, mol40_oracle):
