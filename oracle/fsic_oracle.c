@@ -816,6 +816,32 @@ int orc_sic_spin(const int *n, double h, const double *origin, int p, int lmax,
     return st;
 }
 
+/* The two energy terms of one orbital density (Eq. 1): the Hartree energy
+ * U = 1/2 dV sum_r rho v_H[rho] and the fully polarised LSDA energy
+ * X = dV sum_r rho (eps_x + eps_c), for sampled checks on large grids. */
+int orc_orbital_terms(const int *n, double h, const double *origin, int p, int lmax,
+                      double tol, int maxit, double rho_floor, const double *rho,
+                      double *U, double *X, int *iters, double *relres)
+{
+    if (!n || !origin || !rho || !U || !X || h <= 0) return ORC_EBADARG;
+    const long M = grid_size(n);
+    const double dV = h * h * h;
+    double *v = malloc((size_t)M * sizeof(double));
+    if (!v) return ORC_EBADARG;
+    int st = orc_poisson(n, h, origin, p, lmax, rho, tol, maxit, v, iters, relres);
+    double u = 0.0, x = 0.0;
+    for (long m = 0; m < M; ++m) {
+        double ex, ec, vx, vc;
+        u += rho[m] * v[m];
+        orc_xc_pol(rho[m], rho_floor, &ex, &ec, &vx, &vc);
+        x += rho[m] * (ex + ec);
+    }
+    *U = 0.5 * dV * u;
+    *X = dV * x;
+    free(v);
+    return st;
+}
+
 /* ------------------------------------------------------------------------ */
 /* FOD gradient (Eq. 9-11), tangent mode                                     */
 /* ------------------------------------------------------------------------ */

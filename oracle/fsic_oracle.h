@@ -73,6 +73,13 @@ int orc_interp(const int *n, double h, const double *origin, int N, const double
  * A = U diag(lam) U^T, U column j = eigenvector j (row-major U[i*N+j]). */
 int orc_jacobi_eig(int N, const double *A, double *lam, double *U);
 
+/* Energy terms of one orbital density rho[M] (Eq. 1): U = 1/2 dV rho.v_H[rho]
+ * (Poisson problem as in orc_poisson) and X = dV sum rho (eps_x + eps_c) at
+ * full spin polarisation.  iters / relres may be NULL. */
+int orc_orbital_terms(const int *n, double h, const double *origin, int p, int lmax,
+                      double tol, int maxit, double rho_floor, const double *rho,
+                      double *U, double *X, int *iters, double *relres);
+
 /* One spin channel of the SIC path (Fermi orbitals, Loewdin, Poisson,
  * LSDA, Slater average).  Outputs other than e_spin may be NULL.
  *   e_spin = -sum_i (U_i + X_i)

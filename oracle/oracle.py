@@ -132,6 +132,19 @@ def poisson(rho, n, h, origin, p=6, lmax=6, tol=1e-13, maxit=20000, transpose=Fa
     return v, it.value, rr.value
 
 
+def orbital_terms(rho, n, h, origin, p=6, lmax=6, tol=1e-13, maxit=20000, rho_floor=1e-30):
+    """(U, X, iters, relres) of one orbital density: Hartree and LSDA terms of Eq. 1."""
+    n, origin = _grid(n, origin)
+    rho = _f64(rho)
+    U, X, rr = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    it = ctypes.c_int(0)
+    _check(lib().orc_orbital_terms(_i(n), ctypes.c_double(h), _d(origin), p, lmax,
+                                   ctypes.c_double(tol), maxit, ctypes.c_double(rho_floor),
+                                   _d(rho), ctypes.byref(U), ctypes.byref(X), ctypes.byref(it),
+                                   ctypes.byref(rr)))
+    return U.value, X.value, it.value, rr.value
+
+
 def xc_pol(rho, rho_floor=1e-30):
     """(eps_x, eps_c, v_x, v_c) at full spin polarisation, elementwise."""
     rho = np.atleast_1d(_f64(rho))

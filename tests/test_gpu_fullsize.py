@@ -1,0 +1,201 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (both spins batched, mixed precision, tol 1e-10):
+
+* 96^3 / 16 + 15 orbitals: every output against the oracle (E_SIC, U_i, X_i,
+  V_SIC elementwise, spin-up FOD gradient), and the V_SIC scale factor;
+* 128^3 / 32 + 32 orbitals: the FOD gradient through the autograd Function
+  against central differences (step 1e-4 Bohr) of the library's FP64 energy
+  on 8 seeded coordinates, and sampled orbital energies against the oracle;
+* 24 uneven systems in one batch: the smallest systems against the oracle,
+  every system against its own single-system solve, a sampled orbital of
+  the largest system against the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2108_01186_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-8       # Ha, energy target
+F_TOL = 1e-6       # Ha/Bohr, force target
+# per-orbital U_i, X_i at large N: both sides form S^{-1/2} in FP64 from S
+# rounded differently (grid sums in another order), and the condition number
+# of S carries that rounding into phi and rho_i (observed: 1.2e-11 in X_i at
+# N = 39 on a 128^3 grid)
+TERM_TOL = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2108_01186_amd import fsic
+    return fsic
+
+
+def _host(a):
+    return np.asarray(a.cpu().numpy() if hasattr(a, "cpu") else a)
+
+
+def _flags(F):
+    return F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE
+
+
+def _dict(torch, s):
+    return {"n": s.n, "h": s.h, "origin": s.origin, "psi": list(s.psi), "fod": list(s.fod),
+            "vsic": [torch.empty(s.M, dtype=torch.float64, device="cuda") for _ in s.nocc]}
+
+
+def test_mol96_all_outputs_vs_oracle(torch_cuda, F, oracle):
+    torch = torch_cuda
+    _say("mol96: generate")
+    s = synth.make_workload("mol96", device="cuda")
+    ctx = F.Context(precision="mixed", tol=1e-10, flags=_flags(F))
+    d = _dict(torch, s)
+    _say("mol96: GPU forward + backward (mixed)")
+    e, U, X, st = ctx.forward([d])
+    g = ctx.backward([list(s.nocc)])[0]
+    vs = [_host(v) for v in d["vsic"]]
+    assert st["max_relres"] <= 1e-10
+    d_half = _dict(torch, s)
+    ctx.set_opts(vsic_scale=0.5)
+    e_half = ctx.forward([d_half])[0]
+    ctx.close()
+    assert e_half[0] == e[0]
+    for sp in range(2):
+        vh = _host(d_half["vsic"][sp])
+        assert np.abs(vh - 0.5 * vs[sp]).max() <= 1e-15 * np.abs(vs[sp]).max()
+
+    e_ref = 0.0
+    off = 0
+    for sp in range(2):
+        _say(f"mol96: oracle spin {sp}")
+        r = oracle.sic_spin(_host(s.psi[sp]), s.fod[sp], s.n, s.h, s.origin)
+        e_ref += r.e
+        N = s.nocc[sp]
+        assert np.abs(U[off:off + N] - r.U).max() < 1e-9, np.abs(U[off:off + N] - r.U).max()
+        assert np.abs(X[off:off + N] - r.X).max() < 1e-11
+        dv = np.abs(vs[sp] - r.vsic).max()
+        assert dv < 1e-7, dv
+        off += N
+    _say(f"mol96: |dE| = {abs(e[0] - e_ref):.3e}")
+    assert abs(e[0] - e_ref) < E_TOL
+
+    _say("mol96: oracle gradient, spin up")
+    gref = oracle.sic_grad_spin(_host(s.psi[0]), s.fod[0], s.n, s.h, s.origin)
+    dg = np.abs(g[0] - gref).max()
+    _say(f"mol96: max |d grad| = {dg:.3e}")
+    assert dg < F_TOL / 10
+
+
+def _fd_coords(s, count, seed, eps):
+    """Seeded FOD coordinates whose +-eps step stays inside one grid cell
+    (the interpolant is only continuous across node planes)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    ntot = sum(s.nocc)
+    while len(out) < count:
+        k = int(rng.integers(0, ntot))
+        sp, i = (0, k) if k < s.nocc[0] else (1, k - s.nocc[0])
+        dd = int(rng.integers(0, 3))
+        t = (s.fod[sp][i, dd] - s.origin[dd]) / s.h
+        if math.floor(t + eps / s.h) != math.floor(t - eps / s.h):
+            continue
+        if (sp, i, dd) not in out:
+            out.append((sp, i, dd))
+    return out
+
+
+def test_mol128_forces_vs_central_differences(torch_cuda, F, oracle):
+    torch = torch_cuda
+    _say("mol128: generate")
+    s = synth.make_workload("mol128", device="cuda")
+    ctx = F.Context(precision="mixed", tol=1e-10)
+    fods = [torch.tensor(f, requires_grad=True) for f in s.fod]
+    _say("mol128: autograd forward + backward (mixed)")
+    E, *_ = F.flosic_sic(ctx, s.n, s.h, s.origin, list(s.psi), fods)
+    E.backward()
+    g = [f.grad.numpy() for f in fods]
+    _, U, X, _ = ctx.forward([_dict(torch, s)])
+    ctx.close()
+
+    eps = 1e-4
+    fctx = F.Context(precision="fp64", tol=1e-12)
+    base = {"n": s.n, "h": s.h, "origin": s.origin, "psi": list(s.psi)}
+    for (sp, i, dd) in _fd_coords(s, 8, 128, eps):
+        f = [x.copy() for x in s.fod]
+        f[sp][i, dd] += eps
+        ep = fctx.forward([dict(base, fod=f)])[0][0]
+        f[sp][i, dd] -= 2 * eps
+        em = fctx.forward([dict(base, fod=f)])[0][0]
+        fd = (ep - em) / (2 * eps)
+        _say(f"mol128: spin {sp} FOD {i} axis {dd}: adjoint {g[sp][i, dd]:+.9e} FD {fd:+.9e}")
+        assert abs(fd - g[sp][i, dd]) < F_TOL
+    fctx.close()
+
+    _say("mol128: oracle orbital terms (2 sampled orbitals)")
+    for sp, i in ((0, 5), (1, 27)):
+        phi, _, _, _ = oracle.flo_spin(_host(s.psi[sp]), s.fod[sp], s.n, s.h, s.origin)
+        u, x, _, _ = oracle.orbital_terms(phi[i] ** 2, s.n, s.h, s.origin)
+        k = i + (s.nocc[0] if sp else 0)
+        assert abs(U[k] - u) < TERM_TOL, (U[k], u)
+        assert abs(X[k] - x) < TERM_TOL, (X[k], x)
+
+
+def test_batch24_uneven_systems(torch_cuda, F, oracle):
+    torch = torch_cuda
+    specs = synth.batch24_specs()
+    _say("batch24: generate 24 systems")
+    systems = synth.make_batch24(device="cuda")
+    ctx = F.Context(precision="mixed", tol=1e-10, flags=_flags(F))
+    dicts = [_dict(torch, s) for s in systems]
+    _say("batch24: one batched forward + backward")
+    e, U, X, st = ctx.forward(dicts)
+    assert st["nsolves"] == sum(sum(s.nocc) for s in systems)
+    assert st["max_relres"] <= 1e-10
+    gb = ctx.backward([list(s.nocc) for s in systems])
+    ctx.close()
+
+    _say("batch24: each system alone (FP64)")
+    single = F.Context(precision="fp64", tol=1e-10, flags=_flags(F))
+    for k, s in enumerate(systems):
+        ek = single.forward([_dict(torch, s)])[0][0]
+        gk = single.backward([list(s.nocc)])[0]
+        assert abs(e[k] - ek) < E_TOL, (k, e[k], ek)
+        for sp in range(len(s.nocc)):
+            assert np.abs(gb[k][sp] - gk[sp]).max() < F_TOL / 10, k
+    single.close()
+
+    order = sorted(range(len(specs)), key=lambda k: specs[k]["n"] ** 3 * sum(specs[k]["nocc"]))
+    for k in order[:2]:
+        s = systems[k]
+        _say(f"batch24: oracle for system {k} (n={s.n[0]}, N={s.nocc})")
+        eref = 0.0
+        for sp in range(len(s.nocc)):
+            r = oracle.sic_spin(_host(s.psi[sp]), s.fod[sp], s.n, s.h, s.origin)
+            eref += r.e
+            vs = _host(dicts[k]["vsic"][sp])
+            assert np.abs(vs - r.vsic).max() < 1e-7
+        assert abs(e[k] - eref) < E_TOL, (k, e[k], eref)
+
+    k = order[-1]
+    s = systems[k]
+    _say(f"batch24: oracle orbital terms of the largest system {k} (n={s.n[0]}, N={s.nocc})")
+    phi, _, _, _ = oracle.flo_spin(_host(s.psi[0]), s.fod[0], s.n, s.h, s.origin)
+    u, x, _, _ = oracle.orbital_terms(phi[1] ** 2, s.n, s.h, s.origin)
+    base = sum(sum(systems[j].nocc) for j in range(k))
+    assert abs(U[base + 1] - u) < TERM_TOL, (U[base + 1], u)
+    assert abs(X[base + 1] - x) < TERM_TOL, (X[base + 1], x)

@@ -192,6 +192,23 @@ def test_gaussian_self_energy(oracle, n, h, sigma, tol):
     assert abs(U - 1.0 / (2 * math.sqrt(math.pi) * sigma)) < tol
 
 
+def test_orbital_terms_gaussian_and_consistency(oracle, mol40, mol40_oracle):
+    """orbital_terms: U of a centred Gaussian is q^2 / (2 sqrt(pi) sigma); on the
+    FLO densities of a molecule it reproduces the channel's U_i and X_i."""
+    n, h, sigma = 40, 0.3, 1.0
+    rho = synth.gaussian_charge(n, h, sigma)
+    U, X, it, rr = oracle.orbital_terms(rho, (n, n, n), h, _origin(n, h))
+    assert rr <= 1e-13
+    assert abs(U - 1.0 / (2 * math.sqrt(math.pi) * sigma)) < 2e-9
+    assert X < 0
+    s = mol40
+    phi, _, _, _ = oracle.flo_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin)
+    for i in (0, 3):
+        U, X, _, _ = oracle.orbital_terms(phi[i] ** 2, s.n, s.h, s.origin)
+        assert abs(U - mol40_oracle.U[i]) < 1e-12
+        assert abs(X - mol40_oracle.X[i]) < 1e-13
+
+
 def test_gaussian_potential_pointwise(oracle):
     """Potential of a centred Gaussian: erf(r / (sqrt2 sigma)) / r at every node."""
     n, h, sigma = 40, 0.3, 1.0
