@@ -83,7 +83,7 @@ enum { FSIC_CG = 0 };
 #define FSIC_WANT_VSIC       1u  /* write V_SIC into fsic_system.vsic[] */
 #define FSIC_KEEP_TAPE       2u  /* keep what fsic_backward needs */
 #define FSIC_ALLOW_NONORTHO  4u  /* accept non-orthonormal psi (S = T G T^T is exact anyway) */
-#define FSIC_PROFILE         8u  /* time every CG sweep with HIP events (fsic_stats.sweep_*) */
+#define FSIC_PROFILE         8u  /* time sampled CG launches with HIP events (fsic_stats.sweep_*) */
 
 typedef struct {
     int32_t n[3];       /* nodes per axis, each >= 8 */
@@ -127,13 +127,28 @@ typedef struct {
     double  ms_phase[8];      /* host wall time per phase: 0 setup, 1 FO+Loewdin,
                                  2 boundary+RHS, 3 CG, 4 XC+average, 5 adjoint CG,
                                  6 adjoint rest, 7 total */
-    /* with FSIC_PROFILE: HIP-event time of the CG launches on the context's
-     * stream and their algorithmic HBM bytes (each array of an active orbital
-     * read or written once per launch) */
-    int32_t sweep_launches;   /* stencil sweeps (p = r + beta p, q = -L p) */
-    int32_t update_launches;  /* pointwise updates (x += alpha p, r -= alpha q) */
+    /* with FSIC_PROFILE: HIP-event time, on the context's stream, of the CG
+     * launches of every 16th iteration (k % 16 == 15; the environment
+     * variable FSIC_PROFILE_EVERY changes the period, 1 = every launch), and
+     * the algorithmic HBM bytes of exactly those launches (each array of an
+     * active orbital read or written once per launch).  Sampling keeps the
+     * events' own cost (a few microseconds per recorded launch) out of the
+     * timed work. */
+    int32_t sweep_launches;   /* sampled stencil sweeps (p = r + beta p, q = -L p) */
+    int32_t update_launches;  /* sampled pointwise updates (x += alpha p, r -= alpha q) */
     double  sweep_ms, sweep_bytes;
     double  update_ms, update_bytes;
+    /* stencil shape of the CG sweeps: tiles of 32 x 8*stencil_cpt columns,
+     * stencil_depth planes fetched ahead, z-chunks halved until a launch has
+     * stencil_blocks blocks.  The first call for a given (device, precision,
+     * order, grid sizes and orbital counts) times the candidate shapes on
+     * the batch and keeps the fastest for the rest of the process (tune_ms:
+     * time that took, 0 when the shape came from that cache or from
+     * FSIC_STENCIL_CPT / FSIC_STENCIL_DEPTH / FSIC_STENCIL_BLOCKS, or
+     * defaults under FSIC_AUTOTUNE=0). */
+    int32_t stencil_cpt, stencil_depth;
+    int64_t stencil_blocks;
+    double  tune_ms;
 } fsic_stats;
 
 /* Fills *o with the defaults: fd_order 12, lmax 6, CG, FP64, tol 1e-10,

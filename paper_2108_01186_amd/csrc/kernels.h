@@ -23,10 +23,11 @@ struct CGIter {
     int nitems8;
     const OrbDesc *orb;
     T *R;               // residual
-    T *Pold, *Pnew;     // search directions of iterations k-1 and k
+    T *P;               // search direction: p_k before the update of iteration k, p_{k+1} after
     T *Q;               // K p
     T *X;               // solution (FP64 path) or FP32 correction (mixed path)
-    double *part7;      // [tot7]   p.q partial sums
+    double *part7;      // [3*tot7] p.q, r.q and q.q partial sums of the sweep (three blocks of tot7)
+    int tot7;
     double *part8;      // [2*tot8] r.r partial sums, by iteration parity
     double *partRU;     // [tot7]   FP64-residual partial sums
     int tot8;
@@ -34,20 +35,24 @@ struct CGIter {
     int *iters;         // per orbital: iterations at convergence
     int *rs_iter;       // per orbital: iteration that restarts CG from the FP64 residual (or null)
     int *nact;          // per orbital: active sweeps [norb] then active updates [norb]
+    int *nsamp;         // same layout for the profiled launches only (null: not profiled)
     int norb;
     double *rrfin;      // per orbital: residual norm^2 at convergence
     const double *bb;   // per orbital: ||b||^2
     double tol2;        // tol^2
 };
 
-// One stencil sweep (p_k = r_k + beta p_{k-1}; q = -L p_k; p.q partials).
-//   k: iteration; cur_from_ru / prev_from_ru: r_k.r_k (r_{k-1}.r_{k-1}) is in
-//   partRU rather than part8; check: test convergence on r_k.r_k first.
+// One stencil sweep: q = K p_k = -L p_k with partial sums of p.q, r.q, q.q.
+//   k: iteration; cur_from_ru: r_k.r_k is in partRU rather than part8;
+//   check: test convergence on r_k.r_k first.  p_k is read from R when the
+//   recursion (re)starts at k (k == 0 or a restart after a pause).
 template <typename T>
 hipError_t launch_cg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, int k,
-                             int cur_from_ru, int prev_from_ru, int check, hipStream_t s);
+                             int cur_from_ru, int check, hipStream_t s);
 
-// One pointwise update (x += alpha p; r -= alpha q; r.r partials).
+// One pointwise update: x += alpha p; r -= alpha q; r.r partials; and the
+// next search direction p = r + beta p with beta from the sweep's partials
+// (|r - alpha q|^2 = r.r - 2 alpha r.q + alpha^2 q.q).
 //   x_first: x is not read (x = alpha p).
 template <typename T>
 hipError_t launch_cg_update(const CGIter<T> &a, int k, int cur_from_ru, int x_first,

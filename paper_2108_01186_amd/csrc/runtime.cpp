@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -205,8 +207,11 @@ struct fsic_ctx {
     int nsys = 0;
     bool tape = false;
     int radius = 6;
-    int cpt_fp64 = 1, cpt_mixed = 2;  // stencil tile height per solve precision
     Coeffs cf{};
+    // stencil shape of the last batch and the time its tuning took (0: cached)
+    int shape_cpt = 2, shape_depth = 1;
+    long long shape_target = 0;
+    double tune_ms = 0.0;
     HarmTables ht{};
 
     bool fail(fsic_status, const std::string &m) {
@@ -254,24 +259,30 @@ fsic_status validate_grid(const fsic_grid &g, std::string &why) {
     return FSIC_OK;
 }
 
-// Stencil tiling: columns of 32 x 16, z-chunks sized so the launch has
-// enough blocks to fill 256 compute units several times over.
-// target number of stencil blocks per launch (z-chunks are halved until it
-// is reached); FSIC_STENCIL_BLOCKS overrides it for tuning
-long long stencil_block_target() {
-    static long long v = [] {
-        const char *e = getenv("FSIC_STENCIL_BLOCKS");
-        return e ? std::max(1LL, atoll(e)) : 4096LL;
+// Stencil shape: tile height (32 x 8*cpt columns per block), planes
+// prefetched ahead (depth), and the number of blocks a launch should reach
+// (z-chunks are halved until it does, so a launch fills the 256 compute
+// units several times over).
+struct Shape {
+    int cpt, depth;
+    long long target;
+};
+
+// CG iterations between profiled ones (FSIC_PROFILE); FSIC_PROFILE_EVERY
+// overrides the default 16
+int profile_period() {
+    static int v = [] {
+        const char *e = getenv("FSIC_PROFILE_EVERY");
+        return e ? std::max(1, atoi(e)) : 16;
     }();
     return v;
 }
 
-void tile_orbital(OrbDesc &od, int radius, int cpt, long long total_cols_blocks) {
+void tile_orbital(OrbDesc &od, int radius, int cpt, long long total_cols_blocks, long long target) {
     od.tiles_x = (od.nx + kTX - 1) / kTX;
     od.tiles_y = (od.ny + 8 * cpt - 1) / (8 * cpt);
     int zc = od.nz;
     long long blocks = total_cols_blocks;
-    const long long target = stencil_block_target();
     while (blocks < target && zc >= 4 * radius && zc >= 16) {
         zc = (zc + 1) / 2;
         blocks *= 2;
@@ -289,7 +300,8 @@ struct Group {
     int chan;
 };
 
-void build_batch(const std::vector<Group> &groups, int radius, int cpt, Batch &b) {
+void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, Batch &b) {
+    const int cpt = sh.cpt;
     b = Batch{};
     long long cols = 0;
     for (const Group &g : groups)
@@ -300,7 +312,7 @@ void build_batch(const std::vector<Group> &groups, int radius, int cpt, Batch &b
         for (int i = 0; i < g.count; ++i) {
             OrbDesc od{};
             od.nx = g.n[0]; od.ny = g.n[1]; od.nz = g.n[2];
-            tile_orbital(od, radius, cpt, cols);
+            tile_orbital(od, radius, cpt, cols, sh.target);
             od.nt7 = od.tiles_x * od.tiles_y * od.tiles_z;
             od.base7 = b.tot7;
             b.tot7 += od.nt7;
@@ -351,19 +363,17 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     if (precision == FSIC_FP64) {
         HIPCHK(c, c->R.ensure(F));
         HIPCHK(c, c->P0.ensure(F));
-        HIPCHK(c, c->P1.ensure(F));
         HIPCHK(c, c->Q.ensure(F));
     } else {
         HIPCHK(c, c->R32.ensure(F));
         HIPCHK(c, c->P32a.ensure(F));
-        HIPCHK(c, c->P32b.ensure(F));
         HIPCHK(c, c->Q32.ensure(F));
         HIPCHK(c, c->X32.ensure(F));
     }
     const int norb = (int)b.orb.size();
     const int nlm = (c->opts.lmax + 1) * (c->opts.lmax + 1);
     HIPCHK(c, c->Gh.ensure((size_t)b.ghosts));
-    HIPCHK(c, c->part7.ensure((size_t)b.tot7));
+    HIPCHK(c, c->part7.ensure(3 * (size_t)b.tot7));
     HIPCHK(c, c->partRU.ensure((size_t)b.tot7));
     HIPCHK(c, c->part8.ensure(2 * (size_t)b.tot8));
     HIPCHK(c, c->partQ.ensure((size_t)b.tot8 * kMaxLM));
@@ -377,7 +387,7 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     HIPCHK(c, c->done.ensure(norb));
     HIPCHK(c, c->iters.ensure(norb));
     HIPCHK(c, c->rs_iter.ensure(norb));
-    HIPCHK(c, c->nact.ensure(3 * (size_t)norb));
+    HIPCHK(c, c->nact.ensure(4 * (size_t)norb));
     if (c->h_done_cap < (size_t)norb) {
         if (c->h_done) hipHostFree(c->h_done);
         c->h_done = nullptr;
@@ -394,6 +404,145 @@ struct SolveReport {
     double max_relres = 0.0;
     bool converged = true;
 };
+
+// ---------------------------------------------------------------------------
+// stencil autotuner
+// ---------------------------------------------------------------------------
+
+Shape default_shape(int radius, int precision) {
+    if (radius != 6) return Shape{2, 2, 4096};
+    return precision == FSIC_MIXED ? Shape{2, 1, 1024} : Shape{1, 1, 1024};
+}
+
+std::vector<Shape> shape_candidates(int radius) {
+    std::vector<Shape> v;
+    const long long targets[] = {1024, 2048, 4096, 8192};
+    if (radius != 6) {
+        for (long long t : targets) v.push_back(Shape{2, 2, t});
+        return v;
+    }
+    const int cd[][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {4, 1}};
+    for (auto &x : cd)
+        for (long long t : targets) v.push_back(Shape{x[0], x[1], t});
+    return v;
+}
+
+// A shape fixed by the environment (FSIC_STENCIL_CPT / _DEPTH / _BLOCKS), or
+// the default when FSIC_AUTOTUNE=0; false: tune.
+bool fixed_shape(int radius, int precision, Shape &sh) {
+    const char *ec = getenv("FSIC_STENCIL_CPT"), *ed = getenv("FSIC_STENCIL_DEPTH");
+    const char *eb = getenv("FSIC_STENCIL_BLOCKS"), *ea = getenv("FSIC_AUTOTUNE");
+    sh = default_shape(radius, precision);
+    if (!ec && !ed && !eb) return ea && atoi(ea) == 0;
+    if (ec) {
+        const int v = atoi(ec);
+        if (v == 2 || (radius == 6 && (v == 1 || v == 4))) sh.cpt = v;
+    }
+    if (ed) {
+        const int v = atoi(ed);
+        if (radius == 6 && (v == 1 || (v == 2 && sh.cpt <= 2))) sh.depth = v;
+    }
+    if (sh.cpt == 4) sh.depth = 1;
+    if (eb) sh.target = std::max(1LL, atoll(eb));
+    return true;
+}
+
+// Time the CG sweep (k = 0, no convergence test) of every candidate shape on
+// the batch's own buffers and keep the fastest.  The solve that follows
+// rewrites everything these launches touch (q, the p.q partials and the
+// activity counters).
+template <typename T>
+fsic_status time_shapes(fsic_ctx *c, const std::vector<Group> &groups, int precision,
+                        const std::vector<Shape> &cands, Shape &best) {
+    hipStream_t s = c->stream;
+    Batch b0;
+    build_batch(groups, c->radius, cands[0], b0);
+    fsic_status st = prepare_batch(c, b0, precision);
+    if (st) return st;
+    const bool mixed = precision == FSIC_MIXED;
+    const size_t F = (size_t)b0.fields;
+    T *R = mixed ? (T *)(void *)c->R32.p : (T *)(void *)c->R.p;
+    T *P = mixed ? (T *)(void *)c->P32a.p : (T *)(void *)c->P0.p;
+    T *Q = mixed ? (T *)(void *)c->Q32.p : (T *)(void *)c->Q.p;
+    HIPCHK(c, hipMemsetAsync(R, 0, F * sizeof(T), s));
+    HIPCHK(c, hipMemsetAsync(P, 0, F * sizeof(T), s));
+    const int norb = (int)b0.orb.size();
+    HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
+    HIPCHK(c, hipMemsetAsync(c->part8.p, 0, 2 * (size_t)b0.tot8 * sizeof(double), s));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return set_err(c, FSIC_EHIP, "hipEventCreate failed");
+    }
+    float best_ms = 0.f;
+    fsic_status res = FSIC_OK;
+    for (const Shape &sh : cands) {
+        Batch b;
+        build_batch(groups, c->radius, sh, b);
+        if ((res = upload(c, c->d_orb, b.orb))) break;
+        if ((res = upload(c, c->d_items7, b.items7))) break;
+        if (c->part7.ensure(3 * (size_t)b.tot7) != hipSuccess) { res = FSIC_ENOMEM; break; }
+        Coeffs cf = c->cf;
+        cf.cpt = sh.cpt;
+        cf.depth = sh.depth;
+        CGIter<T> a{};
+        a.items7 = c->d_items7.p; a.nitems7 = (int)b.items7.size();
+        a.orb = c->d_orb.p;
+        a.R = R; a.P = P; a.Q = Q;
+        a.part7 = c->part7.p; a.tot7 = b.tot7; a.part8 = c->part8.p; a.tot8 = b.tot8;
+        a.partRU = c->partRU.p; a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p;
+        a.bb = c->bb.p; a.nact = c->nact.p; a.norb = norb; a.tol2 = 0.0;
+        hipError_t he = launch_cg_stencil<T>(c->radius, cf, a, 0, 0, 0, s);
+        if (he == hipSuccess) he = hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && he == hipSuccess; ++r) he = launch_cg_stencil<T>(c->radius, cf, a, 0, 0, 0, s);
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) { res = set_err(c, FSIC_EHIP, hipGetErrorString(he)); break; }
+        if (&sh == &cands[0] || ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return res;
+}
+
+// The stencil shape for a batch: fixed by the environment, else the fastest
+// candidate for this (device, precision, order, grids), tuned once per
+// process and then reused, so repeated calls are bitwise reproducible.
+fsic_status choose_shape(fsic_ctx *c, const std::vector<Group> &groups, int precision, Shape &sh) {
+    c->tune_ms = 0.0;
+    if (fixed_shape(c->radius, precision, sh)) return FSIC_OK;
+    std::string key = std::to_string(c->device) + ":" + std::to_string(precision) + ":" +
+                      std::to_string(c->radius);
+    for (const Group &g : groups)
+        key += ":" + std::to_string(g.n[0]) + "x" + std::to_string(g.n[1]) + "x" +
+               std::to_string(g.n[2]) + "*" + std::to_string(g.count);
+    static std::mutex mu;
+    static std::map<std::string, Shape> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto f = cache.find(key);
+        if (f != cache.end()) {
+            sh = f->second;
+            return FSIC_OK;
+        }
+    }
+    const double t0 = now_ms();
+    const std::vector<Shape> cands = shape_candidates(c->radius);
+    fsic_status st = precision == FSIC_MIXED ? time_shapes<float>(c, groups, precision, cands, sh)
+                                             : time_shapes<double>(c, groups, precision, cands, sh);
+    if (st) return st;
+    c->tune_ms = now_ms() - t0;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = sh;
+    return FSIC_OK;
+}
+
 
 // Solve -L x = scale * rho (+ boundary term) for every orbital of batch b.
 //   src: densities (square = 0) or orbitals (square = 1), field layout of b;
@@ -422,13 +571,18 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->iters.p, 0, norb * sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->rs_iter.p, 0xff, norb * sizeof(int), s));  // -1: no restart
-    HIPCHK(c, hipMemsetAsync(c->nact.p, 0, 3 * norb * sizeof(int), s));
+    HIPCHK(c, hipMemsetAsync(c->nact.p, 0, 4 * norb * sizeof(int), s));
     const double tol2 = tol * tol;
     const int chunk = 32;
     int k = 0;
     bool all_done = false;
-    // profiling: one event pair per launch, recorded on the context's stream
+    // profiling: one event pair per launch of every prof_every-th iteration,
+    // recorded on the context's stream; nact[2 norb..] counts what those
+    // launches did
     const bool prof = (c->opts.flags & FSIC_PROFILE) != 0;
+    const int prof_every = profile_period();
+    auto sampled = [&](int kk) { return prof && kk % prof_every == prof_every - 1; };
+    int *const nsamp = c->nact.p + 2 * norb;
     struct Rec { int kind, k, flag; hipEvent_t a, b; };  // kind 0 sweep, 1 update; flag: first access
     std::vector<Rec> recs;
     size_t evn = 0;
@@ -446,31 +600,33 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     };
 #define PROF_BEGIN(kind_, k_, flag_)                                   \
     hipEvent_t _ea = nullptr, _eb = nullptr;                            \
-    if (prof) {                                                         \
+    const bool _sp = sampled(k_);                                       \
+    a.nsamp = _sp ? nsamp : nullptr;                                    \
+    if (_sp) {                                                          \
         HIPCHK(c, ev_pair(_ea, _eb));                                   \
         HIPCHK(c, hipEventRecord(_ea, s));                              \
         recs.push_back(Rec{kind_, k_, flag_, _ea, _eb});                \
     }
 #define PROF_END() \
-    if (prof) HIPCHK(c, hipEventRecord(_eb, s));
+    if (_sp) HIPCHK(c, hipEventRecord(_eb, s));
     if (!mixed) {
         CGIter<double> a{};
         a.items7 = c->d_items7.p; a.nitems7 = nit7;
         a.items8 = c->d_items8.p; a.nitems8 = nit8;
         a.orb = c->d_orb.p;
         a.R = c->R.p; a.Q = c->Q.p; a.X = X;
-        a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.tot8 = b.tot8;
+        a.P = c->P0.p;
+        a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p;
+        a.tot7 = b.tot7; a.tot8 = b.tot8;
         a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
         a.rs_iter = nullptr; a.nact = c->nact.p; a.norb = norb;
         a.tol2 = tol2;
         while (k < max_iter + 1 && !all_done) {
             const int kend = std::min(k + chunk, max_iter + 1);
             for (; k < kend; ++k) {
-                a.Pold = (k & 1) ? c->P0.p : c->P1.p;
-                a.Pnew = (k & 1) ? c->P1.p : c->P0.p;
                 {
                     PROF_BEGIN(0, k, k == 0)
-                    HIPCHK(c, launch_cg_stencil<double>(c->radius, c->cf, a, k, 0, 0, 1, s));
+                    HIPCHK(c, launch_cg_stencil<double>(c->radius, c->cf, a, k, 0, 1, s));
                     PROF_END()
                 }
                 if (k < max_iter) {
@@ -494,7 +650,9 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         a.items8 = c->d_items8.p; a.nitems8 = nit8;
         a.orb = c->d_orb.p;
         a.R = c->R32.p; a.Q = c->Q32.p; a.X = c->X32.p;
-        a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.tot8 = b.tot8;
+        a.P = c->P32a.p;
+        a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p;
+        a.tot7 = b.tot7; a.tot8 = b.tot8;
         a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
         a.rs_iter = c->rs_iter.p; a.nact = c->nact.p; a.norb = norb;
         a.tol2 = tol2;
@@ -504,13 +662,10 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             const int kend = std::min(k + chunk, max_iter);
             for (; k < kend; ++k) {
                 const int j = k - kstart;
-                a.Pold = (k & 1) ? c->P32a.p : c->P32b.p;
-                a.Pnew = (k & 1) ? c->P32b.p : c->P32a.p;
                 const int cur_ru = (j == 0 && k > 0);
-                const int prev_ru = (j == 1 && k - 1 > 0);
                 {
                     PROF_BEGIN(0, k, k == 0)
-                    HIPCHK(c, launch_cg_stencil<float>(c->radius, c->cf, a, k, cur_ru, prev_ru, 1, s));
+                    HIPCHK(c, launch_cg_stencil<float>(c->radius, c->cf, a, k, cur_ru, 1, s));
                     PROF_END()
                 }
                 {
@@ -538,10 +693,10 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                        X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
         HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
     }
-    std::vector<int> it(norb), na(3 * (size_t)norb);
+    std::vector<int> it(norb), na(4 * (size_t)norb);
     std::vector<double> pt(norb), bbh(norb);
     HIPCHK(c, hipMemcpyAsync(it.data(), c->iters.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(na.data(), c->nact.p, 3 * norb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(na.data(), c->nact.p, 4 * norb * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(pt.data(), c->ptrue.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(bbh.data(), c->bb.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -555,10 +710,11 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         if (c->h_done[o] != 1) rep.converged = false;
     }
     if (prof) {
-        // algorithmic bytes: each array of each orbital that did work in a
-        // launch, read or written once (sweep: r, p_old, p, q -- the first
-        // sweep has no p_old; update: x, p, r, q, x, r -- x is not read when
-        // it restarts from zero)
+        // algorithmic bytes of the sampled launches: each array of each
+        // orbital that did work in a launch, read or written once (sweep: p,
+        // r read, q written; update: x, p, r, q read, x, r, p written).
+        // Sampled launches are never the first of a solve or of a restart of
+        // x from zero.
         const double esz = mixed ? 4.0 : 8.0;
         for (const Rec &r : recs) {
             float ms = 0.f;
@@ -568,10 +724,8 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         }
         for (int o = 0; o < norb; ++o) {
             const double Mo = (double)b.orb[o].nx * b.orb[o].ny * b.orb[o].nz;
-            const int n7 = na[o], n8 = na[norb + o];
-            const int xfirst = mixed ? (n8 > 0 ? (n8 + chunk - 1) / chunk : 0) : (n8 > 0 ? 1 : 0);
-            c->sweep_bytes += Mo * esz * (4.0 * n7 - (n7 > 0 ? 1.0 : 0.0));
-            c->update_bytes += Mo * esz * (6.0 * n8 - xfirst);
+            c->sweep_bytes += Mo * esz * 3.0 * na[2 * (size_t)norb + o];
+            c->update_bytes += Mo * esz * 7.0 * na[3 * (size_t)norb + o];
         }
     }
 #undef PROF_BEGIN
@@ -620,22 +774,12 @@ const char *fsic_status_string(fsic_status s) {
 
 const char *fsic_last_error(const fsic_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-// Stencil weights and tile shape for a radius: 32 x 16 columns per block and
-// one plane of prefetch (the 12th-order default); FSIC_STENCIL_CPT and
-// FSIC_STENCIL_DEPTH override the shape for tuning.
+// Stencil weights for a radius, with the default tile of 32 x 16 columns.
 static void set_stencil_defaults(fsic_ctx *c, int radius) {
     c->radius = radius;
     c->cf = fd_weights(radius);
-    c->cpt_fp64 = c->cpt_mixed = 2;
-    if (radius == 6) c->cf.depth = 1;
-    if (const char *e = getenv("FSIC_STENCIL_CPT")) {
-        const int v = atoi(e);
-        if (v == 2 || (radius == 6 && (v == 1 || v == 4))) c->cpt_fp64 = c->cpt_mixed = v;
-    }
-    if (const char *e = getenv("FSIC_STENCIL_DEPTH")) {
-        const int v = atoi(e);
-        if (radius == 6 && (v == 1 || (v == 2 && c->cpt_fp64 <= 2))) c->cf.depth = v;
-    }
+    c->cf.cpt = 2;
+    c->cf.depth = (radius == 6) ? 1 : 2;
 }
 
 fsic_status fsic_create(fsic_ctx **ctx, const fsic_opts *opts, void *hip_stream) {
@@ -752,8 +896,17 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         groups.push_back(g);
     }
     Batch b;
-    c->cf.cpt = (o.precision == FSIC_MIXED) ? c->cpt_mixed : c->cpt_fp64;
-    build_batch(groups, P, c->cf.cpt, b);
+    {
+        Shape sh;
+        fsic_status tst = choose_shape(c, groups, o.precision, sh);
+        if (tst) return tst;
+        c->cf.cpt = sh.cpt;
+        c->cf.depth = sh.depth;
+        c->shape_cpt = sh.cpt;
+        c->shape_depth = sh.depth;
+        c->shape_target = sh.target;
+        build_batch(groups, P, sh, b);
+    }
     // channel descriptors for the average pass
     std::vector<ChanDesc> cd(nchan);
     std::vector<int> blkchan;
@@ -900,6 +1053,10 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         st->sweep_bytes = c->sweep_bytes;
         st->update_ms = c->update_ms;
         st->update_bytes = c->update_bytes;
+        st->stencil_cpt = c->shape_cpt;
+        st->stencil_depth = c->shape_depth;
+        st->stencil_blocks = c->shape_target;
+        st->tune_ms = c->tune_ms;
     }
     c->chans = std::move(chans);
     c->batch = std::move(b);
@@ -932,7 +1089,7 @@ fsic_status fsic_op_laplacian(const int32_t *n, double h, int32_t fd_order, int3
     for (int d = 0; d < 3; ++d) { groups[0].n[d] = n[d]; groups[0].origin[d] = 0.0; }
     groups[0].h = h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
     Batch b;
-    build_batch(groups, P, 2, b);
+    build_batch(groups, P, Shape{2, 2, 4096}, b);  // fd_weights: cpt 2, depth 2
     hipStream_t s = (hipStream_t)hip_stream;
     DBuf<OrbDesc> dorb;
     DBuf<Item> dit;
@@ -958,7 +1115,7 @@ fsic_status fsic_op_laplacian_f32(const int32_t *n, double h, int32_t fd_order, 
     for (int d = 0; d < 3; ++d) { groups[0].n[d] = n[d]; groups[0].origin[d] = 0.0; }
     groups[0].h = h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
     Batch b;
-    build_batch(groups, P, 2, b);
+    build_batch(groups, P, Shape{2, 2, 4096}, b);  // fd_weights: cpt 2, depth 2
     hipStream_t s = (hipStream_t)hip_stream;
     DBuf<OrbDesc> dorb;
     DBuf<Item> dit;
@@ -1002,8 +1159,12 @@ fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lma
     for (int d = 0; d < 3; ++d) { groups[0].n[d] = grid->n[d]; groups[0].origin[d] = grid->origin[d]; }
     groups[0].h = grid->h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
     Batch b;
-    c->cf.cpt = (precision == FSIC_MIXED) ? c->cpt_mixed : c->cpt_fp64;
-    build_batch(groups, c->radius, c->cf.cpt, b);
+    Shape sh;
+    st = choose_shape(c, groups, precision, sh);
+    if (st) return st;
+    c->cf.cpt = sh.cpt;
+    c->cf.depth = sh.depth;
+    build_batch(groups, c->radius, sh, b);
     st = prepare_batch(c, b, precision);
     if (st) return st;
     SolveReport rep;
@@ -1114,6 +1275,7 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     const Batch &b = c->batch;
     hipStream_t s = c->stream;
     const int norb = (int)b.orb.size();
+    c->tune_ms = 0.0;  // the backward pass reuses the forward pass's stencil shape
     c->sweep_launches = c->update_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
     fsic_status pst = prepare_batch(c, b, o.precision);
@@ -1178,6 +1340,10 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         st->sweep_bytes = c->sweep_bytes;
         st->update_ms = c->update_ms;
         st->update_bytes = c->update_bytes;
+        st->stencil_cpt = c->shape_cpt;
+        st->stencil_depth = c->shape_depth;
+        st->stencil_blocks = c->shape_target;
+        st->tune_ms = c->tune_ms;
     }
     if (!rep.converged) return set_err(c, FSIC_ENOCONV, "an adjoint Poisson solve missed tol within max_iter");
     return FSIC_OK;

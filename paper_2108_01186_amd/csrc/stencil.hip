@@ -8,12 +8,14 @@
 // 2p + 1 z-neighbours of its cpt columns in registers; the current xy plane
 // with its p-deep cross-shaped halo is staged in double-buffered LDS, and the
 // next plane is fetched into registers while the current one is computed,
-// so one barrier per plane separates the stages.  The operand of the
-// stencil is produced on the fly by a policy (p = r + beta p_old for CG,
-// x64 + x32 for the FP64 residual), so every CG iteration is two HBM
-// passes: this sweep and one pointwise update.  Dot products accumulate in
-// FP64 into per-block partial sums that later blocks add up in a fixed
-// order, so results are bitwise reproducible.
+// so one barrier per plane separates the stages.  A policy supplies the
+// operand (p for CG, x64 + x32 for the FP64 residual), one extra value per
+// column node fetched with the plane (r for CG, b for the residual) and the
+// epilogue.  Every CG iteration is two HBM passes: this sweep, whose halo
+// carries the single operand array, and one pointwise update that also forms
+// the next search direction.  Dot products accumulate in FP64 into per-block
+// partial sums that later blocks add up in a fixed order, so results are
+// bitwise reproducible.
 #include <type_traits>
 
 #include "kernels.h"
@@ -75,7 +77,9 @@ __device__ __forceinline__ void unroll_steps(F &f, A arg) {
 
 template <typename T, int P, int CPT, int D, class Pol>
 __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
-    using Raw = typename Pol::Raw;
+    using Raw = typename Pol::Raw;  // operand load (columns and halo)
+    using Ext = typename Pol::Ext;  // per-column value at the current plane
+    using Acc = typename Pol::Acc;  // epilogue accumulators
     constexpr int TY = 8 * CPT;              // tile rows (each thread owns CPT columns)
     // LDS row stride 64 elements (>= kTX + 2P): the +-k-row neighbours are
     // then multiples of 64 elements apart and fit the ds_read2st64 offsets
@@ -164,18 +168,23 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) q[cc][j] = use(p.raw(coff[cc], pz), cval[cc] && zin);
     }
-    // prefetch ring: stage d holds the raw loads of plane z + d (+ P for the columns)
+    // prefetch ring: stage d holds the raw loads of plane z + d (+ P for the
+    // columns' operand)
     Raw sc[D][CPT], sh[D][HS];
+    Ext se[D][CPT];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const int pc = zoff(z0 + d + P), ph = zoff(z0 + d);
 #pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) sc[d][cc] = p.raw(coff[cc], pc);
+        for (int cc = 0; cc < CPT; ++cc) {
+            sc[d][cc] = p.raw(coff[cc], pc);
+            se[d][cc] = p.ext(coff[cc], ph);
+        }
 #pragma unroll
         for (int sl = 0; sl < HS; ++sl) sh[d][sl] = p.raw(hoff[sl], ph);
     }
 
-    double dot = 0.0;
+    Acc acc{};
     // one z step; U is the compile-time position in the unrolled block of NW*D
     auto step = [&](auto uc, int zb) {
         constexpr int u = decltype(uc)::value;
@@ -195,10 +204,16 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
 #pragma unroll
         for (int sl = 0; sl < HS; ++sl) S[hlds[sl]] = use(sh[d][sl], hval[sl]);
         lds_barrier();
+        Ext ecur[CPT];
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) ecur[cc] = se[d][cc];
         if (z + D < z1) {  // refill this stage with plane z + D
             const int pc = zoff(z + D + P), ph = zoff(z + D);
 #pragma unroll
-            for (int cc = 0; cc < CPT; ++cc) sc[d][cc] = p.raw(coff[cc], pc);
+            for (int cc = 0; cc < CPT; ++cc) {
+                sc[d][cc] = p.raw(coff[cc], pc);
+                se[d][cc] = p.ext(coff[cc], ph);
+            }
 #pragma unroll
             for (int sl = 0; sl < HS; ++sl) sh[d][sl] = p.raw(hoff[sl], ph);
         }
@@ -214,14 +229,11 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
                 lap += c[k] * ((xb[P + k] + xb[P - k]) + (yb[(P + k) * W] + yb[(P - k) * W]) +
                                (q[cc][(sl0 + P + k) % NW] + q[cc][(sl0 + P - k) % NW]));
             lap *= ih2;
-            if (cval[cc]) dot += p.epilogue(coff[cc], pz, q[cc][(sl0 + P) % NW], lap);
+            if (cval[cc]) p.epilogue(coff[cc], pz, q[cc][(sl0 + P) % NW], lap, ecur[cc], acc);
         }
     };
     for (int zb = z0; zb < z1; zb += NW * D) unroll_steps<NW * D>(step, zb);
-    if (p.wants_dot()) {
-        const double s2 = block_sum256(dot, sred);
-        p.finish(it, od, s2, sred);
-    }
+    p.finish(it, od, acc, sred);  // every thread (block reductions)
 }
 
 // ---------------------------------------------------------------------------
@@ -235,6 +247,8 @@ struct PolApply {  // Lu = L u
     const T *u;
     T *out;
     struct Raw { T a; };
+    struct Ext {};
+    struct Acc {};
     bool tile0;
     Rsrc ru, ro;
     __device__ bool setup(int, const OrbDesc &, double *) { return true; }
@@ -244,13 +258,12 @@ struct PolApply {  // Lu = L u
         ro = make_rsrc(out + od.off, bytes);
     }
     __device__ Raw raw(unsigned i, int zo) const { return Raw{bld<T>(ru, i, zo)}; }
+    __device__ Ext ext(unsigned, int) const { return Ext{}; }
     __device__ T combine(const Raw &r) const { return r.a; }
-    __device__ double epilogue(unsigned i, int zo, T, T lap) const {
+    __device__ void epilogue(unsigned i, int zo, T, T lap, const Ext &, Acc &) const {
         bst(ro, i, zo, lap);
-        return 0.0;
     }
-    __device__ bool wants_dot() const { return false; }
-    __device__ void finish(const Item &, const OrbDesc &, double, double *) const {}
+    __device__ void finish(const Item &, const OrbDesc &, const Acc &, double *) const {}
 };
 
 // r_j.r_j of an orbital: the CG recursion's partial sums (by iteration
@@ -263,12 +276,12 @@ __device__ __forceinline__ double rr_of(const CGIter<T> &a, const OrbDesc &od, i
 }
 
 template <typename T>
-struct PolCG {  // p_k = r_k + beta p_{k-1}; q = K p_k = -L p_k
+struct PolCG {  // q = K p_k = -L p_k; partial sums of p.q, r.q, q.q
     const Item *items;
     const OrbDesc *orb;
     CGIter<T> a;
-    int k, cur_ru, prev_ru, check;
-    double beta;
+    int k, cur_ru, check;
+    bool p_from_r;  // the recursion (re)starts here: p_k = r_k
     bool tile0;
     __device__ bool setup(int o, const OrbDesc &od, double *sbuf) {
         // other blocks of this orbital may change done[o] during this launch:
@@ -293,39 +306,44 @@ struct PolCG {  // p_k = r_k + beta p_{k-1}; q = K p_k = -L p_k
             }
             return false;
         }
-        if (k == 0 || restart) {
-            beta = 0.0;
-        } else {
-            const bool pru = prev_ru || (a.rs_iter && a.rs_iter[o] == k - 1);
-            const double rp = rr_of(a, od, k - 1, pru, sbuf);
-            beta = rr / rp;
+        p_from_r = (k == 0) || restart;
+        if (threadIdx.x == 0 && tile0) {  // one count per orbital and launch
+            a.nact[o] += 1;
+            if (a.nsamp) a.nsamp[o] += 1;
         }
-        if (threadIdx.x == 0 && tile0) a.nact[o] += 1;  // one count per orbital and launch
         return true;
     }
-    struct Raw { T r, p; };
-    Rsrc rr_, rpo, rpn, rq;
+    struct Raw { T p; };
+    typedef T Ext;
+    struct Acc { double pq, rq, qq; };
+    Rsrc rr_, rp, rq;
     __device__ void init(const OrbDesc &od) {
         const unsigned bytes = (unsigned)((long long)od.nx * od.ny * od.nz * sizeof(T));
         rr_ = make_rsrc(a.R + od.off, bytes);
-        rpo = make_rsrc(a.Pold + od.off, bytes);
-        rpn = make_rsrc(a.Pnew + od.off, bytes);
+        rp = make_rsrc((p_from_r ? a.R : a.P) + od.off, bytes);
         rq = make_rsrc(a.Q + od.off, bytes);
     }
-    __device__ Raw raw(unsigned i, int zo) const {
-        // at k == 0 beta is 0 and p_old aliases r (finite), so no branch
-        return Raw{bld<T>(rr_, i, zo), bld<T>(rpo, i, zo)};
-    }
-    __device__ T combine(const Raw &v) const { return v.r + (T)beta * v.p; }
-    __device__ double epilogue(unsigned i, int zo, T c, T lap) const {
+    __device__ Raw raw(unsigned i, int zo) const { return Raw{bld<T>(rp, i, zo)}; }
+    __device__ Ext ext(unsigned i, int zo) const { return bld<T>(rr_, i, zo); }
+    __device__ T combine(const Raw &v) const { return v.p; }
+    __device__ void epilogue(unsigned i, int zo, T pv, T lap, const Ext &rv, Acc &s) const {
         const T qv = -lap;
-        bst(rpn, i, zo, c);
         bst(rq, i, zo, qv);
-        return (double)c * (double)qv;
+        const double qd = (double)qv;
+        s.pq += (double)pv * qd;
+        s.rq += (double)rv * qd;
+        s.qq += qd * qd;
     }
-    __device__ bool wants_dot() const { return true; }
-    __device__ void finish(const Item &it, const OrbDesc &od, double s, double *) const {
-        if (threadIdx.x == 0) a.part7[od.base7 + it.tile] = s;
+    __device__ void finish(const Item &it, const OrbDesc &od, const Acc &s, double *sred) const {
+        const double pq = block_sum256(s.pq, sred);
+        const double rq = block_sum256(s.rq, sred);
+        const double qq = block_sum256(s.qq, sred);
+        if (threadIdx.x == 0) {
+            const size_t j = (size_t)od.base7 + it.tile;
+            a.part7[j] = pq;
+            a.part7[(size_t)a.tot7 + j] = rq;
+            a.part7[2 * (size_t)a.tot7 + j] = qq;
+        }
     }
 };
 
@@ -341,6 +359,8 @@ struct PolRes {  // res = b + L x, x = x64 (+ x32)
     float *R32;
     double *partRU;
     struct Raw { double a; float b; };
+    typedef double Ext;
+    typedef double Acc;
     bool tile0;
     Rsrc rx, rx32, rb, rxn, rr32;
     __device__ bool setup(int o, const OrbDesc &, double *) { return done == nullptr || done[o] != 1; }
@@ -356,16 +376,17 @@ struct PolRes {  // res = b + L x, x = x64 (+ x32)
         if constexpr (HAS32) return Raw{bld<double>(rx, i, zo), bld<float>(rx32, i, zo)};
         return Raw{bld<double>(rx, i, zo), 0.0f};
     }
+    __device__ Ext ext(unsigned i, int zo) const { return bld<double>(rb, i, zo); }
     __device__ double combine(const Raw &v) const { return v.a + (double)v.b; }
-    __device__ double epilogue(unsigned i, int zo, double c, double lap) const {
-        const double res = bld<double>(rb, i, zo) + lap;
+    __device__ void epilogue(unsigned i, int zo, double c, double lap, const Ext &b, Acc &s) const {
+        const double res = b + lap;
         if (X64new) bst(rxn, i, zo, c);
         if (R32) bst(rr32, i, zo, (float)res);
-        return res * res;
+        s += res * res;
     }
-    __device__ bool wants_dot() const { return true; }
-    __device__ void finish(const Item &it, const OrbDesc &od, double s, double *) const {
-        if (threadIdx.x == 0) partRU[od.base7 + it.tile] = s;
+    __device__ void finish(const Item &it, const OrbDesc &od, const Acc &s, double *sred) const {
+        const double t = block_sum256(s, sred);
+        if (threadIdx.x == 0) partRU[od.base7 + it.tile] = t;
     }
 };
 
@@ -377,10 +398,12 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { typedef float4 V; static constexpr int n = 4; };
 template <> struct Vec16<double> { typedef double2 V; static constexpr int n = 2; };
 
+// x += alpha p; r -= alpha q; p = r + beta p (one node)
 template <typename T>
-__device__ __forceinline__ double upd_elem(T &x, T &r, T pv, T qv, T al, int x_first) {
-    x = x_first ? al * pv : x + al * pv;
+__device__ __forceinline__ double upd_elem(T &x, T &r, T &p, T qv, T al, T be, int x_first) {
+    x = x_first ? al * p : x + al * p;
     r = r - al * qv;
+    p = r + be * p;
     return (double)r * (double)r;
 }
 
@@ -396,8 +419,16 @@ __global__ __launch_bounds__(256) void k_cg_update(CGIter<T> a, int k, int cur_r
     const bool restart = a.rs_iter && a.rs_iter[it.orb] == k;
     const double rr = rr_of(a, od, k, cur_ru || restart, sred);
     const double pq = sum_partials(a.part7 + od.base7, od.nt7, sred);
+    const double rq = sum_partials(a.part7 + (size_t)a.tot7 + od.base7, od.nt7, sred);
+    const double qq = sum_partials(a.part7 + 2 * (size_t)a.tot7 + od.base7, od.nt7, sred);
     const double alpha = rr / pq;
-    const T al = (T)alpha;
+    // |r_{k+1}|^2 = |r_k|^2 - 2 alpha r_k.q_k + alpha^2 |q_k|^2, so the next
+    // direction is formed here; the direct r.r of this pass (below) decides
+    // alpha and convergence of the next iteration
+    const double rn = rr - 2.0 * alpha * rq + alpha * alpha * qq;
+    const double beta = rn > 0.0 ? rn / rr : 0.0;
+    const T al = (T)alpha, be = (T)beta;
+    const T *Pin = ((k == 0) || restart) ? a.R : a.P;  // p_k = r_k at a (re)start
     const long long M = (long long)od.nx * od.ny * od.nz;
     const long long base = (long long)it.tile * kPW;
     double acc = 0.0;
@@ -408,16 +439,19 @@ __global__ __launch_bounds__(256) void k_cg_update(CGIter<T> a, int k, int cur_r
             const long long i = base + (long long)(e * 256 + threadIdx.x) * VN;
             if (i < M) {
                 const long long g = od.off + i;
-                V pv = *reinterpret_cast<const V *>(a.Pnew + g);
+                V pv = *reinterpret_cast<const V *>(Pin + g);
                 V qv = *reinterpret_cast<const V *>(a.Q + g);
                 V rv = *reinterpret_cast<const V *>(a.R + g);
                 V xv = x_first ? V{} : *reinterpret_cast<const V *>(a.X + g);
                 T *px = reinterpret_cast<T *>(&xv), *pr = reinterpret_cast<T *>(&rv);
-                const T *pp = reinterpret_cast<const T *>(&pv), *pqv = reinterpret_cast<const T *>(&qv);
+                T *pp = reinterpret_cast<T *>(&pv);
+                const T *pqv = reinterpret_cast<const T *>(&qv);
 #pragma unroll
-                for (int j = 0; j < VN; ++j) acc += upd_elem(px[j], pr[j], pp[j], pqv[j], al, x_first);
+                for (int j = 0; j < VN; ++j)
+                    acc += upd_elem(px[j], pr[j], pp[j], pqv[j], al, be, x_first);
                 *reinterpret_cast<V *>(a.X + g) = xv;
                 *reinterpret_cast<V *>(a.R + g) = rv;
+                *reinterpret_cast<V *>(a.P + g) = pv;
             }
         }
     } else {
@@ -428,16 +462,21 @@ __global__ __launch_bounds__(256) void k_cg_update(CGIter<T> a, int k, int cur_r
                 const long long g = od.off + i;
                 T xv = x_first ? T(0) : a.X[g];
                 T rv = a.R[g];
-                acc += upd_elem(xv, rv, a.Pnew[g], a.Q[g], al, x_first);
+                T pv = Pin[g];
+                acc += upd_elem(xv, rv, pv, a.Q[g], al, be, x_first);
                 a.X[g] = xv;
                 a.R[g] = rv;
+                a.P[g] = pv;
             }
         }
     }
     const double s = block_sum256(acc, sred);
     if (threadIdx.x == 0) {
         a.part8[(size_t)((k + 1) & 1) * a.tot8 + od.base8 + it.tile] = s;
-        if (it.tile == 0) a.nact[a.norb + it.orb] += 1;
+        if (it.tile == 0) {
+            a.nact[a.norb + it.orb] += 1;
+            if (a.nsamp) a.nsamp[a.norb + it.orb] += 1;
+        }
     }
 }
 
@@ -526,10 +565,9 @@ hipError_t launch_apply(int radius, const Coeffs &c, const Item *items, int nite
 
 template <typename T>
 hipError_t launch_cg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, int k,
-                             int cur_from_ru, int prev_from_ru, int check, hipStream_t s) {
+                             int cur_from_ru, int check, hipStream_t s) {
     if (a.nitems7 <= 0) return hipSuccess;
-    PolCG<T> pol{a.items7, a.orb, a, k, cur_from_ru, prev_from_ru, check, 0.0, false};
-    if (k == 0) pol.a.Pold = a.R;  // beta = 0: any finite p_old will do
+    PolCG<T> pol{a.items7, a.orb, a, k, cur_from_ru, check, false, false};
 #define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolCG<T>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
     FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
@@ -594,9 +632,9 @@ template hipError_t launch_apply<double>(int, const Coeffs &, const Item *, int,
 template hipError_t launch_apply<float>(int, const Coeffs &, const Item *, int, const OrbDesc *,
                                         const float *, float *, hipStream_t);
 template hipError_t launch_cg_stencil<double>(int, const Coeffs &, const CGIter<double> &, int, int,
-                                              int, int, hipStream_t);
+                                              int, hipStream_t);
 template hipError_t launch_cg_stencil<float>(int, const Coeffs &, const CGIter<float> &, int, int,
-                                             int, int, hipStream_t);
+                                             int, hipStream_t);
 template hipError_t launch_cg_update<double>(const CGIter<double> &, int, int, int, hipStream_t);
 template hipError_t launch_cg_update<float>(const CGIter<float> &, int, int, int, hipStream_t);
 

@@ -61,7 +61,9 @@ class fsic_stats(ctypes.Structure):
                 ("ms_phase", ctypes.c_double * 8),
                 ("sweep_launches", ctypes.c_int32), ("update_launches", ctypes.c_int32),
                 ("sweep_ms", ctypes.c_double), ("sweep_bytes", ctypes.c_double),
-                ("update_ms", ctypes.c_double), ("update_bytes", ctypes.c_double)]
+                ("update_ms", ctypes.c_double), ("update_bytes", ctypes.c_double),
+                ("stencil_cpt", ctypes.c_int32), ("stencil_depth", ctypes.c_int32),
+                ("stencil_blocks", ctypes.c_int64), ("tune_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms_phase"}
