@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
 
 def parse():
@@ -30,7 +31,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mol96")
-    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--tol", type=float, default=1e-11,
+                    help="relative FP64 residual of every solve (1e-11 keeps E_SIC within 1e-8 Ha "
+                         "on every workload here)")
+    ap.add_argument("--solver", default="pcg", choices=["pcg", "cg"],
+                    help="pcg: CG with the sine-transform preconditioner; cg: plain CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
@@ -42,8 +47,9 @@ def parse():
 
 def run_steps(F, torch, ctx, dicts, noccs, steps):
     """Timed region: `steps` full passes (forward + backward) over all systems."""
-    agg = dict(sweep_ms=0.0, sweep_bytes=0.0, sweep_launches=0, update_ms=0.0, update_bytes=0.0,
-               update_launches=0, iters=0, solves=0, refinements=0, max_relres=0.0)
+    keys = ("sweep_ms", "sweep_bytes", "sweep_launches", "update_ms", "update_bytes",
+            "update_launches", "precond_ms", "precond_bytes", "precond_flops", "precond_launches")
+    agg = dict({k: 0.0 for k in keys}, iters=0, solves=0, refinements=0, max_relres=0.0)
     e = g = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -51,8 +57,7 @@ def run_steps(F, torch, ctx, dicts, noccs, steps):
         e, U, X, st = ctx.forward(dicts)
         agg["shape"] = {"tile": f"32x{8 * st['stencil_cpt']}", "prefetch_planes": st["stencil_depth"],
                         "block_target": st["stencil_blocks"]}
-        for k in ("sweep_ms", "sweep_bytes", "sweep_launches", "update_ms", "update_bytes",
-                  "update_launches"):
+        for k in keys:
             agg[k] += st[k]
         agg["iters"] += st["total_iters"]
         agg["solves"] += st["nsolves"]
@@ -60,8 +65,7 @@ def run_steps(F, torch, ctx, dicts, noccs, steps):
         agg["max_relres"] = max(agg["max_relres"], st["max_relres"])
         g = ctx.backward(noccs)
         st = ctx.stats
-        for k in ("sweep_ms", "sweep_bytes", "sweep_launches", "update_ms", "update_bytes",
-                  "update_launches"):
+        for k in keys:
             agg[k] += st[k]
         agg["iters"] += st["total_iters"]
         agg["solves"] += st["nsolves"]
@@ -109,20 +113,20 @@ def cpu_baseline(sysobj, tol, budget_s):
 
 
 def kernel_source_hash():
-    """Hash of the stencil kernel sources (invalidates stored HBM traffic)."""
+    """Hash of the solver kernel sources (invalidates stored HBM traffic)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("stencil.hip", "common.h"):
+    for f in ("stencil.hip", "dst.hip", "common.h"):
         with open(os.path.join(ROOT, "paper_2108_01186_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload):
-    """HBM bytes per launch of the FP32 CG sweep from the committed counter
+def stored_traffic(workload, kernel, solver):
+    """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy); None when
     the summary is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"zmarch_f32_cg_{workload}_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{solver}_f32_{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -151,8 +155,58 @@ def copy_calibration(torch, mib):
     print(f"[bench] copy calibration: 3 x {mib} MiB device copy", file=sys.stderr, flush=True)
 
 
+def kernel_rates(agg):
+    """Per-kernel averages of the sampled launches (HIP events in the timed
+    region): time per launch, algorithmic GB/s and, for the preconditioner,
+    matrix-core TFLOP/s."""
+    out = {}
+    for k in ("sweep", "update", "precond"):
+        n, ms = agg[f"{k}_launches"], agg[f"{k}_ms"]
+        if n <= 0 or ms <= 0:
+            continue
+        d = {"launches": int(n), "avg_launch_us": ms / n * 1e3,
+             "gbs": agg[f"{k}_bytes"] / (ms * 1e-3) / 1e9,
+             "algorithmic_bytes_per_launch": agg[f"{k}_bytes"] / n}
+        if k == "precond":
+            d["tflops"] = agg["precond_flops"] / (ms * 1e-3) / 1e12
+        out[k] = d
+    return out
+
+
+KERNEL_NAMES = {
+    "sweep": "k_zmarch (CG stencil sweep: p, q = -L p, p.q)",
+    "update": "k_pcg_update / k_cg_update (x += alpha p, r -= alpha q)",
+    "precond": "k_dst_pass x5 (sine-transform preconditioner, FP32 MFMA)",
+}
+
+
+def roofline(args, agg):
+    """Roofline line for the kernel with the largest sampled time; the
+    preconditioner is bound by HBM or by FP32 matrix-core throughput,
+    whichever fraction of peak is larger."""
+    rates = kernel_rates(agg)
+    dom = max(rates, key=lambda k: agg[f"{k}_ms"])
+    r = rates[dom]
+    out = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": r["gbs"], "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": r["gbs"] / HBM_PEAK_GBS}
+    if dom == "precond":
+        ffrac = r["tflops"] / FP32_MFMA_PEAK_TFLOPS
+        if ffrac > out["frac"]:
+            out.update(bound="mfma", achieved=r["tflops"], peak=FP32_MFMA_PEAK_TFLOPS,
+                       unit="TFLOP/s", frac=ffrac)
+    out["traffic"] = stored_traffic(args.workload, dom, args.solver)
+    out["algorithmic_bytes_per_launch"] = r["algorithmic_bytes_per_launch"]
+    out["avg_launch_us"] = r["avg_launch_us"]
+    out["launches"] = r["launches"]
+    out["kernels"] = rates
+    out["stencil_shape"] = agg.get("shape")
+    return out
+
+
 def workload_config(args, systems, solves_per_step):
-    common = {"fd_order": 12, "lmax": 6, "tol": args.tol, "solves_per_step": solves_per_step}
+    common = {"fd_order": 12, "lmax": 6, "tol": args.tol, "solves_per_step": solves_per_step,
+              "solver": {"pcg": "CG preconditioned by type-I sine transforms",
+                         "cg": "plain CG"}[args.solver]}
     if len(systems) == 1:
         s = systems[0]
         nocc = list(s.nocc)
@@ -195,7 +249,7 @@ def main():
     results = {}
     legs = ["mixed"] + ([] if args.no_fp64 else ["fp64"])
     for leg in legs:
-        ctx = F.Context(precision=leg, tol=args.tol, flags=flags)
+        ctx = F.Context(precision=leg, tol=args.tol, flags=flags, solver=args.solver)
         for _ in range(args.warmup):
             ctx.forward(dicts)
             ctx.backward(noccs)
@@ -210,7 +264,7 @@ def main():
     steps = args.steps
     solves_per_step = mx["agg"]["solves"] / steps
     value = mx["agg"]["solves"] / mx["dt"]
-    sweep_gbs = mx["agg"]["sweep_bytes"] / (mx["agg"]["sweep_ms"] * 1e-3) / 1e9
+    roof = roofline(args, mx["agg"])
     out = {
         "metric": "orbital Poisson solves/sec + E_SIC&FOD-force time at 1e-8 Ha, mixed vs FP64",
         "value": value,
@@ -228,21 +282,7 @@ def main():
         "e_sic_force_ms_mixed": mx["dt"] / steps * 1e3,
         "mean_cg_iters_mixed": mx["agg"]["iters"] / max(1, mx["agg"]["solves"]),
         "max_relres_mixed": mx["agg"]["max_relres"],
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_zmarch<float,6,cpt,depth,PolCG<float>> (FP32 CG stencil sweep; shape below)",
-            "achieved": sweep_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": sweep_gbs / HBM_PEAK_GBS,
-            "traffic": stored_traffic(args.workload),
-            "algorithmic_bytes_per_launch": mx["agg"]["sweep_bytes"] / max(1, mx["agg"]["sweep_launches"]),
-            "launches": mx["agg"]["sweep_launches"],
-            "avg_launch_us": mx["agg"]["sweep_ms"] / max(1, mx["agg"]["sweep_launches"]) * 1e3,
-            "update_kernel_gbs": mx["agg"]["update_bytes"] / (mx["agg"]["update_ms"] * 1e-3) / 1e9
-            if mx["agg"]["update_ms"] > 0 else None,
-            "stencil_shape": mx["agg"].get("shape"),
-        },
+        "roofline": roof,
     }
     if "fp64" in results:
         fp = results["fp64"]
@@ -252,7 +292,7 @@ def main():
         out["mean_cg_iters_fp64"] = fp["agg"]["iters"] / max(1, fp["agg"]["solves"])
         out["dE_mixed_vs_fp64"] = float(np.abs(mx["e"] - fp["e"]).max())
         out["dF_max_mixed_vs_fp64"] = float(np.abs(mx["g"] - fp["g"]).max())
-        out["fp64_sweep_gbs"] = fp["agg"]["sweep_bytes"] / (fp["agg"]["sweep_ms"] * 1e-3) / 1e9
+        out["fp64_kernels"] = kernel_rates(fp["agg"])
     if args.copy_calibration > 0:
         copy_calibration(torch, args.copy_calibration)
     if not args.no_cpu_baseline:

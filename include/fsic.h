@@ -76,8 +76,15 @@ typedef enum {
  * energies stay FP64. */
 enum { FSIC_FP64 = 0, FSIC_MIXED = 1 };
 
-/* Poisson solver (c): conjugate gradients on -L v = 4 pi rho + boundary term. */
-enum { FSIC_CG = 0 };
+/* Poisson solver (c) for -L v = 4 pi rho + boundary term:
+ *   FSIC_CG   plain conjugate gradients;
+ *   FSIC_PCG  conjugate gradients preconditioned by the inverse of the same
+ *             stencil with odd-reflection faces, applied with type-I sine
+ *             transforms along each axis (a few iterations instead of
+ *             hundreds); a batch with a grid axis above 256 nodes is solved
+ *             with plain CG instead.  The default.
+ * Both stop on the same FP64 relative residual. */
+enum { FSIC_CG = 0, FSIC_PCG = 1 };
 
 /* option flags */
 #define FSIC_WANT_VSIC       1u  /* write V_SIC into fsic_system.vsic[] */
@@ -94,7 +101,7 @@ typedef struct {
 typedef struct {
     int32_t fd_order;   /* even, 2..12: order of the central second difference; radius p = fd_order/2 */
     int32_t lmax;       /* multipole order of the Dirichlet values, 0..8 */
-    int32_t solver;     /* FSIC_CG */
+    int32_t solver;     /* FSIC_CG | FSIC_PCG */
     int32_t precision;  /* FSIC_FP64 | FSIC_MIXED */
     double  tol;        /* relative FP64 residual ||b + L v|| / ||b|| to reach, (0, 1) */
     int32_t max_iter;   /* CG iteration cap per solve, >= 1 */
@@ -138,6 +145,11 @@ typedef struct {
     int32_t update_launches;  /* sampled pointwise updates (x += alpha p, r -= alpha q) */
     double  sweep_ms, sweep_bytes;
     double  update_ms, update_bytes;
+    /* FSIC_PCG with FSIC_PROFILE: iterations are sampled every other one, and
+     * each sampled preconditioner application (five transform passes) is
+     * timed as one unit with its algorithmic bytes and flops */
+    int32_t precond_launches;
+    double  precond_ms, precond_bytes, precond_flops;
     /* stencil shape of the CG sweeps: tiles of 32 x 8*stencil_cpt columns,
      * stencil_depth planes fetched ahead, z-chunks halved until a launch has
      * stencil_blocks blocks.  The first call for a given (device, precision,
@@ -151,7 +163,7 @@ typedef struct {
     double  tune_ms;
 } fsic_stats;
 
-/* Fills *o with the defaults: fd_order 12, lmax 6, CG, FP64, tol 1e-10,
+/* Fills *o with the defaults: fd_order 12, lmax 6, FSIC_PCG, FP64, tol 1e-10,
  * max_iter 20000, vsic_scale 1, rho_floor 1e-30, s_eig_floor 1e-12,
  * flags FSIC_WANT_VSIC. */
 fsic_status fsic_default_opts(fsic_opts *o);
@@ -213,12 +225,12 @@ fsic_status fsic_op_xc(int64_t count, const double *rho, double rho_floor, doubl
 
 /* Hartree potentials v[f] of count densities rho[f] on one grid: -L v =
  * 4 pi rho with multipole Dirichlet values of order lmax about the box
- * centre (Sec. II.A), conjugate gradients to tol.  iters, relres: HOST
- * [count] or NULL.  precision: FSIC_FP64 or FSIC_MIXED. */
+ * centre (Sec. II.A), solved to tol.  iters, relres: HOST [count] or NULL.
+ * precision: FSIC_FP64 or FSIC_MIXED; solver: FSIC_CG or FSIC_PCG. */
 fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lmax,
                             int32_t count, const double *rho, double *v, double tol,
-                            int32_t max_iter, int32_t precision, int32_t *iters,
-                            double *relres, void *hip_stream);
+                            int32_t max_iter, int32_t precision, int32_t solver,
+                            int32_t *iters, double *relres, void *hip_stream);
 
 /* Inverse square root of count symmetric positive definite N x N matrices
  * (row-major, N <= 128) by parallel cyclic Jacobi on the device: Z =

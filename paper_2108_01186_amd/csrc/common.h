@@ -38,12 +38,21 @@ struct OrbDesc {
     double origin[3];
     double centre[3];
     int chan;                           // spin channel (for the moment tables)
+    int nt9, base9;                     // spectral-preconditioner partial-sum slots (x-pass panels)
+    int dst_s[3];                       // sine-matrix offsets (x, y, z) in the spectral table
+    int dst_g[3];                       // eigenvalue-symbol offsets (x, y, z) in the spectral table
     int pad;
 };
+
 
 // Work item of a block: orbital and tile index; orb < 0 means idle block.
 struct Item {
     int orb, tile;
+};
+// Work lists of the three spectral-preconditioner passes (see dst.hip).
+struct DstItems {
+    const Item *x, *y, *z;
+    int nx, ny, nz;
 };
 
 struct Coeffs {

@@ -1,0 +1,234 @@
+// Spectral preconditioner of the per-orbital Poisson problems.
+//
+// The star Laplacian with zero values outside the box (Sec. II.A, the
+// operator the CG solves with) differs from its odd reflection at the faces
+// only in the few rows whose taps reach past the first ghost.  The
+// reflected operator is diagonalised by the type-I discrete sine transform
+// along each axis, S_n[m][k] = sin(pi (m+1)(k+1) / (n+1)), with eigenvalues
+//   lambda(j, k, l) = (s_x(j) + s_y(k) + s_z(l)) / h^2,
+//   s_n(j) = -(c_0 + 2 sum_m c_m cos(m theta_j)), theta_j = pi (j+1) / (n+1),
+// so M^{-1} r = (prod_d 2 / (n_d + 1)) S_x S_y S_z diag(1/lambda) S_z S_y S_x r
+// is an SPD preconditioner that leaves only the face corrections for CG.
+//
+// Each application is five batched passes, one per axis transform (x, y,
+// then z with the eigenvalue scaling between its forward and inverse
+// transforms, then y, x).  A pass multiplies n x 32 column panels of one
+// orbital by the n x n sine matrix on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32): the panel is staged in LDS (transposed for the x
+// axis so every global access is along x), the sine matrix comes from a
+// small L2-resident table.  Passes work in place on a float work array; the
+// first reads the CG residual (float or double) and the last writes the
+// preconditioned residual z and the partial sums of r.z.
+#include "kernels.h"
+
+namespace fsic {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kPC = 32;      // panel columns per block
+constexpr int kLW = kPC + 1;  // LDS row stride (odd: conflict-free column access)
+
+__device__ __forceinline__ int axis_n(const OrbDesc &od, int ax) {
+    return ax == 0 ? od.nx : (ax == 1 ? od.ny : od.nz);
+}
+
+}  // namespace
+
+// One pass along axis AX of the orbitals in `items`.
+//   MODE 0: out = S in;  MODE 1 (z axis only): out = S W S in, W the scaled
+//   inverse eigenvalues.  TIN is the type of `in` (the CG residual in the
+//   first pass), out is always float; RZ (last pass): partial sums of r.z
+//   with r = rres (type TR) into rz[base9 + block index of the orbital].
+//   Orbitals with done != 0 are skipped.
+//   cnt (first pass, may be null): per orbital, applications that did work.
+template <int AX, int MODE, typename TIN, typename TR, bool RZ>
+__global__ __launch_bounds__(256) void k_dst_pass(const Item *items, const OrbDesc *orb,
+                                                  const int *done, const float *tab, const TIN *in,
+                                                  float *out, const TR *rres, double *rz, int *cnt) {
+    __shared__ float sx[256 * kLW];
+    __shared__ double sred[4];
+    const Item it = items[blockIdx.x];
+    if (it.orb < 0) return;
+    if (done[it.orb]) return;
+    if (cnt && it.tile == 0 && threadIdx.x == 0) cnt[it.orb] += 1;
+    const OrbDesc od = orb[it.orb];
+    const int n = axis_n(od, AX);
+    const int np = (n + 15) & ~15;
+    const long long plane = (long long)od.nx * od.ny;
+    const float *S = tab + od.dst_s[AX];  // np x np, zero beyond n
+    const int t = threadIdx.x;
+
+    // panel: columns c0 .. c0 + 31 of the (n x ncol) matrix view of the field
+    //   x axis: column c = row index y + ny z, element k at c nx + k
+    //   y axis: column = x in plane zc, element k at zc plane + k nx + x
+    //   z axis: column = in-plane index q, element k at k plane + q
+    long long cbase = 0;  // element offset of column c0
+    long long kstr = 1;   // element stride along k (y, z axes)
+    int ncol = 0, c0 = 0;
+    if (AX == 0) {
+        ncol = od.ny * od.nz;
+        c0 = it.tile * kPC;
+    } else if (AX == 1) {
+        const int xt = (od.nx + kPC - 1) / kPC;
+        const int zc = it.tile / xt;
+        c0 = (it.tile - zc * xt) * kPC;
+        ncol = od.nx;
+        cbase = (long long)zc * plane + c0;
+        kstr = od.nx;
+    } else {
+        c0 = it.tile * kPC;
+        ncol = (int)plane;
+        cbase = c0;
+        kstr = plane;
+    }
+    const int cval = min(kPC, ncol - c0);  // valid columns in this panel
+    const TIN *src = in + od.off;
+
+    // ---- stage the panel in LDS: sx[k * kLW + c], zero-padded to np rows
+    if (AX == 0) {
+        // rows of nx contiguous values: 64 threads along k, 4 rows at a time
+        const int kk = t & 63, cc = t >> 6;
+        for (int c = cc; c < kPC; c += 4) {
+            const bool cv = c < cval;
+            const TIN *row = src + (long long)(c0 + c) * od.nx;
+            for (int k = kk; k < np; k += 64)
+                sx[k * kLW + c] = (cv && k < n) ? (float)row[k] : 0.f;
+        }
+    } else {
+        const int cc = t & 31, kk = t >> 5;
+        const bool cv = cc < cval;
+        for (int k = kk; k < np; k += 8)
+            sx[k * kLW + cc] = (cv && k < n) ? (float)src[cbase + (long long)k * kstr + cc] : 0.f;
+    }
+    __syncthreads();
+
+    // ---- out panel = S (np x np) . panel (np x 32) on the matrix cores
+    // wave w: column tile w & 1, row tiles (w >> 1) + 2 i
+    const int lane = t & 63, w = t >> 6;
+    const int ct = w & 1;
+    const int nrt = np >> 4;
+    const int r0 = w >> 1;
+    constexpr int MT = 8;  // up to 8 row tiles per wave (np <= 256)
+    flt4 acc[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
+    const int lr = lane & 15, lk = lane >> 4;
+    auto gemm = [&]() {
+        for (int k0 = 0; k0 < np; k0 += 4) {
+            const float b = sx[(k0 + lk) * kLW + ct * 16 + lr];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const int rt = r0 + 2 * i;
+                if (rt < nrt) {
+                    const float a = S[(long long)(rt * 16 + lr) * np + k0 + lk];
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i], 0, 0, 0);
+                }
+            }
+        }
+    };
+    gemm();
+    if (MODE == 1) {
+        // scale by norm / lambda(jx, jy, l) and transform again along z
+        const float *gx = tab + od.dst_g[0], *gy = tab + od.dst_g[1], *gz = tab + od.dst_g[2];
+        const float norm = 8.f / ((float)(od.nx + 1) * (float)(od.ny + 1) * (float)(od.nz + 1));
+        const float ih2 = (float)od.inv_h2;
+        const int c = ct * 16 + lr;
+        const int q = c0 + c;  // in-plane spectral index (jx, jy)
+        const int jy = q / od.nx, jx = q - jy * od.nx;
+        const float gxy = (c < cval) ? gx[jx] + gy[jy] : 1.f;
+        __syncthreads();  // every wave is done reading the panel
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            const int rt = r0 + 2 * i;
+            if (rt < nrt) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int m = rt * 16 + 4 * lk + j;
+                    const float lam = (m < n) ? (gxy + gz[m]) * ih2 : 1.f;
+                    sx[m * kLW + c] = (m < n && c < cval) ? acc[i][j] * (norm / lam) : 0.f;
+                }
+                acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        __syncthreads();
+        gemm();
+    }
+
+    // ---- write back (x axis: through LDS so rows go out along x)
+    float *dst = out + od.off;
+    double part = 0.0;
+    if (AX == 0) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            const int rt = r0 + 2 * i;
+            if (rt < nrt) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sx[(rt * 16 + 4 * lk + j) * kLW + ct * 16 + lr] = acc[i][j];
+            }
+        }
+        __syncthreads();
+        const int kk = t & 63, cc = t >> 6;
+        for (int c = cc; c < cval; c += 4) {
+            const long long row = (long long)(c0 + c) * od.nx;
+            for (int k = kk; k < n; k += 64) {
+                const float v = sx[k * kLW + c];
+                dst[row + k] = v;
+                if (RZ) part += (double)rres[od.off + row + k] * (double)v;
+            }
+        }
+    } else {
+        const int c = ct * 16 + lr;
+        if (c < cval) {
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const int rt = r0 + 2 * i;
+                if (rt < nrt) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int m = rt * 16 + 4 * lk + j;
+                        if (m < n) dst[cbase + (long long)m * kstr + c] = acc[i][j];
+                    }
+                }
+            }
+        }
+    }
+    if (RZ) {
+        const double s = block_sum256(part, sred);
+        if (t == 0) rz[od.base9 + it.tile] = s;
+    }
+}
+
+// z = M^{-1} r for the orbitals of the batch, with r.z partial sums.
+template <typename T>
+hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int *done,
+                              const float *tab, const T *r, float *work, float *z, double *rz,
+                              int *cnt, hipStream_t s) {
+    if (di.nx <= 0) return hipSuccess;
+    const float *wk = work;
+    const T *nr = nullptr;
+    double *nd = nullptr;
+    int *nc = nullptr;
+    hipLaunchKernelGGL((k_dst_pass<0, 0, T, T, false>), dim3(di.nx), dim3(256), 0, s, di.x, orb,
+                       done, tab, r, work, nr, nd, cnt);
+    hipLaunchKernelGGL((k_dst_pass<1, 0, float, T, false>), dim3(di.ny), dim3(256), 0, s, di.y,
+                       orb, done, tab, wk, work, nr, nd, nc);
+    hipLaunchKernelGGL((k_dst_pass<2, 1, float, T, false>), dim3(di.nz), dim3(256), 0, s, di.z,
+                       orb, done, tab, wk, work, nr, nd, nc);
+    hipLaunchKernelGGL((k_dst_pass<1, 0, float, T, false>), dim3(di.ny), dim3(256), 0, s, di.y,
+                       orb, done, tab, wk, work, nr, nd, nc);
+    hipLaunchKernelGGL((k_dst_pass<0, 0, float, T, true>), dim3(di.nx), dim3(256), 0, s, di.x,
+                       orb, done, tab, wk, z, r, rz, nc);
+    return hipGetLastError();
+}
+
+template hipError_t launch_dst_precond<float>(const DstItems &, const OrbDesc *, const int *,
+                                              const float *, const float *, float *, float *,
+                                              double *, int *, hipStream_t);
+template hipError_t launch_dst_precond<double>(const DstItems &, const OrbDesc *, const int *,
+                                               const float *, const double *, float *, float *,
+                                               double *, int *, hipStream_t);
+
+}  // namespace fsic

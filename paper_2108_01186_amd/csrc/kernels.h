@@ -24,6 +24,11 @@ struct CGIter {
     const OrbDesc *orb;
     T *R;               // residual
     T *P;               // search direction: p_k before the update of iteration k, p_{k+1} after
+                        // (preconditioned CG: p_k written by the sweep of iteration k)
+    T *Pold;            // preconditioned CG: p_{k-1}
+    float *Z;           // preconditioned CG: z_k = M^{-1} r_k
+    double *partRZ;     // preconditioned CG: [2*tot9] r.z partial sums, by iteration parity
+    int tot9;
     T *Q;               // K p
     T *X;               // solution (FP64 path) or FP32 correction (mixed path)
     double *part7;      // [3*tot7] p.q, r.q and q.q partial sums of the sweep (three blocks of tot7)
@@ -58,6 +63,19 @@ template <typename T>
 hipError_t launch_cg_update(const CGIter<T> &a, int k, int cur_from_ru, int x_first,
                             hipStream_t s);
 
+// Preconditioned CG sweep: p_k = z_k + beta p_{k-1} (beta = r_k.z_k /
+// r_{k-1}.z_{k-1}; 0 when k == 0 or restart), q = -L p_k, p.q partials.
+//   cur_from_ru: r_k.r_k is in partRU; pause: a converged FP32 recursion
+//   waits for the FP64 check (done = 2) instead of finishing.
+template <typename T>
+hipError_t launch_pcg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, int k,
+                              int cur_from_ru, int restart, int pause, hipStream_t s);
+
+// Preconditioned CG update: alpha = r_k.z_k / p.q; x += alpha p; r -= alpha q;
+// r.r partials.  x_first: x is not read (x = alpha p).
+template <typename T>
+hipError_t launch_pcg_update(const CGIter<T> &a, int k, int x_first, hipStream_t s);
+
 // FP64 residual of x64 (+ x32): res = b + L (x64 + x32); writes x64new =
 // x64 + x32, r32 = (float) res (if r32 != null), res.res partials.
 hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7, int nitems7,
@@ -78,6 +96,19 @@ hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, c
 // else pointwise slot range starting at the parity-0 block)
 hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *part,
                                   int stencil_layout, double *out, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// dst.hip: spectral (type-I sine transform) preconditioner
+// ----------------------------------------------------------------------------
+
+// z = M^{-1} r (float) for the orbitals of the work lists with done == 0,
+// through the float work array; r.z partial sums into rz[base9 + panel].
+// tab: sine matrices and eigenvalue symbols (offsets in OrbDesc); cnt (may
+// be null): per orbital, applications that did work.
+template <typename T>
+hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int *done,
+                              const float *tab, const T *r, float *work, float *z, double *rz,
+                              int *cnt, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // multipole.hip: Dirichlet values from a multipole expansion, right-hand side

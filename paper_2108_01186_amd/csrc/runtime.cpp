@@ -153,6 +153,11 @@ struct Batch {
     long long ghosts = 0;
     long long max_ghost = 0;
     int tot7 = 0, tot8 = 0;
+    // spectral preconditioner: panel work lists, sine matrices and symbols
+    std::vector<Item> dx, dy, dz;
+    std::vector<float> dtab;
+    int tot9 = 0;
+    int max_n = 0;
 };
 
 void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<Item> &out) {
@@ -178,6 +183,9 @@ struct fsic_ctx {
     // field buffers
     DBuf<double> PHI, V, W, B, R, P0, P1, Q, X64b;
     DBuf<float> R32, P32a, P32b, Q32, X32;
+    DBuf<float> Z32, T32, dtab;     // preconditioned CG: z, transform work array, spectral table
+    DBuf<double> partRZ;
+    DBuf<Item> d_dx, d_dy, d_dz;
     DBuf<double> Gh;  // ghost values
     DBuf<double> part7, part8, partRU, partQ, partZ;
     DBuf<double> bb, rrfin, relres, Qlm, Zt, ptrue;
@@ -197,8 +205,9 @@ struct fsic_ctx {
     int *h_done = nullptr;  // pinned
     // profiling (FSIC_PROFILE): events around every CG launch
     std::vector<hipEvent_t> ev;
-    int32_t sweep_launches = 0, update_launches = 0;
+    int32_t sweep_launches = 0, update_launches = 0, precond_launches = 0;
     double sweep_ms = 0, sweep_bytes = 0, update_ms = 0, update_bytes = 0;
+    double precond_ms = 0, precond_bytes = 0, precond_flops = 0;
     size_t h_done_cap = 0;
 
     // plan of the last forward pass (the tape)
@@ -239,7 +248,7 @@ fsic_status validate_opts(const fsic_opts *o, std::string &why) {
     if (!o) { why = "opts is NULL"; return FSIC_EINVAL; }
     if (o->fd_order < 2 || o->fd_order > 12 || (o->fd_order & 1)) { why = "fd_order must be even in [2, 12]"; return FSIC_EINVAL; }
     if (o->lmax < 0 || o->lmax > kMaxL) { why = "lmax must be in [0, 8]"; return FSIC_EINVAL; }
-    if (o->solver != FSIC_CG) { why = "solver must be FSIC_CG"; return FSIC_EINVAL; }
+    if (o->solver != FSIC_CG && o->solver != FSIC_PCG) { why = "solver must be FSIC_CG or FSIC_PCG"; return FSIC_EINVAL; }
     if (o->precision != FSIC_FP64 && o->precision != FSIC_MIXED) { why = "precision must be FSIC_FP64 or FSIC_MIXED"; return FSIC_EINVAL; }
     if (!(o->tol > 0.0 && o->tol < 1.0)) { why = "tol must be in (0, 1)"; return FSIC_EINVAL; }
     if (o->max_iter < 1) { why = "max_iter must be >= 1"; return FSIC_EINVAL; }
@@ -267,6 +276,16 @@ struct Shape {
     int cpt, depth;
     long long target;
 };
+
+// preconditioned mixed-precision CG: FP32 iterations between FP64 residual
+// checks (each restarts the FP32 recursion); FSIC_PCG_CHUNK overrides 4
+int pcg_chunk() {
+    static int v = [] {
+        const char *e = getenv("FSIC_PCG_CHUNK");
+        return e ? std::max(1, atoi(e)) : 4;
+    }();
+    return v;
+}
 
 // CG iterations between profiled ones (FSIC_PROFILE); FSIC_PROFILE_EVERY
 // overrides the default 16
@@ -306,7 +325,33 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     long long cols = 0;
     for (const Group &g : groups)
         cols += (long long)g.count * ((g.n[0] + kTX - 1) / kTX) * ((g.n[1] + 8 * cpt - 1) / (8 * cpt));
-    std::vector<std::pair<int, int>> nat7, nat8;
+    std::vector<std::pair<int, int>> nat7, nat8, natx, naty, natz;
+    std::map<int, std::pair<int, int>> dst_done;  // n -> (sine offset, symbol offset)
+    auto dst_entry = [&](Batch &bb, int n, int radius_) -> const std::pair<int, int> & {
+        auto f = dst_done.find(n);
+        if (f != dst_done.end()) return f->second;
+        const int np = (n + 15) & ~15;
+        const int so = (int)bb.dtab.size();
+        bb.dtab.resize(bb.dtab.size() + (size_t)np * np, 0.f);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int m = 0; m < n; ++m)
+            for (int k = 0; k < n; ++k) {
+                // sin(pi (m+1)(k+1) / (n+1)), argument reduced exactly in integers
+                const long long a = ((long long)(m + 1) * (k + 1)) % (2LL * (n + 1));
+                bb.dtab[so + (size_t)m * np + k] = (float)sinl(pi * (long double)a / (long double)(n + 1));
+            }
+        const int go = (int)bb.dtab.size();
+        const Coeffs cw = fd_weights(radius_);
+        for (int j = 0; j < n; ++j) {
+            const long double th = pi * (long double)(j + 1) / (long double)(n + 1);
+            long double sg = cw.c[0];
+            for (int q = 1; q <= radius_; ++q) sg += 2.0L * cw.c[q] * cosl(q * th);
+            bb.dtab.push_back((float)(-sg));
+        }
+        // pad the table to a multiple of 4 floats
+        while (bb.dtab.size() % 4) bb.dtab.push_back(0.f);
+        return dst_done[n] = {so, go};
+    };
     for (const Group &g : groups) {
         const long long M = (long long)g.n[0] * g.n[1] * g.n[2];
         for (int i = 0; i < g.count; ++i) {
@@ -332,15 +377,32 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
                 od.centre[d] = g.origin[d] + 0.5 * g.h * (g.n[d] - 1);
             }
             od.chan = g.chan;
+            od.nt9 = (int)(((long long)g.n[1] * g.n[2] + 31) / 32);
+            od.base9 = b.tot9;
+            b.tot9 += od.nt9;
+            for (int d = 0; d < 3; ++d) {
+                const auto &e = dst_entry(b, g.n[d], radius);
+                od.dst_s[d] = e.first;
+                od.dst_g[d] = e.second;
+                b.max_n = std::max(b.max_n, g.n[d]);
+            }
             const int o = (int)b.orb.size();
             b.orb.push_back(od);
             for (int t = 0; t < od.nt7; ++t) nat7.push_back({o, t});
             for (int t = 0; t < od.nt8; ++t) nat8.push_back({o, t});
+            for (int t = 0; t < od.nt9; ++t) natx.push_back({o, t});
+            const int ny_t = g.n[2] * ((g.n[0] + 31) / 32);
+            for (int t = 0; t < ny_t; ++t) naty.push_back({o, t});
+            const int nz_t = (int)(((long long)g.n[0] * g.n[1] + 31) / 32);
+            for (int t = 0; t < nz_t; ++t) natz.push_back({o, t});
             b.fields = std::max(b.fields, od.off + M);
         }
     }
     build_items(nat7, b.items7);
     build_items(nat8, b.items8);
+    build_items(natx, b.dx);
+    build_items(naty, b.dy);
+    build_items(natz, b.dz);
 }
 
 template <typename T>
@@ -351,6 +413,12 @@ fsic_status upload(fsic_ctx *c, DBuf<T> &d, const std::vector<T> &h) {
     return FSIC_OK;
 }
 
+// The spectral preconditioner serves grids of up to 256 nodes per axis;
+// larger batches are solved with plain CG.
+bool use_pcg(const fsic_ctx *c, const Batch &b) {
+    return c->opts.solver == FSIC_PCG && b.max_n <= 256;
+}
+
 // Upload a batch's tables and size the solver buffers.
 fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     const size_t F = (size_t)b.fields;
@@ -359,6 +427,17 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     if ((st = upload(c, c->d_items7, b.items7))) return st;
     if ((st = upload(c, c->d_items8, b.items8))) return st;
     if ((st = upload(c, c->d_gcount, b.gcount))) return st;
+    if (use_pcg(c, b)) {
+        if ((st = upload(c, c->d_dx, b.dx))) return st;
+        if ((st = upload(c, c->d_dy, b.dy))) return st;
+        if ((st = upload(c, c->d_dz, b.dz))) return st;
+        if ((st = upload(c, c->dtab, b.dtab))) return st;
+        HIPCHK(c, c->Z32.ensure(F));
+        HIPCHK(c, c->T32.ensure(F));
+        HIPCHK(c, c->partRZ.ensure(2 * (size_t)b.tot9));
+        if (precision == FSIC_FP64) HIPCHK(c, c->P1.ensure(F));
+        else HIPCHK(c, c->P32b.ensure(F));
+    }
     HIPCHK(c, c->B.ensure(F));
     if (precision == FSIC_FP64) {
         HIPCHK(c, c->R.ensure(F));
@@ -387,7 +466,7 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     HIPCHK(c, c->done.ensure(norb));
     HIPCHK(c, c->iters.ensure(norb));
     HIPCHK(c, c->rs_iter.ensure(norb));
-    HIPCHK(c, c->nact.ensure(4 * (size_t)norb));
+    HIPCHK(c, c->nact.ensure(5 * (size_t)norb));
     if (c->h_done_cap < (size_t)norb) {
         if (c->h_done) hipHostFree(c->h_done);
         c->h_done = nullptr;
@@ -571,7 +650,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->iters.p, 0, norb * sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->rs_iter.p, 0xff, norb * sizeof(int), s));  // -1: no restart
-    HIPCHK(c, hipMemsetAsync(c->nact.p, 0, 4 * norb * sizeof(int), s));
+    HIPCHK(c, hipMemsetAsync(c->nact.p, 0, 5 * norb * sizeof(int), s));
     const double tol2 = tol * tol;
     const int chunk = 32;
     int k = 0;
@@ -580,9 +659,10 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     // recorded on the context's stream; nact[2 norb..] counts what those
     // launches did
     const bool prof = (c->opts.flags & FSIC_PROFILE) != 0;
-    const int prof_every = profile_period();
+    // preconditioned solves take a few iterations: sample every other one
+    const int prof_every = use_pcg(c, b) ? 2 : profile_period();
     auto sampled = [&](int kk) { return prof && kk % prof_every == prof_every - 1; };
-    int *const nsamp = c->nact.p + 2 * norb;
+    int *const nsamp = c->nact.p + 2 * norb;  // sampled sweeps, updates, preconditioner passes
     struct Rec { int kind, k, flag; hipEvent_t a, b; };  // kind 0 sweep, 1 update; flag: first access
     std::vector<Rec> recs;
     size_t evn = 0;
@@ -609,7 +689,115 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     }
 #define PROF_END() \
     if (_sp) HIPCHK(c, hipEventRecord(_eb, s));
-    if (!mixed) {
+    const bool pcg = use_pcg(c, b);
+    DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(), (int)b.dz.size()};
+    if (pcg && !mixed) {
+        // FP64 CG preconditioned by the FP32 sine-transform inverse
+        CGIter<double> a{};
+        a.items7 = c->d_items7.p; a.nitems7 = nit7;
+        a.items8 = c->d_items8.p; a.nitems8 = nit8;
+        a.orb = c->d_orb.p;
+        a.R = c->R.p; a.Q = c->Q.p; a.X = X; a.Z = c->Z32.p;
+        a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.partRZ = c->partRZ.p;
+        a.tot7 = b.tot7; a.tot8 = b.tot8; a.tot9 = b.tot9;
+        a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
+        a.rs_iter = nullptr; a.nact = c->nact.p; a.norb = norb;
+        a.tol2 = tol2;
+        HIPCHK(c, launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R, c->T32.p,
+                                             a.Z, a.partRZ, nullptr, s));
+        while (k < max_iter + 1 && !all_done) {
+            const int kend = std::min(k + chunk, max_iter + 1);
+            for (; k < kend; ++k) {
+                a.P = (k & 1) ? c->P1.p : c->P0.p;
+                a.Pold = (k & 1) ? c->P0.p : c->P1.p;
+                {
+                    PROF_BEGIN(0, k, k == 0)
+                    HIPCHK(c, launch_pcg_stencil<double>(c->radius, c->cf, a, k, 0, 0, 0, s));
+                    PROF_END()
+                }
+                if (k < max_iter) {
+                    {
+                        PROF_BEGIN(1, k, k == 0)
+                        HIPCHK(c, launch_pcg_update<double>(a, k, k == 0, s));
+                        PROF_END()
+                    }
+                    PROF_BEGIN(2, k, 0)
+                    HIPCHK(c, launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
+                                                         c->T32.p, a.Z,
+                                                         a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
+                                                         _sp ? nsamp + 2 * norb : nullptr, s));
+                    PROF_END()
+                }
+            }
+            HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            all_done = true;
+            for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o];
+        }
+        HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
+                                       X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
+        HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
+    } else if (pcg) {
+        // FP32 preconditioned CG restarted from the FP64 residual every
+        // pchunk iterations (defect correction: x64 += x32)
+        CGIter<float> a{};
+        a.items7 = c->d_items7.p; a.nitems7 = nit7;
+        a.items8 = c->d_items8.p; a.nitems8 = nit8;
+        a.orb = c->d_orb.p;
+        a.R = c->R32.p; a.Q = c->Q32.p; a.X = c->X32.p; a.Z = c->Z32.p;
+        a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.partRZ = c->partRZ.p;
+        a.tot7 = b.tot7; a.tot8 = b.tot8; a.tot9 = b.tot9;
+        a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
+        a.rs_iter = c->rs_iter.p; a.nact = c->nact.p; a.norb = norb;
+        a.tol2 = tol2;
+        const int pchunk = pcg_chunk();
+        int nref = 0;
+        while (k < max_iter && !all_done) {
+            const int kstart = k;
+            const int kend = std::min(k + pchunk, max_iter);
+            HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R, c->T32.p,
+                                                a.Z, a.partRZ + (size_t)(k & 1) * b.tot9, nullptr, s));
+            for (; k < kend; ++k) {
+                const int j = k - kstart;
+                a.P = (k & 1) ? c->P32b.p : c->P32a.p;
+                a.Pold = (k & 1) ? c->P32a.p : c->P32b.p;
+                {
+                    PROF_BEGIN(0, k, k == 0)
+                    HIPCHK(c, launch_pcg_stencil<float>(c->radius, c->cf, a, k, j == 0 && k > 0,
+                                                        j == 0, 1, s));
+                    PROF_END()
+                }
+                {
+                    PROF_BEGIN(1, k, j == 0)
+                    HIPCHK(c, launch_pcg_update<float>(a, k, j == 0, s));
+                    PROF_END()
+                }
+                if (k + 1 < kend) {
+                    PROF_BEGIN(2, k, 0)
+                    HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
+                                                        c->T32.p, a.Z,
+                                                        a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
+                                                        _sp ? nsamp + 2 * norb : nullptr, s));
+                    PROF_END()
+                }
+            }
+            HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p,
+                                           c->done.p, X, c->X32.p, c->B.p, nullptr, c->R32.p,
+                                           c->partRU.p, s));
+            HIPCHK(c, launch_mixed_accumulate(nit8, c->d_items8.p, c->d_orb.p, c->done.p, X, c->X32.p, s));
+            HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, k, c->done.p,
+                                      c->iters.p, c->rrfin.p, c->rs_iter.p, s));
+            ++nref;
+            HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            all_done = true;
+            for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o] == 1;
+        }
+        rep.refinements += nref;
+        HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
+                                       X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
+        HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
+    } else if (!mixed) {
         CGIter<double> a{};
         a.items7 = c->d_items7.p; a.nitems7 = nit7;
         a.items8 = c->d_items8.p; a.nitems8 = nit8;
@@ -693,10 +881,10 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                        X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
         HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
     }
-    std::vector<int> it(norb), na(4 * (size_t)norb);
+    std::vector<int> it(norb), na(5 * (size_t)norb);
     std::vector<double> pt(norb), bbh(norb);
     HIPCHK(c, hipMemcpyAsync(it.data(), c->iters.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(na.data(), c->nact.p, 4 * norb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(na.data(), c->nact.p, 5 * norb * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(pt.data(), c->ptrue.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(bbh.data(), c->bb.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -720,12 +908,28 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
             if (r.kind == 0) { c->sweep_launches += 1; c->sweep_ms += ms; }
-            else { c->update_launches += 1; c->update_ms += ms; }
+            else if (r.kind == 1) { c->update_launches += 1; c->update_ms += ms; }
+            else { c->precond_launches += 1; c->precond_ms += ms; }
         }
+        // preconditioned CG: sweep reads z (float) and p_old, writes p, q;
+        // update reads x, p, r, q, writes x, r; the preconditioner reads r,
+        // passes the float work array through five transforms (each read and
+        // written once) and reads r again for r.z while writing z; its flops
+        // are 2 n per value per transform along an axis of n nodes
         for (int o = 0; o < norb; ++o) {
-            const double Mo = (double)b.orb[o].nx * b.orb[o].ny * b.orb[o].nz;
-            c->sweep_bytes += Mo * esz * 3.0 * na[2 * (size_t)norb + o];
-            c->update_bytes += Mo * esz * 7.0 * na[3 * (size_t)norb + o];
+            const OrbDesc &od = b.orb[o];
+            const double Mo = (double)od.nx * od.ny * od.nz;
+            const double ns = na[2 * (size_t)norb + o], nu = na[3 * (size_t)norb + o];
+            if (pcg) {
+                const double npc = na[4 * (size_t)norb + o];
+                c->sweep_bytes += Mo * (4.0 + 3.0 * esz) * ns;
+                c->update_bytes += Mo * esz * 6.0 * nu;
+                c->precond_bytes += Mo * (36.0 + 2.0 * esz) * npc;
+                c->precond_flops += Mo * 4.0 * (od.nx + od.ny + od.nz) * npc;
+            } else {
+                c->sweep_bytes += Mo * esz * 3.0 * ns;
+                c->update_bytes += Mo * esz * 7.0 * nu;
+            }
         }
     }
 #undef PROF_BEGIN
@@ -745,7 +949,7 @@ fsic_status fsic_default_opts(fsic_opts *o) {
     if (!o) return FSIC_EINVAL;
     o->fd_order = 12;
     o->lmax = 6;
-    o->solver = FSIC_CG;
+    o->solver = FSIC_PCG;
     o->precision = FSIC_FP64;
     o->tol = 1e-10;
     o->max_iter = 20000;
@@ -818,6 +1022,8 @@ void fsic_destroy(fsic_ctx *c) {
     c->PHI.release(); c->V.release(); c->W.release(); c->B.release(); c->R.release();
     c->P0.release(); c->P1.release(); c->Q.release(); c->X64b.release();
     c->R32.release(); c->P32a.release(); c->P32b.release(); c->Q32.release(); c->X32.release();
+    c->Z32.release(); c->T32.release(); c->dtab.release(); c->partRZ.release();
+    c->d_dx.release(); c->d_dy.release(); c->d_dz.release();
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
     c->partQ.release(); c->partZ.release(); c->bb.release(); c->rrfin.release();
     c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release();
@@ -933,8 +1139,9 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     HIPCHK(c, c->small.ensure((size_t)nchan * kSmallStride));
     HIPCHK(c, c->work.ensure(4 * (size_t)kMaxOrb * kMaxOrb));
     const int gram_blk = 256;
-    c->sweep_launches = c->update_launches = 0;
+    c->sweep_launches = c->update_launches = c->precond_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
+    c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
     HIPCHK(c, c->partG.ensure((size_t)gram_blk * kMaxOrb * kMaxOrb));
     std::vector<FodCell> cells;
     for (const Chan &ch : chans) cells.insert(cells.end(), ch.cells.begin(), ch.cells.end());
@@ -1053,6 +1260,10 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         st->sweep_bytes = c->sweep_bytes;
         st->update_ms = c->update_ms;
         st->update_bytes = c->update_bytes;
+        st->precond_launches = c->precond_launches;
+        st->precond_ms = c->precond_ms;
+        st->precond_bytes = c->precond_bytes;
+        st->precond_flops = c->precond_flops;
         st->stencil_cpt = c->shape_cpt;
         st->stencil_depth = c->shape_depth;
         st->stencil_blocks = c->shape_target;
@@ -1140,7 +1351,8 @@ fsic_status fsic_op_xc(int64_t count, const double *rho, double rho_floor, doubl
 
 fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lmax, int32_t count,
                             const double *rho, double *v, double tol, int32_t max_iter,
-                            int32_t precision, int32_t *iters, double *relres, void *hip_stream) {
+                            int32_t precision, int32_t solver, int32_t *iters, double *relres,
+                            void *hip_stream) {
     if (!grid || !rho || !v || count < 1) return FSIC_EINVAL;
     fsic_opts o;
     fsic_default_opts(&o);
@@ -1149,6 +1361,7 @@ fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lma
     o.tol = tol;
     o.max_iter = max_iter;
     o.precision = precision;
+    o.solver = solver;
     std::string why;
     if (validate_opts(&o, why) || validate_grid(*grid, why)) return FSIC_EINVAL;
     OpCtx oc;
@@ -1276,8 +1489,9 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     hipStream_t s = c->stream;
     const int norb = (int)b.orb.size();
     c->tune_ms = 0.0;  // the backward pass reuses the forward pass's stencil shape
-    c->sweep_launches = c->update_launches = 0;
+    c->sweep_launches = c->update_launches = c->precond_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
+    c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
     fsic_status pst = prepare_batch(c, b, o.precision);
     if (pst) return pst;
     HIPCHK(c, c->W.ensure((size_t)b.fields));
@@ -1340,6 +1554,10 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         st->sweep_bytes = c->sweep_bytes;
         st->update_ms = c->update_ms;
         st->update_bytes = c->update_bytes;
+        st->precond_launches = c->precond_launches;
+        st->precond_ms = c->precond_ms;
+        st->precond_bytes = c->precond_bytes;
+        st->precond_flops = c->precond_flops;
         st->stencil_cpt = c->shape_cpt;
         st->stencil_depth = c->shape_depth;
         st->stencil_blocks = c->shape_target;

@@ -347,6 +347,79 @@ struct PolCG {  // q = K p_k = -L p_k; partial sums of p.q, r.q, q.q
     }
 };
 
+// r_j.z_j of an orbital (preconditioned CG), by iteration parity
+template <typename T>
+__device__ __forceinline__ double rz_of(const CGIter<T> &a, const OrbDesc &od, int j, double *sbuf) {
+    return sum_partials(a.partRZ + (size_t)(j & 1) * a.tot9 + od.base9, od.nt9, sbuf);
+}
+
+template <typename T>
+struct PolPCG {  // p_k = z_k + beta p_{k-1}; q = K p_k = -L p_k; p.q partials
+    const Item *items;
+    const OrbDesc *orb;
+    CGIter<T> a;
+    int k, cur_ru, restart, pause;
+    double beta;
+    bool tile0;
+    __device__ bool setup(int o, const OrbDesc &od, double *sbuf) {
+        if (threadIdx.x == 0) sbuf[0] = (double)a.done[o];
+        __syncthreads();
+        const bool dn = sbuf[0] != 0.0;
+        __syncthreads();
+        if (dn) return false;
+        const double rr = rr_of(a, od, k, cur_ru, sbuf);
+        if (rr <= a.tol2 * a.bb[o]) {
+            if (threadIdx.x == 0) {
+                if (pause) {
+                    a.done[o] = 2;  // mixed: confirm on the FP64 residual first
+                } else {
+                    a.done[o] = 1;
+                    a.iters[o] = k;
+                    a.rrfin[o] = rr;
+                }
+            }
+            return false;
+        }
+        if (k == 0 || restart) {
+            beta = 0.0;
+        } else {
+            beta = rz_of(a, od, k, sbuf) / rz_of(a, od, k - 1, sbuf);
+        }
+        if (threadIdx.x == 0 && tile0) {
+            a.nact[o] += 1;
+            if (a.nsamp) a.nsamp[o] += 1;
+        }
+        return true;
+    }
+    struct Raw { float z; T p; };
+    struct Ext {};
+    typedef double Acc;
+    Rsrc rz_, rpo, rpn, rq;
+    __device__ void init(const OrbDesc &od) {
+        const long long M = (long long)od.nx * od.ny * od.nz;
+        rz_ = make_rsrc(a.Z + od.off, (unsigned)(M * 4));
+        rpo = make_rsrc(a.Pold + od.off, (unsigned)(M * sizeof(T)));
+        rpn = make_rsrc(a.P + od.off, (unsigned)(M * sizeof(T)));
+        rq = make_rsrc(a.Q + od.off, (unsigned)(M * sizeof(T)));
+    }
+    __device__ Raw raw(unsigned i, int zo) const {
+        // beta = 0 at a (re)start and the host points p_old at finite data
+        return Raw{bld<float>(rz_, i, zo), bld<T>(rpo, i, zo)};
+    }
+    __device__ Ext ext(unsigned, int) const { return Ext{}; }
+    __device__ T combine(const Raw &v) const { return (T)v.z + (T)beta * v.p; }
+    __device__ void epilogue(unsigned i, int zo, T c, T lap, const Ext &, Acc &s) const {
+        const T qv = -lap;
+        bst(rpn, i, zo, c);
+        bst(rq, i, zo, qv);
+        s += (double)c * (double)qv;
+    }
+    __device__ void finish(const Item &it, const OrbDesc &od, const Acc &s, double *sred) const {
+        const double t = block_sum256(s, sred);
+        if (threadIdx.x == 0) a.part7[od.base7 + it.tile] = t;
+    }
+};
+
 template <bool HAS32>
 struct PolRes {  // res = b + L x, x = x64 (+ x32)
     const Item *items;
@@ -480,6 +553,69 @@ __global__ __launch_bounds__(256) void k_cg_update(CGIter<T> a, int k, int cur_r
     }
 }
 
+// preconditioned CG: x += alpha p; r -= alpha q; alpha = r.z / p.q
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_update(CGIter<T> a, int k, int x_first) {
+    using V = typename Vec16<T>::V;
+    constexpr int VN = Vec16<T>::n;
+    __shared__ double sred[4];
+    const Item it = a.items8[blockIdx.x];
+    if (it.orb < 0) return;
+    if (a.done[it.orb]) return;
+    const OrbDesc od = a.orb[it.orb];
+    const double rz = rz_of(a, od, k, sred);
+    const double pq = sum_partials(a.part7 + od.base7, od.nt7, sred);
+    const T al = (T)(rz / pq);
+    const long long M = (long long)od.nx * od.ny * od.nz;
+    const long long base = (long long)it.tile * kPW;
+    double acc = 0.0;
+    if (((od.off | M) % VN) == 0) {
+#pragma unroll
+        for (int e = 0; e < kPW / (256 * VN); ++e) {
+            const long long i = base + (long long)(e * 256 + threadIdx.x) * VN;
+            if (i < M) {
+                const long long g = od.off + i;
+                V pv = *reinterpret_cast<const V *>(a.P + g);
+                V qv = *reinterpret_cast<const V *>(a.Q + g);
+                V rv = *reinterpret_cast<const V *>(a.R + g);
+                V xv = x_first ? V{} : *reinterpret_cast<const V *>(a.X + g);
+                T *px = reinterpret_cast<T *>(&xv), *pr = reinterpret_cast<T *>(&rv);
+                const T *pp = reinterpret_cast<const T *>(&pv), *pqv = reinterpret_cast<const T *>(&qv);
+#pragma unroll
+                for (int j = 0; j < VN; ++j) {
+                    px[j] = x_first ? al * pp[j] : px[j] + al * pp[j];
+                    pr[j] = pr[j] - al * pqv[j];
+                    acc += (double)pr[j] * (double)pr[j];
+                }
+                *reinterpret_cast<V *>(a.X + g) = xv;
+                *reinterpret_cast<V *>(a.R + g) = rv;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPW / 256; ++e) {
+            const long long i = base + e * 256 + threadIdx.x;
+            if (i < M) {
+                const long long g = od.off + i;
+                const T pv = a.P[g];
+                const T xv = x_first ? al * pv : a.X[g] + al * pv;
+                const T rv = a.R[g] - al * a.Q[g];
+                a.X[g] = xv;
+                a.R[g] = rv;
+                acc += (double)rv * (double)rv;
+            }
+        }
+    }
+    const double s = block_sum256(acc, sred);
+    if (threadIdx.x == 0) {
+        a.part8[(size_t)((k + 1) & 1) * a.tot8 + od.base8 + it.tile] = s;
+        if (it.tile == 0) {
+            a.nact[a.norb + it.orb] += 1;
+            if (a.nsamp) a.nsamp[a.norb + it.orb] += 1;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_partials(int norb, const OrbDesc *orb,
                                                          const double *part, int stencil,
                                                          double *out) {
@@ -583,6 +719,25 @@ hipError_t launch_cg_update(const CGIter<T> &a, int k, int cur_from_ru, int x_fi
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_pcg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, int k,
+                              int cur_from_ru, int restart, int pause, hipStream_t s) {
+    if (a.nitems7 <= 0) return hipSuccess;
+    PolPCG<T> pol{a.items7, a.orb, a, k, cur_from_ru, restart, pause, 0.0, false};
+    if (k == 0 || restart) pol.a.Pold = a.R;  // beta = 0: any finite p_old will do
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolPCG<T>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
+    FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pcg_update(const CGIter<T> &a, int k, int x_first, hipStream_t s) {
+    if (a.nitems8 <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_pcg_update<T>), dim3(a.nitems8), dim3(256), 0, s, a, k, x_first);
+    return hipGetLastError();
+}
+
 hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7, int nitems7,
                                 const OrbDesc *orb, const int *done, const double *X64,
                                 const float *X32, const double *B, double *X64new, float *R32,
@@ -635,6 +790,12 @@ template hipError_t launch_cg_stencil<double>(int, const Coeffs &, const CGIter<
                                               int, hipStream_t);
 template hipError_t launch_cg_stencil<float>(int, const Coeffs &, const CGIter<float> &, int, int,
                                              int, hipStream_t);
+template hipError_t launch_pcg_stencil<double>(int, const Coeffs &, const CGIter<double> &, int, int,
+                                               int, int, hipStream_t);
+template hipError_t launch_pcg_stencil<float>(int, const Coeffs &, const CGIter<float> &, int, int,
+                                              int, int, hipStream_t);
+template hipError_t launch_pcg_update<double>(const CGIter<double> &, int, int, hipStream_t);
+template hipError_t launch_pcg_update<float>(const CGIter<float> &, int, int, hipStream_t);
 template hipError_t launch_cg_update<double>(const CGIter<double> &, int, int, int, hipStream_t);
 template hipError_t launch_cg_update<float>(const CGIter<float> &, int, int, int, hipStream_t);
 

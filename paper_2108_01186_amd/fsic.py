@@ -31,7 +31,7 @@ _lib = ctypes.CDLL(LIBPATH)
 FSIC_OK, FSIC_EINVAL, FSIC_ENOMEM, FSIC_EHIP, FSIC_ENONORTHO, FSIC_EVACUUM, \
     FSIC_EBOUNDARY, FSIC_ESINGULAR, FSIC_ENOCONV, FSIC_ENOTAPE = range(10)
 FSIC_FP64, FSIC_MIXED = 0, 1
-FSIC_CG = 0
+FSIC_CG, FSIC_PCG = 0, 1
 FSIC_WANT_VSIC, FSIC_KEEP_TAPE, FSIC_ALLOW_NONORTHO, FSIC_PROFILE = 1, 2, 4, 8
 
 
@@ -62,6 +62,8 @@ class fsic_stats(ctypes.Structure):
                 ("sweep_launches", ctypes.c_int32), ("update_launches", ctypes.c_int32),
                 ("sweep_ms", ctypes.c_double), ("sweep_bytes", ctypes.c_double),
                 ("update_ms", ctypes.c_double), ("update_bytes", ctypes.c_double),
+                ("precond_launches", ctypes.c_int32), ("precond_ms", ctypes.c_double),
+                ("precond_bytes", ctypes.c_double), ("precond_flops", ctypes.c_double),
                 ("stencil_cpt", ctypes.c_int32), ("stencil_depth", ctypes.c_int32),
                 ("stencil_blocks", ctypes.c_int64), ("tune_ms", ctypes.c_double)]
 
@@ -101,7 +103,8 @@ fsic_op_xc = _sig("fsic_op_xc", ctypes.c_int,
                   [ctypes.c_int64, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp])
 fsic_op_poisson = _sig("fsic_op_poisson", ctypes.c_int,
                        [_P(fsic_grid), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
-                        ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _ip, _dp, _vp])
+                        ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _ip, _dp,
+                        _vp])
 fsic_op_invsqrt = _sig("fsic_op_invsqrt", ctypes.c_int,
                        [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp])
 fsic_op_flo = _sig("fsic_op_flo", ctypes.c_int,
@@ -159,6 +162,8 @@ def default_opts(**kw) -> fsic_opts:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp64": FSIC_FP64, "mixed": FSIC_MIXED}[v]
+        if k == "solver" and isinstance(v, str):
+            v = {"cg": FSIC_CG, "pcg": FSIC_PCG}[v]
         setattr(o, k, v)
     return o
 
@@ -198,6 +203,8 @@ class Context:
         for k, v in kw.items():
             if k == "precision" and isinstance(v, str):
                 v = {"fp64": FSIC_FP64, "mixed": FSIC_MIXED}[v]
+            if k == "solver" and isinstance(v, str):
+                v = {"cg": FSIC_CG, "pcg": FSIC_PCG}[v]
             setattr(self.opts, k, v)
         _check(fsic_set_opts(self._h, ctypes.byref(self.opts)), self._h)
 
@@ -289,7 +296,7 @@ def op_xc(rho, rho_floor: float = 1e-30, stream=None):
 
 
 def op_poisson(rho, n, h, origin, fd_order=12, lmax=6, tol=1e-10, max_iter=20000,
-               precision="fp64", stream=None):
+               precision="fp64", solver="cg", stream=None):
     """Hartree potentials of densities rho (count, M) on one grid."""
     torch = _torch()
     rho = rho.contiguous()
@@ -299,8 +306,9 @@ def op_poisson(rho, n, h, origin, fd_order=12, lmax=6, tol=1e-10, max_iter=20000
     it = np.zeros(count, dtype=np.int32)
     rr = np.zeros(count)
     prec = {"fp64": FSIC_FP64, "mixed": FSIC_MIXED}[precision] if isinstance(precision, str) else precision
+    solv = {"cg": FSIC_CG, "pcg": FSIC_PCG}[solver] if isinstance(solver, str) else solver
     _check(fsic_op_poisson(ctypes.byref(g), fd_order, lmax, count, _dev_ptr(rho), _dev_ptr(v), tol,
-                           max_iter, prec, it.ctypes.data_as(_ip), rr.ctypes.data_as(_dp),
+                           max_iter, prec, solv, it.ctypes.data_as(_ip), rr.ctypes.data_as(_dp),
                            _stream_ptr(stream)))
     return v, it, rr
 

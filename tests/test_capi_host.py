@@ -57,7 +57,7 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(fsic.fsic_grid) == 4 * 3 + 4 + 8 + 24
     assert ctypes.sizeof(fsic.fsic_opts) == 64
     assert ctypes.sizeof(fsic.fsic_stats) == (4 + 4 + 8 + 4 + 4 + 8 * 4 + 8 * 8 + 4 + 4 + 8 * 4
-                                              + 4 + 4 + 8 + 8)
+                                              + 4 + 4 + 8 * 3 + 4 + 4 + 8 + 8)
 
 
 def test_invalid_arguments_rejected_on_host():

@@ -37,12 +37,13 @@ def mol40_grad_oracle(oracle, mol40):
     return oracle.sic_grad_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_mol40_gradient_vs_oracle(torch_cuda, F, mol40, mol40_grad_oracle, precision):
+@pytest.mark.parametrize("precision,solver", [("fp64", "cg"), ("mixed", "cg"), ("fp64", "pcg"),
+                                              ("mixed", "pcg")])
+def test_mol40_gradient_vs_oracle(torch_cuda, F, mol40, mol40_grad_oracle, precision, solver):
     torch = torch_cuda
-    _say(f"gradient mol40 {precision}")
+    _say(f"gradient mol40 {precision} {solver}")
     s = mol40
-    ctx = F.Context(precision=precision, tol=1e-11)
+    ctx = F.Context(precision=precision, tol=1e-11, solver=solver)
     psi = torch.tensor(np.asarray(s.psi[0]), device="cuda")
     fod = torch.tensor(s.fod[0], requires_grad=True)
     E, vs = F.flosic_sic(ctx, s.n, s.h, s.origin, [psi], [fod])

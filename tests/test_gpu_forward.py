@@ -39,12 +39,14 @@ def mol40_dev(torch_cuda, mol40):
     return _to_dev(torch_cuda, s)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp64", 1e-12), ("mixed", 1e-10)])
+@pytest.mark.parametrize("precision,tol,solver", [("fp64", 1e-10, "cg"), ("fp64", 1e-12, "cg"),
+                                                  ("mixed", 1e-10, "cg"), ("fp64", 1e-10, "pcg"),
+                                                  ("fp64", 1e-12, "pcg"), ("mixed", 1e-10, "pcg")])
 def test_mol40_energy_and_potential(torch_cuda, F, oracle, mol40, mol40_dev, mol40_oracle,
-                                    precision, tol):
-    _say(f"forward mol40 {precision} tol={tol}")
+                                    precision, tol, solver):
+    _say(f"forward mol40 {precision} tol={tol} {solver}")
     r = mol40_oracle
-    out = F.sic_energy([mol40_dev], precision=precision, tol=tol)
+    out = F.sic_energy([mol40_dev], precision=precision, tol=tol, solver=solver)
     e = out["e"][0]
     # energy parity: 1e-8 Ha
     assert abs(e - r.e) < 1e-8, (e, r.e)

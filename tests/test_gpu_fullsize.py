@@ -1,5 +1,7 @@
 """Parity at the full workload sizes, in the launch configuration the
-benchmark times (both spins batched, mixed precision, tol 1e-10):
+benchmark times (both spins batched, mixed precision, preconditioned CG to
+a relative residual of 1e-11, which keeps E_SIC within 1e-8 Ha even on the
+largest systems of the uneven batch; 1e-10 left 1.02e-8 Ha there):
 
 * 96^3 / 16 + 15 orbitals: every output against the oracle (E_SIC, U_i, X_i,
   V_SIC elementwise, spin-up FOD gradient), and the V_SIC scale factor;
@@ -20,6 +22,7 @@ from paper_2108_01186_amd import synth
 pytestmark = pytest.mark.gpu
 
 E_TOL = 1e-8       # Ha, energy target
+TOL = 1e-11        # relative FP64 residual of every solve
 F_TOL = 1e-6       # Ha/Bohr, force target
 # per-orbital U_i, X_i at large N: both sides form S^{-1/2} in FP64 from S
 # rounded differently (grid sums in another order), and the condition number
@@ -63,13 +66,13 @@ def test_mol96_all_outputs_vs_oracle(torch_cuda, F, oracle):
     torch = torch_cuda
     _say("mol96: generate")
     s = synth.make_workload("mol96", device="cuda")
-    ctx = F.Context(precision="mixed", tol=1e-10, flags=_flags(F))
+    ctx = F.Context(precision="mixed", tol=TOL, flags=_flags(F))
     d = _dict(torch, s)
     _say("mol96: GPU forward + backward (mixed)")
     e, U, X, st = ctx.forward([d])
     g = ctx.backward([list(s.nocc)])[0]
     vs = [_host(v) for v in d["vsic"]]
-    assert st["max_relres"] <= 1e-10
+    assert st["max_relres"] <= TOL
     d_half = _dict(torch, s)
     ctx.set_opts(vsic_scale=0.5)
     e_half = ctx.forward([d_half])[0]
@@ -123,7 +126,7 @@ def test_mol128_forces_vs_central_differences(torch_cuda, F, oracle):
     torch = torch_cuda
     _say("mol128: generate")
     s = synth.make_workload("mol128", device="cuda")
-    ctx = F.Context(precision="mixed", tol=1e-10)
+    ctx = F.Context(precision="mixed", tol=TOL)
     fods = [torch.tensor(f, requires_grad=True) for f in s.fod]
     _say("mol128: autograd forward + backward (mixed)")
     E, *_ = F.flosic_sic(ctx, s.n, s.h, s.origin, list(s.psi), fods)
@@ -160,17 +163,17 @@ def test_batch24_uneven_systems(torch_cuda, F, oracle):
     specs = synth.batch24_specs()
     _say("batch24: generate 24 systems")
     systems = synth.make_batch24(device="cuda")
-    ctx = F.Context(precision="mixed", tol=1e-10, flags=_flags(F))
+    ctx = F.Context(precision="mixed", tol=TOL, flags=_flags(F))
     dicts = [_dict(torch, s) for s in systems]
     _say("batch24: one batched forward + backward")
     e, U, X, st = ctx.forward(dicts)
     assert st["nsolves"] == sum(sum(s.nocc) for s in systems)
-    assert st["max_relres"] <= 1e-10
+    assert st["max_relres"] <= TOL
     gb = ctx.backward([list(s.nocc) for s in systems])
     ctx.close()
 
     _say("batch24: each system alone (FP64)")
-    single = F.Context(precision="fp64", tol=1e-10, flags=_flags(F))
+    single = F.Context(precision="fp64", tol=TOL, flags=_flags(F))
     for k, s in enumerate(systems):
         ek = single.forward([_dict(torch, s)])[0][0]
         gk = single.backward([list(s.nocc)])[0]

@@ -84,19 +84,23 @@ def test_invsqrt(torch_cuda, F, N):
     assert np.abs(Z @ S @ Z - np.eye(N)).max() < 1e-11 * np.linalg.cond(S)
 
 
-@pytest.mark.parametrize("n,h,precision", [(40, 0.3, "fp64"), (33, 0.25, "fp64"), (40, 0.3, "mixed")])
-def test_poisson_vs_oracle(torch_cuda, F, oracle, n, h, precision):
+@pytest.mark.parametrize("n,h,precision,solver", [(40, 0.3, "fp64", "cg"), (33, 0.25, "fp64", "cg"),
+                                                   (40, 0.3, "mixed", "cg"), (40, 0.3, "fp64", "pcg"),
+                                                   (33, 0.25, "fp64", "pcg"), (40, 0.3, "mixed", "pcg")])
+def test_poisson_vs_oracle(torch_cuda, F, oracle, n, h, precision, solver):
     torch = torch_cuda
-    _say(f"poisson n={n} h={h} {precision}")
+    _say(f"poisson n={n} h={h} {precision} {solver}")
     origin = np.full(3, -h * (n - 1) / 2)
     rhos = [synth.gaussian_charge(n, h, 0.8, centre=(0.5, -0.3, 0.2)),
             synth.gaussian_charge(n, h, 0.6, centre=(-1.0, 0.7, -0.4))
             + 0.3 * synth.gaussian_charge(n, h, 1.1, centre=(1.2, 0.0, 0.9))]
     rho = np.stack([r.reshape(-1) for r in rhos])
     v, it, rr = F.op_poisson(torch.tensor(rho, device="cuda"), (n, n, n), h, origin, tol=1e-12,
-                             precision=precision)
+                             precision=precision, solver=solver)
     v = v.cpu().numpy()
     assert np.all(rr <= 1e-12), rr
+    if solver == "pcg":
+        assert np.all(it < 40), it  # the spectral preconditioner leaves only the face corrections
     for f in range(2):
         ref, _, _ = oracle.poisson(rho[f], (n, n, n), h, origin)
         # |dv| <= ||K^{-1}|| ||r||: relative 1e-12 residual leaves ~1e-10 in v
@@ -104,6 +108,25 @@ def test_poisson_vs_oracle(torch_cuda, F, oracle, n, h, precision):
         U = 0.5 * h ** 3 * rho[f] @ v[f]
         Uref = 0.5 * h ** 3 * rho[f] @ ref
         assert abs(U - Uref) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_non_cubic_grid(torch_cuda, F, oracle, precision):
+    """Preconditioned solve on a box with a different node count per axis
+    (ragged 16-row tiles of every sine transform), against the oracle."""
+    torch = torch_cuda
+    _say(f"pcg non-cubic {precision}")
+    n, h = (37, 29, 45), 0.28
+    origin = np.array([-h * (m - 1) / 2 for m in n])
+    axes = [origin[d] + h * np.arange(n[d]) for d in range(3)]
+    r2 = ((axes[2][:, None, None] - 0.3) ** 2 + (axes[1][None, :, None] + 0.2) ** 2
+          + (axes[0][None, None, :] - 0.5) ** 2)
+    rho = (np.exp(-r2 / (2 * 0.7 ** 2)) + 0.2 * np.exp(-r2 / 3.0)).reshape(1, -1)
+    v, it, rr = F.op_poisson(torch.tensor(rho, device="cuda"), n, h, origin, tol=1e-12,
+                             precision=precision, solver="pcg")
+    assert rr[0] <= 1e-12 and it[0] < 40, (rr, it)
+    ref, _, _ = oracle.poisson(rho[0], n, h, origin)
+    assert np.abs(v.cpu().numpy()[0] - ref).max() < 1e-9 * np.abs(ref).max()
 
 
 def test_poisson_gaussian_closed_form(torch_cuda, F):
