@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_dst_pass(const Item *items, const OrbDe
     if (cnt && it.tile == 0 && threadIdx.x == 0) cnt[it.orb] += 1;
     const OrbDesc od = orb[it.orb];
     const int n = axis_n(od, AX);
-    const int np = (n + 15) & ~15;
+    const int np = (n + 31) & ~31;
     const long long plane = (long long)od.nx * od.ny;
     const float *S = tab + od.dst_s[AX];  // np x np, zero beyond n
     const int t = threadIdx.x;
@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void k_dst_pass(const Item *items, const OrbDe
     const int nrt = np >> 4;
     const int r0 = w >> 1;
     constexpr int MT = 8;  // up to 8 row tiles per wave (np <= 256)
+    if (np > 256) return;  // the host routes such grids to plain CG
     flt4 acc[MT];
 #pragma unroll
     for (int i = 0; i < MT; ++i) acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
@@ -201,6 +202,230 @@ __global__ __launch_bounds__(256) void k_dst_pass(const Item *items, const OrbDe
     }
 }
 
+// ---------------------------------------------------------------------------
+// fast pass (axes of at most 128 nodes): bf16 matrix cores with split operands
+// ---------------------------------------------------------------------------
+//
+// Each fp32 operand is split into bf16 hi + lo (lo = x - hi), and
+// S X ~ S_hi X_hi + S_hi X_lo + S_lo X_hi on v_mfma_f32_16x16x32_bf16 with
+// fp32 accumulation, which keeps about 16 significant bits (the dropped
+// S_lo X_lo term is ~2^-16 relative): the preconditioner then behaves as in
+// fp32 while the matrix cores do five times less work.  A 1024-thread block
+// keeps S (hi, lo) of its axis in LDS and streams G panels of 128 columns:
+// the next panel's loads are in flight while the current one is multiplied.
+// Operand layouts: A lane l holds S[m0 + l%16][k0 + 8(l/16) .. +7], B lane l
+// holds X[k0 + 8(l/16) .. +7][c0 + l%16] (the panel is stored transposed,
+// Xt[c][k], so both are one 16-byte LDS read), and D lane l, item j is
+// C[m0 + 4(l/16) + j][c0 + l%16].
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+
+constexpr int kFC = kDstFastCols;    // panel columns
+constexpr int kFT = 1024;   // threads per block
+constexpr int kFG = kDstFastGroup;   // panels per block
+
+__device__ __forceinline__ void bsplit(float x, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+// fixed-order sum over the 16 waves of a 1024-thread block (all threads get it)
+__device__ __forceinline__ double block_sum1024(double v, double *sbuf) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sbuf[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += sbuf[i];
+    return s;
+}
+
+size_t dst_fast_lds(int np) {
+    const int sw = np + 8;
+    return (size_t)2 * np * sw * 2 + (size_t)2 * kFC * sw * 2 + 16 * sizeof(double);
+}
+
+template <int AX, int MODE, typename TIN, typename TR, bool RZ>
+__global__ __launch_bounds__(kFT) void k_dst_fast(const Item *items, const OrbDesc *orb,
+                                                  const int *done, const float *tab, const TIN *in,
+                                                  float *out, const TR *rres, double *rz, int *cnt) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const Item it = items[blockIdx.x];
+    if (it.orb < 0) return;
+    if (done[it.orb]) return;
+    if (cnt && it.tile == 0 && threadIdx.x == 0) cnt[it.orb] += 1;
+    const OrbDesc od = orb[it.orb];
+    const int n = axis_n(od, AX);
+    const int np = (n + 31) & ~31;
+    if (np > 128) return;  // the host routes such grids to the fp32 pass
+    const int sw = np + 8;  // LDS row stride (bf16): 16-byte rows
+    __bf16 *Shi = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *Slo = Shi + (size_t)np * sw;
+    __bf16 *Xhi = Slo + (size_t)np * sw;
+    __bf16 *Xlo = Xhi + (size_t)kFC * sw;
+    double *sred = reinterpret_cast<double *>(Xlo + (size_t)kFC * sw);
+    const int t = threadIdx.x;
+    const long long plane = (long long)od.nx * od.ny;
+    // matrix view: column cg of ncol, element k at eoff(cg) + k * kstr
+    const long long ncol = AX == 0 ? (long long)od.ny * od.nz
+                         : (AX == 1 ? (long long)od.nx * od.nz : plane);
+    const long long kstr = AX == 0 ? 1 : (AX == 1 ? od.nx : plane);
+    auto eoff = [&](long long cg) -> long long {
+        if (AX == 0) return cg * od.nx;
+        if (AX == 1) {
+            const long long z = cg / od.nx;
+            return z * plane + (cg - z * od.nx);
+        }
+        return cg;
+    };
+
+    // stage S (hi, lo), zero beyond n (the table is zero there)
+    {
+        const float *S = tab + od.dst_s[AX];
+        for (int e = t; e < np * np; e += kFT) {
+            const int m = e / np, k = e - m * np;
+            __bf16 hi, lo;
+            bsplit(S[e], hi, lo);
+            Shi[m * sw + k] = hi;
+            Slo[m * sw + k] = lo;
+        }
+    }
+
+    // panel loads: thread t holds column c, rows k = 2 kg + 16 i (+1)
+    const int c_ld = AX == 0 ? (t >> 3) : (t & (kFC - 1));
+    const int kg = AX == 0 ? (t & 7) : (t >> 7);
+    const int npair = np >> 4;  // pairs per thread
+    float vreg[16];             // 2 * npair <= 16
+    const TIN *src = in + od.off;
+    auto load = [&](int pnl) {
+        const long long cg = (long long)pnl * kFC + c_ld;
+        const bool cv = cg < ncol;
+        const long long base = cv ? eoff(cg) : 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i < npair) {
+                const int k = 2 * kg + 16 * i;
+                vreg[2 * i] = (cv && k < n) ? (float)src[base + (long long)k * kstr] : 0.f;
+                vreg[2 * i + 1] = (cv && k + 1 < n) ? (float)src[base + (long long)(k + 1) * kstr] : 0.f;
+            }
+        }
+    };
+    auto to_lds = [&]() {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i < npair) {
+                const int k = 2 * kg + 16 * i;
+                __bf16 h0, l0, h1, l1;
+                bsplit(vreg[2 * i], h0, l0);
+                bsplit(vreg[2 * i + 1], h1, l1);
+                *reinterpret_cast<bf2 *>(Xhi + c_ld * sw + k) = bf2{h0, h1};
+                *reinterpret_cast<bf2 *>(Xlo + c_ld * sw + k) = bf2{l0, l1};
+            }
+        }
+    };
+
+    // wave tiling: column tile w & 7, row tiles (w >> 3) + 2 i
+    const int lane = t & 63, w = t >> 6;
+    const int ct = w & 7, r0 = w >> 3;
+    const int nrt = np >> 4;
+    const int lr = lane & 15, lq = lane >> 4;
+    flt4 acc[4];
+    auto gemm = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < np; k0 += 32) {
+            const int kb = k0 + 8 * lq;
+            const bf8 bh = *reinterpret_cast<const bf8 *>(Xhi + (ct * 16 + lr) * sw + kb);
+            const bf8 bl = *reinterpret_cast<const bf8 *>(Xlo + (ct * 16 + lr) * sw + kb);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int rt = r0 + 2 * i;
+                if (rt < nrt) {
+                    const bf8 ah = *reinterpret_cast<const bf8 *>(Shi + (rt * 16 + lr) * sw + kb);
+                    const bf8 al = *reinterpret_cast<const bf8 *>(Slo + (rt * 16 + lr) * sw + kb);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i], 0, 0, 0);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i], 0, 0, 0);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    float *dst = out + od.off;
+    double part = 0.0;
+    const int npanel = (int)((ncol + kFC - 1) / kFC);
+    const int p0 = it.tile * kFG, p1 = min(npanel, p0 + kFG);
+    load(p0);
+    for (int pnl = p0; pnl < p1; ++pnl) {
+        __syncthreads();  // the previous panel's products are done with Xt
+        to_lds();
+        __syncthreads();
+        if (pnl + 1 < p1) load(pnl + 1);  // in flight during the products
+        gemm();
+        const int c = ct * 16 + lr;
+        const long long cg = (long long)pnl * kFC + c;
+        const bool cv = cg < ncol;
+        if (MODE == 1) {
+            // scale by norm / lambda(jx, jy, m) and transform again
+            const float *gx = tab + od.dst_g[0], *gy = tab + od.dst_g[1], *gz = tab + od.dst_g[2];
+            const float norm = 8.f / ((float)(od.nx + 1) * (float)(od.ny + 1) * (float)(od.nz + 1));
+            const float ih2 = (float)od.inv_h2;
+            const int jy = cv ? (int)(cg / od.nx) : 0, jx = cv ? (int)(cg - (long long)jy * od.nx) : 0;
+            const float gxy = cv ? gx[jx] + gy[jy] : 1.f;
+            __syncthreads();  // every wave is done reading Xt
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int rt = r0 + 2 * i;
+                if (rt < nrt) {
+                    const int m0 = rt * 16 + 4 * lq;
+                    __bf16 hh[4], ll[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int m = m0 + j;
+                        const float v = (cv && m < n) ? acc[i][j] * (norm / ((gxy + gz[m]) * ih2)) : 0.f;
+                        bsplit(v, hh[j], ll[j]);
+                    }
+                    *reinterpret_cast<bf4 *>(Xhi + c * sw + m0) = bf4{hh[0], hh[1], hh[2], hh[3]};
+                    *reinterpret_cast<bf4 *>(Xlo + c * sw + m0) = bf4{ll[0], ll[1], ll[2], ll[3]};
+                }
+            }
+            __syncthreads();
+            gemm();
+        }
+        if (cv) {
+            const long long eo = eoff(cg);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int rt = r0 + 2 * i;
+                if (rt < nrt) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int m = rt * 16 + 4 * lq + j;
+                        if (m < n) {
+                            const long long a = eo + (long long)m * kstr;
+                            dst[a] = acc[i][j];
+                            if (RZ) part += (double)rres[od.off + a] * (double)acc[i][j];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (RZ) {
+        const double s = block_sum1024(part, sred);
+        if (t == 0) rz[od.base9 + it.tile] = s;
+    }
+}
+
+template <class K>
+void set_lds_limit(K kern, size_t bytes) {
+    if (bytes > 65536) hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 // z = M^{-1} r for the orbitals of the batch, with r.z partial sums.
 template <typename T>
 hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int *done,
@@ -211,6 +436,24 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
     const T *nr = nullptr;
     double *nd = nullptr;
     int *nc = nullptr;
+    if (di.fast) {
+        const size_t lds = dst_fast_lds(di.np);
+        set_lds_limit(k_dst_fast<0, 0, T, T, false>, lds);
+        set_lds_limit(k_dst_fast<1, 0, float, T, false>, lds);
+        set_lds_limit(k_dst_fast<2, 1, float, T, false>, lds);
+        set_lds_limit(k_dst_fast<0, 0, float, T, true>, lds);
+        hipLaunchKernelGGL((k_dst_fast<0, 0, T, T, false>), dim3(di.nx), dim3(kFT), lds, s, di.x, orb,
+                           done, tab, r, work, nr, nd, cnt);
+        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false>), dim3(di.ny), dim3(kFT), lds, s, di.y,
+                           orb, done, tab, wk, work, nr, nd, nc);
+        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, false>), dim3(di.nz), dim3(kFT), lds, s, di.z,
+                           orb, done, tab, wk, work, nr, nd, nc);
+        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false>), dim3(di.ny), dim3(kFT), lds, s, di.y,
+                           orb, done, tab, wk, work, nr, nd, nc);
+        hipLaunchKernelGGL((k_dst_fast<0, 0, float, T, true>), dim3(di.nx), dim3(kFT), lds, s, di.x,
+                           orb, done, tab, wk, z, r, rz, nc);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_dst_pass<0, 0, T, T, false>), dim3(di.nx), dim3(256), 0, s, di.x, orb,
                        done, tab, r, work, nr, nd, cnt);
     hipLaunchKernelGGL((k_dst_pass<1, 0, float, T, false>), dim3(di.ny), dim3(256), 0, s, di.y,

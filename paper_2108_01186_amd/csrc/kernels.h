@@ -101,6 +101,9 @@ hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *pa
 // dst.hip: spectral (type-I sine transform) preconditioner
 // ----------------------------------------------------------------------------
 
+// LDS bytes of a fast transform block for axes padded to np (<= 128) nodes.
+size_t dst_fast_lds(int np);
+
 // z = M^{-1} r (float) for the orbitals of the work lists with done == 0,
 // through the float work array; r.z partial sums into rz[base9 + panel].
 // tab: sine matrices and eigenvalue symbols (offsets in OrbDesc); cnt (may

@@ -158,6 +158,7 @@ struct Batch {
     std::vector<float> dtab;
     int tot9 = 0;
     int max_n = 0;
+    bool dst_fast = false;
 };
 
 void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<Item> &out) {
@@ -319,18 +320,30 @@ struct Group {
     int chan;
 };
 
+// LDS bytes one workgroup may use on the current device
+size_t device_lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    return (size_t)v;
+}
+
 void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, Batch &b) {
     const int cpt = sh.cpt;
     b = Batch{};
     long long cols = 0;
     for (const Group &g : groups)
         cols += (long long)g.count * ((g.n[0] + kTX - 1) / kTX) * ((g.n[1] + 8 * cpt - 1) / (8 * cpt));
+    for (const Group &g : groups)
+        for (int d = 0; d < 3; ++d) b.max_n = std::max(b.max_n, g.n[d]);
+    const bool fast = b.max_n <= 128 && dst_fast_lds((b.max_n + 31) & ~31) <= device_lds_limit();
+    b.dst_fast = fast;
     std::vector<std::pair<int, int>> nat7, nat8, natx, naty, natz;
     std::map<int, std::pair<int, int>> dst_done;  // n -> (sine offset, symbol offset)
     auto dst_entry = [&](Batch &bb, int n, int radius_) -> const std::pair<int, int> & {
         auto f = dst_done.find(n);
         if (f != dst_done.end()) return f->second;
-        const int np = (n + 15) & ~15;
+        const int np = (n + 31) & ~31;
         const int so = (int)bb.dtab.size();
         bb.dtab.resize(bb.dtab.size() + (size_t)np * np, 0.f);
         const long double pi = 3.141592653589793238462643383279502884L;
@@ -377,23 +390,28 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
                 od.centre[d] = g.origin[d] + 0.5 * g.h * (g.n[d] - 1);
             }
             od.chan = g.chan;
-            od.nt9 = (int)(((long long)g.n[1] * g.n[2] + 31) / 32);
+            // preconditioner panels: 128 columns, 2 per item (fast) or 32, 1
+            auto nitem = [&](long long ncol) {
+                if (!fast) return (int)((ncol + 31) / 32);
+                const long long np_ = (ncol + kDstFastCols - 1) / kDstFastCols;
+                return (int)((np_ + kDstFastGroup - 1) / kDstFastGroup);
+            };
+            od.nt9 = nitem((long long)g.n[1] * g.n[2]);
             od.base9 = b.tot9;
             b.tot9 += od.nt9;
             for (int d = 0; d < 3; ++d) {
                 const auto &e = dst_entry(b, g.n[d], radius);
                 od.dst_s[d] = e.first;
                 od.dst_g[d] = e.second;
-                b.max_n = std::max(b.max_n, g.n[d]);
             }
             const int o = (int)b.orb.size();
             b.orb.push_back(od);
             for (int t = 0; t < od.nt7; ++t) nat7.push_back({o, t});
             for (int t = 0; t < od.nt8; ++t) nat8.push_back({o, t});
             for (int t = 0; t < od.nt9; ++t) natx.push_back({o, t});
-            const int ny_t = g.n[2] * ((g.n[0] + 31) / 32);
+            const int ny_t = fast ? nitem((long long)g.n[0] * g.n[2]) : g.n[2] * ((g.n[0] + 31) / 32);
             for (int t = 0; t < ny_t; ++t) naty.push_back({o, t});
-            const int nz_t = (int)(((long long)g.n[0] * g.n[1] + 31) / 32);
+            const int nz_t = nitem((long long)g.n[0] * g.n[1]);
             for (int t = 0; t < nz_t; ++t) natz.push_back({o, t});
             b.fields = std::max(b.fields, od.off + M);
         }
@@ -690,7 +708,8 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
 #define PROF_END() \
     if (_sp) HIPCHK(c, hipEventRecord(_eb, s));
     const bool pcg = use_pcg(c, b);
-    DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(), (int)b.dz.size()};
+    DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(),
+                (int)b.dz.size(), b.dst_fast ? 1 : 0, (b.max_n + 31) & ~31};
     if (pcg && !mixed) {
         // FP64 CG preconditioned by the FP32 sine-transform inverse
         CGIter<double> a{};

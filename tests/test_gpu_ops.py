@@ -110,13 +110,15 @@ def test_poisson_vs_oracle(torch_cuda, F, oracle, n, h, precision, solver):
         assert abs(U - Uref) < 1e-10
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_pcg_non_cubic_grid(torch_cuda, F, oracle, precision):
+@pytest.mark.parametrize("precision,n", [("fp64", (37, 29, 45)), ("mixed", (37, 29, 45)),
+                                         ("fp64", (136, 21, 18)), ("mixed", (19, 150, 17))])
+def test_pcg_non_cubic_grid(torch_cuda, F, oracle, precision, n):
     """Preconditioned solve on a box with a different node count per axis
-    (ragged 16-row tiles of every sine transform), against the oracle."""
+    (ragged tiles of every sine transform), against the oracle; an axis above
+    128 nodes takes the fp32 transform kernels instead of the split-bf16 ones."""
     torch = torch_cuda
-    _say(f"pcg non-cubic {precision}")
-    n, h = (37, 29, 45), 0.28
+    _say(f"pcg non-cubic {precision} {n}")
+    h = 0.28
     origin = np.array([-h * (m - 1) / 2 for m in n])
     axes = [origin[d] + h * np.arange(n[d]) for d in range(3)]
     r2 = ((axes[2][:, None, None] - 0.3) ** 2 + (axes[1][None, :, None] + 0.2) ** 2
