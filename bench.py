@@ -176,7 +176,7 @@ def kernel_rates(agg):
 KERNEL_NAMES = {
     "sweep": "k_zmarch (CG stencil sweep: p, q = -L p, p.q)",
     "update": "k_pcg_update / k_cg_update (x += alpha p, r -= alpha q)",
-    "precond": "k_dst_pass x5 (sine-transform preconditioner, FP32 MFMA)",
+    "precond": "k_dst_fast x5 (sine-transform preconditioner, split-bf16 MFMA; k_dst_pass above 128 nodes)",
 }
 
 

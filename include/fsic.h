@@ -91,6 +91,9 @@ enum { FSIC_CG = 0, FSIC_PCG = 1 };
 #define FSIC_KEEP_TAPE       2u  /* keep what fsic_backward needs */
 #define FSIC_ALLOW_NONORTHO  4u  /* accept non-orthonormal psi (S = T G T^T is exact anyway) */
 #define FSIC_PROFILE         8u  /* time sampled CG launches with HIP events (fsic_stats.sweep_*) */
+#define FSIC_FP32_ORBITALS  16u  /* Fermi-Loewdin orbitals phi = (Z T) psi from an fp32 GEMM on the
+                                    matrix cores (fp32 operands and accumulation); costs about 1e-7
+                                    relative in phi, more than the 1e-8 Ha energy budget allows */
 
 typedef struct {
     int32_t n[3];       /* nodes per axis, each >= 8 */
@@ -108,7 +111,8 @@ typedef struct {
     double  vsic_scale; /* s: scales V_SIC only, never E_SIC or the gradient */
     double  rho_floor;  /* densities <= floor give zero XC and zero V_SIC; FOD vacuum test */
     double  s_eig_floor;/* smallest admissible eigenvalue of the FO overlap S */
-    uint32_t flags;     /* FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE */
+    uint32_t flags;     /* FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE |
+                           FSIC_FP32_ORBITALS */
 } fsic_opts;
 
 /* One system: up to two spin channels on one grid. */

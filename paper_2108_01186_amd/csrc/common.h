@@ -50,16 +50,16 @@ struct Item {
     int orb, tile;
 };
 // Work lists of the three spectral-preconditioner passes (see dst.hip);
-// fast: every axis has at most 128 nodes (bf16 split-operand kernels with
-// panels of 128 columns, 2 panels per item), np: largest axis padded to 32.
+// fast: every axis has at most 128 nodes (persistent bf16 split-operand
+// kernels over units of one 128-column panel, `blocks` blocks per pass), np:
+// largest axis padded to 32.
 struct DstItems {
     const Item *x, *y, *z;
     int nx, ny, nz;
-    int fast, np;
+    int fast, np, blocks;
 };
 
 constexpr int kDstFastCols = 128;   // panel columns of the fast transform kernels
-constexpr int kDstFastGroup = 2;    // panels per block of the fast transform kernels
 
 struct Coeffs {
     double c[kMaxRadius + 1];  // unit-spacing second-difference weights

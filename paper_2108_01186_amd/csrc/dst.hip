@@ -19,6 +19,8 @@
 // small L2-resident table.  Passes work in place on a float work array; the
 // first reads the CG residual (float or double) and the last writes the
 // preconditioned residual z and the partial sums of r.z.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace fsic {
@@ -210,9 +212,11 @@ __global__ __launch_bounds__(256) void k_dst_pass(const Item *items, const OrbDe
 // S X ~ S_hi X_hi + S_hi X_lo + S_lo X_hi on v_mfma_f32_16x16x32_bf16 with
 // fp32 accumulation, which keeps about 16 significant bits (the dropped
 // S_lo X_lo term is ~2^-16 relative): the preconditioner then behaves as in
-// fp32 while the matrix cores do five times less work.  A 1024-thread block
-// keeps S (hi, lo) of its axis in LDS and streams G panels of 128 columns:
-// the next panel's loads are in flight while the current one is multiplied.
+// fp32 while the matrix cores do five times less work.  A persistent
+// 1024-thread block streams a contiguous range of (orbital, 128-column panel)
+// units: S (hi, lo) of the current axis length stays in LDS (restaged only
+// when the length changes) and the next unit's loads are in flight while the
+// current panel is multiplied.
 // Operand layouts: A lane l holds S[m0 + l%16][k0 + 8(l/16) .. +7], B lane l
 // holds X[k0 + 8(l/16) .. +7][c0 + l%16] (the panel is stored transposed,
 // Xt[c][k], so both are one 16-byte LDS read), and D lane l, item j is
@@ -224,7 +228,6 @@ typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 constexpr int kFC = kDstFastCols;    // panel columns
 constexpr int kFT = 1024;   // threads per block
-constexpr int kFG = kDstFastGroup;   // panels per block
 
 __device__ __forceinline__ void bsplit(float x, __bf16 &hi, __bf16 &lo) {
     hi = (__bf16)x;
@@ -250,71 +253,64 @@ size_t dst_fast_lds(int np) {
 }
 
 template <int AX, int MODE, typename TIN, typename TR, bool RZ>
-__global__ __launch_bounds__(kFT) void k_dst_fast(const Item *items, const OrbDesc *orb,
-                                                  const int *done, const float *tab, const TIN *in,
-                                                  float *out, const TR *rres, double *rz, int *cnt) {
+__global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits, int npmax,
+                                                  const OrbDesc *orb, const int *done,
+                                                  const float *tab, const TIN *in, float *out,
+                                                  const TR *rres, double *rz, int *cnt) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const Item it = items[blockIdx.x];
-    if (it.orb < 0) return;
-    if (done[it.orb]) return;
-    if (cnt && it.tile == 0 && threadIdx.x == 0) cnt[it.orb] += 1;
-    const OrbDesc od = orb[it.orb];
-    const int n = axis_n(od, AX);
-    const int np = (n + 31) & ~31;
-    if (np > 128) return;  // the host routes such grids to the fp32 pass
-    const int sw = np + 8;  // LDS row stride (bf16): 16-byte rows
+    // persistent: block b streams the units [u0, u1) (unit = orbital, panel);
+    // the LDS layout is sized for the largest axis of the batch
+    const int sw = npmax + 8;  // LDS row stride (bf16): 16-byte rows
     __bf16 *Shi = reinterpret_cast<__bf16 *>(smem);
-    __bf16 *Slo = Shi + (size_t)np * sw;
-    __bf16 *Xhi = Slo + (size_t)np * sw;
+    __bf16 *Slo = Shi + (size_t)npmax * sw;
+    __bf16 *Xhi = Slo + (size_t)npmax * sw;
     __bf16 *Xlo = Xhi + (size_t)kFC * sw;
     double *sred = reinterpret_cast<double *>(Xlo + (size_t)kFC * sw);
     const int t = threadIdx.x;
-    const long long plane = (long long)od.nx * od.ny;
-    // matrix view: column cg of ncol, element k at eoff(cg) + k * kstr
-    const long long ncol = AX == 0 ? (long long)od.ny * od.nz
-                         : (AX == 1 ? (long long)od.nx * od.nz : plane);
-    const long long kstr = AX == 0 ? 1 : (AX == 1 ? od.nx : plane);
-    auto eoff = [&](long long cg) -> long long {
+    const int u0 = (int)((long long)blockIdx.x * nunits / gridDim.x);
+    const int u1 = (int)((long long)(blockIdx.x + 1) * nunits / gridDim.x);
+    auto next_active = [&](int u) {  // done[] does not change during this launch: uniform
+        while (u < u1 && (units[u].orb < 0 || done[units[u].orb])) ++u;
+        return u;
+    };
+
+    // matrix view of an orbital's field along AX: column cg of ncol,
+    // element k at eoff(cg) + k * kstr
+    auto ncol_of = [&](const OrbDesc &od) -> long long {
+        return AX == 0 ? (long long)od.ny * od.nz
+                       : (AX == 1 ? (long long)od.nx * od.nz : (long long)od.nx * od.ny);
+    };
+    auto kstr_of = [&](const OrbDesc &od) -> long long {
+        return AX == 0 ? 1 : (AX == 1 ? (long long)od.nx : (long long)od.nx * od.ny);
+    };
+    auto eoff = [&](const OrbDesc &od, long long cg) -> long long {
         if (AX == 0) return cg * od.nx;
         if (AX == 1) {
             const long long z = cg / od.nx;
-            return z * plane + (cg - z * od.nx);
+            return z * ((long long)od.nx * od.ny) + (cg - z * od.nx);
         }
         return cg;
     };
 
-    // stage S (hi, lo), zero beyond n (the table is zero there)
-    {
-        const float *S = tab + od.dst_s[AX];
-        for (int e = t; e < np * np; e += kFT) {
-            const int m = e / np, k = e - m * np;
-            __bf16 hi, lo;
-            bsplit(S[e], hi, lo);
-            Shi[m * sw + k] = hi;
-            Slo[m * sw + k] = lo;
-        }
-    }
-
-    // panel loads: thread t holds column c, rows k = 2 kg + 16 i (+1)
+    // panel loads: thread t holds column c_ld, rows k = 2 kg + 16 i (+1)
     const int c_ld = AX == 0 ? (t >> 3) : (t & (kFC - 1));
     const int kg = AX == 0 ? (t & 7) : (t >> 7);
-    const int npair = np >> 4;  // pairs per thread
-    float vreg[16];             // 2 * npair <= 16
-    const TIN *src = in + od.off;
-    auto load = [&](int pnl) {
+    float vreg[16];
+    auto load = [&](const OrbDesc &od, int pnl) {
+        const int n = axis_n(od, AX);
+        const int npair = ((n + 31) & ~31) >> 4;
         const long long cg = (long long)pnl * kFC + c_ld;
-        const bool cv = cg < ncol;
-        const long long base = cv ? eoff(cg) : 0;
+        const bool cv = cg < ncol_of(od);
+        const long long base = od.off + (cv ? eoff(od, cg) : 0);
+        const long long ks = kstr_of(od);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            if (i < npair) {
-                const int k = 2 * kg + 16 * i;
-                vreg[2 * i] = (cv && k < n) ? (float)src[base + (long long)k * kstr] : 0.f;
-                vreg[2 * i + 1] = (cv && k + 1 < n) ? (float)src[base + (long long)(k + 1) * kstr] : 0.f;
-            }
+            const int k = 2 * kg + 16 * i;
+            vreg[2 * i] = (i < npair && cv && k < n) ? (float)in[base + (long long)k * ks] : 0.f;
+            vreg[2 * i + 1] = (i < npair && cv && k + 1 < n) ? (float)in[base + (long long)(k + 1) * ks] : 0.f;
         }
     };
-    auto to_lds = [&]() {
+    auto to_lds = [&](int npair) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             if (i < npair) {
@@ -331,10 +327,10 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *items, const OrbDe
     // wave tiling: column tile w & 7, row tiles (w >> 3) + 2 i
     const int lane = t & 63, w = t >> 6;
     const int ct = w & 7, r0 = w >> 3;
-    const int nrt = np >> 4;
     const int lr = lane & 15, lq = lane >> 4;
     flt4 acc[4];
-    auto gemm = [&]() {
+    auto gemm = [&](int np) {
+        const int nrt = np >> 4;
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < np; k0 += 32) {
@@ -355,26 +351,47 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *items, const OrbDe
         }
     };
 
-    float *dst = out + od.off;
-    double part = 0.0;
-    const int npanel = (int)((ncol + kFC - 1) / kFC);
-    const int p0 = it.tile * kFG, p1 = min(npanel, p0 + kFG);
-    load(p0);
-    for (int pnl = p0; pnl < p1; ++pnl) {
-        __syncthreads();  // the previous panel's products are done with Xt
-        to_lds();
+    int u = next_active(u0);
+    if (u >= u1) return;
+    OrbDesc od = orb[units[u].orb];
+    load(od, units[u].tile);
+    int staged = -1;  // axis length whose sine matrix is in LDS
+    while (u < u1) {
+        const Item cur = units[u];
+        const OrbDesc oc = od;
+        const int n = axis_n(oc, AX);
+        const int np = (n + 31) & ~31;
+        const int un = next_active(u + 1);
+        if (cnt && cur.tile == 0 && t == 0) cnt[cur.orb] += 1;
+        __syncthreads();  // the previous unit's products are done with S and Xt
+        if (n != staged) {
+            const float *S = tab + oc.dst_s[AX];  // np x np, zero beyond n
+            for (int e = t; e < np * np; e += kFT) {
+                const int m = e / np, k = e - m * np;
+                __bf16 hi, lo;
+                bsplit(S[e], hi, lo);
+                Shi[m * sw + k] = hi;
+                Slo[m * sw + k] = lo;
+            }
+            staged = n;
+        }
+        to_lds(np >> 4);
         __syncthreads();
-        if (pnl + 1 < p1) load(pnl + 1);  // in flight during the products
-        gemm();
+        if (un < u1) {  // next unit's panel is in flight during the products
+            od = orb[units[un].orb];
+            load(od, units[un].tile);
+        }
+        gemm(np);
+        const int nrt = np >> 4;
         const int c = ct * 16 + lr;
-        const long long cg = (long long)pnl * kFC + c;
-        const bool cv = cg < ncol;
+        const long long cg = (long long)cur.tile * kFC + c;
+        const bool cv = cg < ncol_of(oc);
         if (MODE == 1) {
             // scale by norm / lambda(jx, jy, m) and transform again
-            const float *gx = tab + od.dst_g[0], *gy = tab + od.dst_g[1], *gz = tab + od.dst_g[2];
-            const float norm = 8.f / ((float)(od.nx + 1) * (float)(od.ny + 1) * (float)(od.nz + 1));
-            const float ih2 = (float)od.inv_h2;
-            const int jy = cv ? (int)(cg / od.nx) : 0, jx = cv ? (int)(cg - (long long)jy * od.nx) : 0;
+            const float *gx = tab + oc.dst_g[0], *gy = tab + oc.dst_g[1], *gz = tab + oc.dst_g[2];
+            const float norm = 8.f / ((float)(oc.nx + 1) * (float)(oc.ny + 1) * (float)(oc.nz + 1));
+            const float ih2 = (float)oc.inv_h2;
+            const int jy = cv ? (int)(cg / oc.nx) : 0, jx = cv ? (int)(cg - (long long)jy * oc.nx) : 0;
             const float gxy = cv ? gx[jx] + gy[jy] : 1.f;
             __syncthreads();  // every wave is done reading Xt
 #pragma unroll
@@ -394,10 +411,12 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *items, const OrbDe
                 }
             }
             __syncthreads();
-            gemm();
+            gemm(np);
         }
+        double part = 0.0;
         if (cv) {
-            const long long eo = eoff(cg);
+            const long long eo = oc.off + eoff(oc, cg);
+            const long long ks = kstr_of(oc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int rt = r0 + 2 * i;
@@ -406,18 +425,19 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *items, const OrbDe
                     for (int j = 0; j < 4; ++j) {
                         const int m = rt * 16 + 4 * lq + j;
                         if (m < n) {
-                            const long long a = eo + (long long)m * kstr;
-                            dst[a] = acc[i][j];
-                            if (RZ) part += (double)rres[od.off + a] * (double)acc[i][j];
+                            const long long a = eo + (long long)m * ks;
+                            out[a] = acc[i][j];
+                            if (RZ) part += (double)rres[a] * (double)acc[i][j];
                         }
                     }
                 }
             }
         }
-    }
-    if (RZ) {
-        const double s = block_sum1024(part, sred);
-        if (t == 0) rz[od.base9 + it.tile] = s;
+        if (RZ) {
+            const double sum = block_sum1024(part, sred);
+            if (t == 0) rz[oc.base9 + cur.tile] = sum;
+        }
+        u = un;
     }
 }
 
@@ -442,16 +462,17 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
         set_lds_limit(k_dst_fast<1, 0, float, T, false>, lds);
         set_lds_limit(k_dst_fast<2, 1, float, T, false>, lds);
         set_lds_limit(k_dst_fast<0, 0, float, T, true>, lds);
-        hipLaunchKernelGGL((k_dst_fast<0, 0, T, T, false>), dim3(di.nx), dim3(kFT), lds, s, di.x, orb,
-                           done, tab, r, work, nr, nd, cnt);
-        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false>), dim3(di.ny), dim3(kFT), lds, s, di.y,
-                           orb, done, tab, wk, work, nr, nd, nc);
-        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, false>), dim3(di.nz), dim3(kFT), lds, s, di.z,
-                           orb, done, tab, wk, work, nr, nd, nc);
-        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false>), dim3(di.ny), dim3(kFT), lds, s, di.y,
-                           orb, done, tab, wk, work, nr, nd, nc);
-        hipLaunchKernelGGL((k_dst_fast<0, 0, float, T, true>), dim3(di.nx), dim3(kFT), lds, s, di.x,
-                           orb, done, tab, wk, z, r, rz, nc);
+        auto grid = [&](int units) { return dim3((unsigned)std::min(units, di.blocks)); };
+        hipLaunchKernelGGL((k_dst_fast<0, 0, T, T, false>), grid(di.nx), dim3(kFT), lds, s, di.x,
+                           di.nx, di.np, orb, done, tab, r, work, nr, nd, cnt);
+        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false>), grid(di.ny), dim3(kFT), lds, s, di.y,
+                           di.ny, di.np, orb, done, tab, wk, work, nr, nd, nc);
+        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, false>), grid(di.nz), dim3(kFT), lds, s, di.z,
+                           di.nz, di.np, orb, done, tab, wk, work, nr, nd, nc);
+        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false>), grid(di.ny), dim3(kFT), lds, s, di.y,
+                           di.ny, di.np, orb, done, tab, wk, work, nr, nd, nc);
+        hipLaunchKernelGGL((k_dst_fast<0, 0, float, T, true>), grid(di.nx), dim3(kFT), lds, s, di.x,
+                           di.nx, di.np, orb, done, tab, wk, z, r, rz, nc);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_dst_pass<0, 0, T, T, false>), dim3(di.nx), dim3(256), 0, s, di.x, orb,

@@ -385,6 +385,57 @@ __global__ __launch_bounds__(256) void k_orb_gemm(int N, long long M, const doub
     }
 }
 
+// fp32 variant: A and psi rounded to fp32, products accumulated in fp32 on
+// v_mfma_f32_16x16x4f32 (D lane l, item j: row 4 (l/16) + j), out in fp64
+typedef float flt4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_orb_gemm32(int N, long long M, const double *A,
+                                                    const double *psi, double *out) {
+    const int Nt = (N + 15) >> 4;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kk = lane >> 4;
+    const long long nstrip = (M + 15) >> 4;
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwave = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long st = wave; st < nstrip; st += nwave) {
+        const long long m = st * 16 + row;
+        flt4 acc[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] = flt4{0.f, 0.f, 0.f, 0.f};
+        for (int a0 = 0; a0 < N; a0 += 4) {
+            const int a = a0 + kk;
+            const float b = (a < N && m < M) ? (float)psi[(long long)a * M + m] : 0.f;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t < Nt) {
+                    const int i = 16 * t + row;
+                    const float av = (i < N && a < N) ? (float)A[i * N + a] : 0.f;
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        const long long mo = st * 16 + row;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t < Nt && mo < M) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = 16 * t + 4 * kk + j;
+                    if (i < N) out[(long long)i * M + mo] = (double)acc[t][j];
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_orb_gemm32(int N, long long M, const double *A, const double *psi, double *out,
+                             hipStream_t s) {
+    const long long nstrip = (M + 15) / 16;
+    long long nblk = (nstrip + 3) / 4;
+    if (nblk > 8192) nblk = 8192;
+    hipLaunchKernelGGL(k_orb_gemm32, dim3((unsigned)nblk), dim3(256), 0, s, N, M, A, psi, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *psi, double *out,
                            hipStream_t s) {
     const long long nstrip = (M + 15) / 16;

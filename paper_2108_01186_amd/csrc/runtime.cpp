@@ -256,7 +256,7 @@ fsic_status validate_opts(const fsic_opts *o, std::string &why) {
     if (!std::isfinite(o->vsic_scale)) { why = "vsic_scale must be finite"; return FSIC_EINVAL; }
     if (!(o->rho_floor >= 0.0) || !std::isfinite(o->rho_floor)) { why = "rho_floor must be finite and >= 0"; return FSIC_EINVAL; }
     if (!(o->s_eig_floor > 0.0) || !std::isfinite(o->s_eig_floor)) { why = "s_eig_floor must be finite and > 0"; return FSIC_EINVAL; }
-    if (o->flags & ~(FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE)) { why = "unknown flag bits"; return FSIC_EINVAL; }
+    if (o->flags & ~(FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE | FSIC_FP32_ORBITALS)) { why = "unknown flag bits"; return FSIC_EINVAL; }
     return FSIC_OK;
 }
 
@@ -319,6 +319,16 @@ struct Group {
     long long off;  // field offset of the first orbital
     int chan;
 };
+
+// blocks of the persistent transform kernels: one per compute unit, or
+// FSIC_DST_BLOCKS
+int dst_blocks(const fsic_ctx *c) {
+    if (const char *e = getenv("FSIC_DST_BLOCKS")) return std::max(1, atoi(e));
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || v < 1)
+        v = 256;
+    return v;
+}
 
 // LDS bytes one workgroup may use on the current device
 size_t device_lds_limit() {
@@ -390,11 +400,10 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
                 od.centre[d] = g.origin[d] + 0.5 * g.h * (g.n[d] - 1);
             }
             od.chan = g.chan;
-            // preconditioner panels: 128 columns, 2 per item (fast) or 32, 1
+            // preconditioner units: panels of 128 columns (fast) or 32
             auto nitem = [&](long long ncol) {
-                if (!fast) return (int)((ncol + 31) / 32);
-                const long long np_ = (ncol + kDstFastCols - 1) / kDstFastCols;
-                return (int)((np_ + kDstFastGroup - 1) / kDstFastGroup);
+                const int pc = fast ? kDstFastCols : 32;
+                return (int)((ncol + pc - 1) / pc);
             };
             od.nt9 = nitem((long long)g.n[1] * g.n[2]);
             od.base9 = b.tot9;
@@ -418,9 +427,19 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     }
     build_items(nat7, b.items7);
     build_items(nat8, b.items8);
-    build_items(natx, b.dx);
-    build_items(naty, b.dy);
-    build_items(natz, b.dz);
+    if (fast) {
+        // persistent kernels take contiguous unit ranges: keep orbital order
+        // so one sine matrix serves a whole range
+        for (auto *pr : {&natx, &naty, &natz}) {
+            std::vector<Item> &dst = pr == &natx ? b.dx : (pr == &naty ? b.dy : b.dz);
+            dst.clear();
+            for (const auto &q : *pr) dst.push_back(Item{q.first, q.second});
+        }
+    } else {
+        build_items(natx, b.dx);
+        build_items(naty, b.dy);
+        build_items(natz, b.dz);
+    }
 }
 
 template <typename T>
@@ -709,7 +728,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     if (_sp) HIPCHK(c, hipEventRecord(_eb, s));
     const bool pcg = use_pcg(c, b);
     DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(),
-                (int)b.dz.size(), b.dst_fast ? 1 : 0, (b.max_n + 31) & ~31};
+                (int)b.dz.size(), b.dst_fast ? 1 : 0, (b.max_n + 31) & ~31, dst_blocks(c)};
     if (pcg && !mixed) {
         // FP64 CG preconditioned by the FP32 sine-transform inverse
         CGIter<double> a{};
@@ -1232,7 +1251,10 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     // phi = Q psi on the matrix cores
     for (int ci = 0; ci < nchan; ++ci) {
         const Chan &ch = chans[ci];
-        HIPCHK(c, launch_orb_gemm(ch.N, ch.M, c->small.p + ch.so + small_off(sQ), ch.psi, c->PHI.p + ch.off, s));
+        if (o.flags & FSIC_FP32_ORBITALS)
+            HIPCHK(c, launch_orb_gemm32(ch.N, ch.M, c->small.p + ch.so + small_off(sQ), ch.psi, c->PHI.p + ch.off, s));
+        else
+            HIPCHK(c, launch_orb_gemm(ch.N, ch.M, c->small.p + ch.so + small_off(sQ), ch.psi, c->PHI.p + ch.off, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
     const double t2 = now_ms();
