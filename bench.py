@@ -38,6 +38,8 @@ def parse():
                     help="pcg: CG with the sine-transform preconditioner; cg: plain CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="skip the unprofiled eager and graph-replay legs")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle solving in the CPU-baseline sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -261,6 +263,21 @@ def main():
         print(f"[bench] {leg}: {dt / args.steps * 1e3:.1f} ms/step, E_SIC={e[0]:.12f}",
               file=sys.stderr, flush=True)
 
+    # beside the profiled legs: the mixed leg without events, eager and with
+    # each chunk of CG iterations replayed as a captured HIP graph
+    extra = {}
+    if not args.no_graphs:
+        for name, fl in (("mixed_unprofiled_solves_per_s", F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE),
+                         ("mixed_graphs_solves_per_s",
+                          F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE | F.FSIC_GRAPHS)):
+            ctx = F.Context(precision="mixed", tol=args.tol, flags=fl, solver=args.solver)
+            for _ in range(args.warmup):
+                ctx.forward(dicts)
+                ctx.backward(noccs)
+            dt, _, _, agg = run_steps(F, torch, ctx, dicts, noccs, args.steps)
+            ctx.close()
+            extra[name] = agg["solves"] / dt
+
     mx = results["mixed"]
     steps = args.steps
     solves_per_step = mx["agg"]["solves"] / steps
@@ -294,6 +311,7 @@ def main():
         out["dE_mixed_vs_fp64"] = float(np.abs(mx["e"] - fp["e"]).max())
         out["dF_max_mixed_vs_fp64"] = float(np.abs(mx["g"] - fp["g"]).max())
         out["fp64_kernels"] = kernel_rates(fp["agg"])
+    out.update(extra)
     if args.copy_calibration > 0:
         copy_calibration(torch, args.copy_calibration)
     if not args.no_cpu_baseline:

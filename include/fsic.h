@@ -91,6 +91,9 @@ enum { FSIC_CG = 0, FSIC_PCG = 1 };
 #define FSIC_KEEP_TAPE       2u  /* keep what fsic_backward needs */
 #define FSIC_ALLOW_NONORTHO  4u  /* accept non-orthonormal psi (S = T G T^T is exact anyway) */
 #define FSIC_PROFILE         8u  /* time sampled CG launches with HIP events (fsic_stats.sweep_*) */
+#define FSIC_GRAPHS         32u  /* preconditioned solves: capture each chunk of CG iterations (with its
+                                    FP64 residual check) as a HIP graph once per batch layout and
+                                    replay it; ignored with FSIC_PROFILE */
 #define FSIC_FP32_ORBITALS  16u  /* Fermi-Loewdin orbitals phi = (Z T) psi from an fp32 GEMM on the
                                     matrix cores (fp32 operands and accumulation); costs about 1e-7
                                     relative in phi, more than the 1e-8 Ha energy budget allows */
@@ -112,7 +115,7 @@ typedef struct {
     double  rho_floor;  /* densities <= floor give zero XC and zero V_SIC; FOD vacuum test */
     double  s_eig_floor;/* smallest admissible eigenvalue of the FO overlap S */
     uint32_t flags;     /* FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE |
-                           FSIC_FP32_ORBITALS */
+                           FSIC_FP32_ORBITALS | FSIC_GRAPHS */
 } fsic_opts;
 
 /* One system: up to two spin channels on one grid. */

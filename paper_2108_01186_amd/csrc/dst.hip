@@ -213,10 +213,11 @@ __global__ __launch_bounds__(256) void k_dst_pass(const Item *items, const OrbDe
 // fp32 accumulation, which keeps about 16 significant bits (the dropped
 // S_lo X_lo term is ~2^-16 relative): the preconditioner then behaves as in
 // fp32 while the matrix cores do five times less work.  A persistent
-// 1024-thread block streams a contiguous range of (orbital, 128-column panel)
+// 512-thread block streams a contiguous range of (orbital, 128-column panel)
 // units: S (hi, lo) of the current axis length stays in LDS (restaged only
 // when the length changes) and the next unit's loads are in flight while the
-// current panel is multiplied.
+// current panel is multiplied (two register buffers: the loads of the unit
+// after next are issued once the current unit's values are in LDS).
 // Operand layouts: A lane l holds S[m0 + l%16][k0 + 8(l/16) .. +7], B lane l
 // holds X[k0 + 8(l/16) .. +7][c0 + l%16] (the panel is stored transposed,
 // Xt[c][k], so both are one 16-byte LDS read), and D lane l, item j is
@@ -227,15 +228,16 @@ typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 constexpr int kFC = kDstFastCols;    // panel columns
-constexpr int kFT = 1024;   // threads per block
+constexpr int kFT = 512;    // threads per block (8 waves, one column tile each)
+constexpr int kFV = kFC * 128 / kFT;  // panel values per thread and buffer (np <= 128): 32
 
 __device__ __forceinline__ void bsplit(float x, __bf16 &hi, __bf16 &lo) {
     hi = (__bf16)x;
     lo = (__bf16)(x - (float)hi);
 }
 
-// fixed-order sum over the 16 waves of a 1024-thread block (all threads get it)
-__device__ __forceinline__ double block_sum1024(double v, double *sbuf) {
+// fixed-order sum over the waves of a kFT-thread block (all threads get it)
+__device__ __forceinline__ double block_sum_fast(double v, double *sbuf) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
     __syncthreads();
@@ -243,13 +245,31 @@ __device__ __forceinline__ double block_sum1024(double v, double *sbuf) {
     __syncthreads();
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) s += sbuf[i];
+    for (int i = 0; i < kFT / 64; ++i) s += sbuf[i];
     return s;
 }
 
 size_t dst_fast_lds(int np) {
     const int sw = np + 8;
-    return (size_t)2 * np * sw * 2 + (size_t)2 * kFC * sw * 2 + 16 * sizeof(double);
+    return (size_t)2 * np * sw * 2 + (size_t)2 * kFC * sw * 2 + 16 * sizeof(double) +
+           (size_t)np * sizeof(float);
+}
+
+// 16-byte loads of four consecutive values as floats
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ float4 ld4(const double *p) {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    return float4{(float)a.x, (float)a.y, (float)b.x, (float)b.y};
+}
+__device__ __forceinline__ double dot4(const float *p, const float4 &v) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    return (double)a.x * v.x + (double)a.y * v.y + (double)a.z * v.z + (double)a.w * v.w;
+}
+__device__ __forceinline__ double dot4(const double *p, const float4 &v) {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    return a.x * v.x + a.y * v.y + b.x * v.z + b.y * v.w;
 }
 
 template <int AX, int MODE, typename TIN, typename TR, bool RZ>
@@ -265,7 +285,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
     __bf16 *Slo = Shi + (size_t)npmax * sw;
     __bf16 *Xhi = Slo + (size_t)npmax * sw;
     __bf16 *Xlo = Xhi + (size_t)kFC * sw;
-    double *sred = reinterpret_cast<double *>(Xlo + (size_t)kFC * sw);
+    double *sred = reinterpret_cast<double *>(Xlo + (size_t)kFC * sw);  // kFT / 64 doubles
     const int t = threadIdx.x;
     const int u0 = (int)((long long)blockIdx.x * nunits / gridDim.x);
     const int u1 = (int)((long long)(blockIdx.x + 1) * nunits / gridDim.x);
@@ -292,54 +312,87 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         return cg;
     };
 
-    // panel loads: thread t holds column c_ld, rows k = 2 kg + 16 i (+1)
-    const int c_ld = AX == 0 ? (t >> 3) : (t & (kFC - 1));
-    const int kg = AX == 0 ? (t & 7) : (t >> 7);
-    float vreg[16];
-    auto load = [&](const OrbDesc &od, int pnl) {
+    // x axis with nx and the orbital offset multiples of 4: rows go in and out
+    // as 16-byte vectors
+    auto xvec = [&](const OrbDesc &od) -> bool {
+        return AX == 0 && (od.nx & 3) == 0 && (od.off & 3) == 0;
+    };
+    // panel loads into v[kFV]: thread t holds column c_ld and, per i, either
+    // rows k = 2 kg + 8 i, k + 1 (pairs) or k = 4 kg + 16 i .. + 3 (x vectors)
+    const int c_ld = AX == 0 ? (t >> 2) : (t & (kFC - 1));
+    const int kg = AX == 0 ? (t & 3) : (t >> 7);
+    auto load = [&](float (&v)[kFV], const OrbDesc &od, int pnl) {
         const int n = axis_n(od, AX);
-        const int npair = ((n + 31) & ~31) >> 4;
+        const int np = (n + 31) & ~31;
         const long long cg = (long long)pnl * kFC + c_ld;
         const bool cv = cg < ncol_of(od);
         const long long base = od.off + (cv ? eoff(od, cg) : 0);
-        const long long ks = kstr_of(od);
+        if (xvec(od)) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = 2 * kg + 16 * i;
-            vreg[2 * i] = (i < npair && cv && k < n) ? (float)in[base + (long long)k * ks] : 0.f;
-            vreg[2 * i + 1] = (i < npair && cv && k + 1 < n) ? (float)in[base + (long long)(k + 1) * ks] : 0.f;
+            for (int i = 0; i < kFV / 4; ++i) {
+                const int k = 4 * kg + 16 * i;
+                const float4 q = (k < np && cv && k < n) ? ld4(in + base + k) : float4{0.f, 0.f, 0.f, 0.f};
+                v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
+            }
+            return;
+        }
+        const long long ks = kstr_of(od);
+        const int npair = np >> 3;
+#pragma unroll
+        for (int i = 0; i < kFV / 2; ++i) {
+            const int k = 2 * kg + 8 * i;
+            v[2 * i] = (i < npair && cv && k < n) ? (float)in[base + (long long)k * ks] : 0.f;
+            v[2 * i + 1] = (i < npair && cv && k + 1 < n) ? (float)in[base + (long long)(k + 1) * ks] : 0.f;
         }
     };
-    auto to_lds = [&](int npair) {
+    auto to_lds = [&](const float (&v)[kFV], const OrbDesc &od) {
+        const int np = (axis_n(od, AX) + 31) & ~31;
+        if (xvec(od)) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < kFV / 4; ++i) {
+                const int k = 4 * kg + 16 * i;
+                if (k < np) {
+                    __bf16 h[4], l[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bsplit(v[4 * i + j], h[j], l[j]);
+                    *reinterpret_cast<bf4 *>(Xhi + c_ld * sw + k) = bf4{h[0], h[1], h[2], h[3]};
+                    *reinterpret_cast<bf4 *>(Xlo + c_ld * sw + k) = bf4{l[0], l[1], l[2], l[3]};
+                }
+            }
+            return;
+        }
+        const int npair = np >> 3;
+#pragma unroll
+        for (int i = 0; i < kFV / 2; ++i) {
             if (i < npair) {
-                const int k = 2 * kg + 16 * i;
+                const int k = 2 * kg + 8 * i;
                 __bf16 h0, l0, h1, l1;
-                bsplit(vreg[2 * i], h0, l0);
-                bsplit(vreg[2 * i + 1], h1, l1);
+                bsplit(v[2 * i], h0, l0);
+                bsplit(v[2 * i + 1], h1, l1);
                 *reinterpret_cast<bf2 *>(Xhi + c_ld * sw + k) = bf2{h0, h1};
                 *reinterpret_cast<bf2 *>(Xlo + c_ld * sw + k) = bf2{l0, l1};
             }
         }
     };
 
-    // wave tiling: column tile w & 7, row tiles (w >> 3) + 2 i
+    // wave tiling: wave w owns column tile w and every row tile
     const int lane = t & 63, w = t >> 6;
-    const int ct = w & 7, r0 = w >> 3;
+    const int ct = w, r0 = 0;
+    constexpr int RS = 1;   // row-tile stride between the waves of a column tile
+    constexpr int MT = 8;   // row tiles per wave (np <= 128)
     const int lr = lane & 15, lq = lane >> 4;
-    flt4 acc[4];
+    flt4 acc[MT];
     auto gemm = [&](int np) {
         const int nrt = np >> 4;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < MT; ++i) acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < np; k0 += 32) {
             const int kb = k0 + 8 * lq;
             const bf8 bh = *reinterpret_cast<const bf8 *>(Xhi + (ct * 16 + lr) * sw + kb);
             const bf8 bl = *reinterpret_cast<const bf8 *>(Xlo + (ct * 16 + lr) * sw + kb);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int rt = r0 + 2 * i;
+            for (int i = 0; i < MT; ++i) {
+                const int rt = r0 + RS * i;
                 if (rt < nrt) {
                     const bf8 ah = *reinterpret_cast<const bf8 *>(Shi + (rt * 16 + lr) * sw + kb);
                     const bf8 al = *reinterpret_cast<const bf8 *>(Slo + (rt * 16 + lr) * sw + kb);
@@ -351,17 +404,15 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         }
     };
 
-    int u = next_active(u0);
-    if (u >= u1) return;
-    OrbDesc od = orb[units[u].orb];
-    load(od, units[u].tile);
+    float *gzs = reinterpret_cast<float *>(sred + 16);  // eigenvalue symbol of the staged z length
     int staged = -1;  // axis length whose sine matrix is in LDS
-    while (u < u1) {
+    // one unit: products of the panel held in v; the unit `pf` (or u1: none)
+    // is loaded into v once its values are in LDS
+    auto unit = [&](float (&v)[kFV], int u, OrbDesc &od, int pf) {
         const Item cur = units[u];
         const OrbDesc oc = od;
         const int n = axis_n(oc, AX);
         const int np = (n + 31) & ~31;
-        const int un = next_active(u + 1);
         if (cnt && cur.tile == 0 && t == 0) cnt[cur.orb] += 1;
         __syncthreads();  // the previous unit's products are done with S and Xt
         if (n != staged) {
@@ -373,13 +424,15 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
                 Shi[m * sw + k] = hi;
                 Slo[m * sw + k] = lo;
             }
+            if (MODE == 1)
+                for (int m = t; m < n; m += kFT) gzs[m] = tab[oc.dst_g[2] + m];
             staged = n;
         }
-        to_lds(np >> 4);
+        to_lds(v, oc);
         __syncthreads();
-        if (un < u1) {  // next unit's panel is in flight during the products
-            od = orb[units[un].orb];
-            load(od, units[un].tile);
+        if (pf < u1) {  // two units ahead: in flight during this unit and the next
+            od = orb[units[pf].orb];
+            load(v, od, units[pf].tile);
         }
         gemm(np);
         const int nrt = np >> 4;
@@ -388,23 +441,23 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         const bool cv = cg < ncol_of(oc);
         if (MODE == 1) {
             // scale by norm / lambda(jx, jy, m) and transform again
-            const float *gx = tab + oc.dst_g[0], *gy = tab + oc.dst_g[1], *gz = tab + oc.dst_g[2];
+            const float *gx = tab + oc.dst_g[0], *gy = tab + oc.dst_g[1];
             const float norm = 8.f / ((float)(oc.nx + 1) * (float)(oc.ny + 1) * (float)(oc.nz + 1));
             const float ih2 = (float)oc.inv_h2;
             const int jy = cv ? (int)(cg / oc.nx) : 0, jx = cv ? (int)(cg - (long long)jy * oc.nx) : 0;
             const float gxy = cv ? gx[jx] + gy[jy] : 1.f;
             __syncthreads();  // every wave is done reading Xt
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int rt = r0 + 2 * i;
+            for (int i = 0; i < MT; ++i) {
+                const int rt = r0 + RS * i;
                 if (rt < nrt) {
                     const int m0 = rt * 16 + 4 * lq;
                     __bf16 hh[4], ll[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int m = m0 + j;
-                        const float v = (cv && m < n) ? acc[i][j] * (norm / ((gxy + gz[m]) * ih2)) : 0.f;
-                        bsplit(v, hh[j], ll[j]);
+                        const float vv = (cv && m < n) ? acc[i][j] * (norm / ((gxy + gzs[m]) * ih2)) : 0.f;
+                        bsplit(vv, hh[j], ll[j]);
                     }
                     *reinterpret_cast<bf4 *>(Xhi + c * sw + m0) = bf4{hh[0], hh[1], hh[2], hh[3]};
                     *reinterpret_cast<bf4 *>(Xlo + c * sw + m0) = bf4{ll[0], ll[1], ll[2], ll[3]};
@@ -417,27 +470,58 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         if (cv) {
             const long long eo = oc.off + eoff(oc, cg);
             const long long ks = kstr_of(oc);
+            const bool vec = xvec(oc);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int rt = r0 + 2 * i;
+            for (int i = 0; i < MT; ++i) {
+                const int rt = r0 + RS * i;
                 if (rt < nrt) {
+                    const int m0 = rt * 16 + 4 * lq;
+                    if (vec) {
+                        if (m0 < n) {  // n % 4 == 0: all four rows are in range
+                            const float4 q = float4{acc[i][0], acc[i][1], acc[i][2], acc[i][3]};
+                            *reinterpret_cast<float4 *>(out + eo + m0) = q;
+                            if (RZ) part += dot4(rres + eo + m0, q);
+                        }
+                    } else {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int m = rt * 16 + 4 * lq + j;
-                        if (m < n) {
-                            const long long a = eo + (long long)m * ks;
-                            out[a] = acc[i][j];
-                            if (RZ) part += (double)rres[a] * (double)acc[i][j];
+                        for (int j = 0; j < 4; ++j) {
+                            const int m = m0 + j;
+                            if (m < n) {
+                                const long long a = eo + (long long)m * ks;
+                                out[a] = acc[i][j];
+                                if (RZ) part += (double)rres[a] * (double)acc[i][j];
+                            }
                         }
                     }
                 }
             }
         }
         if (RZ) {
-            const double sum = block_sum1024(part, sred);
+            const double sum = block_sum_fast(part, sred);
             if (t == 0) rz[oc.base9 + cur.tile] = sum;
         }
-        u = un;
+    };
+
+    // two register buffers: va holds unit q0, vb unit q1 (u1: none)
+    float va[kFV], vb[kFV];
+    int q0 = next_active(u0);
+    if (q0 >= u1) return;
+    int q1 = next_active(q0 + 1);
+    OrbDesc o0 = orb[units[q0].orb], o1;
+    load(va, o0, units[q0].tile);
+    if (q1 < u1) {
+        o1 = orb[units[q1].orb];
+        load(vb, o1, units[q1].tile);
+    }
+    while (true) {
+        const int q2 = q1 < u1 ? next_active(q1 + 1) : u1;
+        unit(va, q0, o0, q2);
+        q0 = q2;
+        if (q1 >= u1) break;
+        const int q3 = q0 < u1 ? next_active(q0 + 1) : u1;
+        unit(vb, q1, o1, q3);
+        q1 = q3;
+        if (q0 >= u1) break;
     }
 }
 
@@ -458,10 +542,6 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
     int *nc = nullptr;
     if (di.fast) {
         const size_t lds = dst_fast_lds(di.np);
-        set_lds_limit(k_dst_fast<0, 0, T, T, false>, lds);
-        set_lds_limit(k_dst_fast<1, 0, float, T, false>, lds);
-        set_lds_limit(k_dst_fast<2, 1, float, T, false>, lds);
-        set_lds_limit(k_dst_fast<0, 0, float, T, true>, lds);
         auto grid = [&](int units) { return dim3((unsigned)std::min(units, di.blocks)); };
         hipLaunchKernelGGL((k_dst_fast<0, 0, T, T, false>), grid(di.nx), dim3(kFT), lds, s, di.x,
                            di.nx, di.np, orb, done, tab, r, work, nr, nd, cnt);
@@ -485,6 +565,21 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
                        orb, done, tab, wk, work, nr, nd, nc);
     hipLaunchKernelGGL((k_dst_pass<0, 0, float, T, true>), dim3(di.nx), dim3(256), 0, s, di.x,
                        orb, done, tab, wk, z, r, rz, nc);
+    return hipGetLastError();
+}
+
+// raise the dynamic-LDS limit of the fast transform kernels (once per batch,
+// outside any stream capture)
+hipError_t dst_setup(int np) {
+    const size_t lds = dst_fast_lds(np);
+    set_lds_limit(k_dst_fast<0, 0, float, float, false>, lds);
+    set_lds_limit(k_dst_fast<0, 0, double, double, false>, lds);
+    set_lds_limit(k_dst_fast<1, 0, float, float, false>, lds);
+    set_lds_limit(k_dst_fast<1, 0, float, double, false>, lds);
+    set_lds_limit(k_dst_fast<2, 1, float, float, false>, lds);
+    set_lds_limit(k_dst_fast<2, 1, float, double, false>, lds);
+    set_lds_limit(k_dst_fast<0, 0, float, float, true>, lds);
+    set_lds_limit(k_dst_fast<0, 0, float, double, true>, lds);
     return hipGetLastError();
 }
 

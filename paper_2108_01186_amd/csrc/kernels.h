@@ -104,6 +104,9 @@ hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *pa
 // LDS bytes of a fast transform block for axes padded to np (<= 128) nodes.
 size_t dst_fast_lds(int np);
 
+// Allows the fast transform kernels their dynamic LDS for axes up to np.
+hipError_t dst_setup(int np);
+
 // z = M^{-1} r (float) for the orbitals of the work lists with done == 0,
 // through the float work array; r.z partial sums into rz[base9 + panel].
 // tab: sine matrices and eigenvalue symbols (offsets in OrbDesc); cnt (may

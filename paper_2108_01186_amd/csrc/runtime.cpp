@@ -222,6 +222,9 @@ struct fsic_ctx {
     int shape_cpt = 2, shape_depth = 1;
     long long shape_target = 0;
     double tune_ms = 0.0;
+    // FSIC_GRAPHS: captured CG chunks, and the stream they are captured on
+    std::map<std::string, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;
     HarmTables ht{};
 
     bool fail(fsic_status, const std::string &m) {
@@ -256,7 +259,7 @@ fsic_status validate_opts(const fsic_opts *o, std::string &why) {
     if (!std::isfinite(o->vsic_scale)) { why = "vsic_scale must be finite"; return FSIC_EINVAL; }
     if (!(o->rho_floor >= 0.0) || !std::isfinite(o->rho_floor)) { why = "rho_floor must be finite and >= 0"; return FSIC_EINVAL; }
     if (!(o->s_eig_floor > 0.0) || !std::isfinite(o->s_eig_floor)) { why = "s_eig_floor must be finite and > 0"; return FSIC_EINVAL; }
-    if (o->flags & ~(FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE | FSIC_FP32_ORBITALS)) { why = "unknown flag bits"; return FSIC_EINVAL; }
+    if (o->flags & ~(FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE | FSIC_FP32_ORBITALS | FSIC_GRAPHS)) { why = "unknown flag bits"; return FSIC_EINVAL; }
     return FSIC_OK;
 }
 
@@ -469,6 +472,7 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
         if ((st = upload(c, c->d_dy, b.dy))) return st;
         if ((st = upload(c, c->d_dz, b.dz))) return st;
         if ((st = upload(c, c->dtab, b.dtab))) return st;
+        if (b.dst_fast) HIPCHK(c, dst_setup((b.max_n + 31) & ~31));
         HIPCHK(c, c->Z32.ensure(F));
         HIPCHK(c, c->T32.ensure(F));
         HIPCHK(c, c->partRZ.ensure(2 * (size_t)b.tot9));
@@ -664,6 +668,55 @@ fsic_status choose_shape(fsic_ctx *c, const std::vector<Group> &groups, int prec
 //   src: densities (square = 0) or orbitals (square = 1), field layout of b;
 //   with_bc: Dirichlet values from the multipole expansion (else zero);
 //   X: solution (field layout of b).
+// Key of a captured CG chunk: everything its launches depend on.
+template <typename T>
+std::string chunk_key(const fsic_ctx *c, const CGIter<T> &a, const DstItems &di, const double *X,
+                      int tag, int kstart, int kend) {
+    std::string k;
+    auto put = [&](const void *p, size_t n) { k.append(static_cast<const char *>(p), n); };
+    put(&a, sizeof(a));
+    put(&di, sizeof(di));
+    put(&X, sizeof(X));
+    put(&c->cf, sizeof(c->cf));
+    const void *ptrs[] = {c->P0.p, c->P1.p, c->P32a.p, c->P32b.p, c->T32.p, c->dtab.p, c->B.p,
+                          c->X32.p, c->R32.p, c->h_done};
+    put(ptrs, sizeof(ptrs));
+    const int ints[] = {tag, kstart, kend, c->radius, c->opts.max_iter};
+    put(ints, sizeof(ints));
+    return k;
+}
+
+// Enqueue one CG chunk on stream s: directly, or (FSIC_GRAPHS) as a graph
+// captured once per key on the context's capture stream and replayed.
+template <class Body>
+fsic_status run_chunk(fsic_ctx *c, bool graphs, const std::string &key, Body &body, hipStream_t s) {
+    if (!graphs) return body(s);
+    auto f = c->graphs.find(key);
+    if (f == c->graphs.end()) {
+        if (c->graphs.size() >= 64) {  // bound the cache (buffers reallocated, other batches)
+            for (auto &e : c->graphs) hipGraphExecDestroy(e.second);
+            c->graphs.clear();
+        }
+        if (!c->cap_stream) HIPCHK(c, hipStreamCreate(&c->cap_stream));
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        const fsic_status st = body(c->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (st) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return set_err(c, FSIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ei != hipSuccess) return set_err(c, FSIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        f = c->graphs.emplace(key, ex).first;
+    }
+    HIPCHK(c, hipGraphLaunch(f->second, s));
+    return FSIC_OK;
+}
+
 fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int square, double scale,
                         bool with_bc, double *X, int precision, double tol, int max_iter,
                         SolveReport &rep) {
@@ -727,6 +780,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
 #define PROF_END() \
     if (_sp) HIPCHK(c, hipEventRecord(_eb, s));
     const bool pcg = use_pcg(c, b);
+    const bool graphs = (c->opts.flags & FSIC_GRAPHS) && !prof;
     DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(),
                 (int)b.dz.size(), b.dst_fast ? 1 : 0, (b.max_n + 31) & ~31, dst_blocks(c)};
     if (pcg && !mixed) {
@@ -741,33 +795,43 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
         a.rs_iter = nullptr; a.nact = c->nact.p; a.norb = norb;
         a.tol2 = tol2;
+        const CGIter<double> a0 = a;
         HIPCHK(c, launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R, c->T32.p,
                                              a.Z, a.partRZ, nullptr, s));
         while (k < max_iter + 1 && !all_done) {
+            const int kstart = k;
             const int kend = std::min(k + chunk, max_iter + 1);
-            for (; k < kend; ++k) {
-                a.P = (k & 1) ? c->P1.p : c->P0.p;
-                a.Pold = (k & 1) ? c->P0.p : c->P1.p;
-                {
-                    PROF_BEGIN(0, k, k == 0)
-                    HIPCHK(c, launch_pcg_stencil<double>(c->radius, c->cf, a, k, 0, 0, 0, s));
-                    PROF_END()
-                }
-                if (k < max_iter) {
+            // one chunk of iterations on stream `s` (shadowing the context's)
+            auto body = [&](hipStream_t s) -> fsic_status {
+                CGIter<double> a = a0;
+                for (int k = kstart; k < kend; ++k) {
+                    a.P = (k & 1) ? c->P1.p : c->P0.p;
+                    a.Pold = (k & 1) ? c->P0.p : c->P1.p;
                     {
-                        PROF_BEGIN(1, k, k == 0)
-                        HIPCHK(c, launch_pcg_update<double>(a, k, k == 0, s));
+                        PROF_BEGIN(0, k, k == 0)
+                        HIPCHK(c, launch_pcg_stencil<double>(c->radius, c->cf, a, k, 0, 0, 0, s));
                         PROF_END()
                     }
-                    PROF_BEGIN(2, k, 0)
-                    HIPCHK(c, launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
-                                                         c->T32.p, a.Z,
-                                                         a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
-                                                         _sp ? nsamp + 2 * norb : nullptr, s));
-                    PROF_END()
+                    if (k < max_iter) {
+                        {
+                            PROF_BEGIN(1, k, k == 0)
+                            HIPCHK(c, launch_pcg_update<double>(a, k, k == 0, s));
+                            PROF_END()
+                        }
+                        PROF_BEGIN(2, k, 0)
+                        HIPCHK(c, launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
+                                                             c->T32.p, a.Z,
+                                                             a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
+                                                             _sp ? nsamp + 2 * norb : nullptr, s));
+                        PROF_END()
+                    }
                 }
-            }
-            HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+                return FSIC_OK;
+            };
+            const fsic_status cs = run_chunk(c, graphs, chunk_key(c, a0, di, X, 64, kstart, kend), body, s);
+            if (cs) return cs;
+            k = kend;
             HIPCHK(c, hipStreamSynchronize(s));
             all_done = true;
             for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o];
@@ -789,44 +853,54 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         a.rs_iter = c->rs_iter.p; a.nact = c->nact.p; a.norb = norb;
         a.tol2 = tol2;
         const int pchunk = pcg_chunk();
+        const CGIter<float> a0 = a;
         int nref = 0;
         while (k < max_iter && !all_done) {
             const int kstart = k;
             const int kend = std::min(k + pchunk, max_iter);
-            HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R, c->T32.p,
-                                                a.Z, a.partRZ + (size_t)(k & 1) * b.tot9, nullptr, s));
-            for (; k < kend; ++k) {
-                const int j = k - kstart;
-                a.P = (k & 1) ? c->P32b.p : c->P32a.p;
-                a.Pold = (k & 1) ? c->P32a.p : c->P32b.p;
-                {
-                    PROF_BEGIN(0, k, k == 0)
-                    HIPCHK(c, launch_pcg_stencil<float>(c->radius, c->cf, a, k, j == 0 && k > 0,
-                                                        j == 0, 1, s));
-                    PROF_END()
+            // one restart cycle on stream `s` (shadowing the context's)
+            auto body = [&](hipStream_t s) -> fsic_status {
+                CGIter<float> a = a0;
+                HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R, c->T32.p,
+                                                    a.Z, a.partRZ + (size_t)(kstart & 1) * b.tot9,
+                                                    nullptr, s));
+                for (int k = kstart; k < kend; ++k) {
+                    const int j = k - kstart;
+                    a.P = (k & 1) ? c->P32b.p : c->P32a.p;
+                    a.Pold = (k & 1) ? c->P32a.p : c->P32b.p;
+                    {
+                        PROF_BEGIN(0, k, k == 0)
+                        HIPCHK(c, launch_pcg_stencil<float>(c->radius, c->cf, a, k, j == 0 && k > 0,
+                                                            j == 0, 1, s));
+                        PROF_END()
+                    }
+                    {
+                        PROF_BEGIN(1, k, j == 0)
+                        HIPCHK(c, launch_pcg_update<float>(a, k, j == 0, s));
+                        PROF_END()
+                    }
+                    if (k + 1 < kend) {
+                        PROF_BEGIN(2, k, 0)
+                        HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
+                                                            c->T32.p, a.Z,
+                                                            a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
+                                                            _sp ? nsamp + 2 * norb : nullptr, s));
+                        PROF_END()
+                    }
                 }
-                {
-                    PROF_BEGIN(1, k, j == 0)
-                    HIPCHK(c, launch_pcg_update<float>(a, k, j == 0, s));
-                    PROF_END()
-                }
-                if (k + 1 < kend) {
-                    PROF_BEGIN(2, k, 0)
-                    HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
-                                                        c->T32.p, a.Z,
-                                                        a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
-                                                        _sp ? nsamp + 2 * norb : nullptr, s));
-                    PROF_END()
-                }
-            }
-            HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p,
-                                           c->done.p, X, c->X32.p, c->B.p, nullptr, c->R32.p,
-                                           c->partRU.p, s));
-            HIPCHK(c, launch_mixed_accumulate(nit8, c->d_items8.p, c->d_orb.p, c->done.p, X, c->X32.p, s));
-            HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, k, c->done.p,
-                                      c->iters.p, c->rrfin.p, c->rs_iter.p, s));
+                HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p,
+                                               c->done.p, X, c->X32.p, c->B.p, nullptr, c->R32.p,
+                                               c->partRU.p, s));
+                HIPCHK(c, launch_mixed_accumulate(nit8, c->d_items8.p, c->d_orb.p, c->done.p, X, c->X32.p, s));
+                HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, kend, c->done.p,
+                                          c->iters.p, c->rrfin.p, c->rs_iter.p, s));
+                HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+                return FSIC_OK;
+            };
+            const fsic_status cs = run_chunk(c, graphs, chunk_key(c, a0, di, X, 32, kstart, kend), body, s);
+            if (cs) return cs;
+            k = kend;
             ++nref;
-            HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));
             all_done = true;
             for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o] == 1;
@@ -1071,6 +1145,8 @@ void fsic_destroy(fsic_ctx *c) {
     c->partU.release(); c->partX.release(); c->Uo.release(); c->Xo.release(); c->Ech.release();
     c->status.release(); c->bmat.release();
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     if (c->h_done) hipHostFree(c->h_done);
     delete c;
 }

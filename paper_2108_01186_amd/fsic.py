@@ -33,6 +33,7 @@ FSIC_OK, FSIC_EINVAL, FSIC_ENOMEM, FSIC_EHIP, FSIC_ENONORTHO, FSIC_EVACUUM, \
 FSIC_FP64, FSIC_MIXED = 0, 1
 FSIC_CG, FSIC_PCG = 0, 1
 FSIC_WANT_VSIC, FSIC_KEEP_TAPE, FSIC_ALLOW_NONORTHO, FSIC_PROFILE, FSIC_FP32_ORBITALS = 1, 2, 4, 8, 16
+FSIC_GRAPHS = 32
 
 
 class fsic_grid(ctypes.Structure):

@@ -115,3 +115,27 @@ def test_fp32_orbital_gemm_error(torch_cuda, F, mol40_dev, mol40_oracle):
     _say(f"fp32 orbitals: |dE| = {de:.3e} Ha, max |dV_SIC| = {dv:.3e} Ha (E = {base['e'][0]:.6f})")
     assert de < 1e-6 * abs(base["e"][0]) + 1e-9
     assert dv < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_match_eager(torch_cuda, F, mol40_dev, precision):
+    """FSIC_GRAPHS: CG chunks captured once and replayed.  Three forward +
+    backward passes, each after eager work of another context, all bitwise
+    equal to the eager path (same kernels, same order)."""
+    _say(f"graphs mol40 {precision}")
+    d = F.system_dict(mol40_dev)
+    eager = F.Context(precision=precision, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE)
+    e0 = eager.forward([d])[0][0]
+    g0 = eager.backward([[5]])[0][0]
+    v0 = d["vsic"][0].cpu().numpy().copy()
+    graph = F.Context(precision=precision,
+                      flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE | F.FSIC_GRAPHS)
+    for rep in range(3):
+        eager.forward([d])  # eager work on the same device between replays
+        e1 = graph.forward([d])[0][0]
+        g1 = graph.backward([[5]])[0][0]
+        assert e1 == e0, (rep, e1, e0)
+        assert np.array_equal(g1, g0), rep
+        assert np.array_equal(d["vsic"][0].cpu().numpy(), v0), rep
+    eager.close()
+    graph.close()
