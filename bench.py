@@ -51,7 +51,8 @@ def run_steps(F, torch, ctx, dicts, noccs, steps):
     """Timed region: `steps` full passes (forward + backward) over all systems."""
     keys = ("sweep_ms", "sweep_bytes", "sweep_launches", "update_ms", "update_bytes",
             "update_launches", "precond_ms", "precond_bytes", "precond_flops", "precond_launches")
-    agg = dict({k: 0.0 for k in keys}, iters=0, solves=0, refinements=0, max_relres=0.0)
+    agg = dict({k: 0.0 for k in keys}, iters=0, solves=0, refinements=0, max_relres=0.0,
+               phase_ms=[0.0] * 8)
     e = g = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -65,6 +66,8 @@ def run_steps(F, torch, ctx, dicts, noccs, steps):
         agg["solves"] += st["nsolves"]
         agg["refinements"] += st["outer_refinements"]
         agg["max_relres"] = max(agg["max_relres"], st["max_relres"])
+        for q in (0, 1, 2, 3, 4):
+            agg["phase_ms"][q] += st["ms_phase"][q] / steps
         g = ctx.backward(noccs)
         st = ctx.stats
         for k in keys:
@@ -73,6 +76,8 @@ def run_steps(F, torch, ctx, dicts, noccs, steps):
         agg["solves"] += st["nsolves"]
         agg["refinements"] += st["outer_refinements"]
         agg["max_relres"] = max(agg["max_relres"], st["max_relres"])
+        for q in (5, 6):
+            agg["phase_ms"][q] += st["ms_phase"][q] / steps
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dt, e, g, agg
@@ -300,6 +305,9 @@ def main():
         "e_sic_force_ms_mixed": mx["dt"] / steps * 1e3,
         "mean_cg_iters_mixed": mx["agg"]["iters"] / max(1, mx["agg"]["solves"]),
         "max_relres_mixed": mx["agg"]["max_relres"],
+        "host_phase_ms_mixed": dict(zip(["setup", "fo_loewdin", "boundary_rhs", "cg", "xc_average",
+                                         "adjoint_cg", "adjoint_rest"],
+                                        [round(v, 3) for v in mx["agg"]["phase_ms"][:7]])),
         "roofline": roof,
     }
     if "fp64" in results:

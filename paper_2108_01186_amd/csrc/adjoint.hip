@@ -175,14 +175,17 @@ __global__ __launch_bounds__(256) void k_adj_contract(int N, long long M, long l
     }
 }
 
-__global__ void k_adj_contract_final(int N, int nblk, const double *partB, double *Bm) {
+// Bm[i][j] = sum of the blocks' partial tiles; one 256-thread block per element
+__global__ __launch_bounds__(256) void k_adj_contract_final(int N, int nblk, const double *partB,
+                                                            double *Bm) {
+    __shared__ double sred[4];
     const int NP = ((N + 15) >> 4) * 16;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
-        const int i = e / N, j = e % N;
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += partB[(size_t)b * NP * NP + (size_t)i * NP + j];
-        Bm[e] = s;
-    }
+    const int e = blockIdx.x;
+    const int i = e / N, j = e % N;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += partB[(size_t)b * NP * NP + (size_t)i * NP + j];
+    s = block_sum256(s, sred);
+    if (threadIdx.x == 0) Bm[e] = s;
 }
 
 // C = op(A) op(B) for N x N row-major matrices (flat pointers)
@@ -285,12 +288,13 @@ hipError_t launch_adj_field(int lmax, const HarmTables &ht, const OrbDesc *orb, 
 
 hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,
                                     const double *W, const double *psi, double floor, double *partB,
-                                    int nblk, double *Bm, hipStream_t s) {
+                                    size_t cap, double *Bm, hipStream_t s) {
+    const int nblk = grid_blocks(N, M, cap);
     long long chunk = (M + nblk - 1) / nblk;
     chunk = (chunk + 3) & ~3LL;
     hipLaunchKernelGGL(k_adj_contract, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
                        floor, partB);
-    hipLaunchKernelGGL(k_adj_contract_final, dim3(64), dim3(256), 0, s, N, nblk, partB, Bm);
+    hipLaunchKernelGGL(k_adj_contract_final, dim3(N * N), dim3(256), 0, s, N, nblk, partB, Bm);
     return hipGetLastError();
 }
 

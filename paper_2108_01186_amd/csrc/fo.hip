@@ -9,6 +9,8 @@
 //   * the Fermi-Loewdin orbitals phi = Q psi with Q = S^{-1/2} T.
 // Everything N x N (N <= 128) runs in one workgroup: S = T G T^T, a parallel
 // cyclic Jacobi eigen-decomposition (round-robin pairing), S^{-1/2}, Q.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace fsic {
@@ -163,23 +165,37 @@ __global__ __launch_bounds__(256) void k_gram(int N, long long M, long long chun
     }
 }
 
-__global__ void k_gram_final(int N, int nblk, double dV, const double *partG, double *G) {
+// G[i][j] = dV * sum over the blocks' partial tiles (the upper block triangle
+// holds the tile pairs); one 256-thread block per element, fixed order
+__global__ __launch_bounds__(256) void k_gram_final(int N, int nblk, double dV, const double *partG,
+                                                    double *G) {
+    __shared__ double sred[4];
     const int NP = ((N + 15) >> 4) * 16;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
-        int i = e / N, j = e % N;
-        if ((i >> 4) > (j >> 4)) { const int t = i; i = j; j = t; }
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += partG[(size_t)b * NP * NP + (size_t)i * NP + j];
-        G[e] = dV * s;
-    }
+    const int e = blockIdx.x;
+    int i = e / N, j = e % N;
+    if ((i >> 4) > (j >> 4)) { const int t = i; i = j; j = t; }
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += partG[(size_t)b * NP * NP + (size_t)i * NP + j];
+    s = block_sum256(s, sred);
+    if (threadIdx.x == 0) G[e] = dV * s;
 }
 
-hipError_t launch_gram(int N, long long M, double dV, const double *psi, double *partG, int nblk,
+// partial-sum blocks for a node range split: enough to fill the device
+// several times over, within the partial buffer (cap doubles)
+int grid_blocks(int N, long long M, size_t cap) {
+    const size_t NP = (size_t)((N + 15) >> 4) * 16;
+    long long nb = (long long)std::min<size_t>(4096, cap / (NP * NP));
+    nb = std::min(nb, (M + 63) / 64);
+    return (int)std::max(1LL, nb);
+}
+
+hipError_t launch_gram(int N, long long M, double dV, const double *psi, double *partG, size_t cap,
                        double *G, hipStream_t s) {
+    const int nblk = grid_blocks(N, M, cap);
     long long chunk = (M + nblk - 1) / nblk;
     chunk = (chunk + 3) & ~3LL;
     hipLaunchKernelGGL(k_gram, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, partG);
-    hipLaunchKernelGGL(k_gram_final, dim3(64), dim3(256), 0, s, N, nblk, dV, partG, G);
+    hipLaunchKernelGGL(k_gram_final, dim3(N * N), dim3(256), 0, s, N, nblk, dV, partG, G);
     return hipGetLastError();
 }
 

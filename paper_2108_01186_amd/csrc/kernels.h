@@ -195,8 +195,11 @@ hipError_t launch_interp(int N, int nx, int ny, int nz, double h, const double *
                          double *rhoa, double *T, int *status, hipStream_t s);
 
 // G = dV psi psi^T (MFMA FP64), partial sums then reduction; nonortho = max|G - I|
-hipError_t launch_gram(int N, long long M, double dV, const double *psi, double *partG,
-                       int nblk, double *G, hipStream_t s);
+// blocks of a node-range split whose N x N partial tiles fit in cap doubles
+int grid_blocks(int N, long long M, size_t cap);
+
+hipError_t launch_gram(int N, long long M, double dV, const double *psi, double *partG, size_t cap,
+                       double *G, hipStream_t s);
 
 // Loewdin step on one block: S = T G T^T; S = U diag(lam) U^T (parallel
 // Jacobi); Z = S^{-1/2}; Q = Z T.  work: device scratch of >= 2 N^2 doubles.
@@ -218,8 +221,8 @@ hipError_t launch_adj_field(int lmax, const HarmTables &ht, const OrbDesc *orb, 
 // B[i][a] = sum_m Gam_i(m) psi_a(m) with Gam_i = 2 dV phi_i omega_i built on
 // the fly, omega_i = -((v_i + w_i) / 2 + vxc(phi_i^2)) (MFMA FP64)
 hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,
-                                   const double *W, const double *psi, double floor, double *partB,
-                                   int nblk, double *Bm, hipStream_t s);
+                                    const double *W, const double *psi, double floor, double *partB,
+                                    size_t cap, double *Bm, hipStream_t s);
 
 // reverse mode through Q = S^{-1/2} T, S = T G T^T, T = u/|u|, u = psi(a):
 // dEda[i][d] = gscale * sum_a Gam_u[i][a] dpsi_a(a_i)/da_d

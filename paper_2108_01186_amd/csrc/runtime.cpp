@@ -333,6 +333,34 @@ int dst_blocks(const fsic_ctx *c) {
     return v;
 }
 
+// Spectral-table block of an axis of n nodes (cached per process): the
+// np x np sine matrix sin(pi (m+1)(k+1) / (n+1)) (zero beyond n, np = n
+// rounded up to 32), then the n symbols -(c_0 + 2 sum_q c_q cos(q theta_j)).
+const std::vector<float> &dst_block(int n, int radius) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, std::vector<float>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto f = cache.find({n, radius});
+    if (f != cache.end()) return f->second;
+    const int np = (n + 31) & ~31;
+    std::vector<float> v((size_t)np * np, 0.f);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int m = 0; m < n; ++m)
+        for (int k = 0; k < n; ++k) {
+            // argument reduced exactly in integers
+            const long long a = ((long long)(m + 1) * (k + 1)) % (2LL * (n + 1));
+            v[(size_t)m * np + k] = (float)sinl(pi * (long double)a / (long double)(n + 1));
+        }
+    const Coeffs cw = fd_weights(radius);
+    for (int j = 0; j < n; ++j) {
+        const long double th = pi * (long double)(j + 1) / (long double)(n + 1);
+        long double sg = cw.c[0];
+        for (int q = 1; q <= radius; ++q) sg += 2.0L * cw.c[q] * cosl(q * th);
+        v.push_back((float)(-sg));
+    }
+    return cache.emplace(std::make_pair(n, radius), std::move(v)).first->second;
+}
+
 // LDS bytes one workgroup may use on the current device
 size_t device_lds_limit() {
     int dev = 0, v = 0;
@@ -357,23 +385,10 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
         auto f = dst_done.find(n);
         if (f != dst_done.end()) return f->second;
         const int np = (n + 31) & ~31;
+        const std::vector<float> &blk = dst_block(n, radius_);  // np x np sines, then n symbols
         const int so = (int)bb.dtab.size();
-        bb.dtab.resize(bb.dtab.size() + (size_t)np * np, 0.f);
-        const long double pi = 3.141592653589793238462643383279502884L;
-        for (int m = 0; m < n; ++m)
-            for (int k = 0; k < n; ++k) {
-                // sin(pi (m+1)(k+1) / (n+1)), argument reduced exactly in integers
-                const long long a = ((long long)(m + 1) * (k + 1)) % (2LL * (n + 1));
-                bb.dtab[so + (size_t)m * np + k] = (float)sinl(pi * (long double)a / (long double)(n + 1));
-            }
-        const int go = (int)bb.dtab.size();
-        const Coeffs cw = fd_weights(radius_);
-        for (int j = 0; j < n; ++j) {
-            const long double th = pi * (long double)(j + 1) / (long double)(n + 1);
-            long double sg = cw.c[0];
-            for (int q = 1; q <= radius_; ++q) sg += 2.0L * cw.c[q] * cosl(q * th);
-            bb.dtab.push_back((float)(-sg));
-        }
+        bb.dtab.insert(bb.dtab.end(), blk.begin(), blk.end());
+        const int go = so + np * np;
         // pad the table to a multiple of 4 floats
         while (bb.dtab.size() % 4) bb.dtab.push_back(0.f);
         return dst_done[n] = {so, go};
@@ -1280,7 +1295,7 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         HIPCHK(c, launch_interp(ch.N, ch.n[0], ch.n[1], ch.n[2], ch.h, ch.psi, c->d_cells.p + cell_base,
                                 o.rho_floor, sm + small_off(sU_), sm + small_off(sDU),
                                 sm + small_off(sRHOA), sm + small_off(sT), c->status.p, s));
-        HIPCHK(c, launch_gram(ch.N, ch.M, dV, ch.psi, c->partG.p, gram_blk, sm + small_off(sG), s));
+        HIPCHK(c, launch_gram(ch.N, ch.M, dV, ch.psi, c->partG.p, c->partG.cap, sm + small_off(sG), s));
         HIPCHK(c, launch_lowdin(ch.N, sm + small_off(sT), sm + small_off(sG), sm + small_off(sS),
                                 sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
                                 sm + small_off(sQ), c->work.p, o.s_eig_floor, c->status.p,
@@ -1574,7 +1589,7 @@ fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, con
     if (!e) e = launch_interp(N, grid->n[0], grid->n[1], grid->n[2], grid->h, psi, dc.p, rho_floor,
                               b + small_off(sU_), b + small_off(sDU), b + small_off(sRHOA),
                               b + small_off(sT), status.p, s);
-    if (!e) e = launch_gram(N, M, dV, psi, partG.p, 256, b + small_off(sG), s);
+    if (!e) e = launch_gram(N, M, dV, psi, partG.p, partG.cap, b + small_off(sG), s);
     if (!e) e = launch_lowdin(N, b + small_off(sT), b + small_off(sG), b + small_off(sS),
                               b + small_off(sLAM), b + small_off(sEV), b + small_off(sZ),
                               b + small_off(sQ), work.p, 0.0, status.p, b + small_off(sINFO), s);
@@ -1637,7 +1652,7 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         double *sm = c->small.p + ch.so;
         const double dV = ch.h * ch.h * ch.h;
         HIPCHK(c, launch_adjoint_contract(ch.N, ch.M, dV, c->PHI.p + ch.off, c->V.p + ch.off,
-                                          c->W.p + ch.off, ch.psi, o.rho_floor, c->partG.p, 256,
+                                          c->W.p + ch.off, ch.psi, o.rho_floor, c->partG.p, c->partG.cap,
                                           c->bmat.p, s));
         HIPCHK(c, launch_lowdin_backward(ch.N, c->bmat.p, sm + small_off(sT), sm + small_off(sG),
                                          sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
