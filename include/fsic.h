@@ -230,6 +230,17 @@ fsic_status fsic_op_laplacian_f32(const int32_t *n, double h, int32_t fd_order,
 fsic_status fsic_op_xc(int64_t count, const double *rho, double rho_floor, double *ex,
                        double *ec, double *vx, double *vc, void *hip_stream);
 
+/* Kohn-Sham Hamiltonian applied to count orbitals (the step after this
+ * path in the self-consistent cycle, Sec. II.C, where V_SIC enters the
+ * local potential): out[f] = -1/2 L psi[f] + v psi[f], L the fd_order-th
+ * order star Laplacian with zero Dirichlet values (Sec. II.A), v one [M]
+ * potential (for instance v_KS + V_SIC of the orbitals' spin channel).
+ * psi, out: [count][M] FP64, not overlapping; v: [M] FP64.  FSIC_EINVAL on
+ * bad sizes. */
+fsic_status fsic_op_hamiltonian(const int32_t *n /* HOST [3] */, double h, int32_t fd_order,
+                                int32_t count, const double *psi, const double *v, double *out,
+                                void *hip_stream);
+
 /* Hartree potentials v[f] of count densities rho[f] on one grid: -L v =
  * 4 pi rho with multipole Dirichlet values of order lmax about the box
  * centre (Sec. II.A), solved to tol.  iters, relres: HOST [count] or NULL.

@@ -144,6 +144,23 @@ int orc_apply_laplacian(const int *n, double h, int p, const double *u, double *
     return 0;
 }
 
+/* Kohn-Sham Hamiltonian applied to count orbitals (Sec. II.C: the SIC
+ * potential enters the KS equations as a local term): out = -1/2 L psi +
+ * v psi, zero Dirichlet values, v one field for all orbitals. */
+int orc_hamiltonian(const int *n, double h, int p, int count, const double *psi,
+                    const double *v, double *out)
+{
+    if (!n || !psi || !v || !out || count < 1) return ORC_EBADARG;
+    const long M = grid_size(n);
+    for (int f = 0; f < count; ++f) {
+        int st = orc_apply_laplacian(n, h, p, psi + (long)f * M, out + (long)f * M);
+        if (st) return st;
+        for (long m = 0; m < M; ++m)
+            out[(long)f * M + m] = -0.5 * out[(long)f * M + m] + v[m] * psi[(long)f * M + m];
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Multipole expansion for the Dirichlet values (Sec. II.A, isolated case)   */
 /* ------------------------------------------------------------------------ */

@@ -35,6 +35,11 @@ int orc_fd_coeffs(int p, double *c);
 /* Lu = L u with the 2p-th order star Laplacian and zero Dirichlet ghosts. */
 int orc_apply_laplacian(const int *n, double h, int p, const double *u, double *Lu);
 
+/* Kohn-Sham Hamiltonian of count orbitals: out = -1/2 L psi + v psi (L as
+ * above, zero Dirichlet values; v: one [M] potential for all orbitals). */
+int orc_hamiltonian(const int *n, double h, int p, int count, const double *psi,
+                    const double *v, double *out);
+
 /* Real orthonormal spherical harmonics times r^l ("regular solid
  * harmonics") at (x, y, z): out[l*l + l + m] = r^l Y_lm, m = -l..l. */
 int orc_solid_harmonics(int lmax, double x, double y, double z, double *out);

@@ -97,6 +97,16 @@ def apply_laplacian(u: np.ndarray, h: float, p: int) -> np.ndarray:
     return out
 
 
+def hamiltonian(psi: np.ndarray, v: np.ndarray, h: float, p: int = 6) -> np.ndarray:
+    """-1/2 L psi + v psi for psi of shape (count, nz, ny, nx), v of shape (nz, ny, nx)."""
+    psi = _f64(psi)
+    v = _f64(v)
+    n = np.array([psi.shape[3], psi.shape[2], psi.shape[1]], dtype=np.int32)
+    out = np.empty_like(psi)
+    _check(lib().orc_hamiltonian(_i(n), ctypes.c_double(h), p, psi.shape[0], _d(psi), _d(v), _d(out)))
+    return out
+
+
 def solid_harmonics(lmax: int, x: float, y: float, z: float) -> np.ndarray:
     out = np.zeros((lmax + 1) ** 2)
     _check(lib().orc_solid_harmonics(lmax, ctypes.c_double(x), ctypes.c_double(y),

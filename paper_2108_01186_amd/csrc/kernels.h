@@ -14,6 +14,11 @@ template <typename T>
 hipError_t launch_apply(int radius, const Coeffs &c, const Item *items, int nitems,
                         const OrbDesc *orb, const T *u, T *Lu, hipStream_t s);
 
+// out = -1/2 L psi + v psi for the orbitals of an item table (v: [M], shared).
+hipError_t launch_hamiltonian(int radius, const Coeffs &c, const Item *items, int nitems,
+                              const OrbDesc *orb, const double *psi, const double *v, double *out,
+                              hipStream_t s);
+
 // Arguments of one CG iteration over a batch of orbitals.
 template <typename T>
 struct CGIter {

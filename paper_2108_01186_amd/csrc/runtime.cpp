@@ -1446,6 +1446,32 @@ fsic_status fsic_op_laplacian(const int32_t *n, double h, int32_t fd_order, int3
     return (e || e2) ? FSIC_EHIP : FSIC_OK;
 }
 
+fsic_status fsic_op_hamiltonian(const int32_t *n, double h, int32_t fd_order, int32_t count,
+                                const double *psi, const double *v, double *out, void *hip_stream) {
+    if (!n || !psi || !v || !out || count < 1 || fd_order < 2 || fd_order > 12 || (fd_order & 1))
+        return FSIC_EINVAL;
+    fsic_grid g{{n[0], n[1], n[2]}, h, {0, 0, 0}};
+    std::string why;
+    if (validate_grid(g, why)) return FSIC_EINVAL;
+    const int P = fd_order / 2;
+    std::vector<Group> groups(1);
+    for (int d = 0; d < 3; ++d) { groups[0].n[d] = n[d]; groups[0].origin[d] = 0.0; }
+    groups[0].h = h; groups[0].count = count; groups[0].off = 0; groups[0].chan = 0;
+    Batch b;
+    build_batch(groups, P, Shape{2, 2, 4096}, b);  // fd_weights: cpt 2, depth 2
+    hipStream_t s = (hipStream_t)hip_stream;
+    DBuf<OrbDesc> dorb;
+    DBuf<Item> dit;
+    if (dorb.ensure(b.orb.size()) || dit.ensure(b.items7.size())) return FSIC_ENOMEM;
+    hipError_t e = hipMemcpyAsync(dorb.p, b.orb.data(), b.orb.size() * sizeof(OrbDesc), hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemcpyAsync(dit.p, b.items7.data(), b.items7.size() * sizeof(Item), hipMemcpyHostToDevice, s);
+    if (!e) e = launch_hamiltonian(P, fd_weights(P), dit.p, (int)b.items7.size(), dorb.p, psi, v, out, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    dorb.release();
+    dit.release();
+    return (e || e2) ? FSIC_EHIP : FSIC_OK;
+}
+
 fsic_status fsic_op_laplacian_f32(const int32_t *n, double h, int32_t fd_order, int32_t count,
                                   const float *u, float *Lu, void *hip_stream) {
     if (!n || !u || !Lu || count < 1 || fd_order < 2 || fd_order > 12 || (fd_order & 1))

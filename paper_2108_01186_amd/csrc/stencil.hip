@@ -266,6 +266,34 @@ struct PolApply {  // Lu = L u
     __device__ void finish(const Item &, const OrbDesc &, const Acc &, double *) const {}
 };
 
+template <typename T>
+struct PolHam {  // out = -1/2 L psi + v psi (v: one field shared by the orbitals)
+    const Item *items;
+    const OrbDesc *orb;
+    const T *psi;
+    const T *v;
+    T *out;
+    struct Raw { T a; };
+    typedef T Ext;
+    struct Acc {};
+    bool tile0;
+    Rsrc ru, rv, ro;
+    __device__ bool setup(int, const OrbDesc &, double *) { return true; }
+    __device__ void init(const OrbDesc &od) {
+        const unsigned bytes = (unsigned)((long long)od.nx * od.ny * od.nz * sizeof(T));
+        ru = make_rsrc(psi + od.off, bytes);
+        rv = make_rsrc(v, bytes);
+        ro = make_rsrc(out + od.off, bytes);
+    }
+    __device__ Raw raw(unsigned i, int zo) const { return Raw{bld<T>(ru, i, zo)}; }
+    __device__ Ext ext(unsigned i, int zo) const { return bld<T>(rv, i, zo); }
+    __device__ T combine(const Raw &r) const { return r.a; }
+    __device__ void epilogue(unsigned i, int zo, T c, T lap, const Ext &vv, Acc &) const {
+        bst(ro, i, zo, T(-0.5) * lap + vv * c);
+    }
+    __device__ void finish(const Item &, const OrbDesc &, const Acc &, double *) const {}
+};
+
 // r_j.r_j of an orbital: the CG recursion's partial sums (by iteration
 // parity) or those of the last FP64 residual, added in a fixed order
 template <typename T>
@@ -694,6 +722,17 @@ hipError_t launch_apply(int radius, const Coeffs &c, const Item *items, int nite
     if (nitems <= 0) return hipSuccess;
     PolApply<T> pol{items, orb, u, Lu, false};
 #define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolApply<T>>), dim3(nitems), dim3(256), 0, s, pol, c)
+    FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_hamiltonian(int radius, const Coeffs &c, const Item *items, int nitems,
+                              const OrbDesc *orb, const double *psi, const double *v, double *out,
+                              hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    PolHam<double> pol{items, orb, psi, v, out, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolHam<double>>), dim3(nitems), dim3(256), 0, s, pol, c)
     FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
     return hipGetLastError();

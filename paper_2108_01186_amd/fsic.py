@@ -102,6 +102,8 @@ fsic_op_laplacian_f32 = _sig("fsic_op_laplacian_f32", ctypes.c_int,
                              [_ip, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp])
 fsic_op_xc = _sig("fsic_op_xc", ctypes.c_int,
                   [ctypes.c_int64, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp])
+fsic_op_hamiltonian = _sig("fsic_op_hamiltonian", ctypes.c_int,
+                           [_ip, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp])
 fsic_op_poisson = _sig("fsic_op_poisson", ctypes.c_int,
                        [_P(fsic_grid), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                         ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _ip, _dp,
@@ -115,6 +117,7 @@ fsic_op_flo = _sig("fsic_op_flo", ctypes.c_int,
 EXPORTED = ["fsic_default_opts", "fsic_create", "fsic_set_opts", "fsic_forward", "fsic_backward",
             "fsic_status_string", "fsic_last_error", "fsic_destroy", "fsic_op_laplacian",
             "fsic_op_laplacian_f32", "fsic_op_xc", "fsic_op_poisson", "fsic_op_invsqrt",
+            "fsic_op_hamiltonian",
             "fsic_op_flo"]
 
 
@@ -294,6 +297,19 @@ def op_xc(rho, rho_floor: float = 1e-30, stream=None):
     _check(fsic_op_xc(rho.numel(), _dev_ptr(rho), rho_floor, *[_dev_ptr(o) for o in outs],
                       _stream_ptr(stream)))
     return outs
+
+
+def op_hamiltonian(psi, v, n, h: float, fd_order: int = 12, stream=None):
+    """-1/2 L psi + v psi for device psi (count, M) and v (M,), float64."""
+    torch = _torch()
+    psi = psi.contiguous()
+    v = v.contiguous()
+    count = psi.shape[0] if psi.dim() > 1 else 1
+    out = torch.empty_like(psi)
+    nn = (ctypes.c_int32 * 3)(*[int(x) for x in n])
+    _check(fsic_op_hamiltonian(nn, h, fd_order, count, _dev_ptr(psi), _dev_ptr(v), _dev_ptr(out),
+                               _stream_ptr(stream)))
+    return out
 
 
 def op_poisson(rho, n, h, origin, fd_order=12, lmax=6, tol=1e-10, max_iter=20000,

@@ -209,6 +209,21 @@ def test_orbital_terms_gaussian_and_consistency(oracle, mol40, mol40_oracle):
         assert abs(X - mol40_oracle.X[i]) < 1e-13
 
 
+def test_hamiltonian_harmonic_ground_state(oracle):
+    """H = -1/2 Lap + 1/2 w^2 r^2 on the Gaussian exp(-w r^2 / 2): the 3-D
+    oscillator ground state, H psi = (3/2) w psi up to the stencil's error,
+    and a constant shift of v shifts H psi by that constant times psi."""
+    n, h, w = 64, 0.15, 2.0  # box edge psi ~ 2e-10: truncation below the stencil error
+    x = -h * (n - 1) / 2 + h * np.arange(n)
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    psi = np.exp(-0.5 * w * r2)[None]
+    v = 0.5 * w * w * r2
+    hp = oracle.hamiltonian(psi, v, h)
+    assert np.abs(hp - 1.5 * w * psi).max() < 1e-7
+    hs = oracle.hamiltonian(psi, v + 0.37, h)
+    assert np.abs(hs - hp - 0.37 * psi).max() < 1e-13
+
+
 def test_gaussian_potential_pointwise(oracle):
     """Potential of a centred Gaussian: erf(r / (sqrt2 sigma)) / r at every node."""
     n, h, sigma = 40, 0.3, 1.0
