@@ -50,16 +50,19 @@ struct Item {
     int orb, tile;
 };
 // Work lists of the three spectral-preconditioner passes (see dst.hip);
-// fast: every axis has at most 128 nodes (persistent bf16 split-operand
-// kernels over units of one 128-column panel, `blocks` blocks per pass), np:
-// largest axis padded to 32.
+// fast: 0 fp32 kernels (32-column panels); 1 persistent split-bf16 kernels
+// with 128-column panels; 2 the same with 64-column panels; 3 64-column
+// panels with the sine matrix rounded to bf16 (no S_lo term), for axes whose
+// split sine matrix does not fit the LDS.  np: largest axis padded to 32;
+// blocks: persistent blocks per pass.
 struct DstItems {
     const Item *x, *y, *z;
     int nx, ny, nz;
     int fast, np, blocks;
 };
 
-constexpr int kDstFastCols = 128;   // panel columns of the fast transform kernels
+// panel columns of a fast transform variant
+inline int dst_panel_cols(int variant) { return variant == 1 ? 128 : (variant ? 64 : 32); }
 
 struct Coeffs {
     double c[kMaxRadius + 1];  // unit-spacing second-difference weights

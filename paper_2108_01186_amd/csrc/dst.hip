@@ -227,9 +227,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
-constexpr int kFC = kDstFastCols;    // panel columns
-constexpr int kFT = 512;    // threads per block (8 waves, one column tile each)
-constexpr int kFV = kFC * 128 / kFT;  // panel values per thread and buffer (np <= 128): 32
+constexpr int kFT = 512;   // threads per block (8 waves)
+constexpr int kFV = 32;    // panel values per thread and buffer: np * PC / kFT <= 32
 
 __device__ __forceinline__ void bsplit(float x, __bf16 &hi, __bf16 &lo) {
     hi = (__bf16)x;
@@ -249,9 +248,9 @@ __device__ __forceinline__ double block_sum_fast(double v, double *sbuf) {
     return s;
 }
 
-size_t dst_fast_lds(int np) {
+size_t dst_fast_lds(int np, int pc, bool slo) {
     const int sw = np + 8;
-    return (size_t)2 * np * sw * 2 + (size_t)2 * kFC * sw * 2 + 16 * sizeof(double) +
+    return (size_t)(slo ? 2 : 1) * np * sw * 2 + (size_t)2 * pc * sw * 2 + 16 * sizeof(double) +
            (size_t)np * sizeof(float);
 }
 
@@ -272,7 +271,7 @@ __device__ __forceinline__ double dot4(const double *p, const float4 &v) {
     return a.x * v.x + a.y * v.y + b.x * v.z + b.y * v.w;
 }
 
-template <int AX, int MODE, typename TIN, typename TR, bool RZ>
+template <int AX, int MODE, typename TIN, typename TR, bool RZ, int PC, bool SLO>
 __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits, int npmax,
                                                   const OrbDesc *orb, const int *done,
                                                   const float *tab, const TIN *in, float *out,
@@ -281,11 +280,12 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
     // persistent: block b streams the units [u0, u1) (unit = orbital, panel);
     // the LDS layout is sized for the largest axis of the batch
     const int sw = npmax + 8;  // LDS row stride (bf16): 16-byte rows
+    constexpr int G = kFT / PC;  // threads per panel column in the loads
     __bf16 *Shi = reinterpret_cast<__bf16 *>(smem);
-    __bf16 *Slo = Shi + (size_t)npmax * sw;
-    __bf16 *Xhi = Slo + (size_t)npmax * sw;
-    __bf16 *Xlo = Xhi + (size_t)kFC * sw;
-    double *sred = reinterpret_cast<double *>(Xlo + (size_t)kFC * sw);  // kFT / 64 doubles
+    __bf16 *Slo = Shi + (size_t)npmax * sw;  // only with SLO
+    __bf16 *Xhi = Slo + (SLO ? (size_t)npmax * sw : 0);
+    __bf16 *Xlo = Xhi + (size_t)PC * sw;
+    double *sred = reinterpret_cast<double *>(Xlo + (size_t)PC * sw);  // kFT / 64 doubles
     const int t = threadIdx.x;
     const int u0 = (int)((long long)blockIdx.x * nunits / gridDim.x);
     const int u1 = (int)((long long)(blockIdx.x + 1) * nunits / gridDim.x);
@@ -318,29 +318,29 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         return AX == 0 && (od.nx & 3) == 0 && (od.off & 3) == 0;
     };
     // panel loads into v[kFV]: thread t holds column c_ld and, per i, either
-    // rows k = 2 kg + 8 i, k + 1 (pairs) or k = 4 kg + 16 i .. + 3 (x vectors)
-    const int c_ld = AX == 0 ? (t >> 2) : (t & (kFC - 1));
-    const int kg = AX == 0 ? (t & 3) : (t >> 7);
+    // rows k = 2 kg + 2 G i, k + 1 (pairs) or k = 4 kg + 4 G i .. + 3 (x vectors)
+    const int c_ld = AX == 0 ? (t / G) : (t % PC);
+    const int kg = AX == 0 ? (t % G) : (t / PC);
     auto load = [&](float (&v)[kFV], const OrbDesc &od, int pnl) {
         const int n = axis_n(od, AX);
         const int np = (n + 31) & ~31;
-        const long long cg = (long long)pnl * kFC + c_ld;
+        const long long cg = (long long)pnl * PC + c_ld;
         const bool cv = cg < ncol_of(od);
         const long long base = od.off + (cv ? eoff(od, cg) : 0);
         if (xvec(od)) {
 #pragma unroll
             for (int i = 0; i < kFV / 4; ++i) {
-                const int k = 4 * kg + 16 * i;
+                const int k = 4 * kg + 4 * G * i;
                 const float4 q = (k < np && cv && k < n) ? ld4(in + base + k) : float4{0.f, 0.f, 0.f, 0.f};
                 v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
             }
             return;
         }
         const long long ks = kstr_of(od);
-        const int npair = np >> 3;
+        const int npair = np / (2 * G);
 #pragma unroll
         for (int i = 0; i < kFV / 2; ++i) {
-            const int k = 2 * kg + 8 * i;
+            const int k = 2 * kg + 2 * G * i;
             v[2 * i] = (i < npair && cv && k < n) ? (float)in[base + (long long)k * ks] : 0.f;
             v[2 * i + 1] = (i < npair && cv && k + 1 < n) ? (float)in[base + (long long)(k + 1) * ks] : 0.f;
         }
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         if (xvec(od)) {
 #pragma unroll
             for (int i = 0; i < kFV / 4; ++i) {
-                const int k = 4 * kg + 16 * i;
+                const int k = 4 * kg + 4 * G * i;
                 if (k < np) {
                     __bf16 h[4], l[4];
 #pragma unroll
@@ -361,11 +361,11 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
             }
             return;
         }
-        const int npair = np >> 3;
+        const int npair = np / (2 * G);
 #pragma unroll
         for (int i = 0; i < kFV / 2; ++i) {
             if (i < npair) {
-                const int k = 2 * kg + 8 * i;
+                const int k = 2 * kg + 2 * G * i;
                 __bf16 h0, l0, h1, l1;
                 bsplit(v[2 * i], h0, l0);
                 bsplit(v[2 * i + 1], h1, l1);
@@ -375,11 +375,13 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         }
     };
 
-    // wave tiling: wave w owns column tile w and every row tile
+    // wave tiling: PC / 16 column tiles; the waves of a column tile split its
+    // row tiles (stride RS)
     const int lane = t & 63, w = t >> 6;
-    const int ct = w, r0 = 0;
-    constexpr int RS = 1;   // row-tile stride between the waves of a column tile
-    constexpr int MT = 8;   // row tiles per wave (np <= 128)
+    constexpr int NCT = PC / 16;
+    constexpr int RS = (kFT / 64) / NCT;
+    const int ct = w % NCT, r0 = w / NCT;
+    constexpr int MT = 8;   // row tiles per wave: np / 16 / RS <= 8
     const int lr = lane & 15, lq = lane >> 4;
     flt4 acc[MT];
     auto gemm = [&](int np) {
@@ -395,8 +397,10 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
                 const int rt = r0 + RS * i;
                 if (rt < nrt) {
                     const bf8 ah = *reinterpret_cast<const bf8 *>(Shi + (rt * 16 + lr) * sw + kb);
-                    const bf8 al = *reinterpret_cast<const bf8 *>(Slo + (rt * 16 + lr) * sw + kb);
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i], 0, 0, 0);
+                    if constexpr (SLO) {
+                        const bf8 al = *reinterpret_cast<const bf8 *>(Slo + (rt * 16 + lr) * sw + kb);
+                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i], 0, 0, 0);
+                    }
                     acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i], 0, 0, 0);
                     acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i], 0, 0, 0);
                 }
@@ -422,7 +426,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
                 __bf16 hi, lo;
                 bsplit(S[e], hi, lo);
                 Shi[m * sw + k] = hi;
-                Slo[m * sw + k] = lo;
+                if constexpr (SLO) Slo[m * sw + k] = lo;
             }
             if (MODE == 1)
                 for (int m = t; m < n; m += kFT) gzs[m] = tab[oc.dst_g[2] + m];
@@ -437,7 +441,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         gemm(np);
         const int nrt = np >> 4;
         const int c = ct * 16 + lr;
-        const long long cg = (long long)cur.tile * kFC + c;
+        const long long cg = (long long)cur.tile * PC + c;
         const bool cv = cg < ncol_of(oc);
         if (MODE == 1) {
             // scale by norm / lambda(jx, jy, m) and transform again
@@ -541,18 +545,25 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
     double *nd = nullptr;
     int *nc = nullptr;
     if (di.fast) {
-        const size_t lds = dst_fast_lds(di.np);
         auto grid = [&](int units) { return dim3((unsigned)std::min(units, di.blocks)); };
-        hipLaunchKernelGGL((k_dst_fast<0, 0, T, T, false>), grid(di.nx), dim3(kFT), lds, s, di.x,
-                           di.nx, di.np, orb, done, tab, r, work, nr, nd, cnt);
-        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false>), grid(di.ny), dim3(kFT), lds, s, di.y,
-                           di.ny, di.np, orb, done, tab, wk, work, nr, nd, nc);
-        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, false>), grid(di.nz), dim3(kFT), lds, s, di.z,
-                           di.nz, di.np, orb, done, tab, wk, work, nr, nd, nc);
-        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false>), grid(di.ny), dim3(kFT), lds, s, di.y,
-                           di.ny, di.np, orb, done, tab, wk, work, nr, nd, nc);
-        hipLaunchKernelGGL((k_dst_fast<0, 0, float, T, true>), grid(di.nx), dim3(kFT), lds, s, di.x,
-                           di.nx, di.np, orb, done, tab, wk, z, r, rz, nc);
+#define FSIC_DST_FAST(PC_, SLO_)                                                                   \
+    do {                                                                                           \
+        const size_t lds = dst_fast_lds(di.np, PC_, SLO_);                                         \
+        hipLaunchKernelGGL((k_dst_fast<0, 0, T, T, false, PC_, SLO_>), grid(di.nx), dim3(kFT),      \
+                           lds, s, di.x, di.nx, di.np, orb, done, tab, r, work, nr, nd, cnt);        \
+        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false, PC_, SLO_>), grid(di.ny), dim3(kFT),  \
+                           lds, s, di.y, di.ny, di.np, orb, done, tab, wk, work, nr, nd, nc);        \
+        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, false, PC_, SLO_>), grid(di.nz), dim3(kFT),  \
+                           lds, s, di.z, di.nz, di.np, orb, done, tab, wk, work, nr, nd, nc);        \
+        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false, PC_, SLO_>), grid(di.ny), dim3(kFT),  \
+                           lds, s, di.y, di.ny, di.np, orb, done, tab, wk, work, nr, nd, nc);        \
+        hipLaunchKernelGGL((k_dst_fast<0, 0, float, T, true, PC_, SLO_>), grid(di.nx), dim3(kFT),   \
+                           lds, s, di.x, di.nx, di.np, orb, done, tab, wk, z, r, rz, nc);            \
+    } while (0)
+        if (di.fast == 1) FSIC_DST_FAST(128, true);
+        else if (di.fast == 2) FSIC_DST_FAST(64, true);
+        else FSIC_DST_FAST(64, false);
+#undef FSIC_DST_FAST
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_dst_pass<0, 0, T, T, false>), dim3(di.nx), dim3(256), 0, s, di.x, orb,
@@ -570,16 +581,23 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
 
 // raise the dynamic-LDS limit of the fast transform kernels (once per batch,
 // outside any stream capture)
-hipError_t dst_setup(int np) {
-    const size_t lds = dst_fast_lds(np);
-    set_lds_limit(k_dst_fast<0, 0, float, float, false>, lds);
-    set_lds_limit(k_dst_fast<0, 0, double, double, false>, lds);
-    set_lds_limit(k_dst_fast<1, 0, float, float, false>, lds);
-    set_lds_limit(k_dst_fast<1, 0, float, double, false>, lds);
-    set_lds_limit(k_dst_fast<2, 1, float, float, false>, lds);
-    set_lds_limit(k_dst_fast<2, 1, float, double, false>, lds);
-    set_lds_limit(k_dst_fast<0, 0, float, float, true>, lds);
-    set_lds_limit(k_dst_fast<0, 0, float, double, true>, lds);
+hipError_t dst_setup(int np, int variant) {
+#define FSIC_DST_LIMITS(PC_, SLO_)                                                      \
+    do {                                                                                \
+        const size_t lds = dst_fast_lds(np, PC_, SLO_);                                 \
+        set_lds_limit(k_dst_fast<0, 0, float, float, false, PC_, SLO_>, lds);           \
+        set_lds_limit(k_dst_fast<0, 0, double, double, false, PC_, SLO_>, lds);         \
+        set_lds_limit(k_dst_fast<1, 0, float, float, false, PC_, SLO_>, lds);           \
+        set_lds_limit(k_dst_fast<1, 0, float, double, false, PC_, SLO_>, lds);          \
+        set_lds_limit(k_dst_fast<2, 1, float, float, false, PC_, SLO_>, lds);           \
+        set_lds_limit(k_dst_fast<2, 1, float, double, false, PC_, SLO_>, lds);          \
+        set_lds_limit(k_dst_fast<0, 0, float, float, true, PC_, SLO_>, lds);            \
+        set_lds_limit(k_dst_fast<0, 0, float, double, true, PC_, SLO_>, lds);           \
+    } while (0)
+    if (variant == 1) FSIC_DST_LIMITS(128, true);
+    else if (variant == 2) FSIC_DST_LIMITS(64, true);
+    else if (variant == 3) FSIC_DST_LIMITS(64, false);
+#undef FSIC_DST_LIMITS
     return hipGetLastError();
 }
 

@@ -106,11 +106,13 @@ hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *pa
 // dst.hip: spectral (type-I sine transform) preconditioner
 // ----------------------------------------------------------------------------
 
-// LDS bytes of a fast transform block for axes padded to np (<= 128) nodes.
-size_t dst_fast_lds(int np);
+// LDS bytes of a fast transform block for axes padded to np nodes, panels
+// of pc columns, with (slo) or without the sine matrix's low bf16 part.
+size_t dst_fast_lds(int np, int pc, bool slo);
 
-// Allows the fast transform kernels their dynamic LDS for axes up to np.
-hipError_t dst_setup(int np);
+// Allows the fast transform kernels of a variant (1..3, see DstItems) their
+// dynamic LDS for axes up to np.
+hipError_t dst_setup(int np, int variant);
 
 // z = M^{-1} r (float) for the orbitals of the work lists with done == 0,
 // through the float work array; r.z partial sums into rz[base9 + panel].

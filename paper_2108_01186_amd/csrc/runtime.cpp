@@ -158,7 +158,7 @@ struct Batch {
     std::vector<float> dtab;
     int tot9 = 0;
     int max_n = 0;
-    bool dst_fast = false;
+    int dst_fast = 0;  // transform variant (see DstItems)
 };
 
 void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<Item> &out) {
@@ -377,8 +377,15 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
         cols += (long long)g.count * ((g.n[0] + kTX - 1) / kTX) * ((g.n[1] + 8 * cpt - 1) / (8 * cpt));
     for (const Group &g : groups)
         for (int d = 0; d < 3; ++d) b.max_n = std::max(b.max_n, g.n[d]);
-    const bool fast = b.max_n <= 128 && dst_fast_lds((b.max_n + 31) & ~31) <= device_lds_limit();
-    b.dst_fast = fast;
+    // fastest transform variant whose LDS fits the device
+    const int npx = (b.max_n + 31) & ~31;
+    const size_t ldsmax = device_lds_limit();
+    int variant = 0;
+    if (npx <= 128 && dst_fast_lds(npx, 128, true) <= ldsmax) variant = 1;
+    else if (npx <= 256 && dst_fast_lds(npx, 64, true) <= ldsmax) variant = 2;
+    else if (npx <= 256 && dst_fast_lds(npx, 64, false) <= ldsmax) variant = 3;
+    const bool fast = variant != 0;
+    b.dst_fast = variant;
     std::vector<std::pair<int, int>> nat7, nat8, natx, naty, natz;
     std::map<int, std::pair<int, int>> dst_done;  // n -> (sine offset, symbol offset)
     auto dst_entry = [&](Batch &bb, int n, int radius_) -> const std::pair<int, int> & {
@@ -420,7 +427,7 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
             od.chan = g.chan;
             // preconditioner units: panels of 128 columns (fast) or 32
             auto nitem = [&](long long ncol) {
-                const int pc = fast ? kDstFastCols : 32;
+                const int pc = dst_panel_cols(variant);
                 return (int)((ncol + pc - 1) / pc);
             };
             od.nt9 = nitem((long long)g.n[1] * g.n[2]);
@@ -487,7 +494,7 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
         if ((st = upload(c, c->d_dy, b.dy))) return st;
         if ((st = upload(c, c->d_dz, b.dz))) return st;
         if ((st = upload(c, c->dtab, b.dtab))) return st;
-        if (b.dst_fast) HIPCHK(c, dst_setup((b.max_n + 31) & ~31));
+        if (b.dst_fast) HIPCHK(c, dst_setup((b.max_n + 31) & ~31, b.dst_fast));
         HIPCHK(c, c->Z32.ensure(F));
         HIPCHK(c, c->T32.ensure(F));
         HIPCHK(c, c->partRZ.ensure(2 * (size_t)b.tot9));
@@ -797,7 +804,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     const bool pcg = use_pcg(c, b);
     const bool graphs = (c->opts.flags & FSIC_GRAPHS) && !prof;
     DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(),
-                (int)b.dz.size(), b.dst_fast ? 1 : 0, (b.max_n + 31) & ~31, dst_blocks(c)};
+                (int)b.dz.size(), b.dst_fast, (b.max_n + 31) & ~31, dst_blocks(c)};
     if (pcg && !mixed) {
         // FP64 CG preconditioned by the FP32 sine-transform inverse
         CGIter<double> a{};

@@ -112,11 +112,15 @@ def test_poisson_vs_oracle(torch_cuda, F, oracle, n, h, precision, solver):
 
 
 @pytest.mark.parametrize("precision,n", [("fp64", (37, 29, 45)), ("mixed", (37, 29, 45)),
-                                         ("fp64", (136, 21, 18)), ("mixed", (19, 150, 17))])
+                                         ("fp64", (136, 21, 18)), ("mixed", (19, 150, 17)),
+                                         ("fp64", (190, 14, 12)), ("mixed", (12, 13, 185)),
+                                         ("fp64", (230, 9, 10))])
 def test_pcg_non_cubic_grid(torch_cuda, F, oracle, precision, n):
     """Preconditioned solve on a box with a different node count per axis
-    (ragged tiles of every sine transform), against the oracle; an axis above
-    128 nodes takes the fp32 transform kernels instead of the split-bf16 ones."""
+    (ragged tiles of every sine transform), against the oracle.  The longest
+    axis picks the transform variant: <= 128 nodes 128-column split-bf16
+    panels, 136-150 64-column ones, 185-190 the bf16 sine matrix without its
+    low part, 230 the fp32 kernels."""
     torch = torch_cuda
     _say(f"pcg non-cubic {precision} {n}")
     h = 0.28
