@@ -575,6 +575,59 @@ int orc_interp(const int *n, double h, const double *origin, int N, const double
 
 /* ------------------------------------------------------------------------ */
 /* Symmetric eigenproblem: cyclic Jacobi (Golub & Van Loan, Alg. 8.4.3)      */
+
+/* Per-node gradient of one grid field by first differences along each axis,
+ * the scheme of Sec. II.B: central (f[i+1] - f[i-1]) / 2h at inner nodes,
+ * forward (f[1] - f[0]) / h at the first node and backward
+ * (f[n-1] - f[n-2]) / h at the last.  g[3*M] holds the x, y and z
+ * components one after another. */
+int orc_grid_gradient(const int *n, double h, const double *f, double *g)
+{
+    if (!n || !f || !g || !(h > 0)) return ORC_EBADARG;
+    for (int d = 0; d < 3; ++d)
+        if (n[d] < 2) return ORC_EBADARG;
+    const long M = grid_size(n);
+    const long stride[3] = {1, n[0], (long)n[0] * n[1]};
+    for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    const long m = ((long)k * n[1] + j) * n[0] + i;
+                    const int q = (d == 0) ? i : (d == 1) ? j : k;
+                    const long s = stride[d];
+                    double v;
+                    if (q == 0)
+                        v = (f[m + s] - f[m]) / h;
+                    else if (q == n[d] - 1)
+                        v = (f[m] - f[m - s]) / h;
+                    else
+                        v = (f[m + s] - f[m - s]) / (2.0 * h);
+                    g[d * M + m] = v;
+                }
+    return 0;
+}
+
+/* psi_alpha(a) and grad psi_alpha(a) the way Sec. II.B builds them: the
+ * value by cubic interpolation, the gradient by first forming the per-node
+ * difference gradient of each orbital (orc_grid_gradient) and interpolating
+ * its three components at a with the same cubic scheme. */
+int orc_interp_fdgrad(const int *n, double h, const double *origin, int N, const double *psi,
+                      const double *a, double *u, double *du)
+{
+    if (!n || !origin || !psi || !a || !u || !du || N < 0) return ORC_EBADARG;
+    const long M = grid_size(n);
+    double *g = malloc(3 * M * sizeof(double));
+    if (!g) return ORC_EBADARG;
+    int st = 0;
+    for (int al = 0; al < N && !st; ++al) {
+        st = orc_interp(n, h, origin, 1, psi + (long)al * M, a, u + al, NULL);
+        if (!st) st = orc_grid_gradient(n, h, psi + (long)al * M, g);
+        if (!st) st = orc_interp(n, h, origin, 3, g, a, du + 3 * al, NULL);
+    }
+    free(g);
+    return st;
+}
+
 /* ------------------------------------------------------------------------ */
 
 int orc_jacobi_eig(int N, const double *A, double *lam, double *U)
@@ -663,7 +716,7 @@ static void fwd_free(fwd_t *f)
 
 static int forward_impl(const int *n, double h, const double *origin, int p, int lmax,
                         double tol, int maxit, double rho_floor, int N, const double *psi,
-                        const double *fod, fwd_t *f, int flo_only)
+                        const double *fod, fwd_t *f, int flo_only, int gmode)
 {
     memset(f, 0, sizeof(*f));
     if (!n || !origin || !psi || !fod || N < 1 || h <= 0) return ORC_EBADARG;
@@ -694,13 +747,25 @@ static int forward_impl(const int *n, double h, const double *origin, int p, int
      * with f = 1; T_i,alpha = psi_alpha(a_i) / sqrt(rho(a_i))  (Sec. II.B, Eq. 8) */
     for (int i = 0; i < N; ++i) {
         int st = orc_interp(n, h, origin, N, psi, fod + 3 * i, f->u + (long)i * N,
-                            f->du + (long)i * N * 3);
+                            gmode ? NULL : f->du + (long)i * N * 3);
         if (st) return st;
         double s = 0.0;
         for (int al = 0; al < N; ++al) s += f->u[i * N + al] * f->u[i * N + al];
         if (!(s > rho_floor)) return ORC_EVACUUM;
         f->rhoa[i] = s;
         for (int al = 0; al < N; ++al) f->T[i * N + al] = f->u[i * N + al] / sqrt(s);
+    }
+    if (gmode) {
+        /* grad psi_alpha(a_i) as Sec. II.B builds it: per-node differences of
+         * each orbital, interpolated at the FODs like the values */
+        double *g = malloc(3 * M * sizeof(double));
+        if (!g) return ORC_EBADARG;
+        for (int al = 0; al < N; ++al) {
+            orc_grid_gradient(n, h, psi + (long)al * M, g);
+            for (int i = 0; i < N; ++i)
+                orc_interp(n, h, origin, 3, g, fod + 3 * i, f->du + ((long)i * N + al) * 3, NULL);
+        }
+        free(g);
     }
     /* Fermi orbitals F_i = sum_alpha T_i,alpha psi_alpha  (Eq. 6-7) */
 #pragma omp parallel for schedule(static)
@@ -765,7 +830,7 @@ static int forward(const int *n, double h, const double *origin, int p, int lmax
                    int maxit, double rho_floor, int N, const double *psi, const double *fod,
                    fwd_t *f)
 {
-    return forward_impl(n, h, origin, p, lmax, tol, maxit, rho_floor, N, psi, fod, f, 0);
+    return forward_impl(n, h, origin, p, lmax, tol, maxit, rho_floor, N, psi, fod, f, 0, 0);
 }
 
 int orc_flo_spin(const int *n, double h, const double *origin, double rho_floor, int N,
@@ -773,7 +838,7 @@ int orc_flo_spin(const int *n, double h, const double *origin, double rho_floor,
                  double *Z)
 {
     fwd_t f;
-    int st = forward_impl(n, h, origin, 1, 0, 1e-10, 1, rho_floor, N, psi, fod, &f, 1);
+    int st = forward_impl(n, h, origin, 1, 0, 1e-10, 1, rho_floor, N, psi, fod, &f, 1, 0);
     if (st == 0) {
         const long M = grid_size(n);
         if (phi) memcpy(phi, f.phi, (size_t)N * M * sizeof(double));
@@ -874,102 +939,184 @@ static void matmul(int r, int k, int c, const double *A, const double *B, double
         }
 }
 
+/* Tangent of Q = Z T (phi = Q psi) along FOD coordinate (mi, d):
+ * row mi of T moves as T_m = u_m / |u_m| (Eq. 8, and Eq. 11 in a form free of
+ * 1/psi), S = T G T^T moves as dS = dT G T^T + T G dT^T, Z = S^{-1/2} moves by
+ * the Frechet derivative dZ = U [(U^T dS U) o K] U^T, and dQ = dZ T + Z dT. */
+typedef struct {
+    int N;
+    const fwd_t *f;
+    double *K, *TG, *UT, *dT, *dS, *dZ, *tmp, *tmp2;
+} tangent_t;
+
+static int tangent_init(tangent_t *t, const fwd_t *f, const double *G)
+{
+    const int N = f->N;
+    const size_t bytes = (size_t)N * N * sizeof(double);
+    t->N = N;
+    t->f = f;
+    t->K = malloc(bytes); t->TG = malloc(bytes); t->UT = malloc(bytes); t->dT = malloc(bytes);
+    t->dS = malloc(bytes); t->dZ = malloc(bytes); t->tmp = malloc(bytes); t->tmp2 = malloc(bytes);
+    if (!t->K || !t->TG || !t->UT || !t->dT || !t->dS || !t->dZ || !t->tmp || !t->tmp2)
+        return ORC_EBADARG;
+    /* K_jk = (lam_j^{-1/2} - lam_k^{-1/2}) / (lam_j - lam_k) in its stable form */
+    for (int j = 0; j < N; ++j)
+        for (int k = 0; k < N; ++k) {
+            double sj = sqrt(f->lam[j]), sk = sqrt(f->lam[k]);
+            t->K[j * N + k] = -1.0 / (sj * sk * (sj + sk));
+        }
+    matmul(N, N, N, f->T, G, t->TG); /* T G */
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) t->UT[i * N + j] = f->Us[j * N + i];
+    return 0;
+}
+
+static void tangent_free(tangent_t *t)
+{
+    free(t->K); free(t->TG); free(t->UT); free(t->dT); free(t->dS); free(t->dZ);
+    free(t->tmp); free(t->tmp2);
+}
+
+static void tangent_dQ(tangent_t *t, int mi, int d, double *dQ)
+{
+    const int N = t->N;
+    const fwd_t *f = t->f;
+    const double norm = sqrt(f->rhoa[mi]);
+    double *dT = t->dT, *dS = t->dS, *dZ = t->dZ, *tmp = t->tmp, *tmp2 = t->tmp2;
+    memset(dT, 0, (size_t)N * N * sizeof(double));
+    double tdu = 0.0;
+    for (int al = 0; al < N; ++al) tdu += f->T[mi * N + al] * f->du[((long)mi * N + al) * 3 + d];
+    for (int al = 0; al < N; ++al)
+        dT[mi * N + al] = (f->du[((long)mi * N + al) * 3 + d] - tdu * f->T[mi * N + al]) / norm;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < N; ++q)
+                s += dT[i * N + q] * t->TG[j * N + q] + t->TG[i * N + q] * dT[j * N + q];
+            dS[i * N + j] = s;
+        }
+    matmul(N, N, N, t->UT, dS, tmp);
+    matmul(N, N, N, tmp, f->Us, tmp2);
+    for (int q = 0; q < N * N; ++q) tmp2[q] *= t->K[q];
+    matmul(N, N, N, f->Us, tmp2, tmp);
+    matmul(N, N, N, tmp, t->UT, dZ);
+    matmul(N, N, N, dZ, f->T, tmp);
+    matmul(N, N, N, f->Z, dT, tmp2);
+    for (int q = 0; q < N * N; ++q) dQ[q] = tmp[q] + tmp2[q];
+}
+
+int orc_sic_grad_spin_mode(const int *n, double h, const double *origin, int p, int lmax,
+                           double tol, int maxit, double rho_floor,
+                           int N, const double *psi, const double *fod, int gmode, int form,
+                           double *dEda)
+{
+    if (!dEda || gmode < 0 || gmode > 1 || form < 0 || form > 1) return ORC_EBADARG;
+    fwd_t f;
+    int st = forward_impl(n, h, origin, p, lmax, tol, maxit, rho_floor, N, psi, fod, &f, 0, gmode);
+    if (st && st != ORC_ENOCONV) { fwd_free(&f); return st; }
+    const long M = f.M;
+    const double dV = h * h * h;
+    double *G = malloc((size_t)N * N * sizeof(double));
+    double *dQ = malloc((size_t)N * N * sizeof(double));
+    tangent_t tg;
+    memset(&tg, 0, sizeof(tg));
+    int st2 = (!G || !dQ) ? ORC_EBADARG : 0;
+    if (!st2) {
+        for (int i = 0; i < N; ++i)
+            for (int al = 0; al < N; ++al)
+                G[i * N + al] = dV * dot(M, psi + (long)i * M, psi + (long)al * M);
+        st2 = tangent_init(&tg, &f, G);
+    }
+    if (!st2 && form == 0) {
+        /* exact derivative of the discrete E_SIC.  With respect to phi_i(r):
+         *   dE/dphi_i = 2 dV phi_i omega_i,
+         *   omega_i = -( (1/2)(v_i + A^T rho_i) + v_xc(rho_i) ),
+         * because U_i = (1/2) dV rho_i^T A rho_i and dE_xc/drho = dV v_xc.
+         * phi = Q psi, so dE = sum_{i,alpha} dQ_i,alpha B_i,alpha, B = Gam psi^T. */
+        double *Gam = malloc((size_t)N * M * sizeof(double));
+        double *B = malloc((size_t)N * N * sizeof(double));
+        if (!Gam || !B) st2 = ORC_EBADARG;
+        const int nrun = st2 ? 0 : N;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int i = 0; i < nrun; ++i) {
+            double *rho = malloc(M * sizeof(double));
+            double *at = malloc(M * sizeof(double));
+            const double *ph = f.phi + (long)i * M;
+            for (long m = 0; m < M; ++m) rho[m] = ph[m] * ph[m];
+            int s = orc_poisson_transpose(n, h, origin, p, lmax, rho, tol, maxit, at, NULL, NULL);
+            if (s) {
+#pragma omp critical
+                st2 = s;
+            }
+            for (long m = 0; m < M; ++m) {
+                double ex, ec, vx, vc;
+                orc_xc_pol(rho[m], rho_floor, &ex, &ec, &vx, &vc);
+                double om = -(0.5 * (f.v[(long)i * M + m] + at[m]) + vx + vc);
+                Gam[(long)i * M + m] = 2.0 * dV * ph[m] * om;
+            }
+            free(rho); free(at);
+        }
+        if (B && Gam)
+            for (int i = 0; i < N; ++i)
+                for (int al = 0; al < N; ++al) B[i * N + al] = dot(M, Gam + (long)i * M, psi + (long)al * M);
+        for (int mi = 0; mi < N && B && Gam; ++mi)
+            for (int d = 0; d < 3; ++d) {
+                tangent_dQ(&tg, mi, d, dQ);
+                double dE = 0.0;
+                for (int q = 0; q < N * N; ++q) dE += dQ[q] * B[q];
+                dEda[mi * 3 + d] = dE;
+            }
+        free(Gam); free(B);
+    } else if (!st2) {
+        /* Eq. 9: dE/da_m = sum_kl eps_kl ( <dphi_k/da_m|phi_l> - <dphi_l/da_m|phi_k> )
+         * with eps_kl = <phi_l| V_k |phi_k> and the orbital SIC potential
+         * V_k = -(v_k + v_xc(rho_k)) of Eq. 5 */
+        double *eps = malloc((size_t)N * N * sizeof(double));
+        double *Vphi = malloc((size_t)N * M * sizeof(double));
+        double *dphi = malloc((size_t)N * M * sizeof(double));
+        double *A = malloc((size_t)N * N * sizeof(double));
+        if (!eps || !Vphi || !dphi || !A) st2 = ORC_EBADARG;
+        const int nrun = st2 ? 0 : N;
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < nrun; ++k)
+            for (long m = 0; m < M; ++m) {
+                const double ph = f.phi[(long)k * M + m];
+                double ex, ec, vx, vc;
+                orc_xc_pol(ph * ph, rho_floor, &ex, &ec, &vx, &vc);
+                Vphi[(long)k * M + m] = -(f.v[(long)k * M + m] + vx + vc) * ph;
+            }
+        for (int k = 0; k < nrun; ++k)
+            for (int l = 0; l < N; ++l) eps[k * N + l] = dV * dot(M, f.phi + (long)l * M, Vphi + (long)k * M);
+        for (int mi = 0; mi < nrun; ++mi)
+            for (int d = 0; d < 3; ++d) {
+                tangent_dQ(&tg, mi, d, dQ);
+                /* dphi_k = sum_alpha dQ_k,alpha psi_alpha; A_kl = <dphi_k | phi_l> */
+#pragma omp parallel for schedule(static)
+                for (int k = 0; k < N; ++k)
+                    for (long m = 0; m < M; ++m) {
+                        double sacc = 0.0;
+                        for (int al = 0; al < N; ++al) sacc += dQ[k * N + al] * psi[(long)al * M + m];
+                        dphi[(long)k * M + m] = sacc;
+                    }
+                for (int k = 0; k < N; ++k)
+                    for (int l = 0; l < N; ++l) A[k * N + l] = dV * dot(M, dphi + (long)k * M, f.phi + (long)l * M);
+                double dE = 0.0;
+                for (int k = 0; k < N; ++k)
+                    for (int l = 0; l < N; ++l) dE += eps[k * N + l] * (A[k * N + l] - A[l * N + k]);
+                dEda[mi * 3 + d] = dE;
+            }
+        free(eps); free(Vphi); free(dphi); free(A);
+    }
+    tangent_free(&tg);
+    free(G); free(dQ);
+    fwd_free(&f);
+    return st2 ? st2 : st;
+}
+
 int orc_sic_grad_spin(const int *n, double h, const double *origin, int p, int lmax,
                       double tol, int maxit, double rho_floor,
                       int N, const double *psi, const double *fod, double *dEda)
 {
-    if (!dEda) return ORC_EBADARG;
-    fwd_t f;
-    int st = forward(n, h, origin, p, lmax, tol, maxit, rho_floor, N, psi, fod, &f);
-    if (st && st != ORC_ENOCONV) { fwd_free(&f); return st; }
-    const long M = f.M;
-    const double dV = h * h * h;
-    /* derivative of E_SIC with respect to phi_i(r):
-     *   dE/dphi_i = 2 dV phi_i omega_i,
-     *   omega_i = -( (1/2)(v_i + A^T rho_i) + v_xc(rho_i) ),
-     * because U_i = (1/2) dV rho_i^T A rho_i and dE_xc/drho = dV v_xc. */
-    double *Gam = malloc((size_t)N * M * sizeof(double));
-    if (!Gam) { fwd_free(&f); return ORC_EBADARG; }
-    int st2 = 0;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int i = 0; i < N; ++i) {
-        double *rho = malloc(M * sizeof(double));
-        double *at = malloc(M * sizeof(double));
-        const double *ph = f.phi + (long)i * M;
-        for (long m = 0; m < M; ++m) rho[m] = ph[m] * ph[m];
-        int s = orc_poisson_transpose(n, h, origin, p, lmax, rho, tol, maxit, at, NULL, NULL);
-        if (s) {
-#pragma omp critical
-            st2 = s;
-        }
-        for (long m = 0; m < M; ++m) {
-            double ex, ec, vx, vc;
-            orc_xc_pol(rho[m], rho_floor, &ex, &ec, &vx, &vc);
-            double om = -(0.5 * (f.v[(long)i * M + m] + at[m]) + vx + vc);
-            Gam[(long)i * M + m] = 2.0 * dV * ph[m] * om;
-        }
-        free(rho); free(at);
-    }
-    /* phi = Q psi with Q = Z T, so dE = sum_{i,alpha} dQ_i,alpha B_i,alpha, B = Gam psi^T */
-    double *B = malloc((size_t)N * N * sizeof(double));
-    double *G = malloc((size_t)N * N * sizeof(double));
-    for (int i = 0; i < N; ++i)
-        for (int al = 0; al < N; ++al) {
-            B[i * N + al] = dot(M, Gam + (long)i * M, psi + (long)al * M);
-            G[i * N + al] = dV * dot(M, psi + (long)i * M, psi + (long)al * M);
-        }
-    free(Gam);
-    /* Frechet derivative of S^{-1/2}: dZ = U [(U^T dS U) o K] U^T with
-     * K_jk = (lam_j^{-1/2} - lam_k^{-1/2}) / (lam_j - lam_k) in its stable form */
-    double *K = malloc((size_t)N * N * sizeof(double));
-    for (int j = 0; j < N; ++j)
-        for (int k = 0; k < N; ++k) {
-            double sj = sqrt(f.lam[j]), sk = sqrt(f.lam[k]);
-            K[j * N + k] = -1.0 / (sj * sk * (sj + sk));
-        }
-    double *dT = calloc((size_t)N * N, sizeof(double));
-    double *tmp = malloc((size_t)N * N * sizeof(double));
-    double *tmp2 = malloc((size_t)N * N * sizeof(double));
-    double *dS = malloc((size_t)N * N * sizeof(double));
-    double *dZ = malloc((size_t)N * N * sizeof(double));
-    double *TG = malloc((size_t)N * N * sizeof(double));
-    double *UT = malloc((size_t)N * N * sizeof(double));
-    matmul(N, N, N, f.T, G, TG); /* T G */
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) UT[i * N + j] = f.Us[j * N + i];
-    for (int mi = 0; mi < N; ++mi) {
-        const double norm = sqrt(f.rhoa[mi]);
-        for (int d = 0; d < 3; ++d) {
-            /* row mi of T changes: T_m = u_m / |u_m| (Eq. 8, 11 in non-singular form) */
-            memset(dT, 0, (size_t)N * N * sizeof(double));
-            double tdu = 0.0;
-            for (int al = 0; al < N; ++al) tdu += f.T[mi * N + al] * f.du[((long)mi * N + al) * 3 + d];
-            for (int al = 0; al < N; ++al)
-                dT[mi * N + al] = (f.du[((long)mi * N + al) * 3 + d] - tdu * f.T[mi * N + al]) / norm;
-            /* dS = dT G T^T + T G dT^T */
-            for (int i = 0; i < N; ++i)
-                for (int j = 0; j < N; ++j) {
-                    double s = 0.0;
-                    for (int q = 0; q < N; ++q)
-                        s += dT[i * N + q] * TG[j * N + q] + TG[i * N + q] * dT[j * N + q];
-                    dS[i * N + j] = s;
-                }
-            /* dZ = U [(U^T dS U) o K] U^T */
-            matmul(N, N, N, UT, dS, tmp);
-            matmul(N, N, N, tmp, f.Us, tmp2);
-            for (int q = 0; q < N * N; ++q) tmp2[q] *= K[q];
-            matmul(N, N, N, f.Us, tmp2, tmp);
-            matmul(N, N, N, tmp, UT, dZ);
-            /* dQ = dZ T + Z dT;  dE = <dQ, B> */
-            double dE = 0.0;
-            matmul(N, N, N, dZ, f.T, tmp);
-            matmul(N, N, N, f.Z, dT, tmp2);
-            for (int q = 0; q < N * N; ++q) dE += (tmp[q] + tmp2[q]) * B[q];
-            dEda[mi * 3 + d] = dE;
-        }
-    }
-    free(B); free(G); free(K); free(dT); free(tmp); free(tmp2); free(dS); free(dZ);
-    free(TG); free(UT);
-    fwd_free(&f);
-    return st ? st : st2;
+    return orc_sic_grad_spin_mode(n, h, origin, p, lmax, tol, maxit, rho_floor, N, psi, fod, 0, 0,
+                                  dEda);
 }

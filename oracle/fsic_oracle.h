@@ -74,6 +74,17 @@ void orc_xc_pol(double rho, double rho_floor, double *ex, double *ec, double *vx
 int orc_interp(const int *n, double h, const double *origin, int N, const double *psi,
                const double *a, double *u, double *du);
 
+/* Per-node gradient of one field by first differences along each axis
+ * (Sec. II.B): central inside, forward at the first node, backward at the
+ * last.  g[3*M] = x, y, z components; every n[d] >= 2. */
+int orc_grid_gradient(const int *n, double h, const double *f, double *g);
+
+/* Values u[N] by cubic interpolation and gradients du[N*3] by interpolating
+ * orc_grid_gradient's per-node gradient with the same cubic scheme
+ * (Sec. II.B's construction of grad psi at the FODs). */
+int orc_interp_fdgrad(const int *n, double h, const double *origin, int N, const double *psi,
+                      const double *a, double *u, double *du);
+
 /* Cyclic Jacobi eigen-decomposition of a symmetric N x N matrix:
  * A = U diag(lam) U^T, U column j = eigenvector j (row-major U[i*N+j]). */
 int orc_jacobi_eig(int N, const double *A, double *lam, double *U);
@@ -102,6 +113,17 @@ int orc_sic_spin(const int *n, double h, const double *origin, int p, int lmax,
 int orc_sic_grad_spin(const int *n, double h, const double *origin, int p, int lmax,
                       double tol, int maxit, double rho_floor,
                       int N, const double *psi, const double *fod, double *dEda);
+
+/* Same gradient with a choice of ingredients:
+ *   gmode 0: grad psi(a_i) = derivative of the cubic interpolant;
+ *   gmode 1: grad psi(a_i) = interpolated per-node differences (Sec. II.B);
+ *   form 0:  exact derivative of the discrete E_SIC (adjoint Poisson solves);
+ *   form 1:  Eq. 9 with eps_kl = <phi_l|V_k|phi_k>, V_k = -(v_k + vxc_k) (Eq. 5),
+ *            which treats the Poisson map as symmetric (no adjoint solves). */
+int orc_sic_grad_spin_mode(const int *n, double h, const double *origin, int p, int lmax,
+                           double tol, int maxit, double rho_floor,
+                           int N, const double *psi, const double *fod, int gmode, int form,
+                           double *dEda);
 
 /* Fermi-Loewdin orbitals only (steps (a) and (b) of orc_sic_spin):
  * phi[N*M]; T, S, Z may be NULL. */

@@ -183,6 +183,28 @@ def interp(psi, n, h, origin, a):
     return u, du
 
 
+def grid_gradient(f, n, h):
+    """per-node difference gradient (3, M) of one field (Sec. II.B)."""
+    n = np.asarray(n, dtype=np.int32).copy()
+    f = _f64(f).reshape(-1)
+    g = np.zeros((3, f.size))
+    _check(lib().orc_grid_gradient(_i(n), ctypes.c_double(h), _d(f), _d(g)))
+    return g
+
+
+def interp_fdgrad(psi, n, h, origin, a):
+    """values u[N] and interpolated per-node difference gradients du[N,3] at a."""
+    n, origin = _grid(n, origin)
+    psi = _f64(psi)
+    N = psi.shape[0]
+    a = _f64(a)
+    u = np.zeros(N)
+    du = np.zeros((N, 3))
+    _check(lib().orc_interp_fdgrad(_i(n), ctypes.c_double(h), _d(origin), N, _d(psi), _d(a), _d(u),
+                                   _d(du)))
+    return u, du
+
+
 def jacobi_eig(A):
     A = _f64(A)
     N = A.shape[0]
@@ -249,16 +271,20 @@ def num_threads():
     return int(lib().orc_num_threads())
 
 
-def sic_grad_spin(psi, fod, n, h, origin, p=6, lmax=6, tol=1e-13, maxit=20000, rho_floor=1e-30):
-    """dE_SIC/da for one spin channel, shape (N, 3)."""
+def sic_grad_spin(psi, fod, n, h, origin, p=6, lmax=6, tol=1e-13, maxit=20000, rho_floor=1e-30,
+                  fd_gradient=False, eq9=False):
+    """dE_SIC/da for one spin channel, shape (N, 3).  fd_gradient: grad psi at
+    the FODs from interpolated per-node differences (Sec. II.B) instead of the
+    interpolant's derivative; eq9: the Eq. 9 form with V_k = -(v_k + vxc_k)
+    instead of the exact derivative of the discrete energy."""
     n, origin = _grid(n, origin)
     psi = _f64(psi).reshape(psi.shape[0], -1)
     fod = _f64(fod).reshape(-1, 3)
     N = psi.shape[0]
     g = np.zeros((N, 3))
-    st = lib().orc_sic_grad_spin(_i(n), ctypes.c_double(h), _d(origin), p, lmax,
-                                 ctypes.c_double(tol), maxit, ctypes.c_double(rho_floor), N,
-                                 _d(psi), _d(fod), _d(g))
+    st = lib().orc_sic_grad_spin_mode(_i(n), ctypes.c_double(h), _d(origin), p, lmax,
+                                      ctypes.c_double(tol), maxit, ctypes.c_double(rho_floor), N,
+                                      _d(psi), _d(fod), int(bool(fd_gradient)), int(bool(eq9)), _d(g))
     _check(st)
     return g
 

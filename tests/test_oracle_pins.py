@@ -341,6 +341,76 @@ def test_interp_boundary_rejected(oracle):
         oracle.interp(psi, (n, n, n), h, origin, np.array([2.0, 2.0, h * (n - 2) + 0.1]))  # i0 = n-2
 
 
+def test_grid_gradient_closed_forms(oracle):
+    """Per-node differences of a quadratic (Sec. II.B): central differences are
+    exact inside; the one-sided differences at the first and last node carry
+    the known +-h f''/2 term.  A non-cubic grid pins the axis strides."""
+    n, h = (7, 9, 6), 0.3
+    origin = np.array([-0.7, 0.2, 1.1])
+    x = [origin[d] + h * np.arange(n[d]) for d in range(3)]
+    Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    f = X ** 2 + 3 * Y ** 2 - Z ** 2 + X * Y + 2.0
+    g = oracle.grid_gradient(f, n, h).reshape(3, n[2], n[1], n[0])
+    ex = 2 * X + Y
+    ex[:, :, 0] += h
+    ex[:, :, -1] -= h
+    ey = 6 * Y + X
+    ey[:, 0, :] += 3 * h
+    ey[:, -1, :] -= 3 * h
+    ez = -2 * Z
+    ez[0] -= h
+    ez[-1] += h
+    for d, e in enumerate((ex, ey, ez)):
+        assert np.abs(g[d] - e).max() < 1e-12, d
+
+
+def test_interp_fdgrad_cubic_closed_form(oracle):
+    """Away from the edges the central difference of x^3 is 3x^2 + h^2, and the
+    cubic interpolant reproduces it exactly: the paper-mode gradient exceeds
+    the interpolant's derivative by exactly h^2 in x, and agrees in y and z
+    (their differences are exact on this field)."""
+    rng = np.random.default_rng(11)
+    n, h = 13, 0.25
+    origin = np.array([0.3, -1.0, 0.8])
+    x = [origin[d] + h * np.arange(n) for d in range(3)]
+    Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    psi = np.stack([(X ** 3 + Y ** 2 * Z + 0.5 * X * Y).reshape(-1),
+                    (2 * Z ** 2 - X * Z).reshape(-1)])
+    for _ in range(8):
+        a = origin + h * rng.uniform(2.0, n - 4.0 - 1e-9, size=3)
+        u, du = oracle.interp_fdgrad(psi, (n, n, n), h, origin, a)
+        u0, du0 = oracle.interp(psi, (n, n, n), h, origin, a)
+        ax, ay, az = a
+        assert np.allclose(u, u0, rtol=0, atol=1e-12)
+        assert abs(u[0] - (ax ** 3 + ay ** 2 * az + 0.5 * ax * ay)) < 1e-11
+        assert np.allclose(du[0], [3 * ax ** 2 + h ** 2 + 0.5 * ay, 2 * ay * az + 0.5 * ax, ay ** 2],
+                           rtol=0, atol=1e-10)
+        assert np.allclose(du[1], [-az, 0.0, 4 * az - ax], rtol=0, atol=1e-10)
+        assert abs((du[0, 0] - du0[0, 0]) - h ** 2) < 1e-10
+
+
+def test_interp_fdgrad_edge_nodes(oracle):
+    """An FOD whose stencil touches the first or last node picks up that node's
+    one-sided difference: for f = x^2 the gradient is 2a + h w_0(t) at the
+    lower edge and 2a - h w_3(t) at the upper edge (w = Lagrange weights on
+    the nodes -1, 0, 1, 2)."""
+    n, h = 10, 0.4
+    origin = np.zeros(3)
+    x = h * np.arange(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    psi = (X ** 2).reshape(1, -1)
+    for t in (0.1, 0.55, 0.9):
+        a = np.array([h * (1 + t), h * 4.3, h * 5.6])  # i0 = 1: node 0 in the stencil
+        du = oracle.interp_fdgrad(psi, (n, n, n), h, origin, a)[1]
+        w0 = -t * (t - 1) * (t - 2) / 6
+        assert abs(du[0, 0] - (2 * a[0] + h * w0)) < 1e-12
+        assert abs(du[0, 1]) < 1e-12 and abs(du[0, 2]) < 1e-12
+        a = np.array([h * (n - 3 + t), h * 4.3, h * 5.6])  # i0 = n - 3: node n - 1 in it
+        du = oracle.interp_fdgrad(psi, (n, n, n), h, origin, a)[1]
+        w3 = (t + 1) * t * (t - 1) / 6
+        assert abs(du[0, 0] - (2 * a[0] - h * w3)) < 1e-12
+
+
 # ---------------------------------------------------------------------------
 # symmetric eigenproblem used for S^{-1/2}
 # ---------------------------------------------------------------------------
@@ -448,8 +518,10 @@ def test_one_electron_s_gaussian(oracle):
     assert abs(r.U[0] - U) < 1e-7
     assert abs(r.X[0] - (Ex + Ec)) < 1e-6
     assert abs(e[0] + U + Ex + Ec) < 2e-6
-    grad = oracle.sic_grad_spin(psi, np.array([[0.1, -0.2, 0.3]]), (n, n, n), h, origin)
-    assert np.abs(grad).max() < 1e-12
+    for fdg, eq9 in ((False, False), (True, False), (False, True), (True, True)):
+        grad = oracle.sic_grad_spin(psi, np.array([[0.1, -0.2, 0.3]]), (n, n, n), h, origin,
+                                    fd_gradient=fdg, eq9=eq9)
+        assert np.abs(grad).max() < 1e-12, (fdg, eq9)
 
 
 def test_gradient_matches_central_differences(oracle, mol40):
@@ -473,3 +545,86 @@ def test_gradient_matches_central_differences(oracle, mol40):
         assert abs(fd - g[i, d]) < 1e-8, (i, d, fd, g[i, d])
         checked += 1
     assert checked >= 4
+
+
+def _skip_fd(s, i, d, eps):
+    t = (s.fod[0][i, d] - s.origin[d]) / s.h
+    return math.floor(t + eps / s.h) != math.floor(t - eps / s.h)
+
+
+def test_eq9_is_frozen_potential_derivative(oracle, mol40, mol40_oracle):
+    """Eq. 9 is the exact derivative of F(a) = dV sum_k <phi_k(a)| V_k |phi_k(a)>
+    with the orbital SIC potentials V_k = -(v_k + vxc_k) frozen at the current
+    FODs: orthonormality of the FLOs makes <dphi_k|phi_l> antisymmetric, which
+    turns 2 sum A_kl eps_kl into Eq. 9's bracket.  Central differences of F
+    (step 1e-4 Bohr) through the Fermi-Loewdin map alone check eps, the
+    antisymmetric combination and the Loewdin tangent together."""
+    s, r = mol40, mol40_oracle
+    g = oracle.sic_grad_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin, eq9=True)
+    xc = oracle.xc_pol(r.phi ** 2)
+    V = -(r.v + xc[2] + xc[3])
+    dV = s.h ** 3
+
+    def F(fod):
+        phi = oracle.flo_spin(s.psi[0], fod, s.n, s.h, s.origin)[0]
+        return dV * float((V * phi * phi).sum())
+
+    eps = 1e-4
+    checked = 0
+    for (i, d) in [(0, 2), (1, 0), (2, 1), (3, 0), (4, 2)]:
+        if _skip_fd(s, i, d, eps):
+            continue
+        f = s.fod[0].copy()
+        f[i, d] += eps
+        fp = F(f)
+        f[i, d] -= 2 * eps
+        fm = F(f)
+        fd = (fp - fm) / (2 * eps)
+        assert abs(fd - g[i, d]) < 1e-8, (i, d, fd, g[i, d])
+        checked += 1
+    assert checked >= 3
+
+
+def test_paper_mode_gradients_close_to_exact(oracle, mol40):
+    """The Eq. 9 form differs from the exact discrete gradient only through the
+    boundary part of the Poisson map (small for densities inside the box); the
+    per-node difference gradient is an O(h^2) approximation of grad psi, which
+    at h = 0.3 Bohr moves the forces by a visible fraction of the largest one.
+    Eq. 9 and the exact form stay as close with either grad psi."""
+    s = mol40
+    g = {}
+    for fdg in (False, True):
+        for eq9 in (False, True):
+            g[fdg, eq9] = oracle.sic_grad_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin,
+                                               fd_gradient=fdg, eq9=eq9)
+    scale = np.abs(g[False, False]).max()
+    for fdg in (False, True):
+        rel = np.abs(g[fdg, True] - g[fdg, False]).max() / scale
+        assert 0 < rel < 1e-4, (fdg, rel)
+    rel = np.abs(g[True, False] - g[False, False]).max() / scale
+    assert 1e-3 < rel < 0.3, rel
+
+
+def test_fd_gradient_second_order(oracle):
+    """Interpolated per-node differences of a Gaussian converge to its analytic
+    gradient at second order in h (the central-difference error h^2 f'''/6
+    dominates the cubic interpolation's O(h^4)); the interpolant's own
+    derivative converges faster (third order, with a constant that depends on
+    where the point falls in its cell) and is the more accurate at both h."""
+    a = np.array([0.113, -0.271, 0.352])
+    alpha = 0.8
+    err_fd, err_ex = [], []
+    for h in (0.2, 0.1):
+        n = int(round(6.0 / h)) + 1
+        origin = np.full(3, -3.0)
+        x = origin[0] + h * np.arange(n)
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        psi = np.exp(-alpha * (X ** 2 + Y ** 2 + Z ** 2)).reshape(1, -1)
+        exact = -2 * alpha * a * math.exp(-alpha * float(a @ a))
+        du_fd = oracle.interp_fdgrad(psi, (n, n, n), h, origin, a)[1][0]
+        du_ex = oracle.interp(psi, (n, n, n), h, origin, a)[1][0]
+        err_fd.append(np.abs(du_fd - exact).max())
+        err_ex.append(np.abs(du_ex - exact).max())
+    assert 3.3 < err_fd[0] / err_fd[1] < 4.7, err_fd
+    assert err_ex[0] / err_ex[1] > 4.5, err_ex
+    assert err_ex[0] < err_fd[0] and err_ex[1] < err_fd[1], (err_ex, err_fd)
