@@ -97,6 +97,14 @@ enum { FSIC_CG = 0, FSIC_PCG = 1 };
 #define FSIC_FP32_ORBITALS  16u  /* Fermi-Loewdin orbitals phi = (Z T) psi from an fp32 GEMM on the
                                     matrix cores (fp32 operands and accumulation); costs about 1e-7
                                     relative in phi, more than the 1e-8 Ha energy budget allows */
+#define FSIC_PAPER_GRADIENT 64u  /* forward pass: grad psi at each FOD by interpolating per-node first
+                                    differences (central inside, one-sided at the first and last node),
+                                    as Sec. II.B does, instead of differentiating the cubic interpolant;
+                                    the gradient is then no longer that of the discrete E_SIC(a) */
+#define FSIC_EQ9_FORCES    128u  /* backward pass: the FOD gradient in the form of Eq. 9 with
+                                    eps_kl = <phi_l|V_k|phi_k>, V_k = -(v_k + vxc_k) (Eq. 5); it treats
+                                    the Poisson map as symmetric, so no adjoint Poisson solves run
+                                    (the boundary part of the map is the only difference) */
 
 typedef struct {
     int32_t n[3];       /* nodes per axis, each >= 8 */
@@ -115,7 +123,7 @@ typedef struct {
     double  rho_floor;  /* densities <= floor give zero XC and zero V_SIC; FOD vacuum test */
     double  s_eig_floor;/* smallest admissible eigenvalue of the FO overlap S */
     uint32_t flags;     /* FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE |
-                           FSIC_FP32_ORBITALS | FSIC_GRAPHS */
+                           FSIC_FP32_ORBITALS | FSIC_GRAPHS | FSIC_PAPER_GRADIENT | FSIC_EQ9_FORCES */
 } fsic_opts;
 
 /* One system: up to two spin channels on one grid. */
@@ -199,6 +207,9 @@ fsic_status fsic_forward(fsic_ctx *ctx, int32_t nsys, const fsic_system *sys,
  * grad_e[k] * dE_SIC/da for system k (Eq. 9-11 in exact discrete form:
  * one adjoint Poisson solve per orbital, reverse mode through the Loewdin
  * step, the Fermi-orbital construction and the cubic interpolation).
+ * With FSIC_EQ9_FORCES set at this call, Eq. 9 with the orbital SIC
+ * potentials instead (no adjoint solves); with FSIC_PAPER_GRADIENT set at
+ * the forward call, grad psi at the FODs comes from per-node differences.
  * grad_e: HOST [nsys], NULL means all ones.  The input orbitals of the
  * forward pass must still be valid and unchanged. */
 fsic_status fsic_backward(fsic_ctx *ctx, const double *grad_e, double *const *dE_da,
@@ -255,6 +266,18 @@ fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lma
  * U diag(lam)^{-1/2} U^T.  S, Z: [count][N][N]; lam: [count][N] or NULL. */
 fsic_status fsic_op_invsqrt(int32_t N, int32_t count, const double *S, double *Z, double *lam,
                             void *hip_stream);
+
+/* Cubic interpolation of N orbitals at K points (Sec. II.B): psi DEVICE
+ * [N][M], pts HOST [K][3] (Bohr); u DEVICE [K][N] receives psi_a(p_k) and
+ * du DEVICE [K][N][3] its gradient: fd_gradient = 0, the derivative of the
+ * tensor cubic interpolant (4 nodes per axis); fd_gradient = 1, the same
+ * interpolation applied to per-node first differences (central inside,
+ * one-sided at the first and last node; 6 nodes per axis).  N <= 128.
+ * FSIC_EBOUNDARY when a point's 4-node stencil leaves the grid (its cell
+ * index floor((p - origin)/h) must lie in [1, n-3] on every axis). */
+fsic_status fsic_op_interp(const fsic_grid *grid, int32_t N, int32_t K, const double *psi,
+                           const double *pts, int32_t fd_gradient, double *u, double *du,
+                           void *hip_stream);
 
 /* Fermi-Loewdin orbitals of one spin channel (Eq. 6-8, Sec. I.B, II.B):
  * psi (DEVICE [N][M]) and FODs (HOST [N][3]) give, for every non-NULL

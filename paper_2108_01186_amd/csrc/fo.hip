@@ -43,6 +43,37 @@ __device__ __forceinline__ void cubic_weights(double t, double *w, double *dw) {
     dw[3] = (3.0 * t2 - 1.0) * (1.0 / 6.0);
 }
 
+// Weights, over the six nodes i0-2 .. i0+3 of one axis, that turn grid
+// values into the cubic interpolant (at offset t from node i0) of the
+// per-node first differences: central (f[j+1] - f[j-1]) / 2 inside, forward
+// at node 0, backward at node n-1 (in units of 1/h).  Sec. II.B builds
+// grad psi at an FOD this way.  Entries 0 and 5 stay zero whenever their
+// node lies outside the grid (i0 is in [1, n-3]).
+__device__ __forceinline__ void fd_interp_weights(const double *w, int i0, int n, double *e) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) e[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = i0 - 1 + q;  // node carrying weight w[q]; its slot is q + 1
+        if (j == 0) {
+            e[q + 2] += w[q];
+            e[q + 1] -= w[q];
+        } else if (j == n - 1) {
+            e[q + 1] += w[q];
+            e[q] -= w[q];
+        } else {
+            e[q + 2] += 0.5 * w[q];
+            e[q] -= 0.5 * w[q];
+        }
+    }
+}
+
+// One block per FOD (or query point) i, one thread per orbital a < N (N <=
+// 128): u = psi_a(a_i), du = grad psi_a(a_i), and, for the FOD path,
+// rho(a_i) and T_i,a = u / sqrt(rho).  FD = false: du is the derivative of
+// the cubic interpolant (the exact derivative of the discrete u); FD = true:
+// du interpolates the per-node difference gradient.
+template <bool FD>
 __global__ __launch_bounds__(128) void k_interp(int N, int nx, int ny, int nz, double h,
                                                 const double *psi, const FodCell *cells,
                                                 double floor, double *u, double *du,
@@ -57,7 +88,7 @@ __global__ __launch_bounds__(128) void k_interp(int N, int nx, int ny, int nz, d
     const long long M = (long long)nx * ny * nz;
     const int a = threadIdx.x;
     double val = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    if (a < N) {
+    if (a < N && !FD) {
         const double *f = psi + (long long)a * M;
         for (int c = 0; c < 4; ++c) {
             for (int b = 0; b < 4; ++b) {
@@ -74,6 +105,39 @@ __global__ __launch_bounds__(128) void k_interp(int N, int nx, int ny, int nz, d
                 gz += dz[c] * wy[b] * sx;
             }
         }
+    } else if (a < N) {
+        // six-node windows: value weights padded with zeros, difference weights
+        double vx6[6] = {0.0, wx[0], wx[1], wx[2], wx[3], 0.0};
+        double vy6[6] = {0.0, wy[0], wy[1], wy[2], wy[3], 0.0};
+        double vz6[6] = {0.0, wz[0], wz[1], wz[2], wz[3], 0.0};
+        double ex[6], ey[6], ez[6];
+        fd_interp_weights(wx, cl.i0[0], nx, ex);
+        fd_interp_weights(wy, cl.i0[1], ny, ey);
+        fd_interp_weights(wz, cl.i0[2], nz, ez);
+        int xs[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) xs[q] = min(max(cl.i0[0] - 2 + q, 0), nx - 1);
+        const double *f = psi + (long long)a * M;
+        for (int c = 0; c < 6; ++c) {
+            const int kz = min(max(cl.i0[2] - 2 + c, 0), nz - 1);
+            for (int b = 0; b < 6; ++b) {
+                const int jy = min(max(cl.i0[1] - 2 + b, 0), ny - 1);
+                const double *row = f + ((long long)kz * ny + jy) * nx;
+                double sx = 0.0, sdx = 0.0;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    const double fv = row[xs[q]];
+                    sx += vx6[q] * fv;
+                    sdx += ex[q] * fv;
+                }
+                val += vz6[c] * vy6[b] * sx;
+                gx += vz6[c] * vy6[b] * sdx;
+                gy += vz6[c] * ey[b] * sx;
+                gz += ez[c] * vy6[b] * sx;
+            }
+        }
+    }
+    if (a < N) {
         const double ih = 1.0 / h;
         u[(size_t)i * N + a] = val;
         du[((size_t)i * N + a) * 3 + 0] = gx * ih;
@@ -94,11 +158,16 @@ __global__ __launch_bounds__(128) void k_interp(int N, int nx, int ny, int nz, d
     if (a < N) T[(size_t)i * N + a] = (rho > floor) ? val / sqrt(rho) : 0.0;
 }
 
-hipError_t launch_interp(int N, int nx, int ny, int nz, double h, const double *psi,
+hipError_t launch_interp(int K, int N, int nx, int ny, int nz, double h, const double *psi,
                          const FodCell *cells, double floor, double *u, double *du,
-                         double *rhoa, double *T, int *status, hipStream_t s) {
-    hipLaunchKernelGGL(k_interp, dim3(N), dim3(128), 0, s, N, nx, ny, nz, h, psi, cells, floor, u,
-                       du, rhoa, T, status);
+                         double *rhoa, double *T, int *status, bool fd_gradient, hipStream_t s) {
+    if (K < 1 || N < 1 || N > 128) return hipErrorInvalidValue;
+    if (fd_gradient)
+        hipLaunchKernelGGL(k_interp<true>, dim3(K), dim3(128), 0, s, N, nx, ny, nz, h, psi, cells,
+                           floor, u, du, rhoa, T, status);
+    else
+        hipLaunchKernelGGL(k_interp<false>, dim3(K), dim3(128), 0, s, N, nx, ny, nz, h, psi, cells,
+                           floor, u, du, rhoa, T, status);
     return hipGetLastError();
 }
 

@@ -197,9 +197,9 @@ struct FodCell {
 };
 
 // u[i][a] = psi_a(a_i), du[i][a][3]; rhoa[i]; T[i][a]; sets status on vacuum
-hipError_t launch_interp(int N, int nx, int ny, int nz, double h, const double *psi,
+hipError_t launch_interp(int K, int N, int nx, int ny, int nz, double h, const double *psi,
                          const FodCell *cells, double floor, double *u, double *du,
-                         double *rhoa, double *T, int *status, hipStream_t s);
+                         double *rhoa, double *T, int *status, bool fd_gradient, hipStream_t s);
 
 // G = dV psi psi^T (MFMA FP64), partial sums then reduction; nonortho = max|G - I|
 // blocks of a node-range split whose N x N partial tiles fit in cap doubles

@@ -259,7 +259,8 @@ fsic_status validate_opts(const fsic_opts *o, std::string &why) {
     if (!std::isfinite(o->vsic_scale)) { why = "vsic_scale must be finite"; return FSIC_EINVAL; }
     if (!(o->rho_floor >= 0.0) || !std::isfinite(o->rho_floor)) { why = "rho_floor must be finite and >= 0"; return FSIC_EINVAL; }
     if (!(o->s_eig_floor > 0.0) || !std::isfinite(o->s_eig_floor)) { why = "s_eig_floor must be finite and > 0"; return FSIC_EINVAL; }
-    if (o->flags & ~(FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE | FSIC_FP32_ORBITALS | FSIC_GRAPHS)) { why = "unknown flag bits"; return FSIC_EINVAL; }
+    if (o->flags & ~(FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE | FSIC_FP32_ORBITALS |
+                     FSIC_GRAPHS | FSIC_PAPER_GRADIENT | FSIC_EQ9_FORCES)) { why = "unknown flag bits"; return FSIC_EINVAL; }
     return FSIC_OK;
 }
 
@@ -1299,9 +1300,10 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         const Chan &ch = chans[ci];
         double *sm = c->small.p + ch.so;
         const double dV = ch.h * ch.h * ch.h;
-        HIPCHK(c, launch_interp(ch.N, ch.n[0], ch.n[1], ch.n[2], ch.h, ch.psi, c->d_cells.p + cell_base,
+        HIPCHK(c, launch_interp(ch.N, ch.N, ch.n[0], ch.n[1], ch.n[2], ch.h, ch.psi, c->d_cells.p + cell_base,
                                 o.rho_floor, sm + small_off(sU_), sm + small_off(sDU),
-                                sm + small_off(sRHOA), sm + small_off(sT), c->status.p, s));
+                                sm + small_off(sRHOA), sm + small_off(sT), c->status.p,
+                                (o.flags & FSIC_PAPER_GRADIENT) != 0, s));
         HIPCHK(c, launch_gram(ch.N, ch.M, dV, ch.psi, c->partG.p, c->partG.cap, sm + small_off(sG), s));
         HIPCHK(c, launch_lowdin(ch.N, sm + small_off(sT), sm + small_off(sG), sm + small_off(sS),
                                 sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
@@ -1590,6 +1592,39 @@ fsic_status fsic_op_invsqrt(int32_t N, int32_t count, const double *S, double *Z
     return (hs & kStSingular) ? FSIC_ESINGULAR : FSIC_OK;
 }
 
+fsic_status fsic_op_interp(const fsic_grid *grid, int32_t N, int32_t K, const double *psi,
+                           const double *pts, int32_t fd_gradient, double *u, double *du,
+                           void *hip_stream) {
+    if (!grid || !psi || !pts || !u || !du || N < 1 || N > kMaxOrb || K < 1 ||
+        (fd_gradient != 0 && fd_gradient != 1))
+        return FSIC_EINVAL;
+    std::string why;
+    if (validate_grid(*grid, why)) return FSIC_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<FodCell> cells(K);
+    for (int i = 0; i < K; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double a = pts[3 * i + d];
+            if (!std::isfinite(a)) return FSIC_EINVAL;
+            const double sc = (a - grid->origin[d]) / grid->h;
+            const double fl = std::floor(sc);
+            if (fl < 1.0 || fl > (double)(grid->n[d] - 3)) return FSIC_EBOUNDARY;
+            cells[i].i0[d] = (int)fl;
+            cells[i].t[d] = sc - fl;
+        }
+    DBuf<double> rhoa, T;
+    DBuf<FodCell> dc;
+    DBuf<int> status;
+    if (rhoa.ensure(K) || T.ensure((size_t)K * N) || dc.ensure(K) || status.ensure(1)) return FSIC_ENOMEM;
+    hipError_t e = hipMemcpyAsync(dc.p, cells.data(), K * sizeof(FodCell), hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemsetAsync(status.p, 0, sizeof(int), s);
+    if (!e) e = launch_interp(K, N, grid->n[0], grid->n[1], grid->n[2], grid->h, psi, dc.p, -1.0, u, du,
+                              rhoa.p, T.p, status.p, fd_gradient != 0, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    rhoa.release(); T.release(); dc.release(); status.release();
+    return (e || e2) ? FSIC_EHIP : FSIC_OK;
+}
+
 fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, const double *fod,
                         double rho_floor, double *T, double *G, double *S, double *Z, double *phi,
                         void *hip_stream) {
@@ -1619,9 +1654,9 @@ fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, con
     hipError_t e = hipMemcpyAsync(dc.p, cells.data(), N * sizeof(FodCell), hipMemcpyHostToDevice, s);
     if (!e) e = hipMemsetAsync(status.p, 0, sizeof(int), s);
     double *b = sm.p;
-    if (!e) e = launch_interp(N, grid->n[0], grid->n[1], grid->n[2], grid->h, psi, dc.p, rho_floor,
+    if (!e) e = launch_interp(N, N, grid->n[0], grid->n[1], grid->n[2], grid->h, psi, dc.p, rho_floor,
                               b + small_off(sU_), b + small_off(sDU), b + small_off(sRHOA),
-                              b + small_off(sT), status.p, s);
+                              b + small_off(sT), status.p, false, s);
     if (!e) e = launch_gram(N, M, dV, psi, partG.p, partG.cap, b + small_off(sG), s);
     if (!e) e = launch_lowdin(N, b + small_off(sT), b + small_off(sG), b + small_off(sS),
                               b + small_off(sLAM), b + small_off(sEV), b + small_off(sZ),
@@ -1659,22 +1694,30 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
     fsic_status pst = prepare_batch(c, b, o.precision);
     if (pst) return pst;
-    HIPCHK(c, c->W.ensure((size_t)b.fields));
     HIPCHK(c, c->bmat.ensure((size_t)kMaxOrb * kMaxOrb));
-    // adjoint solves: K w' = 4 pi rho_i with zero Dirichlet values
     SolveReport rep;
-    fsic_status sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, false, c->W.p, o.precision, o.tol,
-                                  o.max_iter, rep);
-    if (sst) return sst;
+    rep.converged = true;
+    // Eq. 9 form: the orbital SIC potential -(v_i + vxc_i) in place of the
+    // exact -((v_i + A^T rho_i)/2 + vxc_i), so A^T rho_i is taken as v_i
+    const bool eq9 = (o.flags & FSIC_EQ9_FORCES) != 0;
+    const double *Wt = c->V.p;
+    if (!eq9) {
+        HIPCHK(c, c->W.ensure((size_t)b.fields));
+        // adjoint solves: K w' = 4 pi rho_i with zero Dirichlet values
+        fsic_status sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, false, c->W.p, o.precision, o.tol,
+                                      o.max_iter, rep);
+        if (sst) return sst;
+        // boundary part of A^T rho: zt = E_g^T C^T w' / (4 pi), then W += P^T zt
+        HarmTables hta = c->ht;
+        for (int q = 0; q < kMaxLM; ++q) hta.gfac[q] /= 4.0 * M_PI;
+        const int zchunks = 64;
+        HIPCHK(c, launch_adjoint_boundary(c->radius, o.lmax, hta, c->cf, norb, c->d_orb.p, c->d_gcount.p,
+                                          c->W.p, c->partZ.p, zchunks, c->Zt.p, b.max_ghost, s));
+        HIPCHK(c, launch_adj_field(o.lmax, c->ht, c->d_orb.p, c->d_items8.p, (int)b.items8.size(),
+                                   c->Zt.p, c->W.p, s));
+        Wt = c->W.p;
+    }
     const double t1 = now_ms();
-    // boundary part of A^T rho: zt = E_g^T C^T w' / (4 pi), then W += P^T zt
-    HarmTables hta = c->ht;
-    for (int q = 0; q < kMaxLM; ++q) hta.gfac[q] /= 4.0 * M_PI;
-    const int zchunks = 64;
-    HIPCHK(c, launch_adjoint_boundary(c->radius, o.lmax, hta, c->cf, norb, c->d_orb.p, c->d_gcount.p,
-                                      c->W.p, c->partZ.p, zchunks, c->Zt.p, b.max_ghost, s));
-    HIPCHK(c, launch_adj_field(o.lmax, c->ht, c->d_orb.p, c->d_items8.p, (int)b.items8.size(),
-                               c->Zt.p, c->W.p, s));
     // per channel: B = Gam psi^T, then the N x N reverse chain
     std::vector<int> spin0(c->nsys, 0);
     for (const Chan &ch : c->chans)
@@ -1685,7 +1728,7 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         double *sm = c->small.p + ch.so;
         const double dV = ch.h * ch.h * ch.h;
         HIPCHK(c, launch_adjoint_contract(ch.N, ch.M, dV, c->PHI.p + ch.off, c->V.p + ch.off,
-                                          c->W.p + ch.off, ch.psi, o.rho_floor, c->partG.p, c->partG.cap,
+                                          Wt + ch.off, ch.psi, o.rho_floor, c->partG.p, c->partG.cap,
                                           c->bmat.p, s));
         HIPCHK(c, launch_lowdin_backward(ch.N, c->bmat.p, sm + small_off(sT), sm + small_off(sG),
                                          sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
@@ -1705,7 +1748,7 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     const double t2 = now_ms();
     if (st) {
         std::memset(st, 0, sizeof(*st));
-        st->nsolves = norb;
+        st->nsolves = eq9 ? 0 : norb;
         st->max_iters = rep.max_iters;
         st->total_iters = rep.total_iters;
         st->outer_refinements = rep.refinements;

@@ -34,6 +34,7 @@ FSIC_FP64, FSIC_MIXED = 0, 1
 FSIC_CG, FSIC_PCG = 0, 1
 FSIC_WANT_VSIC, FSIC_KEEP_TAPE, FSIC_ALLOW_NONORTHO, FSIC_PROFILE, FSIC_FP32_ORBITALS = 1, 2, 4, 8, 16
 FSIC_GRAPHS = 32
+FSIC_PAPER_GRADIENT, FSIC_EQ9_FORCES = 64, 128
 
 
 class fsic_grid(ctypes.Structure):
@@ -113,11 +114,14 @@ fsic_op_invsqrt = _sig("fsic_op_invsqrt", ctypes.c_int,
 fsic_op_flo = _sig("fsic_op_flo", ctypes.c_int,
                    [_P(fsic_grid), ctypes.c_int32, _vp, _dp, ctypes.c_double, _vp, _vp, _vp, _vp,
                     _vp, _vp])
+fsic_op_interp = _sig("fsic_op_interp", ctypes.c_int,
+                      [_P(fsic_grid), ctypes.c_int32, ctypes.c_int32, _vp, _dp, ctypes.c_int32, _vp,
+                       _vp, _vp])
 
 EXPORTED = ["fsic_default_opts", "fsic_create", "fsic_set_opts", "fsic_forward", "fsic_backward",
             "fsic_status_string", "fsic_last_error", "fsic_destroy", "fsic_op_laplacian",
             "fsic_op_laplacian_f32", "fsic_op_xc", "fsic_op_poisson", "fsic_op_invsqrt",
-            "fsic_op_hamiltonian",
+            "fsic_op_hamiltonian", "fsic_op_interp",
             "fsic_op_flo"]
 
 
@@ -342,6 +346,23 @@ def op_invsqrt(S, stream=None):
     _check(fsic_op_invsqrt(S.shape[1], S.shape[0], _dev_ptr(S), _dev_ptr(Z), _dev_ptr(lam),
                            _stream_ptr(stream)))
     return (Z[0], lam[0]) if squeeze else (Z, lam)
+
+
+def op_interp(psi, pts, n, h, origin, fd_gradient=False, stream=None):
+    """psi_a(p_k) (K x N) and its gradient (K x N x 3) at K points: the
+    cubic interpolant's derivative, or (fd_gradient) the interpolated
+    per-node first differences."""
+    torch = _torch()
+    psi = psi.contiguous()
+    N = psi.shape[0]
+    pts = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+    K = pts.shape[0]
+    u = torch.empty(K, N, dtype=torch.float64, device=psi.device)
+    du = torch.empty(K, N, 3, dtype=torch.float64, device=psi.device)
+    g = make_grid(n, h, origin)
+    _check(fsic_op_interp(ctypes.byref(g), N, K, _dev_ptr(psi), pts.ctypes.data_as(_dp),
+                          int(bool(fd_gradient)), _dev_ptr(u), _dev_ptr(du), _stream_ptr(stream)))
+    return u, du
 
 
 def op_flo(psi, fod, n, h, origin, rho_floor=1e-30, stream=None):

@@ -54,6 +54,31 @@ def test_mol40_gradient_vs_oracle(torch_cuda, F, mol40, mol40_grad_oracle, preci
     ctx.close()
 
 
+@pytest.mark.parametrize("fd_gradient,eq9", [(True, False), (False, True), (True, True)])
+def test_mol40_paper_mode_gradient_vs_oracle(torch_cuda, F, oracle, mol40, mol40_grad_oracle,
+                                             fd_gradient, eq9):
+    """The paper's ingredients on the device: grad psi from interpolated
+    per-node differences (FSIC_PAPER_GRADIENT) and the Eq. 9 form without
+    adjoint solves (FSIC_EQ9_FORCES), against the oracle's same variants;
+    their distance from the exact discrete gradient is printed."""
+    torch = torch_cuda
+    _say(f"paper-mode gradient mol40 fd_gradient={fd_gradient} eq9={eq9}")
+    s = mol40
+    ref = oracle.sic_grad_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin, fd_gradient=fd_gradient, eq9=eq9)
+    flags = F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE
+    flags |= (F.FSIC_PAPER_GRADIENT if fd_gradient else 0) | (F.FSIC_EQ9_FORCES if eq9 else 0)
+    ctx = F.Context(tol=1e-11, flags=flags)
+    psi = torch.tensor(np.asarray(s.psi[0]), device="cuda")
+    d = {"n": s.n, "h": s.h, "origin": s.origin, "psi": [psi], "fod": [s.fod[0]]}
+    ctx.forward([d])
+    g = ctx.backward([[5]])[0][0]
+    if eq9:
+        assert ctx.stats["nsolves"] == 0
+    assert np.abs(g - ref).max() < 1e-8, np.abs(g - ref).max()
+    _say(f"  max |g - exact| = {np.abs(g - mol40_grad_oracle).max():.3e} Ha/Bohr")
+    ctx.close()
+
+
 def test_mol40_gradient_vs_central_differences(torch_cuda, F, mol40):
     torch = torch_cuda
     _say("gradient mol40 vs FD of the library energy")

@@ -147,6 +147,33 @@ def test_poisson_gaussian_closed_form(torch_cuda, F):
     assert abs(U - 1 / (2 * math.sqrt(math.pi) * sigma)) < 2e-9
 
 
+@pytest.mark.parametrize("fd_gradient", [False, True])
+def test_interp_vs_oracle(torch_cuda, F, oracle, fd_gradient):
+    """psi and grad psi at points (Sec. II.B) against the oracle, with points
+    whose stencils touch the first and last node of each axis (where the
+    per-node differences turn one-sided) on a non-cubic grid."""
+    torch = torch_cuda
+    _say(f"interp fd_gradient={fd_gradient}")
+    rng = np.random.default_rng(5)
+    n, h = (13, 17, 11), 0.3
+    origin = np.array([-1.0, 0.5, -2.0])
+    N = 7
+    psi = rng.normal(size=(N, n[0] * n[1] * n[2]))
+    cells = [(1, 1, 1), (n[0] - 3, n[1] - 3, n[2] - 3), (1, n[1] - 3, 4), (5, 1, n[2] - 3),
+             (2, 7, 2), (n[0] - 4, 3, 5)]
+    pts = np.array([origin + h * (np.array(c) + rng.uniform(0, 1, 3)) for c in cells]
+                   + [origin + h * rng.uniform([1, 1, 1], [n[0] - 2, n[1] - 2, n[2] - 2]) for _ in range(10)])
+    u, du = F.op_interp(torch.tensor(psi, device="cuda"), pts, n, h, origin, fd_gradient=fd_gradient)
+    u, du = u.cpu().numpy(), du.cpu().numpy()
+    for k, p in enumerate(pts):
+        ru, rdu = (oracle.interp_fdgrad if fd_gradient else oracle.interp)(psi, n, h, origin, p)
+        assert np.abs(u[k] - ru).max() < 1e-13, k
+        assert np.abs(du[k] - rdu).max() < 1e-12, (k, np.abs(du[k] - rdu).max())
+    bad = origin + h * np.array([[0.5, 3.2, 3.2]])  # cell 0: stencil leaves the grid
+    with pytest.raises(F.FsicError):
+        F.op_interp(torch.tensor(psi, device="cuda"), bad, n, h, origin, fd_gradient=fd_gradient)
+
+
 @pytest.mark.parametrize("case", ["mol40", "n20"])
 def test_fermi_loewdin_orbitals(torch_cuda, F, oracle, mol40, case):
     """T (Eq. 8), the FO overlap S, S^{-1/2} and the FLOs against the oracle;
