@@ -59,6 +59,10 @@ struct DstItems {
     const Item *x, *y, *z;
     int nx, ny, nz;
     int fast, np, blocks;
+    const Item *xy;  // fused x-y units (orbital, z plane), or null
+    int nxy, two;    // their count; two: separate x and y sine matrices in LDS
+    int xyvec;       // every nx and orbital offset is a multiple of 4
+    int npxy;        // largest padded in-plane axis (LDS layout of the fused kernel)
 };
 
 // panel columns of a fast transform variant

@@ -529,6 +529,255 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
     }
 }
 
+// ---------------------------------------------------------------------------
+// fused x-y pass: both in-plane transforms of one z plane in one visit
+// ---------------------------------------------------------------------------
+//
+// Unit = (orbital, z plane).  The plane P (ny x nx) is staged in LDS as
+// split bf16 (rows y, stride sw), then
+//   C1 = P Sx      (x transform of every row; Sx symmetric),
+//   C2 = Sy C1     (y transform of every column),
+// with C1 written back transposed (C1t[x][y]) over P so that both products
+// read their B operand as one 16-byte LDS row segment.  The transforms along
+// different axes commute, so the same kernel serves the forward pass (reads
+// the CG residual) and the inverse pass (writes z and the r.z partial of the
+// plane into rz[base9 + z]).  Each application of the preconditioner then
+// moves the field through HBM three times (xy, z, xy) instead of five.
+// VEC (every nx and orbital offset of the batch a multiple of 4) moves the
+// planes as 16-byte vectors; otherwise as single values.
+// Wave w computes the 32 x (npx / 2) block of C at rows 32 (w / 2) and
+// columns (w % 2) npx / 2: two row tiles times npx / 32 column tiles, so each
+// A fragment is reused over the column tiles and each B fragment over both
+// row tiles.  Waves w >= npy / 16 only move data.
+size_t dst_xy_lds(int np, bool two) {
+    const int sw = np + 8;
+    return (size_t)2 * np * sw * 2 + (size_t)(two ? 2 : 1) * 2 * np * sw * 2 + 16 * sizeof(double);
+}
+
+template <bool INV, bool VEC, typename TIN, typename TR>
+__global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, int npmax, int two,
+                                                const OrbDesc *orb, const int *done,
+                                                const float *tab, const TIN *in, float *out,
+                                                const TR *rres, double *rz, int *cnt) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int sw = npmax + 8;  // LDS row stride (bf16): 16-byte rows
+    __bf16 *Xhi = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *Xlo = Xhi + (size_t)npmax * sw;
+    __bf16 *Sxh = Xlo + (size_t)npmax * sw;
+    __bf16 *Sxl = Sxh + (size_t)npmax * sw;
+    __bf16 *Syh = two ? Sxl + (size_t)npmax * sw : Sxh;
+    __bf16 *Syl = two ? Syh + (size_t)npmax * sw : Sxl;
+    double *sred = reinterpret_cast<double *>(Syl + (size_t)npmax * sw);  // kFT / 64 doubles
+    const int t = threadIdx.x;
+    const int u0 = (int)((long long)blockIdx.x * nunits / gridDim.x);
+    const int u1 = (int)((long long)(blockIdx.x + 1) * nunits / gridDim.x);
+    auto next_active = [&](int u) {  // done[] does not change during this launch: uniform
+        while (u < u1 && (units[u].orb < 0 || done[units[u].orb])) ++u;
+        return u;
+    };
+    // VEC (every nx and orbital offset a multiple of 4): planes move as
+    // 16-byte vectors
+    // plane loads into v[kFV]: vector group g = t + kFT i (elements 4g .. 4g+3)
+    // or element e = t + kFT i, in row-major (y, x) order
+    auto load = [&](float (&v)[kFV], const OrbDesc &od, int z) {
+        const int pl = od.nx * od.ny;
+        const long long base = od.off + (long long)z * pl;
+        if (VEC) {
+#pragma unroll
+            for (int i = 0; i < kFV / 4; ++i) {
+                const int g = t + kFT * i;
+                const float4 q = (4 * g < pl) ? ld4(in + base + 4 * g) : float4{0.f, 0.f, 0.f, 0.f};
+                v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
+            }
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < kFV; ++i) {
+            const int e = t + kFT * i;
+            v[i] = (e < pl) ? (float)in[base + e] : 0.f;
+        }
+    };
+    auto to_lds = [&](const float (&v)[kFV], const OrbDesc &od) {
+        const int nx = od.nx, pl = od.nx * od.ny;
+        if (VEC) {
+#pragma unroll
+            for (int i = 0; i < kFV / 4; ++i) {
+                const int g = t + kFT * i;
+                if (4 * g < pl) {
+                    const int y = (4 * g) / nx, x = 4 * g - y * nx;
+                    __bf16 h[4], l[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bsplit(v[4 * i + j], h[j], l[j]);
+                    *reinterpret_cast<bf4 *>(Xhi + y * sw + x) = bf4{h[0], h[1], h[2], h[3]};
+                    *reinterpret_cast<bf4 *>(Xlo + y * sw + x) = bf4{l[0], l[1], l[2], l[3]};
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kFV; ++i) {
+                const int e = t + kFT * i;
+                if (e < pl) {
+                    const int y = e / nx, x = e - y * nx;
+                    __bf16 h, l;
+                    bsplit(v[i], h, l);
+                    Xhi[y * sw + x] = h;
+                    Xlo[y * sw + x] = l;
+                }
+            }
+        }
+        // zero the padding the products read: columns nx .. npx-1, rows ny .. npy-1
+        const int npx = (od.nx + 31) & ~31, npy = (od.ny + 31) & ~31;
+        if (npx != od.nx || npy != od.ny)
+            for (int e = t; e < npy * npx; e += kFT) {
+                const int y = e / npx, x = e - y * npx;
+                if (y >= od.ny || x >= od.nx) {
+                    Xhi[y * sw + x] = (__bf16)0.f;
+                    Xlo[y * sw + x] = (__bf16)0.f;
+                }
+            }
+    };
+
+    const int lane = t & 63, w = t >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int rb = w >> 1, cb = w & 1;
+    constexpr int BC = 4;  // column tiles per wave: npx / 32 <= 4
+    flt4 acc[2][BC];
+    // acc = A B over k < npk for the wave's block; A rows from Ah/Al
+    // (row-major, stride sw), B as Bt[col][k] from Bh/Bl
+    auto gemm = [&](const __bf16 *Ah, const __bf16 *Al, const __bf16 *Bh, const __bf16 *Bl, int npk,
+                    int bc) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < BC; ++c) acc[r][c] = flt4{0.f, 0.f, 0.f, 0.f};
+        const int row0 = 32 * rb, col0 = cb * 16 * bc;
+#pragma unroll 1
+        for (int k0 = 0; k0 < npk; k0 += 32) {
+            const int kb = k0 + 8 * lq;
+            bf8 ah[2], al[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                ah[r] = *reinterpret_cast<const bf8 *>(Ah + (row0 + 16 * r + lr) * sw + kb);
+                al[r] = *reinterpret_cast<const bf8 *>(Al + (row0 + 16 * r + lr) * sw + kb);
+            }
+#pragma unroll
+            for (int c = 0; c < BC; ++c) {
+                if (c < bc) {
+                    const bf8 bh = *reinterpret_cast<const bf8 *>(Bh + (col0 + 16 * c + lr) * sw + kb);
+                    const bf8 bl = *reinterpret_cast<const bf8 *>(Bl + (col0 + 16 * c + lr) * sw + kb);
+#pragma unroll
+                    for (int r = 0; r < 2; ++r) {
+                        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bh, acc[r][c], 0, 0, 0);
+                        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bl, acc[r][c], 0, 0, 0);
+                        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bh, acc[r][c], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+
+    int sx_n = -1, sy_n = -1;  // axis lengths whose sine matrices are in LDS
+    auto stage_s = [&](__bf16 *Sh, __bf16 *Sl, const float *S, int np) {
+        for (int e = t; e < np * np; e += kFT) {
+            const int m = e / np, k = e - m * np;
+            __bf16 hi, lo;
+            bsplit(S[e], hi, lo);
+            Sh[m * sw + k] = hi;
+            Sl[m * sw + k] = lo;
+        }
+    };
+    auto unit = [&](float (&v)[kFV], int u, OrbDesc &od, int pf) {
+        const Item cur = units[u];
+        const OrbDesc oc = od;
+        const int nx = oc.nx, ny = oc.ny;
+        const int npx = (nx + 31) & ~31, npy = (ny + 31) & ~31;
+        const int bc = npx >> 5;
+        const bool act = rb < (npy >> 5);
+        if (cnt && cur.tile == 0 && t == 0) cnt[cur.orb] += 1;
+        __syncthreads();  // the previous unit's products are done with S and X
+        if (nx != sx_n || (two && ny != sy_n)) {
+            stage_s(Sxh, Sxl, tab + oc.dst_s[0], npx);
+            if (two) stage_s(Syh, Syl, tab + oc.dst_s[1], npy);
+            sx_n = nx;
+            sy_n = ny;
+        }
+        to_lds(v, oc);
+        __syncthreads();
+        if (pf < u1) {  // two units ahead: in flight during this unit and the next
+            od = orb[units[pf].orb];
+            load(v, od, units[pf].tile);
+        }
+        // C1 = P Sx: rows y, columns x
+        if (act) gemm(Xhi, Xlo, Sxh, Sxl, npx, bc);
+        __syncthreads();  // every wave is done reading P
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < BC; ++c) {
+                    if (c < bc) {
+                        const int x = cb * 16 * bc + 16 * c + lr;
+                        const int y0 = 32 * rb + 16 * r + 4 * lq;
+                        __bf16 hh[4], ll[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) bsplit(acc[r][c][j], hh[j], ll[j]);
+                        *reinterpret_cast<bf4 *>(Xhi + x * sw + y0) = bf4{hh[0], hh[1], hh[2], hh[3]};
+                        *reinterpret_cast<bf4 *>(Xlo + x * sw + y0) = bf4{ll[0], ll[1], ll[2], ll[3]};
+                    }
+                }
+        }
+        __syncthreads();
+        // C2 = Sy C1: rows y, columns x (B = C1t)
+        if (act) gemm(Syh, Syl, Xhi, Xlo, npy, bc);
+        double part = 0.0;
+        if (act) {
+            const long long base = oc.off + (long long)cur.tile * nx * ny;
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < BC; ++c) {
+                    const int x = cb * 16 * bc + 16 * c + lr;
+                    if (c < bc && x < nx) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int y = 32 * rb + 16 * r + 4 * lq + j;
+                            if (y < ny) {
+                                const long long a = base + (long long)y * nx + x;
+                                out[a] = acc[r][c][j];
+                                if (INV) part += (double)rres[a] * (double)acc[r][c][j];
+                            }
+                        }
+                    }
+                }
+        }
+        if (INV) {
+            const double sum = block_sum_fast(part, sred);
+            if (t == 0) rz[oc.base9 + cur.tile] = sum;
+        }
+    };
+
+    float va[kFV], vb[kFV];
+    int q0 = next_active(u0);
+    if (q0 >= u1) return;
+    int q1 = next_active(q0 + 1);
+    OrbDesc o0 = orb[units[q0].orb], o1;
+    load(va, o0, units[q0].tile);
+    if (q1 < u1) {
+        o1 = orb[units[q1].orb];
+        load(vb, o1, units[q1].tile);
+    }
+    while (true) {
+        const int q2 = q1 < u1 ? next_active(q1 + 1) : u1;
+        unit(va, q0, o0, q2);
+        q0 = q2;
+        if (q1 >= u1) break;
+        const int q3 = q0 < u1 ? next_active(q0 + 1) : u1;
+        unit(vb, q1, o1, q3);
+        q1 = q3;
+        if (q0 >= u1) break;
+    }
+}
+
 template <class K>
 void set_lds_limit(K kern, size_t bytes) {
     if (bytes > 65536) hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -539,7 +788,7 @@ template <typename T>
 hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int *done,
                               const float *tab, const T *r, float *work, float *z, double *rz,
                               int *cnt, hipStream_t s) {
-    if (di.nx <= 0) return hipSuccess;
+    if (di.nx <= 0 && di.nxy <= 0) return hipSuccess;
     const float *wk = work;
     const T *nr = nullptr;
     double *nd = nullptr;
@@ -560,10 +809,34 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
         hipLaunchKernelGGL((k_dst_fast<0, 0, float, T, true, PC_, SLO_>), grid(di.nx), dim3(kFT),   \
                            lds, s, di.x, di.nx, di.np, orb, done, tab, wk, z, r, rz, nc);            \
     } while (0)
-        if (di.fast == 1) FSIC_DST_FAST(128, true);
+#define FSIC_DST_XY(PC_, SLO_)                                                                     \
+    do {                                                                                           \
+        const size_t lxy = dst_xy_lds(di.npxy, di.two != 0);                                       \
+        const size_t lz = dst_fast_lds(di.np, PC_, SLO_);                                          \
+        if (di.xyvec)                                                                              \
+            hipLaunchKernelGGL((k_dst_xy<false, true, T, T>), grid(di.nxy), dim3(kFT), lxy, s,      \
+                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, r, work, nr, nd, cnt); \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_dst_xy<false, false, T, T>), grid(di.nxy), dim3(kFT), lxy, s,     \
+                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, r, work, nr, nd, cnt); \
+        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, false, PC_, SLO_>), grid(di.nz), dim3(kFT),  \
+                           lz, s, di.z, di.nz, di.np, orb, done, tab, wk, work, nr, nd, nc);         \
+        if (di.xyvec)                                                                              \
+            hipLaunchKernelGGL((k_dst_xy<true, true, float, T>), grid(di.nxy), dim3(kFT), lxy, s,   \
+                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, wk, z, r, rz, nc);     \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_dst_xy<true, false, float, T>), grid(di.nxy), dim3(kFT), lxy, s,  \
+                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, wk, z, r, rz, nc);     \
+    } while (0)
+        if (di.nxy > 0) {
+            if (di.fast == 1) FSIC_DST_XY(128, true);
+            else if (di.fast == 2) FSIC_DST_XY(64, true);
+            else FSIC_DST_XY(64, false);
+        } else if (di.fast == 1) FSIC_DST_FAST(128, true);
         else if (di.fast == 2) FSIC_DST_FAST(64, true);
         else FSIC_DST_FAST(64, false);
 #undef FSIC_DST_FAST
+#undef FSIC_DST_XY
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_dst_pass<0, 0, T, T, false>), dim3(di.nx), dim3(256), 0, s, di.x, orb,
@@ -581,7 +854,18 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
 
 // raise the dynamic-LDS limit of the fast transform kernels (once per batch,
 // outside any stream capture)
-hipError_t dst_setup(int np, int variant) {
+hipError_t dst_setup(int np, int variant, int npxy, bool two) {
+    if (npxy > 0) {
+        const size_t lxy = dst_xy_lds(npxy, two);
+        set_lds_limit(k_dst_xy<false, true, float, float>, lxy);
+        set_lds_limit(k_dst_xy<false, true, double, double>, lxy);
+        set_lds_limit(k_dst_xy<true, true, float, float>, lxy);
+        set_lds_limit(k_dst_xy<true, true, float, double>, lxy);
+        set_lds_limit(k_dst_xy<false, false, float, float>, lxy);
+        set_lds_limit(k_dst_xy<false, false, double, double>, lxy);
+        set_lds_limit(k_dst_xy<true, false, float, float>, lxy);
+        set_lds_limit(k_dst_xy<true, false, float, double>, lxy);
+    }
 #define FSIC_DST_LIMITS(PC_, SLO_)                                                      \
     do {                                                                                \
         const size_t lds = dst_fast_lds(np, PC_, SLO_);                                 \

@@ -110,9 +110,14 @@ hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *pa
 // of pc columns, with (slo) or without the sine matrix's low bf16 part.
 size_t dst_fast_lds(int np, int pc, bool slo);
 
+// LDS bytes of the fused x-y transform block for in-plane axes padded to np
+// nodes; two: the x and y sine matrices differ somewhere in the batch.
+size_t dst_xy_lds(int np, bool two);
+
 // Allows the fast transform kernels of a variant (1..3, see DstItems) their
-// dynamic LDS for axes up to np.
-hipError_t dst_setup(int np, int variant);
+// dynamic LDS for axes up to np, and the fused x-y kernel (npxy > 0: in-plane
+// axes up to npxy) its own.
+hipError_t dst_setup(int np, int variant, int npxy, bool two);
 
 // z = M^{-1} r (float) for the orbitals of the work lists with done == 0,
 // through the float work array; r.z partial sums into rz[base9 + panel].

@@ -155,10 +155,15 @@ struct Batch {
     int tot7 = 0, tot8 = 0;
     // spectral preconditioner: panel work lists, sine matrices and symbols
     std::vector<Item> dx, dy, dz;
+    std::vector<Item> dxy;  // fused x-y units (orbital, z plane) when dst_xy
     std::vector<float> dtab;
     int tot9 = 0;
     int max_n = 0;
-    int dst_fast = 0;  // transform variant (see DstItems)
+    int dst_fast = 0;      // transform variant (see DstItems)
+    bool dst_xy = false;   // in-plane transforms fused per z plane
+    bool dst_two = false;  // some orbital has nx != ny
+    bool dst_vec = true;   // every nx and orbital offset is a multiple of 4
+    int npxy = 0;          // largest in-plane axis, padded to 32
 };
 
 void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<Item> &out) {
@@ -186,7 +191,7 @@ struct fsic_ctx {
     DBuf<float> R32, P32a, P32b, Q32, X32;
     DBuf<float> Z32, T32, dtab;     // preconditioned CG: z, transform work array, spectral table
     DBuf<double> partRZ;
-    DBuf<Item> d_dx, d_dy, d_dz;
+    DBuf<Item> d_dx, d_dy, d_dz, d_dxy;
     DBuf<double> Gh;  // ghost values
     DBuf<double> part7, part8, partRU, partQ, partZ;
     DBuf<double> bb, rrfin, relres, Qlm, Zt, ptrue;
@@ -387,6 +392,17 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     else if (npx <= 256 && dst_fast_lds(npx, 64, false) <= ldsmax) variant = 3;
     const bool fast = variant != 0;
     b.dst_fast = variant;
+    // fused x-y passes: in-plane axes of at most 128 nodes and LDS for the
+    // plane plus one sine matrix (two when some grid has nx != ny);
+    // FSIC_DST_XY=0 keeps five separate passes
+    for (const Group &g : groups) b.dst_two = b.dst_two || g.n[0] != g.n[1];
+    for (const Group &g : groups) b.npxy = std::max(b.npxy, std::max(g.n[0], g.n[1]));
+    b.npxy = (b.npxy + 31) & ~31;
+    {
+        const char *env = std::getenv("FSIC_DST_XY");
+        b.dst_xy = fast && b.npxy <= 128 && dst_xy_lds(b.npxy, b.dst_two) <= ldsmax &&
+                   !(env && std::atoi(env) == 0);
+    }
     std::vector<std::pair<int, int>> nat7, nat8, natx, naty, natz;
     std::map<int, std::pair<int, int>> dst_done;  // n -> (sine offset, symbol offset)
     auto dst_entry = [&](Batch &bb, int n, int radius_) -> const std::pair<int, int> & {
@@ -414,6 +430,7 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
             od.base8 = b.tot8;
             b.tot8 += od.nt8;
             od.off = g.off + (long long)i * M;
+            b.dst_vec = b.dst_vec && (g.n[0] % 4 == 0) && (od.off % 4 == 0);
             const long long G = 2LL * radius * ((long long)g.n[1] * g.n[2] + (long long)g.n[0] * g.n[2] + (long long)g.n[0] * g.n[1]);
             od.goff = b.ghosts;
             b.ghosts += G;
@@ -431,7 +448,7 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
                 const int pc = dst_panel_cols(variant);
                 return (int)((ncol + pc - 1) / pc);
             };
-            od.nt9 = nitem((long long)g.n[1] * g.n[2]);
+            od.nt9 = b.dst_xy ? g.n[2] : nitem((long long)g.n[1] * g.n[2]);
             od.base9 = b.tot9;
             b.tot9 += od.nt9;
             for (int d = 0; d < 3; ++d) {
@@ -443,9 +460,13 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
             b.orb.push_back(od);
             for (int t = 0; t < od.nt7; ++t) nat7.push_back({o, t});
             for (int t = 0; t < od.nt8; ++t) nat8.push_back({o, t});
-            for (int t = 0; t < od.nt9; ++t) natx.push_back({o, t});
-            const int ny_t = fast ? nitem((long long)g.n[0] * g.n[2]) : g.n[2] * ((g.n[0] + 31) / 32);
-            for (int t = 0; t < ny_t; ++t) naty.push_back({o, t});
+            if (b.dst_xy) {
+                for (int z = 0; z < g.n[2]; ++z) b.dxy.push_back(Item{o, z});
+            } else {
+                for (int t = 0; t < od.nt9; ++t) natx.push_back({o, t});
+                const int ny_t = fast ? nitem((long long)g.n[0] * g.n[2]) : g.n[2] * ((g.n[0] + 31) / 32);
+                for (int t = 0; t < ny_t; ++t) naty.push_back({o, t});
+            }
             const int nz_t = nitem((long long)g.n[0] * g.n[1]);
             for (int t = 0; t < nz_t; ++t) natz.push_back({o, t});
             b.fields = std::max(b.fields, od.off + M);
@@ -494,8 +515,9 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
         if ((st = upload(c, c->d_dx, b.dx))) return st;
         if ((st = upload(c, c->d_dy, b.dy))) return st;
         if ((st = upload(c, c->d_dz, b.dz))) return st;
+        if (b.dst_xy && (st = upload(c, c->d_dxy, b.dxy))) return st;
         if ((st = upload(c, c->dtab, b.dtab))) return st;
-        if (b.dst_fast) HIPCHK(c, dst_setup((b.max_n + 31) & ~31, b.dst_fast));
+        if (b.dst_fast) HIPCHK(c, dst_setup((b.max_n + 31) & ~31, b.dst_fast, b.dst_xy ? b.npxy : 0, b.dst_two));
         HIPCHK(c, c->Z32.ensure(F));
         HIPCHK(c, c->T32.ensure(F));
         HIPCHK(c, c->partRZ.ensure(2 * (size_t)b.tot9));
@@ -805,7 +827,9 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     const bool pcg = use_pcg(c, b);
     const bool graphs = (c->opts.flags & FSIC_GRAPHS) && !prof;
     DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(),
-                (int)b.dz.size(), b.dst_fast, (b.max_n + 31) & ~31, dst_blocks(c)};
+                (int)b.dz.size(), b.dst_fast, (b.max_n + 31) & ~31, dst_blocks(c),
+                b.dst_xy ? c->d_dxy.p : nullptr, b.dst_xy ? (int)b.dxy.size() : 0, b.dst_two ? 1 : 0,
+                b.dst_vec ? 1 : 0, b.npxy};
     if (pcg && !mixed) {
         // FP64 CG preconditioned by the FP32 sine-transform inverse
         CGIter<double> a{};
@@ -1048,9 +1072,10 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         }
         // preconditioned CG: sweep reads z (float) and p_old, writes p, q;
         // update reads x, p, r, q, writes x, r; the preconditioner reads r,
-        // passes the float work array through five transforms (each read and
-        // written once) and reads r again for r.z while writing z; its flops
-        // are 2 n per value per transform along an axis of n nodes
+        // passes the float work array through its transform passes (five, or
+        // three with the in-plane pair fused; each reads and writes the array
+        // once) and reads r again for r.z while writing z; its flops are 2 n
+        // per value per transform along an axis of n nodes
         for (int o = 0; o < norb; ++o) {
             const OrbDesc &od = b.orb[o];
             const double Mo = (double)od.nx * od.ny * od.nz;
@@ -1059,7 +1084,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                 const double npc = na[4 * (size_t)norb + o];
                 c->sweep_bytes += Mo * (4.0 + 3.0 * esz) * ns;
                 c->update_bytes += Mo * esz * 6.0 * nu;
-                c->precond_bytes += Mo * (36.0 + 2.0 * esz) * npc;
+                c->precond_bytes += Mo * ((b.dst_xy ? 20.0 : 36.0) + 2.0 * esz) * npc;
                 c->precond_flops += Mo * 4.0 * (od.nx + od.ny + od.nz) * npc;
             } else {
                 c->sweep_bytes += Mo * esz * 3.0 * ns;
@@ -1158,7 +1183,7 @@ void fsic_destroy(fsic_ctx *c) {
     c->P0.release(); c->P1.release(); c->Q.release(); c->X64b.release();
     c->R32.release(); c->P32a.release(); c->P32b.release(); c->Q32.release(); c->X32.release();
     c->Z32.release(); c->T32.release(); c->dtab.release(); c->partRZ.release();
-    c->d_dx.release(); c->d_dy.release(); c->d_dz.release();
+    c->d_dx.release(); c->d_dy.release(); c->d_dz.release(); c->d_dxy.release();
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
     c->partQ.release(); c->partZ.release(); c->bb.release(); c->rrfin.release();
     c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release();
