@@ -707,6 +707,24 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
             od = orb[units[pf].orb];
             load(v, od, units[pf].tile);
         }
+        const long long base = oc.off + (long long)cur.tile * nx * ny;
+        // float r for r.z: fetched in the output layout before the products,
+        // so its latency hides behind them
+        constexpr bool RPRE = INV && VEC && sizeof(TR) == 4;
+        float rv[2][BC][4];
+        if (RPRE && act) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < BC; ++c) {
+                    const int x = cb * 16 * bc + 16 * c + lr;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int y = 32 * rb + 16 * r + 4 * lq + j;
+                        rv[r][c][j] = (c < bc && x < nx && y < ny) ? (float)rres[base + (long long)y * nx + x] : 0.f;
+                    }
+                }
+        }
         // C1 = P Sx: rows y, columns x
         if (act) gemm(Xhi, Xlo, Sxh, Sxl, npx, bc);
         __syncthreads();  // every wave is done reading P
@@ -731,7 +749,6 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
         if (act) gemm(Syh, Syl, Xhi, Xlo, npy, bc);
         double part = 0.0;
         if (act) {
-            const long long base = oc.off + (long long)cur.tile * nx * ny;
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -744,7 +761,8 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
                             if (y < ny) {
                                 const long long a = base + (long long)y * nx + x;
                                 out[a] = acc[r][c][j];
-                                if (INV) part += (double)rres[a] * (double)acc[r][c][j];
+                                if (RPRE) part += (double)rv[r][c][j] * (double)acc[r][c][j];
+                                else if (INV) part += (double)rres[a] * (double)acc[r][c][j];
                             }
                         }
                     }
