@@ -183,7 +183,7 @@ def kernel_rates(agg):
 KERNEL_NAMES = {
     "sweep": "k_zmarch (CG stencil sweep: p, q = -L p, p.q)",
     "update": "k_pcg_update / k_cg_update (x += alpha p, r -= alpha q)",
-    "precond": "k_dst_fast x5 (sine-transform preconditioner, split-bf16 MFMA; k_dst_pass above 128 nodes)",
+    "precond": "k_dst_xy + k_dst_fast(z) + k_dst_xy (sine-transform preconditioner, split-bf16 MFMA; five per-axis passes where a plane does not fit in LDS, k_dst_pass above 128 nodes)",
 }
 
 
