@@ -288,13 +288,18 @@ struct Shape {
 };
 
 // preconditioned mixed-precision CG: FP32 iterations between FP64 residual
-// checks (each restarts the FP32 recursion); FSIC_PCG_CHUNK overrides 4
-int pcg_chunk() {
+// checks (each restarts the FP32 recursion).  The FP32 recursion stops
+// gaining after a few iterations of a strong preconditioner (measured on
+// 40^3-192^3 workloads: two iterations per restart need no more iterations
+// in total than FP64 CG with the split-bf16 transforms; three suit the
+// weaker ones).  FSIC_PCG_CHUNK overrides.
+int pcg_chunk(int variant) {
     static int v = [] {
         const char *e = getenv("FSIC_PCG_CHUNK");
-        return e ? std::max(1, atoi(e)) : 4;
+        return e ? std::max(1, atoi(e)) : 0;
     }();
-    return v;
+    if (v) return v;
+    return (variant == 1 || variant == 2) ? 2 : 3;
 }
 
 // CG iterations between profiled ones (FSIC_PROFILE); FSIC_PROFILE_EVERY
@@ -899,7 +904,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
         a.rs_iter = c->rs_iter.p; a.nact = c->nact.p; a.norb = norb;
         a.tol2 = tol2;
-        const int pchunk = pcg_chunk();
+        const int pchunk = pcg_chunk(b.dst_fast);
         const CGIter<float> a0 = a;
         int nref = 0;
         while (k < max_iter && !all_done) {
