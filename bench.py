@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graphs", action="store_true",
                     help="skip the unprofiled eager and graph-replay legs")
+    ap.add_argument("--no-aar", action="store_true",
+                    help="skip the FP64 alternating Anderson-Richardson leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle solving in the CPU-baseline sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -285,6 +287,23 @@ def main():
             dt, _, _, agg = run_steps(F, torch, ctx, dicts, noccs, args.steps)
             ctx.close()
             extra[name] = agg["solves"] / dt
+
+    # beside them: the same steps with the alternating Anderson-Richardson
+    # solver (FP64, same preconditioner, unprofiled)
+    if not args.no_aar:
+        ctx = F.Context(precision="fp64", tol=args.tol, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE,
+                        solver="aar")
+        for _ in range(args.warmup):
+            ctx.forward(dicts)
+            ctx.backward(noccs)
+        dt, e_a, g_a, agg = run_steps(F, torch, ctx, dicts, noccs, args.steps)
+        ctx.close()
+        extra["aar_fp64_solves_per_s"] = agg["solves"] / dt
+        extra["mean_aar_iters"] = agg["iters"] / max(1, agg["solves"])
+        if "fp64" in results:
+            extra["dE_aar_vs_fp64"] = float(np.abs(np.asarray(e_a, dtype=np.float64) - results["fp64"]["e"]).max())
+            ga = np.concatenate([np.concatenate(gs) for gs in g_a])
+            extra["dF_max_aar_vs_fp64"] = float(np.abs(ga - results["fp64"]["g"]).max())
 
     mx = results["mixed"]
     steps = args.steps

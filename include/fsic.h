@@ -83,8 +83,16 @@ enum { FSIC_FP64 = 0, FSIC_MIXED = 1 };
  *             transforms along each axis (a few iterations instead of
  *             hundreds); a batch with a grid axis above 256 nodes is solved
  *             with plain CG instead.  The default.
- * Both stop on the same FP64 relative residual. */
-enum { FSIC_CG = 0, FSIC_PCG = 1 };
+ *   FSIC_AAR  alternating Anderson-Richardson (the solver of the paper's
+ *             real-space code, Sec. II.A) with the same preconditioner:
+ *             Richardson steps x += f, f = M^{-1}(b + L x), and every third
+ *             iteration an Anderson extrapolation over the last 7
+ *             differences of x and f (weights 1 and 1).  Needs precision
+ *             FSIC_FP64 (the iterate and residual are FP64, f is FP32) and
+ *             12 extra bytes per orbital node per history column (84 B).
+ *             Batches with an axis above 256 nodes use plain CG.
+ * All stop on the same FP64 relative residual. */
+enum { FSIC_CG = 0, FSIC_PCG = 1, FSIC_AAR = 2 };
 
 /* option flags */
 #define FSIC_WANT_VSIC       1u  /* write V_SIC into fsic_system.vsic[] */
@@ -115,7 +123,7 @@ typedef struct {
 typedef struct {
     int32_t fd_order;   /* even, 2..12: order of the central second difference; radius p = fd_order/2 */
     int32_t lmax;       /* multipole order of the Dirichlet values, 0..8 */
-    int32_t solver;     /* FSIC_CG | FSIC_PCG */
+    int32_t solver;     /* FSIC_CG | FSIC_PCG | FSIC_AAR */
     int32_t precision;  /* FSIC_FP64 | FSIC_MIXED */
     double  tol;        /* relative FP64 residual ||b + L v|| / ||b|| to reach, (0, 1) */
     int32_t max_iter;   /* CG iteration cap per solve, >= 1 */

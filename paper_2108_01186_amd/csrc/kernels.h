@@ -103,6 +103,39 @@ hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *pa
                                   int stencil_layout, double *out, hipStream_t s);
 
 // ----------------------------------------------------------------------------
+// aar.hip: alternating Anderson-Richardson iteration
+// ----------------------------------------------------------------------------
+
+constexpr int kAarM = 7;                        // history columns
+constexpr int kAarG = kAarM * (kAarM + 1) / 2;  // Gram entries (upper triangle)
+constexpr int kAarD = kAarG + kAarM;            // plus right-hand sides
+
+struct AarBufs {
+    const Item *items8;
+    const OrbDesc *orb;
+    const int *done;
+    const float *F;       // f = M^{-1} r of the current iterate
+    float *Fprev;         // f of the previous iterate
+    float *Fh;            // [m][fields] f differences (ring)
+    double *Xh;           // [m][fields] x steps (ring)
+    double *X;            // iterate
+    double *gamma;        // [norb][kAarM] extrapolation weights
+    double *partD;        // [tot8][kAarD] per-tile Gram partials
+    long long fields;     // elements per history column
+    int m;                // history length (kAarM)
+};
+
+// Records f_k - f_{k-1} (hist) and, with dots, the per-tile partials of
+// F^T F and F^T f over the nh valid columns.
+hipError_t launch_aar_dots(const AarBufs &a, int nitems8, int k, int nh, int hist, int dots,
+                           hipStream_t s);
+// gamma of every unconverged orbital from the partials.
+hipError_t launch_aar_solve(const AarBufs &a, int norb, int nh, hipStream_t s);
+// x += Richardson or Anderson step; the step becomes history column k.
+hipError_t launch_aar_step(const AarBufs &a, int nitems8, int k, int nh, double omega, double beta,
+                           bool anderson, int hist, hipStream_t s);
+
+// ----------------------------------------------------------------------------
 // dst.hip: spectral (type-I sine transform) preconditioner
 // ----------------------------------------------------------------------------
 

@@ -31,7 +31,7 @@ _lib = ctypes.CDLL(LIBPATH)
 FSIC_OK, FSIC_EINVAL, FSIC_ENOMEM, FSIC_EHIP, FSIC_ENONORTHO, FSIC_EVACUUM, \
     FSIC_EBOUNDARY, FSIC_ESINGULAR, FSIC_ENOCONV, FSIC_ENOTAPE = range(10)
 FSIC_FP64, FSIC_MIXED = 0, 1
-FSIC_CG, FSIC_PCG = 0, 1
+FSIC_CG, FSIC_PCG, FSIC_AAR = 0, 1, 2
 FSIC_WANT_VSIC, FSIC_KEEP_TAPE, FSIC_ALLOW_NONORTHO, FSIC_PROFILE, FSIC_FP32_ORBITALS = 1, 2, 4, 8, 16
 FSIC_GRAPHS = 32
 FSIC_PAPER_GRADIENT, FSIC_EQ9_FORCES = 64, 128
@@ -171,7 +171,7 @@ def default_opts(**kw) -> fsic_opts:
         if k == "precision" and isinstance(v, str):
             v = {"fp64": FSIC_FP64, "mixed": FSIC_MIXED}[v]
         if k == "solver" and isinstance(v, str):
-            v = {"cg": FSIC_CG, "pcg": FSIC_PCG}[v]
+            v = {"cg": FSIC_CG, "pcg": FSIC_PCG, "aar": FSIC_AAR}[v]
         setattr(o, k, v)
     return o
 
@@ -212,7 +212,7 @@ class Context:
             if k == "precision" and isinstance(v, str):
                 v = {"fp64": FSIC_FP64, "mixed": FSIC_MIXED}[v]
             if k == "solver" and isinstance(v, str):
-                v = {"cg": FSIC_CG, "pcg": FSIC_PCG}[v]
+                v = {"cg": FSIC_CG, "pcg": FSIC_PCG, "aar": FSIC_AAR}[v]
             setattr(self.opts, k, v)
         _check(fsic_set_opts(self._h, ctypes.byref(self.opts)), self._h)
 
@@ -327,7 +327,7 @@ def op_poisson(rho, n, h, origin, fd_order=12, lmax=6, tol=1e-10, max_iter=20000
     it = np.zeros(count, dtype=np.int32)
     rr = np.zeros(count)
     prec = {"fp64": FSIC_FP64, "mixed": FSIC_MIXED}[precision] if isinstance(precision, str) else precision
-    solv = {"cg": FSIC_CG, "pcg": FSIC_PCG}[solver] if isinstance(solver, str) else solver
+    solv = {"cg": FSIC_CG, "pcg": FSIC_PCG, "aar": FSIC_AAR}[solver] if isinstance(solver, str) else solver
     _check(fsic_op_poisson(ctypes.byref(g), fd_order, lmax, count, _dev_ptr(rho), _dev_ptr(v), tol,
                            max_iter, prec, solv, it.ctypes.data_as(_ip), rr.ctypes.data_as(_dp),
                            _stream_ptr(stream)))

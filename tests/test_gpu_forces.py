@@ -38,7 +38,7 @@ def mol40_grad_oracle(oracle, mol40):
 
 
 @pytest.mark.parametrize("precision,solver", [("fp64", "cg"), ("mixed", "cg"), ("fp64", "pcg"),
-                                              ("mixed", "pcg")])
+                                              ("mixed", "pcg"), ("fp64", "aar")])
 def test_mol40_gradient_vs_oracle(torch_cuda, F, mol40, mol40_grad_oracle, precision, solver):
     torch = torch_cuda
     _say(f"gradient mol40 {precision} {solver}")
