@@ -229,6 +229,7 @@ typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 constexpr int kFT = 512;   // threads per block (8 waves)
 constexpr int kFV = 32;    // panel values per thread and buffer: np * PC / kFT <= 32
+constexpr int kNV2 = 20;   // fused x-y pass with two blocks per compute unit: plane <= kNV2 * kFT
 
 __device__ __forceinline__ void bsplit(float x, __bf16 &hi, __bf16 &lo) {
     hi = (__bf16)x;
@@ -443,6 +444,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         const int c = ct * 16 + lr;
         const long long cg = (long long)cur.tile * PC + c;
         const bool cv = cg < ncol_of(oc);
+        double part = 0.0;
         if (MODE == 1) {
             // scale by norm / lambda(jx, jy, m) and transform again
             const float *gx = tab + oc.dst_g[0], *gy = tab + oc.dst_g[1];
@@ -461,6 +463,8 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
                     for (int j = 0; j < 4; ++j) {
                         const int m = m0 + j;
                         const float vv = (cv && m < n) ? acc[i][j] * (norm / ((gxy + gzs[m]) * ih2)) : 0.f;
+                        // r.z = c sum_k rhat_k^2 / lambda_k (rhat = S r, S^2 = I / c)
+                        if (RZ) part += (double)acc[i][j] * (double)vv;
                         bsplit(vv, hh[j], ll[j]);
                     }
                     *reinterpret_cast<bf4 *>(Xhi + c * sw + m0) = bf4{hh[0], hh[1], hh[2], hh[3]};
@@ -470,7 +474,6 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
             __syncthreads();
             gemm(np);
         }
-        double part = 0.0;
         if (cv) {
             const long long eo = oc.off + eoff(oc, cg);
             const long long ks = kstr_of(oc);
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
                         if (m0 < n) {  // n % 4 == 0: all four rows are in range
                             const float4 q = float4{acc[i][0], acc[i][1], acc[i][2], acc[i][3]};
                             *reinterpret_cast<float4 *>(out + eo + m0) = q;
-                            if (RZ) part += dot4(rres + eo + m0, q);
+                            if (RZ && MODE == 0) part += dot4(rres + eo + m0, q);
                         }
                     } else {
 #pragma unroll
@@ -493,7 +496,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
                             if (m < n) {
                                 const long long a = eo + (long long)m * ks;
                                 out[a] = acc[i][j];
-                                if (RZ) part += (double)rres[a] * (double)acc[i][j];
+                                if (RZ && MODE == 0) part += (double)rres[a] * (double)acc[i][j];
                             }
                         }
                     }
@@ -540,25 +543,33 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
 // with C1 written back transposed (C1t[x][y]) over P so that both products
 // read their B operand as one 16-byte LDS row segment.  The transforms along
 // different axes commute, so the same kernel serves the forward pass (reads
-// the CG residual) and the inverse pass (writes z and the r.z partial of the
-// plane into rz[base9 + z]).  Each application of the preconditioner then
-// moves the field through HBM three times (xy, z, xy) instead of five.
+// the CG residual) and the inverse pass (writes z).  Each application of the
+// preconditioner then moves the field through HBM three times (xy, z, xy)
+// instead of five, and the z pass between them forms r.z from the spectral
+// coefficients it already holds (r.z = c sum_k rhat_k^2 / lambda_k), so the
+// inverse pass does not read r.
 // VEC (every nx and orbital offset of the batch a multiple of 4) moves the
 // planes as 16-byte vectors; otherwise as single values.
 // Wave w computes the 32 x (npx / 2) block of C at rows 32 (w / 2) and
 // columns (w % 2) npx / 2: two row tiles times npx / 32 column tiles, so each
 // A fragment is reused over the column tiles and each B fragment over both
 // row tiles.  Waves w >= npy / 16 only move data.
+// two fused x-y blocks fit one compute unit: the plane (<= 96 x 96) fits the
+// single register buffer and two blocks' LDS fit 160 KB
+bool dst_xy_occ2(int np, bool two) {
+    return np <= 96 && (size_t)np * np <= (size_t)kNV2 * kFT && 2 * dst_xy_lds(np, two) <= 160 * 1024;
+}
+
 size_t dst_xy_lds(int np, bool two) {
     const int sw = np + 8;
     return (size_t)2 * np * sw * 2 + (size_t)(two ? 2 : 1) * 2 * np * sw * 2 + 16 * sizeof(double);
 }
 
-template <bool INV, bool VEC, typename TIN, typename TR>
-__global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, int npmax, int two,
-                                                const OrbDesc *orb, const int *done,
-                                                const float *tab, const TIN *in, float *out,
-                                                const TR *rres, double *rz, int *cnt) {
+template <bool VEC, typename TIN, bool OCC2>
+__global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units, int nunits, int npmax, int two,
+                                                               const OrbDesc *orb, const int *done,
+                                                               const float *tab, const TIN *in, float *out,
+                                                               int *cnt) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int sw = npmax + 8;  // LDS row stride (bf16): 16-byte rows
     __bf16 *Xhi = reinterpret_cast<__bf16 *>(smem);
@@ -577,14 +588,18 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
     };
     // VEC (every nx and orbital offset a multiple of 4): planes move as
     // 16-byte vectors
-    // plane loads into v[kFV]: vector group g = t + kFT i (elements 4g .. 4g+3)
+    // OCC2 (planes up to kNV2 * kFT nodes, two blocks per compute unit): one
+    // register buffer, no prefetch inside the block; the other resident block
+    // overlaps its memory traffic with this one's products
+    constexpr int NV = OCC2 ? kNV2 : kFV;
+    // plane loads into v[NV]: vector group g = t + kFT i (elements 4g .. 4g+3)
     // or element e = t + kFT i, in row-major (y, x) order
-    auto load = [&](float (&v)[kFV], const OrbDesc &od, int z) {
+    auto load = [&](float (&v)[NV], const OrbDesc &od, int z) {
         const int pl = od.nx * od.ny;
         const long long base = od.off + (long long)z * pl;
         if (VEC) {
 #pragma unroll
-            for (int i = 0; i < kFV / 4; ++i) {
+            for (int i = 0; i < NV / 4; ++i) {
                 const int g = t + kFT * i;
                 const float4 q = (4 * g < pl) ? ld4(in + base + 4 * g) : float4{0.f, 0.f, 0.f, 0.f};
                 v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
@@ -592,16 +607,16 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
             return;
         }
 #pragma unroll
-        for (int i = 0; i < kFV; ++i) {
+        for (int i = 0; i < NV; ++i) {
             const int e = t + kFT * i;
             v[i] = (e < pl) ? (float)in[base + e] : 0.f;
         }
     };
-    auto to_lds = [&](const float (&v)[kFV], const OrbDesc &od) {
+    auto to_lds = [&](const float (&v)[NV], const OrbDesc &od) {
         const int nx = od.nx, pl = od.nx * od.ny;
         if (VEC) {
 #pragma unroll
-            for (int i = 0; i < kFV / 4; ++i) {
+            for (int i = 0; i < NV / 4; ++i) {
                 const int g = t + kFT * i;
                 if (4 * g < pl) {
                     const int y = (4 * g) / nx, x = 4 * g - y * nx;
@@ -614,7 +629,7 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < kFV; ++i) {
+            for (int i = 0; i < NV; ++i) {
                 const int e = t + kFT * i;
                 if (e < pl) {
                     const int y = e / nx, x = e - y * nx;
@@ -640,7 +655,7 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
     const int lane = t & 63, w = t >> 6;
     const int lr = lane & 15, lq = lane >> 4;
     const int rb = w >> 1, cb = w & 1;
-    constexpr int BC = 4;  // column tiles per wave: npx / 32 <= 4
+    constexpr int BC = OCC2 ? 3 : 4;  // column tiles per wave: npx / 32 <= BC
     flt4 acc[2][BC];
     // acc = A B over k < npk for the wave's block; A rows from Ah/Al
     // (row-major, stride sw), B as Bt[col][k] from Bh/Bl
@@ -686,7 +701,7 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
             Sl[m * sw + k] = lo;
         }
     };
-    auto unit = [&](float (&v)[kFV], int u, OrbDesc &od, int pf) {
+    auto unit = [&](float (&v)[NV], int u, OrbDesc &od, int pf) {
         const Item cur = units[u];
         const OrbDesc oc = od;
         const int nx = oc.nx, ny = oc.ny;
@@ -708,23 +723,6 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
             load(v, od, units[pf].tile);
         }
         const long long base = oc.off + (long long)cur.tile * nx * ny;
-        // float r for r.z: fetched in the output layout before the products,
-        // so its latency hides behind them
-        constexpr bool RPRE = INV && VEC && sizeof(TR) == 4;
-        float rv[2][BC][4];
-        if (RPRE && act) {
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-#pragma unroll
-                for (int c = 0; c < BC; ++c) {
-                    const int x = cb * 16 * bc + 16 * c + lr;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int y = 32 * rb + 16 * r + 4 * lq + j;
-                        rv[r][c][j] = (c < bc && x < nx && y < ny) ? (float)rres[base + (long long)y * nx + x] : 0.f;
-                    }
-                }
-        }
         // C1 = P Sx: rows y, columns x
         if (act) gemm(Xhi, Xlo, Sxh, Sxl, npx, bc);
         __syncthreads();  // every wave is done reading P
@@ -747,7 +745,6 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
         __syncthreads();
         // C2 = Sy C1: rows y, columns x (B = C1t)
         if (act) gemm(Syh, Syl, Xhi, Xlo, npy, bc);
-        double part = 0.0;
         if (act) {
 #pragma unroll
             for (int r = 0; r < 2; ++r)
@@ -761,20 +758,23 @@ __global__ __launch_bounds__(kFT) void k_dst_xy(const Item *units, int nunits, i
                             if (y < ny) {
                                 const long long a = base + (long long)y * nx + x;
                                 out[a] = acc[r][c][j];
-                                if (RPRE) part += (double)rv[r][c][j] * (double)acc[r][c][j];
-                                else if (INV) part += (double)rres[a] * (double)acc[r][c][j];
                             }
                         }
                     }
                 }
         }
-        if (INV) {
-            const double sum = block_sum_fast(part, sred);
-            if (t == 0) rz[oc.base9 + cur.tile] = sum;
-        }
     };
 
-    float va[kFV], vb[kFV];
+    if constexpr (OCC2) {
+        float v[NV];
+        for (int q = next_active(u0); q < u1; q = next_active(q + 1)) {
+            OrbDesc o = orb[units[q].orb];
+            load(v, o, units[q].tile);
+            unit(v, q, o, u1);
+        }
+        return;
+    }
+    float va[NV], vb[NV];
     int q0 = next_active(u0);
     if (q0 >= u1) return;
     int q1 = next_active(q0 + 1);
@@ -831,20 +831,28 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
     do {                                                                                           \
         const size_t lxy = dst_xy_lds(di.npxy, di.two != 0);                                       \
         const size_t lz = dst_fast_lds(di.np, PC_, SLO_);                                          \
-        if (di.xyvec)                                                                              \
-            hipLaunchKernelGGL((k_dst_xy<false, true, T, T>), grid(di.nxy), dim3(kFT), lxy, s,      \
-                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, r, work, nr, nd, cnt); \
+        const bool o2 = di.xyvec && dst_xy_occ2(di.npxy, di.two != 0);                             \
+        const dim3 gxy = o2 ? dim3((unsigned)std::min(di.nxy, 2 * di.blocks)) : grid(di.nxy);      \
+        if (o2)                                                                                    \
+            hipLaunchKernelGGL((k_dst_xy<true, T, true>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,    \
+                               di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
+        else if (di.xyvec)                                                                         \
+            hipLaunchKernelGGL((k_dst_xy<true, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,   \
+                               di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
         else                                                                                       \
-            hipLaunchKernelGGL((k_dst_xy<false, false, T, T>), grid(di.nxy), dim3(kFT), lxy, s,     \
-                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, r, work, nr, nd, cnt); \
-        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, false, PC_, SLO_>), grid(di.nz), dim3(kFT),  \
-                           lz, s, di.z, di.nz, di.np, orb, done, tab, wk, work, nr, nd, nc);         \
-        if (di.xyvec)                                                                              \
-            hipLaunchKernelGGL((k_dst_xy<true, true, float, T>), grid(di.nxy), dim3(kFT), lxy, s,   \
-                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, wk, z, r, rz, nc);     \
+            hipLaunchKernelGGL((k_dst_xy<false, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,  \
+                               di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
+        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, PC_, SLO_>), grid(di.nz), dim3(kFT),   \
+                           lz, s, di.z, di.nz, di.np, orb, done, tab, wk, work, r, rz, nc);          \
+        if (o2)                                                                                    \
+            hipLaunchKernelGGL((k_dst_xy<true, float, true>), gxy, dim3(kFT), lxy, s, di.xy,        \
+                               di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
+        else if (di.xyvec)                                                                         \
+            hipLaunchKernelGGL((k_dst_xy<true, float, false>), gxy, dim3(kFT), lxy, s, di.xy,       \
+                               di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
         else                                                                                       \
-            hipLaunchKernelGGL((k_dst_xy<true, false, float, T>), grid(di.nxy), dim3(kFT), lxy, s,  \
-                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, wk, z, r, rz, nc);     \
+            hipLaunchKernelGGL((k_dst_xy<false, float, false>), gxy, dim3(kFT), lxy, s, di.xy,      \
+                               di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
     } while (0)
         if (di.nxy > 0) {
             if (di.fast == 1) FSIC_DST_XY(128, true);
@@ -875,14 +883,14 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
 hipError_t dst_setup(int np, int variant, int npxy, bool two) {
     if (npxy > 0) {
         const size_t lxy = dst_xy_lds(npxy, two);
-        set_lds_limit(k_dst_xy<false, true, float, float>, lxy);
-        set_lds_limit(k_dst_xy<false, true, double, double>, lxy);
-        set_lds_limit(k_dst_xy<true, true, float, float>, lxy);
-        set_lds_limit(k_dst_xy<true, true, float, double>, lxy);
-        set_lds_limit(k_dst_xy<false, false, float, float>, lxy);
-        set_lds_limit(k_dst_xy<false, false, double, double>, lxy);
-        set_lds_limit(k_dst_xy<true, false, float, float>, lxy);
-        set_lds_limit(k_dst_xy<true, false, float, double>, lxy);
+        set_lds_limit(k_dst_xy<true, float, false>, lxy);
+        set_lds_limit(k_dst_xy<true, double, false>, lxy);
+        set_lds_limit(k_dst_xy<false, float, false>, lxy);
+        set_lds_limit(k_dst_xy<false, double, false>, lxy);
+        if (dst_xy_occ2(npxy, two)) {
+            set_lds_limit(k_dst_xy<true, float, true>, lxy);
+            set_lds_limit(k_dst_xy<true, double, true>, lxy);
+        }
     }
 #define FSIC_DST_LIMITS(PC_, SLO_)                                                      \
     do {                                                                                \
@@ -893,6 +901,8 @@ hipError_t dst_setup(int np, int variant, int npxy, bool two) {
         set_lds_limit(k_dst_fast<1, 0, float, double, false, PC_, SLO_>, lds);          \
         set_lds_limit(k_dst_fast<2, 1, float, float, false, PC_, SLO_>, lds);           \
         set_lds_limit(k_dst_fast<2, 1, float, double, false, PC_, SLO_>, lds);          \
+        set_lds_limit(k_dst_fast<2, 1, float, float, true, PC_, SLO_>, lds);            \
+        set_lds_limit(k_dst_fast<2, 1, float, double, true, PC_, SLO_>, lds);           \
         set_lds_limit(k_dst_fast<0, 0, float, float, true, PC_, SLO_>, lds);            \
         set_lds_limit(k_dst_fast<0, 0, float, double, true, PC_, SLO_>, lds);           \
     } while (0)

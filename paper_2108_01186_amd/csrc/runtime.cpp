@@ -466,7 +466,9 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
                 const int pc = dst_panel_cols(variant);
                 return (int)((ncol + pc - 1) / pc);
             };
-            od.nt9 = b.dst_xy ? g.n[2] : nitem((long long)g.n[1] * g.n[2]);
+            // r.z partial slots: one per z-pass panel (the z pass forms r.z
+            // when the in-plane transforms are fused), else one per x panel
+            od.nt9 = b.dst_xy ? nitem((long long)g.n[0] * g.n[1]) : nitem((long long)g.n[1] * g.n[2]);
             od.base9 = b.tot9;
             b.tot9 += od.nt9;
             for (int d = 0; d < 3; ++d) {
