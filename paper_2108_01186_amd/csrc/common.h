@@ -63,6 +63,7 @@ struct DstItems {
     int nxy, two;    // their count; two: separate x and y sine matrices in LDS
     int xyvec;       // every nx and orbital offset is a multiple of 4
     int npxy;        // largest padded in-plane axis (LDS layout of the fused kernel)
+    int zocc2;       // z pass: 64-column panels, two blocks per compute unit
 };
 
 // panel columns of a fast transform variant

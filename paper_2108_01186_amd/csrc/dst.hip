@@ -230,6 +230,7 @@ typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 constexpr int kFT = 512;   // threads per block (8 waves)
 constexpr int kFV = 32;    // panel values per thread and buffer: np * PC / kFT <= 32
 constexpr int kNV2 = 20;   // fused x-y pass with two blocks per compute unit: plane <= kNV2 * kFT
+constexpr int kNVZ = 12;   // z pass with two blocks per compute unit: np * 64 <= kNVZ * kFT (np <= 96)
 
 __device__ __forceinline__ void bsplit(float x, __bf16 &hi, __bf16 &lo) {
     hi = (__bf16)x;
@@ -272,8 +273,8 @@ __device__ __forceinline__ double dot4(const double *p, const float4 &v) {
     return a.x * v.x + a.y * v.y + b.x * v.z + b.y * v.w;
 }
 
-template <int AX, int MODE, typename TIN, typename TR, bool RZ, int PC, bool SLO>
-__global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits, int npmax,
+template <int AX, int MODE, typename TIN, typename TR, bool RZ, int PC, bool SLO, bool OCC2 = false>
+__global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *units, int nunits, int npmax,
                                                   const OrbDesc *orb, const int *done,
                                                   const float *tab, const TIN *in, float *out,
                                                   const TR *rres, double *rz, int *cnt) {
@@ -318,11 +319,15 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
     auto xvec = [&](const OrbDesc &od) -> bool {
         return AX == 0 && (od.nx & 3) == 0 && (od.off & 3) == 0;
     };
-    // panel loads into v[kFV]: thread t holds column c_ld and, per i, either
+    // OCC2 (two blocks per compute unit, np * PC <= kNVZ * kFT): one register
+    // buffer and no prefetch inside the block; the other resident block
+    // overlaps its memory traffic with this one's products
+    constexpr int NV = OCC2 ? kNVZ : kFV;
+    // panel loads into v[NV]: thread t holds column c_ld and, per i, either
     // rows k = 2 kg + 2 G i, k + 1 (pairs) or k = 4 kg + 4 G i .. + 3 (x vectors)
     const int c_ld = AX == 0 ? (t / G) : (t % PC);
     const int kg = AX == 0 ? (t % G) : (t / PC);
-    auto load = [&](float (&v)[kFV], const OrbDesc &od, int pnl) {
+    auto load = [&](float (&v)[NV], const OrbDesc &od, int pnl) {
         const int n = axis_n(od, AX);
         const int np = (n + 31) & ~31;
         const long long cg = (long long)pnl * PC + c_ld;
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         const long long base = od.off + (cv ? eoff(od, cg) : 0);
         if (xvec(od)) {
 #pragma unroll
-            for (int i = 0; i < kFV / 4; ++i) {
+            for (int i = 0; i < NV / 4; ++i) {
                 const int k = 4 * kg + 4 * G * i;
                 const float4 q = (k < np && cv && k < n) ? ld4(in + base + k) : float4{0.f, 0.f, 0.f, 0.f};
                 v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
@@ -340,17 +345,17 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         const long long ks = kstr_of(od);
         const int npair = np / (2 * G);
 #pragma unroll
-        for (int i = 0; i < kFV / 2; ++i) {
+        for (int i = 0; i < NV / 2; ++i) {
             const int k = 2 * kg + 2 * G * i;
             v[2 * i] = (i < npair && cv && k < n) ? (float)in[base + (long long)k * ks] : 0.f;
             v[2 * i + 1] = (i < npair && cv && k + 1 < n) ? (float)in[base + (long long)(k + 1) * ks] : 0.f;
         }
     };
-    auto to_lds = [&](const float (&v)[kFV], const OrbDesc &od) {
+    auto to_lds = [&](const float (&v)[NV], const OrbDesc &od) {
         const int np = (axis_n(od, AX) + 31) & ~31;
         if (xvec(od)) {
 #pragma unroll
-            for (int i = 0; i < kFV / 4; ++i) {
+            for (int i = 0; i < NV / 4; ++i) {
                 const int k = 4 * kg + 4 * G * i;
                 if (k < np) {
                     __bf16 h[4], l[4];
@@ -364,7 +369,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         }
         const int npair = np / (2 * G);
 #pragma unroll
-        for (int i = 0; i < kFV / 2; ++i) {
+        for (int i = 0; i < NV / 2; ++i) {
             if (i < npair) {
                 const int k = 2 * kg + 2 * G * i;
                 __bf16 h0, l0, h1, l1;
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
     constexpr int NCT = PC / 16;
     constexpr int RS = (kFT / 64) / NCT;
     const int ct = w % NCT, r0 = w / NCT;
-    constexpr int MT = 8;   // row tiles per wave: np / 16 / RS <= 8
+    constexpr int MT = OCC2 ? 4 : 8;  // row tiles per wave: np / 16 / RS <= MT
     const int lr = lane & 15, lq = lane >> 4;
     flt4 acc[MT];
     auto gemm = [&](int np) {
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
     int staged = -1;  // axis length whose sine matrix is in LDS
     // one unit: products of the panel held in v; the unit `pf` (or u1: none)
     // is loaded into v once its values are in LDS
-    auto unit = [&](float (&v)[kFV], int u, OrbDesc &od, int pf) {
+    auto unit = [&](float (&v)[NV], int u, OrbDesc &od, int pf) {
         const Item cur = units[u];
         const OrbDesc oc = od;
         const int n = axis_n(oc, AX);
@@ -509,8 +514,17 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
         }
     };
 
+    if constexpr (OCC2) {
+        float v[NV];
+        for (int q = next_active(u0); q < u1; q = next_active(q + 1)) {
+            OrbDesc o = orb[units[q].orb];
+            load(v, o, units[q].tile);
+            unit(v, q, o, u1);
+        }
+        return;
+    }
     // two register buffers: va holds unit q0, vb unit q1 (u1: none)
-    float va[kFV], vb[kFV];
+    float va[NV], vb[NV];
     int q0 = next_active(u0);
     if (q0 >= u1) return;
     int q1 = next_active(q0 + 1);
@@ -558,6 +572,11 @@ __global__ __launch_bounds__(kFT) void k_dst_fast(const Item *units, int nunits,
 // single register buffer and two blocks' LDS fit 160 KB
 bool dst_xy_occ2(int np, bool two) {
     return np <= 96 && (size_t)np * np <= (size_t)kNV2 * kFT && 2 * dst_xy_lds(np, two) <= 160 * 1024;
+}
+
+// two z-pass blocks (64-column panels with S_lo) fit one compute unit
+bool dst_z_occ2(int np) {
+    return np <= 96 && np * 64 <= kNVZ * kFT && 2 * dst_fast_lds(np, 64, true) <= 160 * 1024;
 }
 
 size_t dst_xy_lds(int np, bool two) {
@@ -842,8 +861,14 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
         else                                                                                       \
             hipLaunchKernelGGL((k_dst_xy<false, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,  \
                                di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
-        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, PC_, SLO_>), grid(di.nz), dim3(kFT),   \
-                           lz, s, di.z, di.nz, di.np, orb, done, tab, wk, work, r, rz, nc);          \
+        if (di.zocc2)                                                                              \
+            hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, 64, true, true>),                 \
+                               dim3((unsigned)std::min(di.nz, 2 * di.blocks)), dim3(kFT),           \
+                               dst_fast_lds(di.np, 64, true), s, di.z, di.nz, di.np, orb, done, tab, \
+                               wk, work, r, rz, nc);                                                \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, PC_, SLO_>), grid(di.nz), dim3(kFT), \
+                               lz, s, di.z, di.nz, di.np, orb, done, tab, wk, work, r, rz, nc);      \
         if (o2)                                                                                    \
             hipLaunchKernelGGL((k_dst_xy<true, float, true>), gxy, dim3(kFT), lxy, s, di.xy,        \
                                di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
@@ -890,6 +915,10 @@ hipError_t dst_setup(int np, int variant, int npxy, bool two) {
         if (dst_xy_occ2(npxy, two)) {
             set_lds_limit(k_dst_xy<true, float, true>, lxy);
             set_lds_limit(k_dst_xy<true, double, true>, lxy);
+        }
+        if (dst_z_occ2(np)) {
+            set_lds_limit(k_dst_fast<2, 1, float, float, true, 64, true, true>, dst_fast_lds(np, 64, true));
+            set_lds_limit(k_dst_fast<2, 1, float, double, true, 64, true, true>, dst_fast_lds(np, 64, true));
         }
     }
 #define FSIC_DST_LIMITS(PC_, SLO_)                                                      \

@@ -147,6 +147,10 @@ size_t dst_fast_lds(int np, int pc, bool slo);
 // nodes; two: the x and y sine matrices differ somewhere in the batch.
 size_t dst_xy_lds(int np, bool two);
 
+// The z pass of a fused-plane batch with all axes padded to np can run two
+// 64-column blocks per compute unit.
+bool dst_z_occ2(int np);
+
 // Allows the fast transform kernels of a variant (1..3, see DstItems) their
 // dynamic LDS for axes up to np, and the fused x-y kernel (npxy > 0: in-plane
 // axes up to npxy) its own.

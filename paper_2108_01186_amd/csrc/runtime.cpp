@@ -164,6 +164,7 @@ struct Batch {
     bool dst_two = false;  // some orbital has nx != ny
     bool dst_vec = true;   // every nx and orbital offset is a multiple of 4
     int npxy = 0;          // largest in-plane axis, padded to 32
+    bool dst_zocc2 = false;  // z pass in 64-column panels, two blocks per compute unit
 };
 
 void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<Item> &out) {
@@ -420,6 +421,7 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
         const char *env = std::getenv("FSIC_DST_XY");
         b.dst_xy = fast && b.npxy <= 128 && dst_xy_lds(b.npxy, b.dst_two) <= ldsmax &&
                    !(env && std::atoi(env) == 0);
+        b.dst_zocc2 = b.dst_xy && variant == 1 && dst_z_occ2(npx);
     }
     std::vector<std::pair<int, int>> nat7, nat8, natx, naty, natz;
     std::map<int, std::pair<int, int>> dst_done;  // n -> (sine offset, symbol offset)
@@ -468,7 +470,9 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
             };
             // r.z partial slots: one per z-pass panel (the z pass forms r.z
             // when the in-plane transforms are fused), else one per x panel
-            od.nt9 = b.dst_xy ? nitem((long long)g.n[0] * g.n[1]) : nitem((long long)g.n[1] * g.n[2]);
+            const int zpc = b.dst_zocc2 ? 64 : dst_panel_cols(variant);
+            od.nt9 = b.dst_xy ? (int)(((long long)g.n[0] * g.n[1] + zpc - 1) / zpc)
+                              : nitem((long long)g.n[1] * g.n[2]);
             od.base9 = b.tot9;
             b.tot9 += od.nt9;
             for (int d = 0; d < 3; ++d) {
@@ -487,7 +491,7 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
                 const int ny_t = fast ? nitem((long long)g.n[0] * g.n[2]) : g.n[2] * ((g.n[0] + 31) / 32);
                 for (int t = 0; t < ny_t; ++t) naty.push_back({o, t});
             }
-            const int nz_t = nitem((long long)g.n[0] * g.n[1]);
+            const int nz_t = (int)(((long long)g.n[0] * g.n[1] + zpc - 1) / zpc);
             for (int t = 0; t < nz_t; ++t) natz.push_back({o, t});
             b.fields = std::max(b.fields, od.off + M);
         }
@@ -862,7 +866,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(),
                 (int)b.dz.size(), b.dst_fast, (b.max_n + 31) & ~31, dst_blocks(c),
                 b.dst_xy ? c->d_dxy.p : nullptr, b.dst_xy ? (int)b.dxy.size() : 0, b.dst_two ? 1 : 0,
-                b.dst_vec ? 1 : 0, b.npxy};
+                b.dst_vec ? 1 : 0, b.npxy, b.dst_zocc2 ? 1 : 0};
     if (pcg && !mixed) {
         // FP64 CG preconditioned by the FP32 sine-transform inverse
         CGIter<double> a{};
