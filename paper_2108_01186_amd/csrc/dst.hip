@@ -584,7 +584,8 @@ size_t dst_xy_lds(int np, bool two) {
     return (size_t)2 * np * sw * 2 + (size_t)(two ? 2 : 1) * 2 * np * sw * 2 + 16 * sizeof(double);
 }
 
-template <bool VEC, typename TIN, bool OCC2>
+// TR (the solve's residual type) only names the instantiation per precision.
+template <bool VEC, typename TIN, typename TR, bool OCC2>
 __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units, int nunits, int npmax, int two,
                                                                const OrbDesc *orb, const int *done,
                                                                const float *tab, const TIN *in, float *out,
@@ -853,13 +854,13 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
         const bool o2 = di.xyvec && dst_xy_occ2(di.npxy, di.two != 0);                             \
         const dim3 gxy = o2 ? dim3((unsigned)std::min(di.nxy, 2 * di.blocks)) : grid(di.nxy);      \
         if (o2)                                                                                    \
-            hipLaunchKernelGGL((k_dst_xy<true, T, true>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,    \
+            hipLaunchKernelGGL((k_dst_xy<true, T, T, true>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,    \
                                di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
         else if (di.xyvec)                                                                         \
-            hipLaunchKernelGGL((k_dst_xy<true, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,   \
+            hipLaunchKernelGGL((k_dst_xy<true, T, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,   \
                                di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
         else                                                                                       \
-            hipLaunchKernelGGL((k_dst_xy<false, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,  \
+            hipLaunchKernelGGL((k_dst_xy<false, T, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,  \
                                di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
         if (di.zocc2)                                                                              \
             hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, 64, true, true>),                 \
@@ -870,13 +871,13 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
             hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, PC_, SLO_>), grid(di.nz), dim3(kFT), \
                                lz, s, di.z, di.nz, di.np, orb, done, tab, wk, work, r, rz, nc);      \
         if (o2)                                                                                    \
-            hipLaunchKernelGGL((k_dst_xy<true, float, true>), gxy, dim3(kFT), lxy, s, di.xy,        \
+            hipLaunchKernelGGL((k_dst_xy<true, float, T, true>), gxy, dim3(kFT), lxy, s, di.xy,        \
                                di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
         else if (di.xyvec)                                                                         \
-            hipLaunchKernelGGL((k_dst_xy<true, float, false>), gxy, dim3(kFT), lxy, s, di.xy,       \
+            hipLaunchKernelGGL((k_dst_xy<true, float, T, false>), gxy, dim3(kFT), lxy, s, di.xy,       \
                                di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
         else                                                                                       \
-            hipLaunchKernelGGL((k_dst_xy<false, float, false>), gxy, dim3(kFT), lxy, s, di.xy,      \
+            hipLaunchKernelGGL((k_dst_xy<false, float, T, false>), gxy, dim3(kFT), lxy, s, di.xy,      \
                                di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
     } while (0)
         if (di.nxy > 0) {
@@ -908,13 +909,16 @@ hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int 
 hipError_t dst_setup(int np, int variant, int npxy, bool two) {
     if (npxy > 0) {
         const size_t lxy = dst_xy_lds(npxy, two);
-        set_lds_limit(k_dst_xy<true, float, false>, lxy);
-        set_lds_limit(k_dst_xy<true, double, false>, lxy);
-        set_lds_limit(k_dst_xy<false, float, false>, lxy);
-        set_lds_limit(k_dst_xy<false, double, false>, lxy);
+        set_lds_limit(k_dst_xy<true, float, float, false>, lxy);
+        set_lds_limit(k_dst_xy<true, double, double, false>, lxy);
+        set_lds_limit(k_dst_xy<true, float, double, false>, lxy);
+        set_lds_limit(k_dst_xy<false, float, float, false>, lxy);
+        set_lds_limit(k_dst_xy<false, double, double, false>, lxy);
+        set_lds_limit(k_dst_xy<false, float, double, false>, lxy);
         if (dst_xy_occ2(npxy, two)) {
-            set_lds_limit(k_dst_xy<true, float, true>, lxy);
-            set_lds_limit(k_dst_xy<true, double, true>, lxy);
+            set_lds_limit(k_dst_xy<true, float, float, true>, lxy);
+            set_lds_limit(k_dst_xy<true, double, double, true>, lxy);
+            set_lds_limit(k_dst_xy<true, float, double, true>, lxy);
         }
         if (dst_z_occ2(np)) {
             set_lds_limit(k_dst_fast<2, 1, float, float, true, 64, true, true>, dst_fast_lds(np, 64, true));

@@ -1142,11 +1142,12 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             else { c->precond_launches += 1; c->precond_ms += ms; }
         }
         // preconditioned CG: sweep reads z (float) and p_old, writes p, q;
-        // update reads x, p, r, q, writes x, r; the preconditioner reads r,
-        // passes the float work array through its transform passes (five, or
-        // three with the in-plane pair fused; each reads and writes the array
-        // once) and reads r again for r.z while writing z; its flops are 2 n
-        // per value per transform along an axis of n nodes
+        // update reads x, p, r, q, writes x, r; the preconditioner reads r
+        // and passes the float work array through its transform passes (each
+        // reads and writes it once) until the last writes z: three passes
+        // with the in-plane pair fused (r.z from the spectral coefficients of
+        // the z pass), else five, the last reading r again for r.z; its flops
+        // are 2 n per value per transform along an axis of n nodes
         for (int o = 0; o < norb; ++o) {
             const OrbDesc &od = b.orb[o];
             const double Mo = (double)od.nx * od.ny * od.nz;
@@ -1155,7 +1156,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                 const double npc = na[4 * (size_t)norb + o];
                 c->sweep_bytes += Mo * (4.0 + 3.0 * esz) * ns;
                 c->update_bytes += Mo * esz * 6.0 * nu;
-                c->precond_bytes += Mo * ((b.dst_xy ? 20.0 : 36.0) + 2.0 * esz) * npc;
+                c->precond_bytes += Mo * (b.dst_xy ? 20.0 + esz : 36.0 + 2.0 * esz) * npc;
                 c->precond_flops += Mo * 4.0 * (od.nx + od.ny + od.nz) * npc;
             } else {
                 c->sweep_bytes += Mo * esz * 3.0 * ns;
