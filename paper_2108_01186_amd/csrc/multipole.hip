@@ -35,8 +35,8 @@ __device__ __forceinline__ void regular_harmonics(double x, double y, double z, 
             else if (l == m + 1)
                 pl = (double)(2 * m + 1) * z * pm1;
             else
-                pl = ((double)(2 * l - 1) * z * pm1 - (double)(l + m - 1) * r2 * pm2) /
-                     (double)(l - m);
+                pl = ((double)(2 * l - 1) * z * pm1 - (double)(l + m - 1) * r2 * pm2) *
+                     (1.0 / (double)(l - m));  // compile-time reciprocal: no FP64 divide
             pm2 = pm1;
             pm1 = pl;
             if (m == 0) {
@@ -70,9 +70,10 @@ __global__ __launch_bounds__(256) void k_moments(HarmTables ht, const OrbDesc *o
     for (int e = 0; e < kPW / 256; ++e) {
         const long long i = base + e * 256 + threadIdx.x;
         if (i < M) {
-            const int ix = (int)(i % od.nx);
-            const int iy = (int)((i / od.nx) % od.ny);
-            const int iz = (int)(i / ((long long)od.nx * od.ny));
+            // node indices in 32 bits (at most 2^29 nodes per orbital)
+            const int ii = (int)i, pxy = od.nx * od.ny;
+            const int iz = ii / pxy, rem = ii - iz * pxy;
+            const int iy = rem / od.nx, ix = rem - iy * od.nx;
             const double sv = src[od.off + i];
             const double rho = square ? sv * sv : sv;
             double R[NLM];

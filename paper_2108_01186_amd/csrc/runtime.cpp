@@ -279,6 +279,8 @@ fsic_status validate_grid(const fsic_grid &g, std::string &why) {
         if (!std::isfinite(g.origin[d])) { why = "grid origin must be finite"; return FSIC_EINVAL; }
     }
     if (!(g.h > 0.0) || !std::isfinite(g.h)) { why = "grid spacing h must be finite and > 0"; return FSIC_EINVAL; }
+    // one orbital's FP64 field must stay below 4 GiB (32-bit buffer ranges and node indices)
+    if ((long long)g.n[0] * g.n[1] * g.n[2] > (1LL << 29)) { why = "grid must have at most 2^29 nodes"; return FSIC_EINVAL; }
     return FSIC_OK;
 }
 
