@@ -109,6 +109,9 @@ __device__ __forceinline__ double vxc_pol(double rho, double floor) {
 
 // B[i][a] = sum_m Gam_i(m) psi_a(m); wave w owns Gam tiles t1 = w, w + 4 and
 // every psi tile t2; block b sums the node range [b chunk, (b+1) chunk).
+// TT: column tiles held per wave (2 for N <= 32, else 8), so small N keeps
+// few accumulators and many waves per SIMD.
+template <int TT>
 __global__ __launch_bounds__(256) void k_adj_contract(int N, long long M, long long chunk,
                                                       double dV, const double *PHI,
                                                       const double *V, const double *W,
@@ -117,20 +120,26 @@ __global__ __launch_bounds__(256) void k_adj_contract(int N, long long M, long l
     const int Nt = (N + 15) >> 4;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row = lane & 15, kk = lane >> 4;
-    dbl4 acc[2][8];
+    dbl4 acc[2][TT];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int t = 0; t < 8; ++t) acc[a][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < TT; ++t) acc[a][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // row tiles: wave w takes w and w + 4; with at most two tiles (N <= 32)
+    // every wave takes all of them over a quarter of the nodes instead, and
+    // the four partial tiles are summed in LDS at the end (no wave idles)
+    const bool split = Nt <= 2;
+    auto tile_of = [&](int a) { return split ? a : w + 4 * a; };
     const long long m0 = (long long)blockIdx.x * chunk;
     const long long m1 = min(M, m0 + chunk);
-    for (long long m = m0; m < m1; m += 4) {
+#pragma unroll 4
+    for (long long m = m0 + (split ? 4 * w : 0); m < m1; m += (split ? 16 : 4)) {
         const long long mm = m + kk;
         const bool ok = mm < m1;
         double g[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const int t1 = w + 4 * a;
+            const int t1 = tile_of(a);
             const int i = 16 * t1 + row;
             double gv = 0.0;
             if (t1 < Nt && i < N && ok) {
@@ -142,29 +151,50 @@ __global__ __launch_bounds__(256) void k_adj_contract(int N, long long M, long l
             }
             g[a] = gv;
         }
-        double f[8];
+        double f[TT];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        for (int t = 0; t < TT; ++t) {
             const int r = 16 * t + row;
             f[t] = (t < Nt && r < N && ok) ? psi[(long long)r * M + mm] : 0.0;
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            if (w + 4 * a < Nt) {
+            if (tile_of(a) < Nt) {
 #pragma unroll
-                for (int t = 0; t < 8; ++t)
+                for (int t = 0; t < TT; ++t)
                     if (t < Nt) acc[a][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[a], f[t], acc[a][t], 0, 0, 0);
             }
         }
     }
     const int NP = Nt * 16;
     double *out = partB + (size_t)blockIdx.x * NP * NP;
+    if (split) {
+        __shared__ double sacc[4][4][4][64];  // wave, tile (a, t), item, lane
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                if (a < Nt && t < Nt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) sacc[w][2 * a + t][j][lane] = acc[a][t][j];
+        __syncthreads();
+        if (w != 0) return;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                if (a < Nt && t < Nt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[a][t][j] = (sacc[0][2 * a + t][j][lane] + sacc[1][2 * a + t][j][lane]) +
+                                       (sacc[2][2 * a + t][j][lane] + sacc[3][2 * a + t][j][lane]);
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        const int t1 = w + 4 * a;
+        const int t1 = tile_of(a);
         if (t1 >= Nt) continue;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        for (int t = 0; t < TT; ++t) {
             if (t >= Nt) continue;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -294,7 +324,11 @@ hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *
     const int nblk = grid_blocks(N, M, cap);
     long long chunk = (M + nblk - 1) / nblk;
     chunk = (chunk + 3) & ~3LL;
-    hipLaunchKernelGGL(k_adj_contract, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
+    if (((N + 15) >> 4) <= 2)
+        hipLaunchKernelGGL(k_adj_contract<2>, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
+                       floor, partB);
+    else
+        hipLaunchKernelGGL(k_adj_contract<8>, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
                        floor, partB);
     hipLaunchKernelGGL(k_adj_contract_final, dim3(N * N), dim3(256), 0, s, N, nblk, partB, Bm);
     return hipGetLastError();

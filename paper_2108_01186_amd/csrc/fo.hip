@@ -177,19 +177,26 @@ hipError_t launch_interp(int K, int N, int nx, int ny, int nz, double h, const d
 
 // Block b accumulates the node range [b*chunk, (b+1)*chunk); wave w owns the
 // upper-triangle tile pairs p = w, w+4, ...; partG[b] holds the block's sums.
+// FT: row tiles held per lane (2 for N <= 32, else 8), so small N keeps few
+// registers and many waves per SIMD.
+template <int FT>
 __global__ __launch_bounds__(256) void k_gram(int N, long long M, long long chunk,
                                               const double *psi, double *partG) {
     const int Nt = (N + 15) >> 4;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row = lane & 15, kk = lane >> 4;
-    constexpr int kMaxPairPerWave = 9;  // Nt <= 8: 36 pairs over 4 waves
+    constexpr int kMaxPairPerWave = FT == 2 ? 3 : 9;  // Nt <= 8: 36 pairs over 4 waves
     dbl4 acc[kMaxPairPerWave];
     int pt1[kMaxPairPerWave], pt2[kMaxPairPerWave];
     int np = 0;
     // pairs (t1 <= t2) enumerated row by row; wave w takes indices w, w+4, ...
+    // With at most three pairs (N <= 32) every wave takes all of them over a
+    // quarter of the nodes instead, and the four partial tiles are summed
+    // in LDS at the end (no wave idles).
+    const bool split = Nt * (Nt + 1) / 2 <= 3;
     for (int t1 = 0, idx = 0; t1 < Nt; ++t1)
         for (int t2 = t1; t2 < Nt; ++t2, ++idx)
-            if (idx % 4 == w && np < kMaxPairPerWave) {
+            if ((split || idx % 4 == w) && np < kMaxPairPerWave) {
                 pt1[np] = t1;
                 pt2[np] = t2;
                 ++np;
@@ -198,11 +205,11 @@ __global__ __launch_bounds__(256) void k_gram(int N, long long M, long long chun
     for (int q = 0; q < kMaxPairPerWave; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
     const long long m0 = (long long)blockIdx.x * chunk;
     const long long m1 = min(M, m0 + chunk);
-    for (long long m = m0; m < m1; m += 4) {
-        double frag[8];
+    for (long long m = m0 + (split ? 4 * w : 0); m < m1; m += (split ? 16 : 4)) {
+        double frag[FT];
         const long long mm = m + kk;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        for (int t = 0; t < FT; ++t) {
             const int r = 16 * t + row;
             frag[t] = (t < Nt && r < N && mm < m1) ? psi[(long long)r * M + mm] : 0.0;
         }
@@ -211,7 +218,7 @@ __global__ __launch_bounds__(256) void k_gram(int N, long long M, long long chun
             if (q < np) {
                 double fa = 0.0, fb = 0.0;
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
+                for (int t = 0; t < FT; ++t) {
                     if (t == pt1[q]) fa = frag[t];
                     if (t == pt2[q]) fb = frag[t];
                 }
@@ -221,6 +228,23 @@ __global__ __launch_bounds__(256) void k_gram(int N, long long M, long long chun
     }
     const int NP = Nt * 16;
     double *out = partG + (size_t)blockIdx.x * NP * NP;
+    if (split) {
+        __shared__ double sacc[4][3][4][64];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (q < np)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sacc[w][q][j][lane] = acc[q][j];
+        __syncthreads();
+        if (w != 0) return;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (q < np)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[q][j] = (sacc[0][q][j][lane] + sacc[1][q][j][lane]) +
+                                (sacc[2][q][j][lane] + sacc[3][q][j][lane]);
+    }
 #pragma unroll
     for (int q = 0; q < kMaxPairPerWave; ++q) {
         if (q < np) {
@@ -263,7 +287,10 @@ hipError_t launch_gram(int N, long long M, double dV, const double *psi, double 
     const int nblk = grid_blocks(N, M, cap);
     long long chunk = (M + nblk - 1) / nblk;
     chunk = (chunk + 3) & ~3LL;
-    hipLaunchKernelGGL(k_gram, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, partG);
+    if (((N + 15) >> 4) <= 2)
+        hipLaunchKernelGGL(k_gram<2>, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, partG);
+    else
+        hipLaunchKernelGGL(k_gram<8>, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, partG);
     hipLaunchKernelGGL(k_gram_final, dim3(N * N), dim3(256), 0, s, N, nblk, dV, partG, G);
     return hipGetLastError();
 }
