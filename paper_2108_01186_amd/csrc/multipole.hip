@@ -11,10 +11,13 @@
 
 namespace fsic {
 
-// R[l*l + l + m] = r^l Y_lm(x, y, z) (real, orthonormal, no Condon-Shortley phase)
-template <int L>
-__device__ __forceinline__ void regular_harmonics(double x, double y, double z, const double *norm,
-                                                  double *R) {
+// Calls f(q, l, r^l Y_lm(x, y, z)) for q = l*l + l + m, every l <= L, in the
+// order the recurrence produces the values (real, orthonormal, no
+// Condon-Shortley phase).  Consuming each value at once keeps few of them
+// live, so accumulating kernels need no harmonic array in registers.
+template <int L, class F>
+__device__ __forceinline__ void visit_regular_harmonics(double x, double y, double z, const double *norm,
+                                                        F &&f) {
     const double r2 = x * x + y * y + z * z;
     double cm = 1.0, sm = 0.0;  // Re, Im of (x + i y)^m
     double dfact = 1.0;         // (2m - 1)!!
@@ -40,13 +43,20 @@ __device__ __forceinline__ void regular_harmonics(double x, double y, double z, 
             pm2 = pm1;
             pm1 = pl;
             if (m == 0) {
-                R[l * l + l] = norm[l * l + l] * pl;
+                f(l * l + l, l, norm[l * l + l] * pl);
             } else {
-                R[l * l + l + m] = norm[l * l + l + m] * cm * pl;
-                R[l * l + l - m] = norm[l * l + l - m] * sm * pl;
+                f(l * l + l + m, l, norm[l * l + l + m] * cm * pl);
+                f(l * l + l - m, l, norm[l * l + l - m] * sm * pl);
             }
         }
     }
+}
+
+// R[l*l + l + m] = r^l Y_lm(x, y, z)
+template <int L>
+__device__ __forceinline__ void regular_harmonics(double x, double y, double z, const double *norm,
+                                                  double *R) {
+    visit_regular_harmonics<L>(x, y, z, norm, [&](int q, int, double v) { R[q] = v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -76,12 +86,10 @@ __global__ __launch_bounds__(256) void k_moments(HarmTables ht, const OrbDesc *o
             const int iy = rem / od.nx, ix = rem - iy * od.nx;
             const double sv = src[od.off + i];
             const double rho = square ? sv * sv : sv;
-            double R[NLM];
-            regular_harmonics<L>(od.origin[0] + od.h * ix - od.centre[0],
-                                 od.origin[1] + od.h * iy - od.centre[1],
-                                 od.origin[2] + od.h * iz - od.centre[2], ht.norm, R);
-#pragma unroll
-            for (int q = 0; q < NLM; ++q) acc[q] += rho * R[q];
+            visit_regular_harmonics<L>(od.origin[0] + od.h * ix - od.centre[0],
+                                       od.origin[1] + od.h * iy - od.centre[1],
+                                       od.origin[2] + od.h * iz - od.centre[2], ht.norm,
+                                       [&](int q, int, double v) { acc[q] += rho * v; });
         }
     }
     const int w = threadIdx.x >> 6;
