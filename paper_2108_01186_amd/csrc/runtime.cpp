@@ -973,9 +973,18 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         const int pchunk = pcg_chunk(b.dst_fast);
         const CGIter<float> a0 = a;
         int nref = 0;
+        // x64 lives in two buffers: each restart reads it from xs[cur] and its
+        // FP64 residual pass writes x64 + x32 into xs[cur ^ 1], so no separate
+        // accumulation pass runs; an orbital's final x is in the buffer of the
+        // check that converged it (fin), and is moved to X at the end
+        HIPCHK(c, c->X64b.ensure((size_t)b.fields));
+        double *const xs[2] = {X, c->X64b.p};
+        int cur = 0;
+        std::vector<int> fin(norb, -1);
         while (k < max_iter && !all_done) {
             const int kstart = k;
             const int kend = std::min(k + pchunk, max_iter);
+            double *const Xc = xs[cur], *const Xn = xs[cur ^ 1];
             // one restart cycle on stream `s` (shadowing the context's)
             auto body = [&](hipStream_t s) -> fsic_status {
                 CGIter<float> a = a0;
@@ -1007,21 +1016,32 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                     }
                 }
                 HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p,
-                                               c->done.p, X, c->X32.p, c->B.p, nullptr, c->R32.p,
+                                               c->done.p, Xc, c->X32.p, c->B.p, Xn, c->R32.p,
                                                c->partRU.p, s));
-                HIPCHK(c, launch_mixed_accumulate(nit8, c->d_items8.p, c->d_orb.p, c->done.p, X, c->X32.p, s));
                 HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, kend, c->done.p,
                                           c->iters.p, c->rrfin.p, c->rs_iter.p, s));
                 HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
                 return FSIC_OK;
             };
-            const fsic_status cs = run_chunk(c, graphs, chunk_key(c, a0, di, X, 32, kstart, kend), body, s);
+            const fsic_status cs = run_chunk(c, graphs, chunk_key(c, a0, di, Xc, 32, kstart, kend), body, s);
             if (cs) return cs;
             k = kend;
             ++nref;
             HIPCHK(c, hipStreamSynchronize(s));
             all_done = true;
-            for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o] == 1;
+            for (int o = 0; o < norb; ++o) {
+                if (c->h_done[o] == 1 && fin[o] < 0) fin[o] = cur ^ 1;
+                all_done = all_done && c->h_done[o] == 1;
+            }
+            cur ^= 1;
+        }
+        for (int o = 0; o < norb; ++o) {
+            const int loc = fin[o] >= 0 ? fin[o] : cur;  // unconverged: the latest iterate
+            if (loc == 1) {
+                const OrbDesc &od = b.orb[o];
+                const size_t bytes = (size_t)od.nx * od.ny * od.nz * sizeof(double);
+                HIPCHK(c, hipMemcpyAsync(X + od.off, c->X64b.p + od.off, bytes, hipMemcpyDeviceToDevice, s));
+            }
         }
         rep.refinements += nref;
         HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
