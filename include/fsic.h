@@ -115,7 +115,7 @@ enum { FSIC_CG = 0, FSIC_PCG = 1, FSIC_AAR = 2 };
                                     (the boundary part of the map is the only difference) */
 
 typedef struct {
-    int32_t n[3];       /* nodes per axis, each >= 8 */
+    int32_t n[3];       /* nodes per axis, 8..4096, at most 2^29 nodes in all */
     double h;           /* spacing (Bohr), > 0 */
     double origin[3];   /* position of node (0, 0, 0) */
 } fsic_grid;
