@@ -306,6 +306,62 @@ __global__ __launch_bounds__(256) void k_lowdin_backward(int N, const double *Bm
 // launchers
 // ---------------------------------------------------------------------------
 
+// W_o += dV sum_lm zt_o,lm r^l Y_lm for every orbital o of a channel: the
+// harmonics of a node are built once and applied to all of the channel's
+// orbitals (their coefficients staged in LDS), instead of once per orbital.
+template <int L>
+__global__ __launch_bounds__(256) void k_adj_field_grp(HarmTables ht, const OrbDesc *orb,
+                                                       const GroupItem *items, const double *Zt,
+                                                       double *W) {
+    constexpr int NLM = (L + 1) * (L + 1);
+    extern __shared__ double sz[];  // count x NLM
+    const GroupItem it = items[blockIdx.x];
+    const OrbDesc od = orb[it.first];
+    for (int e = threadIdx.x; e < it.count * NLM; e += 256) sz[e] = Zt[(size_t)it.first * NLM + e];
+    __syncthreads();
+    const long long M = (long long)od.nx * od.ny * od.nz;
+    const double dV = od.h * od.h * od.h;
+    const long long base = (long long)it.tile * kAdjTile;
+    for (int e = 0; e < kAdjTile / 256; ++e) {
+        const long long i = base + e * 256 + threadIdx.x;
+        if (i >= M) continue;
+        // node indices in 32 bits (at most 2^29 nodes per orbital)
+        const int ii = (int)i, pxy = od.nx * od.ny;
+        const int iz = ii / pxy, rem = ii - iz * pxy;
+        const int iy = rem / od.nx, ix = rem - iy * od.nx;
+        double R[NLM];
+        solid_harmonics_adj<L>(od.origin[0] + od.h * ix - od.centre[0],
+                               od.origin[1] + od.h * iy - od.centre[1],
+                               od.origin[2] + od.h * iz - od.centre[2], ht.norm, R);
+        for (int o = 0; o < it.count; ++o) {
+            double f = 0.0;
+#pragma unroll
+            for (int q = 0; q < NLM; ++q) f += sz[o * NLM + q] * R[q];
+            W[od.off + (long long)o * M + i] += dV * f;
+        }
+    }
+}
+
+hipError_t launch_adj_field_groups(int lmax, const HarmTables &ht, const OrbDesc *orb,
+                                   const GroupItem *items, int nitems, int max_count,
+                                   const double *Zt, double *W, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const size_t lds = (size_t)max_count * (lmax + 1) * (lmax + 1) * sizeof(double);
+    switch (lmax) {
+#define CASE(L)                                                                                    \
+    case L:                                                                                        \
+        if (lds > 65536)                                                                           \
+            hipFuncSetAttribute((const void *)k_adj_field_grp<L>,                                  \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
+        hipLaunchKernelGGL(k_adj_field_grp<L>, dim3(nitems), dim3(256), lds, s, ht, orb, items, Zt, W); \
+        break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_field(int lmax, const HarmTables &ht, const OrbDesc *orb, const Item *items8,
                             int nitems8, const double *Zt, double *W, hipStream_t s) {
     if (nitems8 <= 0) return hipSuccess;

@@ -10,15 +10,16 @@
 // so M^{-1} r = (prod_d 2 / (n_d + 1)) S_x S_y S_z diag(1/lambda) S_z S_y S_x r
 // is an SPD preconditioner that leaves only the face corrections for CG.
 //
-// Each application is five batched passes, one per axis transform (x, y,
-// then z with the eigenvalue scaling between its forward and inverse
-// transforms, then y, x).  A pass multiplies n x 32 column panels of one
-// orbital by the n x n sine matrix on the FP32 matrix cores
-// (v_mfma_f32_16x16x4f32): the panel is staged in LDS (transposed for the x
-// axis so every global access is along x), the sine matrix comes from a
-// small L2-resident table.  Passes work in place on a float work array; the
-// first reads the CG residual (float or double) and the last writes the
-// preconditioned residual z and the partial sums of r.z.
+// An application is a sequence of batched passes over a float work array,
+// each multiplying panels of the field by n x n sine matrices on the matrix
+// cores:
+//   * k_dst_xy (in-plane axes up to 128 nodes): the x and y transforms of
+//     one z plane in one visit, forward (reads r) and inverse (writes z);
+//   * k_dst_fast<2, 1>: the z transform, the 1/lambda scaling and the
+//     inverse z transform, with the r.z partial sums;
+//   * otherwise five per-axis passes (k_dst_fast, or k_dst_pass on FP32
+//     matrix cores for axes above 128 nodes), the last writing z and r.z.
+// The fast kernels split each fp32 operand into bf16 hi + lo (see below).
 #include <algorithm>
 
 #include "kernels.h"

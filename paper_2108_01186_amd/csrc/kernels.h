@@ -267,6 +267,19 @@ hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *ps
 hipError_t launch_adj_field(int lmax, const HarmTables &ht, const OrbDesc *orb, const Item *items8,
                             int nitems8, const double *Zt, double *W, hipStream_t s);
 
+// Work item of the per-channel adjoint field: orbitals first .. first+count-1
+// share one grid; tile: kAdjTile nodes of it.
+struct GroupItem {
+    int first, count, tile;
+};
+constexpr int kAdjTile = 1024;
+
+// Same field as launch_adj_field, with the solid harmonics of a node built
+// once for all orbitals of its channel (Zt staged in LDS).
+hipError_t launch_adj_field_groups(int lmax, const HarmTables &ht, const OrbDesc *orb,
+                                   const GroupItem *items, int nitems, int max_count,
+                                   const double *Zt, double *W, hipStream_t s);
+
 // B[i][a] = sum_m Gam_i(m) psi_a(m) with Gam_i = 2 dV phi_i omega_i built on
 // the fly, omega_i = -((v_i + w_i) / 2 + vxc(phi_i^2)) (MFMA FP64)
 hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,

@@ -165,6 +165,8 @@ struct Batch {
     bool dst_vec = true;   // every nx and orbital offset is a multiple of 4
     int npxy = 0;          // largest in-plane axis, padded to 32
     bool dst_zocc2 = false;  // z pass in 64-column panels, two blocks per compute unit
+    std::vector<GroupItem> itemsG;  // (channel, kAdjTile-node tile) items of the adjoint field
+    int max_group = 0;              // most orbitals in one channel
 };
 
 void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<Item> &out) {
@@ -195,6 +197,7 @@ struct fsic_ctx {
     DBuf<float> Fprev, Fh;               // AAR: previous f, f-difference history
     DBuf<double> Xh, aar_gamma, partD;  // AAR: step history, weights, Gram partials
     DBuf<Item> d_dx, d_dy, d_dz, d_dxy;
+    DBuf<GroupItem> d_itemsG;
     DBuf<double> Gh;  // ghost values
     DBuf<double> part7, part8, partRU, partQ, partZ;
     DBuf<double> bb, rrfin, relres, Qlm, Zt, ptrue;
@@ -441,6 +444,12 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     };
     for (const Group &g : groups) {
         const long long M = (long long)g.n[0] * g.n[1] * g.n[2];
+        if (g.count > 0) {
+            const int first = (int)b.orb.size();
+            for (int t = 0; t < (int)((M + kAdjTile - 1) / kAdjTile); ++t)
+                b.itemsG.push_back(GroupItem{first, g.count, t});
+            b.max_group = std::max(b.max_group, g.count);
+        }
         for (int i = 0; i < g.count; ++i) {
             OrbDesc od{};
             od.nx = g.n[0]; od.ny = g.n[1]; od.nz = g.n[2];
@@ -541,6 +550,7 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     if ((st = upload(c, c->d_orb, b.orb))) return st;
     if ((st = upload(c, c->d_items7, b.items7))) return st;
     if ((st = upload(c, c->d_items8, b.items8))) return st;
+    if ((st = upload(c, c->d_itemsG, b.itemsG))) return st;
     if ((st = upload(c, c->d_gcount, b.gcount))) return st;
     if (use_pcg(c, b) || use_aar(c, b)) {
         if ((st = upload(c, c->d_dx, b.dx))) return st;
@@ -1278,7 +1288,7 @@ void fsic_destroy(fsic_ctx *c) {
     c->R32.release(); c->P32a.release(); c->P32b.release(); c->Q32.release(); c->X32.release();
     c->Z32.release(); c->T32.release(); c->dtab.release(); c->partRZ.release();
     c->Fprev.release(); c->Fh.release(); c->Xh.release(); c->aar_gamma.release(); c->partD.release();
-    c->d_dx.release(); c->d_dy.release(); c->d_dz.release(); c->d_dxy.release();
+    c->d_dx.release(); c->d_dy.release(); c->d_dz.release(); c->d_dxy.release(); c->d_itemsG.release();
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
     c->partQ.release(); c->partZ.release(); c->bb.release(); c->rrfin.release();
     c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release();
@@ -1833,8 +1843,8 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         const int zchunks = 64;
         HIPCHK(c, launch_adjoint_boundary(c->radius, o.lmax, hta, c->cf, norb, c->d_orb.p, c->d_gcount.p,
                                           c->W.p, c->partZ.p, zchunks, c->Zt.p, b.max_ghost, s));
-        HIPCHK(c, launch_adj_field(o.lmax, c->ht, c->d_orb.p, c->d_items8.p, (int)b.items8.size(),
-                                   c->Zt.p, c->W.p, s));
+        HIPCHK(c, launch_adj_field_groups(o.lmax, c->ht, c->d_orb.p, c->d_itemsG.p, (int)b.itemsG.size(),
+                                          b.max_group, c->Zt.p, c->W.p, s));
         Wt = c->W.p;
     }
     const double t1 = now_ms();
