@@ -88,13 +88,14 @@ def test_mol40_unitary_invariance(torch_cuda, F, mol40_dev, mol40_oracle):
     assert abs(out["e"][0] - mol40_oracle.e) < 1e-8
 
 
-def test_two_systems_one_batch(torch_cuda, F, oracle, mol40_dev, mol40_oracle):
-    """Two uneven systems solved in the same launches give the same energies
-    as alone."""
-    _say("forward batch of two uneven systems")
+@pytest.mark.parametrize("solver,precision", [("pcg", "mixed"), ("aar", "fp64"), ("cg", "fp64")])
+def test_two_systems_one_batch(torch_cuda, F, oracle, mol40_dev, mol40_oracle, solver, precision):
+    """Two uneven systems (40^3 with one spin, 24^3 with two) solved in the
+    same launches give the oracle's energies, with each solver."""
+    _say(f"forward batch of two uneven systems {solver} {precision}")
     small = synth.make_molecule("tiny", 24, 0.35, 3, 7, (3, 2), seed=77)
     small = _to_dev(torch_cuda, small)
-    both = F.sic_energy([mol40_dev, small])
+    both = F.sic_energy([mol40_dev, small], solver=solver, precision=precision, tol=1e-11)
     e_small_ref = sum(oracle.sic_spin(np.asarray(small.psi[s].cpu()), small.fod[s], small.n, small.h,
                                       small.origin).e for s in range(2))
     assert abs(both["e"][0] - mol40_oracle.e) < 1e-8
