@@ -274,6 +274,10 @@ struct GroupItem {
 };
 constexpr int kAdjTile = 1024;
 
+// Nodes of one channel per block of the Slater average (its partial sums
+// come one per such block).
+constexpr int kSicTile = 1024;
+
 // Same field as launch_adj_field, with the solid harmonics of a node built
 // once for all orbitals of its channel (Zt staged in LDS).
 hipError_t launch_adj_field_groups(int lmax, const HarmTables &ht, const OrbDesc *orb,

@@ -209,9 +209,10 @@ __global__ __launch_bounds__(256) void k_rhs(int P, Coeffs cf, const OrbDesc *or
     for (int e = 0; e < kPW / 256; ++e) {
         const long long i = base + e * 256 + threadIdx.x;
         if (i >= M) continue;
-        const int ix = (int)(i % nx);
-        const int iy = (int)((i / nx) % ny);
-        const int iz = (int)(i / ((long long)nx * ny));
+        // node indices in 32 bits (at most 2^29 nodes per orbital)
+        const int ii = (int)i, pxy = nx * ny;
+        const int iz = ii / pxy, rem = ii - iz * pxy;
+        const int iy = rem / nx, ix = rem - iy * nx;
         const double sv = src[od.off + i];
         double b = scale * (square ? sv * sv : sv);
         if (G) {

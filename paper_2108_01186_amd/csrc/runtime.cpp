@@ -1386,7 +1386,7 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     int nblk_total = 0;
     for (int ci = 0; ci < nchan; ++ci) {
         Chan &ch = chans[ci];
-        ch.nblk = (int)((ch.M + kPW - 1) / kPW);
+        ch.nblk = (int)((ch.M + kSicTile - 1) / kSicTile);
         ch.blk_base = nblk_total;
         nblk_total += ch.nblk;
         for (int t = 0; t < ch.nblk; ++t) blkchan.push_back(ci);

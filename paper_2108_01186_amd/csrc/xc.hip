@@ -73,17 +73,17 @@ __global__ __launch_bounds__(256) void k_sic_average(const ChanDesc *chans, cons
     const int c = blk_chan[blockIdx.x];
     const ChanDesc ch = chans[c];
     const int tile = blockIdx.x - ch.blk_base;
-    const long long base = (long long)tile * kPW;
-    double num[kPW / 256], den[kPW / 256];
+    const long long base = (long long)tile * kSicTile;
+    double num[kSicTile / 256], den[kSicTile / 256];
 #pragma unroll
-    for (int e = 0; e < kPW / 256; ++e) num[e] = den[e] = 0.0;
+    for (int e = 0; e < kSicTile / 256; ++e) num[e] = den[e] = 0.0;
     const int w = threadIdx.x >> 6;
     for (int i = 0; i < ch.N; ++i) {
         const double *ph = PHI + ch.off + (long long)i * ch.M;
         const double *vh = V + ch.off + (long long)i * ch.M;
         double u = 0.0, x = 0.0;
 #pragma unroll
-        for (int e = 0; e < kPW / 256; ++e) {
+        for (int e = 0; e < kSicTile / 256; ++e) {
             const long long m = base + e * 256 + threadIdx.x;
             if (m < ch.M) {
                 const double p = ph[m];
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_sic_average(const ChanDesc *chans, cons
     }
     if (ch.vsic) {
 #pragma unroll
-        for (int e = 0; e < kPW / 256; ++e) {
+        for (int e = 0; e < kSicTile / 256; ++e) {
             const long long m = base + e * 256 + threadIdx.x;
             if (m < ch.M) ch.vsic[m] = (den[e] > floor) ? ch.vscale * num[e] / den[e] : 0.0;
         }
@@ -119,30 +119,31 @@ __global__ __launch_bounds__(256) void k_sic_average(const ChanDesc *chans, cons
     }
 }
 
-__global__ __launch_bounds__(128) void k_sic_energy(const ChanDesc *chans, const double *partU,
+__global__ __launch_bounds__(256) void k_sic_energy(const ChanDesc *chans, const double *partU,
                                                     const double *partX, double *U, double *X,
                                                     double *Echan) {
-    __shared__ double se[kMaxOrb];
+    __shared__ double sred[4];
     const ChanDesc ch = chans[blockIdx.x];
     const double dV = ch.h * ch.h * ch.h;
-    const int i = threadIdx.x;
-    if (i < ch.N) {
+    double e = 0.0;
+    // per orbital: the block's threads sum the partials of the channel's
+    // blocks in a fixed order, then one fixed-order block reduction
+    for (int i = 0; i < ch.N; ++i) {
         double su = 0.0, sx = 0.0;
-        for (int t = 0; t < ch.nblk; ++t) {
+        for (int t = threadIdx.x; t < ch.nblk; t += 256) {
             su += partU[(size_t)(ch.blk_base + t) * kMaxOrb + i];
             sx += partX[(size_t)(ch.blk_base + t) * kMaxOrb + i];
         }
+        su = block_sum256(su, sred);
+        sx = block_sum256(sx, sred);
         const double ui = 0.5 * dV * su, xi = dV * sx;
-        U[ch.first_orb + i] = ui;
-        X[ch.first_orb + i] = xi;
-        se[i] = ui + xi;
+        if (threadIdx.x == 0) {
+            U[ch.first_orb + i] = ui;
+            X[ch.first_orb + i] = xi;
+        }
+        e -= ui + xi;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double e = 0.0;
-        for (int k = 0; k < ch.N; ++k) e -= se[k];
-        Echan[blockIdx.x] = e;
-    }
+    if (threadIdx.x == 0) Echan[blockIdx.x] = e;
 }
 
 hipError_t launch_sic_average(int nchan, const ChanDesc *chan, int nblk_total,
@@ -159,7 +160,7 @@ hipError_t launch_sic_energy(int nchan, const ChanDesc *chan, const double *part
                              const double *partX, double *U, double *X, double *Echan,
                              hipStream_t s) {
     if (nchan <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sic_energy, dim3(nchan), dim3(128), 0, s, chan, partU, partX, U, X, Echan);
+    hipLaunchKernelGGL(k_sic_energy, dim3(nchan), dim3(256), 0, s, chan, partU, partX, U, X, Echan);
     return hipGetLastError();
 }
 
