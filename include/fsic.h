@@ -169,8 +169,10 @@ typedef struct {
     double  sweep_ms, sweep_bytes;
     double  update_ms, update_bytes;
     /* FSIC_PCG with FSIC_PROFILE: iterations are sampled every other one, and
-     * each sampled preconditioner application (five transform passes) is
-     * timed as one unit with its algorithmic bytes and flops */
+     * each sampled preconditioner application (three transform passes with
+     * the in-plane pair fused, else five) is timed as one unit with its
+     * algorithmic bytes (each array of an active orbital read or written
+     * once per pass) and flops */
     int32_t precond_launches;
     double  precond_ms, precond_bytes, precond_flops;
     /* stencil shape of the CG sweeps: tiles of 32 x 8*stencil_cpt columns,
