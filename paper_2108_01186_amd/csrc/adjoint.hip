@@ -55,38 +55,6 @@ __device__ __forceinline__ void solid_harmonics_adj(double x, double y, double z
     }
 }
 
-// W_o += dV sum_lm zt_o,lm r^l Y_lm (the P^T part of A^T rho)
-template <int L>
-__global__ __launch_bounds__(256) void k_adj_field(HarmTables ht, const OrbDesc *orb,
-                                                   const Item *items, const double *Zt, double *W) {
-    constexpr int NLM = (L + 1) * (L + 1);
-    const Item it = items[blockIdx.x];
-    if (it.orb < 0) return;
-    const OrbDesc od = orb[it.orb];
-    const long long M = (long long)od.nx * od.ny * od.nz;
-    const double dV = od.h * od.h * od.h;
-    double z[NLM];
-#pragma unroll
-    for (int q = 0; q < NLM; ++q) z[q] = Zt[(size_t)it.orb * NLM + q];
-    const long long base = (long long)it.tile * kPW;
-    for (int e = 0; e < kPW / 256; ++e) {
-        const long long i = base + e * 256 + threadIdx.x;
-        if (i >= M) continue;
-        // node indices in 32 bits (at most 2^29 nodes per orbital)
-        const int ii = (int)i, pxy = od.nx * od.ny;
-        const int iz = ii / pxy, rem = ii - iz * pxy;
-        const int iy = rem / od.nx, ix = rem - iy * od.nx;
-        double R[NLM];
-        solid_harmonics_adj<L>(od.origin[0] + od.h * ix - od.centre[0],
-                               od.origin[1] + od.h * iy - od.centre[1],
-                               od.origin[2] + od.h * iz - od.centre[2], ht.norm, R);
-        double f = 0.0;
-#pragma unroll
-        for (int q = 0; q < NLM; ++q) f += z[q] * R[q];
-        W[od.off + i] += dV * f;
-    }
-}
-
 // fully polarised LSDA potential (same parameterisation as the forward pass)
 __device__ __forceinline__ double vxc_pol(double rho, double floor) {
     if (!(rho > floor)) return 0.0;
@@ -306,9 +274,9 @@ __global__ __launch_bounds__(256) void k_lowdin_backward(int N, const double *Bm
 // launchers
 // ---------------------------------------------------------------------------
 
-// W_o += dV sum_lm zt_o,lm r^l Y_lm for every orbital o of a channel: the
-// harmonics of a node are built once and applied to all of the channel's
-// orbitals (their coefficients staged in LDS), instead of once per orbital.
+// W_o += dV sum_lm zt_o,lm r^l Y_lm (the P^T part of A^T rho) for every
+// orbital o of a channel: the harmonics of a node are built once and applied
+// to all of the channel's orbitals (their coefficients staged in LDS).
 template <int L>
 __global__ __launch_bounds__(256) void k_adj_field_grp(HarmTables ht, const OrbDesc *orb,
                                                        const GroupItem *items, const double *Zt,
@@ -355,18 +323,6 @@ hipError_t launch_adj_field_groups(int lmax, const HarmTables &ht, const OrbDesc
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
         hipLaunchKernelGGL(k_adj_field_grp<L>, dim3(nitems), dim3(256), lds, s, ht, orb, items, Zt, W); \
         break;
-        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-#undef CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_field(int lmax, const HarmTables &ht, const OrbDesc *orb, const Item *items8,
-                            int nitems8, const double *Zt, double *W, hipStream_t s) {
-    if (nitems8 <= 0) return hipSuccess;
-    switch (lmax) {
-#define CASE(L) case L: hipLaunchKernelGGL(k_adj_field<L>, dim3(nitems8), dim3(256), 0, s, ht, orb, items8, Zt, W); break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: return hipErrorInvalidValue;

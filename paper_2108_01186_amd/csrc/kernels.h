@@ -263,10 +263,6 @@ hipError_t launch_orb_gemm32(int N, long long M, const double *A, const double *
 hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *psi, double *out,
                            hipStream_t s);
 
-// W_o += dV sum_lm zt_o,lm r^l Y_lm for every orbital of the batch
-hipError_t launch_adj_field(int lmax, const HarmTables &ht, const OrbDesc *orb, const Item *items8,
-                            int nitems8, const double *Zt, double *W, hipStream_t s);
-
 // Work item of the per-channel adjoint field: orbitals first .. first+count-1
 // share one grid; tile: kAdjTile nodes of it.
 struct GroupItem {
@@ -278,8 +274,9 @@ constexpr int kAdjTile = 1024;
 // come one per such block).
 constexpr int kSicTile = 1024;
 
-// Same field as launch_adj_field, with the solid harmonics of a node built
-// once for all orbitals of its channel (Zt staged in LDS).
+// W_o += P^T zt_o (the multipole part of A^T rho_o) for every orbital: the
+// solid harmonics of a node are built once for all orbitals of its channel
+// (Zt staged in LDS).  max_count: most orbitals in one channel.
 hipError_t launch_adj_field_groups(int lmax, const HarmTables &ht, const OrbDesc *orb,
                                    const GroupItem *items, int nitems, int max_count,
                                    const double *Zt, double *W, hipStream_t s);
