@@ -257,11 +257,11 @@ hipError_t launch_lowdin(int N, const double *T, const double *G, double *S, dou
                          int *status, double *info, hipStream_t s);
 
 // out[i][m] = sum_a A[i][a] psi[a][m]  (MFMA FP64), N <= 128
-// same with fp32 operands and fp32 accumulation on the matrix cores
-hipError_t launch_orb_gemm32(int N, long long M, const double *A, const double *psi, double *out,
-                             hipStream_t s);
 hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *psi, double *out,
                            hipStream_t s);
+// the same with fp32 operands and fp32 accumulation on the matrix cores
+hipError_t launch_orb_gemm32(int N, long long M, const double *A, const double *psi, double *out,
+                             hipStream_t s);
 
 // Work item of the per-channel adjoint field: orbitals first .. first+count-1
 // share one grid; tile: kAdjTile nodes of it.
