@@ -80,3 +80,38 @@ def test_invalid_arguments_rejected_on_host():
     o = fsic.default_opts(lmax=9)
     assert fsic.fsic_create(ctypes.byref(h), ctypes.byref(o), None) == fsic.FSIC_EINVAL
     assert fsic.fsic_create(None, ctypes.byref(fsic.default_opts()), None) == fsic.FSIC_EINVAL
+
+
+def test_flag_and_solver_constants_match_header():
+    """Every FSIC_* flag and solver value of the header has the same value in
+    the binding (the ABI passes them as plain integers)."""
+    from paper_2108_01186_amd import fsic as F
+    text = open(HEADER).read()
+    flags = dict(re.findall(r"#define\s+(FSIC_[A-Z0-9_]+)\s+(\d+)u", text))
+    assert {"FSIC_WANT_VSIC", "FSIC_KEEP_TAPE", "FSIC_PAPER_GRADIENT", "FSIC_EQ9_FORCES",
+            "FSIC_GRAPHS", "FSIC_FP32_ORBITALS"} <= set(flags)
+    for name, val in flags.items():
+        assert getattr(F, name) == int(val), name
+    enum = re.search(r"enum\s*\{\s*(FSIC_CG[^}]*)\}", text).group(1)
+    for name, val in re.findall(r"(FSIC_[A-Z]+)\s*=\s*(\d+)", enum):
+        assert getattr(F, name) == int(val), name
+
+
+def test_stored_traffic_follows_kernel_sources(tmp_path, monkeypatch):
+    """bench.py reads the committed HBM-traffic summary only while the kernel
+    sources hash to the value stored with it."""
+    import bench
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    src = tmp_path / "paper_2108_01186_amd" / "csrc"
+    src.mkdir(parents=True)
+    for f in ("stencil.hip", "dst.hip", "common.h"):
+        (src / f).write_text("// " + f + "\n")
+    good = bench.kernel_source_hash()
+    path = prof / "precond_pcg_f32_toy_hbm_traffic.txt"
+    path.write_text(f"traffic_bytes_per_launch: 123\nkernel_source_sha256: {good}\n")
+    assert bench.stored_traffic("toy", "precond", "pcg") == 123.0
+    (src / "dst.hip").write_text("// changed\n")
+    assert bench.stored_traffic("toy", "precond", "pcg") is None
+    assert bench.stored_traffic("other", "precond", "pcg") is None
