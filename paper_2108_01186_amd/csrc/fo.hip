@@ -314,10 +314,10 @@ __device__ void small_gemm(int N, const double *A, int ta, const double *B, int 
     }
 }
 
-__global__ __launch_bounds__(256) void k_lowdin(int N, int Ne, const double *T, const double *G,
-                                                double *S, double *lam, double *U, double *Z,
-                                                double *Qm, double *work, int lds_mode,
-                                                double eig_floor, int *status, double *info) {
+__device__ __forceinline__ void lowdin_one(int N, int Ne, const double *T, const double *G,
+                                           double *S, double *lam, double *U, double *Z,
+                                           double *Qm, double *work, int lds_mode,
+                                           double eig_floor, int *status, double *info) {
     extern __shared__ double dsm[];
     __shared__ double rc[kMaxOrb / 2], rs_[kMaxOrb / 2];
     __shared__ int rp[kMaxOrb / 2], rq[kMaxOrb / 2];
@@ -435,9 +435,28 @@ __global__ __launch_bounds__(256) void k_lowdin(int N, int Ne, const double *T, 
     small_gemm(N, Z, 0, T, 0, Qm, 1.0);
 }
 
-hipError_t launch_lowdin(int N, const double *T, const double *G, double *S, double *lam,
-                         double *U, double *Z, double *Qm, double *work, double eig_floor,
-                         int *status, double *info, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_lowdin(int N, int Ne, const double *T, const double *G,
+                                                double *S, double *lam, double *U, double *Z,
+                                                double *Qm, double *work, int lds_mode,
+                                                double eig_floor, int *status, double *info) {
+    lowdin_one(N, Ne, T, G, S, lam, U, Z, Qm, work, lds_mode, eig_floor, status, info);
+}
+
+// one workgroup per channel: channel b's arrays sit at small + so[b] + the
+// given offsets, its scratch at work + b * wstride
+__global__ __launch_bounds__(256) void k_lowdin_batch(LowdinBatch lb, double *small, LowdinOffsets off,
+                                                      double *work, long long wstride, int lds_mode,
+                                                      double eig_floor, int *status) {
+    const int b = blockIdx.x;
+    const int N = lb.N[b], Ne = N + (N & 1);
+    double *sm = small + lb.so[b];
+    lowdin_one(N, Ne, sm + off.T, sm + off.G, sm + off.S, sm + off.lam, sm + off.U, sm + off.Z,
+               sm + off.Q, work + (size_t)b * wstride, lds_mode, eig_floor, status, sm + off.info);
+}
+
+// LDS mode of the Loewdin kernels for channels of up to N orbitals: 2 keeps
+// A and V in LDS, 1 only A, 0 neither (then both live in the scratch)
+static int lowdin_lds(int N, size_t &dyn) {
     const int Ne = N + (N & 1);
     int dev = 0;
     hipGetDevice(&dev);
@@ -445,13 +464,36 @@ hipError_t launch_lowdin(int N, const double *T, const double *G, double *S, dou
     hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     const size_t static_bytes = 4 * 64 * 8 + 64;  // rotation tables, reductions
     const size_t need1 = (size_t)Ne * Ne * sizeof(double);
-    int mode = 0;
+    dyn = 0;
+    if (2 * need1 + static_bytes <= (size_t)maxsh) { dyn = 2 * need1; return 2; }
+    if (need1 + static_bytes <= (size_t)maxsh) { dyn = need1; return 1; }
+    return 0;
+}
+
+hipError_t launch_lowdin(int N, const double *T, const double *G, double *S, double *lam,
+                         double *U, double *Z, double *Qm, double *work, double eig_floor,
+                         int *status, double *info, hipStream_t s) {
+    const int Ne = N + (N & 1);
     size_t dyn = 0;
-    if (2 * need1 + static_bytes <= (size_t)maxsh) { mode = 2; dyn = 2 * need1; }
-    else if (need1 + static_bytes <= (size_t)maxsh) { mode = 1; dyn = need1; }
+    const int mode = lowdin_lds(N, dyn);
     if (dyn > 65536) hipFuncSetAttribute((const void *)k_lowdin, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     hipLaunchKernelGGL(k_lowdin, dim3(1), dim3(256), dyn, s, N, Ne, T, G, S, lam, U, Z, Qm, work,
                        mode, eig_floor, status, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowdin_batch(const LowdinBatch &lb, double *small, const LowdinOffsets &off,
+                               double *work, long long wstride, double eig_floor, int *status,
+                               hipStream_t s) {
+    if (lb.n <= 0 || lb.n > kLowdinBatch) return hipErrorInvalidValue;
+    int nmax = 1;
+    for (int b = 0; b < lb.n; ++b) nmax = std::max(nmax, lb.N[b]);
+    size_t dyn = 0;
+    const int mode = lowdin_lds(nmax, dyn);
+    if (dyn > 65536)
+        hipFuncSetAttribute((const void *)k_lowdin_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    hipLaunchKernelGGL(k_lowdin_batch, dim3(lb.n), dim3(256), dyn, s, lb, small, off, work, wstride, mode,
+                       eig_floor, status);
     return hipGetLastError();
 }
 

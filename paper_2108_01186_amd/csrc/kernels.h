@@ -256,6 +256,22 @@ hipError_t launch_lowdin(int N, const double *T, const double *G, double *S, dou
                          double *U, double *Z, double *Qm, double *work, double eig_floor,
                          int *status, double *info, hipStream_t s);
 
+// Loewdin step of up to kLowdinBatch channels in one launch (one workgroup
+// each): channel b has N[b] orbitals and its small arrays at small + so[b]
+// plus the offsets below; scratch of wstride >= 3 N^2 doubles per channel.
+constexpr int kLowdinBatch = 64;
+struct LowdinBatch {
+    int n;
+    int N[kLowdinBatch];
+    long long so[kLowdinBatch];
+};
+struct LowdinOffsets {
+    long long T, G, S, lam, U, Z, Q, info;
+};
+hipError_t launch_lowdin_batch(const LowdinBatch &lb, double *small, const LowdinOffsets &off,
+                               double *work, long long wstride, double eig_floor, int *status,
+                               hipStream_t s);
+
 // out[i][m] = sum_a A[i][a] psi[a][m]  (MFMA FP64), N <= 128
 hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *psi, double *out,
                            hipStream_t s);

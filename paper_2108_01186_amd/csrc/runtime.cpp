@@ -1404,7 +1404,9 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     fsic_status pst = prepare_batch(c, b, o.precision);
     if (pst) return pst;
     HIPCHK(c, c->small.ensure((size_t)nchan * kSmallStride));
-    HIPCHK(c, c->work.ensure(4 * (size_t)kMaxOrb * kMaxOrb));
+    const long long lw = 3LL * kMaxOrb * kMaxOrb;  // Loewdin scratch per channel of a batched launch
+    HIPCHK(c, c->work.ensure(std::max<size_t>(4 * (size_t)kMaxOrb * kMaxOrb,
+                                              (size_t)std::min(nchan, kLowdinBatch) * (size_t)lw)));
     const int gram_blk = 256;
     c->sweep_launches = c->update_launches = c->precond_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
@@ -1435,11 +1437,20 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
                                 sm + small_off(sRHOA), sm + small_off(sT), c->status.p,
                                 (o.flags & FSIC_PAPER_GRADIENT) != 0, s));
         HIPCHK(c, launch_gram(ch.N, ch.M, dV, ch.psi, c->partG.p, c->partG.cap, sm + small_off(sG), s));
-        HIPCHK(c, launch_lowdin(ch.N, sm + small_off(sT), sm + small_off(sG), sm + small_off(sS),
-                                sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
-                                sm + small_off(sQ), c->work.p, o.s_eig_floor, c->status.p,
-                                sm + small_off(sINFO), s));
         cell_base += ch.N;
+    }
+    // Loewdin steps of all channels, kLowdinBatch per launch (one workgroup each)
+    const LowdinOffsets loff{(long long)small_off(sT), (long long)small_off(sG), (long long)small_off(sS),
+                             (long long)small_off(sLAM), (long long)small_off(sEV), (long long)small_off(sZ),
+                             (long long)small_off(sQ), (long long)small_off(sINFO)};
+    for (int c0 = 0; c0 < nchan; c0 += kLowdinBatch) {
+        LowdinBatch lb{};
+        lb.n = std::min(kLowdinBatch, nchan - c0);
+        for (int q = 0; q < lb.n; ++q) {
+            lb.N[q] = chans[c0 + q].N;
+            lb.so[q] = (long long)chans[c0 + q].so;
+        }
+        HIPCHK(c, launch_lowdin_batch(lb, c->small.p, loff, c->work.p, lw, o.s_eig_floor, c->status.p, s));
     }
     // device-detected problems stop the pass before the solves
     int hstatus = 0;
