@@ -82,7 +82,8 @@ template <typename T>
 hipError_t launch_pcg_update(const CGIter<T> &a, int k, int x_first, hipStream_t s);
 
 // FP64 residual of x64 (+ x32): res = b + L (x64 + x32); writes x64new =
-// x64 + x32, r32 = (float) res (if r32 != null), res.res partials.
+// x64 + x32, r32 = (float) res (if r32 != null), res.res partials.  With
+// x32, a null x64 stands for x64 = 0 (the first restart of a mixed solve).
 hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7, int nitems7,
                                 const OrbDesc *orb, const int *done, const double *X64,
                                 const float *X32, const double *B, double *X64new, float *R32,

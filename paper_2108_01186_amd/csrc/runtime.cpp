@@ -829,7 +829,9 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     // b, r0 = b, x64 = 0 (mixed), ||b||^2 partials in part8 slot 0
     HIPCHK(c, launch_rhs(c->radius, c->cf, c->d_items8.p, nit8, c->d_orb.p, src, square, scale,
                          with_bc ? c->Gh.p : nullptr, c->B.p, mixed ? nullptr : c->R.p,
-                         mixed ? c->R32.p : nullptr, mixed ? X : nullptr, c->part8.p, s));
+                         mixed ? c->R32.p : nullptr,
+                         // the mixed preconditioned solve starts x64 at 0 without storing it
+                         (mixed && !use_pcg(c, b)) ? X : nullptr, c->part8.p, s));
     HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->part8.p, 0, c->bb.p, s));
     HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->iters.p, 0, norb * sizeof(int), s));
@@ -1026,8 +1028,8 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                     }
                 }
                 HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p,
-                                               c->done.p, Xc, c->X32.p, c->B.p, Xn, c->R32.p,
-                                               c->partRU.p, s));
+                                               c->done.p, kstart == 0 ? nullptr : Xc, c->X32.p, c->B.p,
+                                               Xn, c->R32.p, c->partRU.p, s));
                 HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, kend, c->done.p,
                                           c->iters.p, c->rrfin.p, c->rs_iter.p, s));
                 HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -449,7 +449,7 @@ struct PolPCG {  // p_k = z_k + beta p_{k-1}; q = K p_k = -L p_k; p.q partials
 };
 
 template <bool HAS32>
-struct PolRes {  // res = b + L x, x = x64 (+ x32)
+struct PolRes {  // res = b + L x, x = x64 (+ x32); X64 null (with x32): x64 = 0
     const Item *items;
     const OrbDesc *orb;
     const int *done;
@@ -467,14 +467,14 @@ struct PolRes {  // res = b + L x, x = x64 (+ x32)
     __device__ bool setup(int o, const OrbDesc &, double *) { return done == nullptr || done[o] != 1; }
     __device__ void init(const OrbDesc &od) {
         const long long M = (long long)od.nx * od.ny * od.nz;
-        rx = make_rsrc(X64 + od.off, (unsigned)(M * 8));
+        if (X64) rx = make_rsrc(X64 + od.off, (unsigned)(M * 8));
         rb = make_rsrc(B + od.off, (unsigned)(M * 8));
         if constexpr (HAS32) rx32 = make_rsrc(X32 + od.off, (unsigned)(M * 4));
         if (X64new) rxn = make_rsrc(X64new + od.off, (unsigned)(M * 8));
         if (R32) rr32 = make_rsrc(R32 + od.off, (unsigned)(M * 4));
     }
     __device__ Raw raw(unsigned i, int zo) const {
-        if constexpr (HAS32) return Raw{bld<double>(rx, i, zo), bld<float>(rx32, i, zo)};
+        if constexpr (HAS32) return Raw{X64 ? bld<double>(rx, i, zo) : 0.0, bld<float>(rx32, i, zo)};
         return Raw{bld<double>(rx, i, zo), 0.0f};
     }
     __device__ Ext ext(unsigned i, int zo) const { return bld<double>(rb, i, zo); }
