@@ -27,7 +27,7 @@ __device__ __forceinline__ int gram_slot(int i, int j, int nh) {
 //   hist: f_k - f_{k-1} goes into slot (k-1) % m (needs k >= 1);
 //   fprev := f_k.
 __global__ __launch_bounds__(256) void k_aar_dots(AarBufs a, int k, int nh, int hist, int dots) {
-    __shared__ double sred[4];
+    __shared__ double swave[4][kAarD];
     const Item it = a.items8[blockIdx.x];
     if (it.orb < 0) return;
     if (a.done[it.orb] == 1) return;
@@ -62,9 +62,19 @@ __global__ __launch_bounds__(256) void k_aar_dots(AarBufs a, int k, int nh, int 
         }
     }
     if (!dots) return;
+    // every accumulator index is a compile-time constant (a runtime index
+    // would put the array in scratch memory): wave sums into LDS, one
+    // barrier, then thread q adds the four wave sums of entry q in fixed order
+    const int w = threadIdx.x >> 6;
+#pragma unroll
     for (int q = 0; q < kAarD; ++q) {
-        const double t = block_sum256(acc[q], sred);
-        if (threadIdx.x == 0) a.partD[(size_t)(od.base8 + it.tile) * kAarD + q] = t;
+        const double t = wave_sum(acc[q]);
+        if ((threadIdx.x & 63) == 0) swave[w][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kAarD) {
+        const int q = threadIdx.x;
+        a.partD[(size_t)(od.base8 + it.tile) * kAarD + q] = (swave[0][q] + swave[1][q]) + (swave[2][q] + swave[3][q]);
     }
 }
 
