@@ -1768,6 +1768,30 @@ fsic_status fsic_op_interp(const fsic_grid *grid, int32_t N, int32_t K, const do
     return (e || e2) ? FSIC_EHIP : FSIC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Interpolation cells of N FODs on a grid (host validation shared by the
+// Fermi-Loewdin entry points): FSIC_EINVAL for a non-finite coordinate,
+// FSIC_EBOUNDARY when a 4-node stencil leaves the grid.
+fsic_status fod_cells(const fsic_grid &g, int N, const double *fod, FodCell *cells) {
+    for (int i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double a = fod[3 * i + d];
+            if (!std::isfinite(a)) return FSIC_EINVAL;
+            const double sc = (a - g.origin[d]) / g.h;
+            const double fl = std::floor(sc);
+            if (fl < 1.0 || fl > (double)(g.n[d] - 3)) return FSIC_EBOUNDARY;
+            cells[i].i0[d] = (int)fl;
+            cells[i].pad = 0;
+            cells[i].t[d] = sc - fl;
+        }
+    return FSIC_OK;
+}
+}  // namespace
+
+extern "C" {
+
 fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, const double *fod,
                         double rho_floor, double *T, double *G, double *S, double *Z, double *phi,
                         void *hip_stream) {
@@ -1776,16 +1800,10 @@ fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, con
     if (validate_grid(*grid, why)) return FSIC_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
     std::vector<FodCell> cells(N);
-    for (int i = 0; i < N; ++i)
-        for (int d = 0; d < 3; ++d) {
-            const double a = fod[3 * i + d];
-            if (!std::isfinite(a)) return FSIC_EINVAL;
-            const double sc = (a - grid->origin[d]) / grid->h;
-            const double fl = std::floor(sc);
-            if (fl < 1.0 || fl > (double)(grid->n[d] - 3)) return FSIC_EBOUNDARY;
-            cells[i].i0[d] = (int)fl;
-            cells[i].t[d] = sc - fl;
-        }
+    {
+        const fsic_status cs = fod_cells(*grid, N, fod, cells.data());
+        if (cs) return cs;
+    }
     const long long M = (long long)grid->n[0] * grid->n[1] * grid->n[2];
     const double dV = grid->h * grid->h * grid->h;
     DBuf<double> sm, work, partG;

@@ -1,0 +1,104 @@
+// FP64 residual b + L x of a batch (the defect-correction check of the
+// mixed-precision solves and the final residual report), and the small
+// per-orbital kernels around it.
+#include "zmarch.h"
+
+namespace fsic {
+
+__global__ __launch_bounds__(256) void k_reduce_partials(int norb, const OrbDesc *orb,
+                                                         const double *part, int stencil,
+                                                         double *out) {
+    __shared__ double sred[4];
+    const int o = blockIdx.x;
+    if (o >= norb) return;
+    const OrbDesc od = orb[o];
+    const double s = stencil ? sum_partials(part + od.base7, od.nt7, sred)
+                             : sum_partials(part + od.base8, od.nt8, sred);
+    if (threadIdx.x == 0) out[o] = s;
+}
+
+
+// x64 += x32 after a reliable update (mixed precision)
+__global__ __launch_bounds__(256) void k_mixed_accumulate(const Item *items8, const OrbDesc *orb,
+                                                          const int *done, double *X64,
+                                                          const float *X32) {
+    const Item it = items8[blockIdx.x];
+    if (it.orb < 0 || done[it.orb] == 1) return;
+    const OrbDesc od = orb[it.orb];
+    const long long M = (long long)od.nx * od.ny * od.nz;
+    const long long base = (long long)it.tile * kPW;
+#pragma unroll
+    for (int e = 0; e < kPW / 256; ++e) {
+        const long long i = base + e * 256 + threadIdx.x;
+        if (i < M) X64[od.off + i] += (double)X32[od.off + i];
+    }
+}
+
+// convergence on the FP64 residual of the last reliable update
+__global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const double *partRU,
+                                                  const double *bb, double tol2, int k, int *done,
+                                                  int *iters, double *rrfin, int *rs_iter) {
+    __shared__ double sred[4];
+    const int o = blockIdx.x;
+    if (done[o] == 1) return;
+    const OrbDesc od = orb[o];
+    const double rr = sum_partials(partRU + od.base7, od.nt7, sred);
+    if (threadIdx.x == 0) {
+        if (rr <= tol2 * bb[o]) {
+            done[o] = 1;
+            iters[o] = k;
+            rrfin[o] = rr;
+        } else if (done[o] == 2) {
+            // the FP32 recursion met tol but the FP64 residual did not:
+            // resume with a restart from the FP64 residual
+            done[o] = 0;
+            rs_iter[o] = k;
+        }
+    }
+}
+
+hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7, int nitems7,
+                                const OrbDesc *orb, const int *done, const double *X64,
+                                const float *X32, const double *B, double *X64new, float *R32,
+                                double *partRU, hipStream_t s) {
+    if (nitems7 <= 0) return hipSuccess;
+    if (X32) {
+        PolRes<true> pol{items7, orb, done, X64, X32, B, X64new, R32, partRU, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolRes<true>>), dim3(nitems7), dim3(256), 0, s, pol, c)
+        FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
+    } else {
+        PolRes<false> pol{items7, orb, done, X64, X32, B, X64new, R32, partRU, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolRes<false>>), dim3(nitems7), dim3(256), 0, s, pol, c)
+        FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *part,
+                                  int stencil_layout, double *out, hipStream_t s) {
+    if (norb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(norb), dim3(256), 0, s, norb, orb, part,
+                       stencil_layout, out);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDesc *orb,
+                                   const int *done, double *X64, const float *X32, hipStream_t s) {
+    if (nitems8 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mixed_accumulate, dim3(nitems8), dim3(256), 0, s, items8, orb, done, X64, X32);
+    return hipGetLastError();
+}
+
+hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
+                           double tol2, int k, int *done, int *iters, double *rrfin, int *rs_iter,
+                           hipStream_t s) {
+    if (norb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ru_check, dim3(norb), dim3(256), 0, s, orb, partRU, bb, tol2, k, done,
+                       iters, rrfin, rs_iter);
+    return hipGetLastError();
+}
+
+}  // namespace fsic

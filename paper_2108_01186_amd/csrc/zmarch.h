@@ -1,4 +1,4 @@
-// Star-stencil Laplacian and conjugate-gradient sweeps for the per-orbital
+// Star-stencil Laplacian driver and its policies for the per-orbital
 // Poisson problems of the SIC path (Sec. II.A: high-order centred finite
 // differences on a uniform grid; the Laplacian is the Kronecker sum of 1-D
 // second differences applied matrix-free).
@@ -16,6 +16,8 @@
 // the next search direction.  Dot products accumulate in FP64 into per-block
 // partial sums that later blocks add up in a fixed order, so results are
 // bitwise reproducible.
+#pragma once
+
 #include <type_traits>
 
 #include "kernels.h"
@@ -499,207 +501,6 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { typedef float4 V; static constexpr int n = 4; };
 template <> struct Vec16<double> { typedef double2 V; static constexpr int n = 2; };
 
-// x += alpha p; r -= alpha q; p = r + beta p (one node)
-template <typename T>
-__device__ __forceinline__ double upd_elem(T &x, T &r, T &p, T qv, T al, T be, int x_first) {
-    x = x_first ? al * p : x + al * p;
-    r = r - al * qv;
-    p = r + be * p;
-    return (double)r * (double)r;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(CGIter<T> a, int k, int cur_ru, int x_first) {
-    using V = typename Vec16<T>::V;
-    constexpr int VN = Vec16<T>::n;
-    __shared__ double sred[4];
-    const Item it = a.items8[blockIdx.x];
-    if (it.orb < 0) return;
-    if (a.done[it.orb]) return;
-    const OrbDesc od = a.orb[it.orb];
-    const bool restart = a.rs_iter && a.rs_iter[it.orb] == k;
-    const double rr = rr_of(a, od, k, cur_ru || restart, sred);
-    const double pq = sum_partials(a.part7 + od.base7, od.nt7, sred);
-    const double rq = sum_partials(a.part7 + (size_t)a.tot7 + od.base7, od.nt7, sred);
-    const double qq = sum_partials(a.part7 + 2 * (size_t)a.tot7 + od.base7, od.nt7, sred);
-    const double alpha = rr / pq;
-    // |r_{k+1}|^2 = |r_k|^2 - 2 alpha r_k.q_k + alpha^2 |q_k|^2, so the next
-    // direction is formed here; the direct r.r of this pass (below) decides
-    // alpha and convergence of the next iteration
-    const double rn = rr - 2.0 * alpha * rq + alpha * alpha * qq;
-    const double beta = rn > 0.0 ? rn / rr : 0.0;
-    const T al = (T)alpha, be = (T)beta;
-    const T *Pin = ((k == 0) || restart) ? a.R : a.P;  // p_k = r_k at a (re)start
-    const long long M = (long long)od.nx * od.ny * od.nz;
-    const long long base = (long long)it.tile * kPW;
-    double acc = 0.0;
-    if (((od.off | M) % VN) == 0) {
-        // 16-byte vector path: each thread owns VN consecutive nodes per pass
-#pragma unroll
-        for (int e = 0; e < kPW / (256 * VN); ++e) {
-            const long long i = base + (long long)(e * 256 + threadIdx.x) * VN;
-            if (i < M) {
-                const long long g = od.off + i;
-                V pv = *reinterpret_cast<const V *>(Pin + g);
-                V qv = *reinterpret_cast<const V *>(a.Q + g);
-                V rv = *reinterpret_cast<const V *>(a.R + g);
-                V xv = x_first ? V{} : *reinterpret_cast<const V *>(a.X + g);
-                T *px = reinterpret_cast<T *>(&xv), *pr = reinterpret_cast<T *>(&rv);
-                T *pp = reinterpret_cast<T *>(&pv);
-                const T *pqv = reinterpret_cast<const T *>(&qv);
-#pragma unroll
-                for (int j = 0; j < VN; ++j)
-                    acc += upd_elem(px[j], pr[j], pp[j], pqv[j], al, be, x_first);
-                *reinterpret_cast<V *>(a.X + g) = xv;
-                *reinterpret_cast<V *>(a.R + g) = rv;
-                *reinterpret_cast<V *>(a.P + g) = pv;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < kPW / 256; ++e) {
-            const long long i = base + e * 256 + threadIdx.x;
-            if (i < M) {
-                const long long g = od.off + i;
-                T xv = x_first ? T(0) : a.X[g];
-                T rv = a.R[g];
-                T pv = Pin[g];
-                acc += upd_elem(xv, rv, pv, a.Q[g], al, be, x_first);
-                a.X[g] = xv;
-                a.R[g] = rv;
-                a.P[g] = pv;
-            }
-        }
-    }
-    const double s = block_sum256(acc, sred);
-    if (threadIdx.x == 0) {
-        a.part8[(size_t)((k + 1) & 1) * a.tot8 + od.base8 + it.tile] = s;
-        if (it.tile == 0) {
-            a.nact[a.norb + it.orb] += 1;
-            if (a.nsamp) a.nsamp[a.norb + it.orb] += 1;
-        }
-    }
-}
-
-// preconditioned CG: x += alpha p; r -= alpha q; alpha = r.z / p.q
-template <typename T>
-__global__ __launch_bounds__(256) void k_pcg_update(CGIter<T> a, int k, int x_first) {
-    using V = typename Vec16<T>::V;
-    constexpr int VN = Vec16<T>::n;
-    __shared__ double sred[4];
-    const Item it = a.items8[blockIdx.x];
-    if (it.orb < 0) return;
-    if (a.done[it.orb]) return;
-    const OrbDesc od = a.orb[it.orb];
-    const double rz = rz_of(a, od, k, sred);
-    const double pq = sum_partials(a.part7 + od.base7, od.nt7, sred);
-    const T al = (T)(rz / pq);
-    const long long M = (long long)od.nx * od.ny * od.nz;
-    const long long base = (long long)it.tile * kPW;
-    double acc = 0.0;
-    if (((od.off | M) % VN) == 0) {
-#pragma unroll
-        for (int e = 0; e < kPW / (256 * VN); ++e) {
-            const long long i = base + (long long)(e * 256 + threadIdx.x) * VN;
-            if (i < M) {
-                const long long g = od.off + i;
-                V pv = *reinterpret_cast<const V *>(a.P + g);
-                V qv = *reinterpret_cast<const V *>(a.Q + g);
-                V rv = *reinterpret_cast<const V *>(a.R + g);
-                V xv = x_first ? V{} : *reinterpret_cast<const V *>(a.X + g);
-                T *px = reinterpret_cast<T *>(&xv), *pr = reinterpret_cast<T *>(&rv);
-                const T *pp = reinterpret_cast<const T *>(&pv), *pqv = reinterpret_cast<const T *>(&qv);
-#pragma unroll
-                for (int j = 0; j < VN; ++j) {
-                    px[j] = x_first ? al * pp[j] : px[j] + al * pp[j];
-                    pr[j] = pr[j] - al * pqv[j];
-                    acc += (double)pr[j] * (double)pr[j];
-                }
-                *reinterpret_cast<V *>(a.X + g) = xv;
-                *reinterpret_cast<V *>(a.R + g) = rv;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < kPW / 256; ++e) {
-            const long long i = base + e * 256 + threadIdx.x;
-            if (i < M) {
-                const long long g = od.off + i;
-                const T pv = a.P[g];
-                const T xv = x_first ? al * pv : a.X[g] + al * pv;
-                const T rv = a.R[g] - al * a.Q[g];
-                a.X[g] = xv;
-                a.R[g] = rv;
-                acc += (double)rv * (double)rv;
-            }
-        }
-    }
-    const double s = block_sum256(acc, sred);
-    if (threadIdx.x == 0) {
-        a.part8[(size_t)((k + 1) & 1) * a.tot8 + od.base8 + it.tile] = s;
-        if (it.tile == 0) {
-            a.nact[a.norb + it.orb] += 1;
-            if (a.nsamp) a.nsamp[a.norb + it.orb] += 1;
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void k_reduce_partials(int norb, const OrbDesc *orb,
-                                                         const double *part, int stencil,
-                                                         double *out) {
-    __shared__ double sred[4];
-    const int o = blockIdx.x;
-    if (o >= norb) return;
-    const OrbDesc od = orb[o];
-    const double s = stencil ? sum_partials(part + od.base7, od.nt7, sred)
-                             : sum_partials(part + od.base8, od.nt8, sred);
-    if (threadIdx.x == 0) out[o] = s;
-}
-
-
-// x64 += x32 after a reliable update (mixed precision)
-__global__ __launch_bounds__(256) void k_mixed_accumulate(const Item *items8, const OrbDesc *orb,
-                                                          const int *done, double *X64,
-                                                          const float *X32) {
-    const Item it = items8[blockIdx.x];
-    if (it.orb < 0 || done[it.orb] == 1) return;
-    const OrbDesc od = orb[it.orb];
-    const long long M = (long long)od.nx * od.ny * od.nz;
-    const long long base = (long long)it.tile * kPW;
-#pragma unroll
-    for (int e = 0; e < kPW / 256; ++e) {
-        const long long i = base + e * 256 + threadIdx.x;
-        if (i < M) X64[od.off + i] += (double)X32[od.off + i];
-    }
-}
-
-// convergence on the FP64 residual of the last reliable update
-__global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const double *partRU,
-                                                  const double *bb, double tol2, int k, int *done,
-                                                  int *iters, double *rrfin, int *rs_iter) {
-    __shared__ double sred[4];
-    const int o = blockIdx.x;
-    if (done[o] == 1) return;
-    const OrbDesc od = orb[o];
-    const double rr = sum_partials(partRU + od.base7, od.nt7, sred);
-    if (threadIdx.x == 0) {
-        if (rr <= tol2 * bb[o]) {
-            done[o] = 1;
-            iters[o] = k;
-            rrfin[o] = rr;
-        } else if (done[o] == 2) {
-            // the FP32 recursion met tol but the FP64 residual did not:
-            // resume with a restart from the FP64 residual
-            done[o] = 0;
-            rs_iter[o] = k;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// launchers
-// ---------------------------------------------------------------------------
-
 #define FSIC_RADIUS_SWITCH(radius, CALL)                           \
     switch (radius * 64 + c.cpt * 8 + c.depth) {                   \
         case 1 * 64 + 2 * 8 + 2: CALL(1, 2, 2); break;             \
@@ -715,127 +516,5 @@ __global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const doub
         default: return hipErrorInvalidValue;                      \
     }
 
-
-template <typename T>
-hipError_t launch_apply(int radius, const Coeffs &c, const Item *items, int nitems,
-                        const OrbDesc *orb, const T *u, T *Lu, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    PolApply<T> pol{items, orb, u, Lu, false};
-#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolApply<T>>), dim3(nitems), dim3(256), 0, s, pol, c)
-    FSIC_RADIUS_SWITCH(radius, CALL)
-#undef CALL
-    return hipGetLastError();
-}
-
-hipError_t launch_hamiltonian(int radius, const Coeffs &c, const Item *items, int nitems,
-                              const OrbDesc *orb, const double *psi, const double *v, double *out,
-                              hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    PolHam<double> pol{items, orb, psi, v, out, false};
-#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolHam<double>>), dim3(nitems), dim3(256), 0, s, pol, c)
-    FSIC_RADIUS_SWITCH(radius, CALL)
-#undef CALL
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_cg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, int k,
-                             int cur_from_ru, int check, hipStream_t s) {
-    if (a.nitems7 <= 0) return hipSuccess;
-    PolCG<T> pol{a.items7, a.orb, a, k, cur_from_ru, check, false, false};
-#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolCG<T>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
-    FSIC_RADIUS_SWITCH(radius, CALL)
-#undef CALL
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_cg_update(const CGIter<T> &a, int k, int cur_from_ru, int x_first,
-                            hipStream_t s) {
-    if (a.nitems8 <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cg_update<T>), dim3(a.nitems8), dim3(256), 0, s, a, k, cur_from_ru,
-                       x_first);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_pcg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, int k,
-                              int cur_from_ru, int restart, int pause, hipStream_t s) {
-    if (a.nitems7 <= 0) return hipSuccess;
-    PolPCG<T> pol{a.items7, a.orb, a, k, cur_from_ru, restart, pause, 0.0, false};
-    if (k == 0 || restart) pol.a.Pold = a.R;  // beta = 0: any finite p_old will do
-#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<T, P, C, DD, PolPCG<T>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
-    FSIC_RADIUS_SWITCH(radius, CALL)
-#undef CALL
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_pcg_update(const CGIter<T> &a, int k, int x_first, hipStream_t s) {
-    if (a.nitems8 <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_pcg_update<T>), dim3(a.nitems8), dim3(256), 0, s, a, k, x_first);
-    return hipGetLastError();
-}
-
-hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7, int nitems7,
-                                const OrbDesc *orb, const int *done, const double *X64,
-                                const float *X32, const double *B, double *X64new, float *R32,
-                                double *partRU, hipStream_t s) {
-    if (nitems7 <= 0) return hipSuccess;
-    if (X32) {
-        PolRes<true> pol{items7, orb, done, X64, X32, B, X64new, R32, partRU, false};
-#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolRes<true>>), dim3(nitems7), dim3(256), 0, s, pol, c)
-        FSIC_RADIUS_SWITCH(radius, CALL)
-#undef CALL
-    } else {
-        PolRes<false> pol{items7, orb, done, X64, X32, B, X64new, R32, partRU, false};
-#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolRes<false>>), dim3(nitems7), dim3(256), 0, s, pol, c)
-        FSIC_RADIUS_SWITCH(radius, CALL)
-#undef CALL
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_partials(int norb, const OrbDesc *orb, const double *part,
-                                  int stencil_layout, double *out, hipStream_t s) {
-    if (norb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(norb), dim3(256), 0, s, norb, orb, part,
-                       stencil_layout, out);
-    return hipGetLastError();
-}
-
-
-hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDesc *orb,
-                                   const int *done, double *X64, const float *X32, hipStream_t s) {
-    if (nitems8 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mixed_accumulate, dim3(nitems8), dim3(256), 0, s, items8, orb, done, X64, X32);
-    return hipGetLastError();
-}
-
-hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
-                           double tol2, int k, int *done, int *iters, double *rrfin, int *rs_iter,
-                           hipStream_t s) {
-    if (norb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ru_check, dim3(norb), dim3(256), 0, s, orb, partRU, bb, tol2, k, done,
-                       iters, rrfin, rs_iter);
-    return hipGetLastError();
-}
-
-template hipError_t launch_apply<double>(int, const Coeffs &, const Item *, int, const OrbDesc *,
-                                         const double *, double *, hipStream_t);
-template hipError_t launch_apply<float>(int, const Coeffs &, const Item *, int, const OrbDesc *,
-                                        const float *, float *, hipStream_t);
-template hipError_t launch_cg_stencil<double>(int, const Coeffs &, const CGIter<double> &, int, int,
-                                              int, hipStream_t);
-template hipError_t launch_cg_stencil<float>(int, const Coeffs &, const CGIter<float> &, int, int,
-                                             int, hipStream_t);
-template hipError_t launch_pcg_stencil<double>(int, const Coeffs &, const CGIter<double> &, int, int,
-                                               int, int, hipStream_t);
-template hipError_t launch_pcg_stencil<float>(int, const Coeffs &, const CGIter<float> &, int, int,
-                                              int, int, hipStream_t);
-template hipError_t launch_pcg_update<double>(const CGIter<double> &, int, int, hipStream_t);
-template hipError_t launch_pcg_update<float>(const CGIter<float> &, int, int, hipStream_t);
-template hipError_t launch_cg_update<double>(const CGIter<double> &, int, int, int, hipStream_t);
-template hipError_t launch_cg_update<float>(const CGIter<float> &, int, int, int, hipStream_t);
 
 }  // namespace fsic

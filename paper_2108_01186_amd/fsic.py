@@ -195,6 +195,10 @@ class Context:
         _check(fsic_create(ctypes.byref(self._h), ctypes.byref(self.opts), self._stream))
         self._keep = []
         self.stats = None
+        # the context holds one tape (the last forward pass); every forward
+        # pass gets a new generation number so a backward pass can tell
+        # whether the tape is still its own
+        self.generation = 0
 
     def close(self):
         if self._h:
@@ -214,6 +218,7 @@ class Context:
             if k == "solver" and isinstance(v, str):
                 v = {"cg": FSIC_CG, "pcg": FSIC_PCG, "aar": FSIC_AAR}[v]
             setattr(self.opts, k, v)
+        self.generation += 1  # the library drops the tape with new options
         _check(fsic_set_opts(self._h, ctypes.byref(self.opts)), self._h)
 
     def forward(self, systems: Sequence[dict], allow_noconv=False):
@@ -248,6 +253,7 @@ class Context:
         st = fsic_stats()
         status = fsic_forward(self._h, nsys, arr, e.ctypes.data_as(_dp), U.ctypes.data_as(_dp),
                               X.ctypes.data_as(_dp), ctypes.byref(st))
+        self.generation += 1
         _check(status, self._h, allow=(FSIC_ENOCONV,) if allow_noconv else ())
         self._keep = keep
         self.stats = st.as_dict()
@@ -422,7 +428,10 @@ def _make_autograd():
                  until backward runs)
           fods:  one host (N_s, 3) float64 tensor per spin channel
         V_SIC outputs are not differentiable; the gradient of E_SIC with
-        respect to each FOD tensor comes from fsic_backward.
+        respect to each FOD tensor comes from fsic_backward.  The context
+        keeps the tape of its last forward pass only: when another forward
+        pass ran on it since this one (two geometries before one backward),
+        backward first repeats this forward pass (same inputs, same result).
         """
 
         @staticmethod
@@ -432,11 +441,13 @@ def _make_autograd():
             n, h, origin = grid
             vs = [torch.empty(p.shape[1], dtype=torch.float64, device=p.device) for p in psis]
             d = {"n": n, "h": h, "origin": origin, "psi": list(psis),
-                 "fod": [f.detach().cpu().numpy() for f in fods], "vsic": vs}
+                 "fod": [f.detach().cpu().numpy().copy() for f in fods], "vsic": vs}
             e, U, X, st = fctx.forward([d])
             actx.fctx = fctx
+            actx.generation = fctx.generation
             actx.nocc = [p.shape[0] for p in psis]
             actx.psis = psis
+            actx.inputs = dict(d, vsic=None)
             actx.mark_non_differentiable(*vs)
             return (torch.tensor(e[0], dtype=torch.float64), *vs)
 
@@ -445,7 +456,14 @@ def _make_autograd():
             for g in gV:
                 if g is not None and bool(torch.any(g != 0)):
                     raise RuntimeError("V_SIC is not differentiable in this library")
-            res = actx.fctx.backward([actx.nocc], grad_e=[float(gE)])
+            fctx = actx.fctx
+            if fctx.generation != actx.generation:
+                # the tape belongs to a later forward pass: rebuild this one
+                if not (fctx.opts.flags & FSIC_KEEP_TAPE):
+                    fctx.set_opts(flags=fctx.opts.flags | FSIC_KEEP_TAPE)
+                fctx.forward([actx.inputs])
+                actx.generation = fctx.generation
+            res = fctx.backward([actx.nocc], grad_e=[float(gE)])
             grads = [torch.tensor(r, dtype=torch.float64) for r in res[0]]
             return (None, None, None, *grads)
 

@@ -153,3 +153,33 @@ def test_backward_without_tape(torch_cuda, F, mol40):
         ctx.backward([[5]])
     assert ei.value.status == F.FSIC_ENOTAPE
     ctx.close()
+
+
+def test_two_geometries_before_one_backward(torch_cuda, F, mol40):
+    """Two forward passes of the autograd Function on one context, then one
+    backward of their sum: each FOD set gets the gradient of its own
+    geometry (the context's single tape is rebuilt for the older pass)."""
+    torch = torch_cuda
+    _say("autograd: two geometries, one backward")
+    s = mol40
+    psi = [torch.tensor(np.asarray(s.psi[0]), device="cuda")]
+    f1 = np.asarray(s.fod[0]).copy()
+    f2 = f1.copy()
+    f2[1, 0] += 0.05
+    f2[3, 2] -= 0.04
+    ctx = F.Context(tol=1e-12)
+    refs = []
+    for f in (f1, f2):
+        ft = torch.tensor(f, requires_grad=True)
+        E, _ = F.flosic_sic(ctx, s.n, s.h, s.origin, psi, [ft])
+        E.backward()
+        refs.append(ft.grad.numpy().copy())
+    assert np.abs(refs[0] - refs[1]).max() > 1e-4  # the geometries differ
+    a = torch.tensor(f1, requires_grad=True)
+    b = torch.tensor(f2, requires_grad=True)
+    E1, _ = F.flosic_sic(ctx, s.n, s.h, s.origin, psi, [a])
+    E2, _ = F.flosic_sic(ctx, s.n, s.h, s.origin, psi, [b])
+    (E1 + E2).backward()
+    assert np.abs(a.grad.numpy() - refs[0]).max() < 1e-12
+    assert np.abs(b.grad.numpy() - refs[1]).max() < 1e-12
+    ctx.close()

@@ -224,6 +224,84 @@ def test_hamiltonian_harmonic_ground_state(oracle):
     assert np.abs(hs - hp - 0.37 * psi).max() < 1e-13
 
 
+def _p_density(n, h, centre=(0.3, -0.2, 0.25), s=0.7):
+    """Normalised density of an off-centre p-type orbital (x + y/2) exp(-r^2 / 2s^2):
+    it has monopole, dipole and quadrupole moments about the box centre."""
+    x = -h * (n - 1) / 2 + h * np.arange(n)
+    X = x[None, None, :] - centre[0]
+    Y = x[None, :, None] - centre[1]
+    Z = x[:, None, None] - centre[2]
+    rho = ((X + 0.5 * Y) * np.exp(-(X * X + Y * Y + Z * Z) / (2 * s * s))) ** 2
+    return rho / (rho.sum() * h ** 3), x
+
+
+def _cube_self_integral():
+    """int over two unit cubes of 1 / |x - y| = 8 int_[0,1]^3 prod_d (1 - u_d) / |u| du
+    (the autocorrelation of the unit cube against the Coulomb kernel)."""
+    from scipy import integrate
+    f = lambda z, y, x: (1 - x) * (1 - y) * (1 - z) / math.sqrt(x * x + y * y + z * z)
+    return 8 * integrate.tplquad(f, 0, 1, 0, 1, 0, 1, epsabs=1e-12, epsrel=1e-12)[0]
+
+
+def _coulomb_direct(rho, x, h, I1):
+    """Direct O(M^2) double sum 1/2 sum_{i != j} w_i w_j / |r_i - r_j| plus the
+    self-cell terms 1/2 w_i^2 I1 / h (uniform charge in a cube of side h), w = rho dV."""
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    w = rho.ravel() * h ** 3
+    tot = 0.0
+    for i0 in range(0, len(w), 2048):
+        d = np.linalg.norm(pos[i0:i0 + 2048, None, :] - pos[None, :, :], axis=2)
+        np.fill_diagonal(d[:, i0:i0 + 2048], np.inf)
+        tot += float((w[i0:i0 + 2048, None] * w[None, :] / d).sum())
+    return 0.5 * (tot + float((w ** 2).sum()) * I1 / h)
+
+
+def _coulomb_convolution(rho, h, I1):
+    """The same discrete double sum as _coulomb_direct, evaluated as an
+    aperiodic convolution (zero padding to 2n per axis, FFT)."""
+    from scipy import fft
+    n = rho.shape[0]
+    w = rho * h ** 3
+    m = 2 * n
+    off = np.arange(m)
+    off = np.where(off < n, off, off - m).astype(float) * h
+    R = np.sqrt(off[:, None, None] ** 2 + off[None, :, None] ** 2 + off[None, None, :] ** 2)
+    K = np.where(R > 0, 1.0 / np.where(R > 0, R, 1.0), I1 / h)
+    W = np.zeros((m, m, m))
+    W[:n, :n, :n] = w
+    phi = fft.irfftn(fft.rfftn(W) * fft.rfftn(K), s=(m, m, m))[:n, :n, :n]
+    return 0.5 * float((w * phi).sum())
+
+
+def test_hartree_energy_vs_direct_coulomb_sum(oracle):
+    """U of Eq. 1 from the oracle's finite-difference Poisson solve with
+    multipole boundary values, against direct Coulomb sums that use neither
+    the Laplacian nor the boundary expansion: the O(M^2) double sum over the
+    nodes (brute force on a 24^3 grid, equal to its convolution form to
+    rounding), on grids h = 0.4 .. 0.12, extrapolated to h -> 0 with
+    U(h) = U_0 + a h^2 + b h^4.  Dropping the dipole (quadrupole) boundary
+    terms moves U by 3e-5 (7e-6) for this density."""
+    I1 = _cube_self_integral()
+    rho, x = _p_density(24, 0.4)
+    brute = _coulomb_direct(rho, x, 0.4, I1)
+    assert abs(brute - _coulomb_convolution(rho, 0.4, I1)) < 1e-12
+    hs, us = [], []
+    for n, h in ((24, 0.4), (32, 0.3), (48, 0.2), (64, 0.15), (80, 0.12)):
+        hs.append(h)
+        us.append(_coulomb_convolution(_p_density(n, h)[0], h, I1))
+    hs = np.array(hs)
+    A = np.stack([np.ones_like(hs), hs ** 2, hs ** 4], 1)
+    U0 = np.linalg.lstsq(A, np.array(us), rcond=None)[0][0]
+    n, h = 40, 0.24
+    U, _, _, rr = oracle.orbital_terms(_p_density(n, h)[0].ravel(), (n, n, n), h, _origin(n, h))
+    assert rr < 1e-12
+    assert abs(U - U0) < 4e-6, (U, U0)
+    # the direct sums converge towards the oracle's value
+    errs = np.abs(np.array(us) - U)
+    assert np.all(np.diff(errs) < 0)
+
+
 def test_gaussian_potential_pointwise(oracle):
     """Potential of a centred Gaussian: erf(r / (sqrt2 sigma)) / r at every node."""
     n, h, sigma = 40, 0.3, 1.0
@@ -518,6 +596,21 @@ def test_one_electron_s_gaussian(oracle):
     assert abs(r.U[0] - U) < 1e-7
     assert abs(r.X[0] - (Ex + Ec)) < 1e-6
     assert abs(e[0] + U + Ex + Ec) < 2e-6
+    # V_SIC = s V_1 with V_1 = -(v_H + v_xc) of the one density (the weights
+    # rho_1 / rho_1 are 1 wherever the density is above the floor); v_H of the
+    # Gaussian density C exp(-2 a r^2) (unit charge, sigma^2 = 1 / (4 a)) is
+    # erf(sqrt(2 a) r) / r
+    rho = (psi ** 2).reshape(-1)
+    rgrid = np.sqrt(r2).reshape(-1)
+    vh = np.array([math.erf(math.sqrt(2 * a) * q) / q if q > 0 else 2 * math.sqrt(2 * a / math.pi)
+                   for q in rgrid])
+    assert np.abs(r.v[0] - vh).max() < 5e-7
+    _, _, vx, vc = oracle.xc_pol(rho)
+    live = rho > 1e-30
+    assert np.abs(r.vsic[live] + 0.5 * (vh + vx + vc)[live]).max() < 5e-7
+    # and exactly (to rounding) with the oracle's own Hartree potential
+    assert np.abs(r.vsic[live] + 0.5 * (r.v[0] + vx + vc)[live]).max() < 1e-14
+    assert np.all(r.vsic[~live] == 0.0)
     for fdg, eq9 in ((False, False), (True, False), (False, True), (True, True)):
         grad = oracle.sic_grad_spin(psi, np.array([[0.1, -0.2, 0.3]]), (n, n, n), h, origin,
                                     fd_gradient=fdg, eq9=eq9)
