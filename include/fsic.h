@@ -298,6 +298,23 @@ fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, con
                         double rho_floor, double *T, double *G, double *S, double *Z, double *phi,
                         void *hip_stream);
 
+/* fsic_op_flo without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, outputs, validation
+ * and status codes as fsic_op_flo.  Every intermediate (interpolated
+ * values, the Gram partial tiles, the N x N matrices, the Jacobi work
+ * space, the device status word) lives in one file-scope device array of
+ * about 18 MiB that each GPU the library runs on holds until the process
+ * ends; N <= 128 and any grid fit in it (larger N is rejected with
+ * FSIC_EINVAL before any launch).  The call itself allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine.  All calls on one GPU
+ * share that GPU's array and it keeps the last call's contents (the status
+ * word is cleared at the start of each call), so calls that overlap on one
+ * GPU race; serialise them.  Synchronous on the given stream. */
+fsic_status fsic_op_flo_noalloc(const fsic_grid *grid, int32_t N, const double *psi,
+                                const double *fod, double rho_floor, double *T, double *G,
+                                double *S, double *Z, double *phi, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfsic.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["stencil_ops.hip", "stencil_cg.hip", "stencil_pcg.hip", "stencil_res.hip", "dst.hip", "aar.hip", "multipole.hip", "xc.hip", "fo.hip", "adjoint.hip", "runtime.cpp"]
+SOURCES = ["stencil_ops.hip", "stencil_cg.hip", "stencil_pcg.hip", "stencil_res.hip", "dst.hip", "aar.hip", "multipole.hip", "xc.hip", "fo.hip", "adjoint.hip", "noalloc.hip", "runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

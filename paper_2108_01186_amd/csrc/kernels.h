@@ -311,4 +311,18 @@ hipError_t launch_lowdin_backward(int N, const double *Bm, const double *T, cons
                                   const double *rhoa, const double *du, double *work,
                                   double *dEda, hipStream_t s);
 
+// ----------------------------------------------------------------------------
+// noalloc.hip: the Fermi-Loewdin step on a file-scope scratch array
+// ----------------------------------------------------------------------------
+
+// Device address and size (doubles) of the current device's scratch array.
+hipError_t noalloc_scratch(double **ptr, size_t *doubles);
+
+// interpolation, Gram matrix, Loewdin step and phi = Z T psi of one channel
+// with every intermediate in the scratch array (synchronous on s); *hstatus
+// receives the device status bits
+hipError_t noalloc_flo(int N, const int n[3], double h, const double *psi, const FodCell *cells,
+                       double rho_floor, double *T, double *G, double *S, double *Z, double *phi,
+                       int *hstatus, hipStream_t s);
+
 }  // namespace fsic

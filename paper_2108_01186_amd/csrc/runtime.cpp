@@ -1792,6 +1792,24 @@ fsic_status fod_cells(const fsic_grid &g, int N, const double *fod, FodCell *cel
 
 extern "C" {
 
+fsic_status fsic_op_flo_noalloc(const fsic_grid *grid, int32_t N, const double *psi, const double *fod,
+                                double rho_floor, double *T, double *G, double *S, double *Z,
+                                double *phi, void *hip_stream) {
+    if (!grid || !psi || !fod || N < 1 || N > kMaxOrb || !(rho_floor >= 0.0)) return FSIC_EINVAL;
+    std::string why;
+    if (validate_grid(*grid, why)) return FSIC_EINVAL;
+    FodCell cells[kMaxOrb];
+    const fsic_status cs = fod_cells(*grid, N, fod, cells);
+    if (cs) return cs;
+    int hs = 0;
+    const hipError_t e = noalloc_flo(N, grid->n, grid->h, psi, cells, rho_floor, T, G, S, Z, phi, &hs,
+                                     (hipStream_t)hip_stream);
+    if (e != hipSuccess) return FSIC_EHIP;
+    if (hs & kStVacuum) return FSIC_EVACUUM;
+    if (hs & kStSingular) return FSIC_ESINGULAR;
+    return FSIC_OK;
+}
+
 fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, const double *fod,
                         double rho_floor, double *T, double *G, double *S, double *Z, double *phi,
                         void *hip_stream) {

@@ -114,6 +114,9 @@ fsic_op_invsqrt = _sig("fsic_op_invsqrt", ctypes.c_int,
 fsic_op_flo = _sig("fsic_op_flo", ctypes.c_int,
                    [_P(fsic_grid), ctypes.c_int32, _vp, _dp, ctypes.c_double, _vp, _vp, _vp, _vp,
                     _vp, _vp])
+fsic_op_flo_noalloc = _sig("fsic_op_flo_noalloc", ctypes.c_int,
+                           [_P(fsic_grid), ctypes.c_int32, _vp, _dp, ctypes.c_double, _vp, _vp, _vp,
+                            _vp, _vp, _vp])
 fsic_op_interp = _sig("fsic_op_interp", ctypes.c_int,
                       [_P(fsic_grid), ctypes.c_int32, ctypes.c_int32, _vp, _dp, ctypes.c_int32, _vp,
                        _vp, _vp])
@@ -122,7 +125,7 @@ EXPORTED = ["fsic_default_opts", "fsic_create", "fsic_set_opts", "fsic_forward",
             "fsic_status_string", "fsic_last_error", "fsic_destroy", "fsic_op_laplacian",
             "fsic_op_laplacian_f32", "fsic_op_xc", "fsic_op_poisson", "fsic_op_invsqrt",
             "fsic_op_hamiltonian", "fsic_op_interp",
-            "fsic_op_flo"]
+            "fsic_op_flo", "fsic_op_flo_noalloc"]
 
 
 class FsicError(RuntimeError):
@@ -371,8 +374,10 @@ def op_interp(psi, pts, n, h, origin, fd_gradient=False, stream=None):
     return u, du
 
 
-def op_flo(psi, fod, n, h, origin, rho_floor=1e-30, stream=None):
-    """T, G, S, Z (N x N) and the Fermi-Loewdin orbitals phi (N x M) of one channel."""
+def op_flo(psi, fod, n, h, origin, rho_floor=1e-30, stream=None, noalloc=False):
+    """T, G, S, Z (N x N) and the Fermi-Loewdin orbitals phi (N x M) of one
+    channel; noalloc: through fsic_op_flo_noalloc (the library allocates
+    nothing; the outputs here are still torch tensors)."""
     torch = _torch()
     psi = psi.contiguous()
     N = psi.shape[0]
@@ -380,8 +385,9 @@ def op_flo(psi, fod, n, h, origin, rho_floor=1e-30, stream=None):
     mats = [torch.empty(N, N, dtype=torch.float64, device=psi.device) for _ in range(4)]
     phi = torch.empty_like(psi)
     g = make_grid(n, h, origin)
-    _check(fsic_op_flo(ctypes.byref(g), N, _dev_ptr(psi), fod.ctypes.data_as(_dp), rho_floor,
-                       *[_dev_ptr(m) for m in mats], _dev_ptr(phi), _stream_ptr(stream)))
+    fn = fsic_op_flo_noalloc if noalloc else fsic_op_flo
+    _check(fn(ctypes.byref(g), N, _dev_ptr(psi), fod.ctypes.data_as(_dp), rho_floor,
+              *[_dev_ptr(m) for m in mats], _dev_ptr(phi), _stream_ptr(stream)))
     return (*mats, phi)
 
 

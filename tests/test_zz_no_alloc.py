@@ -1,0 +1,61 @@
+"""The no-allocation Fermi-Loewdin entry point (fsic_op_flo_noalloc) against
+fsic_op_flo through the C ABI: two calls in a row, the second with a
+smaller input (fewer orbitals on a smaller grid), each output of both
+calls to rounding of the other entry point's."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2108_01186_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _call(F, fn, torch, s, sp=0):
+    psi = s.psi[sp] if isinstance(s.psi[sp], torch.Tensor) else torch.tensor(np.asarray(s.psi[sp]),
+                                                                              device="cuda")
+    psi = psi.contiguous()
+    N = psi.shape[0]
+    fod = np.ascontiguousarray(np.asarray(s.fod[sp], dtype=np.float64))
+    mats = [torch.full((N, N), float("nan"), dtype=torch.float64, device="cuda") for _ in range(4)]
+    phi = torch.full_like(psi, float("nan"))
+    g = F.make_grid(s.n, s.h, s.origin)
+    st = fn(ctypes.byref(g), N, ctypes.c_void_p(psi.data_ptr()),
+            fod.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_double(1e-30),
+            *[ctypes.c_void_p(m.data_ptr()) for m in mats], ctypes.c_void_p(phi.data_ptr()),
+            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == F.FSIC_OK, F.fsic_status_string(st)
+    torch.cuda.synchronize()
+    return [m.cpu().numpy() for m in mats] + [phi.cpu().numpy()]
+
+
+def test_noalloc_flo_matches_allocating_entry_point(torch_cuda):
+    torch = torch_cuda
+    from paper_2108_01186_amd import fsic as F
+    na = F.fsic_op_flo_noalloc
+    big = synth.make_workload("mol40")
+    small = synth.make_molecule("mol28", 28, 0.3, n_atoms=3, n_gauss=8, nocc=(3,), seed=2999)
+    cases = (("mol40 (5 orbitals, 40^3)", big), ("mol28 (3 orbitals, 28^3)", small))
+    refs = [_call(F, F.fsic_op_flo, torch, s) for _, s in cases]
+    # the two no-allocation calls back to back, the second on the smaller input
+    gots = []
+    for name, s in cases:
+        _say(f"no-alloc FLO: {name}")
+        gots.append(_call(F, na, torch, s))
+    for (name, _), got, ref in zip(cases, gots, refs):
+        for lab, a, b in zip(("T", "G", "S", "Z", "phi"), got, ref):
+            assert np.all(np.isfinite(a)), lab
+            assert np.abs(a - b).max() <= 1e-13 * max(1.0, np.abs(b).max()), (name, lab)
