@@ -52,7 +52,8 @@ def parse():
 def run_steps(F, torch, ctx, dicts, noccs, steps):
     """Timed region: `steps` full passes (forward + backward) over all systems."""
     keys = ("sweep_ms", "sweep_bytes", "sweep_launches", "update_ms", "update_bytes",
-            "update_launches", "precond_ms", "precond_bytes", "precond_flops", "precond_launches")
+            "update_launches", "precond_ms", "precond_bytes", "precond_flops", "precond_launches",
+            "resid_ms", "resid_bytes", "resid_launches")
     agg = dict({k: 0.0 for k in keys}, iters=0, solves=0, refinements=0, max_relres=0.0,
                phase_ms=[0.0] * 8)
     e = g = None
@@ -121,11 +122,14 @@ def cpu_baseline(sysobj, tol, budget_s):
                       f"OpenMP over the host cores"}
 
 
+KERNEL_SOURCES = ("zmarch.h", "stencil_pcg.hip", "stencil_res.hip", "dst.hip", "common.h")
+
+
 def kernel_source_hash():
     """Hash of the solver kernel sources (invalidates stored HBM traffic)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("stencil.hip", "dst.hip", "common.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2108_01186_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -169,7 +173,7 @@ def kernel_rates(agg):
     region): time per launch, algorithmic GB/s and, for the preconditioner,
     matrix-core TFLOP/s."""
     out = {}
-    for k in ("sweep", "update", "precond"):
+    for k in ("sweep", "update", "precond", "resid"):
         n, ms = agg[f"{k}_launches"], agg[f"{k}_ms"]
         if n <= 0 or ms <= 0:
             continue
@@ -183,9 +187,10 @@ def kernel_rates(agg):
 
 
 KERNEL_NAMES = {
-    "sweep": "k_zmarch (CG stencil sweep: p, q = -L p, p.q)",
-    "update": "k_pcg_update / k_cg_update (x += alpha p, r -= alpha q)",
-    "precond": "k_dst_xy + k_dst_fast(z) + k_dst_xy (sine-transform preconditioner, split-bf16 MFMA; five per-axis passes where a plane does not fit in LDS, k_dst_pass above 128 nodes)",
+    "sweep": "k_zmarch<PolPQ> (CG stencil sweep: q = -L p, p.q)",
+    "update": "k_pcg_rupd (r -= alpha q)",
+    "precond": "k_dst_xy + k_dst_fast(z) + k_dst_xy<PO> (sine-transform preconditioner, split-bf16 MFMA; its last pass writes p = z + beta p_old; five per-axis passes where a plane does not fit in LDS)",
+    "resid": "k_zmarch<PolResP> (FP64 residual b + L x closing a restart cycle, x = x64 + alpha_a p_a + alpha_b p_b)",
 }
 
 

@@ -99,9 +99,9 @@ enum { FSIC_CG = 0, FSIC_PCG = 1, FSIC_AAR = 2 };
 #define FSIC_KEEP_TAPE       2u  /* keep what fsic_backward needs */
 #define FSIC_ALLOW_NONORTHO  4u  /* accept non-orthonormal psi (S = T G T^T is exact anyway) */
 #define FSIC_PROFILE         8u  /* time sampled CG launches with HIP events (fsic_stats.sweep_*) */
-#define FSIC_GRAPHS         32u  /* preconditioned solves: capture each chunk of CG iterations (with its
-                                    FP64 residual check) as a HIP graph once per batch layout and
-                                    replay it; ignored with FSIC_PROFILE */
+#define FSIC_GRAPHS         32u  /* FSIC_PCG with FSIC_MIXED: capture each restart cycle (its CG
+                                    iterations and the FP64 residual check) as a HIP graph once per
+                                    batch layout and buffers, and replay it; ignored with FSIC_PROFILE */
 #define FSIC_FP32_ORBITALS  16u  /* Fermi-Loewdin orbitals phi = (Z T) psi from an fp32 GEMM on the
                                     matrix cores (fp32 operands and accumulation); costs about 1e-7
                                     relative in phi, more than the 1e-8 Ha energy budget allows */
@@ -115,7 +115,7 @@ enum { FSIC_CG = 0, FSIC_PCG = 1, FSIC_AAR = 2 };
                                     (the boundary part of the map is the only difference) */
 
 typedef struct {
-    int32_t n[3];       /* nodes per axis, 8..4096, at most 2^29 nodes in all */
+    int32_t n[3];       /* nodes per axis, 8..4096, fewer than 2^29 nodes in all */
     double h;           /* spacing (Bohr), > 0 */
     double origin[3];   /* position of node (0, 0, 0) */
 } fsic_grid;
@@ -186,6 +186,13 @@ typedef struct {
     int32_t stencil_cpt, stencil_depth;
     int64_t stencil_blocks;
     double  tune_ms;
+    /* FSIC_PCG in FSIC_MIXED with FSIC_PROFILE: the FP64 residual pass that
+     * closes each restart cycle (every cycle but the first is sampled) */
+    int32_t resid_launches;
+    double  resid_ms, resid_bytes;
+    /* FSIC_GRAPHS: restart-cycle graphs captured so far by this context
+     * (a replayed graph is not counted again) */
+    int32_t graph_captures;
 } fsic_stats;
 
 /* Fills *o with the defaults: fd_order 12, lmax 6, FSIC_PCG, FP64, tol 1e-10,

@@ -49,12 +49,12 @@ struct OrbDesc {
 struct Item {
     int orb, tile;
 };
-// Work lists of the three spectral-preconditioner passes (see dst.hip);
-// fast: 0 fp32 kernels (32-column panels); 1 persistent split-bf16 kernels
-// with 128-column panels; 2 the same with 64-column panels; 3 64-column
-// panels with the sine matrix rounded to bf16 (no S_lo term), for axes whose
-// split sine matrix does not fit the LDS.  np: largest axis padded to 32;
-// blocks: persistent blocks per pass.
+// Work lists of the spectral-preconditioner passes (see dst.hip); fast: 1
+// persistent split-bf16 kernels with 128-column panels; 2 the same with
+// 64-column panels; 3 64-column panels with the sine matrix rounded to bf16
+// (no S_lo term), for axes whose split sine matrix does not fit the LDS
+// (0: no variant fits; such batches are solved without the preconditioner).
+// np: largest axis padded to 32; blocks: persistent blocks per pass.
 struct DstItems {
     const Item *x, *y, *z;
     int nx, ny, nz;
@@ -66,8 +66,22 @@ struct DstItems {
     int zocc2;       // z pass: 64-column panels, two blocks per compute unit
 };
 
-// panel columns of a fast transform variant
-inline int dst_panel_cols(int variant) { return variant == 1 ? 128 : (variant ? 64 : 32); }
+// Output of the last transform pass when it forms the next search
+// direction of preconditioned CG directly: p_k = z_k + beta p_{k-1},
+// beta = r_k.z_k / r_{k-1}.z_{k-1} per orbital from the z pass's partial
+// sums (slots base9 .. base9 + nt9 of each orbital), or p_k = z_k when first.
+struct PcgOut {
+    const float *pold;   // p_{k-1} (not read when first)
+    const double *rzc;   // r_k.z_k partial sums
+    const double *rzp;   // r_{k-1}.z_{k-1} partial sums
+    int first;           // 1: beta = 0 (first iteration of a restart cycle)
+};
+
+// panel columns of a fast transform variant's x and y passes (the z pass
+// uses 64-column panels in every variant)
+inline int dst_panel_cols(int variant) { return variant == 1 ? 128 : 64; }
+// longest padded axis a variant's kernels are sized for
+inline int dst_variant_npmax(int variant) { return variant == 1 ? 128 : (variant == 2 ? 160 : 192); }
 
 struct Coeffs {
     double c[kMaxRadius + 1];  // unit-spacing second-difference weights
@@ -78,6 +92,17 @@ struct Coeffs {
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------
+
+// Workgroup barrier that orders LDS traffic only: this wave's LDS operations
+// complete (lgkmcnt(0)), then s_barrier.  Unlike __syncthreads() it does not
+// wait for outstanding global loads, so the next plane's prefetch stays in
+// flight across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt/expcnt: no wait; lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -17,10 +17,13 @@
 //     one z plane in one visit, forward (reads r) and inverse (writes z);
 //   * k_dst_fast<2, 1>: the z transform, the 1/lambda scaling and the
 //     inverse z transform, with the r.z partial sums;
-//   * otherwise five per-axis passes (k_dst_fast, or k_dst_pass on FP32
-//     matrix cores for axes above 128 nodes), the last writing z and r.z.
-// The fast kernels split each fp32 operand into bf16 hi + lo (see below).
+//   * otherwise five per-axis passes of k_dst_fast (x, y, z with the 1/lambda
+//     scaling and the r.z partial sums, y, x).
+// The last pass writes z, or directly the next CG search direction
+// p = z + beta p_old (PcgOut).  The kernels split each fp32 operand into
+// bf16 hi + lo (see below).
 #include <algorithm>
+#include <cstdlib>
 
 #include "kernels.h"
 
@@ -30,180 +33,11 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kPC = 32;      // panel columns per block
-constexpr int kLW = kPC + 1;  // LDS row stride (odd: conflict-free column access)
-
 __device__ __forceinline__ int axis_n(const OrbDesc &od, int ax) {
     return ax == 0 ? od.nx : (ax == 1 ? od.ny : od.nz);
 }
 
 }  // namespace
-
-// One pass along axis AX of the orbitals in `items`.
-//   MODE 0: out = S in;  MODE 1 (z axis only): out = S W S in, W the scaled
-//   inverse eigenvalues.  TIN is the type of `in` (the CG residual in the
-//   first pass), out is always float; RZ (last pass): partial sums of r.z
-//   with r = rres (type TR) into rz[base9 + block index of the orbital].
-//   Orbitals with done != 0 are skipped.
-//   cnt (first pass, may be null): per orbital, applications that did work.
-template <int AX, int MODE, typename TIN, typename TR, bool RZ>
-__global__ __launch_bounds__(256) void k_dst_pass(const Item *items, const OrbDesc *orb,
-                                                  const int *done, const float *tab, const TIN *in,
-                                                  float *out, const TR *rres, double *rz, int *cnt) {
-    __shared__ float sx[256 * kLW];
-    __shared__ double sred[4];
-    const Item it = items[blockIdx.x];
-    if (it.orb < 0) return;
-    if (done[it.orb]) return;
-    if (cnt && it.tile == 0 && threadIdx.x == 0) cnt[it.orb] += 1;
-    const OrbDesc od = orb[it.orb];
-    const int n = axis_n(od, AX);
-    const int np = (n + 31) & ~31;
-    const long long plane = (long long)od.nx * od.ny;
-    const float *S = tab + od.dst_s[AX];  // np x np, zero beyond n
-    const int t = threadIdx.x;
-
-    // panel: columns c0 .. c0 + 31 of the (n x ncol) matrix view of the field
-    //   x axis: column c = row index y + ny z, element k at c nx + k
-    //   y axis: column = x in plane zc, element k at zc plane + k nx + x
-    //   z axis: column = in-plane index q, element k at k plane + q
-    long long cbase = 0;  // element offset of column c0
-    long long kstr = 1;   // element stride along k (y, z axes)
-    int ncol = 0, c0 = 0;
-    if (AX == 0) {
-        ncol = od.ny * od.nz;
-        c0 = it.tile * kPC;
-    } else if (AX == 1) {
-        const int xt = (od.nx + kPC - 1) / kPC;
-        const int zc = it.tile / xt;
-        c0 = (it.tile - zc * xt) * kPC;
-        ncol = od.nx;
-        cbase = (long long)zc * plane + c0;
-        kstr = od.nx;
-    } else {
-        c0 = it.tile * kPC;
-        ncol = (int)plane;
-        cbase = c0;
-        kstr = plane;
-    }
-    const int cval = min(kPC, ncol - c0);  // valid columns in this panel
-    const TIN *src = in + od.off;
-
-    // ---- stage the panel in LDS: sx[k * kLW + c], zero-padded to np rows
-    if (AX == 0) {
-        // rows of nx contiguous values: 64 threads along k, 4 rows at a time
-        const int kk = t & 63, cc = t >> 6;
-        for (int c = cc; c < kPC; c += 4) {
-            const bool cv = c < cval;
-            const TIN *row = src + (long long)(c0 + c) * od.nx;
-            for (int k = kk; k < np; k += 64)
-                sx[k * kLW + c] = (cv && k < n) ? (float)row[k] : 0.f;
-        }
-    } else {
-        const int cc = t & 31, kk = t >> 5;
-        const bool cv = cc < cval;
-        for (int k = kk; k < np; k += 8)
-            sx[k * kLW + cc] = (cv && k < n) ? (float)src[cbase + (long long)k * kstr + cc] : 0.f;
-    }
-    __syncthreads();
-
-    // ---- out panel = S (np x np) . panel (np x 32) on the matrix cores
-    // wave w: column tile w & 1, row tiles (w >> 1) + 2 i
-    const int lane = t & 63, w = t >> 6;
-    const int ct = w & 1;
-    const int nrt = np >> 4;
-    const int r0 = w >> 1;
-    constexpr int MT = 8;  // up to 8 row tiles per wave (np <= 256)
-    if (np > 256) return;  // the host routes such grids to plain CG
-    flt4 acc[MT];
-#pragma unroll
-    for (int i = 0; i < MT; ++i) acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
-    const int lr = lane & 15, lk = lane >> 4;
-    auto gemm = [&]() {
-        for (int k0 = 0; k0 < np; k0 += 4) {
-            const float b = sx[(k0 + lk) * kLW + ct * 16 + lr];
-#pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                const int rt = r0 + 2 * i;
-                if (rt < nrt) {
-                    const float a = S[(long long)(rt * 16 + lr) * np + k0 + lk];
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i], 0, 0, 0);
-                }
-            }
-        }
-    };
-    gemm();
-    if (MODE == 1) {
-        // scale by norm / lambda(jx, jy, l) and transform again along z
-        const float *gx = tab + od.dst_g[0], *gy = tab + od.dst_g[1], *gz = tab + od.dst_g[2];
-        const float norm = 8.f / ((float)(od.nx + 1) * (float)(od.ny + 1) * (float)(od.nz + 1));
-        const float ih2 = (float)od.inv_h2;
-        const int c = ct * 16 + lr;
-        const int q = c0 + c;  // in-plane spectral index (jx, jy)
-        const int jy = q / od.nx, jx = q - jy * od.nx;
-        const float gxy = (c < cval) ? gx[jx] + gy[jy] : 1.f;
-        __syncthreads();  // every wave is done reading the panel
-#pragma unroll
-        for (int i = 0; i < MT; ++i) {
-            const int rt = r0 + 2 * i;
-            if (rt < nrt) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int m = rt * 16 + 4 * lk + j;
-                    const float lam = (m < n) ? (gxy + gz[m]) * ih2 : 1.f;
-                    sx[m * kLW + c] = (m < n && c < cval) ? acc[i][j] * (norm / lam) : 0.f;
-                }
-                acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
-            }
-        }
-        __syncthreads();
-        gemm();
-    }
-
-    // ---- write back (x axis: through LDS so rows go out along x)
-    float *dst = out + od.off;
-    double part = 0.0;
-    if (AX == 0) {
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < MT; ++i) {
-            const int rt = r0 + 2 * i;
-            if (rt < nrt) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) sx[(rt * 16 + 4 * lk + j) * kLW + ct * 16 + lr] = acc[i][j];
-            }
-        }
-        __syncthreads();
-        const int kk = t & 63, cc = t >> 6;
-        for (int c = cc; c < cval; c += 4) {
-            const long long row = (long long)(c0 + c) * od.nx;
-            for (int k = kk; k < n; k += 64) {
-                const float v = sx[k * kLW + c];
-                dst[row + k] = v;
-                if (RZ) part += (double)rres[od.off + row + k] * (double)v;
-            }
-        }
-    } else {
-        const int c = ct * 16 + lr;
-        if (c < cval) {
-#pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                const int rt = r0 + 2 * i;
-                if (rt < nrt) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int m = rt * 16 + 4 * lk + j;
-                        if (m < n) dst[cbase + (long long)m * kstr + c] = acc[i][j];
-                    }
-                }
-            }
-        }
-    }
-    if (RZ) {
-        const double s = block_sum256(part, sred);
-        if (t == 0) rz[od.base9 + it.tile] = s;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // fast pass (axes of at most 128 nodes): bf16 matrix cores with split operands
@@ -238,13 +72,14 @@ __device__ __forceinline__ void bsplit(float x, __bf16 &hi, __bf16 &lo) {
     lo = (__bf16)(x - (float)hi);
 }
 
-// fixed-order sum over the waves of a kFT-thread block (all threads get it)
+// fixed-order sum over the waves of a kFT-thread block (all threads get it);
+// the barriers order LDS only, so global loads and stores stay in flight
 __device__ __forceinline__ double block_sum_fast(double v, double *sbuf) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
-    __syncthreads();
+    lds_barrier();
     if ((threadIdx.x & 63) == 0) sbuf[w] = v;
-    __syncthreads();
+    lds_barrier();
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < kFT / 64; ++i) s += sbuf[i];
@@ -264,21 +99,19 @@ __device__ __forceinline__ float4 ld4(const double *p) {
     const double2 b = *reinterpret_cast<const double2 *>(p + 2);
     return float4{(float)a.x, (float)a.y, (float)b.x, (float)b.y};
 }
-__device__ __forceinline__ double dot4(const float *p, const float4 &v) {
-    const float4 a = *reinterpret_cast<const float4 *>(p);
-    return (double)a.x * v.x + (double)a.y * v.y + (double)a.z * v.z + (double)a.w * v.w;
-}
-__device__ __forceinline__ double dot4(const double *p, const float4 &v) {
-    const double2 a = *reinterpret_cast<const double2 *>(p);
-    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
-    return a.x * v.x + a.y * v.y + b.x * v.z + b.y * v.w;
-}
 
-template <int AX, int MODE, typename TIN, typename TR, bool RZ, int PC, bool SLO, bool OCC2 = false>
-__global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *units, int nunits, int npmax,
+// TR (the solve's residual type) only names the instantiation per precision.
+// RZ (z pass): r.z partial sums from the spectral coefficients.  PO (last
+// pass): write p = z + beta p_old as described by po.  NPM (one block per
+// compute unit): the longest padded axis the instantiation serves; it sizes
+// the register buffers and accumulator tiles.
+template <int AX, int MODE, typename TIN, typename TR, bool RZ, int PC, bool SLO, bool OCC2 = false,
+          bool PO = false, int NPM = (PC == 128 ? 128 : 256)>
+__global__ __launch_bounds__(kFT, OCC2 ? 4 : 2) void k_dst_fast(const Item *units, int nunits, int npmax,
                                                   const OrbDesc *orb, const int *done,
                                                   const float *tab, const TIN *in, float *out,
-                                                  const TR *rres, double *rz, int *cnt) {
+                                                  double *rz, PcgOut po, int *cnt) {
+    static_assert(!RZ || MODE == 1, "r.z comes from the z pass");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     // persistent: block b streams the units [u0, u1) (unit = orbital, panel);
     // the LDS layout is sized for the largest axis of the batch
@@ -323,7 +156,8 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
     // OCC2 (two blocks per compute unit, np * PC <= kNVZ * kFT): one register
     // buffer and no prefetch inside the block; the other resident block
     // overlaps its memory traffic with this one's products
-    constexpr int NV = OCC2 ? kNVZ : kFV;
+    constexpr int NV = OCC2 ? kNVZ : NPM * PC / kFT;
+    static_assert(OCC2 || (NPM * PC % (4 * kFT) == 0 && NV <= kFV), "panel values per thread");
     // panel loads into v[NV]: thread t holds column c_ld and, per i, either
     // rows k = 2 kg + 2 G i, k + 1 (pairs) or k = 4 kg + 4 G i .. + 3 (x vectors)
     const int c_ld = AX == 0 ? (t / G) : (t % PC);
@@ -388,7 +222,7 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
     constexpr int NCT = PC / 16;
     constexpr int RS = (kFT / 64) / NCT;
     const int ct = w % NCT, r0 = w / NCT;
-    constexpr int MT = OCC2 ? 4 : 8;  // row tiles per wave: np / 16 / RS <= MT
+    constexpr int MT = OCC2 ? 4 : NPM / 16 / RS;  // row tiles per wave: np / 16 / RS <= MT
     const int lr = lane & 15, lq = lane >> 4;
     flt4 acc[MT];
     auto gemm = [&](int np) {
@@ -417,6 +251,8 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
 
     float *gzs = reinterpret_cast<float *>(sred + 16);  // eigenvalue symbol of the staged z length
     int staged = -1;  // axis length whose sine matrix is in LDS
+    int borb = -1;    // orbital whose beta is in `beta` (PO)
+    float beta = 0.f;
     // one unit: products of the panel held in v; the unit `pf` (or u1: none)
     // is loaded into v once its values are in LDS
     auto unit = [&](float (&v)[NV], int u, OrbDesc &od, int pf) {
@@ -425,7 +261,20 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
         const int n = axis_n(oc, AX);
         const int np = (n + 31) & ~31;
         if (cnt && cur.tile == 0 && t == 0) cnt[cur.orb] += 1;
-        __syncthreads();  // the previous unit's products are done with S and Xt
+        lds_barrier();  // the previous unit's products are done with S and Xt
+        if constexpr (PO) {
+            if (!po.first && cur.orb != borb) {  // uniform: the whole block takes it
+                double a = 0.0, b = 0.0;
+                for (int i = t; i < oc.nt9; i += kFT) {
+                    a += po.rzc[oc.base9 + i];
+                    b += po.rzp[oc.base9 + i];
+                }
+                a = block_sum_fast(a, sred);
+                b = block_sum_fast(b, sred);
+                beta = b != 0.0 ? (float)(a / b) : 0.f;
+                borb = cur.orb;
+            }
+        }
         if (n != staged) {
             const float *S = tab + oc.dst_s[AX];  // np x np, zero beyond n
             for (int e = t; e < np * np; e += kFT) {
@@ -440,7 +289,7 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
             staged = n;
         }
         to_lds(v, oc);
-        __syncthreads();
+        lds_barrier();
         if (pf < u1) {  // two units ahead: in flight during this unit and the next
             od = orb[units[pf].orb];
             load(v, od, units[pf].tile);
@@ -458,7 +307,7 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
             const float ih2 = (float)oc.inv_h2;
             const int jy = cv ? (int)(cg / oc.nx) : 0, jx = cv ? (int)(cg - (long long)jy * oc.nx) : 0;
             const float gxy = cv ? gx[jx] + gy[jy] : 1.f;
-            __syncthreads();  // every wave is done reading Xt
+            lds_barrier();  // every wave is done reading Xt
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
                 const int rt = r0 + RS * i;
@@ -477,7 +326,7 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
                     *reinterpret_cast<bf4 *>(Xlo + c * sw + m0) = bf4{ll[0], ll[1], ll[2], ll[3]};
                 }
             }
-            __syncthreads();
+            lds_barrier();
             gemm(np);
         }
         if (cv) {
@@ -491,9 +340,13 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
                     const int m0 = rt * 16 + 4 * lq;
                     if (vec) {
                         if (m0 < n) {  // n % 4 == 0: all four rows are in range
-                            const float4 q = float4{acc[i][0], acc[i][1], acc[i][2], acc[i][3]};
+                            float4 q = float4{acc[i][0], acc[i][1], acc[i][2], acc[i][3]};
+                            if (PO && !po.first) {
+                                const float4 o = ld4(po.pold + eo + m0);
+                                q = float4{q.x + beta * o.x, q.y + beta * o.y, q.z + beta * o.z,
+                                           q.w + beta * o.w};
+                            }
                             *reinterpret_cast<float4 *>(out + eo + m0) = q;
-                            if (RZ && MODE == 0) part += dot4(rres + eo + m0, q);
                         }
                     } else {
 #pragma unroll
@@ -501,8 +354,7 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
                             const int m = m0 + j;
                             if (m < n) {
                                 const long long a = eo + (long long)m * ks;
-                                out[a] = acc[i][j];
-                                if (RZ && MODE == 0) part += (double)rres[a] * (double)acc[i][j];
+                                out[a] = (PO && !po.first) ? acc[i][j] + beta * po.pold[a] : acc[i][j];
                             }
                         }
                     }
@@ -516,6 +368,9 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_fast(const Item *unit
     };
 
     if constexpr (OCC2) {
+        // one register buffer; the other resident block overlaps its memory
+        // traffic with this one's products (a prefetch into this buffer
+        // during the products measured no faster and spills)
         float v[NV];
         for (int q = next_active(u0); q < u1; q = next_active(q + 1)) {
             OrbDesc o = orb[units[q].orb];
@@ -586,11 +441,14 @@ size_t dst_xy_lds(int np, bool two) {
 }
 
 // TR (the solve's residual type) only names the instantiation per precision.
-template <bool VEC, typename TIN, typename TR, bool OCC2>
-__global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units, int nunits, int npmax, int two,
+// PO: write p = z + beta p_old as described by po (the inverse pass).  PV
+// (with PO): load this lane's p_old values before the products instead of at
+// the store.
+template <bool VEC, typename TIN, typename TR, bool OCC2, bool PO = false, bool PV = false>
+__global__ __launch_bounds__(kFT, OCC2 ? 4 : 2) void k_dst_xy(const Item *units, int nunits, int npmax, int two,
                                                                const OrbDesc *orb, const int *done,
                                                                const float *tab, const TIN *in, float *out,
-                                                               int *cnt) {
+                                                               PcgOut po, int *cnt) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int sw = npmax + 8;  // LDS row stride (bf16): 16-byte rows
     __bf16 *Xhi = reinterpret_cast<__bf16 *>(smem);
@@ -713,6 +571,8 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units,
     };
 
     int sx_n = -1, sy_n = -1;  // axis lengths whose sine matrices are in LDS
+    int borb = -1;             // orbital whose beta is in `beta` (PO)
+    float beta = 0.f;
     auto stage_s = [&](__bf16 *Sh, __bf16 *Sl, const float *S, int np) {
         for (int e = t; e < np * np; e += kFT) {
             const int m = e / np, k = e - m * np;
@@ -730,7 +590,20 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units,
         const int bc = npx >> 5;
         const bool act = rb < (npy >> 5);
         if (cnt && cur.tile == 0 && t == 0) cnt[cur.orb] += 1;
-        __syncthreads();  // the previous unit's products are done with S and X
+        lds_barrier();  // the previous unit's products are done with S and X
+        if constexpr (PO) {
+            if (!po.first && cur.orb != borb) {  // uniform: the whole block takes it
+                double a = 0.0, b = 0.0;
+                for (int i = t; i < oc.nt9; i += kFT) {
+                    a += po.rzc[oc.base9 + i];
+                    b += po.rzp[oc.base9 + i];
+                }
+                a = block_sum_fast(a, sred);
+                b = block_sum_fast(b, sred);
+                beta = b != 0.0 ? (float)(a / b) : 0.f;
+                borb = cur.orb;
+            }
+        }
         if (nx != sx_n || (two && ny != sy_n)) {
             stage_s(Sxh, Sxl, tab + oc.dst_s[0], npx);
             if (two) stage_s(Syh, Syl, tab + oc.dst_s[1], npy);
@@ -738,15 +611,30 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units,
             sy_n = ny;
         }
         to_lds(v, oc);
-        __syncthreads();
+        lds_barrier();
         if (pf < u1) {  // two units ahead: in flight during this unit and the next
             od = orb[units[pf].orb];
             load(v, od, units[pf].tile);
         }
         const long long base = oc.off + (long long)cur.tile * nx * ny;
+        // PO: p_old at this lane's output nodes, loaded now so the loads are
+        // in flight during both products
+        float pv[2][BC][4];
+        if (PO && PV && !po.first && act) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < BC; ++c)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int x = cb * 16 * bc + 16 * c + lr;
+                        const int y = 32 * rb + 16 * r + 4 * lq + j;
+                        pv[r][c][j] = (c < bc && x < nx && y < ny) ? po.pold[base + (long long)y * nx + x] : 0.f;
+                    }
+        }
         // C1 = P Sx: rows y, columns x
         if (act) gemm(Xhi, Xlo, Sxh, Sxl, npx, bc);
-        __syncthreads();  // every wave is done reading P
+        lds_barrier();  // every wave is done reading P
         if (act) {
 #pragma unroll
             for (int r = 0; r < 2; ++r)
@@ -763,7 +651,7 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units,
                     }
                 }
         }
-        __syncthreads();
+        lds_barrier();
         // C2 = Sy C1: rows y, columns x (B = C1t)
         if (act) gemm(Syh, Syl, Xhi, Xlo, npy, bc);
         if (act) {
@@ -778,7 +666,9 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units,
                             const int y = 32 * rb + 16 * r + 4 * lq + j;
                             if (y < ny) {
                                 const long long a = base + (long long)y * nx + x;
-                                out[a] = acc[r][c][j];
+                                float o = 0.f;
+                                if (PO && !po.first) o = PV ? pv[r][c][j] : po.pold[a];  // (PV: loaded early)
+                                out[a] = (PO && !po.first) ? acc[r][c][j] + beta * o : acc[r][c][j];
                             }
                         }
                     }
@@ -787,6 +677,9 @@ __global__ __launch_bounds__(kFT, OCC2 ? 2 : 1) void k_dst_xy(const Item *units,
     };
 
     if constexpr (OCC2) {
+        // one register buffer; the other resident block overlaps its memory
+        // traffic with this one's products (a prefetch into this buffer
+        // during the products measured no faster and spills)
         float v[NV];
         for (int q = next_active(u0); q < u1; q = next_active(q + 1)) {
             OrbDesc o = orb[units[q].orb];
@@ -822,87 +715,117 @@ void set_lds_limit(K kern, size_t bytes) {
     if (bytes > 65536) hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+namespace {
+
+// inverse pass (PO): read p_old before the products where registers allow
+// (FSIC_DST_PV=0 reads it at the store)
+bool dst_early_pold() {
+    static const bool v = [] {
+        const char *e = getenv("FSIC_DST_PV");
+        return !(e && atoi(e) == 0);
+    }();
+    return v;
+}
+
+// The passes of one preconditioner application.  T: type of r; PO: the last
+// pass writes p = z + beta p_old (po) into `out` instead of z.
+template <typename T, bool PO>
+hipError_t dst_apply(const DstItems &di, const OrbDesc *orb, const int *done, const float *tab,
+                     const T *r, float *work, float *out, double *rz, const PcgOut &po, int *cnt,
+                     hipStream_t s) {
+    if (di.nx <= 0 && di.nxy <= 0) return hipSuccess;
+    if (!di.fast) return hipErrorInvalidValue;  // the host solves such batches without it
+    const float *wk = work;
+    int *nc = nullptr;
+    const PcgOut none{nullptr, nullptr, nullptr, 1};
+    const bool pv = dst_early_pold();
+    auto grid = [&](int units) { return dim3((unsigned)std::min(units, di.blocks)); };
+#define FSIC_DST_FAST(PC_, SLO_, NPM_)                                                                \
+    do {                                                                                              \
+        const size_t lds = dst_fast_lds(di.np, PC_, SLO_);                                            \
+        const size_t lz = dst_fast_lds(di.np, 64, SLO_);                                              \
+        hipLaunchKernelGGL((k_dst_fast<0, 0, T, T, false, PC_, SLO_, false, false, NPM_>), grid(di.nx), \
+                           dim3(kFT), lds, s, di.x, di.nx, di.np, orb, done, tab, r, work, nullptr,    \
+                           none, cnt);                                                                 \
+        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false, PC_, SLO_, false, false, NPM_>),          \
+                           grid(di.ny), dim3(kFT), lds, s, di.y, di.ny, di.np, orb, done, tab, wk,     \
+                           work, nullptr, none, nc);                                                   \
+        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, 64, SLO_, false, false, NPM_>),            \
+                           grid(di.nz), dim3(kFT), lz, s, di.z, di.nz, di.np, orb, done, tab, wk, work, \
+                           rz, none, nc);                                                              \
+        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false, PC_, SLO_, false, false, NPM_>),          \
+                           grid(di.ny), dim3(kFT), lds, s, di.y, di.ny, di.np, orb, done, tab, wk,     \
+                           work, nullptr, none, nc);                                                   \
+        hipLaunchKernelGGL((k_dst_fast<0, 0, float, T, false, PC_, SLO_, false, PO, NPM_>), grid(di.nx), \
+                           dim3(kFT), lds, s, di.x, di.nx, di.np, orb, done, tab, wk, out, nullptr,    \
+                           po, nc);                                                                    \
+    } while (0)
+#define FSIC_DST_XY(SLO_, NPM_)                                                                       \
+    do {                                                                                              \
+        const size_t lxy = dst_xy_lds(di.npxy, di.two != 0);                                          \
+        const size_t lz = dst_fast_lds(di.np, 64, SLO_);                                              \
+        const bool o2 = di.xyvec && dst_xy_occ2(di.npxy, di.two != 0);                                \
+        const dim3 gxy = o2 ? dim3((unsigned)std::min(di.nxy, 2 * di.blocks)) : grid(di.nxy);         \
+        if (o2)                                                                                       \
+            hipLaunchKernelGGL((k_dst_xy<true, T, T, true>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,   \
+                               di.npxy, di.two, orb, done, tab, r, work, none, cnt);                  \
+        else if (di.xyvec)                                                                            \
+            hipLaunchKernelGGL((k_dst_xy<true, T, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,  \
+                               di.npxy, di.two, orb, done, tab, r, work, none, cnt);                  \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_dst_xy<false, T, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy, \
+                               di.npxy, di.two, orb, done, tab, r, work, none, cnt);                  \
+        if (di.zocc2)                                                                                 \
+            hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, 64, true, true>),                    \
+                               dim3((unsigned)std::min(di.nz, 2 * di.blocks)), dim3(kFT),              \
+                               dst_fast_lds(di.np, 64, true), s, di.z, di.nz, di.np, orb, done, tab,   \
+                               wk, work, rz, none, nc);                                                \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, 64, SLO_, false, false, NPM_>),       \
+                               grid(di.nz), dim3(kFT), lz, s, di.z, di.nz, di.np, orb, done, tab, wk,  \
+                               work, rz, none, nc);                                                    \
+        if (o2 && pv)                                                                                 \
+            hipLaunchKernelGGL((k_dst_xy<true, float, T, true, PO, PO>), gxy, dim3(kFT), lxy, s, di.xy, \
+                               di.nxy, di.npxy, di.two, orb, done, tab, wk, out, po, nc);             \
+        else if (o2)                                                                                  \
+            hipLaunchKernelGGL((k_dst_xy<true, float, T, true, PO>), gxy, dim3(kFT), lxy, s, di.xy,   \
+                               di.nxy, di.npxy, di.two, orb, done, tab, wk, out, po, nc);             \
+        else if (di.xyvec)                                                                            \
+            hipLaunchKernelGGL((k_dst_xy<true, float, T, false, PO, PO>), gxy, dim3(kFT), lxy, s,     \
+                               di.xy, di.nxy, di.npxy, di.two, orb, done, tab, wk, out, po, nc);      \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_dst_xy<false, float, T, false, PO>), gxy, dim3(kFT), lxy, s, di.xy, \
+                               di.nxy, di.npxy, di.two, orb, done, tab, wk, out, po, nc);             \
+    } while (0)
+    // the longest padded axis of each variant (kDstNpm) sizes its kernels
+    if (di.nxy > 0) {
+        if (di.fast == 1) FSIC_DST_XY(true, 128);
+        else if (di.fast == 2) FSIC_DST_XY(true, 160);
+        else FSIC_DST_XY(false, 192);
+    } else if (di.fast == 1) FSIC_DST_FAST(128, true, 128);
+    else if (di.fast == 2) FSIC_DST_FAST(64, true, 160);
+    else FSIC_DST_FAST(64, false, 192);
+#undef FSIC_DST_FAST
+#undef FSIC_DST_XY
+    return hipGetLastError();
+}
+
+}  // namespace
+
 // z = M^{-1} r for the orbitals of the batch, with r.z partial sums.
 template <typename T>
 hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int *done,
                               const float *tab, const T *r, float *work, float *z, double *rz,
                               int *cnt, hipStream_t s) {
-    if (di.nx <= 0 && di.nxy <= 0) return hipSuccess;
-    const float *wk = work;
-    const T *nr = nullptr;
-    double *nd = nullptr;
-    int *nc = nullptr;
-    if (di.fast) {
-        auto grid = [&](int units) { return dim3((unsigned)std::min(units, di.blocks)); };
-#define FSIC_DST_FAST(PC_, SLO_)                                                                   \
-    do {                                                                                           \
-        const size_t lds = dst_fast_lds(di.np, PC_, SLO_);                                         \
-        hipLaunchKernelGGL((k_dst_fast<0, 0, T, T, false, PC_, SLO_>), grid(di.nx), dim3(kFT),      \
-                           lds, s, di.x, di.nx, di.np, orb, done, tab, r, work, nr, nd, cnt);        \
-        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false, PC_, SLO_>), grid(di.ny), dim3(kFT),  \
-                           lds, s, di.y, di.ny, di.np, orb, done, tab, wk, work, nr, nd, nc);        \
-        hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, false, PC_, SLO_>), grid(di.nz), dim3(kFT),  \
-                           lds, s, di.z, di.nz, di.np, orb, done, tab, wk, work, nr, nd, nc);        \
-        hipLaunchKernelGGL((k_dst_fast<1, 0, float, T, false, PC_, SLO_>), grid(di.ny), dim3(kFT),  \
-                           lds, s, di.y, di.ny, di.np, orb, done, tab, wk, work, nr, nd, nc);        \
-        hipLaunchKernelGGL((k_dst_fast<0, 0, float, T, true, PC_, SLO_>), grid(di.nx), dim3(kFT),   \
-                           lds, s, di.x, di.nx, di.np, orb, done, tab, wk, z, r, rz, nc);            \
-    } while (0)
-#define FSIC_DST_XY(PC_, SLO_)                                                                     \
-    do {                                                                                           \
-        const size_t lxy = dst_xy_lds(di.npxy, di.two != 0);                                       \
-        const size_t lz = dst_fast_lds(di.np, PC_, SLO_);                                          \
-        const bool o2 = di.xyvec && dst_xy_occ2(di.npxy, di.two != 0);                             \
-        const dim3 gxy = o2 ? dim3((unsigned)std::min(di.nxy, 2 * di.blocks)) : grid(di.nxy);      \
-        if (o2)                                                                                    \
-            hipLaunchKernelGGL((k_dst_xy<true, T, T, true>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,    \
-                               di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
-        else if (di.xyvec)                                                                         \
-            hipLaunchKernelGGL((k_dst_xy<true, T, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,   \
-                               di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
-        else                                                                                       \
-            hipLaunchKernelGGL((k_dst_xy<false, T, T, false>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,  \
-                               di.npxy, di.two, orb, done, tab, r, work, cnt);                      \
-        if (di.zocc2)                                                                              \
-            hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, 64, true, true>),                 \
-                               dim3((unsigned)std::min(di.nz, 2 * di.blocks)), dim3(kFT),           \
-                               dst_fast_lds(di.np, 64, true), s, di.z, di.nz, di.np, orb, done, tab, \
-                               wk, work, r, rz, nc);                                                \
-        else                                                                                       \
-            hipLaunchKernelGGL((k_dst_fast<2, 1, float, T, true, PC_, SLO_>), grid(di.nz), dim3(kFT), \
-                               lz, s, di.z, di.nz, di.np, orb, done, tab, wk, work, r, rz, nc);      \
-        if (o2)                                                                                    \
-            hipLaunchKernelGGL((k_dst_xy<true, float, T, true>), gxy, dim3(kFT), lxy, s, di.xy,        \
-                               di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
-        else if (di.xyvec)                                                                         \
-            hipLaunchKernelGGL((k_dst_xy<true, float, T, false>), gxy, dim3(kFT), lxy, s, di.xy,       \
-                               di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
-        else                                                                                       \
-            hipLaunchKernelGGL((k_dst_xy<false, float, T, false>), gxy, dim3(kFT), lxy, s, di.xy,      \
-                               di.nxy, di.npxy, di.two, orb, done, tab, wk, z, nc);                 \
-    } while (0)
-        if (di.nxy > 0) {
-            if (di.fast == 1) FSIC_DST_XY(128, true);
-            else if (di.fast == 2) FSIC_DST_XY(64, true);
-            else FSIC_DST_XY(64, false);
-        } else if (di.fast == 1) FSIC_DST_FAST(128, true);
-        else if (di.fast == 2) FSIC_DST_FAST(64, true);
-        else FSIC_DST_FAST(64, false);
-#undef FSIC_DST_FAST
-#undef FSIC_DST_XY
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_dst_pass<0, 0, T, T, false>), dim3(di.nx), dim3(256), 0, s, di.x, orb,
-                       done, tab, r, work, nr, nd, cnt);
-    hipLaunchKernelGGL((k_dst_pass<1, 0, float, T, false>), dim3(di.ny), dim3(256), 0, s, di.y,
-                       orb, done, tab, wk, work, nr, nd, nc);
-    hipLaunchKernelGGL((k_dst_pass<2, 1, float, T, false>), dim3(di.nz), dim3(256), 0, s, di.z,
-                       orb, done, tab, wk, work, nr, nd, nc);
-    hipLaunchKernelGGL((k_dst_pass<1, 0, float, T, false>), dim3(di.ny), dim3(256), 0, s, di.y,
-                       orb, done, tab, wk, work, nr, nd, nc);
-    hipLaunchKernelGGL((k_dst_pass<0, 0, float, T, true>), dim3(di.nx), dim3(256), 0, s, di.x,
-                       orb, done, tab, wk, z, r, rz, nc);
-    return hipGetLastError();
+    return dst_apply<T, false>(di, orb, done, tab, r, work, z, rz, PcgOut{nullptr, nullptr, nullptr, 1},
+                               cnt, s);
+}
+
+// p = M^{-1} r + beta p_old for the orbitals of the batch, with r.z partial sums.
+hipError_t launch_dst_pcg(const DstItems &di, const OrbDesc *orb, const int *done, const float *tab,
+                          const float *r, float *work, float *p, double *rz, const PcgOut &po, int *cnt,
+                          hipStream_t s) {
+    return dst_apply<float, true>(di, orb, done, tab, r, work, p, rz, po, cnt, s);
 }
 
 // raise the dynamic-LDS limit of the fast transform kernels (once per batch,
@@ -916,33 +839,36 @@ hipError_t dst_setup(int np, int variant, int npxy, bool two) {
         set_lds_limit(k_dst_xy<false, float, float, false>, lxy);
         set_lds_limit(k_dst_xy<false, double, double, false>, lxy);
         set_lds_limit(k_dst_xy<false, float, double, false>, lxy);
+        set_lds_limit(k_dst_xy<true, float, float, false, true, true>, lxy);
+        set_lds_limit(k_dst_xy<true, float, float, false, true, false>, lxy);
+        set_lds_limit(k_dst_xy<false, float, float, false, true>, lxy);
         if (dst_xy_occ2(npxy, two)) {
             set_lds_limit(k_dst_xy<true, float, float, true>, lxy);
             set_lds_limit(k_dst_xy<true, double, double, true>, lxy);
             set_lds_limit(k_dst_xy<true, float, double, true>, lxy);
+            set_lds_limit(k_dst_xy<true, float, float, true, true>, lxy);
+            set_lds_limit(k_dst_xy<true, float, float, true, true, true>, lxy);
         }
         if (dst_z_occ2(np)) {
             set_lds_limit(k_dst_fast<2, 1, float, float, true, 64, true, true>, dst_fast_lds(np, 64, true));
             set_lds_limit(k_dst_fast<2, 1, float, double, true, 64, true, true>, dst_fast_lds(np, 64, true));
         }
     }
-#define FSIC_DST_LIMITS(PC_, SLO_)                                                      \
-    do {                                                                                \
-        const size_t lds = dst_fast_lds(np, PC_, SLO_);                                 \
-        set_lds_limit(k_dst_fast<0, 0, float, float, false, PC_, SLO_>, lds);           \
-        set_lds_limit(k_dst_fast<0, 0, double, double, false, PC_, SLO_>, lds);         \
-        set_lds_limit(k_dst_fast<1, 0, float, float, false, PC_, SLO_>, lds);           \
-        set_lds_limit(k_dst_fast<1, 0, float, double, false, PC_, SLO_>, lds);          \
-        set_lds_limit(k_dst_fast<2, 1, float, float, false, PC_, SLO_>, lds);           \
-        set_lds_limit(k_dst_fast<2, 1, float, double, false, PC_, SLO_>, lds);          \
-        set_lds_limit(k_dst_fast<2, 1, float, float, true, PC_, SLO_>, lds);            \
-        set_lds_limit(k_dst_fast<2, 1, float, double, true, PC_, SLO_>, lds);           \
-        set_lds_limit(k_dst_fast<0, 0, float, float, true, PC_, SLO_>, lds);            \
-        set_lds_limit(k_dst_fast<0, 0, float, double, true, PC_, SLO_>, lds);           \
+#define FSIC_DST_LIMITS(PC_, SLO_, NPM_)                                                                  \
+    do {                                                                                                  \
+        const size_t lds = dst_fast_lds(np, PC_, SLO_), lz = dst_fast_lds(np, 64, SLO_);                  \
+        set_lds_limit(k_dst_fast<0, 0, float, float, false, PC_, SLO_, false, false, NPM_>, lds);         \
+        set_lds_limit(k_dst_fast<0, 0, double, double, false, PC_, SLO_, false, false, NPM_>, lds);       \
+        set_lds_limit(k_dst_fast<1, 0, float, float, false, PC_, SLO_, false, false, NPM_>, lds);         \
+        set_lds_limit(k_dst_fast<1, 0, float, double, false, PC_, SLO_, false, false, NPM_>, lds);        \
+        set_lds_limit(k_dst_fast<2, 1, float, float, true, 64, SLO_, false, false, NPM_>, lz);            \
+        set_lds_limit(k_dst_fast<2, 1, float, double, true, 64, SLO_, false, false, NPM_>, lz);           \
+        set_lds_limit(k_dst_fast<0, 0, float, float, false, PC_, SLO_, false, true, NPM_>, lds);          \
+        set_lds_limit(k_dst_fast<0, 0, float, double, false, PC_, SLO_, false, false, NPM_>, lds);        \
     } while (0)
-    if (variant == 1) FSIC_DST_LIMITS(128, true);
-    else if (variant == 2) FSIC_DST_LIMITS(64, true);
-    else if (variant == 3) FSIC_DST_LIMITS(64, false);
+    if (variant == 1) FSIC_DST_LIMITS(128, true, 128);
+    else if (variant == 2) FSIC_DST_LIMITS(64, true, 160);
+    else if (variant == 3) FSIC_DST_LIMITS(64, false, 192);
 #undef FSIC_DST_LIMITS
     return hipGetLastError();
 }

@@ -36,6 +36,7 @@ struct CGIter {
     int tot9;
     T *Q;               // K p
     T *X;               // solution (FP64 path) or FP32 correction (mixed path)
+    const double *B64;  // right-hand side (mixed restart cycles' residual pass)
     double *part7;      // [3*tot7] p.q, r.q and q.q partial sums of the sweep (three blocks of tot7)
     int tot7;
     double *part8;      // [2*tot8] r.r partial sums, by iteration parity
@@ -46,6 +47,7 @@ struct CGIter {
     int *rs_iter;       // per orbital: iteration that restarts CG from the FP64 residual (or null)
     int *nact;          // per orbital: active sweeps [norb] then active updates [norb]
     int *nsamp;         // same layout for the profiled launches only (null: not profiled)
+    int *ndone;         // orbitals marked converged (counted once each), or null
     int norb;
     double *rrfin;      // per orbital: residual norm^2 at convergence
     const double *bb;   // per orbital: ||b||^2
@@ -81,6 +83,40 @@ hipError_t launch_pcg_stencil(int radius, const Coeffs &c, const CGIter<T> &a, i
 template <typename T>
 hipError_t launch_pcg_update(const CGIter<T> &a, int k, int x_first, hipStream_t s);
 
+// Mixed-precision preconditioned CG (restart cycles of FP32 iterations
+// checked on the FP64 residual).  Sweep of iteration k: q_k = -L p_k with the
+// p_k.q_k partials in part7 slice (k & 1); p_k was formed by the last
+// preconditioner pass.
+hipError_t launch_pcg_sweep(int radius, const Coeffs &c, const CGIter<float> &a, int k, hipStream_t s);
+
+// Update after the sweep of iteration k: alpha_k = r_k.z_k / p_k.q_k,
+// r_{k+1} = r_k - alpha_k q_k; xmode 1: x = alpha_k p_k, 2: x += alpha_k p_k
+// (0: x untouched; the residual pass adds the last steps itself).
+hipError_t launch_pcg_rupdate(const CGIter<float> &a, int k, int xmode, hipStream_t s);
+
+// FP64 residual of x = x64 + x32 + alpha_a p_a + alpha_b p_b at the end of a
+// restart cycle (alpha_j = r_j.z_j / p_j.q_j from the partials of
+// iterations ka and kb, p_a and p_b the FP32 directions of those
+// iterations): res = b + L x; writes xnew = x, r32 = (float) res and the
+// res.res partials.  Null x64 (x32) stands for zero.  Orbitals with
+// done == 1 are skipped.
+struct ResStep {
+    const double *X64;
+    const float *X32;
+    const float *Pa, *Pb;
+    int ka, kb;
+    double *X64new;
+    float *R32;
+};
+hipError_t launch_res_steps(int radius, const Coeffs &c, const CGIter<float> &a, const ResStep &rs,
+                            hipStream_t s);
+
+// Final x of the mixed restart cycles: X[o] = Xb[o] for the orbitals whose
+// result is in the second buffer (fin[o] == 1, or fallback == 1 where
+// fin[o] < 0: not converged).
+hipError_t launch_take_x(int nitems8, const Item *items8, const OrbDesc *orb, const int *fin, int fallback,
+                         double *X, const double *Xb, hipStream_t s);
+
 // FP64 residual of x64 (+ x32): res = b + L (x64 + x32); writes x64new =
 // x64 + x32, r32 = (float) res (if r32 != null), res.res partials.  With
 // x32, a null x64 stands for x64 = 0 (the first restart of a mixed solve).
@@ -93,10 +129,11 @@ hipError_t launch_true_residual(int radius, const Coeffs &c, const Item *items7,
 hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDesc *orb,
                                    const int *done, double *X64, const float *X32, hipStream_t s);
 
-// mixed precision: mark orbitals whose FP64 residual (partRU) meets tol
+// mixed precision: mark orbitals whose FP64 residual (partRU) meets tol;
+// counts them in *ndone (if not null) and stores xfin in fin[o] (if not null)
 hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
                            double tol2, int k, int *done, int *iters, double *rrfin, int *rs_iter,
-                           hipStream_t s);
+                           int *ndone, int *fin, int xfin, hipStream_t s);
 
 // per orbital: out[o] = sum of partials (stencil layout if stencil_layout,
 // else pointwise slot range starting at the parity-0 block)
@@ -165,6 +202,12 @@ template <typename T>
 hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int *done,
                               const float *tab, const T *r, float *work, float *z, double *rz,
                               int *cnt, hipStream_t s);
+
+// The same application for the mixed CG, whose last pass writes the next
+// search direction p = M^{-1} r + beta p_old (po) instead of z.
+hipError_t launch_dst_pcg(const DstItems &di, const OrbDesc *orb, const int *done, const float *tab,
+                          const float *r, float *work, float *p, double *rz, const PcgOut &po, int *cnt,
+                          hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // multipole.hip: Dirichlet values from a multipole expansion, right-hand side

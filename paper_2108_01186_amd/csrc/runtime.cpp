@@ -181,6 +181,19 @@ void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<It
     }
 }
 
+// one sampled launch (FSIC_PROFILE): kind 0 sweep, 1 update, 2 preconditioner,
+// 3 residual pass; HIP events around it
+struct ProfRec {
+    int kind, k, flag;
+    hipEvent_t a, b;
+};
+
+// what a pinned-memory upload cache remembers of the last upload of a table
+struct UpCache {
+    const void *dev = nullptr;
+    std::vector<char> bytes;
+};
+
 }  // namespace
 
 struct fsic_ctx {
@@ -215,11 +228,34 @@ struct fsic_ctx {
     DBuf<int> status;
     DBuf<double> bmat;
     int *h_done = nullptr;  // pinned
+    DBuf<int> ndone, fin;   // converged-orbital counter; buffer holding each final x (mixed PCG)
+    int *h_nd = nullptr;    // pinned: two copies of the counter, one per cycle parity
+    hipEvent_t evc[2] = {nullptr, nullptr};
+    int pred_cycles = 0;    // restart cycles the last mixed solve needed (host checks skipped before)
+    // statistics of the last solve, copied to pinned memory and read after
+    // the caller's synchronisation (finish_solve)
+    int *h_si = nullptr;     // [7 norb]: iters, then the six nact blocks
+    double *h_sd = nullptr;  // [2 norb]: final residual^2, ||b||^2
+    size_t h_s_cap = 0;
+    std::vector<ProfRec> recs;
+    bool pend_prof = false, pend_aar = false, pend_pcg = false, pend_mixed = false;
+    bool pend_dst_xy = false;
+    int pend_dst_fast = 0;
+    // device status word of the forward pass, copied once the Loewdin step
+    // has run; a solve stops early when it shows an error
+    int *h_stat = nullptr;
+    bool watch_status = false;
+    // pinned staging of the per-channel host checks (G, info, rho(a))
+    double *h_chk = nullptr;
+    size_t h_chk_cap = 0;
+    std::map<const void *, UpCache> upcache;  // last upload per device table
     // profiling (FSIC_PROFILE): events around every CG launch
     std::vector<hipEvent_t> ev;
     int32_t sweep_launches = 0, update_launches = 0, precond_launches = 0;
     double sweep_ms = 0, sweep_bytes = 0, update_ms = 0, update_bytes = 0;
     double precond_ms = 0, precond_bytes = 0, precond_flops = 0;
+    int32_t resid_launches = 0;
+    double resid_ms = 0, resid_bytes = 0;
     size_t h_done_cap = 0;
 
     // plan of the last forward pass (the tape)
@@ -234,7 +270,8 @@ struct fsic_ctx {
     long long shape_target = 0;
     double tune_ms = 0.0;
     // FSIC_GRAPHS: captured CG chunks, and the stream they are captured on
-    std::map<std::string, hipGraphExec_t> graphs;
+    std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+    int graph_captures = 0;  // graphs captured over the context's life (FSIC_GRAPHS)
     hipStream_t cap_stream = nullptr;
     HarmTables ht{};
 
@@ -283,7 +320,7 @@ fsic_status validate_grid(const fsic_grid &g, std::string &why) {
     }
     if (!(g.h > 0.0) || !std::isfinite(g.h)) { why = "grid spacing h must be finite and > 0"; return FSIC_EINVAL; }
     // one orbital's FP64 field must stay below 4 GiB (32-bit buffer ranges and node indices)
-    if ((long long)g.n[0] * g.n[1] * g.n[2] > (1LL << 29)) { why = "grid must have at most 2^29 nodes"; return FSIC_EINVAL; }
+    if ((long long)g.n[0] * g.n[1] * g.n[2] >= (1LL << 29)) { why = "grid must have fewer than 2^29 nodes"; return FSIC_EINVAL; }
     return FSIC_OK;
 }
 
@@ -411,9 +448,9 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     const int npx = (b.max_n + 31) & ~31;
     const size_t ldsmax = device_lds_limit();
     int variant = 0;
-    if (npx <= 128 && dst_fast_lds(npx, 128, true) <= ldsmax) variant = 1;
-    else if (npx <= 256 && dst_fast_lds(npx, 64, true) <= ldsmax) variant = 2;
-    else if (npx <= 256 && dst_fast_lds(npx, 64, false) <= ldsmax) variant = 3;
+    if (npx <= dst_variant_npmax(1) && dst_fast_lds(npx, 128, true) <= ldsmax) variant = 1;
+    else if (npx <= dst_variant_npmax(2) && dst_fast_lds(npx, 64, true) <= ldsmax) variant = 2;
+    else if (npx <= dst_variant_npmax(3) && dst_fast_lds(npx, 64, false) <= ldsmax) variant = 3;
     const bool fast = variant != 0;
     b.dst_fast = variant;
     // fused x-y passes: in-plane axes of at most 128 nodes and LDS for the
@@ -480,10 +517,9 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
                 return (int)((ncol + pc - 1) / pc);
             };
             // r.z partial slots: one per z-pass panel (the z pass forms r.z
-            // when the in-plane transforms are fused), else one per x panel
-            const int zpc = b.dst_zocc2 ? 64 : dst_panel_cols(variant);
-            od.nt9 = b.dst_xy ? (int)(((long long)g.n[0] * g.n[1] + zpc - 1) / zpc)
-                              : nitem((long long)g.n[1] * g.n[2]);
+            // from the spectral coefficients)
+            const int zpc = 64;  // z-pass panel columns (every variant)
+            od.nt9 = (int)(((long long)g.n[0] * g.n[1] + zpc - 1) / zpc);
             od.base9 = b.tot9;
             b.tot9 += od.nt9;
             for (int d = 0; d < 3; ++d) {
@@ -498,8 +534,9 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
             if (b.dst_xy) {
                 for (int z = 0; z < g.n[2]; ++z) b.dxy.push_back(Item{o, z});
             } else {
-                for (int t = 0; t < od.nt9; ++t) natx.push_back({o, t});
-                const int ny_t = fast ? nitem((long long)g.n[0] * g.n[2]) : g.n[2] * ((g.n[0] + 31) / 32);
+                const int nx_t = nitem((long long)g.n[1] * g.n[2]);  // x-pass panels
+                for (int t = 0; t < nx_t; ++t) natx.push_back({o, t});
+                const int ny_t = nitem((long long)g.n[0] * g.n[2]);
                 for (int t = 0; t < ny_t; ++t) naty.push_back({o, t});
             }
             const int nz_t = (int)(((long long)g.n[0] * g.n[1] + zpc - 1) / zpc);
@@ -509,38 +546,40 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     }
     build_items(nat7, b.items7);
     build_items(nat8, b.items8);
-    if (fast) {
-        // persistent kernels take contiguous unit ranges: keep orbital order
-        // so one sine matrix serves a whole range
-        for (auto *pr : {&natx, &naty, &natz}) {
-            std::vector<Item> &dst = pr == &natx ? b.dx : (pr == &naty ? b.dy : b.dz);
-            dst.clear();
-            for (const auto &q : *pr) dst.push_back(Item{q.first, q.second});
-        }
-    } else {
-        build_items(natx, b.dx);
-        build_items(naty, b.dy);
-        build_items(natz, b.dz);
+    // persistent kernels take contiguous unit ranges: keep orbital order so
+    // one sine matrix serves a whole range
+    for (auto *pr : {&natx, &naty, &natz}) {
+        std::vector<Item> &dst = pr == &natx ? b.dx : (pr == &naty ? b.dy : b.dz);
+        dst.clear();
+        for (const auto &q : *pr) dst.push_back(Item{q.first, q.second});
     }
 }
 
 template <typename T>
 fsic_status upload(fsic_ctx *c, DBuf<T> &d, const std::vector<T> &h) {
     HIPCHK(c, d.ensure(h.size()));
-    if (!h.empty())
-        HIPCHK(c, hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    if (h.empty()) return FSIC_OK;
+    // skip the copy when the device table already holds these bytes
+    UpCache &uc = c->upcache[&d];
+    const size_t nb = h.size() * sizeof(T);
+    if (uc.dev == d.p && uc.bytes.size() == nb && std::memcmp(uc.bytes.data(), h.data(), nb) == 0)
+        return FSIC_OK;
+    HIPCHK(c, hipMemcpyAsync(d.p, h.data(), nb, hipMemcpyHostToDevice, c->stream));
+    uc.dev = d.p;
+    uc.bytes.assign(reinterpret_cast<const char *>(h.data()), reinterpret_cast<const char *>(h.data()) + nb);
     return FSIC_OK;
 }
 
-// The spectral preconditioner serves grids of up to 256 nodes per axis;
-// larger batches are solved with plain CG.
+// The spectral preconditioner serves batches whose longest axis fits one of
+// the transform variants (about 208 nodes); larger batches are solved with
+// plain CG.
 bool use_pcg(const fsic_ctx *c, const Batch &b) {
-    return c->opts.solver == FSIC_PCG && b.max_n <= 256;
+    return c->opts.solver == FSIC_PCG && b.dst_fast != 0;
 }
 
 // AAR uses the same preconditioner, so the same limit (larger batches: plain CG)
 bool use_aar(const fsic_ctx *c, const Batch &b) {
-    return c->opts.solver == FSIC_AAR && b.max_n <= 256;
+    return c->opts.solver == FSIC_AAR && b.dst_fast != 0;
 }
 
 // Upload a batch's tables and size the solver buffers.
@@ -601,15 +640,37 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     HIPCHK(c, c->done.ensure(norb));
     HIPCHK(c, c->iters.ensure(norb));
     HIPCHK(c, c->rs_iter.ensure(norb));
-    HIPCHK(c, c->nact.ensure(5 * (size_t)norb));
+    HIPCHK(c, c->nact.ensure(6 * (size_t)norb));
+    HIPCHK(c, c->ndone.ensure(1));
+    HIPCHK(c, c->fin.ensure(norb));
+    if (!c->h_nd) HIPCHK(c, hipHostMalloc((void **)&c->h_nd, 2 * sizeof(int)));
+    for (hipEvent_t &e : c->evc)
+        if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (c->h_done_cap < (size_t)norb) {
         if (c->h_done) hipHostFree(c->h_done);
         c->h_done = nullptr;
         HIPCHK(c, hipHostMalloc((void **)&c->h_done, std::max(norb, 1) * sizeof(int)));
         c->h_done_cap = norb;
     }
+    if (c->h_s_cap < (size_t)norb) {
+        if (c->h_si) hipHostFree(c->h_si);
+        if (c->h_sd) hipHostFree(c->h_sd);
+        c->h_si = nullptr;
+        c->h_sd = nullptr;
+        HIPCHK(c, hipHostMalloc((void **)&c->h_si, 7 * (size_t)std::max(norb, 1) * sizeof(int)));
+        HIPCHK(c, hipHostMalloc((void **)&c->h_sd, 2 * (size_t)std::max(norb, 1) * sizeof(double)));
+        c->h_s_cap = norb;
+    }
+    if (!c->h_stat) {
+        HIPCHK(c, hipHostMalloc((void **)&c->h_stat, sizeof(int)));
+        *c->h_stat = 0;
+    }
     return FSIC_OK;
 }
+
+// The forward pass's device status (copied asynchronously once the
+// Loewdin step has run) shows an error: its solves need not finish.
+bool status_error(const fsic_ctx *c) { return c->watch_status && c->h_stat && *c->h_stat != 0; }
 
 struct SolveReport {
     int max_iters = 0;
@@ -762,30 +823,25 @@ fsic_status choose_shape(fsic_ctx *c, const std::vector<Group> &groups, int prec
 //   src: densities (square = 0) or orbitals (square = 1), field layout of b;
 //   with_bc: Dirichlet values from the multipole expansion (else zero);
 //   X: solution (field layout of b).
-// Key of a captured CG chunk: everything its launches depend on.
-template <typename T>
-std::string chunk_key(const fsic_ctx *c, const CGIter<T> &a, const DstItems &di, const double *X,
-                      int tag, int kstart, int kend) {
-    std::string k;
-    auto put = [&](const void *p, size_t n) { k.append(static_cast<const char *>(p), n); };
-    put(&a, sizeof(a));
-    put(&di, sizeof(di));
-    put(&X, sizeof(X));
-    put(&c->cf, sizeof(c->cf));
-    const void *ptrs[] = {c->P0.p, c->P1.p, c->P32a.p, c->P32b.p, c->T32.p, c->dtab.p, c->B.p,
-                          c->X32.p, c->R32.p, c->h_done};
-    put(ptrs, sizeof(ptrs));
-    const int ints[] = {tag, kstart, kend, c->radius, c->opts.max_iter};
-    put(ints, sizeof(ints));
-    return k;
-}
+// Key of a captured restart cycle: every kernel argument and launch shape
+// of its launches, field by field (no struct bytes, so no padding enters).
+struct GraphKey {
+    std::vector<uint64_t> v;
+    void add(const void *p) { v.push_back((uint64_t)(uintptr_t)p); }
+    void add(long long x) { v.push_back((uint64_t)x); }
+    void add(double x) {
+        uint64_t u;
+        std::memcpy(&u, &x, sizeof(u));
+        v.push_back(u);
+    }
+};
 
-// Enqueue one CG chunk on stream s: directly, or (FSIC_GRAPHS) as a graph
-// captured once per key on the context's capture stream and replayed.
+// Enqueue `body` on stream s: directly, or (graphs) replay its graph,
+// captured on the context's capture stream the first time `key` is seen.
 template <class Body>
-fsic_status run_chunk(fsic_ctx *c, bool graphs, const std::string &key, Body &body, hipStream_t s) {
+fsic_status run_captured(fsic_ctx *c, bool graphs, const GraphKey &key, Body &body, hipStream_t s) {
     if (!graphs) return body(s);
-    auto f = c->graphs.find(key);
+    auto f = c->graphs.find(key.v);
     if (f == c->graphs.end()) {
         if (c->graphs.size() >= 64) {  // bound the cache (buffers reallocated, other batches)
             for (auto &e : c->graphs) hipGraphExecDestroy(e.second);
@@ -805,7 +861,8 @@ fsic_status run_chunk(fsic_ctx *c, bool graphs, const std::string &key, Body &bo
         const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (ei != hipSuccess) return set_err(c, FSIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
-        f = c->graphs.emplace(key, ex).first;
+        f = c->graphs.emplace(key.v, ex).first;
+        c->graph_captures += 1;
     }
     HIPCHK(c, hipGraphLaunch(f->second, s));
     return FSIC_OK;
@@ -836,7 +893,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->iters.p, 0, norb * sizeof(int), s));
     HIPCHK(c, hipMemsetAsync(c->rs_iter.p, 0xff, norb * sizeof(int), s));  // -1: no restart
-    HIPCHK(c, hipMemsetAsync(c->nact.p, 0, 5 * norb * sizeof(int), s));
+    HIPCHK(c, hipMemsetAsync(c->nact.p, 0, 6 * norb * sizeof(int), s));
     const double tol2 = tol * tol;
     const int chunk = 32;
     int k = 0;
@@ -849,8 +906,8 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     const int prof_every = use_pcg(c, b) ? 2 : profile_period();
     auto sampled = [&](int kk) { return prof && kk % prof_every == prof_every - 1; };
     int *const nsamp = c->nact.p + 2 * norb;  // sampled sweeps, updates, preconditioner passes
-    struct Rec { int kind, k, flag; hipEvent_t a, b; };  // kind 0 sweep, 1 update; flag: first access
-    std::vector<Rec> recs;
+    std::vector<ProfRec> &recs = c->recs;
+    recs.clear();
     size_t evn = 0;
     auto ev_pair = [&](hipEvent_t &a, hipEvent_t &b) -> hipError_t {
         while (c->ev.size() < evn + 2) {
@@ -871,7 +928,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     if (_sp) {                                                          \
         HIPCHK(c, ev_pair(_ea, _eb));                                   \
         HIPCHK(c, hipEventRecord(_ea, s));                              \
-        recs.push_back(Rec{kind_, k_, flag_, _ea, _eb});                \
+        recs.push_back(ProfRec{kind_, k_, flag_, _ea, _eb});                \
     }
 #define PROF_END() \
     if (_sp) HIPCHK(c, hipEventRecord(_eb, s));
@@ -882,7 +939,11 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                 b.dst_xy ? c->d_dxy.p : nullptr, b.dst_xy ? (int)b.dxy.size() : 0, b.dst_two ? 1 : 0,
                 b.dst_vec ? 1 : 0, b.npxy, b.dst_zocc2 ? 1 : 0};
     if (pcg && !mixed) {
-        // FP64 CG preconditioned by the FP32 sine-transform inverse
+        // FP64 CG preconditioned by the FP32 sine-transform inverse.  The host
+        // enqueues two iterations at a time and then reads the converged-
+        // orbital counter of the pair before (one pair stays in flight), so
+        // the device never waits for the host and at most one pair of
+        // launches finds every orbital converged.
         CGIter<double> a{};
         a.items7 = c->d_items7.p; a.nitems7 = nit7;
         a.items8 = c->d_items8.p; a.nitems8 = nit8;
@@ -891,48 +952,50 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.partRZ = c->partRZ.p;
         a.tot7 = b.tot7; a.tot8 = b.tot8; a.tot9 = b.tot9;
         a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
-        a.rs_iter = nullptr; a.nact = c->nact.p; a.norb = norb;
+        a.rs_iter = nullptr; a.nact = c->nact.p; a.norb = norb; a.ndone = c->ndone.p;
         a.tol2 = tol2;
         const CGIter<double> a0 = a;
+        HIPCHK(c, hipMemsetAsync(c->ndone.p, 0, sizeof(int), s));
         HIPCHK(c, launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R, c->T32.p,
                                              a.Z, a.partRZ, nullptr, s));
-        while (k < max_iter + 1 && !all_done) {
-            const int kstart = k;
-            const int kend = std::min(k + chunk, max_iter + 1);
-            // one chunk of iterations on stream `s` (shadowing the context's)
-            auto body = [&](hipStream_t s) -> fsic_status {
-                CGIter<double> a = a0;
-                for (int k = kstart; k < kend; ++k) {
-                    a.P = (k & 1) ? c->P1.p : c->P0.p;
-                    a.Pold = (k & 1) ? c->P0.p : c->P1.p;
-                    {
-                        PROF_BEGIN(0, k, k == 0)
-                        HIPCHK(c, launch_pcg_stencil<double>(c->radius, c->cf, a, k, 0, 0, 0, s));
-                        PROF_END()
-                    }
-                    if (k < max_iter) {
-                        {
-                            PROF_BEGIN(1, k, k == 0)
-                            HIPCHK(c, launch_pcg_update<double>(a, k, k == 0, s));
-                            PROF_END()
-                        }
-                        PROF_BEGIN(2, k + 1, 0)  // z of iteration k + 1
-                        HIPCHK(c, launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
-                                                             c->T32.p, a.Z,
-                                                             a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
-                                                             _sp ? nsamp + 2 * norb : nullptr, s));
-                        PROF_END()
-                    }
+        const int pair = 2;
+        const int npairs = (max_iter + 1 + pair - 1) / pair;
+        auto issue = [&](int j) -> fsic_status {
+            CGIter<double> a = a0;
+            const int kend = std::min((j + 1) * pair, max_iter + 1);
+            for (int k = j * pair; k < kend; ++k) {
+                a.P = (k & 1) ? c->P1.p : c->P0.p;
+                a.Pold = (k & 1) ? c->P0.p : c->P1.p;
+                {
+                    PROF_BEGIN(0, k, k == 0)
+                    HIPCHK(c, launch_pcg_stencil<double>(c->radius, c->cf, a, k, 0, 0, 0, s));
+                    PROF_END()
                 }
-                HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
-                return FSIC_OK;
-            };
-            const fsic_status cs = run_chunk(c, graphs, chunk_key(c, a0, di, X, 64, kstart, kend), body, s);
-            if (cs) return cs;
-            k = kend;
-            HIPCHK(c, hipStreamSynchronize(s));
-            all_done = true;
-            for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o];
+                if (k < max_iter) {
+                    {
+                        PROF_BEGIN(1, k, k == 0)
+                        HIPCHK(c, launch_pcg_update<double>(a, k, k == 0, s));
+                        PROF_END()
+                    }
+                    PROF_BEGIN(2, k + 1, 0)  // z of iteration k + 1
+                    HIPCHK(c, launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
+                                                         c->T32.p, a.Z,
+                                                         a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
+                                                         _sp ? nsamp + 2 * norb : nullptr, s));
+                    PROF_END()
+                }
+            }
+            HIPCHK(c, hipMemcpyAsync(c->h_nd + (j & 1), c->ndone.p, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipEventRecord(c->evc[j & 1], s));
+            return FSIC_OK;
+        };
+        fsic_status ist = issue(0);
+        if (ist) return ist;
+        for (int j = 0;; ++j) {
+            const bool more = j + 1 < npairs;
+            if (more && (ist = issue(j + 1))) return ist;
+            HIPCHK(c, hipEventSynchronize(c->evc[j & 1]));
+            if (c->h_nd[j & 1] >= norb || !more || status_error(c)) break;
         }
         HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
                                        X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
@@ -947,13 +1010,13 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, c->done.p,
                                            X, nullptr, c->B.p, nullptr, c->R32.p, c->partRU.p, s));
             HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, k, c->done.p,
-                                      c->iters.p, c->rrfin.p, c->rs_iter.p, s));
+                                      c->iters.p, c->rrfin.p, c->rs_iter.p, nullptr, nullptr, 0, s));
             if (k % kAarCheck == kAarCheck - 1 || k == max_iter) {
                 HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(c, hipStreamSynchronize(s));
                 all_done = true;
                 for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o] == 1;
-                if (all_done || k == max_iter) break;
+                if (all_done || k == max_iter || status_error(c)) break;
             }
             HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, c->R32.p, c->T32.p,
                                                 c->Z32.p, c->partRZ.p, nullptr, s));
@@ -970,94 +1033,154 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                        X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
         HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
     } else if (pcg) {
-        // FP32 preconditioned CG restarted from the FP64 residual every
-        // pchunk iterations (defect correction: x64 += x32)
+        // FP32 preconditioned CG in restart cycles of `cyc` iterations, each
+        // closed by the FP64 residual of x64 plus the cycle's steps (defect
+        // correction).  Per iteration: the preconditioner's last pass forms
+        // p_k = z_k + beta p_{k-1}, the sweep q_k = -L p_k, and (between
+        // iterations) r -= alpha q; the last two steps of a cycle go straight
+        // into the residual pass, x32 holds the earlier ones (cycles of three
+        // or more).  x64 lives in two buffers: cycle j reads xs[j & 1] and
+        // writes xs[(j + 1) & 1]; an orbital's final x is in the buffer of the
+        // cycle that converged it (fin).  Convergence is decided on the FP64
+        // residual only.
         CGIter<float> a{};
         a.items7 = c->d_items7.p; a.nitems7 = nit7;
         a.items8 = c->d_items8.p; a.nitems8 = nit8;
         a.orb = c->d_orb.p;
-        a.R = c->R32.p; a.Q = c->Q32.p; a.X = c->X32.p; a.Z = c->Z32.p;
+        a.R = c->R32.p; a.Q = c->Q32.p; a.X = c->X32.p; a.Z = nullptr; a.B64 = c->B.p;
         a.part7 = c->part7.p; a.part8 = c->part8.p; a.partRU = c->partRU.p; a.partRZ = c->partRZ.p;
         a.tot7 = b.tot7; a.tot8 = b.tot8; a.tot9 = b.tot9;
         a.done = c->done.p; a.iters = c->iters.p; a.rrfin = c->rrfin.p; a.bb = c->bb.p;
-        a.rs_iter = c->rs_iter.p; a.nact = c->nact.p; a.norb = norb;
+        a.rs_iter = nullptr; a.nact = c->nact.p; a.norb = norb; a.ndone = c->ndone.p;
         a.tol2 = tol2;
-        const int pchunk = pcg_chunk(b.dst_fast);
         const CGIter<float> a0 = a;
-        int nref = 0;
-        // x64 lives in two buffers: each restart reads it from xs[cur] and its
-        // FP64 residual pass writes x64 + x32 into xs[cur ^ 1], so no separate
-        // accumulation pass runs; an orbital's final x is in the buffer of the
-        // check that converged it (fin), and is moved to X at the end
+        const int cyc = std::max(2, pcg_chunk(b.dst_fast));
+        const int ncyc = std::max(1, max_iter / cyc);
         HIPCHK(c, c->X64b.ensure((size_t)b.fields));
+        if (cyc > 2) HIPCHK(c, c->X32.ensure((size_t)b.fields));
         double *const xs[2] = {X, c->X64b.p};
-        int cur = 0;
-        std::vector<int> fin(norb, -1);
-        while (k < max_iter && !all_done) {
-            const int kstart = k;
-            const int kend = std::min(k + pchunk, max_iter);
-            double *const Xc = xs[cur], *const Xn = xs[cur ^ 1];
-            // one restart cycle on stream `s` (shadowing the context's)
-            auto body = [&](hipStream_t s) -> fsic_status {
-                CGIter<float> a = a0;
-                HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R, c->T32.p,
-                                                    a.Z, a.partRZ + (size_t)(kstart & 1) * b.tot9,
-                                                    nullptr, s));
-                for (int k = kstart; k < kend; ++k) {
-                    const int j = k - kstart;
-                    a.P = (k & 1) ? c->P32b.p : c->P32a.p;
-                    a.Pold = (k & 1) ? c->P32a.p : c->P32b.p;
+        float *const P2[2] = {c->P32a.p, c->P32b.p};
+        HIPCHK(c, hipMemsetAsync(c->ndone.p, 0, sizeof(int), s));
+        HIPCHK(c, hipMemsetAsync(c->fin.p, 0xff, norb * sizeof(int), s));
+        // cycle variant v: 0 the first (x64 = 0), 1 odd, 2 even (>= 2); the
+        // launches depend on v only (iteration indices enter by parity)
+        auto cycle = [&](hipStream_t s, int v) -> fsic_status {
+            CGIter<float> a = a0;
+            const int ks = v == 1 ? cyc & 1 : 0;  // parity of the cycle's first iteration
+            double *const Xc = v == 0 ? nullptr : xs[v == 1 ? 1 : 0];
+            double *const Xn = xs[v == 1 ? 0 : 1];
+            const bool samp = prof && v != 0;
+            for (int i = 0; i < cyc; ++i) {
+                const int k = ks + i;
+                const bool last = i == cyc - 1;
+                PcgOut po{nullptr, a.partRZ + (size_t)(k & 1) * b.tot9,
+                          a.partRZ + (size_t)((k + 1) & 1) * b.tot9, 1};
+                if (i > 0) {
+                    const int m = i - 1;  // x32 takes the steps of iterations 0 .. cyc - 3
+                    const int xmode = m <= cyc - 3 ? (m == 0 ? 1 : 2) : 0;
+                    a.P = P2[(k - 1) & 1];
                     {
-                        PROF_BEGIN(0, k, k == 0)
-                        HIPCHK(c, launch_pcg_stencil<float>(c->radius, c->cf, a, k, j == 0 && k > 0,
-                                                            j == 0, 1, s));
+                        PROF_BEGIN(1, last && samp ? 1 : 0, 0)
+                        HIPCHK(c, launch_pcg_rupdate(a, k - 1, xmode, s));
                         PROF_END()
                     }
-                    {
-                        PROF_BEGIN(1, k, j == 0)
-                        HIPCHK(c, launch_pcg_update<float>(a, k, j == 0, s));
-                        PROF_END()
-                    }
-                    if (k + 1 < kend) {
-                        PROF_BEGIN(2, k + 1, 0)  // z of iteration k + 1 (sampled with two-iteration restarts)
-                        HIPCHK(c, launch_dst_precond<float>(di, c->d_orb.p, c->done.p, c->dtab.p, a.R,
-                                                            c->T32.p, a.Z,
-                                                            a.partRZ + (size_t)((k + 1) & 1) * b.tot9,
-                                                            _sp ? nsamp + 2 * norb : nullptr, s));
-                        PROF_END()
-                    }
+                    po.pold = P2[(k - 1) & 1];
+                    po.first = 0;
                 }
-                HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p,
-                                               c->done.p, kstart == 0 ? nullptr : Xc, c->X32.p, c->B.p,
-                                               Xn, c->R32.p, c->partRU.p, s));
-                HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, kend, c->done.p,
-                                          c->iters.p, c->rrfin.p, c->rs_iter.p, s));
-                HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
-                return FSIC_OK;
-            };
-            const fsic_status cs = run_chunk(c, graphs, chunk_key(c, a0, di, Xc, 32, kstart, kend), body, s);
-            if (cs) return cs;
-            k = kend;
-            ++nref;
-            HIPCHK(c, hipStreamSynchronize(s));
-            all_done = true;
-            for (int o = 0; o < norb; ++o) {
-                if (c->h_done[o] == 1 && fin[o] < 0) fin[o] = cur ^ 1;
-                all_done = all_done && c->h_done[o] == 1;
+                {
+                    PROF_BEGIN(2, last && samp ? 1 : 0, 0)
+                    HIPCHK(c, launch_dst_pcg(di, c->d_orb.p, c->done.p, c->dtab.p, a.R, c->T32.p,
+                                             P2[k & 1], a.partRZ + (size_t)(k & 1) * b.tot9, po,
+                                             _sp ? nsamp + 2 * norb : nullptr, s));
+                    PROF_END()
+                }
+                a.P = P2[k & 1];
+                {
+                    PROF_BEGIN(0, last && samp ? 1 : 0, 0)
+                    HIPCHK(c, launch_pcg_sweep(c->radius, c->cf, a, k, s));
+                    PROF_END()
+                }
             }
-            cur ^= 1;
-        }
-        for (int o = 0; o < norb; ++o) {
-            const int loc = fin[o] >= 0 ? fin[o] : cur;  // unconverged: the latest iterate
-            if (loc == 1) {
-                const OrbDesc &od = b.orb[o];
-                const size_t bytes = (size_t)od.nx * od.ny * od.nz * sizeof(double);
-                HIPCHK(c, hipMemcpyAsync(X + od.off, c->X64b.p + od.off, bytes, hipMemcpyDeviceToDevice, s));
+            const int ka = ks + cyc - 2, kb = ks + cyc - 1;
+            ResStep rs{Xc, cyc > 2 ? c->X32.p : nullptr, P2[ka & 1], P2[kb & 1], ka, kb, Xn, c->R32.p};
+            {
+                PROF_BEGIN(3, samp ? 1 : 0, 0)
+                HIPCHK(c, launch_res_steps(c->radius, c->cf, a, rs, s));
+                PROF_END()
+            }
+            HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, 0, c->done.p,
+                                      c->iters.p, c->rrfin.p, nullptr, c->ndone.p, c->fin.p,
+                                      Xn == xs[1] ? 1 : 0, s));
+            return FSIC_OK;
+        };
+        auto issue = [&](int j) -> fsic_status {
+            const int v = j == 0 ? 0 : ((j & 1) ? 1 : 2);
+            auto body = [&](hipStream_t ss) { return cycle(ss, v); };
+            GraphKey key;
+            if (graphs) {
+                key.add((long long)v);
+                key.add((long long)cyc);
+                key.add((long long)c->radius);
+                key.add((long long)c->cf.cpt);
+                key.add((long long)c->cf.depth);
+                for (int q = 0; q <= kMaxRadius; ++q) key.add(c->cf.c[q]);
+                key.add(tol2);
+                for (const void *ptr : {(const void *)a0.items7, (const void *)a0.items8, (const void *)a0.orb,
+                                        (const void *)a0.R, (const void *)a0.Q, (const void *)a0.X,
+                                        (const void *)a0.B64, (const void *)a0.part7, (const void *)a0.part8,
+                                        (const void *)a0.partRU, (const void *)a0.partRZ,
+                                        (const void *)a0.done, (const void *)a0.iters, (const void *)a0.rrfin,
+                                        (const void *)a0.bb, (const void *)a0.nact, (const void *)a0.ndone,
+                                        (const void *)c->fin.p, (const void *)xs[0], (const void *)xs[1],
+                                        (const void *)P2[0], (const void *)P2[1], (const void *)c->T32.p,
+                                        (const void *)c->dtab.p, (const void *)di.x, (const void *)di.y,
+                                        (const void *)di.z, (const void *)di.xy})
+                    key.add(ptr);
+                for (long long q : {(long long)a0.nitems7, (long long)a0.nitems8, (long long)a0.tot7,
+                                    (long long)a0.tot8, (long long)a0.tot9, (long long)a0.norb,
+                                    (long long)di.nx, (long long)di.ny, (long long)di.nz, (long long)di.fast,
+                                    (long long)di.np, (long long)di.blocks, (long long)di.nxy,
+                                    (long long)di.two, (long long)di.xyvec, (long long)di.npxy,
+                                    (long long)di.zocc2})
+                    key.add(q);
+            }
+            fsic_status st = run_captured(c, graphs, key, body, s);
+            if (st) return st;
+            HIPCHK(c, hipMemcpyAsync(c->h_nd + (j & 1), c->ndone.p, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipEventRecord(c->evc[j & 1], s));
+            return FSIC_OK;
+        };
+        // one cycle stays in flight while the host reads the counter of the
+        // one before; the first pred_cycles - 1 cycles (the last solve's
+        // count) are not checked at all
+        int used = 0, issued = 1;
+        fsic_status ist = issue(0);
+        if (ist) return ist;
+        for (int j = 0;; ++j) {
+            const bool more = j + 1 < ncyc;
+            if (more) {
+                if ((ist = issue(j + 1))) return ist;
+                issued = j + 2;
+            }
+            if (more && j + 1 < c->pred_cycles) continue;
+            HIPCHK(c, hipEventSynchronize(c->evc[j & 1]));
+            if (c->h_nd[j & 1] >= norb || !more || status_error(c)) {
+                used = j + 1;
+                break;
             }
         }
-        rep.refinements += nref;
-        HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
-                                       X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
+        c->pred_cycles = used;
+        rep.refinements += used;
+        // move x from the second buffer where the converging cycle left it
+        // there; an unconverged orbital's latest x is where the last cycle
+        // that ran wrote it (cycle j writes buffer (j + 1) & 1; cycles up to
+        // `issued` - 1 ran)
+        HIPCHK(c, launch_take_x(nit8, c->d_items8.p, c->d_orb.p, c->fin.p, (issued & 1) ? 1 : 0, X,
+                                c->X64b.p, s));
+        // iterations that did work per orbital (the restart cycles report no index)
+        HIPCHK(c, hipMemcpyAsync(c->iters.p, c->nact.p, norb * sizeof(int), hipMemcpyDeviceToDevice, s));
+        // final FP64 residual: the residual pass of the cycle that produced each
+        // orbital's x left its partial sums in partRU (later cycles skip it)
         HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
     } else if (!mixed) {
         CGIter<double> a{};
@@ -1089,6 +1212,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             HIPCHK(c, hipStreamSynchronize(s));
             all_done = true;
             for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o];
+            if (status_error(c)) break;
         }
         // true FP64 residual of the final iterate
         HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, nullptr,
@@ -1130,12 +1254,13 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                            c->partRU.p, s));
             HIPCHK(c, launch_mixed_accumulate(nit8, c->d_items8.p, c->d_orb.p, c->done.p, X, c->X32.p, s));
             HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, k, c->done.p,
-                                      c->iters.p, c->rrfin.p, c->rs_iter.p, s));
+                                      c->iters.p, c->rrfin.p, c->rs_iter.p, nullptr, nullptr, 0, s));
             ++nref;
             HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));
             all_done = true;
             for (int o = 0; o < norb; ++o) all_done = all_done && c->h_done[o] == 1;
+            if (status_error(c)) break;
         }
         rep.refinements += nref;
         // final report: FP64 residual of x64 (x32 already folded in)
@@ -1143,18 +1268,34 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                        X, nullptr, c->B.p, nullptr, nullptr, c->partRU.p, s));
         HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
     }
-    std::vector<int> it(norb), na(5 * (size_t)norb);
-    std::vector<double> pt(norb), bbh(norb);
-    HIPCHK(c, hipMemcpyAsync(it.data(), c->iters.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(na.data(), c->nact.p, 5 * norb * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(pt.data(), c->ptrue.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(bbh.data(), c->bb.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
+    // statistics: copied now, read by finish_solve after the caller's sync
+    HIPCHK(c, hipMemcpyAsync(c->h_si, c->iters.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_si + norb, c->nact.p, 6 * norb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_sd, c->ptrue.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_sd + norb, c->bb.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    c->pend_prof = prof;
+    c->pend_aar = use_aar(c, b);
+    c->pend_pcg = pcg;
+    c->pend_mixed = mixed;
+    c->pend_dst_xy = b.dst_xy;
+    c->pend_dst_fast = b.dst_fast;
+#undef PROF_BEGIN
+#undef PROF_END
+    return FSIC_OK;
+}
+
+// Read the statistics of the last solve_batch (the caller has synchronised
+// the context's stream since) into rep, and the sampled launch times.
+fsic_status finish_solve(fsic_ctx *c, const Batch &b, SolveReport &rep) {
+    const int norb = (int)b.orb.size();
+    const int *it = c->h_si, *na = c->h_si + norb;
+    const double *pt = c->h_sd, *bbh = c->h_sd + norb;
+    const bool prof = c->pend_prof, pcg = c->pend_pcg, mixed = c->pend_mixed;
     for (int o = 0; o < norb; ++o) {
         // stencil sweeps that did work for this orbital (AAR: residual
         // evaluations before convergence)
-        const int itv = use_aar(c, b) ? it[o] : na[o];
+        const int itv = c->pend_aar ? it[o] : na[o];
         rep.max_iters = std::max(rep.max_iters, itv);
         rep.total_iters += itv;
         const double rr = bbh[o] > 0 ? std::sqrt(pt[o] / bbh[o]) : 0.0;
@@ -1168,12 +1309,13 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         // Sampled launches are never the first of a solve or of a restart of
         // x from zero.
         const double esz = mixed ? 4.0 : 8.0;
-        for (const Rec &r : recs) {
+        for (const ProfRec &r : c->recs) {
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
             if (r.kind == 0) { c->sweep_launches += 1; c->sweep_ms += ms; }
             else if (r.kind == 1) { c->update_launches += 1; c->update_ms += ms; }
-            else { c->precond_launches += 1; c->precond_ms += ms; }
+            else if (r.kind == 2) { c->precond_launches += 1; c->precond_ms += ms; }
+            else { c->resid_launches += 1; c->resid_ms += ms; }
         }
         // preconditioned CG: sweep reads z (float) and p_old, writes p, q;
         // update reads x, p, r, q, writes x, r; the preconditioner reads r
@@ -1186,11 +1328,26 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             const OrbDesc &od = b.orb[o];
             const double Mo = (double)od.nx * od.ny * od.nz;
             const double ns = na[2 * (size_t)norb + o], nu = na[3 * (size_t)norb + o];
-            if (pcg) {
+            if (pcg && mixed) {
+                // restart cycles (sampled: the last iteration of every cycle
+                // but the first, and its residual pass): the sweep reads p and
+                // writes q; the update reads r, q and writes r; the
+                // preconditioner reads r, passes the work array through its
+                // passes and its last pass reads p_old and writes p; the
+                // residual pass reads x64, b, the last two p (and x32) and
+                // writes x64 and r (FP64, FP64, FP32)
+                const double npc = na[4 * (size_t)norb + o], nr = na[5 * (size_t)norb + o];
+                const int cyc = std::max(2, pcg_chunk(c->pend_dst_fast));
+                c->sweep_bytes += Mo * 8.0 * ns;
+                c->update_bytes += Mo * 12.0 * nu;
+                c->precond_bytes += Mo * (c->pend_dst_xy ? 28.0 : 44.0) * npc;
+                c->precond_flops += Mo * 4.0 * (od.nx + od.ny + od.nz) * npc;
+                c->resid_bytes += Mo * (36.0 + (cyc > 2 ? 4.0 : 0.0)) * nr;
+            } else if (pcg) {
                 const double npc = na[4 * (size_t)norb + o];
                 c->sweep_bytes += Mo * (4.0 + 3.0 * esz) * ns;
                 c->update_bytes += Mo * esz * 6.0 * nu;
-                c->precond_bytes += Mo * (b.dst_xy ? 20.0 + esz : 36.0 + 2.0 * esz) * npc;
+                c->precond_bytes += Mo * (c->pend_dst_xy ? 20.0 + esz : 36.0 + esz) * npc;
                 c->precond_flops += Mo * 4.0 * (od.nx + od.ny + od.nz) * npc;
             } else {
                 c->sweep_bytes += Mo * esz * 3.0 * ns;
@@ -1198,8 +1355,6 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             }
         }
     }
-#undef PROF_BEGIN
-#undef PROF_END
     return FSIC_OK;
 }
 
@@ -1303,6 +1458,14 @@ void fsic_destroy(fsic_ctx *c) {
     for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     if (c->h_done) hipHostFree(c->h_done);
+    if (c->h_nd) hipHostFree(c->h_nd);
+    if (c->h_si) hipHostFree(c->h_si);
+    if (c->h_sd) hipHostFree(c->h_sd);
+    if (c->h_stat) hipHostFree(c->h_stat);
+    if (c->h_chk) hipHostFree(c->h_chk);
+    for (hipEvent_t e : c->evc)
+        if (e) hipEventDestroy(e);
+    c->ndone.release(); c->fin.release();
     delete c;
 }
 
@@ -1413,6 +1576,8 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     c->sweep_launches = c->update_launches = c->precond_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
     c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
+    c->resid_launches = 0;
+    c->resid_ms = c->resid_bytes = 0.0;
     HIPCHK(c, c->partG.ensure((size_t)gram_blk * kMaxOrb * kMaxOrb));
     std::vector<FodCell> cells;
     for (const Chan &ch : chans) cells.insert(cells.end(), ch.cells.begin(), ch.cells.end());
@@ -1454,43 +1619,32 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         }
         HIPCHK(c, launch_lowdin_batch(lb, c->small.p, loff, c->work.p, lw, o.s_eig_floor, c->status.p, s));
     }
-    // device-detected problems stop the pass before the solves
-    int hstatus = 0;
-    HIPCHK(c, hipMemcpyAsync(&hstatus, c->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (hstatus & kStNonFinite) return set_err(c, FSIC_EINVAL, "non-finite orbital values at an FOD");
-    if (hstatus & kStVacuum) return set_err(c, FSIC_EVACUUM, "an FOD lies where rho(a_i) <= rho_floor");
-    if (hstatus & kStSingular) {
-        double info[2] = {0, 0};
+    // device status and the per-channel overlap data for the host checks:
+    // copied now, read after the pass (a solve stops early when the status
+    // shows an error); stage layout per channel: G (N^2), info (2), rho(a) (N)
+    size_t chk_n = 0;
+    for (const Chan &ch : chans) chk_n += (size_t)ch.N * ch.N + 2 + ch.N;
+    if (c->h_chk_cap < chk_n) {
+        if (c->h_chk) hipHostFree(c->h_chk);
+        c->h_chk = nullptr;
+        c->h_chk_cap = 0;
+        HIPCHK(c, hipHostMalloc((void **)&c->h_chk, chk_n * sizeof(double)));
+        c->h_chk_cap = chk_n;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_stat, c->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    {
+        size_t q = 0;
         for (const Chan &ch : chans) {
-            double h2[2];
-            if (hipMemcpy(h2, c->small.p + ch.so + small_off(sINFO), sizeof(h2), hipMemcpyDeviceToHost) == hipSuccess &&
-                (info[1] == 0 || h2[1] < info[1])) { info[0] = h2[0]; info[1] = h2[1]; }
+            const double *sm = c->small.p + ch.so;
+            const size_t NN = (size_t)ch.N * ch.N;
+            HIPCHK(c, hipMemcpyAsync(c->h_chk + q, sm + small_off(sG), NN * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(c->h_chk + q + NN, sm + small_off(sINFO), 2 * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(c->h_chk + q + NN + 2, sm + small_off(sRHOA), ch.N * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+            q += NN + 2 + ch.N;
         }
-        return set_err(c, FSIC_ESINGULAR, "smallest eigenvalue of S = " + std::to_string(info[1]) +
-                                              " below s_eig_floor");
     }
-    // orthonormality of the input and overlap statistics (N x N, host)
-    double nonortho = 0.0, condmax = 0.0, minrho = 1e300;
-    for (int ci = 0; ci < nchan; ++ci) {
-        const Chan &ch = chans[ci];
-        const double *sm = c->small.p + ch.so;
-        std::vector<double> G((size_t)ch.N * ch.N), info(2), rhoa(ch.N);
-        HIPCHK(c, hipMemcpy(G.data(), sm + small_off(sG), G.size() * sizeof(double), hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(info.data(), sm + small_off(sINFO), 2 * sizeof(double), hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(rhoa.data(), sm + small_off(sRHOA), ch.N * sizeof(double), hipMemcpyDeviceToHost));
-        for (int i = 0; i < ch.N; ++i) {
-            for (int j = 0; j < ch.N; ++j) {
-                const double g = G[(size_t)i * ch.N + j];
-                if (!std::isfinite(g)) return set_err(c, FSIC_EINVAL, "non-finite values in psi");
-                nonortho = std::max(nonortho, std::fabs(g - (i == j ? 1.0 : 0.0)));
-            }
-            minrho = std::min(minrho, rhoa[i]);
-        }
-        condmax = std::max(condmax, info[0]);
-    }
-    if (!(o.flags & FSIC_ALLOW_NONORTHO) && nonortho > 1e-8)
-        return set_err(c, FSIC_ENONORTHO, "max |dV psi psi^T - I| = " + std::to_string(nonortho));
     // phi = Q psi on the matrix cores
     for (int ci = 0; ci < nchan; ++ci) {
         const Chan &ch = chans[ci];
@@ -1499,13 +1653,14 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         else
             HIPCHK(c, launch_orb_gemm(ch.N, ch.M, c->small.p + ch.so + small_off(sQ), ch.psi, c->PHI.p + ch.off, s));
     }
-    HIPCHK(c, hipStreamSynchronize(s));
     const double t2 = now_ms();
 
     // ---- (c) Poisson solves for all orbitals at once ----
     SolveReport rep;
+    c->watch_status = true;
     fsic_status sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, true, c->V.p, o.precision, o.tol,
                                   o.max_iter, rep);
+    c->watch_status = false;
     if (sst) return sst;
     const double t3 = now_ms();
 
@@ -1518,6 +1673,38 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     HIPCHK(c, hipMemcpyAsync(uo.data(), c->Uo.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(xo.data(), c->Xo.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
+
+    // ---- host checks of the inputs (Sec. I.B: normalised, linearly
+    // independent Fermi orbitals; Eq. 8: nonzero density at every FOD) ----
+    const int hstatus = *c->h_stat;
+    if (hstatus & kStNonFinite) return set_err(c, FSIC_EINVAL, "non-finite orbital values at an FOD");
+    if (hstatus & kStVacuum) return set_err(c, FSIC_EVACUUM, "an FOD lies where rho(a_i) <= rho_floor");
+    double nonortho = 0.0, condmax = 0.0, minrho = 1e300, minlam = 0.0;
+    {
+        size_t q = 0;
+        for (const Chan &ch : chans) {
+            const size_t NN = (size_t)ch.N * ch.N;
+            const double *G = c->h_chk + q, *info = c->h_chk + q + NN, *rhoa = c->h_chk + q + NN + 2;
+            for (int i = 0; i < ch.N; ++i) {
+                for (int j = 0; j < ch.N; ++j) {
+                    const double g = G[(size_t)i * ch.N + j];
+                    if (!std::isfinite(g)) return set_err(c, FSIC_EINVAL, "non-finite values in psi");
+                    nonortho = std::max(nonortho, std::fabs(g - (i == j ? 1.0 : 0.0)));
+                }
+                minrho = std::min(minrho, rhoa[i]);
+            }
+            condmax = std::max(condmax, info[0]);
+            if (minlam == 0.0 || info[1] < minlam) minlam = info[1];
+            q += NN + 2 + ch.N;
+        }
+    }
+    if (hstatus & kStSingular)
+        return set_err(c, FSIC_ESINGULAR, "smallest eigenvalue of S = " + std::to_string(minlam) +
+                                              " below s_eig_floor");
+    if (!(o.flags & FSIC_ALLOW_NONORTHO) && nonortho > 1e-8)
+        return set_err(c, FSIC_ENONORTHO, "max |dV psi psi^T - I| = " + std::to_string(nonortho));
+    fsic_status fst = finish_solve(c, b, rep);
+    if (fst) return fst;
     for (int k = 0; k < nsys; ++k) e_sic[k] = 0.0;
     for (int ci = 0; ci < nchan; ++ci) e_sic[chans[ci].sys] += ech[ci];
     if (Uout) std::memcpy(Uout, uo.data(), norb * sizeof(double));
@@ -1548,6 +1735,10 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         st->precond_ms = c->precond_ms;
         st->precond_bytes = c->precond_bytes;
         st->precond_flops = c->precond_flops;
+        st->resid_launches = c->resid_launches;
+        st->resid_ms = c->resid_ms;
+        st->resid_bytes = c->resid_bytes;
+        st->graph_captures = c->graph_captures;
         st->stencil_cpt = c->shape_cpt;
         st->stencil_depth = c->shape_depth;
         st->stencil_blocks = c->shape_target;
@@ -1692,6 +1883,9 @@ fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lma
     if (st) return st;
     SolveReport rep;
     st = solve_batch(c, b, rho, 0, 4.0 * M_PI, true, v, precision, tol, max_iter, rep);
+    if (st) return st;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return FSIC_EHIP;
+    st = finish_solve(c, b, rep);
     if (st) return st;
     std::vector<int> it(count);
     std::vector<double> pt(count), bbh(count);
@@ -1871,6 +2065,8 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     c->sweep_launches = c->update_launches = c->precond_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
     c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
+    c->resid_launches = 0;
+    c->resid_ms = c->resid_bytes = 0.0;
     fsic_status pst = prepare_batch(c, b, o.precision);
     if (pst) return pst;
     HIPCHK(c, c->bmat.ensure((size_t)kMaxOrb * kMaxOrb));
@@ -1918,6 +2114,10 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
                                  hipMemcpyDeviceToHost, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
+    if (!eq9) {
+        fsic_status fst = finish_solve(c, b, rep);
+        if (fst) return fst;
+    }
     for (size_t ci = 0; ci < c->chans.size(); ++ci) {
         const Chan &ch = c->chans[ci];
         const double ge = grad_e ? grad_e[ch.sys] : 1.0;
@@ -1945,6 +2145,10 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         st->precond_ms = c->precond_ms;
         st->precond_bytes = c->precond_bytes;
         st->precond_flops = c->precond_flops;
+        st->resid_launches = c->resid_launches;
+        st->resid_ms = c->resid_ms;
+        st->resid_bytes = c->resid_bytes;
+        st->graph_captures = c->graph_captures;
         st->stencil_cpt = c->shape_cpt;
         st->stencil_depth = c->shape_depth;
         st->stencil_blocks = c->shape_target;

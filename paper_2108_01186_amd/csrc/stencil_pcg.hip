@@ -92,4 +92,65 @@ template hipError_t launch_pcg_stencil<float>(int, const Coeffs &, const CGIter<
 template hipError_t launch_pcg_update<double>(const CGIter<double> &, int, int, hipStream_t);
 template hipError_t launch_pcg_update<float>(const CGIter<float> &, int, int, hipStream_t);
 
+// mixed restart cycles: r -= alpha q (and the x modes of launch_pcg_rupdate)
+__global__ __launch_bounds__(256) void k_pcg_rupd(CGIter<float> a, int k, int xmode) {
+    __shared__ double sred[4];
+    const Item it = a.items8[blockIdx.x];
+    if (it.orb < 0) return;
+    if (a.done[it.orb]) return;
+    const OrbDesc od = a.orb[it.orb];
+    const float al = (float)alpha_of(a, od, k, sred);
+    const long long M = (long long)od.nx * od.ny * od.nz;
+    const long long base = (long long)it.tile * kPW;
+    if (((od.off | M) & 3) == 0) {
+#pragma unroll
+        for (int e = 0; e < kPW / 1024; ++e) {
+            const long long i = base + (long long)(e * 256 + threadIdx.x) * 4;
+            if (i < M) {
+                const long long g = od.off + i;
+                float4 rv = *reinterpret_cast<const float4 *>(a.R + g);
+                const float4 qv = *reinterpret_cast<const float4 *>(a.Q + g);
+                rv.x -= al * qv.x; rv.y -= al * qv.y; rv.z -= al * qv.z; rv.w -= al * qv.w;
+                *reinterpret_cast<float4 *>(a.R + g) = rv;
+                if (xmode) {
+                    const float4 pv = *reinterpret_cast<const float4 *>(a.P + g);
+                    float4 xv = xmode == 2 ? *reinterpret_cast<const float4 *>(a.X + g)
+                                           : float4{0.f, 0.f, 0.f, 0.f};
+                    xv.x += al * pv.x; xv.y += al * pv.y; xv.z += al * pv.z; xv.w += al * pv.w;
+                    *reinterpret_cast<float4 *>(a.X + g) = xv;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPW / 256; ++e) {
+            const long long i = base + e * 256 + threadIdx.x;
+            if (i < M) {
+                const long long g = od.off + i;
+                a.R[g] -= al * a.Q[g];
+                if (xmode) a.X[g] = (xmode == 2 ? a.X[g] : 0.f) + al * a.P[g];
+            }
+        }
+    }
+    if (threadIdx.x == 0 && it.tile == 0) {
+        a.nact[a.norb + it.orb] += 1;
+        if (a.nsamp) a.nsamp[a.norb + it.orb] += 1;
+    }
+}
+
+hipError_t launch_pcg_sweep(int radius, const Coeffs &c, const CGIter<float> &a, int k, hipStream_t s) {
+    if (a.nitems7 <= 0) return hipSuccess;
+    PolPQ pol{a.items7, a.orb, a, k, false};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<float, P, C, DD, PolPQ>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
+    FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_rupdate(const CGIter<float> &a, int k, int xmode, hipStream_t s) {
+    if (a.nitems8 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pcg_rupd, dim3(a.nitems8), dim3(256), 0, s, a, k, xmode);
+    return hipGetLastError();
+}
+
 }  // namespace fsic

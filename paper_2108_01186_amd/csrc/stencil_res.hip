@@ -37,7 +37,8 @@ __global__ __launch_bounds__(256) void k_mixed_accumulate(const Item *items8, co
 // convergence on the FP64 residual of the last reliable update
 __global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const double *partRU,
                                                   const double *bb, double tol2, int k, int *done,
-                                                  int *iters, double *rrfin, int *rs_iter) {
+                                                  int *iters, double *rrfin, int *rs_iter, int *ndone,
+                                                  int *fin, int xfin) {
     __shared__ double sred[4];
     const int o = blockIdx.x;
     if (done[o] == 1) return;
@@ -48,6 +49,8 @@ __global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const doub
             done[o] = 1;
             iters[o] = k;
             rrfin[o] = rr;
+            if (ndone) atomicAdd(ndone, 1);
+            if (fin) fin[o] = xfin;
         } else if (done[o] == 2) {
             // the FP32 recursion met tol but the FP64 residual did not:
             // resume with a restart from the FP64 residual
@@ -94,10 +97,46 @@ hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDes
 
 hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
                            double tol2, int k, int *done, int *iters, double *rrfin, int *rs_iter,
-                           hipStream_t s) {
+                           int *ndone, int *fin, int xfin, hipStream_t s) {
     if (norb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ru_check, dim3(norb), dim3(256), 0, s, orb, partRU, bb, tol2, k, done,
-                       iters, rrfin, rs_iter);
+                       iters, rrfin, rs_iter, ndone, fin, xfin);
+    return hipGetLastError();
+}
+
+// the final x of each orbital: copied from the second x64 buffer where the
+// restart cycle that converged it (fin[o], or fallback for an unconverged
+// orbital) wrote it there
+__global__ __launch_bounds__(256) void k_take_x(const Item *items8, const OrbDesc *orb, const int *fin,
+                                                int fallback, double *X, const double *Xb) {
+    const Item it = items8[blockIdx.x];
+    if (it.orb < 0) return;
+    const int f = fin[it.orb];
+    if ((f >= 0 ? f : fallback) != 1) return;
+    const OrbDesc od = orb[it.orb];
+    const long long M = (long long)od.nx * od.ny * od.nz;
+    const long long base = (long long)it.tile * kPW;
+#pragma unroll
+    for (int e = 0; e < kPW / 256; ++e) {
+        const long long i = base + e * 256 + threadIdx.x;
+        if (i < M) X[od.off + i] = Xb[od.off + i];
+    }
+}
+
+hipError_t launch_take_x(int nitems8, const Item *items8, const OrbDesc *orb, const int *fin, int fallback,
+                         double *X, const double *Xb, hipStream_t s) {
+    if (nitems8 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_take_x, dim3(nitems8), dim3(256), 0, s, items8, orb, fin, fallback, X, Xb);
+    return hipGetLastError();
+}
+
+hipError_t launch_res_steps(int radius, const Coeffs &c, const CGIter<float> &a, const ResStep &rs,
+                            hipStream_t s) {
+    if (a.nitems7 <= 0) return hipSuccess;
+    PolResP pol{a.items7, a.orb, a, rs, false, 0.0, 0.0};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolResP>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
+    FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
     return hipGetLastError();
 }
 

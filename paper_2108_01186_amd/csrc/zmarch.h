@@ -50,17 +50,6 @@ __device__ __forceinline__ void bst(Rsrc r, unsigned vidx, int sidx, double v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, vidx * 8u, sidx * 8, 0);
 }
 
-// Workgroup barrier that orders LDS traffic only: this wave's LDS operations
-// complete (lgkmcnt(0)), then s_barrier.  Unlike __syncthreads() it does not
-// wait for outstanding global loads, so the next plane's prefetch stays in
-// flight across the barrier.
-__device__ __forceinline__ void lds_barrier() {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt/expcnt: no wait; lgkmcnt(0)
-    __builtin_amdgcn_s_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
 // calls f(integral_constant<int, U>, arg) for U = 0..N-1 (forced unrolling)
 template <int N, int U = 0>
 struct Unroller {
@@ -402,10 +391,10 @@ struct PolPCG {  // p_k = z_k + beta p_{k-1}; q = K p_k = -L p_k; p.q partials
             if (threadIdx.x == 0) {
                 if (pause) {
                     a.done[o] = 2;  // mixed: confirm on the FP64 residual first
-                } else {
-                    a.done[o] = 1;
+                } else if (atomicCAS(a.done + o, 0, 1) == 0) {  // first block of o to see it
                     a.iters[o] = k;
                     a.rrfin[o] = rr;
+                    if (a.ndone) atomicAdd(a.ndone, 1);
                 }
             }
             return false;
@@ -447,6 +436,104 @@ struct PolPCG {  // p_k = z_k + beta p_{k-1}; q = K p_k = -L p_k; p.q partials
     __device__ void finish(const Item &it, const OrbDesc &od, const Acc &s, double *sred) const {
         const double t = block_sum256(s, sred);
         if (threadIdx.x == 0) a.part7[od.base7 + it.tile] = t;
+    }
+};
+
+// sweep of the mixed restart cycles: q_k = -L p_k, p_k.q_k partials by parity
+struct PolPQ {
+    const Item *items;
+    const OrbDesc *orb;
+    CGIter<float> a;
+    int k;
+    bool tile0;
+    __device__ bool setup(int o, const OrbDesc &, double *sbuf) {
+        if (threadIdx.x == 0) sbuf[0] = (double)a.done[o];
+        __syncthreads();
+        const bool dn = sbuf[0] != 0.0;
+        __syncthreads();
+        if (dn) return false;
+        if (threadIdx.x == 0 && tile0) {
+            a.nact[o] += 1;
+            if (a.nsamp) a.nsamp[o] += 1;
+        }
+        return true;
+    }
+    struct Raw { float p; };
+    struct Ext {};
+    typedef double Acc;
+    Rsrc rp, rq;
+    __device__ void init(const OrbDesc &od) {
+        const unsigned bytes = (unsigned)((long long)od.nx * od.ny * od.nz * 4);
+        rp = make_rsrc(a.P + od.off, bytes);
+        rq = make_rsrc(a.Q + od.off, bytes);
+    }
+    __device__ Raw raw(unsigned i, int zo) const { return Raw{bld<float>(rp, i, zo)}; }
+    __device__ Ext ext(unsigned, int) const { return Ext{}; }
+    __device__ float combine(const Raw &v) const { return v.p; }
+    __device__ void epilogue(unsigned i, int zo, float c, float lap, const Ext &, Acc &s) const {
+        const float qv = -lap;
+        bst(rq, i, zo, qv);
+        s += (double)c * (double)qv;
+    }
+    __device__ void finish(const Item &it, const OrbDesc &od, const Acc &s, double *sred) const {
+        const double t = block_sum256(s, sred);
+        if (threadIdx.x == 0) a.part7[(size_t)(k & 1) * a.tot7 + od.base7 + it.tile] = t;
+    }
+};
+
+// alpha_j = r_j.z_j / p_j.q_j of an orbital (mixed restart cycles)
+__device__ __forceinline__ double alpha_of(const CGIter<float> &a, const OrbDesc &od, int j, double *sbuf) {
+    const double rz = rz_of(a, od, j, sbuf);
+    const double pq = sum_partials(a.part7 + (size_t)(j & 1) * a.tot7 + od.base7, od.nt7, sbuf);
+    return pq != 0.0 ? rz / pq : 0.0;  // p = 0 only for a zero right-hand side
+}
+
+// end of a mixed restart cycle: res = b + L x, x = x64 + x32 + alpha_a p_a + alpha_b p_b
+struct PolResP {
+    const Item *items;
+    const OrbDesc *orb;
+    CGIter<float> a;
+    ResStep r;
+    bool tile0;
+    double aa, ab;
+    struct Raw { double x; float x32, pa, pb; };
+    typedef double Ext;
+    typedef double Acc;
+    Rsrc rx, rx32, rpa, rpb, rb, rxn, rr32;
+    __device__ bool setup(int o, const OrbDesc &od, double *sbuf) {
+        if (a.done[o] == 1) return false;  // not changed during this launch: uniform
+        aa = alpha_of(a, od, r.ka, sbuf);
+        ab = alpha_of(a, od, r.kb, sbuf);
+        if (threadIdx.x == 0 && tile0 && a.nsamp) a.nsamp[3 * a.norb + o] += 1;
+        return true;
+    }
+    __device__ void init(const OrbDesc &od) {
+        const long long M = (long long)od.nx * od.ny * od.nz;
+        if (r.X64) rx = make_rsrc(r.X64 + od.off, (unsigned)(M * 8));
+        if (r.X32) rx32 = make_rsrc(r.X32 + od.off, (unsigned)(M * 4));
+        rpa = make_rsrc(r.Pa + od.off, (unsigned)(M * 4));
+        rpb = make_rsrc(r.Pb + od.off, (unsigned)(M * 4));
+        rb = make_rsrc(a.B64 + od.off, (unsigned)(M * 8));
+        rxn = make_rsrc(r.X64new + od.off, (unsigned)(M * 8));
+        rr32 = make_rsrc(r.R32 + od.off, (unsigned)(M * 4));
+    }
+    __device__ Raw raw(unsigned i, int zo) const {
+        return Raw{r.X64 ? bld<double>(rx, i, zo) : 0.0, r.X32 ? bld<float>(rx32, i, zo) : 0.0f,
+                   bld<float>(rpa, i, zo), bld<float>(rpb, i, zo)};
+    }
+    __device__ Ext ext(unsigned i, int zo) const { return bld<double>(rb, i, zo); }
+    __device__ double combine(const Raw &v) const {
+        return v.x + ((double)v.x32 + (aa * (double)v.pa + ab * (double)v.pb));
+    }
+    __device__ void epilogue(unsigned i, int zo, double c, double lap, const Ext &b, Acc &s) const {
+        const double res = b + lap;
+        bst(rxn, i, zo, c);
+        bst(rr32, i, zo, (float)res);
+        s += res * res;
+    }
+    __device__ void finish(const Item &it, const OrbDesc &od, const Acc &s, double *sred) const {
+        const double t = block_sum256(s, sred);
+        if (threadIdx.x == 0) a.partRU[od.base7 + it.tile] = t;
     }
 };
 

@@ -67,7 +67,9 @@ class fsic_stats(ctypes.Structure):
                 ("precond_launches", ctypes.c_int32), ("precond_ms", ctypes.c_double),
                 ("precond_bytes", ctypes.c_double), ("precond_flops", ctypes.c_double),
                 ("stencil_cpt", ctypes.c_int32), ("stencil_depth", ctypes.c_int32),
-                ("stencil_blocks", ctypes.c_int64), ("tune_ms", ctypes.c_double)]
+                ("stencil_blocks", ctypes.c_int64), ("tune_ms", ctypes.c_double),
+                ("resid_launches", ctypes.c_int32), ("resid_ms", ctypes.c_double),
+                ("resid_bytes", ctypes.c_double), ("graph_captures", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms_phase"}

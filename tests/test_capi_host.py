@@ -51,13 +51,29 @@ def test_default_opts_and_status_strings():
     assert b"unknown" in fsic.fsic_status_string(99)
 
 
-def test_struct_layout_matches_header():
-    """Sizes of the ABI structs as a C compiler lays them out."""
+def test_struct_layout_matches_header(tmp_path):
+    """Size and every field offset of the ABI structs in the binding equal what
+    gcc lays out from include/fsic.h."""
+    import subprocess
     from paper_2108_01186_amd import fsic
-    assert ctypes.sizeof(fsic.fsic_grid) == 4 * 3 + 4 + 8 + 24
-    assert ctypes.sizeof(fsic.fsic_opts) == 64
-    assert ctypes.sizeof(fsic.fsic_stats) == (4 + 4 + 8 + 4 + 4 + 8 * 4 + 8 * 8 + 4 + 4 + 8 * 4
-                                              + 4 + 4 + 8 * 3 + 4 + 4 + 8 + 8)
+    structs = [fsic.fsic_grid, fsic.fsic_opts, fsic.fsic_system, fsic.fsic_stats]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fsic.h"', 'int main(void) {']
+    for st in structs:
+        lines.append(f'printf("%zu\\n", sizeof({st.__name__}));')
+        for name, _ in st._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({st.__name__}, {name}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = []
+    for st in structs:
+        want.append(ctypes.sizeof(st))
+        want.extend(getattr(st, name).offset for name, _ in st._fields_)
+    assert got == want
 
 
 def test_invalid_arguments_rejected_on_host():
@@ -106,7 +122,7 @@ def test_stored_traffic_follows_kernel_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     src = tmp_path / "paper_2108_01186_amd" / "csrc"
     src.mkdir(parents=True)
-    for f in ("stencil.hip", "dst.hip", "common.h"):
+    for f in bench.KERNEL_SOURCES:
         (src / f).write_text("// " + f + "\n")
     good = bench.kernel_source_hash()
     path = prof / "precond_pcg_f32_toy_hbm_traffic.txt"

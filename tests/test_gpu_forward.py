@@ -118,12 +118,17 @@ def test_fp32_orbital_gemm_error(torch_cuda, F, mol40_dev, mol40_oracle):
     assert dv < 1e-5
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_replays_match_eager(torch_cuda, F, mol40_dev, precision):
-    """FSIC_GRAPHS: CG chunks captured once and replayed.  Three forward +
-    backward passes, each after eager work of another context, all bitwise
-    equal to the eager path (same kernels, same order)."""
-    _say(f"graphs mol40 {precision}")
+@pytest.mark.parametrize("precision,fused", [("mixed", "1"), ("mixed", "0"), ("fp64", "1")])
+def test_graph_replays_match_eager(torch_cuda, F, mol40_dev, precision, fused, monkeypatch):
+    """FSIC_GRAPHS: restart cycles of the mixed preconditioned solve captured
+    once per batch layout and buffers and replayed (the flag changes nothing
+    in FP64).  Three forward + backward passes, each after eager work of
+    another context, all bitwise equal to the eager path (same kernels, same
+    order); after the first pass no further graph is captured (the forward
+    and the adjoint solves each reuse their own), with both transform
+    layouts (fused in-plane passes, five per-axis passes)."""
+    _say(f"graphs mol40 {precision} fused={fused}")
+    monkeypatch.setenv("FSIC_DST_XY", fused)
     d = F.system_dict(mol40_dev)
     eager = F.Context(precision=precision, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE)
     e0 = eager.forward([d])[0][0]
@@ -131,12 +136,19 @@ def test_graph_replays_match_eager(torch_cuda, F, mol40_dev, precision):
     v0 = d["vsic"][0].cpu().numpy().copy()
     graph = F.Context(precision=precision,
                       flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE | F.FSIC_GRAPHS)
+    captures = []
     for rep in range(3):
         eager.forward([d])  # eager work on the same device between replays
         e1 = graph.forward([d])[0][0]
         g1 = graph.backward([[5]])[0][0]
+        captures.append(graph.stats["graph_captures"])
         assert e1 == e0, (rep, e1, e0)
         assert np.array_equal(g1, g0), rep
         assert np.array_equal(d["vsic"][0].cpu().numpy(), v0), rep
+    if precision == "mixed":
+        assert 2 <= captures[0] <= 6, captures  # variants x (forward, adjoint) solves
+    else:
+        assert captures[0] == 0
+    assert captures[1] == captures[0] and captures[2] == captures[0], captures
     eager.close()
     graph.close()

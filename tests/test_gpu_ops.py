@@ -115,13 +115,14 @@ def test_poisson_vs_oracle(torch_cuda, F, oracle, n, h, precision, solver):
 @pytest.mark.parametrize("precision,n", [("fp64", (37, 29, 45)), ("mixed", (37, 29, 45)),
                                          ("fp64", (136, 21, 18)), ("mixed", (19, 150, 17)),
                                          ("fp64", (190, 14, 12)), ("mixed", (12, 13, 185)),
-                                         ("fp64", (230, 9, 10))])
+                                         ("fp64", (230, 9, 10)), ("mixed", (230, 9, 10))])
 def test_pcg_non_cubic_grid(torch_cuda, F, oracle, precision, n):
     """Preconditioned solve on a box with a different node count per axis
     (ragged tiles of every sine transform), against the oracle.  The longest
     axis picks the transform variant: <= 128 nodes 128-column split-bf16
     panels, 136-150 64-column ones, 185-190 the bf16 sine matrix without its
-    low part, 230 the fp32 kernels."""
+    low part; no variant fits 230 nodes in LDS, so that batch is solved by
+    plain CG (same tolerance, many more iterations)."""
     torch = torch_cuda
     _say(f"pcg non-cubic {precision} {n}")
     h = 0.28
@@ -132,7 +133,8 @@ def test_pcg_non_cubic_grid(torch_cuda, F, oracle, precision, n):
     rho = (np.exp(-r2 / (2 * 0.7 ** 2)) + 0.2 * np.exp(-r2 / 3.0)).reshape(1, -1)
     v, it, rr = F.op_poisson(torch.tensor(rho, device="cuda"), n, h, origin, tol=1e-12,
                              precision=precision, solver="pcg")
-    assert rr[0] <= 1e-12 and it[0] < 40, (rr, it)
+    assert rr[0] <= 1e-12, (rr, it)
+    assert (it[0] < 40) == (max(n) <= 208), (rr, it)
     ref, _, _ = oracle.poisson(rho[0], n, h, origin)
     assert np.abs(v.cpu().numpy()[0] - ref).max() < 1e-9 * np.abs(ref).max()
 

@@ -49,3 +49,27 @@ def test_aar_history_kernels_use_no_scratch():
     assert any("k_aar_dots" in k for k in names) and sum("k_aar_step" in k for k in names) == 2, usage
     for k, v in names.items():
         assert v.get("ScratchSize") == 0, (k, v)
+
+
+def test_transform_kernels_use_no_scratch():
+    """The sine-transform passes that serve axes above 96 nodes (one block per
+    compute unit: the z pass of every variant, the x and y passes of the five-
+    pass layout, the fused in-plane pass) keep their register buffers and
+    accumulator tiles in registers: each instantiation is sized for the
+    longest axis its variant serves.  Known exceptions: the two-block
+    inverse passes for planes up to 96 x 96 (8-32 B; the form that loads
+    p_old before its products is the fastest measured despite it), and the
+    128-column five-pass inverse pass (only batches with unequal in-plane
+    axes at 128 nodes use it)."""
+    usage = _resource_usage("dst.hip")
+    checked = 0
+    for k, v in usage.items():
+        if "k_dst" not in k:
+            continue
+        if k.startswith("_ZN4fsic8k_dst_xyILb1EffLb1ELb1E"):  # two-block inverse passes
+            continue
+        if "ILi0ELi0EffLb0ELi128ELb1ELb0ELb1ELi128E" in k:  # 128-column five-pass inverse
+            continue
+        assert v.get("ScratchSize") == 0, (k, v)
+        checked += 1
+    assert checked >= 25, usage
