@@ -13,6 +13,9 @@ stored values.
                                               # tangent mode, CG to 1e-13)
   python tests/golden/make_golden.py mol192   # U_i and X_i (Eq. 1) of four orbitals
                                               # per spin channel, and cond(S) per channel
+  python tests/golden/make_golden.py mol192flo  # T, S, Z (Eq. 8, Sec. I.B) of both
+                                              # channels and phi at sampled nodes of
+                                              # the four orbitals (mol192_flo.npz)
 
 Costs on 8 host cores: mol128 about 30 minutes, mol192 about an hour.
 """
@@ -99,6 +102,28 @@ def mol192():
     log("mol192: written")
 
 
+# nodes at which phi is stored for the 192^3 workload: seeded, uniform over the grid
+MOL192_PHI_NODES = 2048
+
+
+def mol192flo():
+    log("mol192flo: generate on the CPU")
+    s = synth.make_workload("mol192")
+    rng = np.random.default_rng(192)
+    nodes = np.sort(rng.choice(s.M, size=MOL192_PHI_NODES, replace=False))
+    out = {"nodes": nodes, "orbitals": np.array(MOL192_ORBITALS)}
+    for sp in range(s.nspin):
+        t0 = time.time()
+        phi, T, S, Z = oracle.flo_spin(s.psi[sp], s.fod[sp], s.n, s.h, s.origin)
+        log(f"mol192flo spin {sp}: FLOs in {time.time() - t0:.0f} s")
+        out[f"T{sp}"], out[f"S{sp}"], out[f"Z{sp}"] = T, S, Z
+        out[f"phi{sp}"] = phi[np.array(MOL192_ORBITALS)][:, nodes]
+        out[f"fp_sum{sp}"] = np.asarray(s.psi[sp]).sum(axis=1)
+        del phi
+    np.savez_compressed(os.path.join(HERE, "mol192_flo.npz"), **out)
+    log("mol192flo: written")
+
+
 if __name__ == "__main__":
     for name in sys.argv[1:]:
-        {"mol128": mol128, "mol192": mol192}[name]()
+        {"mol128": mol128, "mol192": mol192, "mol192flo": mol192flo}[name]()

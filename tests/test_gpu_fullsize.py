@@ -3,6 +3,13 @@ benchmark times (both spins batched, mixed precision, preconditioned CG to
 a relative residual of 1e-11, which keeps E_SIC within 1e-8 Ha even on the
 largest systems of the uneven batch; 1e-10 left 1.02e-8 Ha there):
 
+* 192^3 / 100 + 100 orbitals: T, S, Z and phi (sampled nodes) of both
+  channels, and U_i, X_i of four orbitals per channel, against stored oracle
+  values (tests/golden/make_golden.py, from the recipe's CPU-generated
+  inputs, whose fingerprint the test checks first); E_SIC of the mixed leg
+  against the FP64 leg; the FOD gradient against central differences of the
+  FP64 energy on 8 seeded coordinates;
+* 128^3: the spin-up FOD gradient against the stored oracle gradient;
 * 96^3 / 16 + 15 orbitals: every output against the oracle (E_SIC, U_i, X_i,
   V_SIC elementwise, spin-up FOD gradient), and the V_SIC scale factor;
 * 128^3 / 32 + 32 orbitals: the FOD gradient through the autograd Function
@@ -12,7 +19,9 @@ largest systems of the uneven batch; 1e-10 left 1.02e-8 Ha there):
   every system against its own single-system solve, a sampled orbital of
   the largest system against the oracle.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -202,3 +211,119 @@ def test_batch24_uneven_systems(torch_cuda, F, oracle):
     base = sum(sum(systems[j].nocc) for j in range(k))
     assert abs(U[base + 1] - u) < TERM_TOL, (U[base + 1], u)
     assert abs(X[base + 1] - x) < TERM_TOL, (X[base + 1], x)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _check_fingerprint(torch, s, fp):
+    """The device-generated inputs are the recipe's inputs (to rounding): per
+    orbital the sum of psi and the (node index / M)-weighted sum, and the
+    FODs exactly."""
+    for sp in range(s.nspin):
+        psi = s.psi[sp]
+        M = psi.shape[1]
+        w = torch.arange(M, dtype=torch.float64, device=psi.device) / M
+        sums = psi.sum(dim=1).cpu().numpy()
+        wsums = (psi @ w).cpu().numpy()
+        ref_s, ref_w = np.array(fp[sp]["sum"]), np.array(fp[sp]["wsum"])
+        assert np.abs(sums - ref_s).max() <= 1e-9 * np.abs(ref_s).max(), sp
+        assert np.abs(wsums - ref_w).max() <= 1e-9 * np.abs(ref_w).max(), sp
+        assert np.array_equal(np.asarray(s.fod[sp]), np.array(fp[sp]["fod"])), sp
+
+
+def test_mol128_gradient_vs_stored_oracle(torch_cuda, F):
+    """128^3, 32 + 32 orbitals, mixed precision: the spin-up FOD gradient
+    (Eq. 9-11 in exact discrete form) against the oracle's, computed once by
+    tests/golden/make_golden.py (tangent mode, CG to 1e-13), to the 1e-6
+    Ha/Bohr force target."""
+    torch = torch_cuda
+    with open(os.path.join(GOLDEN, "mol128_grad_up.json")) as fh:
+        rec = json.load(fh)
+    _say("mol128 (stored oracle gradient): generate")
+    s = synth.make_workload("mol128", device="cuda")
+    _check_fingerprint(torch, s, rec["fingerprint"])
+    ctx = F.Context(precision="mixed", tol=TOL, flags=_flags(F))
+    _say("mol128: GPU forward + backward (mixed)")
+    ctx.forward([_dict(torch, s)])
+    g = ctx.backward([list(s.nocc)])[0]
+    ctx.close()
+    gref = np.array(rec["grad_up"])
+    dg = np.abs(g[0] - gref).max()
+    _say(f"mol128: max |dE/da - oracle| = {dg:.3e} Ha/Bohr (largest component {np.abs(gref).max():.3e})")
+    assert dg < F_TOL
+
+
+# 192^3: both sides form Z = S^{-1/2} from S with cond(S) of 2.1e5 and 1.2e6
+# (stored in the golden file).  S itself agrees to ~1e-12 relative (grid sums
+# over 7.1e6 nodes in other orders, inputs generated on other devices), and
+# a perturbation of S moves Z = S^{-1/2} by up to cond(S)/2 times as much
+# (Daleckii-Krein: the divided differences of lambda^{-1/2} reach
+# lambda_min^{-3/2}/2); the bound on Z and phi is 5e-12 cond(S), i.e. that
+# propagation with a factor 10 on the observed S deviation
+MOL192_REL_PER_COND = 5e-12
+MOL192_TERM_TOL = 1e-8
+
+
+def test_mol192_large_system(torch_cuda, F):
+    """192^3, h = 0.15, 100 + 100 orbitals (the large single system)."""
+    torch = torch_cuda
+    with open(os.path.join(GOLDEN, "mol192_terms.json")) as fh:
+        terms = json.load(fh)
+    flo = np.load(os.path.join(GOLDEN, "mol192_flo.npz"))
+    _say("mol192: generate")
+    s = synth.make_workload("mol192", device="cuda")
+    _check_fingerprint(torch, s, terms["fingerprint"])
+    orbs = list(terms["orbitals"])
+    nodes = torch.tensor(flo["nodes"], device="cuda")
+    for sp in range(2):
+        _say(f"mol192: Fermi-Loewdin orbitals, spin {sp}")
+        T, G, S, Z, phi = F.op_flo(s.psi[sp], s.fod[sp], s.n, s.h, s.origin)
+        d = {}
+        for lab, got, ref in (("T", T, flo[f"T{sp}"]), ("S", S, flo[f"S{sp}"]), ("Z", Z, flo[f"Z{sp}"])):
+            d[lab] = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
+        ph = phi[orbs][:, nodes].cpu().numpy()
+        d["phi"] = np.abs(ph - flo[f"phi{sp}"]).max() / np.abs(flo[f"phi{sp}"]).max()
+        Zh, Sh = Z.cpu().numpy(), S.cpu().numpy()
+        d["ZSZ-I"] = np.abs(Zh @ Sh @ Zh - np.eye(Zh.shape[0])).max()
+        rel = MOL192_REL_PER_COND * terms["cond_S"][sp]
+        _say(f"mol192 spin {sp} (cond S {terms['cond_S'][sp]:.2e}, bound {rel:.1e}): max relative "
+             "deviation from the oracle " + ", ".join(f"{k} {v:.2e}" for k, v in d.items()))
+        # S = T G T^T with G a sum over 7.1e6 grid nodes, taken in other
+        # orders on the two sides (observed 1.0e-12)
+        assert d["T"] < 1e-12 and d["S"] < 1e-11, d
+        assert d["Z"] < rel and d["phi"] < rel, d
+        assert d["ZSZ-I"] < 1e-8, d
+        del T, G, S, Z, phi
+    torch.cuda.empty_cache()
+
+    _say("mol192: GPU forward + backward (mixed)")
+    ctx = F.Context(precision="mixed", tol=TOL, flags=_flags(F))
+    dd = _dict(torch, s)
+    e, U, X, st = ctx.forward([dd])
+    g = ctx.backward([list(s.nocc)])[0]
+    assert st["max_relres"] <= TOL
+    ctx.close()
+    for sp in range(2):
+        base = 0 if sp == 0 else s.nocc[0]
+        du = max(abs(U[base + i] - u) for i, u in zip(orbs, terms["U"][sp]))
+        dx = max(abs(X[base + i] - x) for i, x in zip(orbs, terms["X"][sp]))
+        _say(f"mol192 spin {sp}: max |dU_i| = {du:.2e}, max |dX_i| = {dx:.2e} Ha (orbitals {orbs})")
+        assert du < MOL192_TERM_TOL and dx < MOL192_TERM_TOL
+
+    eps = 1e-4
+    fctx = F.Context(precision="fp64", tol=1e-12)
+    base = {"n": s.n, "h": s.h, "origin": s.origin, "psi": list(s.psi)}
+    e64 = fctx.forward([dict(base, fod=list(s.fod))])[0][0]
+    _say(f"mol192: E_SIC mixed {e[0]:.12f}, FP64 {e64:.12f}, |dE| = {abs(e[0] - e64):.2e}")
+    assert abs(e[0] - e64) < E_TOL
+    for (sp, i, dd_) in _fd_coords(s, 8, 192, eps):
+        f = [x.copy() for x in s.fod]
+        f[sp][i, dd_] += eps
+        ep = fctx.forward([dict(base, fod=f)])[0][0]
+        f[sp][i, dd_] -= 2 * eps
+        em = fctx.forward([dict(base, fod=f)])[0][0]
+        fd = (ep - em) / (2 * eps)
+        _say(f"mol192: spin {sp} FOD {i} axis {dd_}: adjoint {g[sp][i, dd_]:+.9e} FD {fd:+.9e}")
+        assert abs(fd - g[sp][i, dd_]) < F_TOL
+    fctx.close()
