@@ -75,6 +75,11 @@ struct PcgOut {
     const double *rzc;   // r_k.z_k partial sums
     const double *rzp;   // r_{k-1}.z_{k-1} partial sums
     int first;           // 1: beta = 0 (first iteration of a restart cycle)
+    // mixed restart cycles: an orbital with pz[o] <= li (the cycle's local
+    // iteration of this application) is paused for the rest of the cycle
+    // and skipped like a converged one (pz null: none)
+    const int *pz;
+    int li;
 };
 
 // panel columns of a fast transform variant's x and y passes (the z pass

@@ -125,8 +125,9 @@ __global__ __launch_bounds__(kFT, OCC2 ? 4 : 2) void k_dst_fast(const Item *unit
     const int t = threadIdx.x;
     const int u0 = (int)((long long)blockIdx.x * nunits / gridDim.x);
     const int u1 = (int)((long long)(blockIdx.x + 1) * nunits / gridDim.x);
-    auto next_active = [&](int u) {  // done[] does not change during this launch: uniform
-        while (u < u1 && (units[u].orb < 0 || done[units[u].orb])) ++u;
+    auto next_active = [&](int u) {  // done[] and pz[] do not change during this launch: uniform
+        while (u < u1 && (units[u].orb < 0 || done[units[u].orb] || (po.pz && po.pz[units[u].orb] <= po.li)))
+            ++u;
         return u;
     };
 
@@ -461,8 +462,9 @@ __global__ __launch_bounds__(kFT, OCC2 ? 4 : 2) void k_dst_xy(const Item *units,
     const int t = threadIdx.x;
     const int u0 = (int)((long long)blockIdx.x * nunits / gridDim.x);
     const int u1 = (int)((long long)(blockIdx.x + 1) * nunits / gridDim.x);
-    auto next_active = [&](int u) {  // done[] does not change during this launch: uniform
-        while (u < u1 && (units[u].orb < 0 || done[units[u].orb])) ++u;
+    auto next_active = [&](int u) {  // done[] and pz[] do not change during this launch: uniform
+        while (u < u1 && (units[u].orb < 0 || done[units[u].orb] || (po.pz && po.pz[units[u].orb] <= po.li)))
+            ++u;
         return u;
     };
     // VEC (every nx and orbital offset a multiple of 4): planes move as
@@ -737,7 +739,8 @@ hipError_t dst_apply(const DstItems &di, const OrbDesc *orb, const int *done, co
     if (!di.fast) return hipErrorInvalidValue;  // the host solves such batches without it
     const float *wk = work;
     int *nc = nullptr;
-    const PcgOut none{nullptr, nullptr, nullptr, 1};
+    // forward and middle passes: no p output, but the pause state of po
+    const PcgOut none{nullptr, nullptr, nullptr, 1, po.pz, po.li};
     const bool pv = dst_early_pold();
     auto grid = [&](int units) { return dim3((unsigned)std::min(units, di.blocks)); };
 #define FSIC_DST_FAST(PC_, SLO_, NPM_)                                                                \
@@ -817,8 +820,8 @@ template <typename T>
 hipError_t launch_dst_precond(const DstItems &di, const OrbDesc *orb, const int *done,
                               const float *tab, const T *r, float *work, float *z, double *rz,
                               int *cnt, hipStream_t s) {
-    return dst_apply<T, false>(di, orb, done, tab, r, work, z, rz, PcgOut{nullptr, nullptr, nullptr, 1},
-                               cnt, s);
+    return dst_apply<T, false>(di, orb, done, tab, r, work, z, rz,
+                               PcgOut{nullptr, nullptr, nullptr, 1, nullptr, 0}, cnt, s);
 }
 
 // p = M^{-1} r + beta p_old for the orbitals of the batch, with r.z partial sums.

@@ -87,12 +87,25 @@ hipError_t launch_pcg_update(const CGIter<T> &a, int k, int x_first, hipStream_t
 // checked on the FP64 residual).  Sweep of iteration k: q_k = -L p_k with the
 // p_k.q_k partials in part7 slice (k & 1); p_k was formed by the last
 // preconditioner pass.
-hipError_t launch_pcg_sweep(int radius, const Coeffs &c, const CGIter<float> &a, int k, hipStream_t s);
+hipError_t launch_pcg_sweep(int radius, const Coeffs &c, const CGIter<float> &a, int k, const int *pz,
+                            int li, hipStream_t s);
 
 // Update after the sweep of iteration k: alpha_k = r_k.z_k / p_k.q_k,
-// r_{k+1} = r_k - alpha_k q_k; xmode 1: x = alpha_k p_k, 2: x += alpha_k p_k
-// (0: x untouched; the residual pass adds the last steps itself).
-hipError_t launch_pcg_rupdate(const CGIter<float> &a, int k, int xmode, hipStream_t s);
+// r_{k+1} = r_k - alpha_k q_k with its r.r partials (part8 slice (k+1) & 1);
+// xmode 1: x = alpha_k p_k, 2: x += alpha_k p_k (0: x untouched; the residual
+// pass adds the last steps itself).  li: the cycle's local index of
+// iteration k + 1; orbitals paused before it (pz[o] < li) are skipped.
+hipError_t launch_pcg_rupdate(const CGIter<float> &a, int k, int xmode, const int *pz, int li,
+                              hipStream_t s);
+
+// Pause check after that update: an orbital not paused before local
+// iteration li whose r_{k+1}.r_{k+1} <= ftol2 ||b||^2 is paused from li on
+// (pz[o] = li) for the rest of the cycle; the residual pass that closes the
+// cycle decides its convergence.
+hipError_t launch_pause_check(const CGIter<float> &a, int k, double ftol2, int *pz, int li, hipStream_t s);
+
+// p[i] = v for n ints (a fill kernel, usable inside a captured graph)
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s);
 
 // FP64 residual of x = x64 + x32 + alpha_a p_a + alpha_b p_b at the end of a
 // restart cycle (alpha_j = r_j.z_j / p_j.q_j from the partials of
@@ -107,6 +120,8 @@ struct ResStep {
     int ka, kb;
     double *X64new;
     float *R32;
+    const int *pz;  // paused orbitals: a step of local iteration >= pz[o] did not run
+    int la, lb;     // local iterations of ka and kb
 };
 hipError_t launch_res_steps(int radius, const Coeffs &c, const CGIter<float> &a, const ResStep &rs,
                             hipStream_t s);
@@ -130,10 +145,11 @@ hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDes
                                    const int *done, double *X64, const float *X32, hipStream_t s);
 
 // mixed precision: mark orbitals whose FP64 residual (partRU) meets tol;
-// counts them in *ndone (if not null) and stores xfin in fin[o] (if not null)
+// counts them in *ndone (if not null), stores xfin in fin[o] (if not null)
+// and resets the pause of the others (pz[o] = cyc, if pz is not null)
 hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
                            double tol2, int k, int *done, int *iters, double *rrfin, int *rs_iter,
-                           int *ndone, int *fin, int xfin, hipStream_t s);
+                           int *ndone, int *fin, int xfin, int *pz, int cyc, hipStream_t s);
 
 // per orbital: out[o] = sum of partials (stencil layout if stencil_layout,
 // else pointwise slot range starting at the parity-0 block)

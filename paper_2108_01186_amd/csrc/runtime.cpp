@@ -229,6 +229,7 @@ struct fsic_ctx {
     DBuf<double> bmat;
     int *h_done = nullptr;  // pinned
     DBuf<int> ndone, fin;   // converged-orbital counter; buffer holding each final x (mixed PCG)
+    DBuf<int> pz;           // mixed PCG: local iteration from which an orbital pauses in its cycle
     int *h_nd = nullptr;    // pinned: two copies of the counter, one per cycle parity
     hipEvent_t evc[2] = {nullptr, nullptr};
     int pred_cycles = 0;    // restart cycles the last mixed solve needed (host checks skipped before)
@@ -643,6 +644,7 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     HIPCHK(c, c->nact.ensure(6 * (size_t)norb));
     HIPCHK(c, c->ndone.ensure(1));
     HIPCHK(c, c->fin.ensure(norb));
+    HIPCHK(c, c->pz.ensure(norb));
     if (!c->h_nd) HIPCHK(c, hipHostMalloc((void **)&c->h_nd, 2 * sizeof(int)));
     for (hipEvent_t &e : c->evc)
         if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1010,7 +1012,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             HIPCHK(c, launch_true_residual(c->radius, c->cf, c->d_items7.p, nit7, c->d_orb.p, c->done.p,
                                            X, nullptr, c->B.p, nullptr, c->R32.p, c->partRU.p, s));
             HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, k, c->done.p,
-                                      c->iters.p, c->rrfin.p, c->rs_iter.p, nullptr, nullptr, 0, s));
+                                      c->iters.p, c->rrfin.p, c->rs_iter.p, nullptr, nullptr, 0, nullptr, 0, s));
             if (k % kAarCheck == kAarCheck - 1 || k == max_iter) {
                 HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(c, hipStreamSynchronize(s));
@@ -1062,6 +1064,10 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         float *const P2[2] = {c->P32a.p, c->P32b.p};
         HIPCHK(c, hipMemsetAsync(c->ndone.p, 0, sizeof(int), s));
         HIPCHK(c, hipMemsetAsync(c->fin.p, 0xff, norb * sizeof(int), s));
+        HIPCHK(c, launch_fill_int(c->pz.p, norb, cyc, s));
+        // an orbital whose FP32 recursion has reached half the tolerance
+        // pauses for the rest of its cycle (its residual pass decides)
+        const double ftol2 = 0.25 * tol2;
         // cycle variant v: 0 the first (x64 = 0), 1 odd, 2 even (>= 2); the
         // launches depend on v only (iteration indices enter by parity)
         auto cycle = [&](hipStream_t s, int v) -> fsic_status {
@@ -1074,16 +1080,17 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                 const int k = ks + i;
                 const bool last = i == cyc - 1;
                 PcgOut po{nullptr, a.partRZ + (size_t)(k & 1) * b.tot9,
-                          a.partRZ + (size_t)((k + 1) & 1) * b.tot9, 1};
+                          a.partRZ + (size_t)((k + 1) & 1) * b.tot9, 1, c->pz.p, i};
                 if (i > 0) {
                     const int m = i - 1;  // x32 takes the steps of iterations 0 .. cyc - 3
                     const int xmode = m <= cyc - 3 ? (m == 0 ? 1 : 2) : 0;
                     a.P = P2[(k - 1) & 1];
                     {
                         PROF_BEGIN(1, last && samp ? 1 : 0, 0)
-                        HIPCHK(c, launch_pcg_rupdate(a, k - 1, xmode, s));
+                        HIPCHK(c, launch_pcg_rupdate(a, k - 1, xmode, c->pz.p, i, s));
                         PROF_END()
                     }
+                    HIPCHK(c, launch_pause_check(a, k - 1, ftol2, c->pz.p, i, s));
                     po.pold = P2[(k - 1) & 1];
                     po.first = 0;
                 }
@@ -1097,12 +1104,13 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                 a.P = P2[k & 1];
                 {
                     PROF_BEGIN(0, last && samp ? 1 : 0, 0)
-                    HIPCHK(c, launch_pcg_sweep(c->radius, c->cf, a, k, s));
+                    HIPCHK(c, launch_pcg_sweep(c->radius, c->cf, a, k, c->pz.p, i, s));
                     PROF_END()
                 }
             }
             const int ka = ks + cyc - 2, kb = ks + cyc - 1;
-            ResStep rs{Xc, cyc > 2 ? c->X32.p : nullptr, P2[ka & 1], P2[kb & 1], ka, kb, Xn, c->R32.p};
+            ResStep rs{Xc, cyc > 2 ? c->X32.p : nullptr, P2[ka & 1], P2[kb & 1], ka, kb, Xn, c->R32.p,
+                       c->pz.p, cyc - 2, cyc - 1};
             {
                 PROF_BEGIN(3, samp ? 1 : 0, 0)
                 HIPCHK(c, launch_res_steps(c->radius, c->cf, a, rs, s));
@@ -1110,7 +1118,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             }
             HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, 0, c->done.p,
                                       c->iters.p, c->rrfin.p, nullptr, c->ndone.p, c->fin.p,
-                                      Xn == xs[1] ? 1 : 0, s));
+                                      Xn == xs[1] ? 1 : 0, c->pz.p, cyc, s));
             return FSIC_OK;
         };
         auto issue = [&](int j) -> fsic_status {
@@ -1131,7 +1139,8 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                         (const void *)a0.partRU, (const void *)a0.partRZ,
                                         (const void *)a0.done, (const void *)a0.iters, (const void *)a0.rrfin,
                                         (const void *)a0.bb, (const void *)a0.nact, (const void *)a0.ndone,
-                                        (const void *)c->fin.p, (const void *)xs[0], (const void *)xs[1],
+                                        (const void *)c->fin.p, (const void *)c->pz.p,
+                                        (const void *)xs[0], (const void *)xs[1],
                                         (const void *)P2[0], (const void *)P2[1], (const void *)c->T32.p,
                                         (const void *)c->dtab.p, (const void *)di.x, (const void *)di.y,
                                         (const void *)di.z, (const void *)di.xy})
@@ -1254,7 +1263,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                            c->partRU.p, s));
             HIPCHK(c, launch_mixed_accumulate(nit8, c->d_items8.p, c->d_orb.p, c->done.p, X, c->X32.p, s));
             HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, k, c->done.p,
-                                      c->iters.p, c->rrfin.p, c->rs_iter.p, nullptr, nullptr, 0, s));
+                                      c->iters.p, c->rrfin.p, c->rs_iter.p, nullptr, nullptr, 0, nullptr, 0, s));
             ++nref;
             HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));
@@ -1465,7 +1474,7 @@ void fsic_destroy(fsic_ctx *c) {
     if (c->h_chk) hipHostFree(c->h_chk);
     for (hipEvent_t e : c->evc)
         if (e) hipEventDestroy(e);
-    c->ndone.release(); c->fin.release();
+    c->ndone.release(); c->fin.release(); c->pz.release();
     delete c;
 }
 

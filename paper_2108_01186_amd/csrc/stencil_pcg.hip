@@ -92,16 +92,18 @@ template hipError_t launch_pcg_stencil<float>(int, const Coeffs &, const CGIter<
 template hipError_t launch_pcg_update<double>(const CGIter<double> &, int, int, hipStream_t);
 template hipError_t launch_pcg_update<float>(const CGIter<float> &, int, int, hipStream_t);
 
-// mixed restart cycles: r -= alpha q (and the x modes of launch_pcg_rupdate)
-__global__ __launch_bounds__(256) void k_pcg_rupd(CGIter<float> a, int k, int xmode) {
+// mixed restart cycles: r -= alpha q with the new r.r partials (and the x
+// modes of launch_pcg_rupdate)
+__global__ __launch_bounds__(256) void k_pcg_rupd(CGIter<float> a, int k, int xmode, const int *pz, int li) {
     __shared__ double sred[4];
     const Item it = a.items8[blockIdx.x];
     if (it.orb < 0) return;
-    if (a.done[it.orb]) return;
+    if (a.done[it.orb] || (pz && pz[it.orb] < li)) return;
     const OrbDesc od = a.orb[it.orb];
     const float al = (float)alpha_of(a, od, k, sred);
     const long long M = (long long)od.nx * od.ny * od.nz;
     const long long base = (long long)it.tile * kPW;
+    double acc = 0.0;
     if (((od.off | M) & 3) == 0) {
 #pragma unroll
         for (int e = 0; e < kPW / 1024; ++e) {
@@ -111,6 +113,7 @@ __global__ __launch_bounds__(256) void k_pcg_rupd(CGIter<float> a, int k, int xm
                 float4 rv = *reinterpret_cast<const float4 *>(a.R + g);
                 const float4 qv = *reinterpret_cast<const float4 *>(a.Q + g);
                 rv.x -= al * qv.x; rv.y -= al * qv.y; rv.z -= al * qv.z; rv.w -= al * qv.w;
+                acc += (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z + (double)rv.w * rv.w;
                 *reinterpret_cast<float4 *>(a.R + g) = rv;
                 if (xmode) {
                     const float4 pv = *reinterpret_cast<const float4 *>(a.P + g);
@@ -127,29 +130,64 @@ __global__ __launch_bounds__(256) void k_pcg_rupd(CGIter<float> a, int k, int xm
             const long long i = base + e * 256 + threadIdx.x;
             if (i < M) {
                 const long long g = od.off + i;
-                a.R[g] -= al * a.Q[g];
+                const float rv = a.R[g] - al * a.Q[g];
+                a.R[g] = rv;
+                acc += (double)rv * rv;
                 if (xmode) a.X[g] = (xmode == 2 ? a.X[g] : 0.f) + al * a.P[g];
             }
         }
     }
-    if (threadIdx.x == 0 && it.tile == 0) {
-        a.nact[a.norb + it.orb] += 1;
-        if (a.nsamp) a.nsamp[a.norb + it.orb] += 1;
+    const double ssum = block_sum256(acc, sred);
+    if (threadIdx.x == 0) {
+        a.part8[(size_t)((k + 1) & 1) * a.tot8 + od.base8 + it.tile] = ssum;
+        if (it.tile == 0) {
+            a.nact[a.norb + it.orb] += 1;
+            if (a.nsamp) a.nsamp[a.norb + it.orb] += 1;
+        }
     }
 }
 
-hipError_t launch_pcg_sweep(int radius, const Coeffs &c, const CGIter<float> &a, int k, hipStream_t s) {
+// pause check: one block per orbital
+__global__ __launch_bounds__(256) void k_pause_check(CGIter<float> a, int k, double ftol2, int *pz, int li) {
+    __shared__ double sred[4];
+    const int o = blockIdx.x;
+    if (a.done[o] || pz[o] < li) return;  // converged, or paused before this update ran
+    const OrbDesc od = a.orb[o];
+    const double rr = sum_partials(a.part8 + (size_t)((k + 1) & 1) * a.tot8 + od.base8, od.nt8, sred);
+    if (threadIdx.x == 0 && rr <= ftol2 * a.bb[o]) pz[o] = li;
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_pcg_sweep(int radius, const Coeffs &c, const CGIter<float> &a, int k, const int *pz,
+                            int li, hipStream_t s) {
     if (a.nitems7 <= 0) return hipSuccess;
-    PolPQ pol{a.items7, a.orb, a, k, false};
+    PolPQ pol{a.items7, a.orb, a, k, pz, li, false};
 #define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<float, P, C, DD, PolPQ>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
     FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_rupdate(const CGIter<float> &a, int k, int xmode, hipStream_t s) {
+hipError_t launch_pcg_rupdate(const CGIter<float> &a, int k, int xmode, const int *pz, int li,
+                              hipStream_t s) {
     if (a.nitems8 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pcg_rupd, dim3(a.nitems8), dim3(256), 0, s, a, k, xmode);
+    hipLaunchKernelGGL(k_pcg_rupd, dim3(a.nitems8), dim3(256), 0, s, a, k, xmode, pz, li);
+    return hipGetLastError();
+}
+
+hipError_t launch_pause_check(const CGIter<float> &a, int k, double ftol2, int *pz, int li, hipStream_t s) {
+    if (a.norb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pause_check, dim3(a.norb), dim3(256), 0, s, a, k, ftol2, pz, li);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_mixed_accumulate(const Item *items8, co
 __global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const double *partRU,
                                                   const double *bb, double tol2, int k, int *done,
                                                   int *iters, double *rrfin, int *rs_iter, int *ndone,
-                                                  int *fin, int xfin) {
+                                                  int *fin, int xfin, int *pz, int cyc) {
     __shared__ double sred[4];
     const int o = blockIdx.x;
     if (done[o] == 1) return;
@@ -51,6 +51,8 @@ __global__ __launch_bounds__(256) void k_ru_check(const OrbDesc *orb, const doub
             rrfin[o] = rr;
             if (ndone) atomicAdd(ndone, 1);
             if (fin) fin[o] = xfin;
+        } else if (pz) {
+            pz[o] = cyc;  // not confirmed: the next cycle runs in full
         } else if (done[o] == 2) {
             // the FP32 recursion met tol but the FP64 residual did not:
             // resume with a restart from the FP64 residual
@@ -97,10 +99,10 @@ hipError_t launch_mixed_accumulate(int nitems8, const Item *items8, const OrbDes
 
 hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, const double *bb,
                            double tol2, int k, int *done, int *iters, double *rrfin, int *rs_iter,
-                           int *ndone, int *fin, int xfin, hipStream_t s) {
+                           int *ndone, int *fin, int xfin, int *pz, int cyc, hipStream_t s) {
     if (norb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ru_check, dim3(norb), dim3(256), 0, s, orb, partRU, bb, tol2, k, done,
-                       iters, rrfin, rs_iter, ndone, fin, xfin);
+                       iters, rrfin, rs_iter, ndone, fin, xfin, pz, cyc);
     return hipGetLastError();
 }
 

@@ -445,9 +445,11 @@ struct PolPQ {
     const OrbDesc *orb;
     CGIter<float> a;
     int k;
+    const int *pz;  // paused orbitals (pz[o] <= li) are skipped
+    int li;
     bool tile0;
     __device__ bool setup(int o, const OrbDesc &, double *sbuf) {
-        if (threadIdx.x == 0) sbuf[0] = (double)a.done[o];
+        if (threadIdx.x == 0) sbuf[0] = (double)(a.done[o] || (pz && pz[o] <= li));
         __syncthreads();
         const bool dn = sbuf[0] != 0.0;
         __syncthreads();
@@ -502,8 +504,10 @@ struct PolResP {
     Rsrc rx, rx32, rpa, rpb, rb, rxn, rr32;
     __device__ bool setup(int o, const OrbDesc &od, double *sbuf) {
         if (a.done[o] == 1) return false;  // not changed during this launch: uniform
-        aa = alpha_of(a, od, r.ka, sbuf);
-        ab = alpha_of(a, od, r.kb, sbuf);
+        // steps of iterations at or after the pause of o did not run
+        const int p = r.pz ? r.pz[o] : (1 << 30);
+        aa = r.la < p ? alpha_of(a, od, r.ka, sbuf) : 0.0;
+        ab = r.lb < p ? alpha_of(a, od, r.kb, sbuf) : 0.0;
         if (threadIdx.x == 0 && tile0 && a.nsamp) a.nsamp[3 * a.norb + o] += 1;
         return true;
     }
