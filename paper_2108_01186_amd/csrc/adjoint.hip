@@ -18,43 +18,6 @@ namespace fsic {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// regular solid harmonics (same construction as the multipole kernels)
-template <int L>
-__device__ __forceinline__ void solid_harmonics_adj(double x, double y, double z, const double *norm,
-                                                    double *R) {
-    const double r2 = x * x + y * y + z * z;
-    double cm = 1.0, sm = 0.0, dfact = 1.0;
-#pragma unroll
-    for (int m = 0; m <= L; ++m) {
-        if (m > 0) {
-            const double c2 = cm * x - sm * y;
-            sm = cm * y + sm * x;
-            cm = c2;
-            dfact *= (double)(2 * m - 1);
-        }
-        double pm2 = 0.0, pm1 = 0.0;
-#pragma unroll
-        for (int l = m; l <= L; ++l) {
-            double pl;
-            if (l == m)
-                pl = dfact;
-            else if (l == m + 1)
-                pl = (double)(2 * m + 1) * z * pm1;
-            else
-                pl = ((double)(2 * l - 1) * z * pm1 - (double)(l + m - 1) * r2 * pm2) *
-                     (1.0 / (double)(l - m));  // compile-time reciprocal: no FP64 divide
-            pm2 = pm1;
-            pm1 = pl;
-            if (m == 0) {
-                R[l * l + l] = norm[l * l + l] * pl;
-            } else {
-                R[l * l + l + m] = norm[l * l + l + m] * cm * pl;
-                R[l * l + l - m] = norm[l * l + l - m] * sm * pl;
-            }
-        }
-    }
-}
-
 // fully polarised LSDA potential (same parameterisation as the forward pass)
 __device__ __forceinline__ double vxc_pol(double rho, double floor) {
     if (!(rho > floor)) return 0.0;
@@ -273,62 +236,6 @@ __global__ __launch_bounds__(256) void k_lowdin_backward(int N, const double *Bm
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-
-// W_o += dV sum_lm zt_o,lm r^l Y_lm (the P^T part of A^T rho) for every
-// orbital o of a channel: the harmonics of a node are built once and applied
-// to all of the channel's orbitals (their coefficients staged in LDS).
-template <int L>
-__global__ __launch_bounds__(256) void k_adj_field_grp(HarmTables ht, const OrbDesc *orb,
-                                                       const GroupItem *items, const double *Zt,
-                                                       double *W) {
-    constexpr int NLM = (L + 1) * (L + 1);
-    extern __shared__ double sz[];  // count x NLM
-    const GroupItem it = items[blockIdx.x];
-    const OrbDesc od = orb[it.first];
-    for (int e = threadIdx.x; e < it.count * NLM; e += 256) sz[e] = Zt[(size_t)it.first * NLM + e];
-    __syncthreads();
-    const long long M = (long long)od.nx * od.ny * od.nz;
-    const double dV = od.h * od.h * od.h;
-    const long long base = (long long)it.tile * kAdjTile;
-    for (int e = 0; e < kAdjTile / 256; ++e) {
-        const long long i = base + e * 256 + threadIdx.x;
-        if (i >= M) continue;
-        // node indices in 32 bits (at most 2^29 nodes per orbital)
-        const int ii = (int)i, pxy = od.nx * od.ny;
-        const int iz = ii / pxy, rem = ii - iz * pxy;
-        const int iy = rem / od.nx, ix = rem - iy * od.nx;
-        double R[NLM];
-        solid_harmonics_adj<L>(od.origin[0] + od.h * ix - od.centre[0],
-                               od.origin[1] + od.h * iy - od.centre[1],
-                               od.origin[2] + od.h * iz - od.centre[2], ht.norm, R);
-        for (int o = 0; o < it.count; ++o) {
-            double f = 0.0;
-#pragma unroll
-            for (int q = 0; q < NLM; ++q) f += sz[o * NLM + q] * R[q];
-            W[od.off + (long long)o * M + i] += dV * f;
-        }
-    }
-}
-
-hipError_t launch_adj_field_groups(int lmax, const HarmTables &ht, const OrbDesc *orb,
-                                   const GroupItem *items, int nitems, int max_count,
-                                   const double *Zt, double *W, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    const size_t lds = (size_t)max_count * (lmax + 1) * (lmax + 1) * sizeof(double);
-    switch (lmax) {
-#define CASE(L)                                                                                    \
-    case L:                                                                                        \
-        if (lds > 65536)                                                                           \
-            hipFuncSetAttribute((const void *)k_adj_field_grp<L>,                                  \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
-        hipLaunchKernelGGL(k_adj_field_grp<L>, dim3(nitems), dim3(256), lds, s, ht, orb, items, Zt, W); \
-        break;
-        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-#undef CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,
                                     const double *W, const double *psi, double floor, double *partB,

@@ -234,15 +234,40 @@ struct HarmTables {
     double gfac[kMaxLM];   // 4 pi / (2l + 1)
 };
 
-// Q[o][lm] = dV sum_r rho_o(r) |r-c|^l Y_lm; rho = src^2 if square else src.
-hipError_t launch_moments(int lmax, const HarmTables &ht, int norb, const OrbDesc *orb,
-                          const Item *items8, int nitems8, const double *src, int square,
-                          double *partQ, int tot8, double *Q, hipStream_t s);
+// Harmonic contractions of one channel's orbitals on the matrix cores (the
+// harmonics built once per node for all of them): mode 0, the moments
+// Q[o][lm] = dV sum_r rho_o(r) r^l Y_lm (rho = src^2 if square); mode 1, the
+// adjoint boundary term zt[o][lm] = sum_ghost gfac_lm Y_lm / r^(l+1)
+// (C^T w_o)_ghost with src = w (square 0).  Work items: per block a
+// contiguous range of 64-node chunks of one channel and the offset of its
+// partial tile; per channel its partial tiles, which the second kernel adds
+// in item order (a fixed order: the result does not depend on timing).
+struct HcItem {
+    int first, count;  // orbitals of the channel
+    int t0, t1;        // chunks [t0, t1) of 64 nodes (grid nodes or ghosts)
+    long long poff;    // element offset of this block's partial tile
+};
+struct HcChan {
+    int first, count;  // orbitals of the channel
+    int nparts;        // its partial tiles, consecutive from poff
+    long long poff;
+};
+// rows of a partial tile: (kMaxL + 1)^2 harmonics padded to 16; columns: the
+// channel's orbitals padded to 16
+constexpr int kHcRows = (kMaxLM + 15) / 16 * 16;
+hipError_t launch_harm_contract(int mode, int lmax, const HarmTables &ht, const Coeffs &c, int radius,
+                                const OrbDesc *orb, const long long *ghost_count, const HcItem *items,
+                                int nitems, const HcChan *chans, int nchans, int max_count,
+                                const double *src, int square, double *part, double *out, hipStream_t s);
 
-// ghost values on the face slabs: g[o] = sum_lm gfac Q_lm Y_lm / r^(l+1)
-hipError_t launch_ghosts(int radius, int lmax, const HarmTables &ht, int norb,
-                         const OrbDesc *orb, const long long *ghost_count, const double *Q,
-                         double *G, long long max_ghost, hipStream_t s);
+// Harmonic expansions of one channel's orbitals on the matrix cores: mode 0,
+// the ghost values g_o = sum_lm gfac_lm Q[o][lm] Y_lm / r^(l+1) on the face
+// slabs (written to out = G); mode 1, the multipole part of the adjoint
+// field, W_o += dV sum_lm zt[o][lm] r^l Y_lm on the grid.  items: the
+// ghost-chunk (mode 0) or node-chunk (mode 1) list of launch_harm_contract.
+hipError_t launch_harm_expand(int mode, int lmax, const HarmTables &ht, int radius, const OrbDesc *orb,
+                              const long long *ghost_count, const HcItem *items, int nitems, int max_count,
+                              const double *C, double *out, hipStream_t s);
 
 // b = scale * rho + (boundary term of the ghosts, if G != null); writes B,
 // R64 or R32 = b, optionally X64 = 0, and b.b partials into part8 slot 0.
@@ -250,12 +275,6 @@ hipError_t launch_rhs(int radius, const Coeffs &c, const Item *items8, int nitem
                       const OrbDesc *orb, const double *src, int square, double scale,
                       const double *G, double *B, double *R64, float *R32, double *X64zero,
                       double *part8, hipStream_t s);
-
-// Adjoint boundary term: zt[o][lm] = sum_ghost gfac Y_lm / r^(l+1) (C^T w)_ghost
-hipError_t launch_adjoint_boundary(int radius, int lmax, const HarmTables &ht, const Coeffs &c,
-                                   int norb, const OrbDesc *orb, const long long *ghost_count,
-                                   const double *W, double *partZ, int zchunks, double *Zt,
-                                   long long max_ghost, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // xc.hip: LSDA at full polarisation, Slater average, energies, adjoint source
@@ -339,23 +358,9 @@ hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *ps
 hipError_t launch_orb_gemm32(int N, long long M, const double *A, const double *psi, double *out,
                              hipStream_t s);
 
-// Work item of the per-channel adjoint field: orbitals first .. first+count-1
-// share one grid; tile: kAdjTile nodes of it.
-struct GroupItem {
-    int first, count, tile;
-};
-constexpr int kAdjTile = 1024;
-
 // Nodes of one channel per block of the Slater average (its partial sums
 // come one per such block).
 constexpr int kSicTile = 1024;
-
-// W_o += P^T zt_o (the multipole part of A^T rho_o) for every orbital: the
-// solid harmonics of a node are built once for all orbitals of its channel
-// (Zt staged in LDS).  max_count: most orbitals in one channel.
-hipError_t launch_adj_field_groups(int lmax, const HarmTables &ht, const OrbDesc *orb,
-                                   const GroupItem *items, int nitems, int max_count,
-                                   const double *Zt, double *W, hipStream_t s);
 
 // B[i][a] = sum_m Gam_i(m) psi_a(m) with Gam_i = 2 dV phi_i omega_i built on
 // the fly, omega_i = -((v_i + w_i) / 2 + vxc(phi_i^2)) (MFMA FP64)

@@ -11,180 +11,7 @@
 
 namespace fsic {
 
-// Calls f(q, l, r^l Y_lm(x, y, z)) for q = l*l + l + m, every l <= L, in the
-// order the recurrence produces the values (real, orthonormal, no
-// Condon-Shortley phase).  Consuming each value at once keeps few of them
-// live, so accumulating kernels need no harmonic array in registers.
-template <int L, class F>
-__device__ __forceinline__ void visit_regular_harmonics(double x, double y, double z, const double *norm,
-                                                        F &&f) {
-    const double r2 = x * x + y * y + z * z;
-    double cm = 1.0, sm = 0.0;  // Re, Im of (x + i y)^m
-    double dfact = 1.0;         // (2m - 1)!!
-#pragma unroll
-    for (int m = 0; m <= L; ++m) {
-        if (m > 0) {
-            const double c2 = cm * x - sm * y;
-            sm = cm * y + sm * x;
-            cm = c2;
-            dfact *= (double)(2 * m - 1);
-        }
-        double pm2 = 0.0, pm1 = 0.0;
-#pragma unroll
-        for (int l = m; l <= L; ++l) {
-            double pl;
-            if (l == m)
-                pl = dfact;
-            else if (l == m + 1)
-                pl = (double)(2 * m + 1) * z * pm1;
-            else
-                pl = ((double)(2 * l - 1) * z * pm1 - (double)(l + m - 1) * r2 * pm2) *
-                     (1.0 / (double)(l - m));  // compile-time reciprocal: no FP64 divide
-            pm2 = pm1;
-            pm1 = pl;
-            if (m == 0) {
-                f(l * l + l, l, norm[l * l + l] * pl);
-            } else {
-                f(l * l + l + m, l, norm[l * l + l + m] * cm * pl);
-                f(l * l + l - m, l, norm[l * l + l - m] * sm * pl);
-            }
-        }
-    }
-}
-
-// R[l*l + l + m] = r^l Y_lm(x, y, z)
-template <int L>
-__device__ __forceinline__ void regular_harmonics(double x, double y, double z, const double *norm,
-                                                  double *R) {
-    visit_regular_harmonics<L>(x, y, z, norm, [&](int q, int, double v) { R[q] = v; });
-}
-
-// ---------------------------------------------------------------------------
-// moments Q_lm = dV sum_r rho(r) R_lm(r - c)
-// ---------------------------------------------------------------------------
-
-template <int L>
-__global__ __launch_bounds__(256) void k_moments(HarmTables ht, const OrbDesc *orb,
-                                                 const Item *items, const double *src, int square,
-                                                 double *partQ) {
-    constexpr int NLM = (L + 1) * (L + 1);
-    __shared__ double sw[4][NLM];
-    const Item it = items[blockIdx.x];
-    if (it.orb < 0) return;
-    const OrbDesc od = orb[it.orb];
-    const long long M = (long long)od.nx * od.ny * od.nz;
-    double acc[NLM];
-#pragma unroll
-    for (int q = 0; q < NLM; ++q) acc[q] = 0.0;
-    const long long base = (long long)it.tile * kPW;
-    for (int e = 0; e < kPW / 256; ++e) {
-        const long long i = base + e * 256 + threadIdx.x;
-        if (i < M) {
-            // node indices in 32 bits (at most 2^29 nodes per orbital)
-            const int ii = (int)i, pxy = od.nx * od.ny;
-            const int iz = ii / pxy, rem = ii - iz * pxy;
-            const int iy = rem / od.nx, ix = rem - iy * od.nx;
-            const double sv = src[od.off + i];
-            const double rho = square ? sv * sv : sv;
-            visit_regular_harmonics<L>(od.origin[0] + od.h * ix - od.centre[0],
-                                       od.origin[1] + od.h * iy - od.centre[1],
-                                       od.origin[2] + od.h * iz - od.centre[2], ht.norm,
-                                       [&](int q, int, double v) { acc[q] += rho * v; });
-        }
-    }
-    const int w = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NLM; ++q) {
-        const double v = wave_sum(acc[q]);
-        if ((threadIdx.x & 63) == 0) sw[w][q] = v;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < NLM; q += 256)
-        partQ[(size_t)(od.base8 + it.tile) * NLM + q] = (sw[0][q] + sw[1][q]) + (sw[2][q] + sw[3][q]);
-}
-
-__global__ __launch_bounds__(256) void k_moments_final(int nlm, const OrbDesc *orb,
-                                                       const double *partQ, double *Q) {
-    const int o = blockIdx.x;
-    const OrbDesc od = orb[o];
-    const double dV = od.h * od.h * od.h;
-    for (int q = threadIdx.x; q < nlm; q += 256) {
-        double s = 0.0;
-        for (int t = 0; t < od.nt8; ++t) s += partQ[(size_t)(od.base8 + t) * nlm + q];
-        Q[(size_t)o * nlm + q] = dV * s;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// ghost nodes: six face slabs of depth P; per orbital, in the order
-// x-, x+, y-, y+, z-, z+; layer d = 1..P; then the face's 2-D index.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ bool ghost_decode(const OrbDesc &od, int P, long long g, int &gi, int &gj,
-                                             int &gk, int &face, int &d) {
-    const long long Fx = (long long)od.ny * od.nz, Fy = (long long)od.nx * od.nz,
-                    Fz = (long long)od.nx * od.ny;
-    const long long sz[3] = {P * Fx, P * Fy, P * Fz};
-    const long long Fs[3] = {Fx, Fy, Fz};
-    long long rem = g;
-    for (int ax = 0; ax < 3; ++ax) {
-        for (int side = 0; side < 2; ++side) {
-            if (rem < sz[ax]) {
-                d = (int)(rem / Fs[ax]) + 1;
-                const long long f2 = rem % Fs[ax];
-                face = 2 * ax + side;
-                if (ax == 0) {
-                    gj = (int)(f2 % od.ny);
-                    gk = (int)(f2 / od.ny);
-                    gi = side ? od.nx - 1 + d : -d;
-                } else if (ax == 1) {
-                    gi = (int)(f2 % od.nx);
-                    gk = (int)(f2 / od.nx);
-                    gj = side ? od.ny - 1 + d : -d;
-                } else {
-                    gi = (int)(f2 % od.nx);
-                    gj = (int)(f2 / od.nx);
-                    gk = side ? od.nz - 1 + d : -d;
-                }
-                return true;
-            }
-            rem -= sz[ax];
-        }
-    }
-    return false;
-}
-
-template <int L>
-__global__ __launch_bounds__(256) void k_ghosts(int P, HarmTables ht, const OrbDesc *orb,
-                                                const long long *gcount, const double *Q,
-                                                double *G) {
-    constexpr int NLM = (L + 1) * (L + 1);
-    const int o = blockIdx.y;
-    const OrbDesc od = orb[o];
-    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (g >= gcount[o]) return;
-    int gi, gj, gk, face, d;
-    if (!ghost_decode(od, P, g, gi, gj, gk, face, d)) return;
-    const double x = od.origin[0] + od.h * gi - od.centre[0];
-    const double y = od.origin[1] + od.h * gj - od.centre[1];
-    const double z = od.origin[2] + od.h * gk - od.centre[2];
-    double R[NLM];
-    regular_harmonics<L>(x, y, z, ht.norm, R);
-    const double r2 = x * x + y * y + z * z;
-    const double ir2 = 1.0 / r2;
-    const double ir = sqrt(ir2);
-    double v = 0.0;
-    double pw = ir;  // r^-(2l+1)
-#pragma unroll
-    for (int l = 0; l <= L; ++l) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = -l; m <= l; ++m) s += ht.gfac[l * l + l + m] * Q[(size_t)o * NLM + l * l + l + m] * R[l * l + l + m];
-        v += s * pw;
-        pw *= ir2;
-    }
-    G[od.goff + g] = v;
-}
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // right-hand side b = scale * rho + (L g)|interior
@@ -246,71 +73,365 @@ __global__ __launch_bounds__(256) void k_rhs(int P, Coeffs cf, const OrbDesc *or
 }
 
 // ---------------------------------------------------------------------------
-// adjoint boundary: zt_lm = sum_ghost gfac_lm Y_lm / r^(l+1) (C^T w)_ghost,
-// (C^T w)_ghost = sum over interior taps c_k / h^2 w
+// harmonic contractions on the matrix cores: out[o][q] = scale sum_n
+// H_q(n) f_o(n) over the nodes n of one channel's grid, with H built once per
+// node for all orbitals of the channel
+//   MODE 0 (moments): n = grid nodes, H_q = r^l Y_lm, f_o = rho_o (src^2 if
+//          square), scale dV;
+//   MODE 1 (adjoint boundary): n = ghost nodes, H_q = gfac_q Y_lm / r^(l+1),
+//          f_o = (C^T w_o)(n) = sum_t c_(t+d) w_o(t) / h^2 over the interior
+//          taps along the face normal, scale 1.
+// A block takes a contiguous range of 64-node chunks.  Per chunk the four
+// waves build H in LDS (wave w the azimuthal orders m = w mod 4), then per
+// tile of 16 orbitals they stage f in LDS and each wave multiplies its
+// 16-row H tiles against it (v_mfma_f64_16x16x4f64).  The loads of the next
+// tile's f are issued before the products of the current one.  Each block
+// writes one partial tile; a second kernel adds a channel's tiles in item
+// order.
 // ---------------------------------------------------------------------------
 
-template <int L>
-__global__ __launch_bounds__(256) void k_adj_boundary(int P, HarmTables ht, Coeffs cf,
-                                                      const OrbDesc *orb, const long long *gcount,
-                                                      const double *W, double *partZ,
-                                                      int zchunks) {
-    constexpr int NLM = (L + 1) * (L + 1);
-    __shared__ double sw[4][NLM];
-    const int o = blockIdx.y;
-    const OrbDesc od = orb[o];
-    const long long G = gcount[o];
-    double acc[NLM];
+constexpr int kHc = 64;  // nodes per chunk
+
+// f(q, l, r^l Y_lm / norm_lm) for the one azimuthal order MM (m = +MM and
+// -MM): the recurrence of visit_regular_harmonics without the normalisation,
+// which the contractions apply to their (much smaller) other operand or
+// result; no table is read while the harmonics are built
+template <int L, int MM, class F>
+__device__ __forceinline__ void visit_harmonics_m(double x, double y, double z, F &&f) {
+    if constexpr (MM <= L) {
+        const double r2 = x * x + y * y + z * z;
+        double cm = 1.0, sm = 0.0, dfact = 1.0;
 #pragma unroll
-    for (int q = 0; q < NLM; ++q) acc[q] = 0.0;
-    const long long per = (G + zchunks - 1) / zchunks;
-    const long long g0 = per * blockIdx.x, g1 = min(G, g0 + per);
-    const double *w = W + od.off;
-    for (long long g = g0 + threadIdx.x; g < g1; g += 256) {
-        int gi, gj, gk, face, d;
-        if (!ghost_decode(od, P, g, gi, gj, gk, face, d)) continue;
-        // taps from the ghost node into the interior, along the face normal
-        double zsum = 0.0;
-        const int ax = face >> 1, side = face & 1;
-        for (int t = 0; t + d <= P; ++t) {
-            int ii = gi, jj = gj, kk = gk;  // interior node at distance t from the face
-            if (ax == 0) ii = side ? od.nx - 1 - t : t;
-            if (ax == 1) jj = side ? od.ny - 1 - t : t;
-            if (ax == 2) kk = side ? od.nz - 1 - t : t;
-            zsum += cf.c[t + d] * w[((long long)kk * od.ny + jj) * od.nx + ii];
+        for (int m = 1; m <= MM; ++m) {
+            const double c2 = cm * x - sm * y;
+            sm = cm * y + sm * x;
+            cm = c2;
+            dfact *= (double)(2 * m - 1);
         }
-        zsum *= od.inv_h2;
-        const double x = od.origin[0] + od.h * gi - od.centre[0];
-        const double y = od.origin[1] + od.h * gj - od.centre[1];
-        const double z = od.origin[2] + od.h * gk - od.centre[2];
-        double R[NLM];
-        regular_harmonics<L>(x, y, z, ht.norm, R);
-        const double ir2 = 1.0 / (x * x + y * y + z * z);
-        double pw = sqrt(ir2) * zsum;
+        double pm2 = 0.0, pm1 = 0.0;
 #pragma unroll
-        for (int l = 0; l <= L; ++l) {
-#pragma unroll
-            for (int m = -l; m <= l; ++m) acc[l * l + l + m] += ht.gfac[l * l + l + m] * R[l * l + l + m] * pw;
-            pw *= ir2;
+        for (int l = MM; l <= L; ++l) {
+            double pl;
+            if (l == MM)
+                pl = dfact;
+            else if (l == MM + 1)
+                pl = (double)(2 * MM + 1) * z * pm1;
+            else
+                pl = ((double)(2 * l - 1) * z * pm1 - (double)(l + MM - 1) * r2 * pm2) * (1.0 / (double)(l - MM));
+            pm2 = pm1;
+            pm1 = pl;
+            if (MM == 0) {
+                f(l * l + l, l, pl);
+            } else {
+                f(l * l + l + MM, l, cm * pl);
+                f(l * l + l - MM, l, sm * pl);
+            }
         }
     }
-    const int wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NLM; ++q) {
-        const double v = wave_sum(acc[q]);
-        if ((threadIdx.x & 63) == 0) sw[wv][q] = v;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < NLM; q += 256)
-        partZ[((size_t)o * zchunks + blockIdx.x) * NLM + q] = (sw[0][q] + sw[1][q]) + (sw[2][q] + sw[3][q]);
 }
 
-__global__ void k_adj_boundary_final(int nlm, int zchunks, const double *partZ, double *Zt) {
-    const int o = blockIdx.x;
-    for (int q = threadIdx.x; q < nlm; q += blockDim.x) {
-        double s = 0.0;
-        for (int t = 0; t < zchunks; ++t) s += partZ[((size_t)o * zchunks + t) * nlm + q];
-        Zt[(size_t)o * nlm + q] = s;
+// the orders m = W, W + 4, W + 8 (kMaxL = 8)
+template <int L, int W, class F>
+__device__ __forceinline__ void visit_harmonics_set(double x, double y, double z, F &&f) {
+    visit_harmonics_m<L, W>(x, y, z, f);
+    visit_harmonics_m<L, W + 4>(x, y, z, f);
+    visit_harmonics_m<L, W + 8>(x, y, z, f);
+}
+
+// column `lane` of the chunk's harmonic rows (unnormalised), wave w the
+// orders m = w mod 4; KIND 0: r^l P_lm, KIND 1: the same / r^(2l+1)
+template <int L, int KIND>
+__device__ __forceinline__ void hc_build(double x, double y, double z, bool valid, int w, int lane,
+                                         double (*Hs)[65]) {
+    double pw[L + 1];
+    if constexpr (KIND == 1) {
+        const double ir2 = 1.0 / (x * x + y * y + z * z);
+        pw[0] = sqrt(ir2);
+#pragma unroll
+        for (int l = 1; l <= L; ++l) pw[l] = pw[l - 1] * ir2;
+    }
+    auto put = [&](int q, int l, double h) {
+        if constexpr (KIND == 1) h *= pw[l];
+        Hs[q][lane] = valid ? h : 0.0;
+    };
+    switch (w) {
+        case 0: visit_harmonics_set<L, 0>(x, y, z, put); break;
+        case 1: visit_harmonics_set<L, 1>(x, y, z, put); break;
+        case 2: visit_harmonics_set<L, 2>(x, y, z, put); break;
+        default: visit_harmonics_set<L, 3>(x, y, z, put); break;
+    }
+}
+
+// one node of a chunk: position relative to the centre; MODE 1: the interior
+// node next to the face (base), the step inward along the normal, the depth d
+struct HcNode {
+    double x, y, z;
+    int base, st, d;
+    bool valid;
+};
+
+template <int MODE>
+__device__ __forceinline__ HcNode hc_decode(const OrbDesc &od, int P, long long nn, long long n) {
+    HcNode nd{1.0, 1.0, 1.0, 0, 0, 0, n < nn};
+    if (!nd.valid) return nd;
+    int gi, gj, gk;
+    if constexpr (MODE == 0) {
+        // node indices in 32 bits (at most 2^29 nodes per orbital)
+        const int ii = (int)n, pxy = od.nx * od.ny;
+        gk = ii / pxy;
+        const int rem = ii - gk * pxy;
+        gj = rem / od.nx;
+        gi = rem - gj * od.nx;
+        nd.base = ii;
+    } else {
+        // ghost index in 32 bits: a slab holds at most P * 4096^2 nodes and
+        // all of an orbital's ghosts fewer than 2^31
+        const int F[3] = {od.ny * od.nz, od.nx * od.nz, od.nx * od.ny};
+        int rem = (int)n, face = 0;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            const int sz = P * F[f >> 1];
+            if (face == f && rem >= sz) {
+                rem -= sz;
+                face = f + 1;
+            }
+        }
+        const int ax = face >> 1, side = face & 1;
+        const int Fa = ax == 0 ? F[0] : (ax == 1 ? F[1] : F[2]);
+        const int d = rem / Fa + 1, f2 = rem - (d - 1) * Fa;
+        const int nu = ax == 0 ? od.ny : od.nx;  // fastest in-face axis
+        const int a = f2 % nu, b2 = f2 / nu;
+        const int pxy = od.nx * od.ny;
+        if (ax == 0) {
+            gi = side ? od.nx - 1 + d : -d; gj = a; gk = b2;
+            nd.base = (gk * od.ny + gj) * od.nx + (side ? od.nx - 1 : 0);
+            nd.st = side ? -1 : 1;
+        } else if (ax == 1) {
+            gi = a; gj = side ? od.ny - 1 + d : -d; gk = b2;
+            nd.base = (gk * od.ny + (side ? od.ny - 1 : 0)) * od.nx + gi;
+            nd.st = side ? -od.nx : od.nx;
+        } else {
+            gi = a; gj = b2; gk = side ? od.nz - 1 + d : -d;
+            nd.base = (side ? od.nz - 1 : 0) * pxy + gj * od.nx + gi;
+            nd.st = side ? -pxy : pxy;
+        }
+        nd.d = d;
+    }
+    nd.x = od.origin[0] + od.h * gi - od.centre[0];
+    nd.y = od.origin[1] + od.h * gj - od.centre[1];
+    nd.z = od.origin[2] + od.h * gk - od.centre[2];
+    return nd;
+}
+
+template <int L, int MODE>
+__global__ __launch_bounds__(256) void k_harm_contract(Coeffs cf, int P, const OrbDesc *orb,
+                                                       const long long *gcount, const HcItem *items,
+                                                       const double *src, int square, double *part) {
+    constexpr int NLM = (L + 1) * (L + 1);
+    constexpr int QT = (NLM + 15) / 16;                // 16-row tiles of H
+    constexpr int SL = (QT + 3) / 4;                   // tiles per wave
+    constexpr int R = MODE == 0 ? 1 : kMaxRadius;      // loads per f value
+    static_assert(kHc == 64, "hc_build assumes 65-double rows");
+    __shared__ double Hs[QT * 16][kHc + 1];  // odd row stride: conflict-free column reads
+    __shared__ double Fs[16][kHc + 1];
+    __shared__ double cs[2 * kMaxRadius + 2];  // c_k, zero beyond P
+    const HcItem it = items[blockIdx.x];
+    const OrbDesc od = orb[it.first];  // every orbital of the channel shares this grid
+    const int N = it.count;
+    const int OT = (N + 15) >> 4;
+    const long long M = (long long)od.nx * od.ny * od.nz;
+    const long long nn = MODE == 0 ? M : gcount[it.first];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lr = lane & 15, lk = lane >> 4;
+    if (threadIdx.x < 2 * kMaxRadius + 2)
+        cs[threadIdx.x] = threadIdx.x <= P && threadIdx.x <= kMaxRadius ? cf.c[threadIdx.x] : 0.0;
+    for (int e = threadIdx.x; e < (QT * 16 - NLM) * kHc; e += 256) Hs[NLM + e / kHc][e % kHc] = 0.0;
+    dbl4 acc[SL][8];
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl)
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot) acc[sl][ot] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // f of orbitals 16 ot + w + 4 k (k < 4) at the thread's node: raw loads
+    double raw[4][R];
+    auto issue = [&](const HcNode &nd, int ot) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int o = 16 * ot + w + 4 * k;
+            const bool ok = nd.valid && o < N;
+            const double *fo = src + od.off + (long long)(ok ? o : 0) * M;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const bool tap = ok && (MODE == 0 || q + nd.d <= P);
+                raw[k][q] = tap ? fo[nd.base + q * nd.st] : 0.0;
+            }
+        }
+    };
+    HcNode nd = hc_decode<MODE>(od, P, nn, (long long)it.t0 * kHc + lane);
+    if (it.t0 < it.t1) issue(nd, 0);
+    __syncthreads();  // cs and the zero rows
+    for (int t = it.t0; t < it.t1; ++t) {
+        // this wave's rows of H for chunk t (the previous chunk's products are done)
+        hc_build<L, MODE>(nd.x, nd.y, nd.z, nd.valid, w, lane, Hs);
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot) {
+            if (ot < OT) {  // uniform
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    double f;
+                    if constexpr (MODE == 0) {
+                        f = square ? raw[k][0] * raw[k][0] : raw[k][0];
+                    } else {
+                        f = 0.0;
+#pragma unroll
+                        for (int q = 0; q < R; ++q) f += cs[q + nd.d] * raw[k][q];
+                        f *= od.inv_h2;
+                    }
+                    Fs[w + 4 * k][lane] = f;
+                }
+                // next tile's loads, in flight during the products
+                HcNode nxt = nd;
+                if (ot + 1 < OT) {
+                    issue(nd, ot + 1);
+                } else if (t + 1 < it.t1) {
+                    nxt = hc_decode<MODE>(od, P, nn, (long long)(t + 1) * kHc + lane);
+                    issue(nxt, 0);
+                }
+                __syncthreads();  // H and f staged
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    const int qt = w + 4 * sl;
+                    if (qt < QT) {
+#pragma unroll
+                        for (int k0 = 0; k0 < kHc; k0 += 4)
+                            acc[sl][ot] = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[16 * qt + lr][k0 + lk],
+                                                                               Fs[lr][k0 + lk], acc[sl][ot], 0, 0, 0);
+                    }
+                }
+                __syncthreads();  // products done with Fs (and, after the last tile, Hs)
+                nd = nxt;
+            }
+        }
+    }
+    // partial tile: rows q, columns o (16 * OT of them); D lane l, item j is
+    // (row l / 16 + 4 j, column l % 16) of a 16 x 16 tile
+    const int np = 16 * OT;
+    double *out = part + it.poff;
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+        const int qt = w + 4 * sl;
+        if (qt < QT) {
+#pragma unroll
+            for (int ot = 0; ot < 8; ++ot)
+                if (ot < OT)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        out[(size_t)(16 * qt + lk + 4 * jj) * np + 16 * ot + lr] = acc[sl][ot][jj];
+        }
+    }
+}
+
+// out[first + o][q] = scale_q * (sum of the channel's partial tiles), scale_q
+// = dV norm_q (moments) or gfac_q norm_q (adjoint boundary); one wave per
+// output value, the tiles in item order (lane-strided, then a fixed butterfly)
+template <int L>
+__global__ __launch_bounds__(256) void k_harm_final(HarmTables ht, const HcChan *chans, const OrbDesc *orb,
+                                                    int mode, const double *part, double *out) {
+    constexpr int NLM = (L + 1) * (L + 1);
+    const HcChan ch = chans[blockIdx.y];
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (e >= ch.count * NLM) return;  // wave-uniform
+    const int o = e / NLM, q = e - o * NLM;
+    const int np = 16 * ((ch.count + 15) >> 4);
+    const size_t tile = (size_t)kHcRows * np;  // tiles are kHcRows rows apart
+    const double *pp = part + ch.poff + (size_t)q * np + o;
+    double sum = 0.0;
+    for (int p = lane; p < ch.nparts; p += 64) sum += pp[p * tile];
+    sum = wave_sum(sum);
+    if (lane == 0) {
+        const OrbDesc od = orb[ch.first];
+        const double scale = mode == 0 ? od.h * od.h * od.h * ht.norm[q] : ht.gfac[q] * ht.norm[q];
+        out[(size_t)(ch.first + o) * NLM + q] = scale * sum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// harmonic expansions on the matrix cores: out_o(n) (+)= sum_q C'[o][q] H_q(n)
+// over the nodes n of one channel
+//   MODE 0 (ghost values, Sec. II.A): n = ghosts, H_q = r^l P_lm / r^(2l+1),
+//          C' = gfac_q norm_q Q[o][q], out = G (written);
+//   MODE 1 (multipole part of the adjoint field): n = grid nodes,
+//          H_q = r^l P_lm, C' = dV norm_q zt[o][q], out = W (added to).
+// The block stages C' (16 rows per orbital tile) in LDS once; per 64-node
+// chunk the four waves build H as in the contraction, then wave w forms the
+// 16 x 16 result tiles of nodes 16 w .. 16 w + 15 for every orbital tile.
+// ---------------------------------------------------------------------------
+
+template <int L, int MODE>
+__global__ __launch_bounds__(256) void k_harm_expand(HarmTables ht, int P, const OrbDesc *orb,
+                                                     const long long *gcount, const HcItem *items,
+                                                     const double *C, double *out) {
+    constexpr int NLM = (L + 1) * (L + 1);
+    constexpr int KQ = (NLM + 15) / 16 * 16;  // harmonic rows, padded
+    constexpr int CST = KQ + 1;                // odd row stride of C'
+    static_assert(kHc == 64, "hc_build assumes 65-double rows");
+    __shared__ double Hs[KQ][kHc + 1];
+    extern __shared__ double Cs[];  // [16 OT][CST]
+    const HcItem it = items[blockIdx.x];
+    const OrbDesc od = orb[it.first];  // every orbital of the channel shares this grid
+    const int N = it.count;
+    const int OT = (N + 15) >> 4;
+    const long long M = (long long)od.nx * od.ny * od.nz;
+    const long long nn = MODE == 0 ? gcount[it.first] : M;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lr = lane & 15, lk = lane >> 4;
+    const double dV = od.h * od.h * od.h;
+    for (int e = threadIdx.x; e < 16 * OT * KQ; e += 256) {
+        const int o = e / KQ, q = e - o * KQ;
+        double v = 0.0;
+        if (o < N && q < NLM)
+            v = C[(size_t)(it.first + o) * NLM + q] * ht.norm[q] * (MODE == 0 ? ht.gfac[q] : dV);
+        Cs[o * CST + q] = v;
+    }
+    for (int e = threadIdx.x; e < (KQ - NLM) * kHc; e += 256) Hs[NLM + e / kHc][e % kHc] = 0.0;
+    __syncthreads();
+    for (int t = it.t0; t < it.t1; ++t) {
+        const long long n0 = (long long)t * kHc;
+        const HcNode nd = hc_decode<MODE == 0 ? 1 : 0>(od, P, nn, n0 + lane);
+        const long long nout = n0 + 16 * w + lr;  // this lane's output node
+        double wv[8][4];                           // MODE 1: W before the update
+        if constexpr (MODE == 1) {
+#pragma unroll
+            for (int ot = 0; ot < 8; ++ot)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = 16 * ot + lk + 4 * j;
+                    wv[ot][j] = ot < OT && o < N && nout < nn ? out[od.off + (long long)o * M + nout] : 0.0;
+                }
+        }
+        hc_build<L, MODE == 0 ? 1 : 0>(nd.x, nd.y, nd.z, nd.valid, w, lane, Hs);
+        __syncthreads();  // H staged
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot) {
+            if (ot < OT) {  // uniform
+                dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k0 = 0; k0 < KQ; k0 += 4)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Cs[(16 * ot + lr) * CST + k0 + lk],
+                                                               Hs[k0 + lk][16 * w + lr], acc, 0, 0, 0);
+                // D lane l, item j: orbital 16 ot + l / 16 + 4 j, node 16 w + l % 16
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = 16 * ot + lk + 4 * j;
+                    if (o < N && nout < nn) {
+                        if constexpr (MODE == 0)
+                            out[od.goff + (long long)o * nn + nout] = acc[j];
+                        else
+                            out[od.off + (long long)o * M + nout] = wv[ot][j] + acc[j];
+                    }
+                }
+            }
+        }
+        __syncthreads();  // products done with H
     }
 }
 
@@ -332,25 +453,47 @@ __global__ void k_adj_boundary_final(int nlm, int zchunks, const double *partZ, 
         default: return hipErrorInvalidValue; \
     }
 
-hipError_t launch_moments(int lmax, const HarmTables &ht, int norb, const OrbDesc *orb,
-                          const Item *items8, int nitems8, const double *src, int square,
-                          double *partQ, int tot8, double *Q, hipStream_t s) {
-    (void)tot8;
-    if (nitems8 <= 0 || norb <= 0) return hipSuccess;
-#define CALL(L) hipLaunchKernelGGL(k_moments<L>, dim3(nitems8), dim3(256), 0, s, ht, orb, items8, src, square, partQ)
+hipError_t launch_harm_contract(int mode, int lmax, const HarmTables &ht, const Coeffs &c, int radius,
+                                const OrbDesc *orb, const long long *ghost_count, const HcItem *items,
+                                int nitems, const HcChan *chans, int nchans, int max_count,
+                                const double *src, int square, double *part, double *out, hipStream_t s) {
+    if (nitems <= 0 || nchans <= 0) return hipSuccess;
+    if (radius < 1 || radius > kMaxRadius || max_count < 1 || max_count > kMaxOrb) return hipErrorInvalidValue;
+    const int nlm = (lmax + 1) * (lmax + 1);
+    const dim3 fgrid((unsigned)((max_count * nlm + 3) / 4), (unsigned)nchans);
+#define CALL(L)                                                                                        \
+    do {                                                                                               \
+        if (mode == 0)                                                                                 \
+            hipLaunchKernelGGL((k_harm_contract<L, 0>), dim3(nitems), dim3(256), 0, s, c, radius,      \
+                               orb, ghost_count, items, src, square, part);                            \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_harm_contract<L, 1>), dim3(nitems), dim3(256), 0, s, c, radius,      \
+                               orb, ghost_count, items, src, square, part);                            \
+        hipLaunchKernelGGL(k_harm_final<L>, fgrid, dim3(256), 0, s, ht, chans, orb, mode, part, out);  \
+    } while (0)
     FSIC_L_SWITCH(lmax, CALL)
 #undef CALL
-    hipLaunchKernelGGL(k_moments_final, dim3(norb), dim3(256), 0, s, (lmax + 1) * (lmax + 1), orb,
-                       partQ, Q);
     return hipGetLastError();
 }
 
-hipError_t launch_ghosts(int radius, int lmax, const HarmTables &ht, int norb,
-                         const OrbDesc *orb, const long long *ghost_count, const double *Q,
-                         double *G, long long max_ghost, hipStream_t s) {
-    if (norb <= 0) return hipSuccess;
-    dim3 grid((unsigned)((max_ghost + 255) / 256), (unsigned)norb);
-#define CALL(L) hipLaunchKernelGGL(k_ghosts<L>, grid, dim3(256), 0, s, radius, ht, orb, ghost_count, Q, G)
+hipError_t launch_harm_expand(int mode, int lmax, const HarmTables &ht, int radius, const OrbDesc *orb,
+                              const long long *ghost_count, const HcItem *items, int nitems, int max_count,
+                              const double *C, double *out, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (radius < 1 || radius > kMaxRadius || max_count < 1 || max_count > kMaxOrb) return hipErrorInvalidValue;
+    const int kq = ((lmax + 1) * (lmax + 1) + 15) / 16 * 16;
+    const size_t lds = (size_t)16 * ((max_count + 15) / 16) * (kq + 1) * sizeof(double);
+#define CALL(L)                                                                                        \
+    do {                                                                                               \
+        const void *fn = mode == 0 ? (const void *)k_harm_expand<L, 0> : (const void *)k_harm_expand<L, 1>; \
+        if (lds > 32768) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        if (mode == 0)                                                                                 \
+            hipLaunchKernelGGL((k_harm_expand<L, 0>), dim3(nitems), dim3(256), lds, s, ht, radius, orb, \
+                               ghost_count, items, C, out);                                            \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_harm_expand<L, 1>), dim3(nitems), dim3(256), lds, s, ht, radius, orb, \
+                               ghost_count, items, C, out);                                            \
+    } while (0)
     FSIC_L_SWITCH(lmax, CALL)
 #undef CALL
     return hipGetLastError();
@@ -363,21 +506,6 @@ hipError_t launch_rhs(int radius, const Coeffs &c, const Item *items8, int nitem
     if (nitems8 <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_rhs, dim3(nitems8), dim3(256), 0, s, radius, c, orb, items8, src, square,
                        scale, G, B, R64, R32, X64zero, part8);
-    return hipGetLastError();
-}
-
-hipError_t launch_adjoint_boundary(int radius, int lmax, const HarmTables &ht, const Coeffs &c,
-                                   int norb, const OrbDesc *orb, const long long *ghost_count,
-                                   const double *W, double *partZ, int zchunks, double *Zt,
-                                   long long max_ghost, hipStream_t s) {
-    (void)max_ghost;
-    if (norb <= 0) return hipSuccess;
-    dim3 grid((unsigned)zchunks, (unsigned)norb);
-#define CALL(L) hipLaunchKernelGGL(k_adj_boundary<L>, grid, dim3(256), 0, s, radius, ht, c, orb, ghost_count, W, partZ, zchunks)
-    FSIC_L_SWITCH(lmax, CALL)
-#undef CALL
-    hipLaunchKernelGGL(k_adj_boundary_final, dim3(norb), dim3(128), 0, s, (lmax + 1) * (lmax + 1),
-                       zchunks, partZ, Zt);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -165,9 +166,43 @@ struct Batch {
     bool dst_vec = true;   // every nx and orbital offset is a multiple of 4
     int npxy = 0;          // largest in-plane axis, padded to 32
     bool dst_zocc2 = false;  // z pass in 64-column panels, two blocks per compute unit
-    std::vector<GroupItem> itemsG;  // (channel, kAdjTile-node tile) items of the adjoint field
-    int max_group = 0;              // most orbitals in one channel
+    int max_group = 0;  // most orbitals in one channel
+    // harmonic contractions over grid nodes (moments) and ghosts (adjoint
+    // boundary): block items, channel ranges, partial-tile elements
+    std::vector<HcItem> hcN, hcG;
+    std::vector<HcChan> hchN, hchG;
+    long long hc_elems = 0;
 };
+
+// blocks of a harmonic contraction (about three per compute unit)
+constexpr int kHcBlocks = 768;
+
+// Splits every channel's 64-node chunks into contiguous ranges, blocks per
+// channel in proportion to its work (chunks x orbital tiles).
+void build_hc_items(const std::vector<std::array<long long, 3>> &chans, std::vector<HcItem> &items,
+                    std::vector<HcChan> &out, long long &elems) {
+    items.clear();
+    out.clear();
+    elems = 0;
+    double total = 0.0;
+    for (const auto &ch : chans) total += (double)((ch[2] + 63) / 64) * (double)((ch[1] + 15) / 16);
+    for (const auto &ch : chans) {
+        const int first = (int)ch[0], count = (int)ch[1];
+        const long long chunks = (ch[2] + 63) / 64;
+        if (count <= 0 || chunks <= 0) continue;
+        const double work = (double)chunks * (double)((count + 15) / 16);
+        long long nb = (long long)std::llround(kHcBlocks * work / std::max(total, 1.0));
+        nb = std::max(1LL, std::min(nb, chunks));
+        const long long tile = (long long)kHcRows * 16 * ((count + 15) / 16);
+        HcChan hc{first, count, (int)nb, elems};
+        for (long long i = 0; i < nb; ++i) {
+            items.push_back(HcItem{first, count, (int)(chunks * i / nb), (int)(chunks * (i + 1) / nb), elems});
+            elems += tile;
+        }
+        out.push_back(hc);
+    }
+}
+
 
 void build_items(const std::vector<std::pair<int, int>> &natural, std::vector<Item> &out) {
     const int n = (int)natural.size();
@@ -210,9 +245,10 @@ struct fsic_ctx {
     DBuf<float> Fprev, Fh;               // AAR: previous f, f-difference history
     DBuf<double> Xh, aar_gamma, partD;  // AAR: step history, weights, Gram partials
     DBuf<Item> d_dx, d_dy, d_dz, d_dxy;
-    DBuf<GroupItem> d_itemsG;
     DBuf<double> Gh;  // ghost values
-    DBuf<double> part7, part8, partRU, partQ, partZ;
+    DBuf<double> part7, part8, partRU, partH;  // partH: harmonic-contraction partial tiles
+    DBuf<HcItem> d_hcN, d_hcG;
+    DBuf<HcChan> d_hchN, d_hchG;
     DBuf<double> bb, rrfin, relres, Qlm, Zt, ptrue;
     DBuf<int> done, iters, rs_iter, nact;
     DBuf<OrbDesc> d_orb;
@@ -480,12 +516,15 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
         while (bb.dtab.size() % 4) bb.dtab.push_back(0.f);
         return dst_done[n] = {so, go};
     };
+    std::vector<std::array<long long, 3>> hcn, hcg;  // (first, count, nodes / ghosts)
     for (const Group &g : groups) {
         const long long M = (long long)g.n[0] * g.n[1] * g.n[2];
         if (g.count > 0) {
             const int first = (int)b.orb.size();
-            for (int t = 0; t < (int)((M + kAdjTile - 1) / kAdjTile); ++t)
-                b.itemsG.push_back(GroupItem{first, g.count, t});
+            const long long G = 2LL * radius * ((long long)g.n[1] * g.n[2] + (long long)g.n[0] * g.n[2] +
+                                                (long long)g.n[0] * g.n[1]);
+            hcn.push_back({first, g.count, M});
+            hcg.push_back({first, g.count, G});
             b.max_group = std::max(b.max_group, g.count);
         }
         for (int i = 0; i < g.count; ++i) {
@@ -547,6 +586,10 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     }
     build_items(nat7, b.items7);
     build_items(nat8, b.items8);
+    long long en = 0, eg = 0;
+    build_hc_items(hcn, b.hcN, b.hchN, en);
+    build_hc_items(hcg, b.hcG, b.hchG, eg);
+    b.hc_elems = std::max(en, eg);
     // persistent kernels take contiguous unit ranges: keep orbital order so
     // one sine matrix serves a whole range
     for (auto *pr : {&natx, &naty, &natz}) {
@@ -590,8 +633,11 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     if ((st = upload(c, c->d_orb, b.orb))) return st;
     if ((st = upload(c, c->d_items7, b.items7))) return st;
     if ((st = upload(c, c->d_items8, b.items8))) return st;
-    if ((st = upload(c, c->d_itemsG, b.itemsG))) return st;
     if ((st = upload(c, c->d_gcount, b.gcount))) return st;
+    if ((st = upload(c, c->d_hcN, b.hcN))) return st;
+    if ((st = upload(c, c->d_hcG, b.hcG))) return st;
+    if ((st = upload(c, c->d_hchN, b.hchN))) return st;
+    if ((st = upload(c, c->d_hchG, b.hchG))) return st;
     if (use_pcg(c, b) || use_aar(c, b)) {
         if ((st = upload(c, c->d_dx, b.dx))) return st;
         if ((st = upload(c, c->d_dy, b.dy))) return st;
@@ -630,8 +676,7 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     HIPCHK(c, c->part7.ensure(3 * (size_t)b.tot7));
     HIPCHK(c, c->partRU.ensure((size_t)b.tot7));
     HIPCHK(c, c->part8.ensure(2 * (size_t)b.tot8));
-    HIPCHK(c, c->partQ.ensure((size_t)b.tot8 * kMaxLM));
-    HIPCHK(c, c->partZ.ensure((size_t)norb * 64 * kMaxLM));
+    HIPCHK(c, c->partH.ensure((size_t)b.hc_elems));
     HIPCHK(c, c->bb.ensure(norb));
     HIPCHK(c, c->rrfin.ensure(norb));
     HIPCHK(c, c->relres.ensure(norb));
@@ -879,10 +924,11 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     const int nit7 = (int)b.items7.size(), nit8 = (int)b.items8.size();
     const bool mixed = precision == FSIC_MIXED;
     if (with_bc) {
-        HIPCHK(c, launch_moments(c->opts.lmax, c->ht, norb, c->d_orb.p, c->d_items8.p, nit8, src,
-                                 square, c->partQ.p, b.tot8, c->Qlm.p, s));
-        HIPCHK(c, launch_ghosts(c->radius, c->opts.lmax, c->ht, norb, c->d_orb.p, c->d_gcount.p,
-                                c->Qlm.p, c->Gh.p, b.max_ghost, s));
+        HIPCHK(c, launch_harm_contract(0, c->opts.lmax, c->ht, c->cf, c->radius, c->d_orb.p, c->d_gcount.p,
+                                       c->d_hcN.p, (int)b.hcN.size(), c->d_hchN.p, (int)b.hchN.size(),
+                                       b.max_group, src, square, c->partH.p, c->Qlm.p, s));
+        HIPCHK(c, launch_harm_expand(0, c->opts.lmax, c->ht, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcG.p,
+                                     (int)b.hcG.size(), b.max_group, c->Qlm.p, c->Gh.p, s));
     }
     (void)nlm;
     // b, r0 = b, x64 = 0 (mixed), ||b||^2 partials in part8 slot 0
@@ -1454,9 +1500,10 @@ void fsic_destroy(fsic_ctx *c) {
     c->R32.release(); c->P32a.release(); c->P32b.release(); c->Q32.release(); c->X32.release();
     c->Z32.release(); c->T32.release(); c->dtab.release(); c->partRZ.release();
     c->Fprev.release(); c->Fh.release(); c->Xh.release(); c->aar_gamma.release(); c->partD.release();
-    c->d_dx.release(); c->d_dy.release(); c->d_dz.release(); c->d_dxy.release(); c->d_itemsG.release();
+    c->d_dx.release(); c->d_dy.release(); c->d_dz.release(); c->d_dxy.release();
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
-    c->partQ.release(); c->partZ.release(); c->bb.release(); c->rrfin.release();
+    c->partH.release(); c->d_hcN.release(); c->d_hcG.release(); c->d_hchN.release(); c->d_hchG.release();
+    c->bb.release(); c->rrfin.release();
     c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release();
     c->done.release(); c->iters.release(); c->rs_iter.release(); c->nact.release(); c->d_orb.release(); c->d_items7.release();
     c->d_items8.release(); c->d_gcount.release(); c->small.release(); c->work.release();
@@ -2094,11 +2141,11 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         // boundary part of A^T rho: zt = E_g^T C^T w' / (4 pi), then W += P^T zt
         HarmTables hta = c->ht;
         for (int q = 0; q < kMaxLM; ++q) hta.gfac[q] /= 4.0 * M_PI;
-        const int zchunks = 64;
-        HIPCHK(c, launch_adjoint_boundary(c->radius, o.lmax, hta, c->cf, norb, c->d_orb.p, c->d_gcount.p,
-                                          c->W.p, c->partZ.p, zchunks, c->Zt.p, b.max_ghost, s));
-        HIPCHK(c, launch_adj_field_groups(o.lmax, c->ht, c->d_orb.p, c->d_itemsG.p, (int)b.itemsG.size(),
-                                          b.max_group, c->Zt.p, c->W.p, s));
+        HIPCHK(c, launch_harm_contract(1, o.lmax, hta, c->cf, c->radius, c->d_orb.p, c->d_gcount.p,
+                                       c->d_hcG.p, (int)b.hcG.size(), c->d_hchG.p, (int)b.hchG.size(),
+                                       b.max_group, c->W.p, 0, c->partH.p, c->Zt.p, s));
+        HIPCHK(c, launch_harm_expand(1, o.lmax, c->ht, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcN.p,
+                                     (int)b.hcN.size(), b.max_group, c->Zt.p, c->W.p, s));
         Wt = c->W.p;
     }
     const double t1 = now_ms();
