@@ -269,7 +269,15 @@ hipError_t launch_harm_expand(int mode, int lmax, const HarmTables &ht, int radi
                               const long long *ghost_count, const HcItem *items, int nitems, int max_count,
                               const double *C, double *out, hipStream_t s);
 
-// b = scale * rho + (boundary term of the ghosts, if G != null); writes B,
+// In place of the ghost values G, the boundary term of the interior nodes
+// within reach of each face: layer e of a face column becomes
+// sum_{d=1}^{P-e} c_(e+d) g_d / h^2 (the right-hand side then adds one value
+// per face in reach).  max_cols: most face columns of one orbital,
+// 2 (nx ny + ny nz + nx nz).
+hipError_t launch_bterm(int radius, const Coeffs &c, int norb, const OrbDesc *orb, long long max_cols,
+                        double *G, hipStream_t s);
+
+// b = scale * rho + (boundary term from launch_bterm, if G != null); writes B,
 // R64 or R32 = b, optionally X64 = 0, and b.b partials into part8 slot 0.
 hipError_t launch_rhs(int radius, const Coeffs &c, const Item *items8, int nitems8,
                       const OrbDesc *orb, const double *src, int square, double scale,

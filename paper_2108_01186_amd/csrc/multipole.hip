@@ -17,10 +17,49 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // right-hand side b = scale * rho + (L g)|interior
 // ---------------------------------------------------------------------------
 
+// Boundary term of the interior nodes within reach of each face, computed in
+// place of the ghost values: a face column's layer e (0-based; the interior
+// node at distance e from the face) becomes
+//   t_e = sum_{d = 1}^{P - e} c_(e+d) g_d / h^2,
+// the taps of that node into the column's ghost layers d = 1..P.  One thread
+// per face column; grid.y: orbital.
+__global__ __launch_bounds__(256) void k_bterm(int P, Coeffs cf, const OrbDesc *orb, double *G) {
+    const OrbDesc od = orb[blockIdx.y];
+    const long long F[3] = {(long long)od.ny * od.nz, (long long)od.nx * od.nz, (long long)od.nx * od.ny};
+    long long col = (long long)blockIdx.x * 256 + threadIdx.x;
+    long long base = od.goff;
+    int face = 0;
+    for (; face < 6; ++face) {
+        const long long Fa = F[face >> 1];
+        if (col < Fa) break;
+        col -= Fa;
+        base += P * Fa;
+    }
+    if (face == 6) return;
+    const long long Fa = F[face >> 1];
+    double *gc = G + base + col;
+    double g[kMaxRadius];
+#pragma unroll
+    for (int d = 0; d < kMaxRadius; ++d) g[d] = d < P ? gc[d * Fa] : 0.0;
+#pragma unroll
+    for (int e = 0; e < kMaxRadius; ++e) {
+        if (e < P) {
+            double t = 0.0;
+#pragma unroll
+            for (int d = 1; d <= kMaxRadius; ++d)
+                if (d <= P - e) t += cf.c[e + d] * g[d - 1];
+            gc[e * Fa] = t * od.inv_h2;
+        }
+    }
+}
+
+constexpr int kRhsU = 4;  // nodes per thread whose loads are issued together
+
 __global__ __launch_bounds__(256) void k_rhs(int P, Coeffs cf, const OrbDesc *orb,
-                                             const Item *items, const double *src, int square,
-                                             double scale, const double *G, double *B,
-                                             double *R64, float *R32, double *X64zero,
+                                             const Item *items, const double *__restrict__ src, int square,
+                                             double scale, const double *__restrict__ G,
+                                             double *__restrict__ B, double *__restrict__ R64,
+                                             float *__restrict__ R32, double *__restrict__ X64zero,
                                              double *part8) {
     __shared__ double sred[4];
     const Item it = items[blockIdx.x];
@@ -32,41 +71,58 @@ __global__ __launch_bounds__(256) void k_rhs(int P, Coeffs cf, const OrbDesc *or
     const long long oxm = 0, oxp = P * Fx, oym = 2 * P * Fx, oyp = oym + P * Fy,
                     ozm = oym + 2 * P * Fy, ozp = ozm + P * Fz;
     const long long base = (long long)it.tile * kPW;
+    const double *g = G ? G + od.goff : nullptr;
+    // node indices of the thread's first node (32 bits: at most 2^29 nodes
+    // per orbital), then advanced by 256 nodes per step without dividing
+    const int pxy = nx * ny;
+    const int i0 = (int)base + threadIdx.x;
+    int iz = i0 / pxy;
+    int iy = (i0 - iz * pxy) / nx;
+    int ix = i0 - iz * pxy - iy * nx;
+    const int sx = 256 % nx, sy = (256 / nx) % ny, sz = 256 / pxy;
     double acc = 0.0;
-    for (int e = 0; e < kPW / 256; ++e) {
-        const long long i = base + e * 256 + threadIdx.x;
-        if (i >= M) continue;
-        // node indices in 32 bits (at most 2^29 nodes per orbital)
-        const int ii = (int)i, pxy = nx * ny;
-        const int iz = ii / pxy, rem = ii - iz * pxy;
-        const int iy = rem / nx, ix = rem - iy * nx;
-        const double sv = src[od.off + i];
-        double b = scale * (square ? sv * sv : sv);
-        if (G) {
-            const double *g = G + od.goff;
-            double bt = 0.0;
-            // taps that reach the ghost layers of each face: node at distance e
-            // from the face sees ghost layer d with weight c_{e+d}, e + d <= P
-            int e0 = ix;
-            for (int d = 1; d <= P - e0; ++d) bt += cf.c[e0 + d] * g[oxm + (d - 1) * Fx + iy + (long long)ny * iz];
-            e0 = nx - 1 - ix;
-            for (int d = 1; d <= P - e0; ++d) bt += cf.c[e0 + d] * g[oxp + (d - 1) * Fx + iy + (long long)ny * iz];
-            e0 = iy;
-            for (int d = 1; d <= P - e0; ++d) bt += cf.c[e0 + d] * g[oym + (d - 1) * Fy + ix + (long long)nx * iz];
-            e0 = ny - 1 - iy;
-            for (int d = 1; d <= P - e0; ++d) bt += cf.c[e0 + d] * g[oyp + (d - 1) * Fy + ix + (long long)nx * iz];
-            e0 = iz;
-            for (int d = 1; d <= P - e0; ++d) bt += cf.c[e0 + d] * g[ozm + (d - 1) * Fz + ix + (long long)nx * iy];
-            e0 = nz - 1 - iz;
-            for (int d = 1; d <= P - e0; ++d) bt += cf.c[e0 + d] * g[ozp + (d - 1) * Fz + ix + (long long)nx * iy];
-            b += bt * od.inv_h2;
+    for (int e0 = 0; e0 < kPW / 256; e0 += kRhsU) {
+        double sv[kRhsU];
+#pragma unroll
+        for (int u = 0; u < kRhsU; ++u) {
+            const long long i = base + (e0 + u) * 256 + threadIdx.x;
+            sv[u] = i < M ? src[od.off + i] : 0.0;
         }
-        const long long gi = od.off + i;
-        if (B) B[gi] = b;
-        if (R64) R64[gi] = b;
-        if (R32) R32[gi] = (float)b;
-        if (X64zero) X64zero[gi] = 0.0;
-        acc += b * b;
+#pragma unroll
+        for (int u = 0; u < kRhsU; ++u) {
+            const long long i = base + (e0 + u) * 256 + threadIdx.x;
+            if (i < M) {
+                double b = scale * (square ? sv[u] * sv[u] : sv[u]);
+                if (g) {
+                    // boundary term (k_bterm): layer e of the column of each face
+                    // within reach, faces in the order x-, x+, y-, y+, z-, z+
+                    const long long fx = iy + (long long)ny * iz, fy = ix + (long long)nx * iz,
+                                    fz = ix + (long long)nx * iy;
+                    double bt = 0.0;
+                    if (ix < P) bt += g[oxm + ix * Fx + fx];
+                    if (nx - 1 - ix < P) bt += g[oxp + (nx - 1 - ix) * Fx + fx];
+                    if (iy < P) bt += g[oym + iy * Fy + fy];
+                    if (ny - 1 - iy < P) bt += g[oyp + (ny - 1 - iy) * Fy + fy];
+                    if (iz < P) bt += g[ozm + iz * Fz + fz];
+                    if (nz - 1 - iz < P) bt += g[ozp + (nz - 1 - iz) * Fz + fz];
+                    b += bt;
+                }
+                const long long gi = od.off + i;
+                if (B) B[gi] = b;
+                if (R64) R64[gi] = b;
+                if (R32) R32[gi] = (float)b;
+                if (X64zero) X64zero[gi] = 0.0;
+                acc += b * b;
+            }
+            // next node of this thread: + 256 (sy < ny, so one carry at most per axis)
+            ix += sx;
+            const int cy = ix >= nx;
+            ix -= cy ? nx : 0;
+            iy += sy + cy;
+            const int cz = iy >= ny;
+            iy -= cz ? ny : 0;
+            iz += sz + cz;
+        }
     }
     const double s = block_sum256(acc, sred);
     if (threadIdx.x == 0) part8[od.base8 + it.tile] = s;
@@ -496,6 +552,15 @@ hipError_t launch_harm_expand(int mode, int lmax, const HarmTables &ht, int radi
     } while (0)
     FSIC_L_SWITCH(lmax, CALL)
 #undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_bterm(int radius, const Coeffs &c, int norb, const OrbDesc *orb, long long max_cols,
+                        double *G, hipStream_t s) {
+    if (norb <= 0 || max_cols <= 0) return hipSuccess;
+    if (radius < 1 || radius > kMaxRadius) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bterm, dim3((unsigned)((max_cols + 255) / 256), (unsigned)norb), dim3(256), 0, s, radius,
+                       c, orb, G);
     return hipGetLastError();
 }
 

@@ -929,6 +929,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                                        b.max_group, src, square, c->partH.p, c->Qlm.p, s));
         HIPCHK(c, launch_harm_expand(0, c->opts.lmax, c->ht, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcG.p,
                                      (int)b.hcG.size(), b.max_group, c->Qlm.p, c->Gh.p, s));
+        HIPCHK(c, launch_bterm(c->radius, c->cf, norb, c->d_orb.p, b.max_ghost / c->radius, c->Gh.p, s));
     }
     (void)nlm;
     // b, r0 = b, x64 = 0 (mixed), ||b||^2 partials in part8 slot 0
