@@ -113,13 +113,58 @@ def cpu_baseline(sysobj, tol, budget_s):
             t_solve += time.perf_counter() - t1
             iters.append(it)
             done += 1
-    return {"value": done / t_solve, "unit": "solves/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    out = {"value": done / t_solve, "unit": "solves/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
             "sample": f"{done} of the {sum(sysobj.nocc)} forward FLO-density Poisson solves of the "
                       f"{sysobj.name} workload (FP64 CG to relative residual {tol:g}, "
                       f"{int(np.mean(iters))} iterations on average, {t_solve:.1f} s; the Fermi-"
                       f"Loewdin steps before them took {t_flo:.1f} s and are not in the rate), "
-                      f"OpenMP over the host cores"}
+                      f"OpenMP over the host cores",
+           "cpu_model": host_cpu_model()}
+    out["single_thread_small_case"] = single_thread_small_case()
+    return out
+
+
+def host_cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+_SMALL_CASE = r'''
+import json, time
+from oracle import oracle
+from paper_2108_01186_amd import synth
+s = synth.make_workload("mol40")
+t0 = time.perf_counter()
+r = oracle.sic_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin, tol=1e-10)
+t = time.perf_counter() - t0
+print(json.dumps({"seconds": t, "threads": oracle.num_threads(), "E_SIC": float(r.e)}))
+'''
+
+
+def single_thread_small_case():
+    """The oracle on the 40^3 one-channel case (5 orbitals, CG to 1e-10:
+    Fermi-Loewdin orbitals, their Poisson solves, LSDA, E_SIC and V_SIC) with
+    one OpenMP thread, in a child process that touches no GPU."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", _SMALL_CASE], cwd=ROOT, env=env, capture_output=True,
+                           text=True, timeout=300)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception as e:  # a baseline figure, not a result: report why it is missing
+        return {"error": f"{type(e).__name__}: {e}"}
+    return {"workload": "mol40: 40^3 grid, h=0.3 Bohr, 5 orbitals, one spin channel; E_SIC and V_SIC "
+                        "(FP64 CG to relative residual 1e-10)",
+            "seconds": d["seconds"], "threads": d["threads"], "E_SIC": d["E_SIC"]}
 
 
 KERNEL_SOURCES = ("zmarch.h", "stencil_pcg.hip", "stencil_res.hip", "dst.hip", "common.h")

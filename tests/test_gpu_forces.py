@@ -54,6 +54,24 @@ def test_mol40_gradient_vs_oracle(torch_cuda, F, mol40, mol40_grad_oracle, preci
     ctx.close()
 
 
+@pytest.mark.parametrize("lmax", [2, 8])
+def test_mol40_gradient_other_multipole_orders(torch_cuda, F, oracle, mol40, lmax):
+    """The adjoint boundary contraction and the multipole part of the adjoint
+    field at other orders (fewer and more harmonic tiles than lmax = 6)."""
+    torch = torch_cuda
+    _say(f"gradient mol40 lmax={lmax}")
+    s = mol40
+    ref = oracle.sic_grad_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin, lmax=lmax)
+    ctx = F.Context(precision="mixed", tol=1e-11, solver="pcg", lmax=lmax)
+    psi = torch.tensor(np.asarray(s.psi[0]), device="cuda")
+    fod = torch.tensor(s.fod[0], requires_grad=True)
+    E, vs = F.flosic_sic(ctx, s.n, s.h, s.origin, [psi], [fod])
+    E.backward()
+    g = fod.grad.numpy()
+    assert np.abs(g - ref).max() < 1e-8, np.abs(g - ref).max()
+    ctx.close()
+
+
 @pytest.mark.parametrize("fd_gradient,eq9", [(True, False), (False, True), (True, True)])
 def test_mol40_paper_mode_gradient_vs_oracle(torch_cuda, F, oracle, mol40, mol40_grad_oracle,
                                              fd_gradient, eq9):
