@@ -12,11 +12,13 @@
 // matrix cores); the rest is N x N: Q = Z T, Z = S^{-1/2} (Daleckii-Krein
 // form of the derivative of the inverse square root), S = T G T^T,
 // T_i = u_i / |u_i|, u_i,a = psi_a(a_i) (cubic interpolant).
+#include <algorithm>
+
 #include "kernels.h"
+#include "tsgemm.h"
 
 namespace fsic {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // fully polarised LSDA potential (same parameterisation as the forward pass)
 __device__ __forceinline__ double vxc_pol(double rho, double floor) {
@@ -38,7 +40,7 @@ __device__ __forceinline__ double vxc_pol(double rho, double floor) {
     return vx + (ec - rs * dec * (1.0 / 3.0));
 }
 
-// B[i][a] = sum_m Gam_i(m) psi_a(m); wave w owns Gam tiles t1 = w, w + 4 and
+// Small N (at most two 16-row tiles): B[i][a] = sum_m Gam_i(m) psi_a(m); wave w owns Gam tiles t1 = w, w + 4 and
 // every psi tile t2; block b sums the node range [b chunk, (b+1) chunk).
 // TT: column tiles held per wave (2 for N <= 32, else 8), so small N keeps
 // few accumulators and many waves per SIMD.
@@ -135,6 +137,19 @@ __global__ __launch_bounds__(256) void k_adj_contract(int N, long long M, long l
                 out[(size_t)r * NP + c] = acc[a][t][j];
             }
         }
+    }
+}
+
+// Gam_i(m) = 2 dV phi_i omega_i, omega_i = -((v_i + w_i) / 2 + vxc(phi_i^2)),
+// over the channel's N x M values (Gam may be W: each value is read before
+// it is written, by the same thread)
+__global__ __launch_bounds__(256) void k_gamma(long long count, double dV, const double *PHI,
+                                               const double *V, const double *W, double floor,
+                                               double *Gam) {
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long long)gridDim.x * 256) {
+        const double ph = PHI[i];
+        const double om = -(0.5 * (V[i] + W[i]) + vxc_pol(ph * ph, floor));
+        Gam[i] = 2.0 * dV * ph * om;
     }
 }
 
@@ -239,16 +254,24 @@ __global__ __launch_bounds__(256) void k_lowdin_backward(int N, const double *Bm
 
 hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,
                                     const double *W, const double *psi, double floor, double *partB,
-                                    size_t cap, double *Bm, hipStream_t s) {
+                                    size_t cap, double *Bm, double *Gam, hipStream_t s) {
+    if (N < 1 || N > kMaxOrb) return hipErrorInvalidValue;
     const int nblk = grid_blocks(N, M, cap);
     long long chunk = (M + nblk - 1) / nblk;
-    chunk = (chunk + 3) & ~3LL;
-    if (((N + 15) >> 4) <= 2)
+    if (N <= 32) {  // Gam built on the fly
+        chunk = (chunk + 3) & ~3LL;
         hipLaunchKernelGGL(k_adj_contract<2>, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
-                       floor, partB);
-    else
-        hipLaunchKernelGGL(k_adj_contract<8>, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
-                       floor, partB);
+                           floor, partB);
+        hipLaunchKernelGGL(k_adj_contract_final, dim3(N * N), dim3(256), 0, s, N, nblk, partB, Bm);
+        return hipGetLastError();
+    }
+    const long long count = (long long)N * M;
+    const long long gblk = std::max(1LL, std::min((count + 255) / 256, 4096LL));
+    hipLaunchKernelGGL(k_gamma, dim3((unsigned)gblk), dim3(256), 0, s, count, dV, PHI, V, W, floor, Gam);
+    chunk = (chunk + kTK - 1) / kTK * kTK;
+    const size_t lds = tsg_lds_bytes(N, 2);
+    if (lds > 65536) hipFuncSetAttribute((const void *)k_tsg_nt<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_tsg_nt<false>, dim3(nblk), dim3(256), lds, s, N, M, chunk, Gam, psi, partB);
     hipLaunchKernelGGL(k_adj_contract_final, dim3(N * N), dim3(256), 0, s, N, nblk, partB, Bm);
     return hipGetLastError();
 }

@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "tsgemm.h"
 
 namespace fsic {
 
@@ -172,10 +173,11 @@ hipError_t launch_interp(int K, int N, int nx, int ny, int nz, double h, const d
 }
 
 // ---------------------------------------------------------------------------
-// Gram matrix G = dV psi psi^T on the matrix cores
+// Gram matrix G = dV psi psi^T on the matrix cores: k_tsg_nt<true>
+// (tsgemm.h) for more than 32 orbitals, below for at most 32
 // ---------------------------------------------------------------------------
 
-// Block b accumulates the node range [b*chunk, (b+1)*chunk); wave w owns the
+// Small N (at most two 16-row tiles).  Block b accumulates the node range [b*chunk, (b+1)*chunk); wave w owns the
 // upper-triangle tile pairs p = w, w+4, ...; partG[b] holds the block's sums.
 // FT: row tiles held per lane (2 for N <= 32, else 8), so small N keeps few
 // registers and many waves per SIMD.
@@ -273,24 +275,32 @@ __global__ __launch_bounds__(256) void k_gram_final(int N, int nblk, double dV, 
     if (threadIdx.x == 0) G[e] = dV * s;
 }
 
-// partial-sum blocks for a node range split: enough to fill the device
-// several times over, within the partial buffer (cap doubles)
+// partial-sum blocks for a node range split within the partial buffer (cap
+// doubles): for the staged kernels four per compute unit (at most 1024) of
+// at least four 32-node tiles; for the small-N ones up to 4096 of 64 nodes
 int grid_blocks(int N, long long M, size_t cap) {
     const size_t NP = (size_t)((N + 15) >> 4) * 16;
-    long long nb = (long long)std::min<size_t>(4096, cap / (NP * NP));
-    nb = std::min(nb, (M + 63) / 64);
+    const bool small = NP <= 32;
+    long long nb = (long long)std::min<size_t>(small ? 4096 : 1024, cap / (NP * NP));
+    nb = std::min(nb, small ? (M + 63) / 64 : (M + 4 * kTK - 1) / (4 * kTK));
     return (int)std::max(1LL, nb);
 }
 
 hipError_t launch_gram(int N, long long M, double dV, const double *psi, double *partG, size_t cap,
                        double *G, hipStream_t s) {
+    if (N < 1 || N > kMaxOrb) return hipErrorInvalidValue;
     const int nblk = grid_blocks(N, M, cap);
     long long chunk = (M + nblk - 1) / nblk;
-    chunk = (chunk + 3) & ~3LL;
-    if (((N + 15) >> 4) <= 2)
+    if (N <= 32) {
+        chunk = (chunk + 3) & ~3LL;
         hipLaunchKernelGGL(k_gram<2>, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, partG);
-    else
-        hipLaunchKernelGGL(k_gram<8>, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, partG);
+    } else {
+        chunk = (chunk + kTK - 1) / kTK * kTK;
+        const size_t lds = tsg_lds_bytes(N, 1);
+        if (lds > 65536)
+            hipFuncSetAttribute((const void *)k_tsg_nt<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_tsg_nt<true>, dim3(nblk), dim3(256), lds, s, N, M, chunk, psi, psi, partG);
+    }
     hipLaunchKernelGGL(k_gram_final, dim3(N * N), dim3(256), 0, s, N, nblk, dV, partG, G);
     return hipGetLastError();
 }
@@ -498,7 +508,9 @@ hipError_t launch_lowdin_batch(const LowdinBatch &lb, double *small, const Lowdi
 }
 
 // ---------------------------------------------------------------------------
-// out = A psi  (N x N times N x M) on the matrix cores
+// out = A psi  (N x N times N x M) on the matrix cores: k_tsg_nn (tsgemm.h)
+// for more than 32 orbitals; for at most 32 each wave takes 16-node strips
+// and all output rows, A read through the cache
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_orb_gemm(int N, long long M, const double *A,
@@ -592,10 +604,20 @@ hipError_t launch_orb_gemm32(int N, long long M, const double *A, const double *
 
 hipError_t launch_orb_gemm(int N, long long M, const double *A, const double *psi, double *out,
                            hipStream_t s) {
-    const long long nstrip = (M + 15) / 16;
-    long long nblk = (nstrip + 3) / 4;
-    if (nblk > 8192) nblk = 8192;
-    hipLaunchKernelGGL(k_orb_gemm, dim3((unsigned)nblk), dim3(256), 0, s, N, M, A, psi, out);
+    if (N < 1 || N > kMaxOrb) return hipErrorInvalidValue;
+    if (N <= 32) {
+        const long long nstrip = (M + 15) / 16;
+        const long long nblk = std::max(1LL, std::min((nstrip + 3) / 4, 8192LL));
+        hipLaunchKernelGGL(k_orb_gemm, dim3((unsigned)nblk), dim3(256), 0, s, N, M, A, psi, out);
+        return hipGetLastError();
+    }
+    const long long ntile = (M + kTK - 1) / kTK;
+    const long long nblk = std::max(1LL, std::min(ntile, 512LL));  // two per compute unit
+    const size_t lds = (size_t)16 * ((N + 15) / 16) * kTKS * sizeof(double);  // at most 33 KiB
+    if (N <= 64)
+        hipLaunchKernelGGL((k_tsg_nn<1, 16>), dim3((unsigned)nblk), dim3(256), lds, s, N, M, A, psi, out);
+    else
+        hipLaunchKernelGGL((k_tsg_nn<2, 32>), dim3((unsigned)nblk), dim3(256), lds, s, N, M, A, psi, out);
     return hipGetLastError();
 }
 

@@ -370,11 +370,13 @@ hipError_t launch_orb_gemm32(int N, long long M, const double *A, const double *
 // come one per such block).
 constexpr int kSicTile = 1024;
 
-// B[i][a] = sum_m Gam_i(m) psi_a(m) with Gam_i = 2 dV phi_i omega_i built on
-// the fly, omega_i = -((v_i + w_i) / 2 + vxc(phi_i^2)) (MFMA FP64)
+// B[i][a] = sum_m Gam_i(m) psi_a(m) with Gam_i = 2 dV phi_i omega_i,
+// omega_i = -((v_i + w_i) / 2 + vxc(phi_i^2)), contracted on the matrix cores
+// (FP64); for more than 32 orbitals Gam is first written to Gam (N x M; may
+// be W) by an elementwise pass, for at most 32 it is built on the fly
 hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,
                                     const double *W, const double *psi, double floor, double *partB,
-                                    size_t cap, double *Bm, hipStream_t s);
+                                    size_t cap, double *Bm, double *Gam, hipStream_t s);
 
 // reverse mode through Q = S^{-1/2} T, S = T G T^T, T = u/|u|, u = psi(a):
 // dEda[i][d] = gscale * sum_a Gam_u[i][a] dpsi_a(a_i)/da_d

@@ -2150,6 +2150,7 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         Wt = c->W.p;
     }
     const double t1 = now_ms();
+    HIPCHK(c, c->W.ensure((size_t)b.fields));  // Gam (the Eq. 9 form has no adjoint field)
     // per channel: B = Gam psi^T, then the N x N reverse chain
     std::vector<int> spin0(c->nsys, 0);
     for (const Chan &ch : c->chans)
@@ -2159,9 +2160,10 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         const Chan &ch = c->chans[ci];
         double *sm = c->small.p + ch.so;
         const double dV = ch.h * ch.h * ch.h;
+        // Gam overwrites W (the adjoint field is not needed after it)
         HIPCHK(c, launch_adjoint_contract(ch.N, ch.M, dV, c->PHI.p + ch.off, c->V.p + ch.off,
                                           Wt + ch.off, ch.psi, o.rho_floor, c->partG.p, c->partG.cap,
-                                          c->bmat.p, s));
+                                          c->bmat.p, c->W.p + ch.off, s));
         HIPCHK(c, launch_lowdin_backward(ch.N, c->bmat.p, sm + small_off(sT), sm + small_off(sG),
                                          sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
                                          sm + small_off(sRHOA), sm + small_off(sDU), c->work.p,
