@@ -63,6 +63,10 @@ def run_steps(F, torch, ctx, dicts, noccs, steps):
         e, U, X, st = ctx.forward(dicts)
         agg["shape"] = {"tile": f"32x{8 * st['stencil_cpt']}", "prefetch_planes": st["stencil_depth"],
                         "block_target": st["stencil_blocks"]}
+        lay = st["precond_layout"]
+        agg["precond_layout"] = {"variant": lay >> 4, "fused_xy": bool(lay & 1),
+                                 "xy_two_blocks_per_cu": bool(lay & 2), "z_two_blocks_per_cu": bool(lay & 4),
+                                 "early_p_old": bool(lay & 8)}
         for k in keys:
             agg[k] += st[k]
         agg["iters"] += st["total_iters"]
@@ -263,6 +267,7 @@ def roofline(args, agg):
     out["launches"] = r["launches"]
     out["kernels"] = rates
     out["stencil_shape"] = agg.get("shape")
+    out["precond_layout"] = agg.get("precond_layout")
     return out
 
 

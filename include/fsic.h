@@ -193,6 +193,17 @@ typedef struct {
     /* FSIC_GRAPHS: restart-cycle graphs captured so far by this context
      * (a replayed graph is not counted again) */
     int32_t graph_captures;
+    /* FSIC_PCG / FSIC_AAR: layout of the sine-transform preconditioner, bits
+     * 1 fused in-plane passes (else five per-axis passes), 2 two fused-pass
+     * blocks per compute unit, 4 two-block z pass, 8 inverse pass reads p_old
+     * before its products, plus 16 x the transform variant (1-3; 0: solved
+     * without the preconditioner).  The first call for a given (device,
+     * precision, order, solver, grid sizes and orbital counts) times every
+     * combination of the open choices on the batch and keeps the fastest for
+     * the process (precond_tune_ms: time that took, 0 when cached, when
+     * nothing was open, or under FSIC_AUTOTUNE=0). */
+    int32_t precond_layout;
+    double  precond_tune_ms;
 } fsic_stats;
 
 /* Fills *o with the defaults: fd_order 12, lmax 6, FSIC_PCG, FP64, tol 1e-10,

@@ -64,6 +64,8 @@ struct DstItems {
     int xyvec;       // every nx and orbital offset is a multiple of 4
     int npxy;        // largest padded in-plane axis (LDS layout of the fused kernel)
     int zocc2;       // z pass: 64-column panels, two blocks per compute unit
+    int xyocc2;      // fused x-y passes two blocks per compute unit (where the plane fits)
+    int pv;          // the inverse pass reads p_old before its products (else at the store)
 };
 
 // Output of the last transform pass when it forms the next search

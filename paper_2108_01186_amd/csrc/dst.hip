@@ -719,16 +719,6 @@ void set_lds_limit(K kern, size_t bytes) {
 
 namespace {
 
-// inverse pass (PO): read p_old before the products where registers allow
-// (FSIC_DST_PV=0 reads it at the store)
-bool dst_early_pold() {
-    static const bool v = [] {
-        const char *e = getenv("FSIC_DST_PV");
-        return !(e && atoi(e) == 0);
-    }();
-    return v;
-}
-
 // The passes of one preconditioner application.  T: type of r; PO: the last
 // pass writes p = z + beta p_old (po) into `out` instead of z.
 template <typename T, bool PO>
@@ -741,7 +731,7 @@ hipError_t dst_apply(const DstItems &di, const OrbDesc *orb, const int *done, co
     int *nc = nullptr;
     // forward and middle passes: no p output, but the pause state of po
     const PcgOut none{nullptr, nullptr, nullptr, 1, po.pz, po.li};
-    const bool pv = dst_early_pold();
+    const bool pv = di.pv != 0;
     auto grid = [&](int units) { return dim3((unsigned)std::min(units, di.blocks)); };
 #define FSIC_DST_FAST(PC_, SLO_, NPM_)                                                                \
     do {                                                                                              \
@@ -767,7 +757,7 @@ hipError_t dst_apply(const DstItems &di, const OrbDesc *orb, const int *done, co
     do {                                                                                              \
         const size_t lxy = dst_xy_lds(di.npxy, di.two != 0);                                          \
         const size_t lz = dst_fast_lds(di.np, 64, SLO_);                                              \
-        const bool o2 = di.xyvec && dst_xy_occ2(di.npxy, di.two != 0);                                \
+        const bool o2 = di.xyvec && di.xyocc2 && dst_xy_occ2(di.npxy, di.two != 0);                   \
         const dim3 gxy = o2 ? dim3((unsigned)std::min(di.nxy, 2 * di.blocks)) : grid(di.nxy);         \
         if (o2)                                                                                       \
             hipLaunchKernelGGL((k_dst_xy<true, T, T, true>), gxy, dim3(kFT), lxy, s, di.xy, di.nxy,   \

@@ -204,6 +204,9 @@ size_t dst_xy_lds(int np, bool two);
 // The z pass of a fused-plane batch with all axes padded to np can run two
 // 64-column blocks per compute unit.
 bool dst_z_occ2(int np);
+// The fused in-plane passes of planes padded to np (two: separate x and y
+// sine matrices) can run two blocks per compute unit.
+bool dst_xy_occ2(int np, bool two);
 
 // Allows the fast transform kernels of a variant (1..3, see DstItems) their
 // dynamic LDS for axes up to np, and the fused x-y kernel (npxy > 0: in-plane

@@ -166,6 +166,8 @@ struct Batch {
     bool dst_vec = true;   // every nx and orbital offset is a multiple of 4
     int npxy = 0;          // largest in-plane axis, padded to 32
     bool dst_zocc2 = false;  // z pass in 64-column panels, two blocks per compute unit
+    bool dst_xyocc2 = true;  // fused x-y passes two blocks per compute unit where the plane fits
+    bool dst_pv = true;      // inverse pass reads p_old before its products
     int max_group = 0;  // most orbitals in one channel
     // harmonic contractions over grid nodes (moments) and ghosts (adjoint
     // boundary): block items, channel ranges, partial-tile elements
@@ -306,6 +308,10 @@ struct fsic_ctx {
     int shape_cpt = 2, shape_depth = 1;
     long long shape_target = 0;
     double tune_ms = 0.0;
+    // preconditioner layout of the last batch (fsic_stats.precond_layout) and
+    // the time its tuning took (0: cached or not tuned)
+    int dst_layout = 0;
+    double dst_tune_ms = 0.0;
     // FSIC_GRAPHS: captured CG chunks, and the stream they are captured on
     std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
     int graph_captures = 0;  // graphs captured over the context's life (FSIC_GRAPHS)
@@ -473,7 +479,17 @@ size_t device_lds_limit() {
     return (size_t)v;
 }
 
-void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, Batch &b) {
+// Layout choices of the spectral preconditioner that LDS fit leaves open;
+// each takes effect only where the kernels it names fit (see build_batch):
+// fused x-y passes (else five per-axis passes), two fused-pass blocks per
+// compute unit, the two-block z pass, and the inverse pass reading p_old
+// before its products.  Defaults: all on; choose_dst times the others.
+struct DstTune {
+    bool xy = true, xyocc2 = true, zocc2 = true, pv = true;
+};
+
+void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, Batch &b,
+                 const DstTune &dt = DstTune{}) {
     const int cpt = sh.cpt;
     b = Batch{};
     long long cols = 0;
@@ -499,8 +515,11 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     {
         const char *env = std::getenv("FSIC_DST_XY");
         b.dst_xy = fast && b.npxy <= 128 && dst_xy_lds(b.npxy, b.dst_two) <= ldsmax &&
-                   !(env && std::atoi(env) == 0);
-        b.dst_zocc2 = b.dst_xy && variant == 1 && dst_z_occ2(npx);
+                   !(env && std::atoi(env) == 0) && dt.xy;
+        b.dst_zocc2 = b.dst_xy && variant == 1 && dst_z_occ2(npx) && dt.zocc2;
+        b.dst_xyocc2 = dt.xyocc2;
+        const char *epv = std::getenv("FSIC_DST_PV");
+        b.dst_pv = dt.pv && !(epv && std::atoi(epv) == 0);
     }
     std::vector<std::pair<int, int>> nat7, nat8, natx, naty, natz;
     std::map<int, std::pair<int, int>> dst_done;  // n -> (sine offset, symbol offset)
@@ -866,6 +885,133 @@ fsic_status choose_shape(fsic_ctx *c, const std::vector<Group> &groups, int prec
 }
 
 
+// Time one preconditioner application of a candidate layout on the batch's
+// own buffers (the solve that follows rewrites everything it touches):
+// one application to warm up, then three timed ones.
+fsic_status time_dst_layout(fsic_ctx *c, const std::vector<Group> &groups, int precision, const Shape &sh,
+                            const DstTune &dt, hipEvent_t e0, hipEvent_t e1, float &ms) {
+    hipStream_t s = c->stream;
+    Batch b;
+    build_batch(groups, c->radius, sh, b, dt);
+    fsic_status st = prepare_batch(c, b, precision);
+    if (st) return st;
+    const bool mixed = precision == FSIC_MIXED;
+    const size_t F = (size_t)b.fields;
+    const int norb = (int)b.orb.size();
+    HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
+    // r = 0 and r.z partials of a nonzero pattern (beta finite): the transform
+    // passes take the same time for any values
+    if (mixed) HIPCHK(c, hipMemsetAsync(c->R32.p, 0, F * sizeof(float), s));
+    else HIPCHK(c, hipMemsetAsync(c->R.p, 0, F * sizeof(double), s));
+    HIPCHK(c, hipMemsetAsync(c->partRZ.p, 0x3f, 2 * (size_t)b.tot9 * sizeof(double), s));
+    const DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(),
+                      (int)b.dz.size(), b.dst_fast, (b.max_n + 31) & ~31, dst_blocks(c),
+                      b.dst_xy ? c->d_dxy.p : nullptr, b.dst_xy ? (int)b.dxy.size() : 0, b.dst_two ? 1 : 0,
+                      b.dst_vec ? 1 : 0, b.npxy, b.dst_zocc2 ? 1 : 0, b.dst_xyocc2 ? 1 : 0, b.dst_pv ? 1 : 0};
+    auto apply = [&]() -> hipError_t {
+        if (mixed) {
+            // the mixed solve's form: the inverse pass writes p = z + beta p_old
+            const PcgOut po{c->P32a.p, c->partRZ.p, c->partRZ.p + b.tot9, 0, nullptr, 0};
+            return launch_dst_pcg(di, c->d_orb.p, c->done.p, c->dtab.p, c->R32.p, c->T32.p, c->P32b.p,
+                                  c->partRZ.p, po, nullptr, s);
+        }
+        return launch_dst_precond<double>(di, c->d_orb.p, c->done.p, c->dtab.p, c->R.p, c->T32.p, c->Z32.p,
+                                          c->partRZ.p, nullptr, s);
+    };
+    hipError_t he = apply();
+    if (he == hipSuccess) he = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && he == hipSuccess; ++r) he = apply();
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) return set_err(c, FSIC_EHIP, hipGetErrorString(he));
+    return FSIC_OK;
+}
+
+// fsic_stats.precond_layout bits of a built batch: 1 fused x-y passes,
+// 2 two fused-pass blocks per compute unit, 4 two-block z pass, 8 early
+// p_old read, and the transform variant (1-3) times 16
+int dst_layout_bits(const Batch &b) {
+    const bool o2 = b.dst_xy && b.dst_vec && b.dst_xyocc2 && dst_xy_occ2(b.npxy, b.dst_two);
+    return (b.dst_xy ? 1 : 0) | (o2 ? 2 : 0) | (b.dst_zocc2 ? 4 : 0) | (b.dst_xy && b.dst_pv ? 8 : 0) |
+           16 * b.dst_fast;
+}
+
+// Preconditioner layout for a batch: the first call for a (device,
+// precision, order, grid sizes and orbital counts) times every combination
+// of the choices in DstTune that changes the launches on this batch and
+// keeps the fastest for the process; FSIC_AUTOTUNE=0 keeps the defaults,
+// FSIC_DST_XY=0 / FSIC_DST_PV=0 fix their choice.
+fsic_status choose_dst(fsic_ctx *c, const std::vector<Group> &groups, int precision, const Shape &sh,
+                       DstTune &dt) {
+    dt = DstTune{};
+    c->dst_tune_ms = 0.0;
+    if (c->opts.solver != FSIC_PCG && c->opts.solver != FSIC_AAR) return FSIC_OK;
+    if (const char *ea = getenv("FSIC_AUTOTUNE"))
+        if (atoi(ea) == 0) return FSIC_OK;
+    Batch b0;
+    build_batch(groups, c->radius, sh, b0, dt);
+    if (!b0.dst_fast) return FSIC_OK;  // solved without the preconditioner
+    // which choices change anything here
+    const bool can_xy = b0.dst_xy;
+    const bool can_xyocc2 = can_xy && b0.dst_vec && dst_xy_occ2(b0.npxy, b0.dst_two);
+    const bool can_zocc2 = b0.dst_zocc2;
+    const bool can_pv = can_xy && b0.dst_pv && precision == FSIC_MIXED && c->opts.solver == FSIC_PCG;
+    std::vector<DstTune> cands;
+    for (int xy = can_xy ? 1 : 0; xy >= 0; --xy)
+        for (int o2 = (xy && can_xyocc2) ? 1 : 0; o2 >= 0; --o2)
+            for (int z2 = (xy && can_zocc2) ? 1 : 0; z2 >= 0; --z2)
+                for (int pv = (xy && can_pv) ? 1 : 0; pv >= 0; --pv) {
+                    DstTune t;
+                    t.xy = xy; t.xyocc2 = o2; t.zocc2 = z2; t.pv = pv;
+                    cands.push_back(t);
+                }
+    if (cands.size() <= 1) return FSIC_OK;
+    std::string key = std::to_string(c->device) + ":" + std::to_string(precision) + ":" +
+                      std::to_string(c->radius) + ":" + std::to_string(c->opts.solver);
+    for (const char *ev : {"FSIC_DST_XY", "FSIC_DST_PV", "FSIC_DST_BLOCKS"}) {
+        const char *e = getenv(ev);
+        key += std::string(":") + (e ? e : "-");
+    }
+    for (const Group &g : groups)
+        key += ":" + std::to_string(g.n[0]) + "x" + std::to_string(g.n[1]) + "x" +
+               std::to_string(g.n[2]) + "*" + std::to_string(g.count);
+    static std::mutex mu;
+    static std::map<std::string, DstTune> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto f = cache.find(key);
+        if (f != cache.end()) {
+            dt = f->second;
+            return FSIC_OK;
+        }
+    }
+    const double t0 = now_ms();
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return set_err(c, FSIC_EHIP, "hipEventCreate failed");
+    }
+    float best = 0.f;
+    fsic_status res = FSIC_OK;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        float ms = 0.f;
+        if ((res = time_dst_layout(c, groups, precision, sh, cands[i], e0, e1, ms))) break;
+        if (i == 0 || ms < best) {
+            best = ms;
+            dt = cands[i];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (res) return res;
+    c->dst_tune_ms = now_ms() - t0;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = dt;
+    return FSIC_OK;
+}
+
 // Solve -L x = scale * rho (+ boundary term) for every orbital of batch b.
 //   src: densities (square = 0) or orbitals (square = 1), field layout of b;
 //   with_bc: Dirichlet values from the multipole expansion (else zero);
@@ -986,7 +1132,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     DstItems di{c->d_dx.p, c->d_dy.p, c->d_dz.p, (int)b.dx.size(), (int)b.dy.size(),
                 (int)b.dz.size(), b.dst_fast, (b.max_n + 31) & ~31, dst_blocks(c),
                 b.dst_xy ? c->d_dxy.p : nullptr, b.dst_xy ? (int)b.dxy.size() : 0, b.dst_two ? 1 : 0,
-                b.dst_vec ? 1 : 0, b.npxy, b.dst_zocc2 ? 1 : 0};
+                b.dst_vec ? 1 : 0, b.npxy, b.dst_zocc2 ? 1 : 0, b.dst_xyocc2 ? 1 : 0, b.dst_pv ? 1 : 0};
     if (pcg && !mixed) {
         // FP64 CG preconditioned by the FP32 sine-transform inverse.  The host
         // enqueues two iterations at a time and then reads the converged-
@@ -1600,7 +1746,10 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         c->shape_cpt = sh.cpt;
         c->shape_depth = sh.depth;
         c->shape_target = sh.target;
-        build_batch(groups, P, sh, b);
+        DstTune dt;
+        if ((tst = choose_dst(c, groups, o.precision, sh, dt))) return tst;
+        build_batch(groups, P, sh, b, dt);
+        c->dst_layout = dst_layout_bits(b);
     }
     // channel descriptors for the average pass
     std::vector<ChanDesc> cd(nchan);
@@ -1796,6 +1945,8 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         st->resid_ms = c->resid_ms;
         st->resid_bytes = c->resid_bytes;
         st->graph_captures = c->graph_captures;
+        st->precond_layout = c->dst_layout;
+        st->precond_tune_ms = c->dst_tune_ms;
         st->stencil_cpt = c->shape_cpt;
         st->stencil_depth = c->shape_depth;
         st->stencil_blocks = c->shape_target;
@@ -1935,7 +2086,9 @@ fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lma
     if (st) return st;
     c->cf.cpt = sh.cpt;
     c->cf.depth = sh.depth;
-    build_batch(groups, c->radius, sh, b);
+    DstTune dt;
+    if ((st = choose_dst(c, groups, precision, sh, dt))) return st;
+    build_batch(groups, c->radius, sh, b, dt);
     st = prepare_batch(c, b, precision);
     if (st) return st;
     SolveReport rep;
@@ -2118,7 +2271,8 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     const Batch &b = c->batch;
     hipStream_t s = c->stream;
     const int norb = (int)b.orb.size();
-    c->tune_ms = 0.0;  // the backward pass reuses the forward pass's stencil shape
+    c->tune_ms = 0.0;  // the backward pass reuses the forward pass's stencil shape and
+    c->dst_tune_ms = 0.0;  // preconditioner layout
     c->sweep_launches = c->update_launches = c->precond_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
     c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
@@ -2208,6 +2362,8 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         st->resid_ms = c->resid_ms;
         st->resid_bytes = c->resid_bytes;
         st->graph_captures = c->graph_captures;
+        st->precond_layout = c->dst_layout;
+        st->precond_tune_ms = c->dst_tune_ms;
         st->stencil_cpt = c->shape_cpt;
         st->stencil_depth = c->shape_depth;
         st->stencil_blocks = c->shape_target;

@@ -69,7 +69,8 @@ class fsic_stats(ctypes.Structure):
                 ("stencil_cpt", ctypes.c_int32), ("stencil_depth", ctypes.c_int32),
                 ("stencil_blocks", ctypes.c_int64), ("tune_ms", ctypes.c_double),
                 ("resid_launches", ctypes.c_int32), ("resid_ms", ctypes.c_double),
-                ("resid_bytes", ctypes.c_double), ("graph_captures", ctypes.c_int32)]
+                ("resid_bytes", ctypes.c_double), ("graph_captures", ctypes.c_int32),
+                ("precond_layout", ctypes.c_int32), ("precond_tune_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms_phase"}

@@ -118,6 +118,30 @@ def test_fp32_orbital_gemm_error(torch_cuda, F, mol40_dev, mol40_oracle):
     assert dv < 1e-5
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_preconditioner_layout_tuned_once(torch_cuda, F, precision):
+    """The sine-transform layout is timed on the first batch of a grid
+    signature (a 44^3 molecule no other test uses) and reused after: the
+    second pass reports no tuning time, the same layout and the same energy
+    bit for bit; the layout is a valid variant with fused in-plane passes
+    available at this size."""
+    from paper_2108_01186_amd import synth
+    torch = torch_cuda
+    _say(f"preconditioner layout tuning {precision}")
+    s = synth.make_molecule("tune44", 44, 0.3, 4, 10, (4,), 4411)
+    s = _to_dev(torch, s)
+    d = F.system_dict(s)
+    ctx = F.Context(precision=precision, tol=1e-11)
+    e1, _, _, st1 = ctx.forward([d])
+    e2, _, _, st2 = ctx.forward([d])
+    ctx.close()
+    assert st1["precond_tune_ms"] > 0.0, st1["precond_tune_ms"]
+    assert st2["precond_tune_ms"] == 0.0
+    assert st1["precond_layout"] == st2["precond_layout"]
+    assert st1["precond_layout"] >> 4 == 1, st1["precond_layout"]  # 128-column variant at 44 nodes
+    assert e1[0] == e2[0]
+
+
 @pytest.mark.parametrize("precision,fused", [("mixed", "1"), ("mixed", "0"), ("fp64", "1")])
 def test_graph_replays_match_eager(torch_cuda, F, mol40_dev, precision, fused, monkeypatch):
     """FSIC_GRAPHS: restart cycles of the mixed preconditioned solve captured
