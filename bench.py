@@ -146,6 +146,7 @@ _SMALL_CASE = r'''
 import json, time
 from oracle import oracle
 from paper_2108_01186_amd import synth
+oracle.set_num_threads(1)
 s = synth.make_workload("mol40")
 t0 = time.perf_counter()
 r = oracle.sic_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin, tol=1e-10)
@@ -185,9 +186,10 @@ def kernel_source_hash():
 
 
 def stored_traffic(workload, kernel, solver):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy); None when
-    the summary is missing or was taken on other kernel sources."""
+    """(HBM bytes, algorithmic bytes) per launch with every orbital active of
+    the dominant kernel from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, calibrated on a plain copy); None when the summary is missing
+    or was taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{solver}_f32_{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -200,7 +202,7 @@ def stored_traffic(workload, kernel, solver):
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals["traffic_bytes_per_launch"]), float(vals["algorithmic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -261,7 +263,11 @@ def roofline(args, agg):
         # 2500 / 8 = 312 flop/B, so HBM is the roof; matrix-core use is shown beside
         out["mfma_bf16_tflops"] = 3.0 * r["tflops"]
         out["mfma_bf16_frac"] = 3.0 * r["tflops"] / BF16_MFMA_PEAK_TFLOPS
-    out["traffic"] = stored_traffic(args.workload, dom, args.solver)
+    # measured HBM bytes over algorithmic bytes of a full launch, applied to
+    # this run's sampled launches (the same per launch as `achieved`)
+    st = stored_traffic(args.workload, dom, args.solver)
+    out["traffic"] = st[0] / st[1] * r["algorithmic_bytes_per_launch"] if st else None
+    out["traffic_over_algorithmic"] = st[0] / st[1] if st else None
     out["algorithmic_bytes_per_launch"] = r["algorithmic_bytes_per_launch"]
     out["avg_launch_us"] = r["avg_launch_us"]
     out["launches"] = r["launches"]

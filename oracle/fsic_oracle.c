@@ -852,6 +852,8 @@ int orc_flo_spin(const int *n, double h, const double *origin, double rho_floor,
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
 
+void orc_set_num_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+
 int orc_sic_spin(const int *n, double h, const double *origin, int p, int lmax,
                  double tol, int maxit, double vscale, double rho_floor,
                  int N, const double *psi, const double *fod,

@@ -133,6 +133,8 @@ int orc_flo_spin(const int *n, double h, const double *origin, double rho_floor,
 
 /* OpenMP threads the oracle uses. */
 int orc_num_threads(void);
+/* threads of the parallel loops from here on (n > 0; the default is OpenMP's) */
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -271,6 +271,11 @@ def num_threads():
     return int(lib().orc_num_threads())
 
 
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from here on (OpenMP)."""
+    lib().orc_set_num_threads(int(n))
+
+
 def sic_grad_spin(psi, fod, n, h, origin, p=6, lmax=6, tol=1e-13, maxit=20000, rho_floor=1e-30,
                   fd_gradient=False, eq9=False):
     """dE_SIC/da for one spin channel, shape (N, 3).  fd_gradient: grad psi at
