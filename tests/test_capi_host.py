@@ -126,8 +126,9 @@ def test_stored_traffic_follows_kernel_sources(tmp_path, monkeypatch):
         (src / f).write_text("// " + f + "\n")
     good = bench.kernel_source_hash()
     path = prof / "precond_pcg_f32_toy_hbm_traffic.txt"
-    path.write_text(f"traffic_bytes_per_launch: 123\nkernel_source_sha256: {good}\n")
-    assert bench.stored_traffic("toy", "precond", "pcg") == 123.0
+    path.write_text(f"traffic_bytes_per_launch: 123\nalgorithmic_bytes_per_launch: 100\n"
+                    f"kernel_source_sha256: {good}\n")
+    assert bench.stored_traffic("toy", "precond", "pcg") == (123.0, 100.0)
     (src / "dst.hip").write_text("// changed\n")
     assert bench.stored_traffic("toy", "precond", "pcg") is None
     assert bench.stored_traffic("other", "precond", "pcg") is None
