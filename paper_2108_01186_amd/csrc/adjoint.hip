@@ -15,30 +15,11 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "lsda.h"
 #include "tsgemm.h"
 
 namespace fsic {
 
-
-// fully polarised LSDA potential (same parameterisation as the forward pass)
-__device__ __forceinline__ double vxc_pol(double rho, double floor) {
-    if (!(rho > floor)) return 0.0;
-    constexpr double kSixOverPiCbrt = 1.2407009817988000333;
-    constexpr double kRsCoef = 0.62035049089940001667;
-    const double r13 = cbrt(rho);
-    const double vx = -kSixOverPiCbrt * r13;
-    constexpr double A = 0.015545, a1 = 0.20548;
-    constexpr double b1 = 14.1189, b2 = 6.1977, b3 = 3.3662, b4 = 0.62517;
-    const double rs = kRsCoef / r13;
-    const double s = sqrt(rs);
-    const double q1 = 2.0 * A * (s * (b1 + s * (b2 + s * (b3 + s * b4))));
-    const double q1p = A * (b1 / s + 2.0 * b2 + 3.0 * b3 * s + 4.0 * b4 * rs);
-    const double lg = log1p(1.0 / q1);
-    const double q0 = -2.0 * A * (1.0 + a1 * rs);
-    const double ec = q0 * lg;
-    const double dec = -2.0 * A * a1 * lg - q0 * q1p / (q1 * (q1 + 1.0));
-    return vx + (ec - rs * dec * (1.0 / 3.0));
-}
 
 // Small N (at most two 16-row tiles): B[i][a] = sum_m Gam_i(m) psi_a(m); wave w owns Gam tiles t1 = w, w + 4 and
 // every psi tile t2; block b sums the node range [b chunk, (b+1) chunk).

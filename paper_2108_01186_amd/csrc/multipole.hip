@@ -7,6 +7,8 @@
 // azimuthal factor is (x + i y)^m and the polar factor r^(l-m) d^m P_l/dx^m
 // (z / r) obeys the three-term recurrence in l, so one node costs a few
 // hundred flops and no transcendental calls.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace fsic {
@@ -287,6 +289,7 @@ __global__ __launch_bounds__(256) void k_harm_contract(Coeffs cf, int P, const O
     constexpr int QT = (NLM + 15) / 16;                // 16-row tiles of H
     constexpr int SL = (QT + 3) / 4;                   // tiles per wave
     constexpr int R = MODE == 0 ? 1 : kMaxRadius;      // loads per f value
+    constexpr int D = MODE == 0 ? 3 : 1;               // steps whose loads are in flight
     static_assert(kHc == 64, "hc_build assumes 65-double rows");
     __shared__ double Hs[QT * 16][kHc + 1];  // odd row stride: conflict-free column reads
     __shared__ double Fs[16][kHc + 1];
@@ -307,9 +310,14 @@ __global__ __launch_bounds__(256) void k_harm_contract(Coeffs cf, int P, const O
     for (int sl = 0; sl < SL; ++sl)
 #pragma unroll
         for (int ot = 0; ot < 8; ++ot) acc[sl][ot] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // f of orbitals 16 ot + w + 4 k (k < 4) at the thread's node: raw loads
-    double raw[4][R];
-    auto issue = [&](const HcNode &nd, int ot) {
+    // steps s = (chunk t0 + s / OT, orbital tile s % OT); step s stages f of
+    // orbitals 16 ot + w + 4 k (k < 4) at the thread's node from the raw
+    // loads of ring slot s % D, issued D steps ahead
+    const int nsteps = (it.t1 - it.t0) * OT;
+    double raw[D][4][R];
+    auto issue = [&](int st, double (&rw)[4][R]) {
+        const int tq = st / OT, ot = st - tq * OT;
+        const HcNode nd = hc_decode<MODE>(od, P, nn, (long long)(it.t0 + tq) * kHc + lane);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int o = 16 * ot + w + 4 * k;
@@ -318,54 +326,68 @@ __global__ __launch_bounds__(256) void k_harm_contract(Coeffs cf, int P, const O
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const bool tap = ok && (MODE == 0 || q + nd.d <= P);
-                raw[k][q] = tap ? fo[nd.base + q * nd.st] : 0.0;
+                rw[k][q] = tap ? fo[nd.base + q * nd.st] : 0.0;
             }
         }
     };
-    HcNode nd = hc_decode<MODE>(od, P, nn, (long long)it.t0 * kHc + lane);
-    if (it.t0 < it.t1) issue(nd, 0);
-    __syncthreads();  // cs and the zero rows
-    for (int t = it.t0; t < it.t1; ++t) {
-        // this wave's rows of H for chunk t (the previous chunk's products are done)
-        hc_build<L, MODE>(nd.x, nd.y, nd.z, nd.valid, w, lane, Hs);
+    // products of the staged tile with this wave's harmonic tiles into the
+    // accumulators of orbital tile OC
+    auto products = [&](auto oc) {
+        constexpr int o = decltype(oc)::value;
 #pragma unroll
-        for (int ot = 0; ot < 8; ++ot) {
-            if (ot < OT) {  // uniform
+        for (int sl = 0; sl < SL; ++sl) {
+            const int qt = w + 4 * sl;
+            if (qt < QT) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    double f;
-                    if constexpr (MODE == 0) {
-                        f = square ? raw[k][0] * raw[k][0] : raw[k][0];
-                    } else {
-                        f = 0.0;
-#pragma unroll
-                        for (int q = 0; q < R; ++q) f += cs[q + nd.d] * raw[k][q];
-                        f *= od.inv_h2;
-                    }
-                    Fs[w + 4 * k][lane] = f;
-                }
-                // next tile's loads, in flight during the products
-                HcNode nxt = nd;
-                if (ot + 1 < OT) {
-                    issue(nd, ot + 1);
-                } else if (t + 1 < it.t1) {
-                    nxt = hc_decode<MODE>(od, P, nn, (long long)(t + 1) * kHc + lane);
-                    issue(nxt, 0);
-                }
-                __syncthreads();  // H and f staged
-#pragma unroll
-                for (int sl = 0; sl < SL; ++sl) {
-                    const int qt = w + 4 * sl;
-                    if (qt < QT) {
-#pragma unroll
-                        for (int k0 = 0; k0 < kHc; k0 += 4)
-                            acc[sl][ot] = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[16 * qt + lr][k0 + lk],
-                                                                               Fs[lr][k0 + lk], acc[sl][ot], 0, 0, 0);
-                    }
-                }
-                __syncthreads();  // products done with Fs (and, after the last tile, Hs)
-                nd = nxt;
+                for (int k0 = 0; k0 < kHc; k0 += 4)
+                    acc[sl][o] = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[16 * qt + lr][k0 + lk], Fs[lr][k0 + lk],
+                                                                      acc[sl][o], 0, 0, 0);
             }
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        if (j < nsteps) issue(j, raw[j]);
+    __syncthreads();  // cs and the zero rows
+    HcNode ndc{};
+    for (int s0 = 0; s0 < nsteps; s0 += D) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int st = s0 + j;
+            if (st >= nsteps) break;  // uniform
+            const int tq = st / OT, ot = st - tq * OT;
+            if (ot == 0) {
+                // this wave's rows of H for the chunk (the previous step's
+                // products are done: barrier at the end of every step)
+                ndc = hc_decode<MODE>(od, P, nn, (long long)(it.t0 + tq) * kHc + lane);
+                hc_build<L, MODE>(ndc.x, ndc.y, ndc.z, ndc.valid, w, lane, Hs);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double f;
+                if constexpr (MODE == 0) {
+                    f = square ? raw[j][k][0] * raw[j][k][0] : raw[j][k][0];
+                } else {
+                    f = 0.0;
+#pragma unroll
+                    for (int q = 0; q < R; ++q) f += cs[q + ndc.d] * raw[j][k][q];
+                    f *= od.inv_h2;
+                }
+                Fs[w + 4 * k][lane] = f;
+            }
+            if (st + D < nsteps) issue(st + D, raw[j]);  // in flight during the next D steps
+            __syncthreads();  // H and f staged
+            switch (ot) {
+                case 0: products(std::integral_constant<int, 0>{}); break;
+                case 1: products(std::integral_constant<int, 1>{}); break;
+                case 2: products(std::integral_constant<int, 2>{}); break;
+                case 3: products(std::integral_constant<int, 3>{}); break;
+                case 4: products(std::integral_constant<int, 4>{}); break;
+                case 5: products(std::integral_constant<int, 5>{}); break;
+                case 6: products(std::integral_constant<int, 6>{}); break;
+                default: products(std::integral_constant<int, 7>{}); break;
+            }
+            __syncthreads();  // products done with Fs (and, at a chunk's last tile, Hs)
         }
     }
     // partial tile: rows q, columns o (16 * OT of them); D lane l, item j is
@@ -450,44 +472,60 @@ __global__ __launch_bounds__(256) void k_harm_expand(HarmTables ht, int P, const
     }
     for (int e = threadIdx.x; e < (KQ - NLM) * kHc; e += 256) Hs[NLM + e / kHc][e % kHc] = 0.0;
     __syncthreads();
-    for (int t = it.t0; t < it.t1; ++t) {
-        const long long n0 = (long long)t * kHc;
-        const HcNode nd = hc_decode<MODE == 0 ? 1 : 0>(od, P, nn, n0 + lane);
-        const long long nout = n0 + 16 * w + lr;  // this lane's output node
-        double wv[8][4];                           // MODE 1: W before the update
-        if constexpr (MODE == 1) {
+    // steps s = (chunk t0 + s / OT, orbital tile s % OT); MODE 1 reads the W
+    // values a step updates D steps ahead, so the read-modify-write does not
+    // wait on memory at every chunk
+    constexpr int D = MODE == 1 ? 3 : 1;
+    const int nsteps = (it.t1 - it.t0) * OT;
+    double wv[D][4];
+    auto wload = [&](int st, double (&wr)[4]) {
+        const int tq = st / OT, ot = st - tq * OT;
+        const long long nout = (long long)(it.t0 + tq) * kHc + 16 * w + lr;
 #pragma unroll
-            for (int ot = 0; ot < 8; ++ot)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int o = 16 * ot + lk + 4 * j;
-                    wv[ot][j] = ot < OT && o < N && nout < nn ? out[od.off + (long long)o * M + nout] : 0.0;
-                }
+        for (int j = 0; j < 4; ++j) {
+            const int o = 16 * ot + lk + 4 * j;
+            wr[j] = o < N && nout < nn ? out[od.off + (long long)o * M + nout] : 0.0;
         }
-        hc_build<L, MODE == 0 ? 1 : 0>(nd.x, nd.y, nd.z, nd.valid, w, lane, Hs);
-        __syncthreads();  // H staged
+    };
+    if constexpr (MODE == 1) {
 #pragma unroll
-        for (int ot = 0; ot < 8; ++ot) {
-            if (ot < OT) {  // uniform
-                dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < D; ++j)
+            if (j < nsteps) wload(j, wv[j]);
+    }
+    for (int s0 = 0; s0 < nsteps; s0 += D) {
 #pragma unroll
-                for (int k0 = 0; k0 < KQ; k0 += 4)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Cs[(16 * ot + lr) * CST + k0 + lk],
-                                                               Hs[k0 + lk][16 * w + lr], acc, 0, 0, 0);
-                // D lane l, item j: orbital 16 ot + l / 16 + 4 j, node 16 w + l % 16
+        for (int j = 0; j < D; ++j) {
+            const int st = s0 + j;
+            if (st >= nsteps) break;  // uniform
+            const int tq = st / OT, ot = st - tq * OT;
+            const long long n0 = (long long)(it.t0 + tq) * kHc;
+            if (ot == 0) {
+                if (st > 0) __syncthreads();  // the previous chunk's products are done with H
+                const HcNode nd = hc_decode<MODE == 0 ? 1 : 0>(od, P, nn, n0 + lane);
+                hc_build<L, MODE == 0 ? 1 : 0>(nd.x, nd.y, nd.z, nd.valid, w, lane, Hs);
+                __syncthreads();  // H staged
+            }
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int o = 16 * ot + lk + 4 * j;
-                    if (o < N && nout < nn) {
-                        if constexpr (MODE == 0)
-                            out[od.goff + (long long)o * nn + nout] = acc[j];
-                        else
-                            out[od.off + (long long)o * M + nout] = wv[ot][j] + acc[j];
-                    }
+            for (int k0 = 0; k0 < KQ; k0 += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Cs[(16 * ot + lr) * CST + k0 + lk],
+                                                           Hs[k0 + lk][16 * w + lr], acc, 0, 0, 0);
+            // D lane l, item j: orbital 16 ot + l / 16 + 4 j, node 16 w + l % 16
+            const long long nout = n0 + 16 * w + lr;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int o = 16 * ot + lk + 4 * jj;
+                if (o < N && nout < nn) {
+                    if constexpr (MODE == 0)
+                        out[od.goff + (long long)o * nn + nout] = acc[jj];
+                    else
+                        out[od.off + (long long)o * M + nout] = wv[j][jj] + acc[jj];
                 }
             }
+            // steps st + 1 .. st + D - 1 touch other (orbital, node) pairs
+            if constexpr (MODE == 1)
+                if (st + D < nsteps) wload(st + D, wv[j]);
         }
-        __syncthreads();  // products done with H
     }
 }
 

@@ -7,39 +7,9 @@
 // One fused pass per spin channel: each thread owns nodes and walks the
 // orbitals, so phi_i and v_i are read once and V_SIC is written once.
 #include "kernels.h"
+#include "lsda.h"
 
 namespace fsic {
-
-// (6/pi)^(1/3) and (3/(4 pi))^(1/3)
-constexpr double kSixOverPiCbrt = 1.2407009817988000333;
-constexpr double kRsCoef = 0.62035049089940001667;
-
-// Fully polarised LSDA at one density.
-//   exchange: eps_x = -(3/4)(6/pi)^(1/3) rho^(1/3), v_x = (4/3) eps_x
-//   correlation: PW92 interpolation G(rs) with the zeta = 1 parameters
-//     A = 0.015545, alpha1 = 0.20548, beta1..4 = 14.1189, 6.1977, 3.3662, 0.62517;
-//     v_c = eps_c - (rs/3) d eps_c / d rs (no zeta term at zeta = 1).
-__device__ __forceinline__ void lsda_pol(double rho, double floor, double &ex, double &ec,
-                                         double &vx, double &vc) {
-    if (!(rho > floor)) {
-        ex = ec = vx = vc = 0.0;
-        return;
-    }
-    const double r13 = cbrt(rho);
-    ex = -0.75 * kSixOverPiCbrt * r13;
-    vx = -kSixOverPiCbrt * r13;
-    constexpr double A = 0.015545, a1 = 0.20548;
-    constexpr double b1 = 14.1189, b2 = 6.1977, b3 = 3.3662, b4 = 0.62517;
-    const double rs = kRsCoef / r13;
-    const double s = sqrt(rs);
-    const double q1 = 2.0 * A * (s * (b1 + s * (b2 + s * (b3 + s * b4)))) ;
-    const double q1p = A * (b1 / s + 2.0 * b2 + 3.0 * b3 * s + 4.0 * b4 * rs);
-    const double lg = log1p(1.0 / q1);
-    const double q0 = -2.0 * A * (1.0 + a1 * rs);
-    ec = q0 * lg;
-    const double dec = -2.0 * A * a1 * lg - q0 * q1p / (q1 * (q1 + 1.0));
-    vc = ec - rs * dec * (1.0 / 3.0);
-}
 
 __global__ __launch_bounds__(256) void k_xc_pointwise(long long count, const double *rho,
                                                       double floor, double *ex, double *ec,
