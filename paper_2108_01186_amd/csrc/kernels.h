@@ -249,7 +249,10 @@ struct HcItem {
     int first, count;  // orbitals of the channel
     int t0, t1;        // chunks [t0, t1) of 64 nodes (grid nodes or ghosts)
     long long poff;    // element offset of this block's partial tile
+    int ot0, ot1;      // 16-orbital tiles [ot0, ot1) of the channel (expansions; contractions take all)
 };
+// 16-orbital tiles per expansion block (its coefficient rows in LDS)
+constexpr int kHcExpandTiles = 2;
 struct HcChan {
     int first, count;  // orbitals of the channel
     int nparts;        // its partial tiles, consecutive from poff
@@ -266,10 +269,11 @@ hipError_t launch_harm_contract(int mode, int lmax, const HarmTables &ht, const 
 // Harmonic expansions of one channel's orbitals on the matrix cores: mode 0,
 // the ghost values g_o = sum_lm gfac_lm Q[o][lm] Y_lm / r^(l+1) on the face
 // slabs (written to out = G); mode 1, the multipole part of the adjoint
-// field, W_o += dV sum_lm zt[o][lm] r^l Y_lm on the grid.  items: the
-// ghost-chunk (mode 0) or node-chunk (mode 1) list of launch_harm_contract.
+// field, W_o += dV sum_lm zt[o][lm] r^l Y_lm on the grid.  items: ghost
+// chunks (mode 0) or node chunks (mode 1), each with at most
+// kHcExpandTiles orbital tiles.
 hipError_t launch_harm_expand(int mode, int lmax, const HarmTables &ht, int radius, const OrbDesc *orb,
-                              const long long *ghost_count, const HcItem *items, int nitems, int max_count,
+                              const long long *ghost_count, const HcItem *items, int nitems,
                               const double *C, double *out, hipStream_t s);
 
 // In place of the ghost values G, the boundary term of the interior nodes

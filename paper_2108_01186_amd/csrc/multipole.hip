@@ -439,9 +439,11 @@ __global__ __launch_bounds__(256) void k_harm_final(HarmTables ht, const HcChan 
 //          C' = gfac_q norm_q Q[o][q], out = G (written);
 //   MODE 1 (multipole part of the adjoint field): n = grid nodes,
 //          H_q = r^l P_lm, C' = dV norm_q zt[o][q], out = W (added to).
-// The block stages C' (16 rows per orbital tile) in LDS once; per 64-node
-// chunk the four waves build H as in the contraction, then wave w forms the
-// 16 x 16 result tiles of nodes 16 w .. 16 w + 15 for every orbital tile.
+// A block takes a range of 64-node chunks and at most kHcExpandTiles tiles
+// of 16 orbitals (so their coefficient rows C' in LDS leave room for several
+// blocks per compute unit); per chunk the four waves build H as in the
+// contraction, then wave w forms the 16 x 16 result tiles of nodes
+// 16 w .. 16 w + 15 for each of the block's orbital tiles.
 // ---------------------------------------------------------------------------
 
 template <int L, int MODE>
@@ -453,22 +455,23 @@ __global__ __launch_bounds__(256) void k_harm_expand(HarmTables ht, int P, const
     constexpr int CST = KQ + 1;                // odd row stride of C'
     static_assert(kHc == 64, "hc_build assumes 65-double rows");
     __shared__ double Hs[KQ][kHc + 1];
-    extern __shared__ double Cs[];  // [16 OT][CST]
+    extern __shared__ double Cs[];  // [16 (ot1 - ot0)][CST]
     const HcItem it = items[blockIdx.x];
     const OrbDesc od = orb[it.first];  // every orbital of the channel shares this grid
     const int N = it.count;
-    const int OT = (N + 15) >> 4;
+    const int OT = it.ot1 - it.ot0;  // this block's orbital tiles, from it.ot0
     const long long M = (long long)od.nx * od.ny * od.nz;
     const long long nn = MODE == 0 ? gcount[it.first] : M;
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lr = lane & 15, lk = lane >> 4;
     const double dV = od.h * od.h * od.h;
     for (int e = threadIdx.x; e < 16 * OT * KQ; e += 256) {
-        const int o = e / KQ, q = e - o * KQ;
+        const int r = e / KQ, q = e - r * KQ;
+        const int o = 16 * it.ot0 + r;
         double v = 0.0;
         if (o < N && q < NLM)
             v = C[(size_t)(it.first + o) * NLM + q] * ht.norm[q] * (MODE == 0 ? ht.gfac[q] : dV);
-        Cs[o * CST + q] = v;
+        Cs[r * CST + q] = v;
     }
     for (int e = threadIdx.x; e < (KQ - NLM) * kHc; e += 256) Hs[NLM + e / kHc][e % kHc] = 0.0;
     __syncthreads();
@@ -483,7 +486,7 @@ __global__ __launch_bounds__(256) void k_harm_expand(HarmTables ht, int P, const
         const long long nout = (long long)(it.t0 + tq) * kHc + 16 * w + lr;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int o = 16 * ot + lk + 4 * j;
+            const int o = 16 * (it.ot0 + ot) + lk + 4 * j;
             wr[j] = o < N && nout < nn ? out[od.off + (long long)o * M + nout] : 0.0;
         }
     };
@@ -510,11 +513,11 @@ __global__ __launch_bounds__(256) void k_harm_expand(HarmTables ht, int P, const
             for (int k0 = 0; k0 < KQ; k0 += 4)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Cs[(16 * ot + lr) * CST + k0 + lk],
                                                            Hs[k0 + lk][16 * w + lr], acc, 0, 0, 0);
-            // D lane l, item j: orbital 16 ot + l / 16 + 4 j, node 16 w + l % 16
+            // D lane l, item j: orbital 16 (ot0 + ot) + l / 16 + 4 j, node 16 w + l % 16
             const long long nout = n0 + 16 * w + lr;
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-                const int o = 16 * ot + lk + 4 * jj;
+                const int o = 16 * (it.ot0 + ot) + lk + 4 * jj;
                 if (o < N && nout < nn) {
                     if constexpr (MODE == 0)
                         out[od.goff + (long long)o * nn + nout] = acc[jj];
@@ -571,12 +574,12 @@ hipError_t launch_harm_contract(int mode, int lmax, const HarmTables &ht, const 
 }
 
 hipError_t launch_harm_expand(int mode, int lmax, const HarmTables &ht, int radius, const OrbDesc *orb,
-                              const long long *ghost_count, const HcItem *items, int nitems, int max_count,
+                              const long long *ghost_count, const HcItem *items, int nitems,
                               const double *C, double *out, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    if (radius < 1 || radius > kMaxRadius || max_count < 1 || max_count > kMaxOrb) return hipErrorInvalidValue;
+    if (radius < 1 || radius > kMaxRadius) return hipErrorInvalidValue;
     const int kq = ((lmax + 1) * (lmax + 1) + 15) / 16 * 16;
-    const size_t lds = (size_t)16 * ((max_count + 15) / 16) * (kq + 1) * sizeof(double);
+    const size_t lds = (size_t)16 * kHcExpandTiles * (kq + 1) * sizeof(double);
 #define CALL(L)                                                                                        \
     do {                                                                                               \
         const void *fn = mode == 0 ? (const void *)k_harm_expand<L, 0> : (const void *)k_harm_expand<L, 1>; \

@@ -172,6 +172,7 @@ struct Batch {
     // harmonic contractions over grid nodes (moments) and ghosts (adjoint
     // boundary): block items, channel ranges, partial-tile elements
     std::vector<HcItem> hcN, hcG;
+    std::vector<HcItem> hcNx, hcGx;  // the same split by orbital tile groups (expansions)
     std::vector<HcChan> hchN, hchG;
     long long hc_elems = 0;
 };
@@ -198,7 +199,8 @@ void build_hc_items(const std::vector<std::array<long long, 3>> &chans, std::vec
         const long long tile = (long long)kHcRows * 16 * ((count + 15) / 16);
         HcChan hc{first, count, (int)nb, elems};
         for (long long i = 0; i < nb; ++i) {
-            items.push_back(HcItem{first, count, (int)(chunks * i / nb), (int)(chunks * (i + 1) / nb), elems});
+            items.push_back(HcItem{first, count, (int)(chunks * i / nb), (int)(chunks * (i + 1) / nb), elems, 0,
+                                   (count + 15) / 16});
             elems += tile;
         }
         out.push_back(hc);
@@ -249,7 +251,7 @@ struct fsic_ctx {
     DBuf<Item> d_dx, d_dy, d_dz, d_dxy;
     DBuf<double> Gh;  // ghost values
     DBuf<double> part7, part8, partRU, partH;  // partH: harmonic-contraction partial tiles
-    DBuf<HcItem> d_hcN, d_hcG;
+    DBuf<HcItem> d_hcN, d_hcG, d_hcNx, d_hcGx;
     DBuf<HcChan> d_hchN, d_hchG;
     DBuf<double> bb, rrfin, relres, Qlm, Zt, ptrue;
     DBuf<int> done, iters, rs_iter, nact;
@@ -609,6 +611,17 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     build_hc_items(hcn, b.hcN, b.hchN, en);
     build_hc_items(hcg, b.hcG, b.hchG, eg);
     b.hc_elems = std::max(en, eg);
+    for (auto *pr : {&b.hcN, &b.hcG}) {
+        std::vector<HcItem> &dst = pr == &b.hcN ? b.hcNx : b.hcGx;
+        dst.clear();
+        for (const HcItem &it : *pr)
+            for (int o0 = 0; o0 < it.ot1; o0 += kHcExpandTiles) {
+                HcItem e = it;
+                e.ot0 = o0;
+                e.ot1 = std::min(it.ot1, o0 + kHcExpandTiles);
+                dst.push_back(e);
+            }
+    }
     // persistent kernels take contiguous unit ranges: keep orbital order so
     // one sine matrix serves a whole range
     for (auto *pr : {&natx, &naty, &natz}) {
@@ -655,6 +668,8 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
     if ((st = upload(c, c->d_gcount, b.gcount))) return st;
     if ((st = upload(c, c->d_hcN, b.hcN))) return st;
     if ((st = upload(c, c->d_hcG, b.hcG))) return st;
+    if ((st = upload(c, c->d_hcNx, b.hcNx))) return st;
+    if ((st = upload(c, c->d_hcGx, b.hcGx))) return st;
     if ((st = upload(c, c->d_hchN, b.hchN))) return st;
     if ((st = upload(c, c->d_hchG, b.hchG))) return st;
     if (use_pcg(c, b) || use_aar(c, b)) {
@@ -1073,8 +1088,8 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         HIPCHK(c, launch_harm_contract(0, c->opts.lmax, c->ht, c->cf, c->radius, c->d_orb.p, c->d_gcount.p,
                                        c->d_hcN.p, (int)b.hcN.size(), c->d_hchN.p, (int)b.hchN.size(),
                                        b.max_group, src, square, c->partH.p, c->Qlm.p, s));
-        HIPCHK(c, launch_harm_expand(0, c->opts.lmax, c->ht, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcG.p,
-                                     (int)b.hcG.size(), b.max_group, c->Qlm.p, c->Gh.p, s));
+        HIPCHK(c, launch_harm_expand(0, c->opts.lmax, c->ht, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcGx.p,
+                                     (int)b.hcGx.size(), c->Qlm.p, c->Gh.p, s));
         HIPCHK(c, launch_bterm(c->radius, c->cf, norb, c->d_orb.p, b.max_ghost / c->radius, c->Gh.p, s));
     }
     (void)nlm;
@@ -1649,7 +1664,7 @@ void fsic_destroy(fsic_ctx *c) {
     c->Fprev.release(); c->Fh.release(); c->Xh.release(); c->aar_gamma.release(); c->partD.release();
     c->d_dx.release(); c->d_dy.release(); c->d_dz.release(); c->d_dxy.release();
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
-    c->partH.release(); c->d_hcN.release(); c->d_hcG.release(); c->d_hchN.release(); c->d_hchG.release();
+    c->partH.release(); c->d_hcN.release(); c->d_hcG.release(); c->d_hcNx.release(); c->d_hcGx.release(); c->d_hchN.release(); c->d_hchG.release();
     c->bb.release(); c->rrfin.release();
     c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release();
     c->done.release(); c->iters.release(); c->rs_iter.release(); c->nact.release(); c->d_orb.release(); c->d_items7.release();
@@ -1778,7 +1793,7 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     const long long lw = 3LL * kMaxOrb * kMaxOrb;  // Loewdin scratch per channel of a batched launch
     HIPCHK(c, c->work.ensure(std::max<size_t>(4 * (size_t)kMaxOrb * kMaxOrb,
                                               (size_t)std::min(nchan, kLowdinBatch) * (size_t)lw)));
-    const int gram_blk = 256;
+    const int gram_blk = 1024;  // partial tiles of the orbital GEMMs: up to four blocks per compute unit
     c->sweep_launches = c->update_launches = c->precond_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
     c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
@@ -2299,8 +2314,8 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         HIPCHK(c, launch_harm_contract(1, o.lmax, hta, c->cf, c->radius, c->d_orb.p, c->d_gcount.p,
                                        c->d_hcG.p, (int)b.hcG.size(), c->d_hchG.p, (int)b.hchG.size(),
                                        b.max_group, c->W.p, 0, c->partH.p, c->Zt.p, s));
-        HIPCHK(c, launch_harm_expand(1, o.lmax, c->ht, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcN.p,
-                                     (int)b.hcN.size(), b.max_group, c->Zt.p, c->W.p, s));
+        HIPCHK(c, launch_harm_expand(1, o.lmax, c->ht, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcNx.p,
+                                     (int)b.hcNx.size(), c->Zt.p, c->W.p, s));
         Wt = c->W.p;
     }
     const double t1 = now_ms();
