@@ -48,7 +48,8 @@ __device__ __forceinline__ void tsg_store(double *S, int NP, const double (&reg)
 // part[b] = sum over the nodes [b chunk, (b+1) chunk) of X_i(m) Y_j(m) as an
 // NP x NP tile (NP = 16 ceil(N / 16)).  SYM: Y = X and only the tile pairs
 // t1 <= t2 are formed (the reader mirrors the rest).  Wave w owns row tiles
-// t1 = w and (SYM) NT-1-w or (else) w + 4, each against every column tile;
+// t1 = w and (SYM) NT-1-w when that is above 3, or (else) w + 4, each against
+// every column tile;
 // with at most two row tiles every wave forms all of them over a quarter of
 // the k-steps instead and the four partial tiles are added in LDS.
 // Dynamic LDS: NP x kTKS doubles (SYM) or twice that.
@@ -67,8 +68,10 @@ __global__ __launch_bounds__(256) void k_tsg_nt(int N, long long M, long long ch
         t1[0] = 0;
         t1[1] = NT > 1 ? 1 : 8;
     } else if (SYM) {
+        // rows w and (beyond the four primary rows) NT - 1 - w: the longer
+        // and the shorter row of the tile triangle
         t1[0] = w < NT ? w : 8;
-        t1[1] = (NT - 1 - w > w) ? NT - 1 - w : 8;
+        t1[1] = (NT - 1 - w >= 4) ? NT - 1 - w : 8;
     } else {
         t1[0] = w < NT ? w : 8;
         t1[1] = w + 4 < NT ? w + 4 : 8;

@@ -59,3 +59,24 @@ def test_noalloc_flo_matches_allocating_entry_point(torch_cuda):
         for lab, a, b in zip(("T", "G", "S", "Z", "phi"), got, ref):
             assert np.all(np.isfinite(a)), lab
             assert np.abs(a - b).max() <= 1e-13 * max(1.0, np.abs(b).max()), (name, lab)
+
+
+def test_noalloc_flo_staged_products(torch_cuda):
+    """More than 32 orbitals per channel take the LDS-staged Gram and orbital
+    products inside the no-allocation entry point too (their partial tiles
+    in its fixed array): two calls in a row, the second smaller."""
+    torch = torch_cuda
+    from paper_2108_01186_amd import fsic as F
+    na = F.fsic_op_flo_noalloc
+    big = synth.make_molecule("na36", 36, 0.3, n_atoms=40, n_gauss=96, nocc=(40,), seed=3101)
+    small = synth.make_molecule("na32", 32, 0.3, n_atoms=36, n_gauss=87, nocc=(36,), seed=3102)
+    cases = (("36^3, 40 orbitals", big), ("32^3, 36 orbitals", small))
+    refs = [_call(F, F.fsic_op_flo, torch, s) for _, s in cases]
+    gots = []
+    for name, s in cases:
+        _say(f"no-alloc FLO: {name}")
+        gots.append(_call(F, na, torch, s))
+    for (name, _), got, ref in zip(cases, gots, refs):
+        for lab, a, b in zip(("T", "G", "S", "Z", "phi"), got, ref):
+            assert np.all(np.isfinite(a)), lab
+            assert np.abs(a - b).max() <= 1e-13 * max(1.0, np.abs(b).max()), (name, lab)
