@@ -24,6 +24,12 @@
  *   - orbital SIC potential V_i = -(v_H[rho_i] + v_xc[rho_i, 0]), Slater
  *     average over sum_i rho_i, the scale factor applies to the potential
  *     only.
+ *
+ * Pins: every routine is checked by the CPU tests against closed forms,
+ * invariants or brute force.  One partial exception: the PW92 fit constants
+ * alpha1, beta3, beta4 (zeta = 1) are pinned only to the 0.5 % accuracy of
+ * two other published fits of the same Monte Carlo data; their digits below
+ * that are parity unpinned.
  */
 #include "fsic_oracle.h"
 
