@@ -590,7 +590,14 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
             }
             const int o = (int)b.orb.size();
             b.orb.push_back(od);
-            for (int t = 0; t < od.nt7; ++t) nat7.push_back({o, t});
+            // the z-chunks of one column tile next to each other: their
+            // blocks share an XCD and run together, so the planes beside a
+            // chunk boundary (reached by both at once, the odd chunks marching
+            // downwards) are fetched once into that XCD's L2
+            for (int by = 0; by < od.tiles_y; ++by)
+                for (int bx = 0; bx < od.tiles_x; ++bx)
+                    for (int bz = 0; bz < od.tiles_z; ++bz)
+                        nat7.push_back({o, bx + od.tiles_x * (by + od.tiles_y * bz)});
             for (int t = 0; t < od.nt8; ++t) nat8.push_back({o, t});
             if (b.dst_xy) {
                 for (int z = 0; z < g.n[2]; ++z) b.dxy.push_back(Item{o, z});
@@ -804,9 +811,10 @@ bool fixed_shape(int radius, int precision, Shape &sh) {
 }
 
 // Time the CG sweep (k = 0, no convergence test) of every candidate shape on
-// the batch's own buffers and keep the fastest.  The solve that follows
-// rewrites everything these launches touch (q, the p.q partials and the
-// activity counters).
+// the batch's own buffers, in mixed precision plus half the FP64 residual
+// pass (one per restart cycle of two sweeps), and keep the fastest.  The
+// solve that follows rewrites everything these launches touch (q, the p.q
+// and residual partials, the second x64 buffer and the activity counters).
 template <typename T>
 fsic_status time_shapes(fsic_ctx *c, const std::vector<Group> &groups, int precision,
                         const std::vector<Shape> &cands, Shape &best) {
@@ -856,6 +864,29 @@ fsic_status time_shapes(fsic_ctx *c, const std::vector<Group> &groups, int preci
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.f;
         if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess && mixed) {
+            // the FP64 residual pass that closes each mixed restart cycle of
+            // two FP32 sweeps (three operand arrays: its best shape differs);
+            // it reads B and the FP32 field and writes scratch buffers the
+            // solve rewrites before reading
+            if (c->partRU.ensure((size_t)b.tot7) != hipSuccess || c->X64b.ensure(F) != hipSuccess) {
+                res = FSIC_ENOMEM;
+                break;
+            }
+            auto resid = [&]() {
+                return launch_true_residual(c->radius, cf, c->d_items7.p, (int)b.items7.size(), c->d_orb.p,
+                                            c->done.p, c->B.p, (const float *)(void *)R, c->B.p, c->X64b.p,
+                                            (float *)(void *)Q, c->partRU.p, s);
+            };
+            he = resid();
+            if (he == hipSuccess) he = hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && he == hipSuccess; ++r) he = resid();
+            if (he == hipSuccess) he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float mr = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&mr, e0, e1);
+            ms += 0.5f * mr;
+        }
         if (he != hipSuccess) { res = set_err(c, FSIC_EHIP, hipGetErrorString(he)); break; }
         if (&sh == &cands[0] || ms < best_ms) {
             best_ms = ms;

@@ -99,6 +99,13 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
     const int x = bx * kTX + tx;
     const int z0 = bz * od.zc;
     const int z1 = min(nz, z0 + od.zc);
+    const int len = z1 - z0;
+    // odd z-chunks march downwards: the two chunks beside a chunk boundary
+    // then reach it at the same time (both at their start or both at their
+    // end), so the halo planes one of them fetches are still in L2 for the
+    // other (their blocks are adjacent in the item table, on one XCD)
+    const bool down = (bz & 1) != 0;
+    auto zat = [&](int s) -> int { return down ? z1 - 1 - s : z0 + s; };  // plane at march step s
 
     T c[P + 1];
 #pragma unroll
@@ -149,23 +156,24 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
     auto use = [&](const Raw &r, bool valid) -> T { return valid ? p.combine(r) : T(0); };
 
     // z window of each column in registers, rotated by unrolling (no moves):
-    // plane z - P + j lives in slot (z - z0 + j) % NW
+    // the plane of march step s - P + j lives in slot (s + j) % NW (the
+    // stencil is symmetric in z, so the direction does not matter)
     T q[CPT][NW];
 #pragma unroll
     for (int j = 0; j < 2 * P; ++j) {
-        const int z = z0 - P + j;
+        const int z = zat(j - P);
         const int pz = zoff(z);
         const bool zin = z >= 0 && z < nz;
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) q[cc][j] = use(p.raw(coff[cc], pz), cval[cc] && zin);
     }
-    // prefetch ring: stage d holds the raw loads of plane z + d (+ P for the
+    // prefetch ring: stage d holds the raw loads of march step d (+ P for the
     // columns' operand)
     Raw sc[D][CPT], sh[D][HS];
     Ext se[D][CPT];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const int pc = zoff(z0 + d + P), ph = zoff(z0 + d);
+        const int pc = zoff(zat(d + P)), ph = zoff(zat(d));
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
             sc[d][cc] = p.raw(coff[cc], pc);
@@ -177,16 +185,18 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
 
     Acc acc{};
     // one z step; U is the compile-time position in the unrolled block of NW*D
-    auto step = [&](auto uc, int zb) {
+    auto step = [&](auto uc, int sb) {
         constexpr int u = decltype(uc)::value;
         constexpr int d = u % D;
-        constexpr int sl0 = u % NW;  // slot of plane z - P
-        const int z = zb + u;
-        if (z >= z1) return;
-        // buffer parity follows the plane index (NW*D is odd, so u & 1 would
+        constexpr int sl0 = u % NW;  // slot of march step s - P
+        const int s = sb + u;
+        if (s >= len) return;
+        const int z = zat(s);
+        // buffer parity follows the step index (NW*D is odd, so u & 1 would
         // reuse a buffer across the boundary of two unrolled blocks)
-        T *S = sm[(z - z0) & 1];
-        const bool ztop = (z + P) < nz;
+        T *S = sm[s & 1];
+        const int zt = zat(s + P);
+        const bool ztop = zt >= 0 && zt < nz;
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
             q[cc][(sl0 + 2 * P) % NW] = use(sc[d][cc], cval[cc] && ztop);
@@ -198,8 +208,8 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
         Ext ecur[CPT];
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) ecur[cc] = se[d][cc];
-        if (z + D < z1) {  // refill this stage with plane z + D
-            const int pc = zoff(z + D + P), ph = zoff(z + D);
+        if (s + D < len) {  // refill this stage with march step s + D
+            const int pc = zoff(zat(s + D + P)), ph = zoff(zat(s + D));
 #pragma unroll
             for (int cc = 0; cc < CPT; ++cc) {
                 sc[d][cc] = p.raw(coff[cc], pc);
@@ -223,7 +233,7 @@ __global__ __launch_bounds__(256) void k_zmarch(Pol pol, Coeffs cf) {
             if (cval[cc]) p.epilogue(coff[cc], pz, q[cc][(sl0 + P) % NW], lap, ecur[cc], acc);
         }
     };
-    for (int zb = z0; zb < z1; zb += NW * D) unroll_steps<NW * D>(step, zb);
+    for (int sb = 0; sb < len; sb += NW * D) unroll_steps<NW * D>(step, sb);
     p.finish(it, od, acc, sred);  // every thread (block reductions)
 }
 
