@@ -393,6 +393,17 @@ int pcg_chunk(int variant) {
     return (variant == 1 || variant == 2) ? 2 : 3;
 }
 
+// iterations of the first restart cycle (from x = 0); FSIC_PCG_FIRST
+// overrides
+int pcg_first_chunk(int variant) {
+    static int v = [] {
+        const char *e = getenv("FSIC_PCG_FIRST");
+        return e ? std::max(1, atoi(e)) : 0;
+    }();
+    if (v) return v;
+    return pcg_chunk(variant);
+}
+
 // AAR parameters (the paper does not state them): Richardson weight omega,
 // Anderson mixing beta, an Anderson step every kAarPeriod iterations over
 // the last kAarM differences; with the sine-transform preconditioner these
@@ -1295,15 +1306,18 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         a.rs_iter = nullptr; a.nact = c->nact.p; a.norb = norb; a.ndone = c->ndone.p;
         a.tol2 = tol2;
         const CGIter<float> a0 = a;
+        // the first cycle (from x = 0) runs cyc0 iterations, the others cyc
         const int cyc = std::max(2, pcg_chunk(b.dst_fast));
-        const int ncyc = std::max(1, max_iter / cyc);
+        const int cyc0 = std::max(2, pcg_first_chunk(b.dst_fast));
+        const int cycmax = std::max(cyc, cyc0);
+        const int ncyc = 1 + std::max(0, (max_iter - cyc0) / cyc);
         HIPCHK(c, c->X64b.ensure((size_t)b.fields));
-        if (cyc > 2) HIPCHK(c, c->X32.ensure((size_t)b.fields));
+        if (cycmax > 2) HIPCHK(c, c->X32.ensure((size_t)b.fields));
         double *const xs[2] = {X, c->X64b.p};
         float *const P2[2] = {c->P32a.p, c->P32b.p};
         HIPCHK(c, hipMemsetAsync(c->ndone.p, 0, sizeof(int), s));
         HIPCHK(c, hipMemsetAsync(c->fin.p, 0xff, norb * sizeof(int), s));
-        HIPCHK(c, launch_fill_int(c->pz.p, norb, cyc, s));
+        HIPCHK(c, launch_fill_int(c->pz.p, norb, cycmax, s));
         // an orbital whose FP32 recursion has reached half the tolerance
         // pauses for the rest of its cycle (its residual pass decides)
         const double ftol2 = 0.25 * tol2;
@@ -1311,18 +1325,21 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         // launches depend on v only (iteration indices enter by parity)
         auto cycle = [&](hipStream_t s, int v) -> fsic_status {
             CGIter<float> a = a0;
-            const int ks = v == 1 ? cyc & 1 : 0;  // parity of the cycle's first iteration
+            const int L = v == 0 ? cyc0 : cyc;  // iterations of this cycle
+            // parity of the cycle's first iteration: cycle j >= 1 starts at
+            // iteration cyc0 + (j - 1) cyc
+            const int ks = v == 0 ? 0 : (v == 1 ? cyc0 & 1 : (cyc0 + cyc) & 1);
             double *const Xc = v == 0 ? nullptr : xs[v == 1 ? 1 : 0];
             double *const Xn = xs[v == 1 ? 0 : 1];
             const bool samp = prof && v != 0;
-            for (int i = 0; i < cyc; ++i) {
+            for (int i = 0; i < L; ++i) {
                 const int k = ks + i;
-                const bool last = i == cyc - 1;
+                const bool last = i == L - 1;
                 PcgOut po{nullptr, a.partRZ + (size_t)(k & 1) * b.tot9,
                           a.partRZ + (size_t)((k + 1) & 1) * b.tot9, 1, c->pz.p, i};
                 if (i > 0) {
-                    const int m = i - 1;  // x32 takes the steps of iterations 0 .. cyc - 3
-                    const int xmode = m <= cyc - 3 ? (m == 0 ? 1 : 2) : 0;
+                    const int m = i - 1;  // x32 takes the steps of iterations 0 .. L - 3
+                    const int xmode = m <= L - 3 ? (m == 0 ? 1 : 2) : 0;
                     a.P = P2[(k - 1) & 1];
                     {
                         PROF_BEGIN(1, last && samp ? 1 : 0, 0)
@@ -1347,9 +1364,9 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                     PROF_END()
                 }
             }
-            const int ka = ks + cyc - 2, kb = ks + cyc - 1;
-            ResStep rs{Xc, cyc > 2 ? c->X32.p : nullptr, P2[ka & 1], P2[kb & 1], ka, kb, Xn, c->R32.p,
-                       c->pz.p, cyc - 2, cyc - 1};
+            const int ka = ks + L - 2, kb = ks + L - 1;
+            ResStep rs{Xc, L > 2 ? c->X32.p : nullptr, P2[ka & 1], P2[kb & 1], ka, kb, Xn, c->R32.p,
+                       c->pz.p, L - 2, L - 1};
             {
                 PROF_BEGIN(3, samp ? 1 : 0, 0)
                 HIPCHK(c, launch_res_steps(c->radius, c->cf, a, rs, s));
@@ -1357,7 +1374,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             }
             HIPCHK(c, launch_ru_check(norb, c->d_orb.p, c->partRU.p, c->bb.p, tol2, 0, c->done.p,
                                       c->iters.p, c->rrfin.p, nullptr, c->ndone.p, c->fin.p,
-                                      Xn == xs[1] ? 1 : 0, c->pz.p, cyc, s));
+                                      Xn == xs[1] ? 1 : 0, c->pz.p, cycmax, s));
             return FSIC_OK;
         };
         auto issue = [&](int j) -> fsic_status {
@@ -1367,6 +1384,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             if (graphs) {
                 key.add((long long)v);
                 key.add((long long)cyc);
+                key.add((long long)cyc0);
                 key.add((long long)c->radius);
                 key.add((long long)c->cf.cpt);
                 key.add((long long)c->cf.depth);
@@ -1400,13 +1418,16 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         };
         // one cycle stays in flight while the host reads the counter of the
         // one before; the first pred_cycles - 1 cycles (the last solve's
-        // count) are not checked at all
+        // count) are not checked at all, and the cycle the last solve ended
+        // with is checked before another is issued (a solve like the last
+        // one then runs no cycle beyond its last)
         int used = 0, issued = 1;
         fsic_status ist = issue(0);
         if (ist) return ist;
         for (int j = 0;; ++j) {
             const bool more = j + 1 < ncyc;
-            if (more) {
+            const bool hold = j + 1 == c->pred_cycles;
+            if (more && !hold && issued == j + 1) {
                 if ((ist = issue(j + 1))) return ist;
                 issued = j + 2;
             }
@@ -1415,6 +1436,10 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
             if (c->h_nd[j & 1] >= norb || !more || status_error(c)) {
                 used = j + 1;
                 break;
+            }
+            if (issued == j + 1) {
+                if ((ist = issue(j + 1))) return ist;
+                issued = j + 2;
             }
         }
         c->pred_cycles = used;
