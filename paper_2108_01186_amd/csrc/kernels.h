@@ -106,6 +106,15 @@ hipError_t launch_pause_check(const CGIter<float> &a, int k, double ftol2, int *
 
 // p[i] = v for n ints (a fill kernel, usable inside a captured graph)
 hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s);
+// up to kIntFills integer arrays set to one value each, in one launch
+constexpr int kIntFills = 8;
+struct IntFills {
+    int *p[kIntFills];
+    int n[kIntFills];
+    int v[kIntFills];
+    int count;
+};
+hipError_t launch_fill_ints(const IntFills &f, hipStream_t s);
 
 // FP64 residual of x = x64 + x32 + alpha_a p_a + alpha_b p_b at the end of a
 // restart cycle (alpha_j = r_j.z_j / p_j.q_j from the partials of

@@ -264,7 +264,8 @@ struct fsic_ctx {
     DBuf<FodCell> d_cells;
     DBuf<ChanDesc> d_chan;
     DBuf<int> d_blkchan;
-    DBuf<double> partU, partX, Uo, Xo, Ech;
+    DBuf<double> partU, partX;
+    DBuf<double> eux;  // U_i, X_i of every orbital, then E_SIC of every channel (one copy out)
     DBuf<int> status;
     DBuf<double> bmat;
     int *h_done = nullptr;  // pinned
@@ -289,6 +290,10 @@ struct fsic_ctx {
     // pinned staging of the per-channel host checks (G, info, rho(a))
     double *h_chk = nullptr;
     size_t h_chk_cap = 0;
+    double *h_eux = nullptr;  // pinned host copy of eux
+    size_t h_eux_cap = 0;
+    double *h_grad = nullptr;  // pinned host copy of the channels' dE/da
+    size_t h_grad_cap = 0;
     std::map<const void *, UpCache> upcache;  // last upload per device table
     // profiling (FSIC_PROFILE): events around every CG launch
     std::vector<hipEvent_t> ev;
@@ -1142,10 +1147,14 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
                          // the mixed preconditioned solve starts x64 at 0 without storing it
                          (mixed && !use_pcg(c, b)) ? X : nullptr, c->part8.p, s));
     HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->part8.p, 0, c->bb.p, s));
-    HIPCHK(c, hipMemsetAsync(c->done.p, 0, norb * sizeof(int), s));
-    HIPCHK(c, hipMemsetAsync(c->iters.p, 0, norb * sizeof(int), s));
-    HIPCHK(c, hipMemsetAsync(c->rs_iter.p, 0xff, norb * sizeof(int), s));  // -1: no restart
-    HIPCHK(c, hipMemsetAsync(c->nact.p, 0, 6 * norb * sizeof(int), s));
+    {
+        // done = 0, iters = 0, rs_iter = -1 (no restart), activity counters 0
+        const IntFills f{{c->done.p, c->iters.p, c->rs_iter.p, c->nact.p},
+                         {norb, norb, norb, 6 * norb},
+                         {0, 0, -1, 0},
+                         4};
+        HIPCHK(c, launch_fill_ints(f, s));
+    }
     const double tol2 = tol * tol;
     const int chunk = 32;
     int k = 0;
@@ -1315,9 +1324,11 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         if (cycmax > 2) HIPCHK(c, c->X32.ensure((size_t)b.fields));
         double *const xs[2] = {X, c->X64b.p};
         float *const P2[2] = {c->P32a.p, c->P32b.p};
-        HIPCHK(c, hipMemsetAsync(c->ndone.p, 0, sizeof(int), s));
-        HIPCHK(c, hipMemsetAsync(c->fin.p, 0xff, norb * sizeof(int), s));
-        HIPCHK(c, launch_fill_int(c->pz.p, norb, cycmax, s));
+        {
+            // converged count 0, no final x buffer yet (-1), no pause
+            const IntFills f{{c->ndone.p, c->fin.p, c->pz.p}, {1, norb, norb}, {0, -1, cycmax}, 3};
+            HIPCHK(c, launch_fill_ints(f, s));
+        }
         // an orbital whose FP32 recursion has reached half the tolerance
         // pauses for the rest of its cycle (its residual pass decides)
         const double ftol2 = 0.25 * tol2;
@@ -1726,7 +1737,7 @@ void fsic_destroy(fsic_ctx *c) {
     c->done.release(); c->iters.release(); c->rs_iter.release(); c->nact.release(); c->d_orb.release(); c->d_items7.release();
     c->d_items8.release(); c->d_gcount.release(); c->small.release(); c->work.release();
     c->partG.release(); c->d_cells.release(); c->d_chan.release(); c->d_blkchan.release();
-    c->partU.release(); c->partX.release(); c->Uo.release(); c->Xo.release(); c->Ech.release();
+    c->partU.release(); c->partX.release(); c->eux.release();
     c->status.release(); c->bmat.release();
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
@@ -1737,6 +1748,8 @@ void fsic_destroy(fsic_ctx *c) {
     if (c->h_sd) hipHostFree(c->h_sd);
     if (c->h_stat) hipHostFree(c->h_stat);
     if (c->h_chk) hipHostFree(c->h_chk);
+    if (c->h_eux) hipHostFree(c->h_eux);
+    if (c->h_grad) hipHostFree(c->h_grad);
     for (hipEvent_t e : c->evc)
         if (e) hipEventDestroy(e);
     c->ndone.release(); c->fin.release(); c->pz.release();
@@ -1864,9 +1877,15 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     if ((ust = upload(c, c->d_blkchan, blkchan))) return ust;
     HIPCHK(c, c->partU.ensure((size_t)nblk_total * kMaxOrb));
     HIPCHK(c, c->partX.ensure((size_t)nblk_total * kMaxOrb));
-    HIPCHK(c, c->Uo.ensure(norb));
-    HIPCHK(c, c->Xo.ensure(norb));
-    HIPCHK(c, c->Ech.ensure(nchan));
+    const size_t neux = 2 * (size_t)norb + nchan;
+    HIPCHK(c, c->eux.ensure(neux));
+    if (c->h_eux_cap < neux) {
+        if (c->h_eux) hipHostFree(c->h_eux);
+        c->h_eux = nullptr;
+        c->h_eux_cap = 0;
+        HIPCHK(c, hipHostMalloc((void **)&c->h_eux, neux * sizeof(double)));
+        c->h_eux_cap = neux;
+    }
     HIPCHK(c, hipMemsetAsync(c->status.p, 0, sizeof(int), s));
     const double t1 = now_ms();
 
@@ -1944,12 +1963,12 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     // ---- (d) XC, (e) Slater average and energies ----
     HIPCHK(c, launch_sic_average(nchan, c->d_chan.p, nblk_total, c->d_blkchan.p, c->PHI.p, c->V.p,
                                  o.rho_floor, c->partU.p, c->partX.p, s));
-    HIPCHK(c, launch_sic_energy(nchan, c->d_chan.p, c->partU.p, c->partX.p, c->Uo.p, c->Xo.p, c->Ech.p, s));
-    std::vector<double> ech(nchan), uo(norb), xo(norb);
-    HIPCHK(c, hipMemcpyAsync(ech.data(), c->Ech.p, nchan * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(uo.data(), c->Uo.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(xo.data(), c->Xo.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
+    double *const dU = c->eux.p, *const dX = dU + norb, *const dE = dX + norb;
+    HIPCHK(c, launch_sic_energy(nchan, c->d_chan.p, c->partU.p, c->partX.p, dU, dX, dE, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_eux, c->eux.p, (2 * (size_t)norb + nchan) * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    const double *const uo = c->h_eux, *const xo = uo + norb, *const ech = xo + norb;
 
     // ---- host checks of the inputs (Sec. I.B: normalised, linearly
     // independent Fermi orbitals; Eq. 8: nonzero density at every FOD) ----
@@ -1984,8 +2003,8 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     if (fst) return fst;
     for (int k = 0; k < nsys; ++k) e_sic[k] = 0.0;
     for (int ci = 0; ci < nchan; ++ci) e_sic[chans[ci].sys] += ech[ci];
-    if (Uout) std::memcpy(Uout, uo.data(), norb * sizeof(double));
-    if (Xout) std::memcpy(Xout, xo.data(), norb * sizeof(double));
+    if (Uout) std::memcpy(Uout, uo, norb * sizeof(double));
+    if (Xout) std::memcpy(Xout, xo, norb * sizeof(double));
     const double t4 = now_ms();
     if (st) {
         std::memset(st, 0, sizeof(*st));
@@ -2380,7 +2399,17 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     std::vector<int> spin0(c->nsys, 0);
     for (const Chan &ch : c->chans)
         if (ch.spin == 0) spin0[ch.sys] = ch.N;
-    std::vector<std::vector<double>> host(c->chans.size());
+    // dE/da of every channel lands in one pinned host block (asynchronous
+    // copies, one wait at the end)
+    std::vector<size_t> goff(c->chans.size() + 1, 0);
+    for (size_t ci = 0; ci < c->chans.size(); ++ci) goff[ci + 1] = goff[ci] + 3 * (size_t)c->chans[ci].N;
+    if (c->h_grad_cap < goff.back()) {
+        if (c->h_grad) hipHostFree(c->h_grad);
+        c->h_grad = nullptr;
+        c->h_grad_cap = 0;
+        HIPCHK(c, hipHostMalloc((void **)&c->h_grad, std::max<size_t>(goff.back(), 1) * sizeof(double)));
+        c->h_grad_cap = goff.back();
+    }
     for (size_t ci = 0; ci < c->chans.size(); ++ci) {
         const Chan &ch = c->chans[ci];
         double *sm = c->small.p + ch.so;
@@ -2393,8 +2422,7 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
                                          sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
                                          sm + small_off(sRHOA), sm + small_off(sDU), c->work.p,
                                          sm + small_off(sDEDA), s));
-        host[ci].resize(3 * (size_t)ch.N);
-        HIPCHK(c, hipMemcpyAsync(host[ci].data(), sm + small_off(sDEDA), 3 * ch.N * sizeof(double),
+        HIPCHK(c, hipMemcpyAsync(c->h_grad + goff[ci], sm + small_off(sDEDA), 3 * ch.N * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
@@ -2406,7 +2434,7 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         const Chan &ch = c->chans[ci];
         const double ge = grad_e ? grad_e[ch.sys] : 1.0;
         double *dst = dE_da[ch.sys] + 3 * (ch.spin == 0 ? 0 : spin0[ch.sys]);
-        for (int q = 0; q < 3 * ch.N; ++q) dst[q] = ge * host[ci][q];
+        for (int q = 0; q < 3 * ch.N; ++q) dst[q] = ge * c->h_grad[goff[ci] + q];
     }
     const double t2 = now_ms();
     if (st) {

@@ -1,5 +1,7 @@
 // Preconditioned conjugate gradients (Sec. II.A; preconditioner in dst.hip):
 // the sweep p = z + beta p_old, q = -L p, and the update of x and r.
+#include <algorithm>
+
 #include "zmarch.h"
 
 namespace fsic {
@@ -182,6 +184,22 @@ hipError_t launch_pcg_rupdate(const CGIter<float> &a, int k, int xmode, const in
 hipError_t launch_pause_check(const CGIter<float> &a, int k, double ftol2, int *pz, int li, hipStream_t s) {
     if (a.norb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pause_check, dim3(a.norb), dim3(256), 0, s, a, k, ftol2, pz, li);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill_ints(IntFills f) {
+    const int e = blockIdx.y;
+    int *const p = f.p[e];
+    const int n = f.n[e], v = f.v[e];
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
+}
+
+hipError_t launch_fill_ints(const IntFills &f, hipStream_t s) {
+    if (f.count <= 0 || f.count > kIntFills) return f.count == 0 ? hipSuccess : hipErrorInvalidValue;
+    int nmax = 1;
+    for (int e = 0; e < f.count; ++e) nmax = std::max(nmax, f.n[e]);
+    const unsigned gx = (unsigned)std::min(64, (nmax + 255) / 256);
+    hipLaunchKernelGGL(k_fill_ints, dim3(gx, (unsigned)f.count), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 
