@@ -138,6 +138,10 @@ hipError_t launch_res_steps(int radius, const Coeffs &c, const CGIter<float> &a,
 // Final x of the mixed restart cycles: X[o] = Xb[o] for the orbitals whose
 // result is in the second buffer (fin[o] == 1, or fallback == 1 where
 // fin[o] < 0: not converged).
+// the statistics of a solve gathered for one transfer: stage holds 8 norb
+// ints (iters, nact[6 norb], done) and then 2 norb doubles (ptrue, bb)
+hipError_t launch_stage_stats(int norb, const int *iters, const int *nact, const int *done,
+                              const double *ptrue, const double *bb, double *stage, hipStream_t s);
 hipError_t launch_take_x(int nitems8, const Item *items8, const OrbDesc *orb, const int *fin, int fallback,
                          double *X, const double *Xb, hipStream_t s);
 

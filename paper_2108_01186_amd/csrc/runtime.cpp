@@ -276,9 +276,14 @@ struct fsic_ctx {
     int pred_cycles = 0;    // restart cycles the last mixed solve needed (host checks skipped before)
     // statistics of the last solve, copied to pinned memory and read after
     // the caller's synchronisation (finish_solve)
-    int *h_si = nullptr;     // [7 norb]: iters, then the six nact blocks
-    double *h_sd = nullptr;  // [2 norb]: final residual^2, ||b||^2
+    // pinned copy of the last solve's statistics (one transfer from
+    // d_stage): [8 norb ints: iters, the six nact blocks, done][2 norb
+    // doubles: final residual^2, ||b||^2]; h_si and h_sd point into it
+    double *h_stage = nullptr;
+    int *h_si = nullptr;
+    double *h_sd = nullptr;
     size_t h_s_cap = 0;
+    DBuf<double> d_stage;
     std::vector<ProfRec> recs;
     bool pend_prof = false, pend_aar = false, pend_pcg = false, pend_mixed = false;
     bool pend_dst_xy = false;
@@ -757,12 +762,11 @@ fsic_status prepare_batch(fsic_ctx *c, const Batch &b, int precision) {
         c->h_done_cap = norb;
     }
     if (c->h_s_cap < (size_t)norb) {
-        if (c->h_si) hipHostFree(c->h_si);
-        if (c->h_sd) hipHostFree(c->h_sd);
+        if (c->h_stage) hipHostFree(c->h_stage);
+        c->h_stage = nullptr;
         c->h_si = nullptr;
         c->h_sd = nullptr;
-        HIPCHK(c, hipHostMalloc((void **)&c->h_si, 7 * (size_t)std::max(norb, 1) * sizeof(int)));
-        HIPCHK(c, hipHostMalloc((void **)&c->h_sd, 2 * (size_t)std::max(norb, 1) * sizeof(double)));
+        HIPCHK(c, hipHostMalloc((void **)&c->h_stage, 6 * (size_t)std::max(norb, 1) * sizeof(double)));
         c->h_s_cap = norb;
     }
     if (!c->h_stat) {
@@ -1553,11 +1557,11 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
     }
     // statistics: copied now, read by finish_solve after the caller's sync
-    HIPCHK(c, hipMemcpyAsync(c->h_si, c->iters.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_si + norb, c->nact.p, 6 * norb * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_sd, c->ptrue.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_sd + norb, c->bb.p, norb * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_done, c->done.p, norb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, c->d_stage.ensure(6 * (size_t)std::max(norb, 1)));
+    HIPCHK(c, launch_stage_stats(norb, c->iters.p, c->nact.p, c->done.p, c->ptrue.p, c->bb.p, c->d_stage.p, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_stage, c->d_stage.p, 6 * (size_t)norb * sizeof(double), hipMemcpyDeviceToHost, s));
+    c->h_si = reinterpret_cast<int *>(c->h_stage);
+    c->h_sd = c->h_stage + 4 * (size_t)norb;
     c->pend_prof = prof;
     c->pend_aar = use_aar(c, b);
     c->pend_pcg = pcg;
@@ -1584,7 +1588,7 @@ fsic_status finish_solve(fsic_ctx *c, const Batch &b, SolveReport &rep) {
         rep.total_iters += itv;
         const double rr = bbh[o] > 0 ? std::sqrt(pt[o] / bbh[o]) : 0.0;
         rep.max_relres = std::max(rep.max_relres, rr);
-        if (c->h_done[o] != 1) rep.converged = false;
+        if (it[7 * norb + o] != 1) rep.converged = false;  // done
     }
     if (prof) {
         // algorithmic bytes of the sampled launches: each array of each
@@ -1733,7 +1737,7 @@ void fsic_destroy(fsic_ctx *c) {
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
     c->partH.release(); c->d_hcN.release(); c->d_hcG.release(); c->d_hcNx.release(); c->d_hcGx.release(); c->d_hchN.release(); c->d_hchG.release();
     c->bb.release(); c->rrfin.release();
-    c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release();
+    c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release(); c->d_stage.release();
     c->done.release(); c->iters.release(); c->rs_iter.release(); c->nact.release(); c->d_orb.release(); c->d_items7.release();
     c->d_items8.release(); c->d_gcount.release(); c->small.release(); c->work.release();
     c->partG.release(); c->d_cells.release(); c->d_chan.release(); c->d_blkchan.release();
@@ -1744,8 +1748,7 @@ void fsic_destroy(fsic_ctx *c) {
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     if (c->h_done) hipHostFree(c->h_done);
     if (c->h_nd) hipHostFree(c->h_nd);
-    if (c->h_si) hipHostFree(c->h_si);
-    if (c->h_sd) hipHostFree(c->h_sd);
+    if (c->h_stage) hipHostFree(c->h_stage);
     if (c->h_stat) hipHostFree(c->h_stat);
     if (c->h_chk) hipHostFree(c->h_chk);
     if (c->h_eux) hipHostFree(c->h_eux);

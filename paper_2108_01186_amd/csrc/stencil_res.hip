@@ -1,6 +1,8 @@
 // FP64 residual b + L x of a batch (the defect-correction check of the
 // mixed-precision solves and the final residual report), and the small
 // per-orbital kernels around it.
+#include <algorithm>
+
 #include "zmarch.h"
 
 namespace fsic {
@@ -103,6 +105,26 @@ hipError_t launch_ru_check(int norb, const OrbDesc *orb, const double *partRU, c
     if (norb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ru_check, dim3(norb), dim3(256), 0, s, orb, partRU, bb, tol2, k, done,
                        iters, rrfin, rs_iter, ndone, fin, xfin, pz, cyc);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_stage_stats(int norb, const int *iters, const int *nact,
+                                                     const int *done, const double *ptrue,
+                                                     const double *bb, double *stage) {
+    int *si = reinterpret_cast<int *>(stage);
+    double *sd = stage + 4 * (size_t)norb;
+    const int stride = gridDim.x * 256;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < 8 * norb; i += stride)
+        si[i] = i < norb ? iters[i] : (i < 7 * norb ? nact[i - norb] : done[i - 7 * norb]);
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < 2 * norb; i += stride)
+        sd[i] = i < norb ? ptrue[i] : bb[i - norb];
+}
+
+hipError_t launch_stage_stats(int norb, const int *iters, const int *nact, const int *done,
+                              const double *ptrue, const double *bb, double *stage, hipStream_t s) {
+    if (norb <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min(16, (8 * norb + 255) / 256);
+    hipLaunchKernelGGL(k_stage_stats, dim3(g), dim3(256), 0, s, norb, iters, nact, done, ptrue, bb, stage);
     return hipGetLastError();
 }
 
