@@ -13,6 +13,7 @@
 // form of the derivative of the inverse square root), S = T G T^T,
 // T_i = u_i / |u_i|, u_i,a = psi_a(a_i) (cubic interpolant).
 #include <algorithm>
+#include <cstdint>
 
 #include "kernels.h"
 #include "lsda.h"
@@ -21,104 +22,102 @@
 namespace fsic {
 
 
-// Small N (at most two 16-row tiles): B[i][a] = sum_m Gam_i(m) psi_a(m); wave w owns Gam tiles t1 = w, w + 4 and
-// every psi tile t2; block b sums the node range [b chunk, (b+1) chunk).
-// TT: column tiles held per wave (2 for N <= 32, else 8), so small N keeps
-// few accumulators and many waves per SIMD.
-template <int TT>
-__global__ __launch_bounds__(256) void k_adj_contract(int N, long long M, long long chunk,
-                                                      double dV, const double *PHI,
-                                                      const double *V, const double *W,
-                                                      const double *psi, double floor,
-                                                      double *partB) {
+// Small N (at most two 16-row tiles): B[i][a] = sum_m Gam_i(m) psi_a(m),
+// Gam formed on the fly; block b sums the node range [b chunk, (b+1) chunk)
+// (chunk a multiple of 64).  Every wave forms all the tiles over its own
+// 16-node groups; lane (row r = l % 16, q = l / 16) holds nodes g + 4q ..
+// g + 4q + 3 of row r (32 contiguous bytes: the four lanes of a row read one
+// 128-byte line), and k-step j of a group contracts node g + 4q + j (any
+// assignment of nodes to k-steps splits the sum, as long as both operands
+// use the same one).  The four waves' tiles are added in LDS at the end.
+__global__ __launch_bounds__(256) void k_adj_contract_small(int N, long long M, long long chunk, double dV,
+                                                            const double *PHI, const double *V,
+                                                            const double *W, const double *psi,
+                                                            double floor, int vec, double *partB) {
     const int Nt = (N + 15) >> 4;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row = lane & 15, kk = lane >> 4;
-    dbl4 acc[2][TT];
+    dbl4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int t = 0; t < TT; ++t) acc[a][t] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // row tiles: wave w takes w and w + 4; with at most two tiles (N <= 32)
-    // every wave takes all of them over a quarter of the nodes instead, and
-    // the four partial tiles are summed in LDS at the end (no wave idles)
-    const bool split = Nt <= 2;
-    auto tile_of = [&](int a) { return split ? a : w + 4 * a; };
+        for (int t = 0; t < 2; ++t) acc[a][t] = dbl4{0.0, 0.0, 0.0, 0.0};
     const long long m0 = (long long)blockIdx.x * chunk;
     const long long m1 = min(M, m0 + chunk);
-#pragma unroll 4
-    for (long long m = m0 + (split ? 4 * w : 0); m < m1; m += (split ? 16 : 4)) {
-        const long long mm = m + kk;
-        const bool ok = mm < m1;
-        double g[2];
+    // four consecutive values of row i from node mb (zero past m1)
+    auto load4 = [&](const double *X, int i, long long mb, double (&v)[4]) {
+        const double *src = X + (long long)i * M + mb;
+        if (vec && mb + 4 <= m1) {
+            const double2 lo = *reinterpret_cast<const double2 *>(src);
+            const double2 hi = *reinterpret_cast<const double2 *>(src + 2);
+            v[0] = lo.x; v[1] = lo.y; v[2] = hi.x; v[3] = hi.y;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = mb + j < m1 ? src[j] : 0.0;
+        }
+    };
+    for (long long g = m0 + 16 * w; g < m1; g += 64) {
+        const long long mb = g + 4 * kk;
+        double gam[2][4], f[2][4];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const int t1 = tile_of(a);
-            const int i = 16 * t1 + row;
-            double gv = 0.0;
-            if (t1 < Nt && i < N && ok) {
-                const long long gi = (long long)i * M + mm;
-                const double ph = PHI[gi];
-                const double r = ph * ph;
-                const double om = -(0.5 * (V[gi] + W[gi]) + vxc_pol(r, floor));
-                gv = 2.0 * dV * ph * om;
-            }
-            g[a] = gv;
-        }
-        double f[TT];
+            const int i = 16 * a + row;
 #pragma unroll
-        for (int t = 0; t < TT; ++t) {
+            for (int j = 0; j < 4; ++j) gam[a][j] = 0.0;
+            if (a < Nt && i < N && mb < m1) {
+                double ph[4], vv[4], ww[4];
+                load4(PHI, i, mb, ph);
+                load4(V, i, mb, vv);
+                load4(W, i, mb, ww);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double om = -(0.5 * (vv[j] + ww[j]) + vxc_pol(ph[j] * ph[j], floor));
+                    gam[a][j] = 2.0 * dV * ph[j] * om;  // zero past m1 (ph = 0 there)
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
             const int r = 16 * t + row;
-            f[t] = (t < Nt && r < N && ok) ? psi[(long long)r * M + mm] : 0.0;
+            if (t < Nt && r < N && mb < m1) load4(psi, r, mb, f[t]);
+            else
+#pragma unroll
+                for (int j = 0; j < 4; ++j) f[t][j] = 0.0;
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            if (tile_of(a) < Nt) {
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int t = 0; t < TT; ++t)
-                    if (t < Nt) acc[a][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[a], f[t], acc[a][t], 0, 0, 0);
-            }
-        }
+            for (int a = 0; a < 2; ++a)
+                if (a < Nt)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+                        if (t < Nt) acc[a][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gam[a][j], f[t][j], acc[a][t], 0, 0, 0);
     }
     const int NP = Nt * 16;
     double *out = partB + (size_t)blockIdx.x * NP * NP;
-    if (split) {
-        __shared__ double sacc[4][4][4][64];  // wave, tile (a, t), item, lane
+    __shared__ double sacc[4][4][4][64];  // wave, tile (a, t), item, lane
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
-                if (a < Nt && t < Nt)
+        for (int t = 0; t < 2; ++t)
+            if (a < Nt && t < Nt)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) sacc[w][2 * a + t][j][lane] = acc[a][t][j];
-        __syncthreads();
-        if (w != 0) return;
+                for (int j = 0; j < 4; ++j) sacc[w][2 * a + t][j][lane] = acc[a][t][j];
+    __syncthreads();
+    if (w != 0) return;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
-                if (a < Nt && t < Nt)
+        for (int t = 0; t < 2; ++t)
+            if (a < Nt && t < Nt)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[a][t][j] = (sacc[0][2 * a + t][j][lane] + sacc[1][2 * a + t][j][lane]) +
-                                       (sacc[2][2 * a + t][j][lane] + sacc[3][2 * a + t][j][lane]);
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int t1 = tile_of(a);
-        if (t1 >= Nt) continue;
-#pragma unroll
-        for (int t = 0; t < TT; ++t) {
-            if (t >= Nt) continue;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                // D layout of the f64 16x16x4 MFMA: lane l, item j -> row l/16 + 4 j, col l % 16
-                const int r = 16 * t1 + kk + 4 * j;
-                const int c = 16 * t + row;
-                out[(size_t)r * NP + c] = acc[a][t][j];
-            }
-        }
-    }
+                for (int j = 0; j < 4; ++j) {
+                    // D layout of the f64 16x16x4 MFMA: lane l, item j -> row l/16 + 4 j, col l % 16
+                    const int r = 16 * a + kk + 4 * j;
+                    const int c = 16 * t + row;
+                    out[(size_t)r * NP + c] = (sacc[0][2 * a + t][j][lane] + sacc[1][2 * a + t][j][lane]) +
+                                              (sacc[2][2 * a + t][j][lane] + sacc[3][2 * a + t][j][lane]);
+                }
 }
 
 // Gam_i(m) = 2 dV phi_i omega_i, omega_i = -((v_i + w_i) / 2 + vxc(phi_i^2)),
@@ -240,9 +239,15 @@ hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *
     const int nblk = grid_blocks(N, M, cap);
     long long chunk = (M + nblk - 1) / nblk;
     if (N <= 32) {  // Gam built on the fly
-        chunk = (chunk + 3) & ~3LL;
-        hipLaunchKernelGGL(k_adj_contract<2>, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
-                           floor, partB);
+        chunk = (chunk + 63) & ~63LL;
+        // 16-byte loads where every row start is 16-byte aligned
+        const int vec = ((M & 1) == 0 && ((reinterpret_cast<uintptr_t>(PHI) | reinterpret_cast<uintptr_t>(V) |
+                                           reinterpret_cast<uintptr_t>(W) | reinterpret_cast<uintptr_t>(psi)) &
+                                          15) == 0)
+                            ? 1
+                            : 0;
+        hipLaunchKernelGGL(k_adj_contract_small, dim3(nblk), dim3(256), 0, s, N, M, chunk, dV, PHI, V, W, psi,
+                           floor, vec, partB);
         hipLaunchKernelGGL(k_adj_contract_final, dim3(N * N), dim3(256), 0, s, N, nblk, partB, Bm);
         return hipGetLastError();
     }

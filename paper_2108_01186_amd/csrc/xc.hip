@@ -48,17 +48,36 @@ __global__ __launch_bounds__(256) void k_sic_average(const ChanDesc *chans, cons
 #pragma unroll
     for (int e = 0; e < kSicTile / 256; ++e) num[e] = den[e] = 0.0;
     const int w = threadIdx.x >> 6;
-    for (int i = 0; i < ch.N; ++i) {
+    // the next orbital's phi and v are loaded while this one's are used
+    constexpr int E = kSicTile / 256;
+    double pn[E], vn[E];
+    auto load = [&](int i) {
         const double *ph = PHI + ch.off + (long long)i * ch.M;
         const double *vh = V + ch.off + (long long)i * ch.M;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long m = base + e * 256 + threadIdx.x;
+            pn[e] = m < ch.M ? ph[m] : 0.0;
+            vn[e] = m < ch.M ? vh[m] : 0.0;
+        }
+    };
+    if (ch.N > 0) load(0);
+    for (int i = 0; i < ch.N; ++i) {
+        double pc[E], vc_[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            pc[e] = pn[e];
+            vc_[e] = vn[e];
+        }
+        if (i + 1 < ch.N) load(i + 1);
         double u = 0.0, x = 0.0;
 #pragma unroll
-        for (int e = 0; e < kSicTile / 256; ++e) {
+        for (int e = 0; e < E; ++e) {
             const long long m = base + e * 256 + threadIdx.x;
             if (m < ch.M) {
-                const double p = ph[m];
+                const double p = pc[e];
                 const double r = p * p;
-                const double v = vh[m];
+                const double v = vc_[e];
                 double ex, ec, vx, vc;
                 lsda_pol(r, floor, ex, ec, vx, vc);
                 u += r * v;
