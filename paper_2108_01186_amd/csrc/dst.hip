@@ -24,6 +24,9 @@
 // bf16 hi + lo (see below).
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
+#include <set>
+#include <tuple>
 
 #include "kernels.h"
 
@@ -824,6 +827,15 @@ hipError_t launch_dst_pcg(const DstItems &di, const OrbDesc *orb, const int *don
 // raise the dynamic-LDS limit of the fast transform kernels (once per batch,
 // outside any stream capture)
 hipError_t dst_setup(int np, int variant, int npxy, bool two) {
+    // the limits are set once per (device, shape): a later batch of the same
+    // shape finds them in place
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    const auto key = std::make_tuple(dev, np, variant, npxy, two);
+    static std::mutex mu;
+    static std::set<std::tuple<int, int, int, int, bool>> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count(key)) return hipSuccess;
     if (npxy > 0) {
         const size_t lxy = dst_xy_lds(npxy, two);
         set_lds_limit(k_dst_xy<true, float, float, false>, lxy);
@@ -863,7 +875,9 @@ hipError_t dst_setup(int np, int variant, int npxy, bool two) {
     else if (variant == 2) FSIC_DST_LIMITS(64, true, 160);
     else if (variant == 3) FSIC_DST_LIMITS(64, false, 192);
 #undef FSIC_DST_LIMITS
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) done.insert(key);
+    return e;
 }
 
 template hipError_t launch_dst_precond<float>(const DstItems &, const OrbDesc *, const int *,
