@@ -10,6 +10,7 @@
 // Everything N x N (N <= 128) runs in one workgroup: S = T G T^T, a parallel
 // cyclic Jacobi eigen-decomposition (round-robin pairing), S^{-1/2}, Q.
 #include <algorithm>
+#include <cstdint>
 
 #include "kernels.h"
 #include "tsgemm.h"
@@ -177,88 +178,78 @@ hipError_t launch_interp(int K, int N, int nx, int ny, int nz, double h, const d
 // (tsgemm.h) for more than 32 orbitals, below for at most 32
 // ---------------------------------------------------------------------------
 
-// Small N (at most two 16-row tiles).  Block b accumulates the node range [b*chunk, (b+1)*chunk); wave w owns the
-// upper-triangle tile pairs p = w, w+4, ...; partG[b] holds the block's sums.
-// FT: row tiles held per lane (2 for N <= 32, else 8), so small N keeps few
-// registers and many waves per SIMD.
-template <int FT>
-__global__ __launch_bounds__(256) void k_gram(int N, long long M, long long chunk,
-                                              const double *psi, double *partG) {
+// Small N (at most two 16-row tiles): the tile pairs t1 <= t2 of
+// psi psi^T over the node range [b chunk, (b+1) chunk) of block b (chunk a
+// multiple of 64).  Every wave forms all pairs over its own 16-node groups;
+// lane (row r = l % 16, q = l / 16) holds nodes g + 4q .. g + 4q + 3 of row r
+// (32 contiguous bytes: the four lanes of a row read one 128-byte line) and
+// k-step j contracts node g + 4q + j; the four waves' tiles are added in
+// LDS.  partG[b] holds the block's sums.
+__global__ __launch_bounds__(256) void k_gram_small(int N, long long M, long long chunk, const double *psi,
+                                                    int vec, double *partG) {
     const int Nt = (N + 15) >> 4;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row = lane & 15, kk = lane >> 4;
-    constexpr int kMaxPairPerWave = FT == 2 ? 3 : 9;  // Nt <= 8: 36 pairs over 4 waves
-    dbl4 acc[kMaxPairPerWave];
-    int pt1[kMaxPairPerWave], pt2[kMaxPairPerWave];
-    int np = 0;
-    // pairs (t1 <= t2) enumerated row by row; wave w takes indices w, w+4, ...
-    // With at most three pairs (N <= 32) every wave takes all of them over a
-    // quarter of the nodes instead, and the four partial tiles are summed
-    // in LDS at the end (no wave idles).
-    const bool split = Nt * (Nt + 1) / 2 <= 3;
-    for (int t1 = 0, idx = 0; t1 < Nt; ++t1)
-        for (int t2 = t1; t2 < Nt; ++t2, ++idx)
-            if ((split || idx % 4 == w) && np < kMaxPairPerWave) {
-                pt1[np] = t1;
-                pt2[np] = t2;
-                ++np;
-            }
+    const int np = Nt == 1 ? 1 : 3;  // pairs (0,0) [, (0,1), (1,1)]
+    dbl4 acc[3];
 #pragma unroll
-    for (int q = 0; q < kMaxPairPerWave; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < 3; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
     const long long m0 = (long long)blockIdx.x * chunk;
     const long long m1 = min(M, m0 + chunk);
-    for (long long m = m0 + (split ? 4 * w : 0); m < m1; m += (split ? 16 : 4)) {
-        double frag[FT];
-        const long long mm = m + kk;
+    for (long long g = m0 + 16 * w; g < m1; g += 64) {
+        const long long mb = g + 4 * kk;
+        double f[2][4];
 #pragma unroll
-        for (int t = 0; t < FT; ++t) {
+        for (int t = 0; t < 2; ++t) {
             const int r = 16 * t + row;
-            frag[t] = (t < Nt && r < N && mm < m1) ? psi[(long long)r * M + mm] : 0.0;
+            const double *src = psi + (long long)r * M + mb;
+            if (t < Nt && r < N && mb < m1) {
+                if (vec && mb + 4 <= m1) {
+                    const double2 lo = *reinterpret_cast<const double2 *>(src);
+                    const double2 hi = *reinterpret_cast<const double2 *>(src + 2);
+                    f[t][0] = lo.x; f[t][1] = lo.y; f[t][2] = hi.x; f[t][3] = hi.y;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) f[t][j] = mb + j < m1 ? src[j] : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) f[t][j] = 0.0;
+            }
         }
 #pragma unroll
-        for (int q = 0; q < kMaxPairPerWave; ++q) {
-            if (q < np) {
-                double fa = 0.0, fb = 0.0;
-#pragma unroll
-                for (int t = 0; t < FT; ++t) {
-                    if (t == pt1[q]) fa = frag[t];
-                    if (t == pt2[q]) fb = frag[t];
-                }
-                acc[q] = mfma16x16x4(fa, fb, acc[q]);
+        for (int j = 0; j < 4; ++j) {
+            acc[0] = mfma16x16x4(f[0][j], f[0][j], acc[0]);
+            if (np == 3) {
+                acc[1] = mfma16x16x4(f[0][j], f[1][j], acc[1]);
+                acc[2] = mfma16x16x4(f[1][j], f[1][j], acc[2]);
             }
         }
     }
     const int NP = Nt * 16;
     double *out = partG + (size_t)blockIdx.x * NP * NP;
-    if (split) {
-        __shared__ double sacc[4][3][4][64];
+    __shared__ double sacc[4][3][4][64];
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
-            if (q < np)
+    for (int q = 0; q < 3; ++q)
+        if (q < np)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) sacc[w][q][j][lane] = acc[q][j];
-        __syncthreads();
-        if (w != 0) return;
+            for (int j = 0; j < 4; ++j) sacc[w][q][j][lane] = acc[q][j];
+    __syncthreads();
+    if (w != 0) return;
+    const int pt1[3] = {0, 0, 1}, pt2[3] = {0, 1, 1};
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
-            if (q < np)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[q][j] = (sacc[0][q][j][lane] + sacc[1][q][j][lane]) +
-                                (sacc[2][q][j][lane] + sacc[3][q][j][lane]);
-    }
-#pragma unroll
-    for (int q = 0; q < kMaxPairPerWave; ++q) {
-        if (q < np) {
+    for (int q = 0; q < 3; ++q)
+        if (q < np)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
+                // D lane l, item j: row l / 16 + 4 j, column l % 16
                 const int r = 16 * pt1[q] + kk + 4 * j;
                 const int c = 16 * pt2[q] + row;
-                out[(size_t)r * NP + c] = acc[q][j];
+                out[(size_t)r * NP + c] = (sacc[0][q][j][lane] + sacc[1][q][j][lane]) +
+                                          (sacc[2][q][j][lane] + sacc[3][q][j][lane]);
             }
-        }
-    }
 }
+
 
 // G[i][j] = dV * sum over the blocks' partial tiles (the upper block triangle
 // holds the tile pairs); one 256-thread block per element, fixed order
@@ -292,8 +283,10 @@ hipError_t launch_gram(int N, long long M, double dV, const double *psi, double 
     const int nblk = grid_blocks(N, M, cap);
     long long chunk = (M + nblk - 1) / nblk;
     if (N <= 32) {
-        chunk = (chunk + 3) & ~3LL;
-        hipLaunchKernelGGL(k_gram<2>, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, partG);
+        chunk = (chunk + 63) & ~63LL;
+        // 16-byte loads where every row start is 16-byte aligned
+        const int vec = ((M & 1) == 0 && (reinterpret_cast<uintptr_t>(psi) & 15) == 0) ? 1 : 0;
+        hipLaunchKernelGGL(k_gram_small, dim3(nblk), dim3(256), 0, s, N, M, chunk, psi, vec, partG);
     } else {
         chunk = (chunk + kTK - 1) / kTK * kTK;
         const size_t lds = tsg_lds_bytes(N, 1);
@@ -521,6 +514,40 @@ __global__ __launch_bounds__(256) void k_orb_gemm(int N, long long M, const doub
     const long long nstrip = (M + 15) >> 4;
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const long long nwave = ((long long)gridDim.x * blockDim.x) >> 6;
+    // N <= 16: the 16-row A fragments stay in registers and each pass takes
+    // two strips, whose psi loads are all issued before the products
+    if (Nt == 1) {
+        double af[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int a = 4 * q + kk;
+            af[q] = (row < N && a < N) ? A[row * N + a] : 0.0;
+        }
+        for (long long st = wave; st < nstrip; st += 2 * nwave) {
+            const long long ms[2] = {st * 16 + row, (st + nwave) * 16 + row};
+            double b[2][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int a = 4 * q + kk;
+                    b[u][q] = (a < N && ms[u] < M) ? psi[(long long)a * M + ms[u]] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc = mfma16x16x4(af[q], b[u][q], acc);
+                if (ms[u] < M)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = kk + 4 * j;
+                        if (i < N) out[(long long)i * M + ms[u]] = acc[j];
+                    }
+            }
+        }
+        return;
+    }
     for (long long st = wave; st < nstrip; st += nwave) {
         const long long m = st * 16 + row;
         dbl4 acc[8];
