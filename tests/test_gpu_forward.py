@@ -176,3 +176,33 @@ def test_graph_replays_match_eager(torch_cuda, F, mol40_dev, precision, fused, m
     assert captures[1] == captures[0] and captures[2] == captures[0], captures
     eager.close()
     graph.close()
+
+
+def test_cycle_prediction_does_not_change_results(torch_cuda, F, mol40_dev):
+    """Mixed restart cycles: the host issues as many cycles unread as the
+    previous solve needed and reads the last one of them before issuing
+    another.  A prediction that is too short (a loose solve first) or too
+    long (a tight solve first) changes only when the host waits, not what
+    the device computes: energy, V_SIC and the FOD gradient equal those of
+    a fresh context bit for bit."""
+    _say("cycle prediction mol40")
+    d = F.system_dict(mol40_dev)
+    fl = F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE
+
+    def run(ctx):
+        e = ctx.forward([d])[0][0]
+        g = ctx.backward([[5]])[0][0]
+        return e, d["vsic"][0].cpu().numpy().copy(), np.asarray(g).copy()
+
+    for first, second in ((1e-6, 1e-11), (1e-11, 1e-6)):
+        ctx = F.Context(precision="mixed", tol=first, flags=fl)
+        run(ctx)
+        ctx.set_opts(tol=second)
+        got = run(ctx)
+        ctx.close()
+        fresh = F.Context(precision="mixed", tol=second, flags=fl)
+        ref = run(fresh)
+        fresh.close()
+        assert got[0] == ref[0], (first, second, got[0], ref[0])
+        assert np.array_equal(got[1], ref[1]), (first, second)
+        assert np.array_equal(got[2], ref[2]), (first, second)
