@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kFT, OCC2 ? 4 : 2) void k_dst_fast(const Item *unit
     constexpr int NCT = PC / 16;
     constexpr int RS = (kFT / 64) / NCT;
     const int ct = w % NCT, r0 = w / NCT;
-    constexpr int MT = OCC2 ? 4 : NPM / 16 / RS;  // row tiles per wave: np / 16 / RS <= MT
+    constexpr int MT = OCC2 ? 3 : NPM / 16 / RS;  // row tiles per wave: np / 16 / RS <= MT (OCC2: np <= 96)
     const int lr = lane & 15, lq = lane >> 4;
     flt4 acc[MT];
     auto gemm = [&](int np) {
@@ -372,14 +372,17 @@ __global__ __launch_bounds__(kFT, OCC2 ? 4 : 2) void k_dst_fast(const Item *unit
     };
 
     if constexpr (OCC2) {
-        // one register buffer; the other resident block overlaps its memory
-        // traffic with this one's products (a prefetch into this buffer
-        // during the products measured no faster and spills)
+        // one register buffer: once a unit's values are in LDS the next
+        // unit's loads go into it, in flight during this unit's products
         float v[NV];
-        for (int q = next_active(u0); q < u1; q = next_active(q + 1)) {
-            OrbDesc o = orb[units[q].orb];
-            load(v, o, units[q].tile);
-            unit(v, q, o, u1);
+        int q = next_active(u0);
+        if (q >= u1) return;
+        OrbDesc o = orb[units[q].orb];
+        load(v, o, units[q].tile);
+        while (q < u1) {
+            const int qn = next_active(q + 1);
+            unit(v, q, o, qn);  // o becomes unit qn's descriptor
+            q = qn;
         }
         return;
     }
