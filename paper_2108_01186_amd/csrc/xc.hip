@@ -108,31 +108,35 @@ __global__ __launch_bounds__(256) void k_sic_average(const ChanDesc *chans, cons
     }
 }
 
+// U_i and X_i: one block per (channel, orbital) sums the partials of the
+// channel's blocks in a fixed order
 __global__ __launch_bounds__(256) void k_sic_energy(const ChanDesc *chans, const double *partU,
-                                                    const double *partX, double *U, double *X,
-                                                    double *Echan) {
+                                                    const double *partX, double *U, double *X) {
     __shared__ double sred[4];
-    const ChanDesc ch = chans[blockIdx.x];
+    const ChanDesc ch = chans[blockIdx.y];
+    const int i = blockIdx.x;
+    if (i >= ch.N) return;  // uniform
     const double dV = ch.h * ch.h * ch.h;
-    double e = 0.0;
-    // per orbital: the block's threads sum the partials of the channel's
-    // blocks in a fixed order, then one fixed-order block reduction
-    for (int i = 0; i < ch.N; ++i) {
-        double su = 0.0, sx = 0.0;
-        for (int t = threadIdx.x; t < ch.nblk; t += 256) {
-            su += partU[(size_t)(ch.blk_base + t) * kMaxOrb + i];
-            sx += partX[(size_t)(ch.blk_base + t) * kMaxOrb + i];
-        }
-        su = block_sum256(su, sred);
-        sx = block_sum256(sx, sred);
-        const double ui = 0.5 * dV * su, xi = dV * sx;
-        if (threadIdx.x == 0) {
-            U[ch.first_orb + i] = ui;
-            X[ch.first_orb + i] = xi;
-        }
-        e -= ui + xi;
+    double su = 0.0, sx = 0.0;
+    for (int t = threadIdx.x; t < ch.nblk; t += 256) {
+        su += partU[(size_t)(ch.blk_base + t) * kMaxOrb + i];
+        sx += partX[(size_t)(ch.blk_base + t) * kMaxOrb + i];
     }
-    if (threadIdx.x == 0) Echan[blockIdx.x] = e;
+    su = block_sum256(su, sred);
+    sx = block_sum256(sx, sred);
+    if (threadIdx.x == 0) {
+        U[ch.first_orb + i] = 0.5 * dV * su;
+        X[ch.first_orb + i] = dV * sx;
+    }
+}
+
+// E_SIC of each channel: -sum_i (U_i + X_i) in orbital order
+__global__ void k_sic_echan(const ChanDesc *chans, const double *U, const double *X, double *Echan) {
+    const ChanDesc ch = chans[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    double e = 0.0;
+    for (int i = 0; i < ch.N; ++i) e -= U[ch.first_orb + i] + X[ch.first_orb + i];
+    Echan[blockIdx.x] = e;
 }
 
 hipError_t launch_sic_average(int nchan, const ChanDesc *chan, int nblk_total,
@@ -149,7 +153,8 @@ hipError_t launch_sic_energy(int nchan, const ChanDesc *chan, const double *part
                              const double *partX, double *U, double *X, double *Echan,
                              hipStream_t s) {
     if (nchan <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sic_energy, dim3(nchan), dim3(256), 0, s, chan, partU, partX, U, X, Echan);
+    hipLaunchKernelGGL(k_sic_energy, dim3(kMaxOrb, nchan), dim3(256), 0, s, chan, partU, partX, U, X);
+    hipLaunchKernelGGL(k_sic_echan, dim3(nchan), dim3(64), 0, s, chan, U, X, Echan);
     return hipGetLastError();
 }
 
