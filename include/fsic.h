@@ -113,6 +113,14 @@ enum { FSIC_CG = 0, FSIC_PCG = 1, FSIC_AAR = 2 };
                                     eps_kl = <phi_l|V_k|phi_k>, V_k = -(v_k + vxc_k) (Eq. 5); it treats
                                     the Poisson map as symmetric, so no adjoint Poisson solves run
                                     (the boundary part of the map is the only difference) */
+#define FSIC_DIRECT_BC     256u  /* forward pass with FSIC_KEEP_TAPE: solve each orbital's problem with
+                                    its multipole boundary values directly.  Without it the forward
+                                    pass solves the zero-boundary problems K w_i = 4 pi rho_i (the
+                                    adjoint fields the FOD gradient needs, so fsic_backward runs no
+                                    Poisson solve) and forms v_i = w_i + sum_lm Q_lm,i U_lm from the
+                                    moments and a per-grid basis U of unit-moment boundary solutions
+                                    (the map is linear in the boundary values); the basis is solved
+                                    once per grid and context in FP64 to relative residual 1e-13 */
 
 typedef struct {
     int32_t n[3];       /* nodes per axis, 8..4096, fewer than 2^29 nodes in all */
@@ -204,6 +212,16 @@ typedef struct {
      * nothing was open, or under FSIC_AUTOTUNE=0). */
     int32_t precond_layout;
     double  precond_tune_ms;
+    /* Poisson problems whose solutions this call produced: the CG solves
+     * (nsolves) plus, on a forward pass that formed the multipole-boundary
+     * potentials from the zero-boundary (adjoint) solutions and the boundary
+     * basis (FSIC_KEEP_TAPE without FSIC_DIRECT_BC or FSIC_EQ9_FORCES), those
+     * potentials too; fsic_backward then reports 0 for both.  basis_solves,
+     * basis_ms: unit-moment boundary solutions solved in this call for grids
+     * new to the context, and the time they took */
+    int32_t npoisson;
+    int32_t basis_solves;
+    double  basis_ms;
 } fsic_stats;
 
 /* Fills *o with the defaults: fd_order 12, lmax 6, FSIC_PCG, FP64, tol 1e-10,

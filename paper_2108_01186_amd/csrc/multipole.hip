@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_rhs(int P, Coeffs cf, const OrbDesc *or
 #pragma unroll
         for (int u = 0; u < kRhsU; ++u) {
             const long long i = base + (e0 + u) * 256 + threadIdx.x;
-            sv[u] = i < M ? src[od.off + i] : 0.0;
+            sv[u] = (src && i < M) ? src[od.off + i] : 0.0;  // no source: boundary values only
         }
 #pragma unroll
         for (int u = 0; u < kRhsU; ++u) {
@@ -602,6 +602,49 @@ hipError_t launch_bterm(int radius, const Coeffs &c, int norb, const OrbDesc *or
     if (radius < 1 || radius > kMaxRadius) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bterm, dim3((unsigned)((max_cols + 255) / 256), (unsigned)norb), dim3(256), 0, s, radius,
                        c, orb, G);
+    return hipGetLastError();
+}
+
+// v_o = w_o + sum_q Q[first + o][q] U_q over one channel's grid: the
+// multipole-boundary solution from the zero-boundary one and the basis U of
+// unit-moment boundary solutions (the Poisson map is linear in the boundary
+// values, which are linear in the moments).  Block (node tile, 16-orbital
+// group): each thread one node, the group's moment rows in LDS.
+__global__ __launch_bounds__(256) void k_bc_combine(int N, long long M, int nlm, const double *Q, int first,
+                                                    const double *__restrict__ U, const double *__restrict__ W,
+                                                    double *__restrict__ V) {
+    __shared__ double Qs[16 * kMaxLM];
+    const int o0 = 16 * blockIdx.y;
+    const int no = min(16, N - o0);
+    for (int e = threadIdx.x; e < 16 * nlm; e += 256) {
+        const int j = e / nlm, q = e - j * nlm;
+        Qs[e] = j < no ? Q[(size_t)(first + o0 + j) * nlm + q] : 0.0;
+    }
+    __syncthreads();
+    const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (m >= M) return;
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (int q = 0; q < nlm; ++q) {
+        const double u = U[(size_t)q * M + m];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] += Qs[j * nlm + q] * u;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (j < no) {
+            const size_t a = (size_t)(o0 + j) * M + m;
+            V[a] = W[a] + acc[j];
+        }
+}
+
+hipError_t launch_bc_combine(int N, long long M, int lmax, const double *Q, int first, const double *U,
+                             const double *W, double *V, hipStream_t s) {
+    if (N < 1 || M < 1 || lmax < 0 || lmax > kMaxL) return hipErrorInvalidValue;
+    const int nlm = (lmax + 1) * (lmax + 1);
+    const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + 15) / 16));
+    hipLaunchKernelGGL(k_bc_combine, grid, dim3(256), 0, s, N, M, nlm, Q, first, U, W, V);
     return hipGetLastError();
 }
 

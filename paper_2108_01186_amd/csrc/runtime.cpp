@@ -314,6 +314,15 @@ struct fsic_ctx {
     Batch batch;
     int nsys = 0;
     bool tape = false;
+    // W holds the zero-boundary solutions of the last forward pass (the
+    // adjoint fields), until a backward pass overwrites it
+    bool w_ready = false;
+    // unit-moment boundary solutions per grid (n, h bits, lmax, radius):
+    // (lmax + 1)^2 fields of the grid's size, solved once
+    std::map<std::array<long long, 6>, DBuf<double>> bbasis;
+    DBuf<double> qident;  // identity moments of the basis solves
+    int basis_solves = 0;
+    double basis_ms = 0.0;
     int radius = 6;
     Coeffs cf{};
     // stencil shape of the last batch and the time its tuning took (0: cached)
@@ -364,7 +373,10 @@ fsic_status validate_opts(const fsic_opts *o, std::string &why) {
     if (!(o->rho_floor >= 0.0) || !std::isfinite(o->rho_floor)) { why = "rho_floor must be finite and >= 0"; return FSIC_EINVAL; }
     if (!(o->s_eig_floor > 0.0) || !std::isfinite(o->s_eig_floor)) { why = "s_eig_floor must be finite and > 0"; return FSIC_EINVAL; }
     if (o->flags & ~(FSIC_WANT_VSIC | FSIC_KEEP_TAPE | FSIC_ALLOW_NONORTHO | FSIC_PROFILE | FSIC_FP32_ORBITALS |
-                     FSIC_GRAPHS | FSIC_PAPER_GRADIENT | FSIC_EQ9_FORCES)) { why = "unknown flag bits"; return FSIC_EINVAL; }
+                     FSIC_GRAPHS | FSIC_PAPER_GRADIENT | FSIC_EQ9_FORCES | FSIC_DIRECT_BC)) {
+        why = "unknown flag bits";
+        return FSIC_EINVAL;
+    }
     return FSIC_OK;
 }
 
@@ -1129,18 +1141,21 @@ fsic_status run_captured(fsic_ctx *c, bool graphs, const GraphKey &key, Body &bo
 
 fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int square, double scale,
                         bool with_bc, double *X, int precision, double tol, int max_iter,
-                        SolveReport &rep) {
+                        SolveReport &rep, const double *qlm_in = nullptr) {
     hipStream_t s = c->stream;
     const int norb = (int)b.orb.size();
     const int nlm = (c->opts.lmax + 1) * (c->opts.lmax + 1);
     const int nit7 = (int)b.items7.size(), nit8 = (int)b.items8.size();
     const bool mixed = precision == FSIC_MIXED;
     if (with_bc) {
-        HIPCHK(c, launch_harm_contract(0, c->opts.lmax, c->ht, c->cf, c->radius, c->d_orb.p, c->d_gcount.p,
-                                       c->d_hcN.p, (int)b.hcN.size(), c->d_hchN.p, (int)b.hchN.size(),
-                                       b.max_group, src, square, c->partH.p, c->Qlm.p, s));
+        // boundary values from the moments of the source, or (qlm_in) from
+        // given moments (the unit-moment basis solves, src null)
+        if (!qlm_in)
+            HIPCHK(c, launch_harm_contract(0, c->opts.lmax, c->ht, c->cf, c->radius, c->d_orb.p, c->d_gcount.p,
+                                           c->d_hcN.p, (int)b.hcN.size(), c->d_hchN.p, (int)b.hchN.size(),
+                                           b.max_group, src, square, c->partH.p, c->Qlm.p, s));
         HIPCHK(c, launch_harm_expand(0, c->opts.lmax, c->ht, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcGx.p,
-                                     (int)b.hcGx.size(), c->Qlm.p, c->Gh.p, s));
+                                     (int)b.hcGx.size(), qlm_in ? qlm_in : c->Qlm.p, c->Gh.p, s));
         HIPCHK(c, launch_bterm(c->radius, c->cf, norb, c->d_orb.p, b.max_ghost / c->radius, c->Gh.p, s));
     }
     (void)nlm;
@@ -1728,6 +1743,9 @@ fsic_status fsic_set_opts(fsic_ctx *c, const fsic_opts *opts) {
 void fsic_destroy(fsic_ctx *c) {
     if (!c) return;
     hipStreamSynchronize(c->stream);
+    for (auto &kv : c->bbasis) kv.second.release();
+    c->bbasis.clear();
+    c->qident.release();
     c->PHI.release(); c->V.release(); c->W.release(); c->B.release(); c->R.release();
     c->P0.release(); c->P1.release(); c->Q.release(); c->X64b.release();
     c->R32.release(); c->P32a.release(); c->P32b.release(); c->Q32.release(); c->X32.release();
@@ -1757,6 +1775,56 @@ void fsic_destroy(fsic_ctx *c) {
         if (e) hipEventDestroy(e);
     c->ndone.release(); c->fin.release(); c->pz.release();
     delete c;
+}
+
+// The unit-moment boundary solutions U_q (q < (lmax + 1)^2) of a grid:
+// K U_q = the boundary term of the ghost values of moment vector e_q (no
+// source), solved in FP64 to relative residual 1e-13 with the batch's stencil
+// shape and preconditioner layout, once per grid for the context.  Since the
+// map from moments to ghost values to right-hand side is linear, the
+// multipole-boundary solution of any source is its zero-boundary solution
+// plus sum_q Q_q U_q.  Uses the context's solve buffers (the caller prepares
+// its own batch afterwards).
+fsic_status boundary_basis(fsic_ctx *c, const Chan &ch, const Shape &sh, const DstTune &dt, const double **U) {
+    const int lmax = c->opts.lmax, nlm = (lmax + 1) * (lmax + 1);
+    long long hb = 0;
+    std::memcpy(&hb, &ch.h, sizeof(hb));
+    const std::array<long long, 6> key{ch.n[0], ch.n[1], ch.n[2], hb, lmax, c->radius};
+    auto f = c->bbasis.find(key);
+    if (f != c->bbasis.end()) {
+        *U = f->second.p;
+        return FSIC_OK;
+    }
+    const double t0 = now_ms();
+    Group g{};
+    for (int d = 0; d < 3; ++d) { g.n[d] = ch.n[d]; g.origin[d] = ch.origin[d]; }
+    g.h = ch.h; g.count = nlm; g.off = 0; g.chan = 0;
+    Batch bb;
+    build_batch({g}, c->radius, sh, bb, dt);
+    fsic_status st = prepare_batch(c, bb, FSIC_FP64);
+    if (st) return st;
+    std::vector<double> ident((size_t)nlm * nlm, 0.0);
+    for (int q = 0; q < nlm; ++q) ident[(size_t)q * nlm + q] = 1.0;
+    if ((st = upload(c, c->qident, ident))) return st;
+    DBuf<double> Ub;
+    HIPCHK(c, Ub.ensure((size_t)nlm * ch.M));
+    SolveReport rep;
+    st = solve_batch(c, bb, nullptr, 0, 0.0, true, Ub.p, FSIC_FP64, 1e-13, c->opts.max_iter, rep, c->qident.p);
+    if (!st) {
+        const hipError_t e = hipStreamSynchronize(c->stream);
+        st = e != hipSuccess ? set_err(c, FSIC_EHIP, hipGetErrorString(e)) : finish_solve(c, bb, rep);
+    }
+    if (!st && !rep.converged) st = set_err(c, FSIC_ENOCONV, "boundary basis solve did not converge");
+    if (st) {
+        Ub.release();
+        return st;
+    }
+    c->basis_solves += nlm;
+    c->basis_ms += now_ms() - t0;
+    DBuf<double> &slot = c->bbasis[key];
+    std::swap(slot, Ub);
+    *U = slot.p;
+    return FSIC_OK;
 }
 
 fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, double *e_sic,
@@ -1824,6 +1892,12 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         groups.push_back(g);
     }
     Batch b;
+    // zero-boundary solves plus the boundary basis when a backward pass will
+    // need the zero-boundary (adjoint) solutions anyway
+    const bool use_basis = (o.flags & FSIC_KEEP_TAPE) && !(o.flags & (FSIC_EQ9_FORCES | FSIC_DIRECT_BC));
+    std::vector<const double *> basisU(nchan, nullptr);
+    c->basis_solves = 0;
+    c->basis_ms = 0.0;
     {
         Shape sh;
         fsic_status tst = choose_shape(c, groups, o.precision, sh);
@@ -1835,6 +1909,9 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         c->shape_target = sh.target;
         DstTune dt;
         if ((tst = choose_dst(c, groups, o.precision, sh, dt))) return tst;
+        if (use_basis)
+            for (int ci = 0; ci < nchan; ++ci)
+                if ((tst = boundary_basis(c, chans[ci], sh, dt, &basisU[ci]))) return tst;
         build_batch(groups, P, sh, b, dt);
         c->dst_layout = dst_layout_bits(b);
     }
@@ -1957,8 +2034,25 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     // ---- (c) Poisson solves for all orbitals at once ----
     SolveReport rep;
     c->watch_status = true;
-    fsic_status sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, true, c->V.p, o.precision, o.tol,
-                                  o.max_iter, rep);
+    c->w_ready = false;
+    fsic_status sst;
+    if (use_basis) {
+        // moments of rho_i, zero-boundary solves into W, then
+        // v_i = w_i + sum_q Q_q,i U_q
+        HIPCHK(c, c->W.ensure(F));
+        HIPCHK(c, launch_harm_contract(0, o.lmax, c->ht, c->cf, c->radius, c->d_orb.p, c->d_gcount.p, c->d_hcN.p,
+                                       (int)b.hcN.size(), c->d_hchN.p, (int)b.hchN.size(), b.max_group, c->PHI.p,
+                                       1, c->partH.p, c->Qlm.p, s));
+        sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, false, c->W.p, o.precision, o.tol, o.max_iter, rep);
+        if (!sst)
+            for (int ci = 0; ci < nchan; ++ci) {
+                const Chan &ch = chans[ci];
+                HIPCHK(c, launch_bc_combine(ch.N, ch.M, o.lmax, c->Qlm.p, ch.first_orb, basisU[ci], c->W.p + ch.off,
+                                            c->V.p + ch.off, s));
+            }
+    } else {
+        sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, true, c->V.p, o.precision, o.tol, o.max_iter, rep);
+    }
     c->watch_status = false;
     if (sst) return sst;
     const double t3 = now_ms();
@@ -2044,11 +2138,15 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         st->stencil_depth = c->shape_depth;
         st->stencil_blocks = c->shape_target;
         st->tune_ms = c->tune_ms;
+        st->npoisson = use_basis ? 2 * norb : norb;
+        st->basis_solves = c->basis_solves;
+        st->basis_ms = c->basis_ms;
     }
     c->chans = std::move(chans);
     c->batch = std::move(b);
     c->nsys = nsys;
     c->tape = (o.flags & FSIC_KEEP_TAPE) != 0;
+    c->w_ready = use_basis && rep.converged;
     if (!rep.converged) return set_err(c, FSIC_ENOCONV, "a Poisson solve missed tol within max_iter");
     return FSIC_OK;
 }
@@ -2380,12 +2478,16 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     // exact -((v_i + A^T rho_i)/2 + vxc_i), so A^T rho_i is taken as v_i
     const bool eq9 = (o.flags & FSIC_EQ9_FORCES) != 0;
     const double *Wt = c->V.p;
+    // the forward pass left the adjoint fields in W (zero-boundary solves)
+    const bool reuse_w = !eq9 && c->w_ready;
     if (!eq9) {
         HIPCHK(c, c->W.ensure((size_t)b.fields));
-        // adjoint solves: K w' = 4 pi rho_i with zero Dirichlet values
-        fsic_status sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, false, c->W.p, o.precision, o.tol,
-                                      o.max_iter, rep);
-        if (sst) return sst;
+        if (!reuse_w) {
+            // adjoint solves: K w' = 4 pi rho_i with zero Dirichlet values
+            fsic_status sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, false, c->W.p, o.precision, o.tol,
+                                          o.max_iter, rep);
+            if (sst) return sst;
+        }
         // boundary part of A^T rho: zt = E_g^T C^T w' / (4 pi), then W += P^T zt
         HarmTables hta = c->ht;
         for (int q = 0; q < kMaxLM; ++q) hta.gfac[q] /= 4.0 * M_PI;
@@ -2429,7 +2531,8 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
                                  hipMemcpyDeviceToHost, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
-    if (!eq9) {
+    c->w_ready = false;  // W now holds Gam
+    if (!eq9 && !reuse_w) {
         fsic_status fst = finish_solve(c, b, rep);
         if (fst) return fst;
     }
@@ -2442,7 +2545,8 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
     const double t2 = now_ms();
     if (st) {
         std::memset(st, 0, sizeof(*st));
-        st->nsolves = eq9 ? 0 : norb;
+        st->nsolves = (eq9 || reuse_w) ? 0 : norb;
+        st->npoisson = st->nsolves;
         st->max_iters = rep.max_iters;
         st->total_iters = rep.total_iters;
         st->outer_refinements = rep.refinements;

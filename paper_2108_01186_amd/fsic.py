@@ -34,7 +34,7 @@ FSIC_FP64, FSIC_MIXED = 0, 1
 FSIC_CG, FSIC_PCG, FSIC_AAR = 0, 1, 2
 FSIC_WANT_VSIC, FSIC_KEEP_TAPE, FSIC_ALLOW_NONORTHO, FSIC_PROFILE, FSIC_FP32_ORBITALS = 1, 2, 4, 8, 16
 FSIC_GRAPHS = 32
-FSIC_PAPER_GRADIENT, FSIC_EQ9_FORCES = 64, 128
+FSIC_PAPER_GRADIENT, FSIC_EQ9_FORCES, FSIC_DIRECT_BC = 64, 128, 256
 
 
 class fsic_grid(ctypes.Structure):
@@ -70,7 +70,8 @@ class fsic_stats(ctypes.Structure):
                 ("stencil_blocks", ctypes.c_int64), ("tune_ms", ctypes.c_double),
                 ("resid_launches", ctypes.c_int32), ("resid_ms", ctypes.c_double),
                 ("resid_bytes", ctypes.c_double), ("graph_captures", ctypes.c_int32),
-                ("precond_layout", ctypes.c_int32), ("precond_tune_ms", ctypes.c_double)]
+                ("precond_layout", ctypes.c_int32), ("precond_tune_ms", ctypes.c_double),
+                ("npoisson", ctypes.c_int32), ("basis_solves", ctypes.c_int32), ("basis_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms_phase"}

@@ -206,3 +206,56 @@ def test_cycle_prediction_does_not_change_results(torch_cuda, F, mol40_dev):
         assert got[0] == ref[0], (first, second, got[0], ref[0])
         assert np.array_equal(got[1], ref[1]), (first, second)
         assert np.array_equal(got[2], ref[2]), (first, second)
+
+
+def test_boundary_basis_matches_direct(torch_cuda, F, mol40_dev):
+    """With FSIC_KEEP_TAPE the forward pass solves the zero-boundary problems
+    (the adjoint fields) and forms the multipole-boundary potentials from a
+    per-grid basis of unit-moment boundary solutions; FSIC_DIRECT_BC solves
+    the multipole-boundary problems directly.  On two systems of different
+    grids in one batch both give the same energies, U_i, X_i, V_SIC and FOD
+    gradient to within the solve tolerance; the basis is solved once per grid
+    (49 fields each at lmax 6), the backward pass then runs no Poisson solve,
+    and a second backward on the same tape (the adjoint fields are gone)
+    solves them again and agrees."""
+    torch = torch_cuda
+    _say("boundary basis vs direct, two grids")
+    other = _to_dev(torch, synth.make_molecule("bb36", 36, 0.3, 4, 12, (4, 3), seed=3601))
+    systems = [mol40_dev, other]
+    noccs = [list(s.nocc) for s in systems]
+    norb = sum(sum(n) for n in noccs)
+    fl = F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE
+
+    def run(flags):
+        ctx = F.Context(precision="mixed", tol=1e-11, flags=flags)
+        ds = [F.system_dict(s) for s in systems]
+        e, U, X, st = ctx.forward(ds)
+        g = ctx.backward(noccs)
+        stb = dict(ctx.stats)
+        v = [d["vsic"][k].cpu().numpy().copy() for d in ds for k in range(len(d["vsic"]))]
+        return ctx, ds, e, U, X, st, stb, g, v
+
+    ca, da, ea, Ua, Xa, sta, stba, ga, va = run(fl)
+    cb, db, eb, Ub, Xb, stb_, stbb, gb, vb = run(fl | F.FSIC_DIRECT_BC)
+    assert sta["nsolves"] == norb and sta["npoisson"] == 2 * norb
+    assert sta["basis_solves"] == 2 * 49, sta["basis_solves"]
+    assert stba["nsolves"] == 0 and stba["npoisson"] == 0
+    assert stb_["basis_solves"] == 0 and stbb["nsolves"] == norb
+    assert np.abs(np.asarray(ea) - np.asarray(eb)).max() < 1e-10
+    assert np.abs(Ua - Ub).max() < 1e-10 and np.abs(Xa - Xb).max() < 1e-11
+    for x, y in zip(va, vb):
+        assert np.abs(x - y).max() < 1e-9 * max(1.0, np.abs(y).max())
+    fa = np.concatenate([np.concatenate(s) for s in ga])
+    fb = np.concatenate([np.concatenate(s) for s in gb])
+    assert np.abs(fa - fb).max() < 1e-9, np.abs(fa - fb).max()
+    # basis cached; a second backward on the first tape re-solves the adjoint fields
+    st2 = ca.forward(da)[3]
+    assert st2["basis_solves"] == 0
+    ga1 = ca.backward(noccs)
+    ga2 = ca.backward(noccs)
+    assert ca.stats["nsolves"] == norb
+    f1 = np.concatenate([np.concatenate(s) for s in ga1])
+    f2 = np.concatenate([np.concatenate(s) for s in ga2])
+    assert np.abs(f1 - f2).max() < 1e-9
+    ca.close()
+    cb.close()
