@@ -138,10 +138,9 @@ hipError_t launch_res_steps(int radius, const Coeffs &c, const CGIter<float> &a,
 // Final x of the mixed restart cycles: X[o] = Xb[o] for the orbitals whose
 // result is in the second buffer (fin[o] == 1, or fallback == 1 where
 // fin[o] < 0: not converged).
-// v_o = w_o + sum_q Q[first + o][q] U_q (q < (lmax + 1)^2) for the N
-// orbitals of one channel: U holds the unit-moment boundary solutions of the
-// channel's grid (q-major, M nodes each); W and V point at the channel's
-// first orbital
+// v_o = w_o + sum_q Q[first + o][q] U_q (q < (lmax + 1)^2) for N
+// consecutive orbitals on one grid: U holds the grid's unit-moment boundary
+// solutions (q-major, M nodes each); W and V point at the first orbital
 hipError_t launch_bc_combine(int N, long long M, int lmax, const double *Q, int first, const double *U,
                              const double *W, double *V, hipStream_t s);
 // the statistics of a solve gathered for one transfer: stage holds 8 norb

@@ -605,34 +605,45 @@ hipError_t launch_bterm(int radius, const Coeffs &c, int norb, const OrbDesc *or
     return hipGetLastError();
 }
 
-// v_o = w_o + sum_q Q[first + o][q] U_q over one channel's grid: the
+// v_o = w_o + sum_q Q[first + o][q] U_q for N orbitals on one grid (the
+// channels of a system, which share it and lie next to each other): the
 // multipole-boundary solution from the zero-boundary one and the basis U of
 // unit-moment boundary solutions (the Poisson map is linear in the boundary
-// values, which are linear in the moments).  Block (node tile, 16-orbital
-// group): each thread one node, the group's moment rows in LDS.
+// values, which are linear in the moments).  Block (node tile, group of up to
+// 32 orbitals): each thread one node, the group's moment rows in LDS, so U is
+// read once per node for up to 32 orbitals.
+constexpr int kBcGroup = 32;
 __global__ __launch_bounds__(256) void k_bc_combine(int N, long long M, int nlm, const double *Q, int first,
                                                     const double *__restrict__ U, const double *__restrict__ W,
                                                     double *__restrict__ V) {
-    __shared__ double Qs[16 * kMaxLM];
-    const int o0 = 16 * blockIdx.y;
-    const int no = min(16, N - o0);
-    for (int e = threadIdx.x; e < 16 * nlm; e += 256) {
-        const int j = e / nlm, q = e - j * nlm;
+    __shared__ double Qs[kMaxLM * kBcGroup];  // [q][j]: one broadcast row per q
+    const int o0 = kBcGroup * blockIdx.y;
+    const int no = min(kBcGroup, N - o0);
+    for (int e = threadIdx.x; e < kBcGroup * nlm; e += 256) {
+        const int q = e / kBcGroup, j = e - q * kBcGroup;
         Qs[e] = j < no ? Q[(size_t)(first + o0 + j) * nlm + q] : 0.0;
     }
     __syncthreads();
     const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
     if (m >= M) return;
-    double acc[16];
+    double acc[kBcGroup];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-    for (int q = 0; q < nlm; ++q) {
-        const double u = U[(size_t)q * M + m];
+    for (int j = 0; j < kBcGroup; ++j) acc[j] = 0.0;
+    // eight basis values in flight, then their products
+    for (int q0 = 0; q0 < nlm; q0 += 8) {
+        double u[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] += Qs[j * nlm + q] * u;
+        for (int k = 0; k < 8; ++k) u[k] = q0 + k < nlm ? U[(size_t)(q0 + k) * M + m] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (q0 + k >= nlm) break;
+            const double *qr = Qs + (q0 + k) * kBcGroup;
+#pragma unroll
+            for (int j = 0; j < kBcGroup; ++j) acc[j] += qr[j] * u[k];
+        }
     }
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
+    for (int j = 0; j < kBcGroup; ++j)
         if (j < no) {
             const size_t a = (size_t)(o0 + j) * M + m;
             V[a] = W[a] + acc[j];
@@ -643,7 +654,7 @@ hipError_t launch_bc_combine(int N, long long M, int lmax, const double *Q, int 
                              const double *W, double *V, hipStream_t s) {
     if (N < 1 || M < 1 || lmax < 0 || lmax > kMaxL) return hipErrorInvalidValue;
     const int nlm = (lmax + 1) * (lmax + 1);
-    const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + 15) / 16));
+    const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + kBcGroup - 1) / kBcGroup));
     hipLaunchKernelGGL(k_bc_combine, grid, dim3(256), 0, s, N, M, nlm, Q, first, U, W, V);
     return hipGetLastError();
 }

@@ -2044,12 +2044,20 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
                                        (int)b.hcN.size(), c->d_hchN.p, (int)b.hchN.size(), b.max_group, c->PHI.p,
                                        1, c->partH.p, c->Qlm.p, s));
         sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, false, c->W.p, o.precision, o.tol, o.max_iter, rep);
-        if (!sst)
-            for (int ci = 0; ci < nchan; ++ci) {
-                const Chan &ch = chans[ci];
-                HIPCHK(c, launch_bc_combine(ch.N, ch.M, o.lmax, c->Qlm.p, ch.first_orb, basisU[ci], c->W.p + ch.off,
-                                            c->V.p + ch.off, s));
+        // one launch per run of consecutive channels on one grid (a system's
+        // spins: their orbitals are contiguous), so the basis is read once
+        for (int ci = 0; !sst && ci < nchan;) {
+            const Chan &ch = chans[ci];
+            int cj = ci + 1, n = ch.N;
+            while (cj < nchan && basisU[cj] == basisU[ci] && chans[cj].off == ch.off + (long long)n * ch.M &&
+                   chans[cj].first_orb == ch.first_orb + n) {
+                n += chans[cj].N;
+                ++cj;
             }
+            HIPCHK(c, launch_bc_combine(n, ch.M, o.lmax, c->Qlm.p, ch.first_orb, basisU[ci], c->W.p + ch.off,
+                                        c->V.p + ch.off, s));
+            ci = cj;
+        }
     } else {
         sst = solve_batch(c, b, c->PHI.p, 1, 4.0 * M_PI, true, c->V.p, o.precision, o.tol, o.max_iter, rep);
     }
