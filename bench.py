@@ -56,7 +56,8 @@ def parse():
 
 
 def run_steps(F, torch, ctx, dicts, noccs, steps):
-    """Timed region: `steps` full passes (forward + backward) over all systems."""
+    """Timed region: `steps` full passes (forward + backward, one library
+    call each) over all systems."""
     keys = ("sweep_ms", "sweep_bytes", "sweep_launches", "update_ms", "update_bytes",
             "update_launches", "precond_ms", "precond_bytes", "precond_flops", "precond_launches",
             "resid_ms", "resid_bytes", "resid_launches")
@@ -66,35 +67,26 @@ def run_steps(F, torch, ctx, dicts, noccs, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        e, U, X, st = ctx.forward(dicts)
+        e, U, X, g, st, stb = ctx.forward_backward(dicts)
         agg["shape"] = {"tile": f"32x{8 * st['stencil_cpt']}", "prefetch_planes": st["stencil_depth"],
                         "block_target": st["stencil_blocks"]}
         lay = st["precond_layout"]
         agg["precond_layout"] = {"variant": lay >> 4, "fused_xy": bool(lay & 1),
                                  "xy_two_blocks_per_cu": bool(lay & 2), "z_two_blocks_per_cu": bool(lay & 4),
                                  "early_p_old": bool(lay & 8)}
-        for k in keys:
-            agg[k] += st[k]
-        agg["iters"] += st["total_iters"]
-        agg["solves"] += st["npoisson"]
-        agg["krylov"] += st["nsolves"]
-        agg["basis_solves"] += st["basis_solves"]
-        agg["refinements"] += st["outer_refinements"]
-        agg["max_relres"] = max(agg["max_relres"], st["max_relres"])
+        for part in (st, stb):
+            for k in keys:
+                agg[k] += part[k]
+            agg["iters"] += part["total_iters"]
+            agg["solves"] += part["npoisson"]
+            agg["krylov"] += part["nsolves"]
+            agg["basis_solves"] += part["basis_solves"]
+            agg["refinements"] += part["outer_refinements"]
+            agg["max_relres"] = max(agg["max_relres"], part["max_relres"])
         for q in (0, 1, 2, 3, 4):
             agg["phase_ms"][q] += st["ms_phase"][q] / steps
-        g = ctx.backward(noccs)
-        st = ctx.stats
-        for k in keys:
-            agg[k] += st[k]
-        agg["iters"] += st["total_iters"]
-        agg["solves"] += st["npoisson"]
-        agg["krylov"] += st["nsolves"]
-        agg["basis_solves"] += st["basis_solves"]
-        agg["refinements"] += st["outer_refinements"]
-        agg["max_relres"] = max(agg["max_relres"], st["max_relres"])
         for q in (5, 6):
-            agg["phase_ms"][q] += st["ms_phase"][q] / steps
+            agg["phase_ms"][q] += stb["ms_phase"][q] / steps
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dt, e, g, agg
@@ -336,10 +328,9 @@ def main():
         ctx = F.Context(precision=leg, tol=args.tol, flags=flags, solver=args.solver)
         basis = {"solves": 0, "ms": 0.0}  # unit-moment boundary solutions, once per grid
         for _ in range(args.warmup):
-            st = ctx.forward(dicts)[3]
+            st = ctx.forward_backward(dicts)[4]
             basis["solves"] += st["basis_solves"]
             basis["ms"] += st["basis_ms"]
-            ctx.backward(noccs)
         dt, e, g, agg = run_steps(F, torch, ctx, dicts, noccs, args.steps)
         results[leg] = dict(dt=dt, e=np.asarray(e, dtype=np.float64),
                             g=np.concatenate([np.concatenate(gs) for gs in g]), agg=agg, basis=basis)
@@ -356,8 +347,7 @@ def main():
                           F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE | F.FSIC_GRAPHS)):
             ctx = F.Context(precision="mixed", tol=args.tol, flags=fl, solver=args.solver)
             for _ in range(args.warmup):
-                ctx.forward(dicts)
-                ctx.backward(noccs)
+                ctx.forward_backward(dicts)
             dt, _, _, agg = run_steps(F, torch, ctx, dicts, noccs, args.steps)
             ctx.close()
             extra[name] = agg["solves"] / dt
@@ -368,8 +358,7 @@ def main():
         ctx = F.Context(precision="fp64", tol=args.tol, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE,
                         solver="aar")
         for _ in range(args.warmup):
-            ctx.forward(dicts)
-            ctx.backward(noccs)
+            ctx.forward_backward(dicts)
         dt, e_a, g_a, agg = run_steps(F, torch, ctx, dicts, noccs, args.steps)
         ctx.close()
         extra["aar_fp64_solves_per_s"] = agg["solves"] / dt

@@ -261,6 +261,21 @@ fsic_status fsic_forward(fsic_ctx *ctx, int32_t nsys, const fsic_system *sys,
 fsic_status fsic_backward(fsic_ctx *ctx, const double *grad_e, double *const *dE_da,
                           fsic_stats *st);
 
+/* fsic_forward and then fsic_backward in one call, for callers that want
+ * E_SIC and the FOD gradient of the same FODs (the step of an FOD
+ * optimisation).  Needs FSIC_KEEP_TAPE.  Without FSIC_EQ9_FORCES and
+ * FSIC_DIRECT_BC the backward pass's device work (it runs no Poisson solve:
+ * the forward pass solved the adjoint problems) is enqueued behind the
+ * forward pass's before the host waits, so the two share one
+ * synchronisation; otherwise the two run one after the other.  Arguments
+ * as in the two calls (grad_e may be NULL: 1 per system; st_fwd and st_bwd
+ * may be NULL); the results and the tape left behind are those of the two
+ * calls.  An error of the forward pass is returned before any gradient is
+ * written. */
+fsic_status fsic_forward_backward(fsic_ctx *ctx, int32_t nsys, const fsic_system *sys, double *e_sic,
+                                  double *U, double *X, const double *grad_e, double *const *dE_da,
+                                  fsic_stats *st_fwd, fsic_stats *st_bwd);
+
 const char *fsic_status_string(fsic_status s);
 const char *fsic_last_error(const fsic_ctx *ctx);
 void fsic_destroy(fsic_ctx *ctx);

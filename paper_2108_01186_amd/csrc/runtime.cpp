@@ -1785,7 +1785,8 @@ void fsic_destroy(fsic_ctx *c) {
 // multipole-boundary solution of any source is its zero-boundary solution
 // plus sum_q Q_q U_q.  Uses the context's solve buffers (the caller prepares
 // its own batch afterwards).
-fsic_status boundary_basis(fsic_ctx *c, const Chan &ch, const Shape &sh, const DstTune &dt, const double **U) {
+static fsic_status boundary_basis(fsic_ctx *c, const Chan &ch, const Shape &sh, const DstTune &dt,
+                                  const double **U) {
     const int lmax = c->opts.lmax, nlm = (lmax + 1) * (lmax + 1);
     long long hb = 0;
     std::memcpy(&hb, &ch.h, sizeof(hb));
@@ -1827,8 +1828,29 @@ fsic_status boundary_basis(fsic_ctx *c, const Chan &ch, const Shape &sh, const D
     return FSIC_OK;
 }
 
-fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, double *e_sic,
-                         double *Uout, double *Xout, fsic_stats *st) {
+// The backward pass in two parts: everything up to the gradient copies is
+// enqueued (backward_enqueue), then, after the caller's wait on the stream,
+// backward_finish reads the copies back.  fused: behind a forward pass in
+// the same call (fsic_forward_backward), which prepared the batch and has
+// not yet read its own statistics.
+struct BwdState {
+    double t0 = 0.0, t1 = 0.0;
+    SolveReport rep;
+    bool eq9 = false, reuse_w = false;
+    std::vector<size_t> goff;
+    std::vector<int> spin0;
+};
+
+static fsic_status backward_enqueue(fsic_ctx *c, bool fused, BwdState &bs);
+static fsic_status backward_finish(fsic_ctx *c, bool fused, const double *grad_e, double *const *dE_da,
+                                   fsic_stats *st, BwdState &bs);
+
+// The forward pass; with dE_da (fsic_forward_backward) the backward pass's
+// device work is enqueued behind it before the host waits, and read back
+// after the forward pass's own checks.
+static fsic_status forward_impl(fsic_ctx *c, int32_t nsys, const fsic_system *sys, double *e_sic,
+                                double *Uout, double *Xout, fsic_stats *st, const double *grad_e,
+                                double *const *dE_da, fsic_stats *bst) {
     if (!c) return FSIC_EINVAL;
     const double t0 = now_ms();
     if (nsys < 1 || !sys || !e_sic) return set_err(c, FSIC_EINVAL, "nsys >= 1, sys and e_sic are required");
@@ -2072,6 +2094,21 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     HIPCHK(c, launch_sic_energy(nchan, c->d_chan.p, c->partU.p, c->partX.p, dU, dX, dE, s));
     HIPCHK(c, hipMemcpyAsync(c->h_eux, c->eux.p, (2 * (size_t)norb + nchan) * sizeof(double),
                              hipMemcpyDeviceToHost, s));
+    // the plan becomes the tape (its flag is set once the checks below pass)
+    c->chans = std::move(chans);
+    c->batch = std::move(b);
+    c->nsys = nsys;
+    const std::vector<Chan> &chs = c->chans;
+    const Batch &bt = c->batch;
+    // fused backward pass: enqueued now, behind the forward pass's work
+    const bool fused = dE_da != nullptr && use_basis;
+    BwdState bws;
+    if (fused) {
+        c->w_ready = true;
+        fsic_status bs = backward_enqueue(c, true, bws);
+        c->w_ready = false;  // the enqueued work turns W into Gam
+        if (bs) return bs;
+    }
     HIPCHK(c, hipStreamSynchronize(s));
     const double *const uo = c->h_eux, *const xo = uo + norb, *const ech = xo + norb;
 
@@ -2083,7 +2120,7 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
     double nonortho = 0.0, condmax = 0.0, minrho = 1e300, minlam = 0.0;
     {
         size_t q = 0;
-        for (const Chan &ch : chans) {
+        for (const Chan &ch : chs) {
             const size_t NN = (size_t)ch.N * ch.N;
             const double *G = c->h_chk + q, *info = c->h_chk + q + NN, *rhoa = c->h_chk + q + NN + 2;
             for (int i = 0; i < ch.N; ++i) {
@@ -2104,10 +2141,10 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
                                               " below s_eig_floor");
     if (!(o.flags & FSIC_ALLOW_NONORTHO) && nonortho > 1e-8)
         return set_err(c, FSIC_ENONORTHO, "max |dV psi psi^T - I| = " + std::to_string(nonortho));
-    fsic_status fst = finish_solve(c, b, rep);
+    fsic_status fst = finish_solve(c, bt, rep);
     if (fst) return fst;
     for (int k = 0; k < nsys; ++k) e_sic[k] = 0.0;
-    for (int ci = 0; ci < nchan; ++ci) e_sic[chans[ci].sys] += ech[ci];
+    for (int ci = 0; ci < nchan; ++ci) e_sic[chs[ci].sys] += ech[ci];
     if (Uout) std::memcpy(Uout, uo, norb * sizeof(double));
     if (Xout) std::memcpy(Xout, xo, norb * sizeof(double));
     const double t4 = now_ms();
@@ -2150,13 +2187,34 @@ fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, doub
         st->basis_solves = c->basis_solves;
         st->basis_ms = c->basis_ms;
     }
-    c->chans = std::move(chans);
-    c->batch = std::move(b);
-    c->nsys = nsys;
     c->tape = (o.flags & FSIC_KEEP_TAPE) != 0;
-    c->w_ready = use_basis && rep.converged;
+    c->w_ready = use_basis && rep.converged && !fused;
     if (!rep.converged) return set_err(c, FSIC_ENOCONV, "a Poisson solve missed tol within max_iter");
+    if (fused) return backward_finish(c, true, grad_e, dE_da, bst, bws);
     return FSIC_OK;
+}
+
+fsic_status fsic_forward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, double *e_sic,
+                         double *Uout, double *Xout, fsic_stats *st) {
+    return forward_impl(c, nsys, sys, e_sic, Uout, Xout, st, nullptr, nullptr, nullptr);
+}
+
+fsic_status fsic_forward_backward(fsic_ctx *c, int32_t nsys, const fsic_system *sys, double *e_sic,
+                                  double *Uout, double *Xout, const double *grad_e, double *const *dE_da,
+                                  fsic_stats *st_fwd, fsic_stats *st_bwd) {
+    if (!c) return FSIC_EINVAL;
+    if (!(c->opts.flags & FSIC_KEEP_TAPE))
+        return set_err(c, FSIC_ENOTAPE, "fsic_forward_backward needs FSIC_KEEP_TAPE");
+    if (!dE_da) return set_err(c, FSIC_EINVAL, "dE_da is required");
+    if (nsys < 1 || !sys) return set_err(c, FSIC_EINVAL, "nsys >= 1, sys and e_sic are required");
+    for (int k = 0; k < nsys; ++k)
+        if (!dE_da[k]) return set_err(c, FSIC_EINVAL, "dE_da[k] is required for every system");
+    const bool basis = !(c->opts.flags & (FSIC_EQ9_FORCES | FSIC_DIRECT_BC));
+    if (basis) return forward_impl(c, nsys, sys, e_sic, Uout, Xout, st_fwd, grad_e, dE_da, st_bwd);
+    // the backward pass solves its own adjoint problems: one after the other
+    fsic_status e = forward_impl(c, nsys, sys, e_sic, Uout, Xout, st_fwd, nullptr, nullptr, nullptr);
+    if (e) return e;
+    return fsic_backward(c, grad_e, dE_da, st_bwd);
 }
 
 // ---------------------------------------------------------------------------
@@ -2459,35 +2517,38 @@ fsic_status fsic_op_flo(const fsic_grid *grid, int32_t N, const double *psi, con
     return FSIC_OK;
 }
 
-fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_da, fsic_stats *st) {
-    if (!c) return FSIC_EINVAL;
-    if (!c->tape) return set_err(c, FSIC_ENOTAPE, "backward needs a forward pass with FSIC_KEEP_TAPE");
-    if (!dE_da) return set_err(c, FSIC_EINVAL, "dE_da is required");
-    for (int k = 0; k < c->nsys; ++k)
-        if (!dE_da[k]) return set_err(c, FSIC_EINVAL, "dE_da[k] is required for every system");
-    const double t0 = now_ms();
+static fsic_status backward_enqueue(fsic_ctx *c, bool fused, BwdState &bs) {
+    bs.t0 = now_ms();
+    const double t0 = bs.t0;
+    (void)t0;
     const fsic_opts &o = c->opts;
     const Batch &b = c->batch;
     hipStream_t s = c->stream;
-    const int norb = (int)b.orb.size();
-    c->tune_ms = 0.0;  // the backward pass reuses the forward pass's stencil shape and
-    c->dst_tune_ms = 0.0;  // preconditioner layout
-    c->sweep_launches = c->update_launches = c->precond_launches = 0;
-    c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
-    c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
-    c->resid_launches = 0;
-    c->resid_ms = c->resid_bytes = 0.0;
-    fsic_status pst = prepare_batch(c, b, o.precision);
-    if (pst) return pst;
+    if (!fused) {
+        c->tune_ms = 0.0;  // the backward pass reuses the forward pass's stencil shape and
+        c->dst_tune_ms = 0.0;  // preconditioner layout
+        c->sweep_launches = c->update_launches = c->precond_launches = 0;
+        c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
+        c->precond_ms = c->precond_bytes = c->precond_flops = 0.0;
+        c->resid_launches = 0;
+        c->resid_ms = c->resid_bytes = 0.0;
+        // (fused: the forward pass prepared this batch and its statistics
+        // are still to be read)
+        fsic_status pst = prepare_batch(c, b, o.precision);
+        if (pst) return pst;
+    }
     HIPCHK(c, c->bmat.ensure((size_t)kMaxOrb * kMaxOrb));
-    SolveReport rep;
+    SolveReport &rep = bs.rep;
+    rep = SolveReport{};
     rep.converged = true;
     // Eq. 9 form: the orbital SIC potential -(v_i + vxc_i) in place of the
     // exact -((v_i + A^T rho_i)/2 + vxc_i), so A^T rho_i is taken as v_i
     const bool eq9 = (o.flags & FSIC_EQ9_FORCES) != 0;
+    bs.eq9 = eq9;
     const double *Wt = c->V.p;
     // the forward pass left the adjoint fields in W (zero-boundary solves)
     const bool reuse_w = !eq9 && c->w_ready;
+    bs.reuse_w = reuse_w;
     if (!eq9) {
         HIPCHK(c, c->W.ensure((size_t)b.fields));
         if (!reuse_w) {
@@ -2506,15 +2567,17 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
                                      (int)b.hcNx.size(), c->Zt.p, c->W.p, s));
         Wt = c->W.p;
     }
-    const double t1 = now_ms();
+    bs.t1 = now_ms();
     HIPCHK(c, c->W.ensure((size_t)b.fields));  // Gam (the Eq. 9 form has no adjoint field)
     // per channel: B = Gam psi^T, then the N x N reverse chain
-    std::vector<int> spin0(c->nsys, 0);
+    std::vector<int> &spin0 = bs.spin0;
+    spin0.assign(c->nsys, 0);
     for (const Chan &ch : c->chans)
         if (ch.spin == 0) spin0[ch.sys] = ch.N;
     // dE/da of every channel lands in one pinned host block (asynchronous
     // copies, one wait at the end)
-    std::vector<size_t> goff(c->chans.size() + 1, 0);
+    std::vector<size_t> &goff = bs.goff;
+    goff.assign(c->chans.size() + 1, 0);
     for (size_t ci = 0; ci < c->chans.size(); ++ci) goff[ci + 1] = goff[ci] + 3 * (size_t)c->chans[ci].N;
     if (c->h_grad_cap < goff.back()) {
         if (c->h_grad) hipHostFree(c->h_grad);
@@ -2538,7 +2601,20 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         HIPCHK(c, hipMemcpyAsync(c->h_grad + goff[ci], sm + small_off(sDEDA), 3 * ch.N * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     }
-    HIPCHK(c, hipStreamSynchronize(s));
+    return FSIC_OK;
+}
+
+static fsic_status backward_finish(fsic_ctx *c, bool fused, const double *grad_e, double *const *dE_da,
+                                   fsic_stats *st, BwdState &bs) {
+    const fsic_opts &o = c->opts;
+    (void)o;
+    const Batch &b = c->batch;
+    const int norb = (int)b.orb.size();
+    const double t0 = bs.t0, t1 = bs.t1;
+    SolveReport &rep = bs.rep;
+    const bool eq9 = bs.eq9, reuse_w = bs.reuse_w;
+    const std::vector<size_t> &goff = bs.goff;
+    const std::vector<int> &spin0 = bs.spin0;
     c->w_ready = false;  // W now holds Gam
     if (!eq9 && !reuse_w) {
         fsic_status fst = finish_solve(c, b, rep);
@@ -2582,9 +2658,36 @@ fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_d
         st->stencil_depth = c->shape_depth;
         st->stencil_blocks = c->shape_target;
         st->tune_ms = c->tune_ms;
+        if (fused) {
+            // no solve ran here: the launch statistics and phase times in
+            // the context are the forward pass's
+            const int32_t layout = st->precond_layout, cpt = st->stencil_cpt, depth = st->stencil_depth;
+            const int64_t blocks = st->stencil_blocks;
+            std::memset(st, 0, sizeof(*st));
+            st->precond_layout = layout;
+            st->stencil_cpt = cpt;
+            st->stencil_depth = depth;
+            st->stencil_blocks = blocks;
+            st->graph_captures = c->graph_captures;
+            st->max_relres = rep.max_relres;
+        }
     }
     if (!rep.converged) return set_err(c, FSIC_ENOCONV, "an adjoint Poisson solve missed tol within max_iter");
     return FSIC_OK;
+}
+
+
+fsic_status fsic_backward(fsic_ctx *c, const double *grad_e, double *const *dE_da, fsic_stats *st) {
+    if (!c) return FSIC_EINVAL;
+    if (!c->tape) return set_err(c, FSIC_ENOTAPE, "backward needs a forward pass with FSIC_KEEP_TAPE");
+    if (!dE_da) return set_err(c, FSIC_EINVAL, "dE_da is required");
+    for (int k = 0; k < c->nsys; ++k)
+        if (!dE_da[k]) return set_err(c, FSIC_EINVAL, "dE_da[k] is required for every system");
+    BwdState bs;
+    fsic_status e = backward_enqueue(c, false, bs);
+    if (e) return e;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return backward_finish(c, false, grad_e, dE_da, st, bs);
 }
 
 }  // extern "C"

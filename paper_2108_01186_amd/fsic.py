@@ -98,6 +98,9 @@ fsic_set_opts = _sig("fsic_set_opts", ctypes.c_int, [_vp, _P(fsic_opts)])
 fsic_forward = _sig("fsic_forward", ctypes.c_int,
                     [_vp, ctypes.c_int32, _P(fsic_system), _dp, _dp, _dp, _P(fsic_stats)])
 fsic_backward = _sig("fsic_backward", ctypes.c_int, [_vp, _dp, _P(_dp), _P(fsic_stats)])
+fsic_forward_backward = _sig("fsic_forward_backward", ctypes.c_int,
+                             [_vp, ctypes.c_int32, _P(fsic_system), _dp, _dp, _dp, _dp, _P(_dp),
+                              _P(fsic_stats), _P(fsic_stats)])
 fsic_status_string = _sig("fsic_status_string", ctypes.c_char_p, [ctypes.c_int])
 fsic_last_error = _sig("fsic_last_error", ctypes.c_char_p, [_vp])
 fsic_destroy = _sig("fsic_destroy", None, [_vp])
@@ -126,6 +129,7 @@ fsic_op_interp = _sig("fsic_op_interp", ctypes.c_int,
                        _vp, _vp])
 
 EXPORTED = ["fsic_default_opts", "fsic_create", "fsic_set_opts", "fsic_forward", "fsic_backward",
+            "fsic_forward_backward",
             "fsic_status_string", "fsic_last_error", "fsic_destroy", "fsic_op_laplacian",
             "fsic_op_laplacian_f32", "fsic_op_xc", "fsic_op_poisson", "fsic_op_invsqrt",
             "fsic_op_hamiltonian", "fsic_op_interp",
@@ -228,10 +232,7 @@ class Context:
         self.generation += 1  # the library drops the tape with new options
         _check(fsic_set_opts(self._h, ctypes.byref(self.opts)), self._h)
 
-    def forward(self, systems: Sequence[dict], allow_noconv=False):
-        """systems: dicts with n, h, origin, psi (list of device (N, M) float64
-        tensors), fod (list of host (N, 3) arrays), vsic (list of device (M,)
-        tensors or None).  Returns (E_SIC per system, U, X, stats)."""
+    def _systems(self, systems):
         nsys = len(systems)
         arr = (fsic_system * nsys)()
         keep = []
@@ -254,6 +255,14 @@ class Context:
                 vs = (s.get("vsic") or [None, None])[sp]
                 arr[k].vsic[sp] = _dev_ptr(vs).value if vs is not None else None
                 norb += psi.shape[0]
+        return arr, keep, norb
+
+    def forward(self, systems: Sequence[dict], allow_noconv=False):
+        """systems: dicts with n, h, origin, psi (list of device (N, M) float64
+        tensors), fod (list of host (N, 3) arrays), vsic (list of device (M,)
+        tensors or None).  Returns (E_SIC per system, U, X, stats)."""
+        nsys = len(systems)
+        arr, keep, norb = self._systems(systems)
         e = np.zeros(nsys)
         U = np.zeros(norb)
         X = np.zeros(norb)
@@ -265,6 +274,43 @@ class Context:
         self._keep = keep
         self.stats = st.as_dict()
         return e, U, X, self.stats
+
+    def forward_backward(self, systems: Sequence[dict], grad_e=None):
+        """forward() and backward() of the same systems in one library call
+        (needs FSIC_KEEP_TAPE).  Returns (E_SIC, U, X, dE/da per system as in
+        backward(), forward stats, backward stats)."""
+        nsys = len(systems)
+        arr, keep, norb = self._systems(systems)
+        nocc = [[int(p.shape[0]) for p in s["psi"]] for s in systems]
+        e = np.zeros(nsys)
+        U = np.zeros(norb)
+        X = np.zeros(norb)
+        outs = [np.zeros((sum(no), 3)) for no in nocc]
+        ptrs = (_dp * nsys)(*[o.ctypes.data_as(_dp) for o in outs])
+        ge = None
+        if grad_e is not None:
+            ge = np.ascontiguousarray(np.asarray(grad_e, dtype=np.float64).reshape(nsys))
+        stf, stb = fsic_stats(), fsic_stats()
+        status = fsic_forward_backward(self._h, nsys, arr, e.ctypes.data_as(_dp),
+                                       U.ctypes.data_as(_dp), X.ctypes.data_as(_dp),
+                                       ge.ctypes.data_as(_dp) if ge is not None else None, ptrs,
+                                       ctypes.byref(stf), ctypes.byref(stb))
+        self.generation += 1
+        _check(status, self._h)
+        self._keep = keep
+        self.stats = stb.as_dict()
+        return e, U, X, self._split(outs, nocc), stf.as_dict(), self.stats
+
+    @staticmethod
+    def _split(outs, nocc_per_system):
+        res = []
+        for o, no in zip(outs, nocc_per_system):
+            parts, b = [], 0
+            for n in no:
+                parts.append(o[b:b + n])
+                b += n
+            res.append(parts)
+        return res
 
     def backward(self, nocc_per_system: Sequence[Sequence[int]], grad_e=None):
         """Returns, per system, dE/da as an array (nspin, N, 3) (ragged spins
@@ -279,14 +325,7 @@ class Context:
         _check(fsic_backward(self._h, ge.ctypes.data_as(_dp) if ge is not None else None, ptrs,
                              ctypes.byref(st)), self._h)
         self.stats = st.as_dict()
-        res = []
-        for o, no in zip(outs, nocc_per_system):
-            parts, b = [], 0
-            for n in no:
-                parts.append(o[b:b + n])
-                b += n
-            res.append(parts)
-        return res
+        return self._split(outs, nocc_per_system)
 
 
 # --------------------------------------------------------------------------

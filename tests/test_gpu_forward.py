@@ -259,3 +259,49 @@ def test_boundary_basis_matches_direct(torch_cuda, F, mol40_dev):
     assert np.abs(f1 - f2).max() < 1e-9
     ca.close()
     cb.close()
+
+
+def test_forward_backward_in_one_call(torch_cuda, F, mol40_dev):
+    """fsic_forward_backward enqueues the backward pass's device work behind
+    the forward pass's and waits once; energies, U_i, X_i, V_SIC and the FOD
+    gradient equal those of fsic_forward then fsic_backward bit for bit, with
+    the boundary basis and with FSIC_DIRECT_BC (which runs the two calls one
+    after the other).  The tape it leaves serves a further backward pass,
+    which solves the adjoint problems again; without FSIC_KEEP_TAPE the call
+    is refused."""
+    torch = torch_cuda
+    _say("forward_backward fused vs separate, two grids")
+    other = _to_dev(torch, synth.make_molecule("bb36", 36, 0.3, 4, 12, (4, 3), seed=3601))
+    systems = [mol40_dev, other]
+    noccs = [list(s.nocc) for s in systems]
+    norb = sum(sum(n) for n in noccs)
+    ge = [1.0, -0.5]
+    for extra in (0, F.FSIC_DIRECT_BC):
+        fl = F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE | extra
+        ca = F.Context(precision="mixed", tol=1e-11, flags=fl)
+        da = [F.system_dict(s) for s in systems]
+        ea, Ua, Xa, _ = ca.forward(da)
+        ga = ca.backward(noccs, grad_e=ge)
+        va = [d["vsic"][k].cpu().numpy().copy() for d in da for k in range(len(d["vsic"]))]
+        cb = F.Context(precision="mixed", tol=1e-11, flags=fl)
+        db = [F.system_dict(s) for s in systems]
+        eb, Ub, Xb, gb, stf, stb = cb.forward_backward(db, grad_e=ge)
+        vb = [d["vsic"][k].cpu().numpy().copy() for d in db for k in range(len(d["vsic"]))]
+        assert np.array_equal(ea, eb) and np.array_equal(Ua, Ub) and np.array_equal(Xa, Xb), extra
+        for x, y in zip(va, vb):
+            assert np.array_equal(x, y), extra
+        fa = np.concatenate([np.concatenate(s) for s in ga])
+        fb = np.concatenate([np.concatenate(s) for s in gb])
+        assert np.array_equal(fa, fb), (extra, np.abs(fa - fb).max())
+        assert stf["nsolves"] == norb
+        assert stb["nsolves"] == (0 if extra == 0 else norb)
+        gc = cb.backward(noccs, grad_e=ge)
+        assert cb.stats["nsolves"] == norb
+        fc = np.concatenate([np.concatenate(s) for s in gc])
+        assert np.abs(fc - fb).max() < 1e-9
+        ca.close()
+        cb.close()
+    cn = F.Context(precision="mixed", tol=1e-11, flags=F.FSIC_WANT_VSIC)
+    with pytest.raises(F.FsicError):
+        cn.forward_backward([F.system_dict(mol40_dev)])
+    cn.close()
