@@ -381,34 +381,33 @@ __device__ __forceinline__ void lowdin_one(int N, int Ne, const double *T, const
                 rp[j] = p; rq[j] = q; rc[j] = c; rs_[j] = s;
             }
             __syncthreads();
-            // rows p, q of A <- J^T A
-            for (int e = threadIdx.x; e < half * Ne; e += 256) {
-                const int j = e / Ne, col = e % Ne;
-                const int p = rp[j], q = rq[j];
-                const double c = rc[j], s = rs_[j];
-                const double ap = A[p * Ne + col], aq = A[q * Ne + col];
-                A[p * Ne + col] = c * ap - s * aq;
-                A[q * Ne + col] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns p, q of A and V <- A J, V J
-            for (int e = threadIdx.x; e < half * Ne; e += 256) {
-                const int j = e / Ne, rw = e % Ne;
-                const int p = rp[j], q = rq[j];
-                const double c = rc[j], s = rs_[j];
-                const double ap = A[rw * Ne + p], aq = A[rw * Ne + q];
-                A[rw * Ne + p] = c * ap - s * aq;
-                A[rw * Ne + q] = s * ap + c * aq;
-                const double vp = V[rw * Ne + p], vq = V[rw * Ne + q];
-                V[rw * Ne + p] = c * vp - s * vq;
-                V[rw * Ne + q] = s * vp + c * vq;
-            }
-            __syncthreads();
-            if (threadIdx.x < half) {
-                const int p = rp[threadIdx.x], q = rq[threadIdx.x];
-                if (rs_[threadIdx.x] != 0.0) {
-                    A[p * Ne + q] = 0.0;
-                    A[q * Ne + p] = 0.0;
+            // A <- J^T A J by 2 x 2 blocks (rows of pair i, columns of pair
+            // j: the blocks are disjoint, so each updates in place; rows
+            // first, then columns), the rotated pair's own entry set to
+            // zero; V <- V J by rows
+            const int nA = half * half;
+            for (int e = threadIdx.x; e < nA + Ne * half; e += 256) {
+                if (e < nA) {
+                    const int bi = e / half, bj = e - bi * half;
+                    const int pi = rp[bi], qi = rq[bi], pj = rp[bj], qj = rq[bj];
+                    const double ci = rc[bi], si = rs_[bi], cj = rc[bj], sj = rs_[bj];
+                    const double a_pp = A[pi * Ne + pj], a_pq = A[pi * Ne + qj];
+                    const double a_qp = A[qi * Ne + pj], a_qq = A[qi * Ne + qj];
+                    const double r_pp = ci * a_pp - si * a_qp, r_pq = ci * a_pq - si * a_qq;
+                    const double r_qp = si * a_pp + ci * a_qp, r_qq = si * a_pq + ci * a_qq;
+                    double o_pq = sj * r_pp + cj * r_pq, o_qp = cj * r_qp - sj * r_qq;
+                    if (bi == bj && si != 0.0) o_pq = o_qp = 0.0;
+                    A[pi * Ne + pj] = cj * r_pp - sj * r_pq;
+                    A[pi * Ne + qj] = o_pq;
+                    A[qi * Ne + pj] = o_qp;
+                    A[qi * Ne + qj] = sj * r_qp + cj * r_qq;
+                } else {
+                    const int e2 = e - nA, rw = e2 / half, j = e2 - rw * half;
+                    const int p = rp[j], q = rq[j];
+                    const double c = rc[j], s = rs_[j];
+                    const double vp = V[rw * Ne + p], vq = V[rw * Ne + q];
+                    V[rw * Ne + p] = c * vp - s * vq;
+                    V[rw * Ne + q] = s * vp + c * vq;
                 }
             }
             __syncthreads();

@@ -145,6 +145,17 @@ hipError_t launch_bc_combine(int N, long long M, int lmax, const double *Q, int 
                              const double *W, double *V, hipStream_t s);
 // the statistics of a solve gathered for one transfer: stage holds 8 norb
 // ints (iters, nact[6 norb], done) and then 2 norb doubles (ptrue, bb)
+// The host checks' inputs of up to kChkPack channels, packed one after the
+// other for one copy to the host: channel e's G (N x N), info (2) and
+// rho(a) (N) from small + so[e] (+ oG, oI, oR) to out + q[e].
+constexpr int kChkPack = 32;
+struct ChkPack {
+    int n;
+    long long oG, oI, oR;
+    int N[kChkPack];
+    long long so[kChkPack], q[kChkPack];
+};
+hipError_t launch_pack_checks(const ChkPack &p, const double *small, double *out, hipStream_t s);
 hipError_t launch_stage_stats(int norb, const int *iters, const int *nact, const int *done,
                               const double *ptrue, const double *bb, double *stage, hipStream_t s);
 hipError_t launch_take_x(int nitems8, const Item *items8, const OrbDesc *orb, const int *fin, int fallback,
@@ -279,6 +290,11 @@ struct HcChan {
 // rows of a partial tile: (kMaxL + 1)^2 harmonics padded to 16; columns: the
 // channel's orbitals padded to 16
 constexpr int kHcRows = (kMaxLM + 15) / 16 * 16;
+// Blocks of a harmonic kernel the current device holds at once (blocks per
+// compute unit from the occupancy query, times the compute units): kind 0
+// the contraction over grid nodes, 1 over ghosts, 2 the expansion over
+// ghosts, 3 over grid nodes.  Cached per device; at least 1.
+int harm_slots(int kind, int lmax);
 hipError_t launch_harm_contract(int mode, int lmax, const HarmTables &ht, const Coeffs &c, int radius,
                                 const OrbDesc *orb, const long long *ghost_count, const HcItem *items,
                                 int nitems, const HcChan *chans, int nchans, int max_count,

@@ -7,6 +7,9 @@
 // azimuthal factor is (x + i y)^m and the polar factor r^(l-m) d^m P_l/dx^m
 // (z / r) obeys the three-term recurrence in l, so one node costs a few
 // hundred flops and no transcendental calls.
+#include <array>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.h"
@@ -550,6 +553,45 @@ __global__ __launch_bounds__(256) void k_harm_expand(HarmTables ht, int P, const
         default: return hipErrorInvalidValue; \
     }
 
+int harm_slots(int kind, int lmax) {
+    static std::mutex mu;
+    static std::map<std::array<int, 3>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (kind < 0 || kind > 3 || lmax < 0 || lmax > kMaxL) return 1;
+    std::lock_guard<std::mutex> lock(mu);
+    const std::array<int, 3> key{dev, kind, lmax};
+    const auto f = cache.find(key);
+    if (f != cache.end()) return f->second;
+    const int kq = ((lmax + 1) * (lmax + 1) + 15) / 16 * 16;
+    const size_t lds = kind >= 2 ? (size_t)16 * kHcExpandTiles * (kq + 1) * sizeof(double) : 0;
+    const void *fn = nullptr;
+#define FN(L)                                                                                  \
+    fn = kind == 0 ? (const void *)k_harm_contract<L, 0>                                       \
+                   : kind == 1 ? (const void *)k_harm_contract<L, 1>                           \
+                               : kind == 2 ? (const void *)k_harm_expand<L, 0> : (const void *)k_harm_expand<L, 1>
+    switch (lmax) {
+        case 0: FN(0); break;
+        case 1: FN(1); break;
+        case 2: FN(2); break;
+        case 3: FN(3); break;
+        case 4: FN(4); break;
+        case 5: FN(5); break;
+        case 6: FN(6); break;
+        case 7: FN(7); break;
+        default: FN(8); break;
+    }
+#undef FN
+    if (lds > 32768) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int per = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, lds) != hipSuccess || per < 1) per = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    (void)hipGetLastError();  // a failed query leaves no error behind for the next launch
+    const int slots = per * cus;
+    cache[key] = slots;
+    return slots;
+}
+
 hipError_t launch_harm_contract(int mode, int lmax, const HarmTables &ht, const Coeffs &c, int radius,
                                 const OrbDesc *orb, const long long *ghost_count, const HcItem *items,
                                 int nitems, const HcChan *chans, int nchans, int max_count,
@@ -583,7 +625,7 @@ hipError_t launch_harm_expand(int mode, int lmax, const HarmTables &ht, int radi
 #define CALL(L)                                                                                        \
     do {                                                                                               \
         const void *fn = mode == 0 ? (const void *)k_harm_expand<L, 0> : (const void *)k_harm_expand<L, 1>; \
-        if (lds > 32768) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        if (lds > 32768) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         if (mode == 0)                                                                                 \
             hipLaunchKernelGGL((k_harm_expand<L, 0>), dim3(nitems), dim3(256), lds, s, ht, radius, orb, \
                                ghost_count, items, C, out);                                            \

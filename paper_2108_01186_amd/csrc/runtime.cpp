@@ -177,13 +177,11 @@ struct Batch {
     long long hc_elems = 0;
 };
 
-// blocks of a harmonic contraction (about three per compute unit)
-constexpr int kHcBlocks = 768;
-
-// Splits every channel's 64-node chunks into contiguous ranges, blocks per
-// channel in proportion to its work (chunks x orbital tiles).
+// Splits every channel's 64-node chunks into contiguous ranges, nblocks
+// blocks in all (the blocks the device holds at once: one round, no tail),
+// per channel in proportion to its work (chunks x orbital tiles).
 void build_hc_items(const std::vector<std::array<long long, 3>> &chans, std::vector<HcItem> &items,
-                    std::vector<HcChan> &out, long long &elems) {
+                    std::vector<HcChan> &out, long long &elems, int nblocks) {
     items.clear();
     out.clear();
     elems = 0;
@@ -194,7 +192,7 @@ void build_hc_items(const std::vector<std::array<long long, 3>> &chans, std::vec
         const long long chunks = (ch[2] + 63) / 64;
         if (count <= 0 || chunks <= 0) continue;
         const double work = (double)chunks * (double)((count + 15) / 16);
-        long long nb = (long long)std::llround(kHcBlocks * work / std::max(total, 1.0));
+        long long nb = (long long)std::llround(nblocks * work / std::max(total, 1.0));
         nb = std::max(1LL, std::min(nb, chunks));
         const long long tile = (long long)kHcRows * 16 * ((count + 15) / 16);
         HcChan hc{first, count, (int)nb, elems};
@@ -284,6 +282,7 @@ struct fsic_ctx {
     double *h_sd = nullptr;
     size_t h_s_cap = 0;
     DBuf<double> d_stage;
+    DBuf<double> d_chk;  // the host checks' inputs, packed (forward pass)
     std::vector<ProfRec> recs;
     bool pend_prof = false, pend_aar = false, pend_pcg = false, pend_mixed = false;
     bool pend_dst_xy = false;
@@ -524,7 +523,7 @@ struct DstTune {
 };
 
 void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, Batch &b,
-                 const DstTune &dt = DstTune{}) {
+                 const DstTune &dt = DstTune{}, int lmax = 6) {
     const int cpt = sh.cpt;
     b = Batch{};
     long long cols = 0;
@@ -570,16 +569,33 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
         while (bb.dtab.size() % 4) bb.dtab.push_back(0.f);
         return dst_done[n] = {so, go};
     };
+    // harmonic contractions and expansions: one group per run of
+    // consecutive groups on one grid whose fields follow each other (the two
+    // spins of a system), at most kMaxOrb orbitals, so the harmonics of a
+    // node chunk are built once for all of them
     std::vector<std::array<long long, 3>> hcn, hcg;  // (first, count, nodes / ghosts)
+    const Group *hprev = nullptr;
     for (const Group &g : groups) {
         const long long M = (long long)g.n[0] * g.n[1] * g.n[2];
         if (g.count > 0) {
             const int first = (int)b.orb.size();
             const long long G = 2LL * radius * ((long long)g.n[1] * g.n[2] + (long long)g.n[0] * g.n[2] +
                                                 (long long)g.n[0] * g.n[1]);
-            hcn.push_back({first, g.count, M});
-            hcg.push_back({first, g.count, G});
-            b.max_group = std::max(b.max_group, g.count);
+            const bool join = hprev && !hcn.empty() && hprev->n[0] == g.n[0] && hprev->n[1] == g.n[1] &&
+                              hprev->n[2] == g.n[2] && hprev->h == g.h && hprev->origin[0] == g.origin[0] &&
+                              hprev->origin[1] == g.origin[1] && hprev->origin[2] == g.origin[2] &&
+                              hcn.back()[0] + hcn.back()[1] == first &&
+                              hprev->off + (long long)hprev->count * M == g.off &&
+                              hcn.back()[1] + g.count <= kMaxOrb;
+            if (join) {
+                hcn.back()[1] += g.count;
+                hcg.back()[1] += g.count;
+            } else {
+                hcn.push_back({first, g.count, M});
+                hcg.push_back({first, g.count, G});
+            }
+            b.max_group = std::max(b.max_group, (int)hcn.back()[1]);
+            hprev = &g;
         }
         for (int i = 0; i < g.count; ++i) {
             OrbDesc od{};
@@ -648,13 +664,24 @@ void build_batch(const std::vector<Group> &groups, int radius, const Shape &sh, 
     build_items(nat7, b.items7);
     build_items(nat8, b.items8);
     long long en = 0, eg = 0;
-    build_hc_items(hcn, b.hcN, b.hchN, en);
-    build_hc_items(hcg, b.hcG, b.hchG, eg);
+    build_hc_items(hcn, b.hcN, b.hchN, en, harm_slots(0, lmax));
+    // (a ghost chunk's work falls with its depth, and a block takes
+    // consecutive chunks: half again as many blocks as fit at once lets
+    // the dispatcher even out the blocks of shallow and deep layers)
+    build_hc_items(hcg, b.hcG, b.hchG, eg, harm_slots(1, lmax) * 3 / 2);
     b.hc_elems = std::max(en, eg);
-    for (auto *pr : {&b.hcN, &b.hcG}) {
-        std::vector<HcItem> &dst = pr == &b.hcN ? b.hcNx : b.hcGx;
+    // expansions: their own ranges (a block takes at most kHcExpandTiles
+    // orbital tiles), about as many blocks as the device holds at once
+    int tgroups = 1;
+    for (const auto &h : hcn) tgroups = std::max(tgroups, (int)((h[1] + 15) / 16 + kHcExpandTiles - 1) / kHcExpandTiles);
+    for (int kind = 0; kind < 2; ++kind) {
+        std::vector<HcItem> ranges;
+        std::vector<HcChan> rch;
+        long long rel = 0;
+        build_hc_items(kind ? hcn : hcg, ranges, rch, rel, std::max(1, harm_slots(kind ? 3 : 2, lmax) / tgroups));
+        std::vector<HcItem> &dst = kind ? b.hcNx : b.hcGx;
         dst.clear();
-        for (const HcItem &it : *pr)
+        for (const HcItem &it : ranges)
             for (int o0 = 0; o0 < it.ot1; o0 += kHcExpandTiles) {
                 HcItem e = it;
                 e.ot0 = o0;
@@ -1755,7 +1782,7 @@ void fsic_destroy(fsic_ctx *c) {
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
     c->partH.release(); c->d_hcN.release(); c->d_hcG.release(); c->d_hcNx.release(); c->d_hcGx.release(); c->d_hchN.release(); c->d_hchG.release();
     c->bb.release(); c->rrfin.release();
-    c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release(); c->d_stage.release();
+    c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release(); c->d_stage.release(); c->d_chk.release();
     c->done.release(); c->iters.release(); c->rs_iter.release(); c->nact.release(); c->d_orb.release(); c->d_items7.release();
     c->d_items8.release(); c->d_gcount.release(); c->small.release(); c->work.release();
     c->partG.release(); c->d_cells.release(); c->d_chan.release(); c->d_blkchan.release();
@@ -1801,7 +1828,7 @@ static fsic_status boundary_basis(fsic_ctx *c, const Chan &ch, const Shape &sh, 
     for (int d = 0; d < 3; ++d) { g.n[d] = ch.n[d]; g.origin[d] = ch.origin[d]; }
     g.h = ch.h; g.count = nlm; g.off = 0; g.chan = 0;
     Batch bb;
-    build_batch({g}, c->radius, sh, bb, dt);
+    build_batch({g}, c->radius, sh, bb, dt, c->opts.lmax);
     fsic_status st = prepare_batch(c, bb, FSIC_FP64);
     if (st) return st;
     std::vector<double> ident((size_t)nlm * nlm, 0.0);
@@ -1934,7 +1961,7 @@ static fsic_status forward_impl(fsic_ctx *c, int32_t nsys, const fsic_system *sy
         if (use_basis)
             for (int ci = 0; ci < nchan; ++ci)
                 if ((tst = boundary_basis(c, chans[ci], sh, dt, &basisU[ci]))) return tst;
-        build_batch(groups, P, sh, b, dt);
+        build_batch(groups, P, sh, b, dt, o.lmax);
         c->dst_layout = dst_layout_bits(b);
     }
     // channel descriptors for the average pass
@@ -2031,17 +2058,26 @@ static fsic_status forward_impl(fsic_ctx *c, int32_t nsys, const fsic_system *sy
     }
     HIPCHK(c, hipMemcpyAsync(c->h_stat, c->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
     {
+        // packed on the device, one copy
+        HIPCHK(c, c->d_chk.ensure(chk_n));
+        ChkPack pk{};
+        pk.oG = (long long)small_off(sG);
+        pk.oI = (long long)small_off(sINFO);
+        pk.oR = (long long)small_off(sRHOA);
         size_t q = 0;
-        for (const Chan &ch : chans) {
-            const double *sm = c->small.p + ch.so;
-            const size_t NN = (size_t)ch.N * ch.N;
-            HIPCHK(c, hipMemcpyAsync(c->h_chk + q, sm + small_off(sG), NN * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipMemcpyAsync(c->h_chk + q + NN, sm + small_off(sINFO), 2 * sizeof(double),
-                                     hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipMemcpyAsync(c->h_chk + q + NN + 2, sm + small_off(sRHOA), ch.N * sizeof(double),
-                                     hipMemcpyDeviceToHost, s));
-            q += NN + 2 + ch.N;
+        for (size_t ci = 0; ci < chans.size(); ++ci) {
+            const Chan &ch = chans[ci];
+            pk.N[pk.n] = ch.N;
+            pk.so[pk.n] = (long long)ch.so;
+            pk.q[pk.n] = (long long)q;
+            ++pk.n;
+            q += (size_t)ch.N * ch.N + 2 + ch.N;
+            if (pk.n == kChkPack || ci + 1 == chans.size()) {
+                HIPCHK(c, launch_pack_checks(pk, c->small.p, c->d_chk.p, s));
+                pk.n = 0;
+            }
         }
+        HIPCHK(c, hipMemcpyAsync(c->h_chk, c->d_chk.p, chk_n * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     // phi = Q psi on the matrix cores
     for (int ci = 0; ci < nchan; ++ci) {
@@ -2345,7 +2381,7 @@ fsic_status fsic_op_poisson(const fsic_grid *grid, int32_t fd_order, int32_t lma
     c->cf.depth = sh.depth;
     DstTune dt;
     if ((st = choose_dst(c, groups, precision, sh, dt))) return st;
-    build_batch(groups, c->radius, sh, b, dt);
+    build_batch(groups, c->radius, sh, b, dt, lmax);
     st = prepare_batch(c, b, precision);
     if (st) return st;
     SolveReport rep;

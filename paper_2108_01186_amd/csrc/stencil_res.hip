@@ -128,6 +128,22 @@ hipError_t launch_stage_stats(int norb, const int *iters, const int *nact, const
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_pack_checks(ChkPack p, const double *small, double *out) {
+    const int e = blockIdx.x;
+    const int N = p.N[e], NN = N * N;
+    const double *sm = small + p.so[e];
+    double *o = out + p.q[e];
+    for (int i = threadIdx.x; i < NN + 2 + N; i += 256)
+        o[i] = i < NN ? sm[p.oG + i] : (i < NN + 2 ? sm[p.oI + (i - NN)] : sm[p.oR + (i - NN - 2)]);
+}
+
+hipError_t launch_pack_checks(const ChkPack &p, const double *small, double *out, hipStream_t s) {
+    if (p.n <= 0) return hipSuccess;
+    if (p.n > kChkPack) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pack_checks, dim3(p.n), dim3(256), 0, s, p, small, out);
+    return hipGetLastError();
+}
+
 // the final x of each orbital: copied from the second x64 buffer where the
 // restart cycle that converged it (fin[o], or fallback for an unconverged
 // orbital) wrote it there
