@@ -156,6 +156,13 @@ struct ChkPack {
     long long so[kChkPack], q[kChkPack];
 };
 hipError_t launch_pack_checks(const ChkPack &p, const double *small, double *out, hipStream_t s);
+// The end of a mixed solve in one launch: the final x as launch_take_x, then
+// per orbital the final FP64 residual (partRU partials), iters = nact[0..norb)
+// and the statistics stage of launch_stage_stats.
+hipError_t launch_mixed_finish(int nitems8, const Item *items8, const OrbDesc *orb, const int *fin, int fallback,
+                               double *X, const double *Xb, int norb, const double *partRU, const int *nact,
+                               const int *done, const double *bb, int *iters, double *ptrue, double *stage,
+                               hipStream_t s);
 hipError_t launch_stage_stats(int norb, const int *iters, const int *nact, const int *done,
                               const double *ptrue, const double *bb, double *stage, hipStream_t s);
 hipError_t launch_take_x(int nitems8, const Item *items8, const OrbDesc *orb, const int *fin, int fallback,

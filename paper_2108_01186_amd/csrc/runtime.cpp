@@ -1174,6 +1174,7 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     const int nlm = (c->opts.lmax + 1) * (c->opts.lmax + 1);
     const int nit7 = (int)b.items7.size(), nit8 = (int)b.items8.size();
     const bool mixed = precision == FSIC_MIXED;
+    bool staged = false;  // statistics staged by the solve's own last launch
     if (with_bc) {
         // boundary values from the moments of the source, or (qlm_in) from
         // given moments (the unit-moment basis solves, src null)
@@ -1505,13 +1506,16 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
         // there; an unconverged orbital's latest x is where the last cycle
         // that ran wrote it (cycle j writes buffer (j + 1) & 1; cycles up to
         // `issued` - 1 ran)
-        HIPCHK(c, launch_take_x(nit8, c->d_items8.p, c->d_orb.p, c->fin.p, (issued & 1) ? 1 : 0, X,
-                                c->X64b.p, s));
-        // iterations that did work per orbital (the restart cycles report no index)
-        HIPCHK(c, hipMemcpyAsync(c->iters.p, c->nact.p, norb * sizeof(int), hipMemcpyDeviceToDevice, s));
-        // final FP64 residual: the residual pass of the cycle that produced each
-        // orbital's x left its partial sums in partRU (later cycles skip it)
-        HIPCHK(c, launch_reduce_partials(norb, c->d_orb.p, c->partRU.p, 1, c->ptrue.p, s));
+        // ... in one launch with the per-orbital end: iterations that did
+        // work (the restart cycles report no index), the final FP64 residual
+        // (the residual pass of the cycle that produced each orbital's x left
+        // its partial sums in partRU; later cycles skip it) and the
+        // statistics stage
+        HIPCHK(c, c->d_stage.ensure(6 * (size_t)std::max(norb, 1)));
+        HIPCHK(c, launch_mixed_finish(nit8, c->d_items8.p, c->d_orb.p, c->fin.p, (issued & 1) ? 1 : 0, X,
+                                      c->X64b.p, norb, c->partRU.p, c->nact.p, c->done.p, c->bb.p, c->iters.p,
+                                      c->ptrue.p, c->d_stage.p, s));
+        staged = true;
     } else if (!mixed) {
         CGIter<double> a{};
         a.items7 = c->d_items7.p; a.nitems7 = nit7;
@@ -1600,7 +1604,8 @@ fsic_status solve_batch(fsic_ctx *c, const Batch &b, const double *src, int squa
     }
     // statistics: copied now, read by finish_solve after the caller's sync
     HIPCHK(c, c->d_stage.ensure(6 * (size_t)std::max(norb, 1)));
-    HIPCHK(c, launch_stage_stats(norb, c->iters.p, c->nact.p, c->done.p, c->ptrue.p, c->bb.p, c->d_stage.p, s));
+    if (!staged)
+        HIPCHK(c, launch_stage_stats(norb, c->iters.p, c->nact.p, c->done.p, c->ptrue.p, c->bb.p, c->d_stage.p, s));
     HIPCHK(c, hipMemcpyAsync(c->h_stage, c->d_stage.p, 6 * (size_t)norb * sizeof(double), hipMemcpyDeviceToHost, s));
     c->h_si = reinterpret_cast<int *>(c->h_stage);
     c->h_sd = c->h_stage + 4 * (size_t)norb;

@@ -170,6 +170,57 @@ hipError_t launch_take_x(int nitems8, const Item *items8, const OrbDesc *orb, co
     return hipGetLastError();
 }
 
+// end of a mixed solve in one launch: blocks [0, nitems8) move the final x
+// as k_take_x; block nitems8 + o finishes orbital o: its FP64 residual from
+// the residual pass's partials (as k_reduce_partials), iters = the
+// iterations that did work, and its statistics staged as k_stage_stats
+__global__ __launch_bounds__(256) void k_mixed_finish(int nitems8, const Item *items8, const OrbDesc *orb,
+                                                      const int *fin, int fallback, double *X, const double *Xb,
+                                                      int norb, const double *partRU, const int *nact,
+                                                      const int *done, const double *bb, int *iters,
+                                                      double *ptrue, double *stage) {
+    __shared__ double sred[4];
+    if ((int)blockIdx.x < nitems8) {
+        const Item it = items8[blockIdx.x];
+        if (it.orb < 0) return;
+        const int f = fin[it.orb];
+        if ((f >= 0 ? f : fallback) != 1) return;
+        const OrbDesc od = orb[it.orb];
+        const long long M = (long long)od.nx * od.ny * od.nz;
+        const long long base = (long long)it.tile * kPW;
+#pragma unroll
+        for (int e = 0; e < kPW / 256; ++e) {
+            const long long i = base + e * 256 + threadIdx.x;
+            if (i < M) X[od.off + i] = Xb[od.off + i];
+        }
+        return;
+    }
+    const int o = (int)blockIdx.x - nitems8;
+    const OrbDesc od = orb[o];
+    const double rr = sum_partials(partRU + od.base7, od.nt7, sred);
+    if (threadIdx.x == 0) {
+        ptrue[o] = rr;
+        iters[o] = nact[o];
+        int *si = reinterpret_cast<int *>(stage);
+        double *sd = stage + 4 * (size_t)norb;
+        si[o] = nact[o];
+        for (int q = 0; q < 6; ++q) si[norb + q * norb + o] = nact[q * norb + o];
+        si[7 * norb + o] = done[o];
+        sd[o] = rr;
+        sd[norb + o] = bb[o];
+    }
+}
+
+hipError_t launch_mixed_finish(int nitems8, const Item *items8, const OrbDesc *orb, const int *fin, int fallback,
+                               double *X, const double *Xb, int norb, const double *partRU, const int *nact,
+                               const int *done, const double *bb, int *iters, double *ptrue, double *stage,
+                               hipStream_t s) {
+    if (nitems8 < 0 || norb <= 0) return norb == 0 ? hipSuccess : hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mixed_finish, dim3((unsigned)(nitems8 + norb)), dim3(256), 0, s, nitems8, items8, orb,
+                       fin, fallback, X, Xb, norb, partRU, nact, done, bb, iters, ptrue, stage);
+    return hipGetLastError();
+}
+
 hipError_t launch_res_steps(int radius, const Coeffs &c, const CGIter<float> &a, const ResStep &rs,
                             hipStream_t s) {
     if (a.nitems7 <= 0) return hipSuccess;
