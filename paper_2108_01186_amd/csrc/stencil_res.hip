@@ -224,14 +224,26 @@ hipError_t launch_mixed_finish(int nitems8, const Item *items8, const OrbDesc *o
 hipError_t launch_res_steps(int radius, const Coeffs &c, const CGIter<float> &a, const ResStep &rs,
                             hipStream_t s) {
     if (a.nitems7 <= 0) return hipSuccess;
-    if (rs.X32) {
+    // x64 absent in the first cycle (x starts at 0), x32 only in cycles of
+    // more than two iterations
+    if (rs.X32 && rs.X64) {
         PolResP<true> pol{a.items7, a.orb, a, rs, false, 0.0, 0.0};
 #define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolResP<true>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
         FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
-    } else {
+    } else if (rs.X32) {
+        PolResP<true, false> pol{a.items7, a.orb, a, rs, false, 0.0, 0.0};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolResP<true, false>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
+        FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
+    } else if (rs.X64) {
         PolResP<false> pol{a.items7, a.orb, a, rs, false, 0.0, 0.0};
 #define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolResP<false>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
+        FSIC_RADIUS_SWITCH(radius, CALL)
+#undef CALL
+    } else {
+        PolResP<false, false> pol{a.items7, a.orb, a, rs, false, 0.0, 0.0};
+#define CALL(P, C, DD) hipLaunchKernelGGL((k_zmarch<double, P, C, DD, PolResP<false, false>>), dim3(a.nitems7), dim3(256), 0, s, pol, c)
         FSIC_RADIUS_SWITCH(radius, CALL)
 #undef CALL
     }

@@ -501,7 +501,9 @@ __device__ __forceinline__ double alpha_of(const CGIter<float> &a, const OrbDesc
 }
 
 // end of a mixed restart cycle: res = b + L x, x = x64 + x32 + alpha_a p_a + alpha_b p_b
-template <bool HAS32>  // x32 present (cycles of more than two iterations)
+// HAS32: x32 present (cycles of more than two iterations); HAS64: x64
+// present (every cycle but the first, which starts from x = 0)
+template <bool HAS32, bool HAS64 = true>
 struct PolResP {
     const Item *items;
     const OrbDesc *orb;
@@ -524,7 +526,7 @@ struct PolResP {
     }
     __device__ void init(const OrbDesc &od) {
         const long long M = (long long)od.nx * od.ny * od.nz;
-        if (r.X64) rx = make_rsrc(r.X64 + od.off, (unsigned)(M * 8));
+        if (HAS64) rx = make_rsrc(r.X64 + od.off, (unsigned)(M * 8));
         if (HAS32) rx32 = make_rsrc(r.X32 + od.off, (unsigned)(M * 4));
         rpa = make_rsrc(r.Pa + od.off, (unsigned)(M * 4));
         rpb = make_rsrc(r.Pb + od.off, (unsigned)(M * 4));
@@ -533,7 +535,7 @@ struct PolResP {
         rr32 = make_rsrc(r.R32 + od.off, (unsigned)(M * 4));
     }
     __device__ Raw raw(unsigned i, int zo) const {
-        return Raw{r.X64 ? bld<double>(rx, i, zo) : 0.0, HAS32 ? bld<float>(rx32, i, zo) : 0.0f,
+        return Raw{HAS64 ? bld<double>(rx, i, zo) : 0.0, HAS32 ? bld<float>(rx32, i, zo) : 0.0f,
                    bld<float>(rpa, i, zo), bld<float>(rpb, i, zo)};
     }
     __device__ Ext ext(unsigned i, int zo) const { return bld<double>(rb, i, zo); }

@@ -305,3 +305,50 @@ def test_forward_backward_in_one_call(torch_cuda, F, mol40_dev):
     with pytest.raises(F.FsicError):
         cn.forward_backward([F.system_dict(mol40_dev)])
     cn.close()
+
+
+_LONG_CYCLES = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2108_01186_amd import fsic as F, synth
+s = synth.make_workload("mol40")
+s.psi = [torch.as_tensor(np.asarray(p), device="cuda").contiguous() for p in s.psi]
+d = F.system_dict(s)
+ctx = F.Context(precision="mixed", tol=1e-11, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE)
+e, U, X, g, stf, stb = ctx.forward_backward([d])
+np.savez(sys.argv[2], e=e, g=np.concatenate(g[0]), v=d["vsic"][0].cpu().numpy(),
+         cycles=stf["outer_refinements"], iters=stf["total_iters"])
+ctx.close()
+print("long cycles done", flush=True)
+"""
+
+
+def test_three_iteration_restart_cycles(torch_cuda, F, mol40_dev, tmp_path):
+    """Restart cycles of three iterations (the schedule read from
+    FSIC_PCG_FIRST and FSIC_PCG_CHUNK once per process, so in a child
+    process) carry an FP32 x accumulator into the residual pass, in the
+    first cycle without an x64 operand and later with one; E_SIC, V_SIC and
+    the FOD gradient agree with the default two-iteration cycles to within
+    the solve tolerance."""
+    import os
+    import subprocess
+    import sys
+    _say("three-iteration restart cycles, mol40 (child process)")
+    d = F.system_dict(mol40_dev)
+    ctx = F.Context(precision="mixed", tol=1e-11, flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE)
+    e, U, X, g, stf, _ = ctx.forward_backward([d])
+    v = d["vsic"][0].cpu().numpy().copy()
+    ctx.close()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = str(tmp_path / "long_cycles.npz")
+    env = dict(os.environ, FSIC_PCG_FIRST="3", FSIC_PCG_CHUNK="3")
+    r = subprocess.run([sys.executable, "-c", _LONG_CYCLES, root, out], env=env, timeout=300,
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    z = np.load(out)
+    assert int(z["cycles"]) > 0
+    assert abs(float(z["e"][0]) - float(e[0])) < 1e-10
+    assert np.abs(z["v"] - v).max() < 1e-9 * max(1.0, np.abs(v).max())
+    assert np.abs(z["g"] - np.concatenate(g[0])).max() < 1e-9
