@@ -135,16 +135,15 @@ struct ResStep {
 hipError_t launch_res_steps(int radius, const Coeffs &c, const CGIter<float> &a, const ResStep &rs,
                             hipStream_t s);
 
-// Final x of the mixed restart cycles: X[o] = Xb[o] for the orbitals whose
-// result is in the second buffer (fin[o] == 1, or fallback == 1 where
-// fin[o] < 0: not converged).
 // v_o = w_o + sum_q Q[first + o][q] U_q (q < (lmax + 1)^2) for N
-// consecutive orbitals on one grid: U holds the grid's unit-moment boundary
-// solutions (q-major, M nodes each); W and V point at the first orbital
-hipError_t launch_bc_combine(int N, long long M, int lmax, const double *Q, int first, const double *U,
+// consecutive orbitals on one grid of n[0] x n[1] x n[2] nodes: U holds the
+// first octant of the grid's unit-moment boundary solutions (q-major,
+// ceil(n/2) per axis, x fastest; the rest follows from their parities under
+// the axis reflections); W and V point at the first orbital
+hipError_t launch_bc_combine(int N, const int *n, int lmax, const double *Q, int first, const double *U,
                              const double *W, double *V, hipStream_t s);
-// the statistics of a solve gathered for one transfer: stage holds 8 norb
-// ints (iters, nact[6 norb], done) and then 2 norb doubles (ptrue, bb)
+// Uc = the first octant of nlm full-grid fields U (the layout launch_bc_combine reads)
+hipError_t launch_octant_pack(int nlm, const int *n, const double *U, double *Uc, hipStream_t s);
 // The host checks' inputs of up to kChkPack channels, packed one after the
 // other for one copy to the host: channel e's G (N x N), info (2) and
 // rho(a) (N) from small + so[e] (+ oG, oI, oR) to out + q[e].
@@ -163,8 +162,13 @@ hipError_t launch_mixed_finish(int nitems8, const Item *items8, const OrbDesc *o
                                double *X, const double *Xb, int norb, const double *partRU, const int *nact,
                                const int *done, const double *bb, int *iters, double *ptrue, double *stage,
                                hipStream_t s);
+// the statistics of a solve gathered for one transfer: stage holds 8 norb
+// ints (iters, nact[6 norb], done) and then 2 norb doubles (ptrue, bb)
 hipError_t launch_stage_stats(int norb, const int *iters, const int *nact, const int *done,
                               const double *ptrue, const double *bb, double *stage, hipStream_t s);
+// Final x of the mixed restart cycles: X[o] = Xb[o] for the orbitals whose
+// result is in the second buffer (fin[o] == 1, or fallback == 1 where
+// fin[o] < 0: not converged).
 hipError_t launch_take_x(int nitems8, const Item *items8, const OrbDesc *orb, const int *fin, int fallback,
                          double *X, const double *Xb, hipStream_t s);
 

@@ -655,49 +655,96 @@ hipError_t launch_bterm(int radius, const Coeffs &c, int norb, const OrbDesc *or
 // 32 orbitals): each thread one node, the group's moment rows in LDS, so U is
 // read once per node for up to 32 orbitals.
 constexpr int kBcGroup = 32;
-__global__ __launch_bounds__(256) void k_bc_combine(int N, long long M, int nlm, const double *Q, int first,
-                                                    const double *__restrict__ U, const double *__restrict__ W,
-                                                    double *__restrict__ V) {
+// The grid is symmetric about the expansion centre (the box centre) and the
+// discrete operator, the boundary term and each solid harmonic keep or flip
+// sign under the reflection of an axis, so each unit-moment solution U_q
+// does too: only its first octant (i < ceil(nx/2), likewise j, k) is kept.
+// Parity bits of harmonic q = l^2 + l + mq (mq >= 0: Re (x + iy)^m, mq < 0:
+// Im (x + iy)^m, m = |mq|, times a polynomial in z and r^2 of z-parity l - m):
+// bit 0 odd in x, bit 1 odd in y, bit 2 odd in z.
+__device__ __forceinline__ unsigned harm_parity(int q) {
+    int l = 0;
+    while ((l + 1) * (l + 1) <= q) ++l;
+    const int mq = q - l * l - l, m = mq < 0 ? -mq : mq;
+    const unsigned px = mq >= 0 ? (unsigned)(m & 1) : (unsigned)((m + 1) & 1);
+    const unsigned py = mq >= 0 ? 0u : 1u;
+    const unsigned pz = (unsigned)((l + m) & 1);
+    return px | (py << 1) | (pz << 2);
+}
+
+// Uc[q][octant node] = U[q][the same node of the full grid]
+__global__ __launch_bounds__(256) void k_octant_pack(int nlm, int nx, int ny, int nz, const double *U, double *Uc) {
+    const int hx = (nx + 1) / 2, hy = (ny + 1) / 2, hz = (nz + 1) / 2;
+    const long long Mo = (long long)hx * hy * hz, M = (long long)nx * ny * nz;
+    const long long n = (long long)nlm * Mo;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        const long long q = e / Mo, o = e - q * Mo;
+        const int i = (int)(o % hx), j = (int)((o / hx) % hy), k = (int)(o / ((long long)hx * hy));
+        Uc[e] = U[q * M + ((long long)k * ny + j) * nx + i];
+    }
+}
+
+hipError_t launch_octant_pack(int nlm, const int *n, const double *U, double *Uc, hipStream_t s) {
+    if (nlm < 1 || nlm > kMaxLM || n[0] < 1 || n[1] < 1 || n[2] < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_octant_pack, dim3(1024), dim3(256), 0, s, nlm, n[0], n[1], n[2], U, Uc);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_bc_combine(int N, int nx, int ny, int nz, int nlm, const double *Q,
+                                                    int first, const double *__restrict__ U,
+                                                    const double *__restrict__ W, double *__restrict__ V) {
     __shared__ double Qs[kMaxLM * kBcGroup];  // [q][j]: one broadcast row per q
+    __shared__ unsigned char par[kMaxLM];
     const int o0 = kBcGroup * blockIdx.y;
     const int no = min(kBcGroup, N - o0);
     for (int e = threadIdx.x; e < kBcGroup * nlm; e += 256) {
         const int q = e / kBcGroup, j = e - q * kBcGroup;
         Qs[e] = j < no ? Q[(size_t)(first + o0 + j) * nlm + q] : 0.0;
     }
+    for (int q = threadIdx.x; q < nlm; q += 256) par[q] = (unsigned char)harm_parity(q);
     __syncthreads();
+    const long long M = (long long)nx * ny * nz;
     const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
     if (m >= M) return;
+    // the node's octant image and which axes it mirrors
+    const int i = (int)(m % nx), j = (int)((m / nx) % ny), k = (int)(m / ((long long)nx * ny));
+    const int hx = (nx + 1) / 2, hy = (ny + 1) / 2, hz = (nz + 1) / 2;
+    const int mi = min(i, nx - 1 - i), mj = min(j, ny - 1 - j), mk = min(k, nz - 1 - k);
+    const unsigned flip = (i != mi ? 1u : 0u) | (j != mj ? 2u : 0u) | (k != mk ? 4u : 0u);
+    const long long Mo = (long long)hx * hy * hz;
+    const long long mo = ((long long)mk * hy + mj) * hx + mi;
     double acc[kBcGroup];
 #pragma unroll
-    for (int j = 0; j < kBcGroup; ++j) acc[j] = 0.0;
+    for (int jj = 0; jj < kBcGroup; ++jj) acc[jj] = 0.0;
     // eight basis values in flight, then their products
     for (int q0 = 0; q0 < nlm; q0 += 8) {
         double u[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) u[k] = q0 + k < nlm ? U[(size_t)(q0 + k) * M + m] : 0.0;
+        for (int kk = 0; kk < 8; ++kk) u[kk] = q0 + kk < nlm ? U[(size_t)(q0 + kk) * Mo + mo] : 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (q0 + k >= nlm) break;
-            const double *qr = Qs + (q0 + k) * kBcGroup;
+        for (int kk = 0; kk < 8; ++kk) {
+            if (q0 + kk >= nlm) break;
+            const double uk = (__builtin_popcount(flip & par[q0 + kk]) & 1) ? -u[kk] : u[kk];
+            const double *qr = Qs + (q0 + kk) * kBcGroup;
 #pragma unroll
-            for (int j = 0; j < kBcGroup; ++j) acc[j] += qr[j] * u[k];
+            for (int jj = 0; jj < kBcGroup; ++jj) acc[jj] += qr[jj] * uk;
         }
     }
 #pragma unroll
-    for (int j = 0; j < kBcGroup; ++j)
-        if (j < no) {
-            const size_t a = (size_t)(o0 + j) * M + m;
-            V[a] = W[a] + acc[j];
+    for (int jj = 0; jj < kBcGroup; ++jj)
+        if (jj < no) {
+            const size_t a = (size_t)(o0 + jj) * M + m;
+            V[a] = W[a] + acc[jj];
         }
 }
 
-hipError_t launch_bc_combine(int N, long long M, int lmax, const double *Q, int first, const double *U,
+hipError_t launch_bc_combine(int N, const int *n, int lmax, const double *Q, int first, const double *U,
                              const double *W, double *V, hipStream_t s) {
-    if (N < 1 || M < 1 || lmax < 0 || lmax > kMaxL) return hipErrorInvalidValue;
+    if (N < 1 || n[0] < 1 || n[1] < 1 || n[2] < 1 || lmax < 0 || lmax > kMaxL) return hipErrorInvalidValue;
+    const long long M = (long long)n[0] * n[1] * n[2];
     const int nlm = (lmax + 1) * (lmax + 1);
     const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + kBcGroup - 1) / kBcGroup));
-    hipLaunchKernelGGL(k_bc_combine, grid, dim3(256), 0, s, N, M, nlm, Q, first, U, W, V);
+    hipLaunchKernelGGL(k_bc_combine, grid, dim3(256), 0, s, N, n[0], n[1], n[2], nlm, Q, first, U, W, V);
     return hipGetLastError();
 }
 

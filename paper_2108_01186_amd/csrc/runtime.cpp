@@ -1852,10 +1852,21 @@ static fsic_status boundary_basis(fsic_ctx *c, const Chan &ch, const Shape &sh, 
         Ub.release();
         return st;
     }
+    // kept: the first octant (the solutions' reflection parities give the rest)
+    DBuf<double> Uc;
+    const size_t Mo = (size_t)((ch.n[0] + 1) / 2) * ((ch.n[1] + 1) / 2) * ((ch.n[2] + 1) / 2);
+    hipError_t he = Uc.ensure((size_t)nlm * Mo);
+    if (he == hipSuccess) he = launch_octant_pack(nlm, ch.n, Ub.p, Uc.p, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    Ub.release();
+    if (he != hipSuccess) {
+        Uc.release();
+        return set_err(c, FSIC_EHIP, hipGetErrorString(he));
+    }
     c->basis_solves += nlm;
     c->basis_ms += now_ms() - t0;
     DBuf<double> &slot = c->bbasis[key];
-    std::swap(slot, Ub);
+    std::swap(slot, Uc);
     *U = slot.p;
     return FSIC_OK;
 }
@@ -2117,7 +2128,7 @@ static fsic_status forward_impl(fsic_ctx *c, int32_t nsys, const fsic_system *sy
                 n += chans[cj].N;
                 ++cj;
             }
-            HIPCHK(c, launch_bc_combine(n, ch.M, o.lmax, c->Qlm.p, ch.first_orb, basisU[ci], c->W.p + ch.off,
+            HIPCHK(c, launch_bc_combine(n, ch.n, o.lmax, c->Qlm.p, ch.first_orb, basisU[ci], c->W.p + ch.off,
                                         c->V.p + ch.off, s));
             ci = cj;
         }

@@ -352,3 +352,34 @@ def test_three_iteration_restart_cycles(torch_cuda, F, mol40_dev, tmp_path):
     assert abs(float(z["e"][0]) - float(e[0])) < 1e-10
     assert np.abs(z["v"] - v).max() < 1e-9 * max(1.0, np.abs(v).max())
     assert np.abs(z["g"] - np.concatenate(g[0])).max() < 1e-9
+
+
+def test_boundary_basis_on_odd_box(torch_cuda, F, mol40):
+    """The basis keeps one octant of each unit-moment solution and takes the
+    rest from its reflection parities.  On a box of odd, unequal sides
+    (39 x 37 x 35 nodes: centre planes on every axis, three octant extents)
+    energies, V_SIC and forces agree with the direct multipole-boundary
+    solves to within the solve tolerance."""
+    torch = torch_cuda
+    _say("boundary basis vs direct on a 39 x 37 x 35 box")
+    nx, ny, nz = 39, 37, 35
+    psi = np.asarray(mol40.psi[0]).reshape(-1, 40, 40, 40)[:, :nz, :ny, :nx]
+    psi_d = torch.as_tensor(np.ascontiguousarray(psi).reshape(psi.shape[0], -1), device="cuda")
+    fod = np.asarray(mol40.fod[0])
+
+    def run(extra):
+        d = {"n": (nx, ny, nz), "h": mol40.h, "origin": mol40.origin, "psi": [psi_d], "fod": [fod],
+             "vsic": [torch.empty(nx * ny * nz, dtype=torch.float64, device="cuda")]}
+        ctx = F.Context(precision="mixed", tol=1e-11,
+                        flags=F.FSIC_WANT_VSIC | F.FSIC_KEEP_TAPE | F.FSIC_ALLOW_NONORTHO | extra)
+        e, U, X, g, stf, stb = ctx.forward_backward([d])
+        ctx.close()
+        return e, U, X, np.concatenate(g[0]), d["vsic"][0].cpu().numpy(), stf
+
+    ea, Ua, Xa, ga, va, sta = run(0)
+    eb, Ub, Xb, gb, vb, stb = run(F.FSIC_DIRECT_BC)
+    assert sta["basis_solves"] == 49 and stb["basis_solves"] == 0
+    assert abs(float(ea[0]) - float(eb[0])) < 1e-10
+    assert np.abs(Ua - Ub).max() < 1e-10 and np.abs(Xa - Xb).max() < 1e-11
+    assert np.abs(va - vb).max() < 1e-9 * max(1.0, np.abs(vb).max())
+    assert np.abs(ga - gb).max() < 1e-9, np.abs(ga - gb).max()
