@@ -167,11 +167,11 @@ __device__ void nn_gemm(int N, const double *A, int ta, const double *B, int tb,
 //            K_jk = -1 / (sqrt(l_j) sqrt(l_k) (sqrt(l_j) + sqrt(l_k)))
 //   Gam_u_i = (Gam_T_i - (Gam_T_i . T_i) T_i) / |u_i|
 //   dE/da_i = sum_a Gam_u_i,a grad psi_a(a_i)
-__global__ __launch_bounds__(256) void k_lowdin_backward(int N, const double *Bm, const double *T,
-                                                         const double *G, const double *lam,
-                                                         const double *U, const double *Z,
-                                                         const double *rhoa, const double *du,
-                                                         double *work, double *dEda) {
+__device__ __forceinline__ void lowdin_backward_one(int N, const double *Bm, const double *T,
+                                                       const double *G, const double *lam,
+                                                       const double *U, const double *Z,
+                                                       const double *rhoa, const double *du,
+                                                       double *work, double *dEda) {
     const size_t NN = (size_t)N * N;
     double *GT = work;            // Gam_T
     double *T1 = work + NN;
@@ -228,9 +228,35 @@ __global__ __launch_bounds__(256) void k_lowdin_backward(int N, const double *Bm
     }
 }
 
+// the reverse Loewdin step of up to kLowdinBatch channels in one launch, one
+// workgroup each: channel b's B at Bm + b N_max^2 stride, its small arrays at
+// small + so[b], scratch at work + b wstride; dE/da to its small block and to
+// packed + go[b] (all channels' gradients in one block for one copy)
+__global__ __launch_bounds__(256) void k_lowdin_backward_batch(LowdinBwdBatch lb, const double *Bm, long long bstride,
+                                                               double *small, LowdinBwdOffsets off, double *work,
+                                                               long long wstride, double *packed) {
+    const int b = blockIdx.x;
+    const int N = lb.N[b];
+    double *sm = small + lb.so[b];
+    double *dEda = sm + off.dEda;
+    lowdin_backward_one(N, Bm + (size_t)b * bstride, sm + off.T, sm + off.G, sm + off.lam, sm + off.U,
+                           sm + off.Z, sm + off.rhoa, sm + off.du, work + (size_t)b * wstride, dEda);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) packed[lb.go[b] + e] = dEda[e];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_lowdin_backward_batch(const LowdinBwdBatch &lb, const double *Bm, long long bstride, double *small,
+                                        const LowdinBwdOffsets &off, double *work, long long wstride, double *packed,
+                                        hipStream_t s) {
+    if (lb.n <= 0 || lb.n > kLowdinBatch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lowdin_backward_batch, dim3(lb.n), dim3(256), 0, s, lb, Bm, bstride, small, off, work,
+                       wstride, packed);
+    return hipGetLastError();
+}
 
 hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *PHI, const double *V,
                                     const double *W, const double *psi, double floor, double *partB,
@@ -259,15 +285,6 @@ hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *
     if (lds > 65536) hipFuncSetAttribute((const void *)k_tsg_nt<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_tsg_nt<false>, dim3(nblk), dim3(256), lds, s, N, M, chunk, Gam, psi, partB);
     hipLaunchKernelGGL(k_adj_contract_final, dim3(N * N), dim3(256), 0, s, N, nblk, partB, Bm);
-    return hipGetLastError();
-}
-
-hipError_t launch_lowdin_backward(int N, const double *Bm, const double *T, const double *G,
-                                  const double *lam, const double *U, const double *Z,
-                                  const double *rhoa, const double *du, double *work,
-                                  double *dEda, hipStream_t s) {
-    hipLaunchKernelGGL(k_lowdin_backward, dim3(1), dim3(256), 0, s, N, Bm, T, G, lam, U, Z, rhoa, du,
-                       work, dEda);
     return hipGetLastError();
 }
 

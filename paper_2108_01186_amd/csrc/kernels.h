@@ -432,11 +432,21 @@ hipError_t launch_adjoint_contract(int N, long long M, double dV, const double *
 
 // reverse mode through Q = S^{-1/2} T, S = T G T^T, T = u/|u|, u = psi(a):
 // dEda[i][d] = gscale * sum_a Gam_u[i][a] dpsi_a(a_i)/da_d
-hipError_t launch_lowdin_backward(int N, const double *Bm, const double *T, const double *G,
-                                  const double *lam, const double *U, const double *Z,
-                                  const double *rhoa, const double *du, double *work,
-                                  double *dEda, hipStream_t s);
-
+// the reverse Loewdin step of up to kLowdinBatch channels, one workgroup
+// each (channel b: N[b] orbitals, small arrays at small + so[b] plus the
+// offsets, B at Bm + b bstride, scratch of wstride >= 4 N^2 doubles at
+// work + b wstride); dE/da also to packed + go[b]
+struct LowdinBwdBatch {
+    int n;
+    int N[kLowdinBatch];
+    long long so[kLowdinBatch], go[kLowdinBatch];
+};
+struct LowdinBwdOffsets {
+    long long T, G, lam, U, Z, rhoa, du, dEda;
+};
+hipError_t launch_lowdin_backward_batch(const LowdinBwdBatch &lb, const double *Bm, long long bstride, double *small,
+                                        const LowdinBwdOffsets &off, double *work, long long wstride, double *packed,
+                                        hipStream_t s);
 // ----------------------------------------------------------------------------
 // noalloc.hip: the Fermi-Loewdin step on a file-scope scratch array
 // ----------------------------------------------------------------------------

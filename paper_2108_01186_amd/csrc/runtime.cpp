@@ -283,6 +283,7 @@ struct fsic_ctx {
     size_t h_s_cap = 0;
     DBuf<double> d_stage;
     DBuf<double> d_chk;  // the host checks' inputs, packed (forward pass)
+    DBuf<double> d_grad;  // dE/da of every channel, packed (backward pass)
     std::vector<ProfRec> recs;
     bool pend_prof = false, pend_aar = false, pend_pcg = false, pend_mixed = false;
     bool pend_dst_xy = false;
@@ -1787,7 +1788,7 @@ void fsic_destroy(fsic_ctx *c) {
     c->Gh.release(); c->part7.release(); c->part8.release(); c->partRU.release();
     c->partH.release(); c->d_hcN.release(); c->d_hcG.release(); c->d_hcNx.release(); c->d_hcGx.release(); c->d_hchN.release(); c->d_hchG.release();
     c->bb.release(); c->rrfin.release();
-    c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release(); c->d_stage.release(); c->d_chk.release();
+    c->relres.release(); c->Qlm.release(); c->Zt.release(); c->ptrue.release(); c->d_stage.release(); c->d_chk.release(); c->d_grad.release();
     c->done.release(); c->iters.release(); c->rs_iter.release(); c->nact.release(); c->d_orb.release(); c->d_items7.release();
     c->d_items8.release(); c->d_gcount.release(); c->small.release(); c->work.release();
     c->partG.release(); c->d_cells.release(); c->d_chan.release(); c->d_blkchan.release();
@@ -2005,8 +2006,8 @@ static fsic_status forward_impl(fsic_ctx *c, int32_t nsys, const fsic_system *sy
     if (pst) return pst;
     HIPCHK(c, c->small.ensure((size_t)nchan * kSmallStride));
     const long long lw = 3LL * kMaxOrb * kMaxOrb;  // Loewdin scratch per channel of a batched launch
-    HIPCHK(c, c->work.ensure(std::max<size_t>(4 * (size_t)kMaxOrb * kMaxOrb,
-                                              (size_t)std::min(nchan, kLowdinBatch) * (size_t)lw)));
+    // (sized for the backward pass's 4 kMaxOrb^2 per channel, so it does not grow then)
+    HIPCHK(c, c->work.ensure((size_t)std::min(nchan, kLowdinBatch) * 4 * (size_t)kMaxOrb * kMaxOrb));
     const int gram_blk = 1024;  // partial tiles of the orbital GEMMs: up to four blocks per compute unit
     c->sweep_launches = c->update_launches = c->precond_launches = 0;
     c->sweep_ms = c->sweep_bytes = c->update_ms = c->update_bytes = 0.0;
@@ -2589,7 +2590,6 @@ static fsic_status backward_enqueue(fsic_ctx *c, bool fused, BwdState &bs) {
         fsic_status pst = prepare_batch(c, b, o.precision);
         if (pst) return pst;
     }
-    HIPCHK(c, c->bmat.ensure((size_t)kMaxOrb * kMaxOrb));
     SolveReport &rep = bs.rep;
     rep = SolveReport{};
     rep.converged = true;
@@ -2638,21 +2638,35 @@ static fsic_status backward_enqueue(fsic_ctx *c, bool fused, BwdState &bs) {
         HIPCHK(c, hipHostMalloc((void **)&c->h_grad, std::max<size_t>(goff.back(), 1) * sizeof(double)));
         c->h_grad_cap = goff.back();
     }
-    for (size_t ci = 0; ci < c->chans.size(); ++ci) {
-        const Chan &ch = c->chans[ci];
-        double *sm = c->small.p + ch.so;
-        const double dV = ch.h * ch.h * ch.h;
-        // Gam overwrites W (the adjoint field is not needed after it)
-        HIPCHK(c, launch_adjoint_contract(ch.N, ch.M, dV, c->PHI.p + ch.off, c->V.p + ch.off,
-                                          Wt + ch.off, ch.psi, o.rho_floor, c->partG.p, c->partG.cap,
-                                          c->bmat.p, c->W.p + ch.off, s));
-        HIPCHK(c, launch_lowdin_backward(ch.N, c->bmat.p, sm + small_off(sT), sm + small_off(sG),
-                                         sm + small_off(sLAM), sm + small_off(sEV), sm + small_off(sZ),
-                                         sm + small_off(sRHOA), sm + small_off(sDU), c->work.p,
-                                         sm + small_off(sDEDA), s));
-        HIPCHK(c, hipMemcpyAsync(c->h_grad + goff[ci], sm + small_off(sDEDA), 3 * ch.N * sizeof(double),
-                                 hipMemcpyDeviceToHost, s));
+    // per channel B = Gam psi^T into its own block of bmat, then the reverse
+    // Loewdin steps of up to kLowdinBatch channels in one launch, which also
+    // packs every dE/da for one copy
+    const int nch = (int)c->chans.size();
+    const long long bstride = (long long)kMaxOrb * kMaxOrb, wstride = 4LL * kMaxOrb * kMaxOrb;
+    HIPCHK(c, c->bmat.ensure((size_t)bstride * std::min(nch, kLowdinBatch)));
+    HIPCHK(c, c->work.ensure((size_t)wstride * std::min(nch, kLowdinBatch)));
+    HIPCHK(c, c->d_grad.ensure(std::max<size_t>(goff.back(), 1)));
+    const LowdinBwdOffsets lo{(long long)small_off(sT),   (long long)small_off(sG),   (long long)small_off(sLAM),
+                              (long long)small_off(sEV),  (long long)small_off(sZ),   (long long)small_off(sRHOA),
+                              (long long)small_off(sDU),  (long long)small_off(sDEDA)};
+    for (int c0 = 0; c0 < nch; c0 += kLowdinBatch) {
+        LowdinBwdBatch lb{};
+        lb.n = std::min(kLowdinBatch, nch - c0);
+        for (int q = 0; q < lb.n; ++q) {
+            const Chan &ch = c->chans[c0 + q];
+            const double dV = ch.h * ch.h * ch.h;
+            // Gam overwrites W (the adjoint field is not needed after it)
+            HIPCHK(c, launch_adjoint_contract(ch.N, ch.M, dV, c->PHI.p + ch.off, c->V.p + ch.off,
+                                              Wt + ch.off, ch.psi, o.rho_floor, c->partG.p, c->partG.cap,
+                                              c->bmat.p + (size_t)q * bstride, c->W.p + ch.off, s));
+            lb.N[q] = ch.N;
+            lb.so[q] = (long long)ch.so;
+            lb.go[q] = (long long)goff[c0 + q];
+        }
+        HIPCHK(c, launch_lowdin_backward_batch(lb, c->bmat.p, bstride, c->small.p, lo, c->work.p, wstride,
+                                               c->d_grad.p, s));
     }
+    HIPCHK(c, hipMemcpyAsync(c->h_grad, c->d_grad.p, goff.back() * sizeof(double), hipMemcpyDeviceToHost, s));
     return FSIC_OK;
 }
 
