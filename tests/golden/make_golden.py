@@ -16,6 +16,8 @@ stored values.
   python tests/golden/make_golden.py mol192flo  # T, S, Z (Eq. 8, Sec. I.B) of both
                                               # channels and phi at sampled nodes of
                                               # the four orbitals (mol192_flo.npz)
+  python tests/golden/make_golden.py batch24  # U_i and X_i (Eq. 1) of one spin-up
+                                              # orbital of each of the 24 systems
 
 Costs on 8 host cores: mol128 about 30 minutes, mol192 about an hour.
 """
@@ -124,6 +126,38 @@ def mol192flo():
     log("mol192flo: written")
 
 
+def batch24_orbital(k, nup):
+    """The spin-up orbital whose terms are stored for batch24 system k."""
+    return (7 * k + 3) % nup
+
+
+def batch24():
+    log("batch24: generate on the CPU")
+    systems = synth.make_batch24()
+    rec = {"workload": "batch24", "seed": synth.BATCH24_SEED,
+           "quantity": "U_i and X_i (Ha) of one spin-up orbital per system, orbital (7 k + 3) mod N_up; "
+                       "cond(S) of the spin-up channel",
+           "oracle": "flo_spin then orbital_terms, FP64, CG to relative residual 1e-13, fd_order 12, lmax 6",
+           "orbital": [], "U": [], "X": [], "cond_S": [], "fingerprint": []}
+    for k, s in enumerate(systems):
+        t0 = time.time()
+        i = batch24_orbital(k, s.nocc[0])
+        phi, _, S, _ = oracle.flo_spin(s.psi[0], s.fod[0], s.n, s.h, s.origin)
+        lam = np.linalg.eigvalsh(S)
+        u, x, it, _ = oracle.orbital_terms(phi[i] ** 2, s.n, s.h, s.origin)
+        log(f"batch24 system {k} (n={s.n[0]}, N={s.nocc}) orbital {i}: U={u:.15f} X={x:.15f} "
+            f"cond(S)={lam[-1] / lam[0]:.3e} ({it} CG iterations, {time.time() - t0:.0f} s)")
+        rec["cond_S"].append(float(lam[-1] / lam[0]))
+        rec["orbital"].append(i)
+        rec["U"].append(u)
+        rec["X"].append(x)
+        rec["fingerprint"].append(fingerprint(s))
+        del phi
+    with open(os.path.join(HERE, "batch24_terms.json"), "w") as fh:
+        json.dump(rec, fh)
+    log("batch24: written")
+
+
 if __name__ == "__main__":
     for name in sys.argv[1:]:
-        {"mol128": mol128, "mol192": mol192, "mol192flo": mol192flo}[name]()
+        {"mol128": mol128, "mol192": mol192, "mol192flo": mol192flo, "batch24": batch24}[name]()
