@@ -96,6 +96,10 @@ def test_invalid_arguments_rejected_on_host():
     o = fsic.default_opts(lmax=9)
     assert fsic.fsic_create(ctypes.byref(h), ctypes.byref(o), None) == fsic.FSIC_EINVAL
     assert fsic.fsic_create(None, ctypes.byref(fsic.default_opts()), None) == fsic.FSIC_EINVAL
+    # the context-bound calls reject a null context before anything else
+    assert fsic.fsic_forward(None, 1, None, None, None, None, None) == fsic.FSIC_EINVAL
+    assert fsic.fsic_backward(None, None, None, None) == fsic.FSIC_EINVAL
+    assert fsic.fsic_forward_backward(None, 1, None, None, None, None, None, None, None, None) == fsic.FSIC_EINVAL
 
 
 def test_flag_and_solver_constants_match_header():
